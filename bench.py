@@ -1,0 +1,143 @@
+"""Benchmark: rays per second of the full per-ray pipeline (emit -> index-grid integration ->
+thick lens -> sensor deposit) on one MI355X, on the BOS-through-turbulence workload:
+128^3 k^-5/3 random-phase density field (ratio 1.05) over a 10 cm box, 50 000 dots x 1000 rays
+(5e7 rays per image), f = 105 mm f/11 lens, 1024^2 sensor of 10 um pixels, ds = 0.1 mm.
+
+One step = one pbr_emit_and_trace call over the whole image (sensor cleared on the device first);
+the density field, sources and buffers are resident in HBM before timing starts.  Prints one JSON
+line.  The CPU baseline is the FP64 oracle timed on a bounded prefix of the same sources.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# FP32 operations of one Runge-Kutta step of the method (eqs. 3, 5, 6): three evaluations of D,
+# each a trilinear interpolation of four quantities (4 x 7 lerps x 3 ops) plus n = 1 + dn and
+# D = n grad n (4 ops) = 88; the stage points and updates: A, B, C = h D (9), stage B point (15),
+# stage C point (12), R update (18), T update (15).  3 * 88 + 69 = 333.
+FLOPS_PER_STEP = 333
+PEAK_FP32_TFLOPS = 157.3  # MI355X vector FP32, published
+PMC_FILE = os.path.join(ROOT, "profiles", "trace_turbulence_bos_128_pmc.json")
+
+
+def _kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("trace.hip", "pbr_internal.h"):
+        with open(os.path.join(ROOT, "paper_1812_05902_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _traffic_from_profile():
+    """HBM bytes per trace launch from the committed rocprofv3 counter summary, if it was taken
+    on the current kernel source; else None."""
+    try:
+        with open(PMC_FILE) as fh:
+            d = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_source_hash") != _kernel_source_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(scene, rho, src, target_s: float = 12.0):
+    """FP64 oracle on a prefix of the sources, all host threads; rays/s."""
+    import oracle
+    o = oracle.scene_oracle(scene, rho=rho)
+    threads = oracle.num_threads()
+    n_cal = max(threads, 16)
+    t0 = time.perf_counter()
+    o.render(src[:n_cal], scene.rays_per_src, want_float=False)
+    t_cal = time.perf_counter() - t0
+    n = int(min(len(src), max(n_cal, n_cal * target_s / max(t_cal, 1e-3))))
+    t0 = time.perf_counter()
+    o.render(src[:n], scene.rays_per_src, want_float=False)
+    dt = time.perf_counter() - t0
+    rays = n * scene.rays_per_src
+    return {"value": rays / dt, "unit": "rays/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {n} of {len(src)} sources x {scene.rays_per_src} rays "
+                      f"({rays} rays, {dt:.1f} s, FP64 oracle, OpenMP over sources)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the renderer has no "
+              "multi-GPU path in this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1812_05902_amd import inputs, pbr
+
+    scene = inputs.turbulence_bos()
+    rho = inputs.density(scene)
+    src = inputs.sources(scene)
+    r = pbr.Renderer.from_scene(scene, rho=rho)
+    src_dev = torch.as_tensor(src, device=r.device).contiguous()
+    torch.cuda.synchronize()
+
+    def step(stats):
+        return r.emit_and_trace(src_dev, scene.rays_per_src, scene.ray_seed, scene.ds,
+                                pbr.PBR_CLEAR_FIRST, stats=stats)
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    kernel_ms, steps_total = [], 0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        st = step(True)  # HIP events around the trace launch, on the launch stream
+        kernel_ms.append(st["trace_ms"])
+        steps_total += st["rkn_steps"]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    n_rays = scene.n_rays
+    value = n_rays * args.steps / wall
+    avg_ms = sum(kernel_ms) / len(kernel_ms)
+    flops_per_launch = steps_total / args.steps * FLOPS_PER_STEP
+    achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12
+    out = {
+        "metric": "rays/sec on 1 MI355X (trace+lens+sensor)",
+        "value": value,
+        "unit": "rays/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "turbulence_bos_128", "grid": "128^3", "n_src": scene.n_src,
+                   "rays_per_src": scene.rays_per_src, "rays_per_image": n_rays,
+                   "sensor": f"{scene.width}x{scene.height}", "ds_m": scene.ds,
+                   "mean_rkn_steps_per_ray": steps_total / args.steps / n_rays},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
+                     "traffic": _traffic_from_profile(),
+                     "kernel": "k_trace<float>", "kernel_ms": avg_ms,
+                     "flops_per_rkn_step": FLOPS_PER_STEP},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(scene, rho, src)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

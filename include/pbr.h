@@ -1,0 +1,216 @@
+/*
+ * pbr.h -- C ABI of the MI355X (gfx950) ray-tracing library for synthetic PIV / BOS images.
+ *
+ * The library renders the image-generation method of Rajendran, Bane & Vlachos (arXiv
+ * 1812.05902, section 3): rays are emitted from particles or dots towards the camera lens
+ * (sec. 3.1), integrated through a 3-D refractive-index grid with the Runge-Kutta scheme of
+ * eqs. 3-6 (sec. 3.2), refracted through a thick lens by Snell's law, eq. 7 (sec. 3.3), and
+ * deposited into sensor pixels as error-function-integrated Gaussian spots whose diameter
+ * follows eq. 8 (sec. 3.4).
+ *
+ * Conventions shared by every call:
+ *   - Units are SI (metres, kg/m^3).  The optical axis is +z and light travels towards +z:
+ *     sources, then the density box, then the lens (front vertex at pbr_optics.z_front_vertex),
+ *     then the sensor.  x and y are centred on the axis.  Pixel (i, j) covers
+ *     [i, i+1) x [j, j+1) in sensor pixel coordinates x_px = x / pitch + width / 2 (same for y);
+ *     the image is not flipped (a real image is inverted).
+ *   - "_dev" pointers are device memory of the context's GPU, owned by the caller.  The library
+ *     never allocates large buffers: the caller provides the field workspace, the sensor
+ *     accumulator and the ray-exit record buffer.  pbr_create allocates one 4 KiB device block
+ *     for counters, freed by pbr_destroy.
+ *   - All device work is enqueued on the context's HIP stream and is asynchronous unless a
+ *     function says it synchronises.  The caller keeps its buffers alive until the stream has
+ *     passed the work that uses them.
+ *   - Every int-returning function returns PBR_OK (0) or a negative PBR_ERR_* code, and leaves a
+ *     message for pbr_last_error.  Arguments are validated before any device work is enqueued,
+ *     so a failed call has no effect on the device.  No C++ exception crosses the ABI.
+ *   - One context per host thread and stream; contexts are independent.
+ */
+#ifndef PBR_H
+#define PBR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- return codes */
+#define PBR_OK             0
+#define PBR_ERR_ARG       -1  /* an argument is null, non-finite or out of range */
+#define PBR_ERR_STATE     -2  /* call order: e.g. trace before field, optics or sensor are set */
+#define PBR_ERR_HIP       -3  /* a HIP runtime call failed (message names it) */
+#define PBR_ERR_WORKSPACE -4  /* a caller buffer is smaller than required */
+#define PBR_ERR_OVERFLOW  -5  /* the 64-bit fixed-point sensor could overflow */
+
+/* ---------------------------------------------------------------- per-ray status */
+#define PBR_RAY_DEPOSITED        0  /* reached the sensor; spot deposited */
+#define PBR_RAY_OFF_SENSOR       1  /* hit point outside the pixel array */
+#define PBR_RAY_BLOCKED_APERTURE 2  /* crossed the aperture plane outside the opening (sec. 3.3 (3)) */
+#define PBR_RAY_BLOCKED_LENS     3  /* missed a lens surface or crossed it outside its clear radius */
+#define PBR_RAY_TIR              4  /* total internal reflection inside the lens (sec. 3.3 (2)) */
+#define PBR_RAY_STEP_LIMIT       5  /* exceeded the integration step limit inside the box */
+#define PBR_RAY_MISSED           6  /* never travels towards the lens or the sensor */
+#define PBR_NUM_STATUS           7
+
+/* ---------------------------------------------------------------- pbr_emit_and_trace flags */
+#define PBR_CLEAR_FIRST     (1u << 0)  /* zero the sensor accumulator before depositing */
+#define PBR_RECORD_EXITS    (1u << 1)  /* write exit records for the rays chosen by pbr_set_exit_recording */
+#define PBR_PREC_FP64_ALL   (1u << 2)  /* integrate every step in FP64 (default: FP32) */
+
+/* ---------------------------------------------------------------- pbr_read_image formats */
+#define PBR_FMT_RAW_U64 0  /* copy of the Q32.32 accumulator (uint64 per pixel) */
+#define PBR_FMT_F32     1  /* float: accumulator * 2^-32 (sum of spot fractions times weights) */
+#define PBR_FMT_U16     2  /* uint16: min(65535, round_half_even(value * gain)) */
+
+/* Camera lens: a symmetric biconvex singlet whose two radii follow from the thick-lens
+ * lensmaker equation for the nominal focal length (glass index relative to vacuum); the aperture
+ * stop is a disk of radius focal_length / (2 f_number) in the plane of the front vertex.  The
+ * medium on both sides has the ambient index 1 + K rho_inf of pbr_set_density_field. */
+typedef struct pbr_optics {
+    double z_front_vertex;  /* z of the first lens surface on the axis (m) */
+    double focal_length;    /* nominal focal length (m), > 0 */
+    double f_number;        /* f/#, > 0; aperture radius a = focal_length / (2 f_number) */
+    double thickness;       /* centre thickness (m); <= 0 selects 0.1 * focal_length */
+    double n_glass;         /* lens index (> 1), e.g. 1.5 */
+    double clear_radius;    /* surface clear radius (m); <= 0 selects 1.5 a */
+    double z_focus;         /* object plane imaged sharply when the sensor is auto-placed */
+} pbr_optics;
+
+/* Sensor: pixel array, its plane, and the diffraction spot of eq. 8. */
+typedef struct pbr_sensor {
+    int32_t width, height;  /* pixels, 1 .. 16384 each */
+    double pitch;           /* pixel pitch (m), > 0 */
+    double z_sensor;        /* sensor plane z (m); NaN = paraxial image plane of z_focus */
+    double wavelength;      /* (m), e.g. 532e-9 (effective green) */
+    double sigma_px;        /* Gaussian sigma in pixels; <= 0 = d_tau / 4 from eq. 8 */
+    int32_t dtau_with_pi;   /* 1: keep the factor pi printed in eq. 8; 0: d_tau = 2.44 f# (|M|+1) lambda */
+    int32_t reserved;
+} pbr_sensor;
+
+/* Quantities derived by the library from field, optics and sensor (for checks and reports). */
+typedef struct pbr_derived {
+    double n_inf;           /* ambient refractive index 1 + K rho_inf */
+    double lens_radius;     /* |R1| = |R2| (m) */
+    double thickness;       /* lens centre thickness (m) */
+    double aperture_radius; /* a (m) */
+    double clear_radius;    /* (m) */
+    double z_sensor;        /* sensor plane actually used (m) */
+    double magnification;   /* paraxial lateral magnification (negative: inverted image) */
+    double sigma_px;        /* spot sigma actually used (pixels) */
+    int32_t footprint_r;    /* deposit window half-width: max(1, ceil(3 sigma_px)) */
+    int32_t max_steps;      /* step limit for the last traced ds */
+} pbr_derived;
+
+/* Counters of one pbr_emit_and_trace call. */
+typedef struct pbr_stats {
+    uint64_t rays;                     /* rays emitted */
+    uint64_t status[PBR_NUM_STATUS];   /* rays per PBR_RAY_* status (sums to rays) */
+    uint64_t entered_volume;           /* rays that entered the density box */
+    uint64_t rkn_steps;                /* Runge-Kutta steps taken (all rays) */
+    double trace_ms;                   /* device time of the trace kernel(s) (HIP events) */
+} pbr_stats;
+
+/* Exit record of one ray (sec. 4 uses per-ray displacements on the sensor). */
+typedef struct pbr_ray_exit {
+    int64_t ray_id;          /* s * rays_per_src + j */
+    int32_t status;          /* PBR_RAY_* */
+    int32_t n_steps;         /* Runge-Kutta steps inside the box */
+    int32_t entered;         /* 1 if the ray entered the density box */
+    int32_t reserved;
+    double vol_exit_pos[3];  /* where the ray left the box (the source if it never entered) */
+    double vol_exit_dir[3];  /* unit direction there */
+    double sensor_px[2];     /* hit point in pixel coordinates (valid for DEPOSITED / OFF_SENSOR) */
+} pbr_ray_exit;
+
+/* ---------------------------------------------------------------- context */
+
+typedef struct pbr_ctx pbr_ctx;
+
+/* Creates a context on HIP device `device` that enqueues on `hip_stream` (a hipStream_t; NULL =
+ * the null stream).  Allocates a 4 KiB device block for counters.  *out is NULL on failure.
+ * device = -1 creates a host-only context: every input is validated and pbr_get_derived works,
+ * but no device memory is touched (pbr_set_density_field records the grid without launching) and
+ * calls that need device work (trace, readout, record copies) return PBR_ERR_STATE after their
+ * argument checks.  Errors: ARG (out null, device out of range), HIP. */
+int pbr_create(pbr_ctx **out, int device, void *hip_stream);
+
+/* Waits for the context's stream, frees its counter block and the context. NULL is a no-op. */
+void pbr_destroy(pbr_ctx *ctx);
+
+/* Message of the last failed call on this context (or of the last failed pbr_create when ctx is
+ * NULL).  The string lives until the next call on the context. */
+const char *pbr_last_error(const pbr_ctx *ctx);
+
+/* Changes the stream later calls enqueue on. */
+int pbr_set_stream(pbr_ctx *ctx, void *hip_stream);
+
+/* ---------------------------------------------------------------- inputs */
+
+/* Bytes of field workspace pbr_set_density_field needs for an nx x ny x nz grid (0 if a
+ * dimension is below 2). */
+size_t pbr_field_workspace_bytes(int nx, int ny, int nz);
+
+/* Density grid (sec. 3.2 and Gladstone-Dale eq. 1).  rho_dev: float32 [nz][ny][nx] node values,
+ * x fastest; node (i,j,k) sits at origin + (i,j,k) * spacing.  Enqueues the field preparation
+ * kernel, which writes n - 1 = K rho and grad n (central differences inside, second-order
+ * one-sided differences on the faces) into ws_dev (ws_bytes >= pbr_field_workspace_bytes).
+ * rho_dev may be released once the stream has passed this call; ws_dev must live as long as the
+ * context traces with this field.  Outside the box the index is 1 + K rho_inf with no gradient.
+ * Errors: ARG (null, dims < 2 or > 65535, nx*ny*nz > 2^34, spacing <= 0, K < 0, non-finite
+ * origin/spacing/K/rho_inf), WORKSPACE. */
+int pbr_set_density_field(pbr_ctx *ctx, const float *rho_dev, int nx, int ny, int nz,
+                          const double origin[3], const double spacing[3], double K,
+                          double rho_inf, void *ws_dev, size_t ws_bytes);
+
+/* Lens (sec. 3.3).  Copied; host-side set-up only.  Errors: ARG (null, focal_length <= 0,
+ * f_number <= 0, n_glass <= 1, thickness > n_glass * focal_length (no real lens radius),
+ * clear radius < aperture radius, non-finite values). */
+int pbr_set_optics(pbr_ctx *ctx, const pbr_optics *optics);
+
+/* Sensor (sec. 3.4) and its accumulator: uint64 [height][width] Q32.32 fixed point, owned by
+ * the caller, width * height * 8 bytes.  Deposits are integer atomics, so images do not depend on
+ * the order in which rays arrive.  Errors: ARG. */
+int pbr_set_sensor(pbr_ctx *ctx, const pbr_sensor *sensor, uint64_t *accum_dev);
+
+/* Fills *out with the derived optics; needs field (for n_inf), optics and sensor.  Host only. */
+int pbr_get_derived(pbr_ctx *ctx, pbr_derived *out);
+
+/* Chooses the rays whose exit records later traces with PBR_RECORD_EXITS write: ray ids
+ * first + k * stride for 0 <= k < max_records, record k at buf_dev[k] (caller-owned device
+ * buffer of max_records pbr_ray_exit).  Records of ids beyond the traced ray count are left
+ * untouched.  Errors: ARG (first < 0, stride < 1, max_records < 0, null buffer with
+ * max_records > 0). */
+int pbr_set_exit_recording(pbr_ctx *ctx, int64_t first, int64_t stride, int64_t max_records,
+                           pbr_ray_exit *buf_dev);
+
+/* ---------------------------------------------------------------- the hot path */
+
+/* Emits rays_per_src rays from each of n_src sources and accumulates their spots into the
+ * sensor (all four steps of sec. 3).  src_dev: float32 [n_src][4] = (x, y, z, weight), weight
+ * in [0, 1].  Ray j of source s aims at the aperture point (a sqrt(u1) cos 2 pi u2,
+ * a sqrt(u1) sin 2 pi u2) with (u1, u2) the two 24-bit fields of SplitMix64 output number
+ * (s << 32 | j) for `seed`.  ds: arc length per Runge-Kutta step (m, > 0).  With stats_host
+ * non-NULL the call synchronises the stream and fills the counters; otherwise it is asynchronous.
+ * Errors: STATE (field, optics or sensor missing), ARG (n_src < 0, rays_per_src < 1 or
+ * >= 2^31, ds <= 0, lens not beyond the box, source array null with n_src > 0),
+ * OVERFLOW (n_src * rays_per_src * 2^32 plus what the accumulator may already hold could exceed
+ * 2^64 in one pixel), HIP. */
+int pbr_emit_and_trace(pbr_ctx *ctx, const float *src_dev, int64_t n_src, int32_t rays_per_src,
+                       uint64_t seed, double ds, uint32_t flags, pbr_stats *stats_host);
+
+/* Converts the accumulator into out_dev (caller-owned: width*height elements of uint64, float
+ * or uint16 by fmt).  PBR_FMT_U16 uses `gain` if > 0, else gain = 65535 / (largest pixel value),
+ * found on the device.  Errors: ARG, STATE (no sensor). */
+int pbr_read_image(pbr_ctx *ctx, int fmt, void *out_dev, double gain);
+
+/* Copies records [first, first + count) of the recording buffer to host memory out_host and
+ * synchronises the stream.  Errors: ARG (range outside the buffer), STATE (no recording set). */
+int pbr_read_ray_exits(pbr_ctx *ctx, pbr_ray_exit *out_host, int64_t first, int64_t count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PBR_H */

@@ -96,6 +96,7 @@ def lib():
         l.orc_trace_ids.restype = C.c_int
         l.orc_trace_ids.argtypes = [P, P, C.c_int32, P, C.c_int64, P, C.c_int]
         l.orc_num_threads.restype = C.c_int
+        l.orc_readout_u16.argtypes = [P, C.c_int64, C.c_double, P]
         _lib = l
     return _lib
 
@@ -112,6 +113,17 @@ def ray_uniforms(seed: int, s: int, j: int):
     out = np.zeros(2)
     lib().orc_ray_uniforms(seed, s, j, _ptr(out))
     return out
+
+
+def readout_u16(q: np.ndarray, gain: float = 0.0) -> np.ndarray:
+    q = np.ascontiguousarray(q, dtype=np.uint64)
+    out = np.zeros(q.shape, dtype=np.uint16)
+    lib().orc_readout_u16(_ptr(q), q.size, float(gain), _ptr(out))
+    return out
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())
 
 
 def pixel_fraction(x: float, i: int, sigma: float) -> float:

@@ -585,6 +585,22 @@ int orc_trace_ids(const orc_scene *S, const float *src, int32_t rays_per_src,
     return 0;
 }
 
+/* 16-bit readout of a Q32.32 image: v = q 2^-32, out = min(65535, round_half_even(v gain)),
+ * gain = 65535 / max(v) when gain <= 0 (sec. 3.4: about 1e4 rays per source give 16 bits). */
+void orc_readout_u16(const uint64_t *q, int64_t n, double gain, uint16_t *out)
+{
+    if (!(gain > 0.0)) {
+        uint64_t mx = 0;
+        for (int64_t p = 0; p < n; ++p) if (q[p] > mx) mx = q[p];
+        double vmax = (double)mx / 4294967296.0;
+        gain = vmax > 0.0 ? 65535.0 / vmax : 0.0;
+    }
+    for (int64_t p = 0; p < n; ++p) {
+        double r = rint((double)q[p] / 4294967296.0 * gain);
+        out[p] = (uint16_t)(r < 65535.0 ? r : 65535.0);
+    }
+}
+
 int orc_num_threads(void)
 {
 #ifdef _OPENMP

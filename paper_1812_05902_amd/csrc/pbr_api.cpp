@@ -1,0 +1,469 @@
+// C ABI of the library (include/pbr.h): argument validation, host-side optics set-up and the
+// launches on the context's stream.  No C++ exception crosses the ABI.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "pbr_internal.h"
+
+struct pbr_ctx {
+    int device = 0;            // -1: host-only context (validation and derived optics, no device work)
+    hipStream_t stream = nullptr;
+    std::string err;
+    unsigned long long *counters = nullptr;  // 4 KiB device block
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    // field
+    bool has_field = false;
+    const float4 *node = nullptr;
+    int nx = 0, ny = 0, nz = 0;
+    double origin[3] = {0, 0, 0}, spacing[3] = {0, 0, 0};
+    double K = 0.0, rho_inf = 0.0;
+    // optics
+    bool has_optics = false;
+    pbr_optics optics{};
+    // sensor
+    bool has_sensor = false;
+    pbr_sensor sensor{};
+    unsigned long long *accum = nullptr;
+    double accum_rays = 0.0;  // rays deposited since the last clear (overflow bound)
+    // exit recording
+    pbr_ray_exit *rec = nullptr;
+    int64_t rec_first = 0, rec_stride = 1, rec_max = 0;
+    int last_max_steps = 0;
+};
+
+namespace {
+
+thread_local std::string g_create_err;
+
+int fail(pbr_ctx *c, int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    else g_create_err = buf;
+    return code;
+}
+
+int hip_fail(pbr_ctx *c, int e, const char *what)
+{
+    return fail(c, PBR_ERR_HIP, "%s: %s", what, hipGetErrorString((hipError_t)e));
+}
+
+// Makes the context's device current for the duration of a call.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard()
+    {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+bool finite3(const double *v) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
+
+struct Derived {
+    double n_inf, R, t, a, clear, z_sensor, M, sigma_px;
+    int rfp;
+};
+
+// Host-side optics: lens radii from the thick-lens lensmaker equation (R1 = -R2 = R, glass index
+// relative to vacuum), the paraxial system matrix of the lens in the ambient medium, the image
+// plane of z_focus and the lateral magnification, and the spot sigma from eq. 8.
+int derive(pbr_ctx *c, Derived *d)
+{
+    if (!c->has_field || !c->has_optics || !c->has_sensor)
+        return fail(c, PBR_ERR_STATE, "field, optics and sensor must be set first");
+    const pbr_optics &o = c->optics;
+    const pbr_sensor &s = c->sensor;
+    d->n_inf = 1.0 + c->K * c->rho_inf;
+    const double f = o.focal_length, ng = o.n_glass;
+    d->t = o.thickness > 0.0 ? o.thickness : 0.1 * f;
+    // (ng-1) [2/R - (ng-1) t / (ng R^2)] = 1/f  <=>  R^2 - 2 (ng-1) f R + (ng-1)^2 f t / ng = 0
+    const double p = (ng - 1.0) * f;
+    const double disc = p * p - (ng - 1.0) * (ng - 1.0) * f * d->t / ng;
+    if (!(disc >= 0.0)) return fail(c, PBR_ERR_ARG, "lens thickness admits no real radius");
+    d->R = p + std::sqrt(disc);
+    d->a = f / (2.0 * o.f_number);
+    d->clear = o.clear_radius > 0.0 ? o.clear_radius : 1.5 * d->a;
+    // reduced-angle system matrix [[A, B], [C, D]] of surface 1, glass, surface 2
+    const double na = d->n_inf;
+    const double ph1 = (ng - na) / d->R, ph2 = (na - ng) / (-d->R), tau = d->t / ng;
+    const double A = 1.0 - tau * ph1, B = tau, C = -(ph1 + ph2 - tau * ph1 * ph2), D = 1.0 - tau * ph2;
+    const double so = (o.z_front_vertex - o.z_focus) / na;   // reduced object distance
+    const double si = -(A * so + B) / (C * so + D);          // reduced image distance
+    const double z_img = o.z_front_vertex + d->t + si * na;
+    d->M = A + si * C;
+    d->z_sensor = std::isnan(s.z_sensor) ? z_img : s.z_sensor;
+    if (s.sigma_px > 0.0) {
+        d->sigma_px = s.sigma_px;
+    } else {
+        // eq. 8: d_tau = 2.44 (pi) f# (M + 1) lambda, sigma = d_tau / 4 (1/e^2 diameter)
+        double dt = 2.44 * o.f_number * (std::fabs(d->M) + 1.0) * s.wavelength;
+        if (s.dtau_with_pi) dt *= 3.14159265358979323846;
+        d->sigma_px = dt / 4.0 / s.pitch;
+    }
+    d->rfp = (int)std::ceil(3.0 * d->sigma_px);
+    if (d->rfp < 1) d->rfp = 1;
+    if (d->rfp > pbr::kMaxFootprint)
+        return fail(c, PBR_ERR_ARG, "spot sigma %.3g px needs a window wider than %d px", d->sigma_px,
+                    2 * pbr::kMaxFootprint + 1);
+    return PBR_OK;
+}
+
+int max_steps_for(const pbr_ctx *c, double ds)
+{
+    double d2 = 0.0;
+    const int n3[3] = {c->nx, c->ny, c->nz};
+    for (int a = 0; a < 3; ++a) {
+        const double e = (double)(n3[a] - 1) * c->spacing[a];
+        d2 += e * e;
+    }
+    const double m = 4.0 * std::ceil(std::sqrt(d2) / ds) + 64.0;
+    return m > 2.0e9 ? 2000000000 : (int)m;
+}
+
+}  // namespace
+
+#define PBR_GUARD_BEGIN try {
+#define PBR_GUARD_END                                                        \
+    }                                                                        \
+    catch (...) { return fail(ctx, PBR_ERR_HIP, "internal error (exception)"); }
+
+extern "C" {
+
+int pbr_create(pbr_ctx **out, int device, void *hip_stream)
+{
+    pbr_ctx *ctx = nullptr;
+    PBR_GUARD_BEGIN
+    if (!out) return fail(nullptr, PBR_ERR_ARG, "out is null");
+    *out = nullptr;
+    if (device == -1) {
+        ctx = new (std::nothrow) pbr_ctx();
+        if (!ctx) return fail(nullptr, PBR_ERR_HIP, "out of host memory");
+        ctx->device = -1;
+        *out = ctx;
+        return PBR_OK;
+    }
+    int n = 0;
+    int e = (int)hipGetDeviceCount(&n);
+    if (e) return fail(nullptr, PBR_ERR_HIP, "hipGetDeviceCount: %s", hipGetErrorString((hipError_t)e));
+    if (device < 0 || device >= n) return fail(nullptr, PBR_ERR_ARG, "device %d out of range (%d devices)", device, n);
+    DeviceGuard g(device);
+    if (!g.ok) return fail(nullptr, PBR_ERR_HIP, "hipSetDevice(%d) failed", device);
+    ctx = new (std::nothrow) pbr_ctx();
+    if (!ctx) return fail(nullptr, PBR_ERR_HIP, "out of host memory");
+    ctx->device = device;
+    ctx->stream = (hipStream_t)hip_stream;
+    void *p = nullptr;
+    e = (int)hipMalloc(&p, 4096);
+    if (e) { delete ctx; return fail(nullptr, PBR_ERR_HIP, "hipMalloc(counters): %s", hipGetErrorString((hipError_t)e)); }
+    ctx->counters = (unsigned long long *)p;
+    if ((e = (int)hipEventCreate(&ctx->ev0)) || (e = (int)hipEventCreate(&ctx->ev1))) {
+        (void)hipFree(p);
+        delete ctx;
+        return fail(nullptr, PBR_ERR_HIP, "hipEventCreate: %s", hipGetErrorString((hipError_t)e));
+    }
+    e = pbr::launch_clear_u64(ctx->counters, 4096 / 8, ctx->stream);
+    if (e) { int r = hip_fail(nullptr, e, "clear counters"); (void)hipFree(p); delete ctx; return r; }
+    *out = ctx;
+    return PBR_OK;
+    }
+    catch (...) { delete ctx; return fail(nullptr, PBR_ERR_HIP, "internal error (exception)"); }
+}
+
+void pbr_destroy(pbr_ctx *ctx)
+{
+    if (!ctx) return;
+    if (ctx->device < 0) { delete ctx; return; }
+    try {
+        DeviceGuard g(ctx->device);
+        (void)hipStreamSynchronize(ctx->stream);
+        if (ctx->counters) (void)hipFree(ctx->counters);
+        if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
+        if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+    } catch (...) {
+    }
+    delete ctx;
+}
+
+const char *pbr_last_error(const pbr_ctx *ctx)
+{
+    return ctx ? ctx->err.c_str() : g_create_err.c_str();
+}
+
+int pbr_set_stream(pbr_ctx *ctx, void *hip_stream)
+{
+    if (!ctx) return PBR_ERR_ARG;
+    ctx->stream = (hipStream_t)hip_stream;
+    return PBR_OK;
+}
+
+size_t pbr_field_workspace_bytes(int nx, int ny, int nz)
+{
+    if (nx < 2 || ny < 2 || nz < 2) return 0;
+    return (size_t)nx * (size_t)ny * (size_t)nz * sizeof(float4);
+}
+
+int pbr_set_density_field(pbr_ctx *ctx, const float *rho_dev, int nx, int ny, int nz,
+                          const double origin[3], const double spacing[3], double K,
+                          double rho_inf, void *ws_dev, size_t ws_bytes)
+{
+    if (!ctx) return PBR_ERR_ARG;
+    PBR_GUARD_BEGIN
+    if (!rho_dev || !ws_dev || !origin || !spacing) return fail(ctx, PBR_ERR_ARG, "null pointer argument");
+    if (nx < 2 || ny < 2 || nz < 2 || nx > 65535 || ny > 65535 || nz > 65535)
+        return fail(ctx, PBR_ERR_ARG, "grid dimensions %d x %d x %d outside [2, 65535]", nx, ny, nz);
+    if ((double)nx * ny * nz > 17179869184.0) return fail(ctx, PBR_ERR_ARG, "grid larger than 2^34 nodes");
+    if (!finite3(origin) || !finite3(spacing)) return fail(ctx, PBR_ERR_ARG, "origin/spacing not finite");
+    if (!(spacing[0] > 0 && spacing[1] > 0 && spacing[2] > 0)) return fail(ctx, PBR_ERR_ARG, "spacing must be > 0");
+    if (!std::isfinite(K) || K < 0.0) return fail(ctx, PBR_ERR_ARG, "K must be finite and >= 0");
+    if (!std::isfinite(rho_inf)) return fail(ctx, PBR_ERR_ARG, "rho_inf not finite");
+    const size_t need = pbr_field_workspace_bytes(nx, ny, nz);
+    if (ws_bytes < need) return fail(ctx, PBR_ERR_WORKSPACE, "field workspace %zu bytes < %zu needed", ws_bytes, need);
+    if (((uintptr_t)ws_dev & 15u) != 0) return fail(ctx, PBR_ERR_ARG, "field workspace must be 16-byte aligned");
+    if (ctx->device >= 0) {
+        DeviceGuard g(ctx->device);
+        if (!g.ok) return fail(ctx, PBR_ERR_HIP, "hipSetDevice failed");
+        const int e = pbr::launch_field_prep(rho_dev, (float4 *)ws_dev, nx, ny, nz, spacing, K, ctx->stream);
+        if (e) return hip_fail(ctx, e, "field preparation launch");
+    }
+    ctx->node = (const float4 *)ws_dev;
+    ctx->nx = nx; ctx->ny = ny; ctx->nz = nz;
+    for (int a = 0; a < 3; ++a) { ctx->origin[a] = origin[a]; ctx->spacing[a] = spacing[a]; }
+    ctx->K = K;
+    ctx->rho_inf = rho_inf;
+    ctx->has_field = true;
+    return PBR_OK;
+    PBR_GUARD_END
+}
+
+int pbr_set_optics(pbr_ctx *ctx, const pbr_optics *o)
+{
+    if (!ctx) return PBR_ERR_ARG;
+    if (!o) return fail(ctx, PBR_ERR_ARG, "optics is null");
+    const double v[7] = {o->z_front_vertex, o->focal_length, o->f_number, o->thickness, o->n_glass,
+                         o->clear_radius, o->z_focus};
+    for (double x : v)
+        if (!std::isfinite(x)) return fail(ctx, PBR_ERR_ARG, "optics values must be finite");
+    if (!(o->focal_length > 0.0)) return fail(ctx, PBR_ERR_ARG, "focal_length must be > 0");
+    if (!(o->f_number > 0.0)) return fail(ctx, PBR_ERR_ARG, "f_number must be > 0");
+    if (!(o->n_glass > 1.0)) return fail(ctx, PBR_ERR_ARG, "n_glass must be > 1");
+    const double t = o->thickness > 0.0 ? o->thickness : 0.1 * o->focal_length;
+    if (t > o->n_glass * o->focal_length) return fail(ctx, PBR_ERR_ARG, "thickness > n_glass * focal_length");
+    const double a = o->focal_length / (2.0 * o->f_number);
+    if (o->clear_radius > 0.0 && o->clear_radius < a) return fail(ctx, PBR_ERR_ARG, "clear radius below aperture radius");
+    ctx->optics = *o;
+    ctx->has_optics = true;
+    return PBR_OK;
+}
+
+int pbr_set_sensor(pbr_ctx *ctx, const pbr_sensor *s, uint64_t *accum_dev)
+{
+    if (!ctx) return PBR_ERR_ARG;
+    if (!s || !accum_dev) return fail(ctx, PBR_ERR_ARG, "null pointer argument");
+    if (s->width < 1 || s->height < 1 || s->width > 16384 || s->height > 16384)
+        return fail(ctx, PBR_ERR_ARG, "sensor %d x %d outside [1, 16384]", s->width, s->height);
+    if (!(s->pitch > 0.0) || !std::isfinite(s->pitch)) return fail(ctx, PBR_ERR_ARG, "pitch must be finite and > 0");
+    if (!std::isnan(s->z_sensor) && !std::isfinite(s->z_sensor)) return fail(ctx, PBR_ERR_ARG, "z_sensor must be finite or NaN");
+    if (!(s->wavelength > 0.0) || !std::isfinite(s->wavelength)) return fail(ctx, PBR_ERR_ARG, "wavelength must be > 0");
+    if (!std::isfinite(s->sigma_px)) return fail(ctx, PBR_ERR_ARG, "sigma_px not finite");
+    if (((uintptr_t)accum_dev & 7u) != 0) return fail(ctx, PBR_ERR_ARG, "accumulator must be 8-byte aligned");
+    ctx->sensor = *s;
+    ctx->accum = (unsigned long long *)accum_dev;
+    ctx->accum_rays = 0.0;  // unknown contents: the caller clears with PBR_CLEAR_FIRST
+    ctx->has_sensor = true;
+    return PBR_OK;
+}
+
+int pbr_get_derived(pbr_ctx *ctx, pbr_derived *out)
+{
+    if (!ctx) return PBR_ERR_ARG;
+    if (!out) return fail(ctx, PBR_ERR_ARG, "out is null");
+    Derived d;
+    const int r = derive(ctx, &d);
+    if (r) return r;
+    out->n_inf = d.n_inf;
+    out->lens_radius = d.R;
+    out->thickness = d.t;
+    out->aperture_radius = d.a;
+    out->clear_radius = d.clear;
+    out->z_sensor = d.z_sensor;
+    out->magnification = d.M;
+    out->sigma_px = d.sigma_px;
+    out->footprint_r = d.rfp;
+    out->max_steps = ctx->last_max_steps;
+    return PBR_OK;
+}
+
+int pbr_set_exit_recording(pbr_ctx *ctx, int64_t first, int64_t stride, int64_t max_records,
+                           pbr_ray_exit *buf_dev)
+{
+    if (!ctx) return PBR_ERR_ARG;
+    if (first < 0 || stride < 1 || max_records < 0) return fail(ctx, PBR_ERR_ARG, "bad recording range");
+    if (max_records > 0 && !buf_dev) return fail(ctx, PBR_ERR_ARG, "record buffer is null");
+    if (((uintptr_t)buf_dev & 7u) != 0) return fail(ctx, PBR_ERR_ARG, "record buffer must be 8-byte aligned");
+    ctx->rec = buf_dev;
+    ctx->rec_first = first;
+    ctx->rec_stride = stride;
+    ctx->rec_max = max_records;
+    return PBR_OK;
+}
+
+int pbr_emit_and_trace(pbr_ctx *ctx, const float *src_dev, int64_t n_src, int32_t rays_per_src,
+                       uint64_t seed, double ds, uint32_t flags, pbr_stats *stats)
+{
+    if (!ctx) return PBR_ERR_ARG;
+    PBR_GUARD_BEGIN
+    Derived d;
+    int r = derive(ctx, &d);
+    if (r) return r;
+    if (n_src < 0) return fail(ctx, PBR_ERR_ARG, "n_src < 0");
+    if (n_src > 0 && !src_dev) return fail(ctx, PBR_ERR_ARG, "source array is null");
+    if (((uintptr_t)src_dev & 15u) != 0) return fail(ctx, PBR_ERR_ARG, "source array must be 16-byte aligned");
+    if (rays_per_src < 1) return fail(ctx, PBR_ERR_ARG, "rays_per_src must be >= 1");
+    if (!(ds > 0.0) || !std::isfinite(ds)) return fail(ctx, PBR_ERR_ARG, "ds must be finite and > 0");
+    if (n_src > (int64_t)1 << 31) return fail(ctx, PBR_ERR_ARG, "n_src above 2^31");
+    const double zmax = ctx->origin[2] + (double)(ctx->nz - 1) * ctx->spacing[2];
+    if (!(ctx->optics.z_front_vertex > zmax))
+        return fail(ctx, PBR_ERR_ARG, "lens front vertex must lie beyond the density box (z > %.6g)", zmax);
+    if (!(d.z_sensor > ctx->optics.z_front_vertex + d.t))
+        return fail(ctx, PBR_ERR_ARG, "sensor plane must lie behind the lens");
+    if (flags & ~(uint32_t)(PBR_CLEAR_FIRST | PBR_RECORD_EXITS | PBR_PREC_FP64_ALL))
+        return fail(ctx, PBR_ERR_ARG, "unknown flag bits 0x%x", flags);
+    if ((flags & PBR_RECORD_EXITS) && ctx->rec_max > 0 && !ctx->rec)
+        return fail(ctx, PBR_ERR_STATE, "no exit recording buffer set");
+    const double n_rays_d = (double)n_src * (double)rays_per_src;
+    const double before = (flags & PBR_CLEAR_FIRST) ? 0.0 : ctx->accum_rays;
+    // each ray adds at most 2^32 to a pixel (weight <= 1): the sum stays below 2^64
+    if (before + n_rays_d > 4294967295.0)
+        return fail(ctx, PBR_ERR_OVERFLOW, "more than 2^32 - 1 rays per accumulation; clear the sensor");
+
+    if (ctx->device < 0) return fail(ctx, PBR_ERR_STATE, "host-only context: no device work");
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(ctx, PBR_ERR_HIP, "hipSetDevice failed");
+    int e;
+    if (flags & PBR_CLEAR_FIRST) {
+        e = pbr::launch_clear_u64(ctx->accum, (int64_t)ctx->sensor.width * ctx->sensor.height, ctx->stream);
+        if (e) return hip_fail(ctx, e, "clear sensor");
+    }
+    e = pbr::launch_clear_u64(ctx->counters, pbr::CNT_SLOTS, ctx->stream);
+    if (e) return hip_fail(ctx, e, "clear counters");
+
+    pbr::TraceParams P;
+    std::memset(&P, 0, sizeof P);
+    P.node = ctx->node;
+    P.nx = ctx->nx; P.ny = ctx->ny; P.nz = ctx->nz;
+    P.max_steps = max_steps_for(ctx, ds);
+    ctx->last_max_steps = P.max_steps;
+    const int n3[3] = {ctx->nx, ctx->ny, ctx->nz};
+    P.h = ds / d.n_inf;
+    for (int a = 0; a < 3; ++a) {
+        P.origin[a] = ctx->origin[a];
+        P.spacing[a] = ctx->spacing[a];
+        P.lo[a] = ctx->origin[a];
+        P.hi[a] = ctx->origin[a] + (double)(n3[a] - 1) * ctx->spacing[a];
+        P.step_cell[a] = P.h / ctx->spacing[a];
+    }
+    P.n_inf = d.n_inf;
+    P.src = (const float4 *)src_dev;
+    P.n_src = n_src;
+    P.rays_per_src = rays_per_src;
+    P.n_rays = n_src * (int64_t)rays_per_src;
+    P.seed = seed;
+    P.z_lens = ctx->optics.z_front_vertex;
+    P.a = d.a; P.R = d.R; P.t = d.t; P.clear = d.clear; P.n_glass = ctx->optics.n_glass;
+    P.z_sensor = d.z_sensor;
+    P.accum = ctx->accum;
+    P.W = ctx->sensor.width; P.H = ctx->sensor.height;
+    P.pitch = ctx->sensor.pitch;
+    P.sigma_px = d.sigma_px;
+    P.rfp = d.rfp;
+    P.record = (flags & PBR_RECORD_EXITS) && ctx->rec_max > 0 ? 1 : 0;
+    P.rec = ctx->rec;
+    P.rec_first = ctx->rec_first;
+    P.rec_stride = ctx->rec_stride;
+    P.rec_max = ctx->rec_max;
+    P.counters = ctx->counters;
+
+    if (stats && (e = (int)hipEventRecord(ctx->ev0, ctx->stream))) return hip_fail(ctx, e, "hipEventRecord");
+    e = pbr::launch_trace(P, (flags & PBR_PREC_FP64_ALL) != 0, ctx->stream);
+    if (e) return hip_fail(ctx, e, "trace launch");
+    if (stats && (e = (int)hipEventRecord(ctx->ev1, ctx->stream))) return hip_fail(ctx, e, "hipEventRecord");
+    ctx->accum_rays = before + n_rays_d;
+
+    if (stats) {
+        unsigned long long h[pbr::CNT_SLOTS];
+        e = (int)hipMemcpyAsync(h, ctx->counters, sizeof h, hipMemcpyDeviceToHost, ctx->stream);
+        if (e) return hip_fail(ctx, e, "copy counters");
+        e = (int)hipStreamSynchronize(ctx->stream);
+        if (e) return hip_fail(ctx, e, "trace (stream synchronise)");
+        float ms = 0.0f;
+        e = (int)hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1);
+        if (e) return hip_fail(ctx, e, "hipEventElapsedTime");
+        std::memset(stats, 0, sizeof *stats);
+        stats->rays = (uint64_t)P.n_rays;
+        for (int k = 0; k < PBR_NUM_STATUS; ++k) stats->status[k] = h[pbr::CNT_STATUS + k];
+        stats->entered_volume = h[pbr::CNT_ENTERED];
+        stats->rkn_steps = h[pbr::CNT_STEPS];
+        stats->trace_ms = (double)ms;
+    }
+    return PBR_OK;
+    PBR_GUARD_END
+}
+
+int pbr_read_image(pbr_ctx *ctx, int fmt, void *out_dev, double gain)
+{
+    if (!ctx) return PBR_ERR_ARG;
+    PBR_GUARD_BEGIN
+    if (!ctx->has_sensor) return fail(ctx, PBR_ERR_STATE, "no sensor set");
+    if (!out_dev) return fail(ctx, PBR_ERR_ARG, "out is null");
+    if (fmt != PBR_FMT_RAW_U64 && fmt != PBR_FMT_F32 && fmt != PBR_FMT_U16)
+        return fail(ctx, PBR_ERR_ARG, "unknown image format %d", fmt);
+    const size_t align = fmt == PBR_FMT_RAW_U64 ? 8 : fmt == PBR_FMT_F32 ? 4 : 2;
+    if (((uintptr_t)out_dev % align) != 0) return fail(ctx, PBR_ERR_ARG, "output misaligned");
+    if (!std::isfinite(gain)) return fail(ctx, PBR_ERR_ARG, "gain not finite");
+    if (ctx->device < 0) return fail(ctx, PBR_ERR_STATE, "host-only context: no device work");
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(ctx, PBR_ERR_HIP, "hipSetDevice failed");
+    const int e = pbr::launch_readout(ctx->accum, (int64_t)ctx->sensor.width * ctx->sensor.height, fmt,
+                                      out_dev, gain, ctx->counters, ctx->stream);
+    if (e) return hip_fail(ctx, e, "readout launch");
+    return PBR_OK;
+    PBR_GUARD_END
+}
+
+int pbr_read_ray_exits(pbr_ctx *ctx, pbr_ray_exit *out_host, int64_t first, int64_t count)
+{
+    if (!ctx) return PBR_ERR_ARG;
+    PBR_GUARD_BEGIN
+    if (!ctx->rec || ctx->rec_max == 0) return fail(ctx, PBR_ERR_STATE, "no exit recording set");
+    if (first < 0 || count < 0 || first + count > ctx->rec_max) return fail(ctx, PBR_ERR_ARG, "record range outside the buffer");
+    if (count > 0 && !out_host) return fail(ctx, PBR_ERR_ARG, "out is null");
+    if (count == 0) return PBR_OK;
+    if (ctx->device < 0) return fail(ctx, PBR_ERR_STATE, "host-only context: no device work");
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(ctx, PBR_ERR_HIP, "hipSetDevice failed");
+    int e = (int)hipMemcpyAsync(out_host, ctx->rec + first, (size_t)count * sizeof(pbr_ray_exit),
+                                hipMemcpyDeviceToHost, ctx->stream);
+    if (e) return hip_fail(ctx, e, "copy records");
+    e = (int)hipStreamSynchronize(ctx->stream);
+    if (e) return hip_fail(ctx, e, "records (stream synchronise)");
+    return PBR_OK;
+    PBR_GUARD_END
+}
+
+}  // extern "C"

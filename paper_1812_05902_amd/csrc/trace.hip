@@ -1,0 +1,430 @@
+// The per-ray pipeline of sec. 3 in one kernel: emit (3.1) -> integrate through the index grid
+// (3.2, eqs. 3-6) -> aperture and thick lens (3.3, eq. 7) -> sensor hit and erf-integrated
+// Gaussian spot (3.4, eq. 8), deposited as Q32.32 integers with 64-bit atomics.
+//
+// Precision layout.  The integration inside the box runs in the template type F (float by
+// default).  Positions are kept cell-local: an integer cell index plus a fraction of the cell
+// (summed in FP64, see rkn_step), so the rounding of a position is relative to the cell size
+// rather than to the metres of the scene.  The direction vector T = n dR/ds is kept as its value at the box entry (T_ref,
+// constant) plus the accumulated change dT, so the small increments (A + 4B + C)/6 are summed
+// into a small number.  Emission, the box entry, the lens and the sensor run in FP64: they cost a
+// few hundred operations per ray against a few hundred thousand in the integration loop.
+#include "pbr_internal.h"
+
+namespace pbr {
+namespace {
+
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+constexpr double kTwoPow32 = 4294967296.0;
+
+// SplitMix64 (Steele, Lea & Flood, OOPSLA 2014) evaluated at counter k: output number k of the
+// generator seeded with `seed`.
+__device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t k)
+{
+    uint64_t z = seed + (k + 1ull) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+template <typename F> __device__ __forceinline__ F ffloor(F x);
+template <> __device__ __forceinline__ float ffloor<float>(float x) { return floorf(x); }
+template <> __device__ __forceinline__ double ffloor<double>(double x) { return floor(x); }
+
+template <typename F> __device__ __forceinline__ F lerp(F a, F b, F t) { return a + t * (b - a); }
+
+// Trilinear interpolation of (n - 1, grad n) at the point (cell c, fraction f); the fraction may
+// lie outside [0, 1) (stage points of eq. 5), in which case the point is moved into the cell that
+// holds it and then onto the box.  Returns n, writes D = n grad n (eq. 6).
+template <typename F>
+__device__ __forceinline__ F sample_D(const TraceParams &P, const int c[3], const F f[3], F D[3])
+{
+    const int nmax[3] = {P.nx - 2, P.ny - 2, P.nz - 2};
+    int ic[3];
+    F w[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        F fa = f[a];
+        fa = fa > (F)(-1.0e6) ? fa : (F)(-1.0e6);  // also maps NaN to a finite value
+        fa = fa < (F)(1.0e6) ? fa : (F)(1.0e6);
+        const F o = ffloor<F>(fa);
+        int i = c[a] + (int)o;
+        F t = fa - o;
+        if (i < 0) { i = 0; t = (F)0; }
+        if (i > nmax[a]) { i = nmax[a]; t = (F)1; }
+        ic[a] = i;
+        w[a] = t;
+    }
+    const size_t sy = (size_t)P.nx, sz = (size_t)P.nx * (size_t)P.ny;
+    const float4 *p = P.node + (size_t)ic[2] * sz + (size_t)ic[1] * sy + (size_t)ic[0];
+    const float4 c000 = p[0], c100 = p[1], c010 = p[sy], c110 = p[sy + 1];
+    const float4 c001 = p[sz], c101 = p[sz + 1], c011 = p[sz + sy], c111 = p[sz + sy + 1];
+    F v[4];
+#define PBR_TRI(ch, out)                                                                         \
+    {                                                                                            \
+        const F x00 = lerp<F>((F)c000.ch, (F)c100.ch, w[0]), x10 = lerp<F>((F)c010.ch, (F)c110.ch, w[0]); \
+        const F x01 = lerp<F>((F)c001.ch, (F)c101.ch, w[0]), x11 = lerp<F>((F)c011.ch, (F)c111.ch, w[0]); \
+        out = lerp<F>(lerp<F>(x00, x10, w[1]), lerp<F>(x01, x11, w[1]), w[2]);                    \
+    }
+    PBR_TRI(x, v[0]);
+    PBR_TRI(y, v[1]);
+    PBR_TRI(z, v[2]);
+    PBR_TRI(w, v[3]);
+#undef PBR_TRI
+    const F n = (F)1 + v[0];
+    D[0] = n * v[1];
+    D[1] = n * v[2];
+    D[2] = n * v[3];
+    return n;
+}
+
+// One step of eqs. 3 and 5 of length lam * h in the parameter t (dR/dt = T, dT/dt = D), in
+// cell units: g[a] = h / spacing[a].  The cell fraction fd is accumulated in FP64: its increment
+// is nearly the same every step, so FP32 rounding of the running sum would err the same way
+// every step and grow linearly with the step count.  Stage points are formed in F.
+template <typename F>
+__device__ __forceinline__ void rkn_step(const TraceParams &P, int c[3], double fd[3], const F Tr[3],
+                                         F dT[3], const F g[3], F hstep, F lam)
+{
+    const F hh = lam * hstep;
+    F f[3], gg[3], T[3], A[3], B[3], C[3], q[3], D[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) { f[a] = (F)fd[a]; gg[a] = lam * g[a]; T[a] = Tr[a] + dT[a]; }
+    sample_D<F>(P, c, f, D);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) { A[a] = hh * D[a]; q[a] = f[a] + gg[a] * ((F)0.5 * T[a] + (F)0.125 * A[a]); }
+    sample_D<F>(P, c, q, D);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) { B[a] = hh * D[a]; q[a] = f[a] + gg[a] * (T[a] + (F)0.5 * B[a]); }
+    sample_D<F>(P, c, q, D);
+    const F sixth = (F)1 / (F)6;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        C[a] = hh * D[a];
+        fd[a] += (double)(gg[a] * (T[a] + (A[a] + (F)2 * B[a]) * sixth));
+        dT[a] = dT[a] + (A[a] + (F)4 * B[a] + C[a]) * sixth;
+        const double o = floor(fd[a]);
+        c[a] += (int)o;
+        fd[a] -= o;
+    }
+}
+
+template <typename T> __device__ __forceinline__ T pick3(const T v[3], int k)
+{
+    return k == 0 ? v[0] : (k == 1 ? v[1] : v[2]);
+}
+
+// Integrate from the cell-local state until the ray leaves the box.  Exit rule: before each
+// step find the smallest straight-line step fraction lam at which the ray reaches a face it moves
+// towards; if lam <= 1 take one step of lam (when lam > 0), then move straight along the new T
+// onto that face.  Returns the number of steps; sets *limited when max_steps is exceeded.
+// (Per-axis values are selected with pick3 / unrolled loops: no dynamically indexed arrays.)
+template <typename F>
+__device__ __forceinline__ int trace_box(const TraceParams &P, int c[3], double fd[3], const F Tr[3],
+                                         F dT[3], bool *limited)
+{
+    const F g[3] = {(F)P.step_cell[0], (F)P.step_cell[1], (F)P.step_cell[2]};
+    const F hstep = (F)P.h;
+    const int last[3] = {P.nx - 1, P.ny - 1, P.nz - 1};
+    int steps = 0;
+    *limited = false;
+    for (;;) {
+        F lam = (F)3.0e38;
+        int ax = -1;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const F v = g[a] * (Tr[a] + dT[a]);
+            F l = (F)3.0e38;
+            if (v > (F)0) l = (F)((double)(last[a] - c[a]) - fd[a]) / v;
+            else if (v < (F)0) l = (F)((double)(-c[a]) - fd[a]) / v;
+            if (l < lam) { lam = l; ax = a; }
+        }
+        if (ax < 0) return steps;  // T == 0
+        if (lam <= (F)1) {
+            const bool up = (pick3<F>(Tr, ax) + pick3<F>(dT, ax)) > (F)0;
+            if (lam > (F)0) { rkn_step<F>(P, c, fd, Tr, dT, g, hstep, lam); ++steps; }
+            const F Tn[3] = {Tr[0] + dT[0], Tr[1] + dT[1], Tr[2] + dT[2]};
+            const F Ta = pick3<F>(Tn, ax);
+            if (up ? (Ta > (F)0) : (Ta < (F)0)) {
+                const int la = pick3<int>(last, ax);
+                const double target = up ? (double)la : 0.0;
+                const double l2 = (target - ((double)pick3<int>(c, ax) + pick3<double>(fd, ax))) /
+                                  ((double)pick3<F>(g, ax) * (double)Ta);
+#pragma unroll
+                for (int b = 0; b < 3; ++b) {
+                    if (b == ax) {
+                        c[b] = up ? la - 1 : 0;
+                        fd[b] = up ? 1.0 : 0.0;
+                    } else {
+                        fd[b] += l2 * (double)g[b] * (double)Tn[b];
+                    }
+                }
+                return steps;
+            }
+            if (steps > P.max_steps) { *limited = true; return steps; }
+            continue;  // turned back by the field within the last step
+        }
+        rkn_step<F>(P, c, fd, Tr, dT, g, hstep, (F)1);
+        if (++steps > P.max_steps) { *limited = true; return steps; }
+    }
+}
+
+// Ray-sphere intersection on the cap around the vertex.  Vertex at lens-frame z = zv, signed
+// radius Rs (centre at zv + Rs).  H: hit point, N: unit normal facing -z near the axis.
+__device__ __forceinline__ bool cap_hit(const double Pp[3], const double u[3], double zv,
+                                        double Rs, double H[3], double N[3])
+{
+    const double qx = Pp[0], qy = Pp[1], qz = Pp[2] - zv;
+    const double b = qx * u[0] + qy * u[1] + qz * u[2] - Rs * u[2];
+    const double cc = qx * qx + qy * qy + qz * qz - 2.0 * Rs * qz;
+    const double disc = b * b - cc;
+    if (!(disc >= 0.0)) return false;
+    const double sq = sqrt(disc);
+    const double den = b >= 0.0 ? -(b + sq) : -(b - sq);
+    if (den == 0.0) return false;
+    const double s = cc / den;  // the smaller root: the cap near the vertex
+    H[0] = Pp[0] + s * u[0];
+    H[1] = Pp[1] + s * u[1];
+    H[2] = Pp[2] + s * u[2];
+    const double ir = 1.0 / Rs;
+    N[0] = H[0] * ir;
+    N[1] = H[1] * ir;
+    N[2] = (H[2] - zv - Rs) * ir;
+    return true;
+}
+
+// Snell's law (eq. 7) in vector form; false on total internal reflection.
+__device__ __forceinline__ bool snell(const double u[3], const double N[3], double n1, double n2,
+                                      double out[3])
+{
+    const double eta = n1 / n2;
+    const double ci = -(u[0] * N[0] + u[1] * N[1] + u[2] * N[2]);
+    const double k = 1.0 - eta * eta * (1.0 - ci * ci);
+    if (k < 0.0) return false;
+    const double m = eta * ci - sqrt(k);
+    out[0] = eta * u[0] + m * N[0];
+    out[1] = eta * u[1] + m * N[1];
+    out[2] = eta * u[2] + m * N[2];
+    return true;
+}
+
+// Aperture, both lens surfaces and the sensor plane (lens frame: z from the front vertex).
+__device__ __forceinline__ int optics_to_sensor(const TraceParams &P, const double R[3], const double u[3],
+                                double *xpx, double *ypx)
+{
+    if (!(u[2] > 0.0)) return PBR_RAY_MISSED;
+    const double s = (P.z_lens - R[2]) / u[2];
+    double A[3] = {R[0] + s * u[0], R[1] + s * u[1], 0.0};
+    if (A[0] * A[0] + A[1] * A[1] > P.a * P.a) return PBR_RAY_BLOCKED_APERTURE;
+    double H1[3], N[3], v[3], w[3], H2[3];
+    if (!cap_hit(A, u, 0.0, P.R, H1, N)) return PBR_RAY_BLOCKED_LENS;
+    if (H1[0] * H1[0] + H1[1] * H1[1] > P.clear * P.clear) return PBR_RAY_BLOCKED_LENS;
+    if (!snell(u, N, P.n_inf, P.n_glass, v)) return PBR_RAY_TIR;
+    if (!cap_hit(H1, v, P.t, -P.R, H2, N)) return PBR_RAY_BLOCKED_LENS;
+    if (H2[0] * H2[0] + H2[1] * H2[1] > P.clear * P.clear) return PBR_RAY_BLOCKED_LENS;
+    if (!snell(v, N, P.n_glass, P.n_inf, w)) return PBR_RAY_TIR;
+    if (!(w[2] > 0.0)) return PBR_RAY_MISSED;
+    const double s2 = (P.z_sensor - P.z_lens - H2[2]) / w[2];
+    *xpx = (H2[0] + s2 * w[0]) / P.pitch + 0.5 * (double)P.W;
+    *ypx = (H2[1] + s2 * w[1]) / P.pitch + 0.5 * (double)P.H;
+    return PBR_RAY_DEPOSITED;
+}
+
+__device__ __forceinline__ void atomic_add_u64(unsigned long long *p, unsigned long long v)
+{
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Spot of one ray: fractions of a Gaussian of sigma_px centred at (x, y) over the pixels of the
+// (2R+1)^2 window around the hit pixel, each as the product of two erf differences (sec. 3.4),
+// times the source weight, rounded to Q32.32 and added to the accumulator.
+template <int RF>
+__device__ __forceinline__ void deposit(const TraceParams &P, double x, double y, double w)
+{
+    const int i0 = (int)x, j0 = (int)y;
+    const double inv = 1.0 / (1.4142135623730950488 * P.sigma_px);
+    float ex[2 * RF + 2], ey[2 * RF + 2];
+#pragma unroll
+    for (int m = 0; m < 2 * RF + 2; ++m) {
+        ex[m] = erff((float)(((double)(i0 - RF + m) - x) * inv));
+        ey[m] = erff((float)(((double)(j0 - RF + m) - y) * inv));
+    }
+    const float wf = (float)w;
+#pragma unroll
+    for (int dj = 0; dj <= 2 * RF; ++dj) {
+        const int jj = j0 - RF + dj;
+        if (jj < 0 || jj >= P.H) continue;
+        const float fy = 0.5f * (ey[dj + 1] - ey[dj]) * wf;
+        unsigned long long *row = P.accum + (size_t)jj * (size_t)P.W;
+#pragma unroll
+        for (int di = 0; di <= 2 * RF; ++di) {
+            const int ii = i0 - RF + di;
+            if (ii < 0 || ii >= P.W) continue;
+            const float cval = 0.5f * (ex[di + 1] - ex[di]) * fy;
+            if (!(cval > 0.0f)) continue;
+            const unsigned long long q = (unsigned long long)rint((double)cval * kTwoPow32);
+            if (q) atomic_add_u64(row + ii, q);
+        }
+    }
+}
+
+template <typename F>
+__global__ void __launch_bounds__(256) k_trace(TraceParams P)
+{
+    __shared__ unsigned long long s_cnt[CNT_SLOTS];
+    if (threadIdx.x < CNT_SLOTS) s_cnt[threadIdx.x] = 0ull;
+    __syncthreads();
+
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t rid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; rid < P.n_rays; rid += stride) {
+        const int64_t s = rid / P.rays_per_src;
+        const int32_t j = (int32_t)(rid - s * P.rays_per_src);
+        const float4 sv = P.src[s];
+        const double S[3] = {(double)sv.x, (double)sv.y, (double)sv.z};
+
+        // sec. 3.1: aperture point by area, direction = unit vector source -> lens point
+        const uint64_t hsh = splitmix64_at(P.seed, ((uint64_t)s << 32) | (uint64_t)(uint32_t)j);
+        const double u1 = (double)(hsh >> 40) * (1.0 / 16777216.0);
+        const double u2 = (double)((hsh >> 16) & 0xFFFFFFull) * (1.0 / 16777216.0);
+        const double rr = P.a * sqrt(u1);
+        double sn, cs;
+        sincos(kTwoPi * u2, &sn, &cs);
+        double u[3] = {rr * cs - S[0], rr * sn - S[1], P.z_lens - S[2]};
+        {
+            const double il = 1.0 / sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+            u[0] *= il; u[1] *= il; u[2] *= il;
+        }
+
+        // box entry (slab test); a source inside the box starts there
+        double Rw[3] = {S[0], S[1], S[2]};
+        bool inside = true;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) inside = inside && S[a] >= P.lo[a] && S[a] <= P.hi[a];
+        bool entered = inside;
+        int eax = -1;
+        if (!inside) {
+            double tn = -1.0e308, tf = 1.0e308;
+            bool ok = true;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                if (u[a] != 0.0) {
+                    const double t1 = (P.lo[a] - S[a]) / u[a], t2 = (P.hi[a] - S[a]) / u[a];
+                    const double nr = t1 < t2 ? t1 : t2, fr = t1 < t2 ? t2 : t1;
+                    if (nr > tn) { tn = nr; eax = a; }
+                    if (fr < tf) tf = fr;
+                } else if (S[a] < P.lo[a] || S[a] > P.hi[a]) {
+                    ok = false;
+                }
+            }
+            if (ok && eax >= 0 && tn <= tf && tn >= 0.0) {
+                entered = true;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) Rw[a] = S[a] + tn * u[a];
+            }
+        }
+
+        int status = PBR_RAY_DEPOSITED;
+        int nsteps = 0;
+        double dir[3] = {u[0], u[1], u[2]};
+        if (entered) {
+            const int nn[3] = {P.nx, P.ny, P.nz};
+            int c[3];
+            double fd[3];
+            F f[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                double p = (Rw[a] - P.origin[a]) / P.spacing[a];
+                if (a == eax) p = u[a] > 0.0 ? 0.0 : (double)(nn[a] - 1);
+                p = p < 0.0 ? 0.0 : p;
+                p = p > (double)(nn[a] - 1) ? (double)(nn[a] - 1) : p;
+                int ci = (int)floor(p);
+                ci = ci > nn[a] - 2 ? nn[a] - 2 : ci;
+                c[a] = ci;
+                fd[a] = p - (double)ci;
+                f[a] = (F)fd[a];
+            }
+            F D0[3];
+            const F n0 = sample_D<F>(P, c, f, D0);
+            F Tr[3], dT[3] = {(F)0, (F)0, (F)0};
+#pragma unroll
+            for (int a = 0; a < 3; ++a) Tr[a] = (F)((double)n0 * u[a]);
+            bool limited = false;
+            nsteps = trace_box<F>(P, c, fd, Tr, dT, &limited);
+            if (limited) {
+                status = PBR_RAY_STEP_LIMIT;
+            } else {
+                double T[3], tn2 = 0.0;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    Rw[a] = P.origin[a] + ((double)c[a] + fd[a]) * P.spacing[a];
+                    T[a] = (double)Tr[a] + (double)dT[a];
+                    tn2 += T[a] * T[a];
+                }
+                const double it = 1.0 / sqrt(tn2);
+#pragma unroll
+                for (int a = 0; a < 3; ++a) dir[a] = T[a] * it;
+            }
+        }
+
+        double xpx = 0.0, ypx = 0.0;
+        if (status == PBR_RAY_DEPOSITED) status = optics_to_sensor(P, Rw, dir, &xpx, &ypx);
+        if (status == PBR_RAY_DEPOSITED &&
+            !(xpx >= 0.0 && ypx >= 0.0 && xpx < (double)P.W && ypx < (double)P.H))
+            status = PBR_RAY_OFF_SENSOR;
+        if (status == PBR_RAY_DEPOSITED) {
+            const double w = sv.w > 0.0f ? (sv.w < 1.0f ? (double)sv.w : 1.0) : 0.0;  // weights live in [0, 1]
+            switch (P.rfp) {
+                case 1: deposit<1>(P, xpx, ypx, w); break;
+                case 2: deposit<2>(P, xpx, ypx, w); break;
+                case 3: deposit<3>(P, xpx, ypx, w); break;
+                case 4: deposit<4>(P, xpx, ypx, w); break;
+                case 5: deposit<5>(P, xpx, ypx, w); break;
+                case 6: deposit<6>(P, xpx, ypx, w); break;
+                case 7: deposit<7>(P, xpx, ypx, w); break;
+                default: deposit<8>(P, xpx, ypx, w); break;
+            }
+        }
+
+        if (P.record && rid >= P.rec_first) {
+            const int64_t off = rid - P.rec_first;
+            const int64_t k = off / P.rec_stride;
+            if (k * P.rec_stride == off && k < P.rec_max) {
+                pbr_ray_exit e;
+                e.ray_id = rid;
+                e.status = status;
+                e.n_steps = nsteps;
+                e.entered = entered ? 1 : 0;
+                e.reserved = 0;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) { e.vol_exit_pos[a] = Rw[a]; e.vol_exit_dir[a] = dir[a]; }
+                e.sensor_px[0] = xpx;
+                e.sensor_px[1] = ypx;
+                P.rec[k] = e;
+            }
+        }
+
+        atomicAdd(&s_cnt[CNT_STATUS + status], 1ull);
+        if (entered) atomicAdd(&s_cnt[CNT_ENTERED], 1ull);
+        atomicAdd(&s_cnt[CNT_STEPS], (unsigned long long)nsteps);
+    }
+
+    __syncthreads();
+    if (threadIdx.x < CNT_STEPS + 1 && s_cnt[threadIdx.x] != 0ull)
+        atomic_add_u64(P.counters + threadIdx.x, s_cnt[threadIdx.x]);
+}
+
+}  // namespace
+
+int launch_trace(const TraceParams &p, bool fp64, hipStream_t stream)
+{
+    if (p.n_rays <= 0) return 0;
+    int64_t blocks = (p.n_rays + 255) / 256;
+    if (blocks > (1 << 20)) blocks = 1 << 20;
+    if (fp64)
+        hipLaunchKernelGGL(k_trace<double>, dim3((unsigned)blocks), dim3(256), 0, stream, p);
+    else
+        hipLaunchKernelGGL(k_trace<float>, dim3((unsigned)blocks), dim3(256), 0, stream, p);
+    return (int)hipGetLastError();
+}
+
+}  // namespace pbr

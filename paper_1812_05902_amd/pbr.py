@@ -1,0 +1,307 @@
+"""Thin ctypes binding of libpbr.so (include/pbr.h).
+
+Functions carry the C names and only marshal arguments: device buffers are torch tensors
+(``tensor.data_ptr()``), the stream is torch's current HIP stream.  Every step of the path runs
+in the library's HIP kernels; there is no Python or CPU fallback, and loading fails loudly when
+the library has not been built.
+
+``Renderer`` bundles one context with the caller-owned buffers the C ABI asks for (field
+workspace, Q32.32 sensor accumulator, exit-record buffer).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpbr.so")
+
+PBR_OK, PBR_ERR_ARG, PBR_ERR_STATE, PBR_ERR_HIP, PBR_ERR_WORKSPACE, PBR_ERR_OVERFLOW = 0, -1, -2, -3, -4, -5
+(PBR_RAY_DEPOSITED, PBR_RAY_OFF_SENSOR, PBR_RAY_BLOCKED_APERTURE, PBR_RAY_BLOCKED_LENS,
+ PBR_RAY_TIR, PBR_RAY_STEP_LIMIT, PBR_RAY_MISSED) = range(7)
+PBR_NUM_STATUS = 7
+PBR_CLEAR_FIRST, PBR_RECORD_EXITS, PBR_PREC_FP64_ALL = 1, 2, 4
+PBR_FMT_RAW_U64, PBR_FMT_F32, PBR_FMT_U16 = 0, 1, 2
+
+EXPORTED = ["pbr_create", "pbr_destroy", "pbr_last_error", "pbr_set_stream",
+            "pbr_field_workspace_bytes", "pbr_set_density_field", "pbr_set_optics",
+            "pbr_set_sensor", "pbr_get_derived", "pbr_set_exit_recording",
+            "pbr_emit_and_trace", "pbr_read_image", "pbr_read_ray_exits"]
+
+
+class PbrError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"pbr error {code}: {msg}")
+        self.code = code
+
+
+class pbr_optics(C.Structure):
+    _fields_ = [("z_front_vertex", C.c_double), ("focal_length", C.c_double),
+                ("f_number", C.c_double), ("thickness", C.c_double), ("n_glass", C.c_double),
+                ("clear_radius", C.c_double), ("z_focus", C.c_double)]
+
+
+class pbr_sensor(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("pitch", C.c_double),
+                ("z_sensor", C.c_double), ("wavelength", C.c_double), ("sigma_px", C.c_double),
+                ("dtau_with_pi", C.c_int32), ("reserved", C.c_int32)]
+
+
+class pbr_derived(C.Structure):
+    _fields_ = [("n_inf", C.c_double), ("lens_radius", C.c_double), ("thickness", C.c_double),
+                ("aperture_radius", C.c_double), ("clear_radius", C.c_double),
+                ("z_sensor", C.c_double), ("magnification", C.c_double), ("sigma_px", C.c_double),
+                ("footprint_r", C.c_int32), ("max_steps", C.c_int32)]
+
+
+class pbr_stats(C.Structure):
+    _fields_ = [("rays", C.c_uint64), ("status", C.c_uint64 * PBR_NUM_STATUS),
+                ("entered_volume", C.c_uint64), ("rkn_steps", C.c_uint64), ("trace_ms", C.c_double)]
+
+
+RAY_EXIT_DTYPE = np.dtype([("ray_id", "<i8"), ("status", "<i4"), ("n_steps", "<i4"),
+                           ("entered", "<i4"), ("reserved", "<i4"), ("vol_exit_pos", "<f8", 3),
+                           ("vol_exit_dir", "<f8", 3), ("sensor_px", "<f8", 2)])
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Loads libpbr.so (after torch, so both share one HIP runtime).  Raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    import torch  # noqa: F401  (binds the process to torch's HIP runtime first)
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_1812_05902_amd.build` "
+                           "(there is no fallback path)")
+    l = C.CDLL(path)
+    P, I, I64, U32, U64, D = C.c_void_p, C.c_int, C.c_int64, C.c_uint32, C.c_uint64, C.c_double
+    sig = {
+        "pbr_create": (I, [C.POINTER(P), I, P]),
+        "pbr_destroy": (None, [P]),
+        "pbr_last_error": (C.c_char_p, [P]),
+        "pbr_set_stream": (I, [P, P]),
+        "pbr_field_workspace_bytes": (C.c_size_t, [I, I, I]),
+        "pbr_set_density_field": (I, [P, P, I, I, I, P, P, D, D, P, C.c_size_t]),
+        "pbr_set_optics": (I, [P, C.POINTER(pbr_optics)]),
+        "pbr_set_sensor": (I, [P, C.POINTER(pbr_sensor), P]),
+        "pbr_get_derived": (I, [P, C.POINTER(pbr_derived)]),
+        "pbr_set_exit_recording": (I, [P, I64, I64, I64, P]),
+        "pbr_emit_and_trace": (I, [P, P, I64, C.c_int32, U64, D, U32, C.POINTER(pbr_stats)]),
+        "pbr_read_image": (I, [P, I, P, D]),
+        "pbr_read_ray_exits": (I, [P, P, I64, I64]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(l, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = l
+    return l
+
+
+def _check(ctx, code):
+    if code != PBR_OK:
+        msg = _lib.pbr_last_error(ctx)
+        raise PbrError(code, msg.decode() if msg else "")
+
+
+def _dptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+# ------------------------------------------------------------------ C names (marshalling only)
+
+def pbr_create(device: int = 0, stream=None):
+    l = load()
+    h = C.c_void_p()
+    code = l.pbr_create(C.byref(h), int(device), stream)
+    if code != PBR_OK:
+        raise PbrError(code, l.pbr_last_error(None).decode())
+    return h
+
+
+def pbr_destroy(ctx):
+    load().pbr_destroy(ctx)
+
+
+def pbr_set_stream(ctx, stream):
+    _check(ctx, load().pbr_set_stream(ctx, stream))
+
+
+def pbr_field_workspace_bytes(nx, ny, nz) -> int:
+    return int(load().pbr_field_workspace_bytes(nx, ny, nz))
+
+
+def pbr_set_density_field(ctx, rho, origin, spacing, K, rho_inf, ws):
+    nz, ny, nx = rho.shape
+    o = (C.c_double * 3)(*origin)
+    s = (C.c_double * 3)(*spacing)
+    _check(ctx, load().pbr_set_density_field(ctx, _dptr(rho), nx, ny, nz, o, s, float(K),
+                                             float(rho_inf), _dptr(ws), ws.numel() * ws.element_size()))
+
+
+def pbr_set_optics(ctx, optics: pbr_optics):
+    _check(ctx, load().pbr_set_optics(ctx, C.byref(optics)))
+
+
+def pbr_set_sensor(ctx, sensor: pbr_sensor, accum):
+    _check(ctx, load().pbr_set_sensor(ctx, C.byref(sensor), _dptr(accum)))
+
+
+def pbr_get_derived(ctx) -> pbr_derived:
+    d = pbr_derived()
+    _check(ctx, load().pbr_get_derived(ctx, C.byref(d)))
+    return d
+
+
+def pbr_set_exit_recording(ctx, first, stride, max_records, buf):
+    _check(ctx, load().pbr_set_exit_recording(ctx, int(first), int(stride), int(max_records), _dptr(buf)))
+
+
+def pbr_emit_and_trace(ctx, src, rays_per_src, seed, ds, flags=0, want_stats=False):
+    st = pbr_stats() if want_stats else None
+    n_src = 0 if src is None else int(src.shape[0])
+    _check(ctx, load().pbr_emit_and_trace(ctx, _dptr(src), n_src, int(rays_per_src), int(seed),
+                                          float(ds), int(flags), C.byref(st) if st is not None else None))
+    return st
+
+
+def pbr_read_image(ctx, fmt, out, gain=0.0):
+    _check(ctx, load().pbr_read_image(ctx, int(fmt), _dptr(out), float(gain)))
+
+
+def pbr_read_ray_exits(ctx, first, count) -> np.ndarray:
+    out = np.zeros(int(count), dtype=RAY_EXIT_DTYPE)
+    _check(ctx, load().pbr_read_ray_exits(ctx, out.ctypes.data_as(C.c_void_p), int(first), int(count)))
+    return out
+
+
+# ------------------------------------------------------------------ convenience wrapper
+
+def stats_dict(st: pbr_stats) -> dict:
+    return dict(rays=int(st.rays), status=[int(x) for x in st.status],
+                entered_volume=int(st.entered_volume), rkn_steps=int(st.rkn_steps),
+                trace_ms=float(st.trace_ms))
+
+
+class Renderer:
+    """One context plus the buffers it needs, on torch's current device and stream."""
+
+    def __init__(self, device=None):
+        import torch
+        self.torch = torch
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        self.stream = torch.cuda.current_stream(self.device)
+        self.ctx = pbr_create(self.device.index, C.c_void_p(self.stream.cuda_stream))
+        self.ws = None
+        self.accum = None
+        self.rec = None
+        self.width = self.height = 0
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None:
+            pbr_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_density_field(self, rho, origin, spacing, K, rho_inf):
+        torch = self.torch
+        rho = torch.as_tensor(rho, dtype=torch.float32, device=self.device).contiguous()
+        nz, ny, nx = rho.shape
+        nb = pbr_field_workspace_bytes(nx, ny, nz)
+        if self.ws is None or self.ws.numel() * 4 < nb:
+            self.ws = torch.empty((nb + 3) // 4, dtype=torch.float32, device=self.device)
+        pbr_set_density_field(self.ctx, rho, origin, spacing, K, rho_inf, self.ws)
+        self._rho_keepalive = rho  # until the stream passes field preparation
+
+    def set_optics(self, z_front_vertex, focal_length, f_number, thickness=0.0, n_glass=1.5,
+                   clear_radius=0.0, z_focus=0.0):
+        o = pbr_optics(z_front_vertex, focal_length, f_number, thickness, n_glass, clear_radius, z_focus)
+        pbr_set_optics(self.ctx, o)
+
+    def set_sensor(self, width, height, pitch, z_sensor=float("nan"), wavelength=532e-9,
+                   sigma_px=0.0, dtau_with_pi=False):
+        torch = self.torch
+        s = pbr_sensor(int(width), int(height), pitch, z_sensor, wavelength, sigma_px,
+                       int(bool(dtau_with_pi)), 0)
+        if self.accum is None or self.accum.numel() != width * height:
+            self.accum = torch.zeros(int(height), int(width), dtype=torch.int64, device=self.device)
+        pbr_set_sensor(self.ctx, s, self.accum)
+        self.width, self.height = int(width), int(height)
+
+    def set_exit_recording(self, first, stride, max_records):
+        torch = self.torch
+        nbytes = int(max_records) * RAY_EXIT_DTYPE.itemsize
+        self.rec = torch.zeros(max(nbytes, 8) // 8, dtype=torch.int64, device=self.device)
+        self.rec_max = int(max_records)
+        pbr_set_exit_recording(self.ctx, first, stride, max_records, self.rec)
+
+    def derived(self) -> dict:
+        d = pbr_get_derived(self.ctx)
+        return {k: getattr(d, k) for k, _ in pbr_derived._fields_}
+
+    def emit_and_trace(self, src, rays_per_src, seed, ds, flags=0, stats=False):
+        torch = self.torch
+        src = torch.as_tensor(src, dtype=torch.float32, device=self.device).contiguous()
+        st = pbr_emit_and_trace(self.ctx, src, rays_per_src, seed, ds, flags, want_stats=stats)
+        self._src_keepalive = src
+        return stats_dict(st) if st is not None else None
+
+    def read_image(self, fmt=PBR_FMT_RAW_U64, gain=0.0):
+        torch = self.torch
+        dt = {PBR_FMT_RAW_U64: torch.int64, PBR_FMT_F32: torch.float32, PBR_FMT_U16: torch.int16}[fmt]
+        out = torch.empty(self.height, self.width, dtype=dt, device=self.device)
+        pbr_read_image(self.ctx, fmt, out, gain)
+        return out
+
+    def read_ray_exits(self, first=0, count=None):
+        if count is None:
+            count = self.rec_max - first
+        return pbr_read_ray_exits(self.ctx, first, count)
+
+    @classmethod
+    def from_scene(cls, scene, rho=None, device=None):
+        """Renderer with field, optics and sensor of an ``inputs.Scene``."""
+        from . import inputs
+        r = cls(device)
+        if rho is None:
+            rho = inputs.density(scene)
+        r.set_density_field(rho, scene.origin, scene.spacing, scene.K, scene.rho_inf)
+        r.set_optics(scene.z_lens, scene.focal_length, scene.f_number, scene.thickness,
+                     scene.n_glass, scene.clear_radius, scene.z_focus)
+        r.set_sensor(scene.width, scene.height, scene.pitch, scene.z_sensor, scene.wavelength,
+                     scene.sigma_px, scene.dtau_with_pi)
+        return r
+
+
+def u64_image_to_numpy(t) -> np.ndarray:
+    """int64 tensor holding uint64 Q32.32 values -> numpy uint64."""
+    return t.cpu().numpy().view(np.uint64)
+
+
+def u16_image_to_numpy(t) -> np.ndarray:
+    return t.cpu().numpy().view(np.uint16)
+
+
+def trace_scene(scene, flags=PBR_CLEAR_FIRST, stats=True, record=None, rho=None, src=None):
+    """Convenience: render a scene; ``record`` = (first, stride, max) for exit records.
+    Returns (renderer, stats dict, records or None)."""
+    from . import inputs
+    r = Renderer.from_scene(scene, rho=rho)
+    if record is not None:
+        r.set_exit_recording(*record)
+        flags |= PBR_RECORD_EXITS
+    if src is None:
+        src = inputs.sources(scene)
+    st = r.emit_and_trace(src, scene.rays_per_src, scene.ray_seed, scene.ds, flags, stats=stats)
+    recs = r.read_ray_exits() if record is not None else None
+    return r, st, recs

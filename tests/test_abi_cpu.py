@@ -1,0 +1,198 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function include/pbr.h
+declares, validates its inputs, and derives the same optics as the oracle (two independent
+derivations: the library uses the paraxial system matrix, the oracle a marginal-ray trace)."""
+import ctypes as C
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1812_05902_amd import inputs, pbr
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+FAKE = 0x10000  # host-only contexts never dereference device pointers
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(pbr.LIB_PATH):
+        from paper_1812_05902_amd import build
+        build.build()
+    return pbr.load()
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "pbr.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(pbr_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_exports_every_declared_function(lib):
+    names = _declared()
+    assert len(names) >= 13
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(pbr.EXPORTED) == names
+
+
+def test_struct_sizes_match_header_layout(lib):
+    # the record layout is part of the ABI: 8 + 4*4 + 6*8 + 2*8 bytes
+    assert pbr.RAY_EXIT_DTYPE.itemsize == 88
+    assert C.sizeof(pbr.pbr_optics) == 56
+    assert C.sizeof(pbr.pbr_sensor) == 48
+    assert C.sizeof(pbr.pbr_stats) == 8 * (1 + 7 + 2) + 8
+
+
+def test_workspace_bytes(lib):
+    assert pbr.pbr_field_workspace_bytes(32, 32, 32) == 32 ** 3 * 16
+    assert pbr.pbr_field_workspace_bytes(512, 512, 512) == 512 ** 3 * 16
+    assert pbr.pbr_field_workspace_bytes(1, 4, 4) == 0
+
+
+def _host_ctx(lib):
+    h = C.c_void_p()
+    assert lib.pbr_create(C.byref(h), -1, None) == pbr.PBR_OK
+    return h
+
+
+def _set_field(lib, h, nx=32, ny=32, nz=32, origin=(0, 0, 0.1), spacing=(1e-3,) * 3, K=2.26e-4,
+               rho_inf=1.2, ws=FAKE, ws_bytes=None, rho=FAKE):
+    o = (C.c_double * 3)(*origin)
+    s = (C.c_double * 3)(*spacing)
+    if ws_bytes is None:
+        ws_bytes = max(pbr.pbr_field_workspace_bytes(nx, ny, nz), 16)
+    return lib.pbr_set_density_field(h, rho, nx, ny, nz, o, s, K, rho_inf, ws, ws_bytes)
+
+
+def _err(lib, h):
+    return lib.pbr_last_error(h).decode()
+
+
+def test_null_context_and_create_errors(lib):
+    assert lib.pbr_set_optics(None, None) == pbr.PBR_ERR_ARG
+    assert lib.pbr_emit_and_trace(None, None, 0, 1, 0, 1e-4, 0, None) == pbr.PBR_ERR_ARG
+    assert lib.pbr_create(None, 0, None) == pbr.PBR_ERR_ARG
+    assert "null" in lib.pbr_last_error(None).decode()
+    lib.pbr_destroy(None)
+
+
+def test_field_validation(lib):
+    h = _host_ctx(lib)
+    try:
+        assert _set_field(lib, h, nx=1) == pbr.PBR_ERR_ARG
+        assert _set_field(lib, h, spacing=(1e-3, 0.0, 1e-3)) == pbr.PBR_ERR_ARG
+        assert _set_field(lib, h, origin=(0, math.nan, 0)) == pbr.PBR_ERR_ARG
+        assert _set_field(lib, h, K=-1.0) == pbr.PBR_ERR_ARG
+        assert _set_field(lib, h, ws_bytes=100) == pbr.PBR_ERR_WORKSPACE
+        assert "workspace" in _err(lib, h)
+        assert _set_field(lib, h, ws=FAKE + 4) == pbr.PBR_ERR_ARG  # misaligned
+        assert _set_field(lib, h, rho=None) == pbr.PBR_ERR_ARG
+        assert _set_field(lib, h) == pbr.PBR_OK
+    finally:
+        lib.pbr_destroy(h)
+
+
+def _optics(**kw):
+    d = dict(z_front_vertex=0.5, focal_length=0.05, f_number=8.0, thickness=0.0, n_glass=1.5,
+             clear_radius=0.0, z_focus=0.0)
+    d.update(kw)
+    return pbr.pbr_optics(**d)
+
+
+def _sensor(**kw):
+    d = dict(width=256, height=256, pitch=20e-6, z_sensor=math.nan, wavelength=532e-9,
+             sigma_px=0.0, dtau_with_pi=0, reserved=0)
+    d.update(kw)
+    return pbr.pbr_sensor(**d)
+
+
+def test_optics_and_sensor_validation(lib):
+    h = _host_ctx(lib)
+    try:
+        for bad in (dict(focal_length=0.0), dict(f_number=-1.0), dict(n_glass=1.0),
+                    dict(thickness=1.0), dict(clear_radius=1e-4), dict(z_focus=math.inf)):
+            assert lib.pbr_set_optics(h, C.byref(_optics(**bad))) == pbr.PBR_ERR_ARG, bad
+        assert lib.pbr_set_optics(h, C.byref(_optics())) == pbr.PBR_OK
+        for bad in (dict(width=0), dict(height=20000), dict(pitch=0.0), dict(wavelength=-1.0),
+                    dict(z_sensor=math.inf)):
+            assert lib.pbr_set_sensor(h, C.byref(_sensor(**bad)), FAKE) == pbr.PBR_ERR_ARG, bad
+        assert lib.pbr_set_sensor(h, C.byref(_sensor()), FAKE + 4) == pbr.PBR_ERR_ARG
+        assert lib.pbr_set_sensor(h, C.byref(_sensor()), None) == pbr.PBR_ERR_ARG
+    finally:
+        lib.pbr_destroy(h)
+
+
+def test_call_order_and_trace_validation(lib):
+    h = _host_ctx(lib)
+    try:
+        st = pbr.pbr_stats()
+        assert lib.pbr_emit_and_trace(h, FAKE, 1, 1, 0, 1e-4, 0, None) == pbr.PBR_ERR_STATE
+        d = pbr.pbr_derived()
+        assert lib.pbr_get_derived(h, C.byref(d)) == pbr.PBR_ERR_STATE
+        assert lib.pbr_read_image(h, 0, FAKE, 0.0) == pbr.PBR_ERR_STATE
+        assert lib.pbr_read_ray_exits(h, None, 0, 1) == pbr.PBR_ERR_STATE
+        assert _set_field(lib, h) == pbr.PBR_OK
+        assert lib.pbr_set_optics(h, C.byref(_optics())) == pbr.PBR_OK
+        assert lib.pbr_set_sensor(h, C.byref(_sensor()), FAKE) == pbr.PBR_OK
+        assert lib.pbr_get_derived(h, C.byref(d)) == pbr.PBR_OK
+        # argument errors come before the host-only state error
+        assert lib.pbr_emit_and_trace(h, FAKE, -1, 1, 0, 1e-4, 0, None) == pbr.PBR_ERR_ARG
+        assert lib.pbr_emit_and_trace(h, FAKE, 1, 0, 0, 1e-4, 0, None) == pbr.PBR_ERR_ARG
+        assert lib.pbr_emit_and_trace(h, FAKE, 1, 1, 0, 0.0, 0, None) == pbr.PBR_ERR_ARG
+        assert lib.pbr_emit_and_trace(h, FAKE, 1, 1, 0, math.nan, 0, None) == pbr.PBR_ERR_ARG
+        assert lib.pbr_emit_and_trace(h, None, 5, 1, 0, 1e-4, 0, None) == pbr.PBR_ERR_ARG
+        assert lib.pbr_emit_and_trace(h, FAKE, 1, 1, 0, 1e-4, 1 << 7, None) == pbr.PBR_ERR_ARG
+        # 2^32 rays could overflow one pixel of the Q32.32 sensor
+        assert lib.pbr_emit_and_trace(h, FAKE, 1 << 20, 1 << 12, 0, 1e-4, 1, C.byref(st)) == pbr.PBR_ERR_OVERFLOW
+        assert lib.pbr_emit_and_trace(h, FAKE, 1, 1, 0, 1e-4, 0, None) == pbr.PBR_ERR_STATE
+        # lens inside or before the box
+        assert lib.pbr_set_optics(h, C.byref(_optics(z_front_vertex=0.12))) == pbr.PBR_OK
+        assert lib.pbr_emit_and_trace(h, FAKE, 1, 1, 0, 1e-4, 0, None) == pbr.PBR_ERR_ARG
+        assert "beyond" in _err(lib, h)
+        # exit recording
+        assert lib.pbr_set_exit_recording(h, -1, 1, 1, FAKE) == pbr.PBR_ERR_ARG
+        assert lib.pbr_set_exit_recording(h, 0, 0, 1, FAKE) == pbr.PBR_ERR_ARG
+        assert lib.pbr_set_exit_recording(h, 0, 1, 5, None) == pbr.PBR_ERR_ARG
+        assert lib.pbr_set_exit_recording(h, 0, 1, 5, FAKE) == pbr.PBR_OK
+        assert lib.pbr_read_ray_exits(h, None, 3, 5) == pbr.PBR_ERR_ARG
+        # spot too wide for the deposit window
+        assert lib.pbr_set_sensor(h, C.byref(_sensor(sigma_px=4.0)), FAKE) == pbr.PBR_OK
+        assert lib.pbr_get_derived(h, C.byref(d)) == pbr.PBR_ERR_ARG
+    finally:
+        lib.pbr_destroy(h)
+
+
+@pytest.mark.parametrize("make", [inputs.tiny_bos,
+                                  lambda: inputs.turbulence_bos(n=16, n_src=1, rays_per_src=1),
+                                  lambda: inputs.tomo_piv_shock(n=8, n_src=1, rays_per_src=1),
+                                  lambda: inputs.tiny_bos().replace(dtau_with_pi=True, f_number=4.0)])
+def test_derived_optics_match_oracle(lib, make):
+    sc = make()
+    h = _host_ctx(lib)
+    try:
+        assert _set_field(lib, h, nx=sc.nx, ny=sc.ny, nz=sc.nz, origin=sc.origin, spacing=sc.spacing,
+                          K=sc.K, rho_inf=sc.rho_inf) == pbr.PBR_OK
+        o = _optics(z_front_vertex=sc.z_lens, focal_length=sc.focal_length, f_number=sc.f_number,
+                    thickness=sc.thickness, n_glass=sc.n_glass, clear_radius=sc.clear_radius,
+                    z_focus=sc.z_focus)
+        assert lib.pbr_set_optics(h, C.byref(o)) == pbr.PBR_OK
+        s = _sensor(width=sc.width, height=sc.height, pitch=sc.pitch, z_sensor=sc.z_sensor,
+                    wavelength=sc.wavelength, sigma_px=sc.sigma_px, dtau_with_pi=int(sc.dtau_with_pi))
+        assert lib.pbr_set_sensor(h, C.byref(s), FAKE) == pbr.PBR_OK
+        d = pbr.pbr_derived()
+        assert lib.pbr_get_derived(h, C.byref(d)) == pbr.PBR_OK
+    finally:
+        lib.pbr_destroy(h)
+    oc = oracle.OracleScene(oracle.cfg_from_scene(sc, field_mode=oracle.BUMP, ana=[1, 0, 1, 0, 0, 0]))
+    assert d.n_inf == pytest.approx(oc.n_inf, rel=1e-15)
+    assert d.lens_radius == pytest.approx(oc.R, rel=1e-13)
+    assert d.thickness == pytest.approx(oc.t, rel=1e-15)
+    assert d.aperture_radius == pytest.approx(oc.a, rel=1e-15)
+    assert d.clear_radius == pytest.approx(oc.clear, rel=1e-15)
+    assert d.z_sensor == pytest.approx(oc.z_sensor, rel=1e-12)
+    assert d.magnification == pytest.approx(oc.M, rel=1e-10)
+    assert d.sigma_px == pytest.approx(oc.sigma_px, rel=1e-10)
+    assert d.footprint_r == oc.r_fp
