@@ -15,8 +15,8 @@
  *     [i, i+1) x [j, j+1) in sensor pixel coordinates x_px = x / pitch + width / 2 (same for y);
  *     the image is not flipped (a real image is inverted).
  *   - "_dev" pointers are device memory of the context's GPU, owned by the caller.  The library
- *     never allocates large buffers: the caller provides the field workspace, the sensor
- *     accumulator and the ray-exit record buffer.  pbr_create allocates one 4 KiB device block
+ *     never allocates large buffers: the caller provides the field workspace, the trace
+ *     workspace, the sensor accumulator and the ray-exit record buffer.  pbr_create allocates one 4 KiB device block
  *     for counters, freed by pbr_destroy.
  *   - All device work is enqueued on the context's HIP stream and is asynchronous unless a
  *     function says it synchronises.  The caller keeps its buffers alive until the stream has
@@ -148,21 +148,34 @@ int pbr_set_stream(pbr_ctx *ctx, void *hip_stream);
 
 /* ---------------------------------------------------------------- inputs */
 
-/* Bytes of field workspace pbr_set_density_field needs for an nx x ny x nz grid (0 if a
- * dimension is below 2). */
+/* Bytes of field workspace pbr_set_density_field needs for an nx x ny x nz grid:
+ * (nx-1)(ny-1)(nz-1) * 128 (0 if a dimension is below 2). */
 size_t pbr_field_workspace_bytes(int nx, int ny, int nz);
 
 /* Density grid (sec. 3.2 and Gladstone-Dale eq. 1).  rho_dev: float32 [nz][ny][nx] node values,
  * x fastest; node (i,j,k) sits at origin + (i,j,k) * spacing.  Enqueues the field preparation
- * kernel, which writes n - 1 = K rho and grad n (central differences inside, second-order
- * one-sided differences on the faces) into ws_dev (ws_bytes >= pbr_field_workspace_bytes).
- * rho_dev may be released once the stream has passed this call; ws_dev must live as long as the
- * context traces with this field.  Outside the box the index is 1 + K rho_inf with no gradient.
- * Errors: ARG (null, dims < 2 or > 65535, nx*ny*nz > 2^34, spacing <= 0, K < 0, non-finite
- * origin/spacing/K/rho_inf), WORKSPACE. */
+ * kernel, which forms n - 1 = K rho and grad n at the nodes (central differences inside,
+ * second-order one-sided differences on the faces) and writes, for every cell, the coefficients
+ * of the trilinear interpolant of these four quantities (128 bytes per cell) into ws_dev
+ * (ws_bytes >= pbr_field_workspace_bytes, 16-byte aligned).  rho_dev may be released once the
+ * stream has passed this call; ws_dev must live as long as the context traces with this field.
+ * Outside the box the index is 1 + K rho_inf with no gradient.
+ * Errors: ARG (null, dims < 2 or > 65535, more than 2^31 - 1 cells, spacing <= 0, K < 0,
+ * non-finite origin/spacing/K/rho_inf), WORKSPACE. */
 int pbr_set_density_field(pbr_ctx *ctx, const float *rho_dev, int nx, int ny, int nz,
                           const double origin[3], const double spacing[3], double K,
                           double rho_inf, void *ws_dev, size_t ws_bytes);
+
+/* Bytes of trace workspace for chunks of rays_per_chunk rays (64 bytes per ray, at least 256
+ * rays).  The trace runs the rays of a call in chunks of this size through three kernels
+ * (emission and box entry, ray-equation integration, lens / sensor / deposit) that hand the ray
+ * state over in this workspace. */
+size_t pbr_trace_workspace_bytes(int64_t rays_per_chunk);
+
+/* Sets the trace workspace (device, 16-byte aligned, >= pbr_trace_workspace_bytes(256) bytes;
+ * the chunk is ws_bytes / 64 rays).  It must live as long as traces use it.
+ * Errors: ARG (null, misaligned), WORKSPACE (too small). */
+int pbr_set_trace_workspace(pbr_ctx *ctx, void *ws_dev, size_t ws_bytes);
 
 /* Lens (sec. 3.3).  Copied; host-side set-up only.  Errors: ARG (null, focal_length <= 0,
  * f_number <= 0, n_glass <= 1, thickness > n_glass * focal_length (no real lens radius),
@@ -193,7 +206,7 @@ int pbr_set_exit_recording(pbr_ctx *ctx, int64_t first, int64_t stride, int64_t 
  * a sqrt(u1) sin 2 pi u2) with (u1, u2) the two 24-bit fields of SplitMix64 output number
  * (s << 32 | j) for `seed`.  ds: arc length per Runge-Kutta step (m, > 0).  With stats_host
  * non-NULL the call synchronises the stream and fills the counters; otherwise it is asynchronous.
- * Errors: STATE (field, optics or sensor missing), ARG (n_src < 0, rays_per_src < 1 or
+ * Errors: STATE (field, optics, sensor or trace workspace missing), ARG (n_src < 0, rays_per_src < 1 or
  * >= 2^31, ds <= 0, lens not beyond the box, source array null with n_src > 0),
  * OVERFLOW (n_src * rays_per_src * 2^32 plus what the accumulator may already hold could exceed
  * 2^64 in one pixel), HIP. */

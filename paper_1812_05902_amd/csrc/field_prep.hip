@@ -1,9 +1,10 @@
 // Field preparation (sec. 3.2): Gladstone-Dale n = K rho + 1 (eq. 1) and the refractive-index
-// gradient at every grid node, written as one float4 (n - 1, dn/dx, dn/dy, dn/dz) per node.
+// gradient at the grid nodes (central differences inside, second-order one-sided differences on
+// the faces), stored per cell as the coefficients of the trilinear interpolant of
+// (n - 1, grad n) over the cell's eight corners (layout in pbr_internal.h).
 //
-// The arithmetic is FP64 (the inputs are float32 densities, the outputs are rounded once to
-// float32), so the stored values are the exact node values to float32 rounding.  The kernel is
-// bound by HBM: 4 B read (plus cached neighbour reads) and 16 B written per node.
+// One thread per cell; all arithmetic in FP64, rounded once to float32 on output.  The kernel
+// streams rho (4 B per node, neighbours from cache) and writes 128 B per cell: HBM-bound.
 #include "pbr_internal.h"
 
 namespace pbr {
@@ -27,21 +28,44 @@ __device__ __forceinline__ double index_derivative(const float *__restrict__ rho
 }
 
 __global__ void __launch_bounds__(256)
-k_field_prep(const float *__restrict__ rho, float4 *__restrict__ node, int nx, int ny, int nz,
+k_field_prep(const float *__restrict__ rho, float4 *__restrict__ cells, int nx, int ny, int nz,
              double kx, double ky, double kz, double K)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y;
     const int k = blockIdx.z;
-    if (i >= nx) return;
+    if (i >= nx - 1) return;
     const size_t sx = 1, sy = (size_t)nx, sz = (size_t)nx * (size_t)ny;
-    const size_t q = (size_t)k * sz + (size_t)j * sy + (size_t)i;
-    float4 out;
-    out.x = (float)(K * (double)rho[q]);
-    out.y = (float)(kx * index_derivative(rho, q, sx, i, nx));
-    out.z = (float)(ky * index_derivative(rho, q, sy, j, ny));
-    out.w = (float)(kz * index_derivative(rho, q, sz, k, nz));
-    node[q] = out;
+    // corner values v[corner][quantity], corner = dx + 2 dy + 4 dz
+    double v[8][4];
+#pragma unroll
+    for (int corner = 0; corner < 8; ++corner) {
+        const int ii = i + (corner & 1), jj = j + ((corner >> 1) & 1), kk = k + (corner >> 2);
+        const size_t q = (size_t)kk * sz + (size_t)jj * sy + (size_t)ii;
+        v[corner][0] = K * (double)rho[q];
+        v[corner][1] = kx * index_derivative(rho, q, sx, ii, nx);
+        v[corner][2] = ky * index_derivative(rho, q, sy, jj, ny);
+        v[corner][3] = kz * index_derivative(rho, q, sz, kk, nz);
+    }
+    double c[8][4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        const double f000 = v[0][m], f100 = v[1][m], f010 = v[2][m], f110 = v[3][m];
+        const double f001 = v[4][m], f101 = v[5][m], f011 = v[6][m], f111 = v[7][m];
+        c[0][m] = f000;
+        c[1][m] = f100 - f000;
+        c[2][m] = f010 - f000;
+        c[3][m] = f001 - f000;
+        c[4][m] = f110 - f100 - f010 + f000;
+        c[5][m] = f101 - f100 - f001 + f000;
+        c[6][m] = f011 - f010 - f001 + f000;
+        c[7][m] = f111 - f110 - f101 - f011 + f100 + f010 + f001 - f000;
+    }
+    const size_t cell = ((size_t)k * (size_t)(ny - 1) + (size_t)j) * (size_t)(nx - 1) + (size_t)i;
+    float4 *out = cells + cell * kCellFloat4;
+#pragma unroll
+    for (int m = 0; m < 8; ++m)
+        out[m] = make_float4((float)c[m][0], (float)c[m][1], (float)c[m][2], (float)c[m][3]);
 }
 
 __global__ void __launch_bounds__(256) k_clear_u64(unsigned long long *p, int64_t n)
@@ -52,12 +76,12 @@ __global__ void __launch_bounds__(256) k_clear_u64(unsigned long long *p, int64_
 
 }  // namespace
 
-int launch_field_prep(const float *rho, float4 *node, int nx, int ny, int nz,
+int launch_field_prep(const float *rho, float4 *cells, int nx, int ny, int nz,
                       const double spacing[3], double K, hipStream_t stream)
 {
     dim3 block(256);
-    dim3 grid((unsigned)((nx + 255) / 256), (unsigned)ny, (unsigned)nz);
-    hipLaunchKernelGGL(k_field_prep, grid, block, 0, stream, rho, node, nx, ny, nz,
+    dim3 grid((unsigned)((nx - 1 + 255) / 256), (unsigned)(ny - 1), (unsigned)(nz - 1));
+    hipLaunchKernelGGL(k_field_prep, grid, block, 0, stream, rho, cells, nx, ny, nz,
                        K / spacing[0], K / spacing[1], K / spacing[2], K);
     return (int)hipGetLastError();
 }

@@ -19,7 +19,7 @@ struct pbr_ctx {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     // field
     bool has_field = false;
-    const float4 *node = nullptr;
+    const float4 *cells = nullptr;
     int nx = 0, ny = 0, nz = 0;
     double origin[3] = {0, 0, 0}, spacing[3] = {0, 0, 0};
     double K = 0.0, rho_inf = 0.0;
@@ -31,6 +31,9 @@ struct pbr_ctx {
     pbr_sensor sensor{};
     unsigned long long *accum = nullptr;
     double accum_rays = 0.0;  // rays deposited since the last clear (overflow bound)
+    // per-ray state between the trace kernels
+    pbr::RayState *ray_ws = nullptr;
+    int64_t ray_chunk = 0;
     // exit recording
     pbr_ray_exit *rec = nullptr;
     int64_t rec_first = 0, rec_stride = 1, rec_max = 0;
@@ -133,7 +136,7 @@ int max_steps_for(const pbr_ctx *c, double ds)
         d2 += e * e;
     }
     const double m = 4.0 * std::ceil(std::sqrt(d2) / ds) + 64.0;
-    return m > 2.0e9 ? 2000000000 : (int)m;
+    return m > 67108864.0 ? 67108864 : (int)m;  // the step count is kept in 27 bits
 }
 
 }  // namespace
@@ -215,7 +218,26 @@ int pbr_set_stream(pbr_ctx *ctx, void *hip_stream)
 size_t pbr_field_workspace_bytes(int nx, int ny, int nz)
 {
     if (nx < 2 || ny < 2 || nz < 2) return 0;
-    return (size_t)nx * (size_t)ny * (size_t)nz * sizeof(float4);
+    return (size_t)(nx - 1) * (size_t)(ny - 1) * (size_t)(nz - 1) * pbr::kCellFloat4 * sizeof(float4);
+}
+
+size_t pbr_trace_workspace_bytes(int64_t rays_per_chunk)
+{
+    if (rays_per_chunk < 256) rays_per_chunk = 256;
+    return (size_t)rays_per_chunk * sizeof(pbr::RayState);
+}
+
+int pbr_set_trace_workspace(pbr_ctx *ctx, void *ws_dev, size_t ws_bytes)
+{
+    if (!ctx) return PBR_ERR_ARG;
+    if (!ws_dev) return fail(ctx, PBR_ERR_ARG, "trace workspace is null");
+    if (((uintptr_t)ws_dev & 15u) != 0) return fail(ctx, PBR_ERR_ARG, "trace workspace must be 16-byte aligned");
+    if (ws_bytes < pbr_trace_workspace_bytes(256))
+        return fail(ctx, PBR_ERR_WORKSPACE, "trace workspace %zu bytes < %zu (256 rays)", ws_bytes,
+                    pbr_trace_workspace_bytes(256));
+    ctx->ray_ws = (pbr::RayState *)ws_dev;
+    ctx->ray_chunk = (int64_t)(ws_bytes / sizeof(pbr::RayState));
+    return PBR_OK;
 }
 
 int pbr_set_density_field(pbr_ctx *ctx, const float *rho_dev, int nx, int ny, int nz,
@@ -227,7 +249,8 @@ int pbr_set_density_field(pbr_ctx *ctx, const float *rho_dev, int nx, int ny, in
     if (!rho_dev || !ws_dev || !origin || !spacing) return fail(ctx, PBR_ERR_ARG, "null pointer argument");
     if (nx < 2 || ny < 2 || nz < 2 || nx > 65535 || ny > 65535 || nz > 65535)
         return fail(ctx, PBR_ERR_ARG, "grid dimensions %d x %d x %d outside [2, 65535]", nx, ny, nz);
-    if ((double)nx * ny * nz > 17179869184.0) return fail(ctx, PBR_ERR_ARG, "grid larger than 2^34 nodes");
+    if ((double)(nx - 1) * (ny - 1) * (nz - 1) > 2147483647.0)
+        return fail(ctx, PBR_ERR_ARG, "grid has more than 2^31 - 1 cells");
     if (!finite3(origin) || !finite3(spacing)) return fail(ctx, PBR_ERR_ARG, "origin/spacing not finite");
     if (!(spacing[0] > 0 && spacing[1] > 0 && spacing[2] > 0)) return fail(ctx, PBR_ERR_ARG, "spacing must be > 0");
     if (!std::isfinite(K) || K < 0.0) return fail(ctx, PBR_ERR_ARG, "K must be finite and >= 0");
@@ -241,7 +264,7 @@ int pbr_set_density_field(pbr_ctx *ctx, const float *rho_dev, int nx, int ny, in
         const int e = pbr::launch_field_prep(rho_dev, (float4 *)ws_dev, nx, ny, nz, spacing, K, ctx->stream);
         if (e) return hip_fail(ctx, e, "field preparation launch");
     }
-    ctx->node = (const float4 *)ws_dev;
+    ctx->cells = (const float4 *)ws_dev;
     ctx->nx = nx; ctx->ny = ny; ctx->nz = nz;
     for (int a = 0; a < 3; ++a) { ctx->origin[a] = origin[a]; ctx->spacing[a] = spacing[a]; }
     ctx->K = K;
@@ -344,6 +367,7 @@ int pbr_emit_and_trace(pbr_ctx *ctx, const float *src_dev, int64_t n_src, int32_
         return fail(ctx, PBR_ERR_ARG, "sensor plane must lie behind the lens");
     if (flags & ~(uint32_t)(PBR_CLEAR_FIRST | PBR_RECORD_EXITS | PBR_PREC_FP64_ALL))
         return fail(ctx, PBR_ERR_ARG, "unknown flag bits 0x%x", flags);
+    if (!ctx->ray_ws) return fail(ctx, PBR_ERR_STATE, "no trace workspace set (pbr_set_trace_workspace)");
     if ((flags & PBR_RECORD_EXITS) && ctx->rec_max > 0 && !ctx->rec)
         return fail(ctx, PBR_ERR_STATE, "no exit recording buffer set");
     const double n_rays_d = (double)n_src * (double)rays_per_src;
@@ -365,7 +389,7 @@ int pbr_emit_and_trace(pbr_ctx *ctx, const float *src_dev, int64_t n_src, int32_
 
     pbr::TraceParams P;
     std::memset(&P, 0, sizeof P);
-    P.node = ctx->node;
+    P.cells = ctx->cells;
     P.nx = ctx->nx; P.ny = ctx->ny; P.nz = ctx->nz;
     P.max_steps = max_steps_for(ctx, ds);
     ctx->last_max_steps = P.max_steps;
@@ -400,8 +424,11 @@ int pbr_emit_and_trace(pbr_ctx *ctx, const float *src_dev, int64_t n_src, int32_
     P.counters = ctx->counters;
 
     if (stats && (e = (int)hipEventRecord(ctx->ev0, ctx->stream))) return hip_fail(ctx, e, "hipEventRecord");
-    e = pbr::launch_trace(P, (flags & PBR_PREC_FP64_ALL) != 0, ctx->stream);
-    if (e) return hip_fail(ctx, e, "trace launch");
+    for (int64_t first = 0; first < P.n_rays; first += ctx->ray_chunk) {
+        const int64_t n = P.n_rays - first < ctx->ray_chunk ? P.n_rays - first : ctx->ray_chunk;
+        e = pbr::launch_trace_chunk(P, ctx->ray_ws, first, n, (flags & PBR_PREC_FP64_ALL) != 0, ctx->stream);
+        if (e) return hip_fail(ctx, e, "trace launch");
+    }
     if (stats && (e = (int)hipEventRecord(ctx->ev1, ctx->stream))) return hip_fail(ctx, e, "hipEventRecord");
     ctx->accum_rays = before + n_rays_d;
 

@@ -19,11 +19,18 @@ enum : int {
 
 constexpr int kMaxFootprint = 8;          // deposit window half-width limit (sigma <= 2.67 px)
 
+// Field layout: one 128-byte record per grid cell, [nz-1][ny-1][nx-1], x fastest.  Record =
+// 8 float4; float4 m holds trilinear coefficient m of the four interpolated quantities
+// (n - 1, dn/dx, dn/dy, dn/dz) in its x, y, z, w lanes, so that inside the cell, at fractions
+// (x, y, z) in [0, 1]^3,
+//   q(x, y, z) = c0 + c1 x + c2 y + c3 z + c4 x y + c5 x z + c6 y z + c7 x y z,
+// which is the trilinear interpolant of the eight corner values.
+constexpr int kCellFloat4 = 8;
+
 // Everything one trace launch reads.  Passed by value as the kernel argument.
 struct TraceParams {
-    // field: float4 (n - 1, dn/dx, dn/dy, dn/dz) per node, [nz][ny][nx]
-    const float4 *node;
-    int nx, ny, nz;
+    const float4 *cells;   // field records (see above)
+    int nx, ny, nz;        // node counts
     int max_steps;
     double origin[3], spacing[3];
     double lo[3], hi[3];
@@ -53,10 +60,27 @@ struct TraceParams {
     unsigned long long *counters;
 };
 
+// Per-ray state between the three trace kernels (emit -> box -> finish), 64 bytes.
+// In the box: cell index c, cell fractions fd (FP64), direction T = Tr + dT (Tr at entry).
+// A ray that never entered keeps its world position in fd and its unit direction as Tr + dT.
+struct RayState {
+    double fd[3];
+    float Tr[3];
+    float dT[3];
+    int c[3];
+    int info;  // RS_* bits, step count above RS_STEP_SHIFT
+};
+static_assert(sizeof(RayState) == 64, "RayState layout");
+enum : int { RS_ENTERED = 1, RS_LIMITED = 2, RS_STEP_SHIFT = 4 };
+
+constexpr int kTile = 32;  // deposit pre-aggregation tile (pixels per side, in LDS)
+
 // Launchers (defined in the .hip files; enqueue on `stream`, return hipError_t as int).
-int launch_field_prep(const float *rho, float4 *node, int nx, int ny, int nz,
+int launch_field_prep(const float *rho, float4 *cells, int nx, int ny, int nz,
                       const double spacing[3], double K, hipStream_t stream);
-int launch_trace(const TraceParams &p, bool fp64, hipStream_t stream);
+// Rays [first, first + n) through all four steps; st: n RayState of workspace.
+int launch_trace_chunk(const TraceParams &p, RayState *st, int64_t first, int64_t n, bool fp64,
+                       hipStream_t stream);
 int launch_readout(const unsigned long long *accum, int64_t npx, int fmt, void *out,
                    double gain, unsigned long long *counters, hipStream_t stream);
 int launch_clear_u64(unsigned long long *p, int64_t n, hipStream_t stream);

@@ -31,13 +31,20 @@ template <typename F> __device__ __forceinline__ F ffloor(F x);
 template <> __device__ __forceinline__ float ffloor<float>(float x) { return floorf(x); }
 template <> __device__ __forceinline__ double ffloor<double>(double x) { return floor(x); }
 
-template <typename F> __device__ __forceinline__ F lerp(F a, F b, F t) { return a + t * (b - a); }
+// The coefficients of the cell the ray is in, held in registers: a stage point only gathers
+// from memory when it lies in another cell (about once per cell crossing, since the three stage
+// points of a step run ahead of the ray).
+struct CellCache {
+    int key;         // linear index of the cached cell, -1 = none
+    float4 c[kCellFloat4];
+};
 
 // Trilinear interpolation of (n - 1, grad n) at the point (cell c, fraction f); the fraction may
 // lie outside [0, 1) (stage points of eq. 5), in which case the point is moved into the cell that
 // holds it and then onto the box.  Returns n, writes D = n grad n (eq. 6).
 template <typename F>
-__device__ __forceinline__ F sample_D(const TraceParams &P, const int c[3], const F f[3], F D[3])
+__device__ __forceinline__ F sample_D(const TraceParams &P, CellCache &cc, const int c[3],
+                                      const F f[3], F D[3])
 {
     const int nmax[3] = {P.nx - 2, P.ny - 2, P.nz - 2};
     int ic[3];
@@ -55,16 +62,21 @@ __device__ __forceinline__ F sample_D(const TraceParams &P, const int c[3], cons
         ic[a] = i;
         w[a] = t;
     }
-    const size_t sy = (size_t)P.nx, sz = (size_t)P.nx * (size_t)P.ny;
-    const float4 *p = P.node + (size_t)ic[2] * sz + (size_t)ic[1] * sy + (size_t)ic[0];
-    const float4 c000 = p[0], c100 = p[1], c010 = p[sy], c110 = p[sy + 1];
-    const float4 c001 = p[sz], c101 = p[sz + 1], c011 = p[sz + sy], c111 = p[sz + sy + 1];
+    const int key = (ic[2] * (P.ny - 1) + ic[1]) * (P.nx - 1) + ic[0];
+    if (key != cc.key) {
+        const float4 *p = P.cells + (size_t)key * kCellFloat4;
+#pragma unroll
+        for (int m = 0; m < kCellFloat4; ++m) cc.c[m] = p[m];
+        cc.key = key;
+    }
+    const F x = w[0], y = w[1], z = w[2];
     F v[4];
-#define PBR_TRI(ch, out)                                                                         \
-    {                                                                                            \
-        const F x00 = lerp<F>((F)c000.ch, (F)c100.ch, w[0]), x10 = lerp<F>((F)c010.ch, (F)c110.ch, w[0]); \
-        const F x01 = lerp<F>((F)c001.ch, (F)c101.ch, w[0]), x11 = lerp<F>((F)c011.ch, (F)c111.ch, w[0]); \
-        out = lerp<F>(lerp<F>(x00, x10, w[1]), lerp<F>(x01, x11, w[1]), w[2]);                    \
+#define PBR_TRI(ch, out)                                                                   \
+    {                                                                                      \
+        const F t1 = (F)cc.c[4].ch + z * (F)cc.c[7].ch;                                    \
+        const F t2 = (F)cc.c[1].ch + y * t1 + z * (F)cc.c[5].ch;                           \
+        const F t3 = (F)cc.c[2].ch + z * (F)cc.c[6].ch;                                    \
+        out = (F)cc.c[0].ch + z * (F)cc.c[3].ch + y * t3 + x * t2;                         \
     }
     PBR_TRI(x, v[0]);
     PBR_TRI(y, v[1]);
@@ -83,20 +95,20 @@ __device__ __forceinline__ F sample_D(const TraceParams &P, const int c[3], cons
 // is nearly the same every step, so FP32 rounding of the running sum would err the same way
 // every step and grow linearly with the step count.  Stage points are formed in F.
 template <typename F>
-__device__ __forceinline__ void rkn_step(const TraceParams &P, int c[3], double fd[3], const F Tr[3],
-                                         F dT[3], const F g[3], F hstep, F lam)
+__device__ __forceinline__ void rkn_step(const TraceParams &P, CellCache &cc, int c[3], double fd[3],
+                                         const F Tr[3], F dT[3], const F g[3], F hstep, F lam)
 {
     const F hh = lam * hstep;
     F f[3], gg[3], T[3], A[3], B[3], C[3], q[3], D[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) { f[a] = (F)fd[a]; gg[a] = lam * g[a]; T[a] = Tr[a] + dT[a]; }
-    sample_D<F>(P, c, f, D);
+    sample_D<F>(P, cc, c, f, D);
 #pragma unroll
     for (int a = 0; a < 3; ++a) { A[a] = hh * D[a]; q[a] = f[a] + gg[a] * ((F)0.5 * T[a] + (F)0.125 * A[a]); }
-    sample_D<F>(P, c, q, D);
+    sample_D<F>(P, cc, c, q, D);
 #pragma unroll
     for (int a = 0; a < 3; ++a) { B[a] = hh * D[a]; q[a] = f[a] + gg[a] * (T[a] + (F)0.5 * B[a]); }
-    sample_D<F>(P, c, q, D);
+    sample_D<F>(P, cc, c, q, D);
     const F sixth = (F)1 / (F)6;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -120,8 +132,8 @@ template <typename T> __device__ __forceinline__ T pick3(const T v[3], int k)
 // onto that face.  Returns the number of steps; sets *limited when max_steps is exceeded.
 // (Per-axis values are selected with pick3 / unrolled loops: no dynamically indexed arrays.)
 template <typename F>
-__device__ __forceinline__ int trace_box(const TraceParams &P, int c[3], double fd[3], const F Tr[3],
-                                         F dT[3], bool *limited)
+__device__ __forceinline__ int trace_box(const TraceParams &P, CellCache &cc, int c[3], double fd[3],
+                                         const F Tr[3], F dT[3], bool *limited)
 {
     const F g[3] = {(F)P.step_cell[0], (F)P.step_cell[1], (F)P.step_cell[2]};
     const F hstep = (F)P.h;
@@ -142,7 +154,7 @@ __device__ __forceinline__ int trace_box(const TraceParams &P, int c[3], double 
         if (ax < 0) return steps;  // T == 0
         if (lam <= (F)1) {
             const bool up = (pick3<F>(Tr, ax) + pick3<F>(dT, ax)) > (F)0;
-            if (lam > (F)0) { rkn_step<F>(P, c, fd, Tr, dT, g, hstep, lam); ++steps; }
+            if (lam > (F)0) { rkn_step<F>(P, cc, c, fd, Tr, dT, g, hstep, lam); ++steps; }
             const F Tn[3] = {Tr[0] + dT[0], Tr[1] + dT[1], Tr[2] + dT[2]};
             const F Ta = pick3<F>(Tn, ax);
             if (up ? (Ta > (F)0) : (Ta < (F)0)) {
@@ -164,7 +176,7 @@ __device__ __forceinline__ int trace_box(const TraceParams &P, int c[3], double 
             if (steps > P.max_steps) { *limited = true; return steps; }
             continue;  // turned back by the field within the last step
         }
-        rkn_step<F>(P, c, fd, Tr, dT, g, hstep, (F)1);
+        rkn_step<F>(P, cc, c, fd, Tr, dT, g, hstep, (F)1);
         if (++steps > P.max_steps) { *limited = true; return steps; }
     }
 }
@@ -235,11 +247,157 @@ __device__ __forceinline__ void atomic_add_u64(unsigned long long *p, unsigned l
     __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Spot of one ray: fractions of a Gaussian of sigma_px centred at (x, y) over the pixels of the
-// (2R+1)^2 window around the hit pixel, each as the product of two erf differences (sec. 3.4),
-// times the source weight, rounded to Q32.32 and added to the accumulator.
+// ------------------------------------------------------------------ kernel 1: emission, entry
+
+// sec. 3.1: ray j of source s aims at the aperture point (a sqrt(u1) cos 2 pi u2,
+// a sqrt(u1) sin 2 pi u2) of the front-vertex plane; (u1, u2) are the two 24-bit fields of
+// SplitMix64 output number (s << 32 | j).  The ray goes straight to the box (slab test) and its
+// state is written cell-local; a ray that never enters keeps its world position and direction.
+__global__ void __launch_bounds__(256) k_emit(TraceParams P, RayState *__restrict__ st, int64_t first,
+                                              int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t rid = first + i;
+    const int64_t s = rid / P.rays_per_src;
+    const int32_t j = (int32_t)(rid - s * P.rays_per_src);
+    const float4 sv = P.src[s];
+    const double S[3] = {(double)sv.x, (double)sv.y, (double)sv.z};
+    const uint64_t hsh = splitmix64_at(P.seed, ((uint64_t)s << 32) | (uint64_t)(uint32_t)j);
+    const double u1 = (double)(hsh >> 40) * (1.0 / 16777216.0);
+    const double u2 = (double)((hsh >> 16) & 0xFFFFFFull) * (1.0 / 16777216.0);
+    const double rr = P.a * sqrt(u1);
+    double sn, cs;
+    sincos(kTwoPi * u2, &sn, &cs);
+    double u[3] = {rr * cs - S[0], rr * sn - S[1], P.z_lens - S[2]};
+    {
+        const double il = 1.0 / sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+        u[0] *= il; u[1] *= il; u[2] *= il;
+    }
+    double Rw[3] = {S[0], S[1], S[2]};
+    bool inside = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) inside = inside && S[a] >= P.lo[a] && S[a] <= P.hi[a];
+    bool entered = inside;
+    int eax = -1;
+    if (!inside) {
+        double tn = -1.0e308, tf = 1.0e308;
+        bool ok = true;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            if (u[a] != 0.0) {
+                const double t1 = (P.lo[a] - S[a]) / u[a], t2 = (P.hi[a] - S[a]) / u[a];
+                const double nr = t1 < t2 ? t1 : t2, fr = t1 < t2 ? t2 : t1;
+                if (nr > tn) { tn = nr; eax = a; }
+                if (fr < tf) tf = fr;
+            } else if (S[a] < P.lo[a] || S[a] > P.hi[a]) {
+                ok = false;
+            }
+        }
+        if (ok && eax >= 0 && tn <= tf && tn >= 0.0) {
+            entered = true;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) Rw[a] = S[a] + tn * u[a];
+        }
+    }
+    RayState r;
+    if (!entered) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            r.fd[a] = Rw[a];
+            r.Tr[a] = (float)u[a];
+            r.dT[a] = (float)(u[a] - (double)r.Tr[a]);  // direction kept as a float hi/lo pair
+            r.c[a] = 0;
+        }
+        r.info = 0;
+        st[i] = r;
+        return;
+    }
+    const int nn[3] = {P.nx, P.ny, P.nz};
+    float f[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        double p = (Rw[a] - P.origin[a]) / P.spacing[a];
+        if (a == eax) p = u[a] > 0.0 ? 0.0 : (double)(nn[a] - 1);
+        p = p < 0.0 ? 0.0 : p;
+        p = p > (double)(nn[a] - 1) ? (double)(nn[a] - 1) : p;
+        int ci = (int)floor(p);
+        ci = ci > nn[a] - 2 ? nn[a] - 2 : ci;
+        r.c[a] = ci;
+        r.fd[a] = p - (double)ci;
+        f[a] = (float)r.fd[a];
+    }
+    // inside: T = n dR/ds = n u (eq. 4), n interpolated at the entry point
+    CellCache cc;
+    cc.key = -1;
+    float D0[3];
+    const float n0 = sample_D<float>(P, cc, r.c, f, D0);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {  // T0 as a float hi/lo pair: no rounding of the entry direction
+        const double T0 = (double)n0 * u[a];
+        r.Tr[a] = (float)T0;
+        r.dT[a] = (float)(T0 - (double)r.Tr[a]);
+    }
+    r.info = RS_ENTERED;
+    st[i] = r;
+}
+
+// ------------------------------------------------------------------ kernel 2: the ray equation
+
+template <typename F>
+__device__ __forceinline__ void box_body(const TraceParams &P, RayState *__restrict__ st, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    RayState r = st[i];
+    if (!(r.info & RS_ENTERED)) return;
+    // T = Tr + dT; in FP32 the low part of the entry direction starts the accumulated change
+    F Tr[3], dT[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (sizeof(F) == sizeof(float)) {
+            Tr[a] = (F)r.Tr[a];
+            dT[a] = (F)r.dT[a];
+        } else {
+            Tr[a] = (F)((double)r.Tr[a] + (double)r.dT[a]);
+            dT[a] = (F)0;
+        }
+    }
+    CellCache cc;
+    cc.key = -1;
+    bool limited = false;
+    const int steps = trace_box<F>(P, cc, r.c, r.fd, Tr, dT, &limited);
+    // exit direction as a float hi/lo pair (about 48 significant bits)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double T = (double)Tr[a] + (double)dT[a];
+        r.Tr[a] = (float)T;
+        r.dT[a] = (float)(T - (double)r.Tr[a]);
+    }
+    r.info = RS_ENTERED | (limited ? RS_LIMITED : 0) | (steps << RS_STEP_SHIFT);
+    st[i] = r;
+}
+
+// FP32 integration: 96 VGPRs, five waves per SIMD.
+__global__ void __launch_bounds__(256, 5) k_box32(TraceParams P, RayState *__restrict__ st, int64_t n)
+{
+    box_body<float>(P, st, n);
+}
+
+__global__ void __launch_bounds__(256) k_box64(TraceParams P, RayState *__restrict__ st, int64_t n)
+{
+    box_body<double>(P, st, n);
+}
+
+// ------------------------------------------------------------------ kernel 3: lens, sensor, spot
+
+// Spot of one ray (sec. 3.4): fractions of a Gaussian of sigma_px centred at (x, y) over the
+// pixels of the (2R+1)^2 window around the hit pixel, each the product of two erf differences,
+// times the source weight, rounded to Q32.32.  Pixels inside the block's LDS tile are summed
+// there first (integer adds, so the order does not matter); the others go straight to HBM.
 template <int RF>
-__device__ __forceinline__ void deposit(const TraceParams &P, double x, double y, double w)
+__device__ __forceinline__ void deposit(const TraceParams &P, double x, double y, double w,
+                                        unsigned long long *tile, int tx0, int ty0)
 {
     const int i0 = (int)x, j0 = (int)y;
     const double inv = 1.0 / (1.4142135623730950488 * P.sigma_px);
@@ -255,7 +413,6 @@ __device__ __forceinline__ void deposit(const TraceParams &P, double x, double y
         const int jj = j0 - RF + dj;
         if (jj < 0 || jj >= P.H) continue;
         const float fy = 0.5f * (ey[dj + 1] - ey[dj]) * wf;
-        unsigned long long *row = P.accum + (size_t)jj * (size_t)P.W;
 #pragma unroll
         for (int di = 0; di <= 2 * RF; ++di) {
             const int ii = i0 - RF + di;
@@ -263,167 +420,135 @@ __device__ __forceinline__ void deposit(const TraceParams &P, double x, double y
             const float cval = 0.5f * (ex[di + 1] - ex[di]) * fy;
             if (!(cval > 0.0f)) continue;
             const unsigned long long q = (unsigned long long)rint((double)cval * kTwoPow32);
-            if (q) atomic_add_u64(row + ii, q);
+            if (!q) continue;
+            const int lx = ii - tx0, ly = jj - ty0;
+            if ((unsigned)lx < (unsigned)kTile && (unsigned)ly < (unsigned)kTile)
+                atomicAdd(tile + ly * kTile + lx, q);
+            else
+                atomic_add_u64(P.accum + (size_t)jj * (size_t)P.W + ii, q);
         }
     }
 }
 
-template <typename F>
-__global__ void __launch_bounds__(256) k_trace(TraceParams P)
+__global__ void __launch_bounds__(256) k_finish(TraceParams P, const RayState *__restrict__ st,
+                                                int64_t first, int64_t n)
 {
+    __shared__ unsigned long long tile[kTile * kTile];
     __shared__ unsigned long long s_cnt[CNT_SLOTS];
+    __shared__ int s_lead, s_tx0, s_ty0;
     if (threadIdx.x < CNT_SLOTS) s_cnt[threadIdx.x] = 0ull;
-    __syncthreads();
 
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t rid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; rid < P.n_rays; rid += stride) {
-        const int64_t s = rid / P.rays_per_src;
-        const int32_t j = (int32_t)(rid - s * P.rays_per_src);
-        const float4 sv = P.src[s];
-        const double S[3] = {(double)sv.x, (double)sv.y, (double)sv.z};
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += (int64_t)gridDim.x * blockDim.x) {
+        for (int q = threadIdx.x; q < kTile * kTile; q += blockDim.x) tile[q] = 0ull;
+        if (threadIdx.x == 0) s_lead = 0x7fffffff;
+        __syncthreads();
 
-        // sec. 3.1: aperture point by area, direction = unit vector source -> lens point
-        const uint64_t hsh = splitmix64_at(P.seed, ((uint64_t)s << 32) | (uint64_t)(uint32_t)j);
-        const double u1 = (double)(hsh >> 40) * (1.0 / 16777216.0);
-        const double u2 = (double)((hsh >> 16) & 0xFFFFFFull) * (1.0 / 16777216.0);
-        const double rr = P.a * sqrt(u1);
-        double sn, cs;
-        sincos(kTwoPi * u2, &sn, &cs);
-        double u[3] = {rr * cs - S[0], rr * sn - S[1], P.z_lens - S[2]};
-        {
-            const double il = 1.0 / sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-            u[0] *= il; u[1] *= il; u[2] *= il;
-        }
-
-        // box entry (slab test); a source inside the box starts there
-        double Rw[3] = {S[0], S[1], S[2]};
-        bool inside = true;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) inside = inside && S[a] >= P.lo[a] && S[a] <= P.hi[a];
-        bool entered = inside;
-        int eax = -1;
-        if (!inside) {
-            double tn = -1.0e308, tf = 1.0e308;
-            bool ok = true;
+        const int64_t i = base + threadIdx.x;
+        const bool valid = i < n;
+        int status = PBR_RAY_MISSED, nsteps = 0;
+        bool entered = false;
+        double Rw[3] = {0, 0, 0}, dir[3] = {0, 0, 1}, xpx = 0.0, ypx = 0.0;
+        if (valid) {
+            const RayState r = st[i];
+            entered = (r.info & RS_ENTERED) != 0;
+            nsteps = entered ? (r.info >> RS_STEP_SHIFT) : 0;
+            status = PBR_RAY_DEPOSITED;
+            double tn2 = 0.0, T[3];
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                if (u[a] != 0.0) {
-                    const double t1 = (P.lo[a] - S[a]) / u[a], t2 = (P.hi[a] - S[a]) / u[a];
-                    const double nr = t1 < t2 ? t1 : t2, fr = t1 < t2 ? t2 : t1;
-                    if (nr > tn) { tn = nr; eax = a; }
-                    if (fr < tf) tf = fr;
-                } else if (S[a] < P.lo[a] || S[a] > P.hi[a]) {
-                    ok = false;
-                }
+                Rw[a] = entered ? P.origin[a] + ((double)r.c[a] + r.fd[a]) * P.spacing[a] : r.fd[a];
+                T[a] = (double)r.Tr[a] + (double)r.dT[a];
+                tn2 += T[a] * T[a];
             }
-            if (ok && eax >= 0 && tn <= tf && tn >= 0.0) {
-                entered = true;
+            const double it = 1.0 / sqrt(tn2);
 #pragma unroll
-                for (int a = 0; a < 3; ++a) Rw[a] = S[a] + tn * u[a];
-            }
+            for (int a = 0; a < 3; ++a) dir[a] = T[a] * it;
+            if (r.info & RS_LIMITED) status = PBR_RAY_STEP_LIMIT;
+            if (status == PBR_RAY_DEPOSITED) status = optics_to_sensor(P, Rw, dir, &xpx, &ypx);
+            if (status == PBR_RAY_DEPOSITED &&
+                !(xpx >= 0.0 && ypx >= 0.0 && xpx < (double)P.W && ypx < (double)P.H))
+                status = PBR_RAY_OFF_SENSOR;
+            if (status == PBR_RAY_DEPOSITED) atomicMin(&s_lead, (int)threadIdx.x);
         }
-
-        int status = PBR_RAY_DEPOSITED;
-        int nsteps = 0;
-        double dir[3] = {u[0], u[1], u[2]};
-        if (entered) {
-            const int nn[3] = {P.nx, P.ny, P.nz};
-            int c[3];
-            double fd[3];
-            F f[3];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                double p = (Rw[a] - P.origin[a]) / P.spacing[a];
-                if (a == eax) p = u[a] > 0.0 ? 0.0 : (double)(nn[a] - 1);
-                p = p < 0.0 ? 0.0 : p;
-                p = p > (double)(nn[a] - 1) ? (double)(nn[a] - 1) : p;
-                int ci = (int)floor(p);
-                ci = ci > nn[a] - 2 ? nn[a] - 2 : ci;
-                c[a] = ci;
-                fd[a] = p - (double)ci;
-                f[a] = (F)fd[a];
-            }
-            F D0[3];
-            const F n0 = sample_D<F>(P, c, f, D0);
-            F Tr[3], dT[3] = {(F)0, (F)0, (F)0};
-#pragma unroll
-            for (int a = 0; a < 3; ++a) Tr[a] = (F)((double)n0 * u[a]);
-            bool limited = false;
-            nsteps = trace_box<F>(P, c, fd, Tr, dT, &limited);
-            if (limited) {
-                status = PBR_RAY_STEP_LIMIT;
-            } else {
-                double T[3], tn2 = 0.0;
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    Rw[a] = P.origin[a] + ((double)c[a] + fd[a]) * P.spacing[a];
-                    T[a] = (double)Tr[a] + (double)dT[a];
-                    tn2 += T[a] * T[a];
-                }
-                const double it = 1.0 / sqrt(tn2);
-#pragma unroll
-                for (int a = 0; a < 3; ++a) dir[a] = T[a] * it;
-            }
+        __syncthreads();
+        // the block's first deposited ray anchors the tile: rays of one source land close together
+        if ((int)threadIdx.x == s_lead) {
+            s_tx0 = (int)xpx - kTile / 2;
+            s_ty0 = (int)ypx - kTile / 2;
         }
-
-        double xpx = 0.0, ypx = 0.0;
-        if (status == PBR_RAY_DEPOSITED) status = optics_to_sensor(P, Rw, dir, &xpx, &ypx);
-        if (status == PBR_RAY_DEPOSITED &&
-            !(xpx >= 0.0 && ypx >= 0.0 && xpx < (double)P.W && ypx < (double)P.H))
-            status = PBR_RAY_OFF_SENSOR;
-        if (status == PBR_RAY_DEPOSITED) {
-            const double w = sv.w > 0.0f ? (sv.w < 1.0f ? (double)sv.w : 1.0) : 0.0;  // weights live in [0, 1]
+        __syncthreads();
+        if (valid && status == PBR_RAY_DEPOSITED) {
+            const int64_t rid = first + i;
+            const float4 sv = P.src[rid / P.rays_per_src];
+            const double w = sv.w > 0.0f ? (sv.w < 1.0f ? (double)sv.w : 1.0) : 0.0;  // weights in [0, 1]
+            const int tx0 = s_tx0, ty0 = s_ty0;
             switch (P.rfp) {
-                case 1: deposit<1>(P, xpx, ypx, w); break;
-                case 2: deposit<2>(P, xpx, ypx, w); break;
-                case 3: deposit<3>(P, xpx, ypx, w); break;
-                case 4: deposit<4>(P, xpx, ypx, w); break;
-                case 5: deposit<5>(P, xpx, ypx, w); break;
-                case 6: deposit<6>(P, xpx, ypx, w); break;
-                case 7: deposit<7>(P, xpx, ypx, w); break;
-                default: deposit<8>(P, xpx, ypx, w); break;
+                case 1: deposit<1>(P, xpx, ypx, w, tile, tx0, ty0); break;
+                case 2: deposit<2>(P, xpx, ypx, w, tile, tx0, ty0); break;
+                case 3: deposit<3>(P, xpx, ypx, w, tile, tx0, ty0); break;
+                case 4: deposit<4>(P, xpx, ypx, w, tile, tx0, ty0); break;
+                case 5: deposit<5>(P, xpx, ypx, w, tile, tx0, ty0); break;
+                case 6: deposit<6>(P, xpx, ypx, w, tile, tx0, ty0); break;
+                case 7: deposit<7>(P, xpx, ypx, w, tile, tx0, ty0); break;
+                default: deposit<8>(P, xpx, ypx, w, tile, tx0, ty0); break;
             }
         }
-
-        if (P.record && rid >= P.rec_first) {
-            const int64_t off = rid - P.rec_first;
-            const int64_t k = off / P.rec_stride;
-            if (k * P.rec_stride == off && k < P.rec_max) {
-                pbr_ray_exit e;
-                e.ray_id = rid;
-                e.status = status;
-                e.n_steps = nsteps;
-                e.entered = entered ? 1 : 0;
-                e.reserved = 0;
+        if (valid) {
+            const int64_t rid = first + i;
+            if (P.record && rid >= P.rec_first) {
+                const int64_t off = rid - P.rec_first;
+                const int64_t k = off / P.rec_stride;
+                if (k * P.rec_stride == off && k < P.rec_max) {
+                    pbr_ray_exit e;
+                    e.ray_id = rid;
+                    e.status = status;
+                    e.n_steps = nsteps;
+                    e.entered = entered ? 1 : 0;
+                    e.reserved = 0;
 #pragma unroll
-                for (int a = 0; a < 3; ++a) { e.vol_exit_pos[a] = Rw[a]; e.vol_exit_dir[a] = dir[a]; }
-                e.sensor_px[0] = xpx;
-                e.sensor_px[1] = ypx;
-                P.rec[k] = e;
+                    for (int a = 0; a < 3; ++a) { e.vol_exit_pos[a] = Rw[a]; e.vol_exit_dir[a] = dir[a]; }
+                    e.sensor_px[0] = xpx;
+                    e.sensor_px[1] = ypx;
+                    P.rec[k] = e;
+                }
+            }
+            atomicAdd(&s_cnt[CNT_STATUS + status], 1ull);
+            if (entered) atomicAdd(&s_cnt[CNT_ENTERED], 1ull);
+            atomicAdd(&s_cnt[CNT_STEPS], (unsigned long long)nsteps);
+        }
+        __syncthreads();
+        // flush the tile: one global atomic per touched pixel
+        if (s_lead != 0x7fffffff) {
+            const int tx0 = s_tx0, ty0 = s_ty0;
+            for (int q = threadIdx.x; q < kTile * kTile; q += blockDim.x) {
+                const unsigned long long v = tile[q];
+                if (v) atomic_add_u64(P.accum + (size_t)(ty0 + q / kTile) * (size_t)P.W + (tx0 + q % kTile), v);
             }
         }
-
-        atomicAdd(&s_cnt[CNT_STATUS + status], 1ull);
-        if (entered) atomicAdd(&s_cnt[CNT_ENTERED], 1ull);
-        atomicAdd(&s_cnt[CNT_STEPS], (unsigned long long)nsteps);
+        __syncthreads();
     }
-
-    __syncthreads();
     if (threadIdx.x < CNT_STEPS + 1 && s_cnt[threadIdx.x] != 0ull)
         atomic_add_u64(P.counters + threadIdx.x, s_cnt[threadIdx.x]);
 }
 
 }  // namespace
 
-int launch_trace(const TraceParams &p, bool fp64, hipStream_t stream)
+int launch_trace_chunk(const TraceParams &p, RayState *st, int64_t first, int64_t n, bool fp64,
+                       hipStream_t stream)
 {
-    if (p.n_rays <= 0) return 0;
-    int64_t blocks = (p.n_rays + 255) / 256;
-    if (blocks > (1 << 20)) blocks = 1 << 20;
+    if (n <= 0) return 0;
+    const unsigned blocks = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL(k_emit, dim3(blocks), dim3(256), 0, stream, p, st, first, n);
+    int e = (int)hipGetLastError();
+    if (e) return e;
     if (fp64)
-        hipLaunchKernelGGL(k_trace<double>, dim3((unsigned)blocks), dim3(256), 0, stream, p);
+        hipLaunchKernelGGL(k_box64, dim3(blocks), dim3(256), 0, stream, p, st, n);
     else
-        hipLaunchKernelGGL(k_trace<float>, dim3((unsigned)blocks), dim3(256), 0, stream, p);
+        hipLaunchKernelGGL(k_box32, dim3(blocks), dim3(256), 0, stream, p, st, n);
+    e = (int)hipGetLastError();
+    if (e) return e;
+    unsigned fblocks = blocks < 4096u ? blocks : 4096u;
+    hipLaunchKernelGGL(k_finish, dim3(fblocks), dim3(256), 0, stream, p, (const RayState *)st, first, n);
     return (int)hipGetLastError();
 }
 

@@ -27,7 +27,8 @@ PBR_CLEAR_FIRST, PBR_RECORD_EXITS, PBR_PREC_FP64_ALL = 1, 2, 4
 PBR_FMT_RAW_U64, PBR_FMT_F32, PBR_FMT_U16 = 0, 1, 2
 
 EXPORTED = ["pbr_create", "pbr_destroy", "pbr_last_error", "pbr_set_stream",
-            "pbr_field_workspace_bytes", "pbr_set_density_field", "pbr_set_optics",
+            "pbr_field_workspace_bytes", "pbr_trace_workspace_bytes", "pbr_set_trace_workspace",
+            "pbr_set_density_field", "pbr_set_optics",
             "pbr_set_sensor", "pbr_get_derived", "pbr_set_exit_recording",
             "pbr_emit_and_trace", "pbr_read_image", "pbr_read_ray_exits"]
 
@@ -86,6 +87,8 @@ def load(path: str = LIB_PATH):
         "pbr_last_error": (C.c_char_p, [P]),
         "pbr_set_stream": (I, [P, P]),
         "pbr_field_workspace_bytes": (C.c_size_t, [I, I, I]),
+        "pbr_trace_workspace_bytes": (C.c_size_t, [I64]),
+        "pbr_set_trace_workspace": (I, [P, P, C.c_size_t]),
         "pbr_set_density_field": (I, [P, P, I, I, I, P, P, D, D, P, C.c_size_t]),
         "pbr_set_optics": (I, [P, C.POINTER(pbr_optics)]),
         "pbr_set_sensor": (I, [P, C.POINTER(pbr_sensor), P]),
@@ -134,6 +137,14 @@ def pbr_set_stream(ctx, stream):
 
 def pbr_field_workspace_bytes(nx, ny, nz) -> int:
     return int(load().pbr_field_workspace_bytes(nx, ny, nz))
+
+
+def pbr_trace_workspace_bytes(rays_per_chunk) -> int:
+    return int(load().pbr_trace_workspace_bytes(int(rays_per_chunk)))
+
+
+def pbr_set_trace_workspace(ctx, ws):
+    _check(ctx, load().pbr_set_trace_workspace(ctx, _dptr(ws), ws.numel() * ws.element_size()))
 
 
 def pbr_set_density_field(ctx, rho, origin, spacing, K, rho_inf, ws):
@@ -191,12 +202,15 @@ def stats_dict(st: pbr_stats) -> dict:
 class Renderer:
     """One context plus the buffers it needs, on torch's current device and stream."""
 
-    def __init__(self, device=None):
+    def __init__(self, device=None, rays_per_chunk=1 << 22):
         import torch
         self.torch = torch
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
         self.stream = torch.cuda.current_stream(self.device)
         self.ctx = pbr_create(self.device.index, C.c_void_p(self.stream.cuda_stream))
+        nb = pbr_trace_workspace_bytes(rays_per_chunk)
+        self.trace_ws = torch.empty(nb // 8, dtype=torch.int64, device=self.device)
+        pbr_set_trace_workspace(self.ctx, self.trace_ws)
         self.ws = None
         self.accum = None
         self.rec = None

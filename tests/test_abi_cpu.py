@@ -32,7 +32,7 @@ def _declared():
 
 def test_exports_every_declared_function(lib):
     names = _declared()
-    assert len(names) >= 13
+    assert len(names) >= 15
     for n in names:
         assert hasattr(lib, n), n
     assert sorted(pbr.EXPORTED) == names
@@ -47,9 +47,13 @@ def test_struct_sizes_match_header_layout(lib):
 
 
 def test_workspace_bytes(lib):
-    assert pbr.pbr_field_workspace_bytes(32, 32, 32) == 32 ** 3 * 16
-    assert pbr.pbr_field_workspace_bytes(512, 512, 512) == 512 ** 3 * 16
+    # 128 bytes of trilinear coefficients per cell
+    assert pbr.pbr_field_workspace_bytes(32, 32, 32) == 31 ** 3 * 128
+    assert pbr.pbr_field_workspace_bytes(512, 512, 512) == 511 ** 3 * 128
     assert pbr.pbr_field_workspace_bytes(1, 4, 4) == 0
+    # 64 bytes of ray state per ray of a chunk, at least 256 rays
+    assert pbr.pbr_trace_workspace_bytes(1 << 22) == (1 << 22) * 64
+    assert pbr.pbr_trace_workspace_bytes(10) == 256 * 64
 
 
 def _host_ctx(lib):
@@ -138,6 +142,12 @@ def test_call_order_and_trace_validation(lib):
         assert lib.pbr_set_optics(h, C.byref(_optics())) == pbr.PBR_OK
         assert lib.pbr_set_sensor(h, C.byref(_sensor()), FAKE) == pbr.PBR_OK
         assert lib.pbr_get_derived(h, C.byref(d)) == pbr.PBR_OK
+        assert lib.pbr_emit_and_trace(h, FAKE, 1, 1, 0, 1e-4, 0, None) == pbr.PBR_ERR_STATE
+        assert "trace workspace" in _err(lib, h)
+        assert lib.pbr_set_trace_workspace(h, None, 1 << 20) == pbr.PBR_ERR_ARG
+        assert lib.pbr_set_trace_workspace(h, FAKE + 8, 1 << 20) == pbr.PBR_ERR_ARG
+        assert lib.pbr_set_trace_workspace(h, FAKE, 1000) == pbr.PBR_ERR_WORKSPACE
+        assert lib.pbr_set_trace_workspace(h, FAKE, 1 << 20) == pbr.PBR_OK
         # argument errors come before the host-only state error
         assert lib.pbr_emit_and_trace(h, FAKE, -1, 1, 0, 1e-4, 0, None) == pbr.PBR_ERR_ARG
         assert lib.pbr_emit_and_trace(h, FAKE, 1, 0, 0, 1e-4, 0, None) == pbr.PBR_ERR_ARG
