@@ -49,12 +49,12 @@ def _traffic_from_profile():
     return d.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(scene, rho, src, target_s: float = 12.0):
+def cpu_baseline(scene, rho, src, target_s: float = 15.0):
     """FP64 oracle on a prefix of the sources, all host threads; rays/s."""
     import oracle
     o = oracle.scene_oracle(scene, rho=rho)
     threads = oracle.num_threads()
-    n_cal = max(threads, 16)
+    n_cal = 4 * threads
     t0 = time.perf_counter()
     o.render(src[:n_cal], scene.rays_per_src, want_float=False)
     t_cal = time.perf_counter() - t0
@@ -74,7 +74,19 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only copy a 1 GiB device buffer 4 times (calibrates HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(4):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": a.numel() * 4, "copy_probe_bytes_written": b.numel() * 4,
+                          "launches": 4}))
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the renderer has no "
               "multi-GPU path in this build", file=sys.stderr)
@@ -97,19 +109,22 @@ def main():
     for _ in range(args.warmup):
         step(False)
     torch.cuda.synchronize()
-    kernel_ms, steps_total = [], 0
+    box_ms, box_launches, trace_ms, steps_total = 0.0, 0, 0.0, 0
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        st = step(True)  # HIP events around the trace launch, on the launch stream
-        kernel_ms.append(st["trace_ms"])
+        # HIP events on the launch stream around each integration launch and around the trace
+        st = step(True)
+        box_ms += st["box_ms"]
+        box_launches += st["box_launches"]
+        trace_ms += st["trace_ms"]
         steps_total += st["rkn_steps"]
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
 
     n_rays = scene.n_rays
     value = n_rays * args.steps / wall
-    avg_ms = sum(kernel_ms) / len(kernel_ms)
-    flops_per_launch = steps_total / args.steps * FLOPS_PER_STEP
+    avg_ms = box_ms / box_launches
+    flops_per_launch = steps_total * FLOPS_PER_STEP / box_launches
     achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12
     out = {
         "metric": "rays/sec on 1 MI355X (trace+lens+sensor)",
@@ -131,7 +146,9 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
                      "traffic": _traffic_from_profile(),
-                     "kernel": "k_trace<float>", "kernel_ms": avg_ms,
+                     "kernel": "k_box32", "kernel_ms_per_launch": avg_ms,
+                     "launches_per_step": box_launches / args.steps,
+                     "trace_ms_per_step": trace_ms / args.steps,
                      "flops_per_rkn_step": FLOPS_PER_STEP},
     }
     if not args.no_cpu_baseline:

@@ -109,7 +109,9 @@ typedef struct pbr_stats {
     uint64_t status[PBR_NUM_STATUS];   /* rays per PBR_RAY_* status (sums to rays) */
     uint64_t entered_volume;           /* rays that entered the density box */
     uint64_t rkn_steps;                /* Runge-Kutta steps taken (all rays) */
-    double trace_ms;                   /* device time of the trace kernel(s) (HIP events) */
+    double trace_ms;                   /* device time of the whole trace (HIP events) */
+    double box_ms;                     /* device time of the integration kernel launches alone */
+    uint64_t box_launches;             /* integration kernel launches (one per ray chunk) */
 } pbr_stats;
 
 /* Exit record of one ray (sec. 4 uses per-ray displacements on the sensor). */

@@ -8,6 +8,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "pbr_internal.h"
 
@@ -17,6 +18,7 @@ struct pbr_ctx {
     std::string err;
     unsigned long long *counters = nullptr;  // 4 KiB device block
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    std::vector<hipEvent_t> box_ev;  // pairs around each integration launch (stats only)
     // field
     bool has_field = false;
     const float4 *cells = nullptr;
@@ -198,6 +200,7 @@ void pbr_destroy(pbr_ctx *ctx)
         if (ctx->counters) (void)hipFree(ctx->counters);
         if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
         if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+        for (hipEvent_t ev : ctx->box_ev) (void)hipEventDestroy(ev);
     } catch (...) {
     }
     delete ctx;
@@ -423,10 +426,20 @@ int pbr_emit_and_trace(pbr_ctx *ctx, const float *src_dev, int64_t n_src, int32_
     P.rec_max = ctx->rec_max;
     P.counters = ctx->counters;
 
-    if (stats && (e = (int)hipEventRecord(ctx->ev0, ctx->stream))) return hip_fail(ctx, e, "hipEventRecord");
-    for (int64_t first = 0; first < P.n_rays; first += ctx->ray_chunk) {
+    const int64_t n_chunks = (P.n_rays + ctx->ray_chunk - 1) / ctx->ray_chunk;
+    if (stats) {
+        while ((int64_t)ctx->box_ev.size() < 2 * n_chunks) {
+            hipEvent_t ev;
+            if ((e = (int)hipEventCreate(&ev))) return hip_fail(ctx, e, "hipEventCreate");
+            ctx->box_ev.push_back(ev);
+        }
+        if ((e = (int)hipEventRecord(ctx->ev0, ctx->stream))) return hip_fail(ctx, e, "hipEventRecord");
+    }
+    for (int64_t k = 0; k < n_chunks; ++k) {
+        const int64_t first = k * ctx->ray_chunk;
         const int64_t n = P.n_rays - first < ctx->ray_chunk ? P.n_rays - first : ctx->ray_chunk;
-        e = pbr::launch_trace_chunk(P, ctx->ray_ws, first, n, (flags & PBR_PREC_FP64_ALL) != 0, ctx->stream);
+        e = pbr::launch_trace_chunk(P, ctx->ray_ws, first, n, (flags & PBR_PREC_FP64_ALL) != 0, ctx->stream,
+                                    stats ? ctx->box_ev[2 * k] : nullptr, stats ? ctx->box_ev[2 * k + 1] : nullptr);
         if (e) return hip_fail(ctx, e, "trace launch");
     }
     if (stats && (e = (int)hipEventRecord(ctx->ev1, ctx->stream))) return hip_fail(ctx, e, "hipEventRecord");
@@ -447,6 +460,15 @@ int pbr_emit_and_trace(pbr_ctx *ctx, const float *src_dev, int64_t n_src, int32_
         stats->entered_volume = h[pbr::CNT_ENTERED];
         stats->rkn_steps = h[pbr::CNT_STEPS];
         stats->trace_ms = (double)ms;
+        double box = 0.0;
+        for (int64_t k = 0; k < n_chunks; ++k) {
+            float b = 0.0f;
+            e = (int)hipEventElapsedTime(&b, ctx->box_ev[2 * k], ctx->box_ev[2 * k + 1]);
+            if (e) return hip_fail(ctx, e, "hipEventElapsedTime");
+            box += (double)b;
+        }
+        stats->box_ms = box;
+        stats->box_launches = (uint64_t)n_chunks;
     }
     return PBR_OK;
     PBR_GUARD_END

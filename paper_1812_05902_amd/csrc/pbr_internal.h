@@ -79,8 +79,9 @@ constexpr int kTile = 32;  // deposit pre-aggregation tile (pixels per side, in 
 int launch_field_prep(const float *rho, float4 *cells, int nx, int ny, int nz,
                       const double spacing[3], double K, hipStream_t stream);
 // Rays [first, first + n) through all four steps; st: n RayState of workspace.
+// box_begin / box_end (may be null) are recorded around the integration kernel.
 int launch_trace_chunk(const TraceParams &p, RayState *st, int64_t first, int64_t n, bool fp64,
-                       hipStream_t stream);
+                       hipStream_t stream, hipEvent_t box_begin, hipEvent_t box_end);
 int launch_readout(const unsigned long long *accum, int64_t npx, int fmt, void *out,
                    double gain, unsigned long long *counters, hipStream_t stream);
 int launch_clear_u64(unsigned long long *p, int64_t n, hipStream_t stream);

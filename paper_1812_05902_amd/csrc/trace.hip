@@ -94,14 +94,14 @@ __device__ __forceinline__ F sample_D(const TraceParams &P, CellCache &cc, const
 // cell units: g[a] = h / spacing[a].  The cell fraction fd is accumulated in FP64: its increment
 // is nearly the same every step, so FP32 rounding of the running sum would err the same way
 // every step and grow linearly with the step count.  Stage points are formed in F.
-template <typename F>
+template <typename F, bool FULL>
 __device__ __forceinline__ void rkn_step(const TraceParams &P, CellCache &cc, int c[3], double fd[3],
                                          const F Tr[3], F dT[3], const F g[3], F hstep, F lam)
 {
-    const F hh = lam * hstep;
+    const F hh = FULL ? hstep : lam * hstep;
     F f[3], gg[3], T[3], A[3], B[3], C[3], q[3], D[3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) { f[a] = (F)fd[a]; gg[a] = lam * g[a]; T[a] = Tr[a] + dT[a]; }
+    for (int a = 0; a < 3; ++a) { f[a] = (F)fd[a]; gg[a] = FULL ? g[a] : lam * g[a]; T[a] = Tr[a] + dT[a]; }
     sample_D<F>(P, cc, c, f, D);
 #pragma unroll
     for (int a = 0; a < 3; ++a) { A[a] = hh * D[a]; q[a] = f[a] + gg[a] * ((F)0.5 * T[a] + (F)0.125 * A[a]); }
@@ -141,42 +141,52 @@ __device__ __forceinline__ int trace_box(const TraceParams &P, CellCache &cc, in
     int steps = 0;
     *limited = false;
     for (;;) {
-        F lam = (F)3.0e38;
-        int ax = -1;
+        // cheap test first: does the straight line of a full step reach a face?  (distances in
+        // cell units against the per-step displacement; no division)
+        bool near = false;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             const F v = g[a] * (Tr[a] + dT[a]);
-            F l = (F)3.0e38;
-            if (v > (F)0) l = (F)((double)(last[a] - c[a]) - fd[a]) / v;
-            else if (v < (F)0) l = (F)((double)(-c[a]) - fd[a]) / v;
-            if (l < lam) { lam = l; ax = a; }
+            const F fa = (F)fd[a];
+            near = near || (v > (F)0 && (F)(last[a] - c[a]) - fa <= v) || (v < (F)0 && (F)(-c[a]) - fa >= v);
         }
-        if (ax < 0) return steps;  // T == 0
-        if (lam <= (F)1) {
-            const bool up = (pick3<F>(Tr, ax) + pick3<F>(dT, ax)) > (F)0;
-            if (lam > (F)0) { rkn_step<F>(P, cc, c, fd, Tr, dT, g, hstep, lam); ++steps; }
-            const F Tn[3] = {Tr[0] + dT[0], Tr[1] + dT[1], Tr[2] + dT[2]};
-            const F Ta = pick3<F>(Tn, ax);
-            if (up ? (Ta > (F)0) : (Ta < (F)0)) {
-                const int la = pick3<int>(last, ax);
-                const double target = up ? (double)la : 0.0;
-                const double l2 = (target - ((double)pick3<int>(c, ax) + pick3<double>(fd, ax))) /
-                                  ((double)pick3<F>(g, ax) * (double)Ta);
+        if (near) {
+            F lam = (F)3.0e38;
+            int ax = -1;
 #pragma unroll
-                for (int b = 0; b < 3; ++b) {
-                    if (b == ax) {
-                        c[b] = up ? la - 1 : 0;
-                        fd[b] = up ? 1.0 : 0.0;
-                    } else {
-                        fd[b] += l2 * (double)g[b] * (double)Tn[b];
-                    }
-                }
-                return steps;
+            for (int a = 0; a < 3; ++a) {
+                const F v = g[a] * (Tr[a] + dT[a]);
+                F l = (F)3.0e38;
+                if (v > (F)0) l = (F)((double)(last[a] - c[a]) - fd[a]) / v;
+                else if (v < (F)0) l = (F)((double)(-c[a]) - fd[a]) / v;
+                if (l < lam) { lam = l; ax = a; }
             }
-            if (steps > P.max_steps) { *limited = true; return steps; }
-            continue;  // turned back by the field within the last step
+            if (ax >= 0 && lam <= (F)1) {
+                const bool up = (pick3<F>(Tr, ax) + pick3<F>(dT, ax)) > (F)0;
+                if (lam > (F)0) { rkn_step<F, false>(P, cc, c, fd, Tr, dT, g, hstep, lam); ++steps; }
+                const F Tn[3] = {Tr[0] + dT[0], Tr[1] + dT[1], Tr[2] + dT[2]};
+                const F Ta = pick3<F>(Tn, ax);
+                if (up ? (Ta > (F)0) : (Ta < (F)0)) {
+                    const int la = pick3<int>(last, ax);
+                    const double target = up ? (double)la : 0.0;
+                    const double l2 = (target - ((double)pick3<int>(c, ax) + pick3<double>(fd, ax))) /
+                                      ((double)pick3<F>(g, ax) * (double)Ta);
+#pragma unroll
+                    for (int b = 0; b < 3; ++b) {
+                        if (b == ax) {
+                            c[b] = up ? la - 1 : 0;
+                            fd[b] = up ? 1.0 : 0.0;
+                        } else {
+                            fd[b] += l2 * (double)g[b] * (double)Tn[b];
+                        }
+                    }
+                    return steps;
+                }
+                if (steps > P.max_steps) { *limited = true; return steps; }
+                continue;  // turned back by the field within the last step
+            }
         }
-        rkn_step<F>(P, cc, c, fd, Tr, dT, g, hstep, (F)1);
+        rkn_step<F, true>(P, cc, c, fd, Tr, dT, g, hstep, (F)1);
         if (++steps > P.max_steps) { *limited = true; return steps; }
     }
 }
@@ -534,19 +544,21 @@ __global__ void __launch_bounds__(256) k_finish(TraceParams P, const RayState *_
 }  // namespace
 
 int launch_trace_chunk(const TraceParams &p, RayState *st, int64_t first, int64_t n, bool fp64,
-                       hipStream_t stream)
+                       hipStream_t stream, hipEvent_t box_begin, hipEvent_t box_end)
 {
     if (n <= 0) return 0;
     const unsigned blocks = (unsigned)((n + 255) / 256);
     hipLaunchKernelGGL(k_emit, dim3(blocks), dim3(256), 0, stream, p, st, first, n);
     int e = (int)hipGetLastError();
     if (e) return e;
+    if (box_begin && (e = (int)hipEventRecord(box_begin, stream))) return e;
     if (fp64)
         hipLaunchKernelGGL(k_box64, dim3(blocks), dim3(256), 0, stream, p, st, n);
     else
         hipLaunchKernelGGL(k_box32, dim3(blocks), dim3(256), 0, stream, p, st, n);
     e = (int)hipGetLastError();
     if (e) return e;
+    if (box_end && (e = (int)hipEventRecord(box_end, stream))) return e;
     unsigned fblocks = blocks < 4096u ? blocks : 4096u;
     hipLaunchKernelGGL(k_finish, dim3(fblocks), dim3(256), 0, stream, p, (const RayState *)st, first, n);
     return (int)hipGetLastError();

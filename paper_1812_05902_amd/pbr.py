@@ -60,7 +60,8 @@ class pbr_derived(C.Structure):
 
 class pbr_stats(C.Structure):
     _fields_ = [("rays", C.c_uint64), ("status", C.c_uint64 * PBR_NUM_STATUS),
-                ("entered_volume", C.c_uint64), ("rkn_steps", C.c_uint64), ("trace_ms", C.c_double)]
+                ("entered_volume", C.c_uint64), ("rkn_steps", C.c_uint64), ("trace_ms", C.c_double),
+                ("box_ms", C.c_double), ("box_launches", C.c_uint64)]
 
 
 RAY_EXIT_DTYPE = np.dtype([("ray_id", "<i8"), ("status", "<i4"), ("n_steps", "<i4"),
@@ -196,7 +197,8 @@ def pbr_read_ray_exits(ctx, first, count) -> np.ndarray:
 def stats_dict(st: pbr_stats) -> dict:
     return dict(rays=int(st.rays), status=[int(x) for x in st.status],
                 entered_volume=int(st.entered_volume), rkn_steps=int(st.rkn_steps),
-                trace_ms=float(st.trace_ms))
+                trace_ms=float(st.trace_ms), box_ms=float(st.box_ms),
+                box_launches=int(st.box_launches))
 
 
 class Renderer:

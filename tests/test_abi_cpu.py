@@ -43,7 +43,7 @@ def test_struct_sizes_match_header_layout(lib):
     assert pbr.RAY_EXIT_DTYPE.itemsize == 88
     assert C.sizeof(pbr.pbr_optics) == 56
     assert C.sizeof(pbr.pbr_sensor) == 48
-    assert C.sizeof(pbr.pbr_stats) == 8 * (1 + 7 + 2) + 8
+    assert C.sizeof(pbr.pbr_stats) == 8 * (1 + 7 + 2) + 8 * 3
 
 
 def test_workspace_bytes(lib):
