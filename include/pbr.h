@@ -58,6 +58,7 @@ extern "C" {
 #define PBR_CLEAR_FIRST     (1u << 0)  /* zero the sensor accumulator before depositing */
 #define PBR_RECORD_EXITS    (1u << 1)  /* write exit records for the rays chosen by pbr_set_exit_recording */
 #define PBR_PREC_FP64_ALL   (1u << 2)  /* integrate every step in FP64 (default: FP32) */
+#define PBR_PREC_SHOCK_FP64 (1u << 3)  /* FP64 steps inside the bricks flagged by pbr_calibrate_precision */
 
 /* ---------------------------------------------------------------- pbr_read_image formats */
 #define PBR_FMT_RAW_U64 0  /* copy of the Q32.32 accumulator (uint64 per pixel) */
@@ -109,6 +110,7 @@ typedef struct pbr_stats {
     uint64_t status[PBR_NUM_STATUS];   /* rays per PBR_RAY_* status (sums to rays) */
     uint64_t entered_volume;           /* rays that entered the density box */
     uint64_t rkn_steps;                /* Runge-Kutta steps taken (all rays) */
+    uint64_t rkn_steps_fp64;           /* of which in FP64 */
     double trace_ms;                   /* device time of the whole trace (HIP events) */
     double box_ms;                     /* device time of the integration kernel launches alone */
     uint64_t box_launches;             /* integration kernel launches (one per ray chunk) */
@@ -125,6 +127,19 @@ typedef struct pbr_ray_exit {
     double vol_exit_dir[3];  /* unit direction there */
     double sensor_px[2];     /* hit point in pixel coordinates (valid for DEPOSITED / OFF_SENSOR) */
 } pbr_ray_exit;
+
+/* Result of pbr_calibrate_precision.  A brick is kBrick^3 = 8^3 cells. */
+typedef struct pbr_precision_report {
+    int64_t n_bricks;        /* bricks of the grid */
+    int64_t n_steep;         /* bricks whose largest node |grad n| >= steep_frac * grid maximum */
+    int64_t n_fp64;          /* steep bricks whose FP32 error exceeded tol_px: FP64 steps there */
+    double grad_threshold;   /* |grad n| of the steepness test (1/m) */
+    double grad_max;         /* largest node |grad n| of the grid (1/m) */
+    double max_err_px;       /* largest measured FP32-vs-FP64 difference over steep bricks (pixels) */
+    double tol_px;
+    int32_t steps_per_sample;
+    int32_t rays_per_brick;
+} pbr_precision_report;
 
 /* ---------------------------------------------------------------- context */
 
@@ -150,8 +165,9 @@ int pbr_set_stream(pbr_ctx *ctx, void *hip_stream);
 
 /* ---------------------------------------------------------------- inputs */
 
-/* Bytes of field workspace pbr_set_density_field needs for an nx x ny x nz grid:
- * (nx-1)(ny-1)(nz-1) * 128 (0 if a dimension is below 2). */
+/* Bytes of field workspace pbr_set_density_field needs for an nx x ny x nz grid: 128 bytes per
+ * cell plus 5 bytes per brick of 8^3 cells, each part rounded up to 256 bytes (0 if a dimension
+ * is below 2). */
 size_t pbr_field_workspace_bytes(int nx, int ny, int nz);
 
 /* Density grid (sec. 3.2 and Gladstone-Dale eq. 1).  rho_dev: float32 [nz][ny][nx] node values,
@@ -214,6 +230,23 @@ int pbr_set_exit_recording(pbr_ctx *ctx, int64_t first, int64_t stride, int64_t 
  * 2^64 in one pixel), HIP. */
 int pbr_emit_and_trace(pbr_ctx *ctx, const float *src_dev, int64_t n_src, int32_t rays_per_src,
                        uint64_t seed, double ds, uint32_t flags, pbr_stats *stats_host);
+
+/* Precision policy for steep-gradient (shock) cells.  Finds the steep bricks of the current field
+ * (largest node |grad n| >= steep_frac times the grid maximum), and in each traces rays_per_brick
+ * sample rays (uniform start in the brick, aimed at a uniform aperture point) over enough full
+ * steps of arc length ds to cross the brick, once in FP32 and once in FP64 from the same state.
+ * The difference is measured where it shows: the apparent source point on the focused plane
+ * z_focus times |M| / pitch, in pixels.  Bricks whose largest difference exceeds tol_px are flagged;
+ * later traces with PBR_PREC_SHOCK_FP64 take their Runge-Kutta steps in FP64 inside flagged bricks
+ * and in FP32 elsewhere.  Synchronises the stream.  Uses the trace workspace as scratch.
+ * Errors: STATE (field/optics/sensor/trace workspace missing, host-only context), ARG, WORKSPACE. */
+int pbr_calibrate_precision(pbr_ctx *ctx, double tol_px, double steep_frac, int32_t rays_per_brick,
+                            uint64_t seed, double ds, pbr_precision_report *out);
+
+/* Reads (write = 0) or replaces (write = 1) the per-brick FP64 flags of the current field:
+ * n_bricks bytes, brick (bx, by, bz) at (bz * nby + by) * nbx + bx with nb* = ceil((n* - 1) / 8).
+ * Synchronises the stream.  Errors: STATE, ARG (n_bricks differs from the grid's). */
+int pbr_brick_flags(pbr_ctx *ctx, uint8_t *inout_host, int64_t n_bricks, int write);
 
 /* Converts the accumulator into out_dev (caller-owned: width*height elements of uint64, float
  * or uint16 by fmt).  PBR_FMT_U16 uses `gain` if > 0, else gain = 65535 / (largest pixel value),

@@ -28,8 +28,8 @@ __device__ __forceinline__ double index_derivative(const float *__restrict__ rho
 }
 
 __global__ void __launch_bounds__(256)
-k_field_prep(const float *__restrict__ rho, float4 *__restrict__ cells, int nx, int ny, int nz,
-             double kx, double ky, double kz, double K)
+k_field_prep(const float *__restrict__ rho, float4 *__restrict__ cells, unsigned *__restrict__ brick_gmax,
+             int nx, int ny, int nz, double kx, double ky, double kz, double K)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y;
@@ -46,6 +46,17 @@ k_field_prep(const float *__restrict__ rho, float4 *__restrict__ cells, int nx, 
         v[corner][1] = kx * index_derivative(rho, q, sx, ii, nx);
         v[corner][2] = ky * index_derivative(rho, q, sy, jj, ny);
         v[corner][3] = kz * index_derivative(rho, q, sz, kk, nz);
+    }
+    // steepness of the cell: largest |grad n| at its corners, folded into its brick
+    double gm = 0.0;
+#pragma unroll
+    for (int corner = 0; corner < 8; ++corner)
+        gm = fmax(gm, sqrt(v[corner][1] * v[corner][1] + v[corner][2] * v[corner][2] + v[corner][3] * v[corner][3]));
+    {
+        const int nbx = (nx - 1 + kBrick - 1) / kBrick, nby = (ny - 1 + kBrick - 1) / kBrick;
+        const size_t b = ((size_t)(k / kBrick) * nby + (size_t)(j / kBrick)) * nbx + (size_t)(i / kBrick);
+        const float gf = (float)gm;
+        if (gf > 0.0f) atomicMax(brick_gmax + b, __float_as_uint(gf));  // non-negative floats order as uints
     }
     double c[8][4];
 #pragma unroll
@@ -76,12 +87,12 @@ __global__ void __launch_bounds__(256) k_clear_u64(unsigned long long *p, int64_
 
 }  // namespace
 
-int launch_field_prep(const float *rho, float4 *cells, int nx, int ny, int nz,
+int launch_field_prep(const float *rho, float4 *cells, unsigned *brick_gmax, int nx, int ny, int nz,
                       const double spacing[3], double K, hipStream_t stream)
 {
     dim3 block(256);
     dim3 grid((unsigned)((nx - 1 + 255) / 256), (unsigned)(ny - 1), (unsigned)(nz - 1));
-    hipLaunchKernelGGL(k_field_prep, grid, block, 0, stream, rho, cells, nx, ny, nz,
+    hipLaunchKernelGGL(k_field_prep, grid, block, 0, stream, rho, cells, brick_gmax, nx, ny, nz,
                        K / spacing[0], K / spacing[1], K / spacing[2], K);
     return (int)hipGetLastError();
 }

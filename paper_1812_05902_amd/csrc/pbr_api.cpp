@@ -22,6 +22,10 @@ struct pbr_ctx {
     // field
     bool has_field = false;
     const float4 *cells = nullptr;
+    unsigned *brick_gmax = nullptr;        // per-brick max |grad n| (float bits), device
+    unsigned char *brick_fp64 = nullptr;   // per-brick FP64 flags, device
+    pbr::FieldLayout layout{};
+    int64_t n_fp64_bricks = 0;
     int nx = 0, ny = 0, nz = 0;
     double origin[3] = {0, 0, 0}, spacing[3] = {0, 0, 0};
     double K = 0.0, rho_inf = 0.0;
@@ -141,6 +145,41 @@ int max_steps_for(const pbr_ctx *c, double ds)
     return m > 67108864.0 ? 67108864 : (int)m;  // the step count is kept in 27 bits
 }
 
+// Launch parameters shared by the trace and the calibration (sources and rays left empty).
+void fill_params(const pbr_ctx *ctx, const Derived &d, double ds, pbr::TraceParams *out)
+{
+    pbr::TraceParams &P = *out;
+    std::memset(&P, 0, sizeof P);
+    P.cells = ctx->cells;
+    P.brick_fp64 = ctx->brick_fp64;
+    P.nbx = ctx->layout.nbx; P.nby = ctx->layout.nby; P.nbz = ctx->layout.nbz;
+    P.nx = ctx->nx; P.ny = ctx->ny; P.nz = ctx->nz;
+    P.max_steps = max_steps_for(ctx, ds);
+    const int n3[3] = {ctx->nx, ctx->ny, ctx->nz};
+    P.h = ds / d.n_inf;
+    for (int a = 0; a < 3; ++a) {
+        P.origin[a] = ctx->origin[a];
+        P.spacing[a] = ctx->spacing[a];
+        P.lo[a] = ctx->origin[a];
+        P.hi[a] = ctx->origin[a] + (double)(n3[a] - 1) * ctx->spacing[a];
+        P.step_cell[a] = P.h / ctx->spacing[a];
+    }
+    P.n_inf = d.n_inf;
+    P.z_lens = ctx->optics.z_front_vertex;
+    P.a = d.a; P.R = d.R; P.t = d.t; P.clear = d.clear; P.n_glass = ctx->optics.n_glass;
+    P.z_sensor = d.z_sensor;
+    P.accum = ctx->accum;
+    P.W = ctx->sensor.width; P.H = ctx->sensor.height;
+    P.pitch = ctx->sensor.pitch;
+    P.sigma_px = d.sigma_px;
+    P.rfp = d.rfp;
+    P.rec = ctx->rec;
+    P.rec_first = ctx->rec_first;
+    P.rec_stride = ctx->rec_stride;
+    P.rec_max = ctx->rec_max;
+    P.counters = ctx->counters;
+}
+
 }  // namespace
 
 #define PBR_GUARD_BEGIN try {
@@ -221,7 +260,7 @@ int pbr_set_stream(pbr_ctx *ctx, void *hip_stream)
 size_t pbr_field_workspace_bytes(int nx, int ny, int nz)
 {
     if (nx < 2 || ny < 2 || nz < 2) return 0;
-    return (size_t)(nx - 1) * (size_t)(ny - 1) * (size_t)(nz - 1) * pbr::kCellFloat4 * sizeof(float4);
+    return pbr::field_layout(nx, ny, nz).total;
 }
 
 size_t pbr_trace_workspace_bytes(int64_t rays_per_chunk)
@@ -261,13 +300,24 @@ int pbr_set_density_field(pbr_ctx *ctx, const float *rho_dev, int nx, int ny, in
     const size_t need = pbr_field_workspace_bytes(nx, ny, nz);
     if (ws_bytes < need) return fail(ctx, PBR_ERR_WORKSPACE, "field workspace %zu bytes < %zu needed", ws_bytes, need);
     if (((uintptr_t)ws_dev & 15u) != 0) return fail(ctx, PBR_ERR_ARG, "field workspace must be 16-byte aligned");
+    const pbr::FieldLayout L = pbr::field_layout(nx, ny, nz);
+    char *base = (char *)ws_dev;
     if (ctx->device >= 0) {
         DeviceGuard g(ctx->device);
         if (!g.ok) return fail(ctx, PBR_ERR_HIP, "hipSetDevice failed");
-        const int e = pbr::launch_field_prep(rho_dev, (float4 *)ws_dev, nx, ny, nz, spacing, K, ctx->stream);
+        // brick max |grad n| and FP64 flags start at zero (fill kernel, no memset node)
+        int e = pbr::launch_clear_u64((unsigned long long *)(base + L.gmax_off),
+                                      (int64_t)((L.total - L.gmax_off) / 8), ctx->stream);
+        if (e) return hip_fail(ctx, e, "clear brick tables");
+        e = pbr::launch_field_prep(rho_dev, (float4 *)(base + L.cells_off), (unsigned *)(base + L.gmax_off),
+                                   nx, ny, nz, spacing, K, ctx->stream);
         if (e) return hip_fail(ctx, e, "field preparation launch");
     }
-    ctx->cells = (const float4 *)ws_dev;
+    ctx->layout = L;
+    ctx->brick_gmax = (unsigned *)(base + L.gmax_off);
+    ctx->brick_fp64 = (unsigned char *)(base + L.flags_off);
+    ctx->n_fp64_bricks = 0;
+    ctx->cells = (const float4 *)(base + L.cells_off);
     ctx->nx = nx; ctx->ny = ny; ctx->nz = nz;
     for (int a = 0; a < 3; ++a) { ctx->origin[a] = origin[a]; ctx->spacing[a] = spacing[a]; }
     ctx->K = K;
@@ -368,7 +418,7 @@ int pbr_emit_and_trace(pbr_ctx *ctx, const float *src_dev, int64_t n_src, int32_
         return fail(ctx, PBR_ERR_ARG, "lens front vertex must lie beyond the density box (z > %.6g)", zmax);
     if (!(d.z_sensor > ctx->optics.z_front_vertex + d.t))
         return fail(ctx, PBR_ERR_ARG, "sensor plane must lie behind the lens");
-    if (flags & ~(uint32_t)(PBR_CLEAR_FIRST | PBR_RECORD_EXITS | PBR_PREC_FP64_ALL))
+    if (flags & ~(uint32_t)(PBR_CLEAR_FIRST | PBR_RECORD_EXITS | PBR_PREC_FP64_ALL | PBR_PREC_SHOCK_FP64))
         return fail(ctx, PBR_ERR_ARG, "unknown flag bits 0x%x", flags);
     if (!ctx->ray_ws) return fail(ctx, PBR_ERR_STATE, "no trace workspace set (pbr_set_trace_workspace)");
     if ((flags & PBR_RECORD_EXITS) && ctx->rec_max > 0 && !ctx->rec)
@@ -391,41 +441,18 @@ int pbr_emit_and_trace(pbr_ctx *ctx, const float *src_dev, int64_t n_src, int32_
     if (e) return hip_fail(ctx, e, "clear counters");
 
     pbr::TraceParams P;
-    std::memset(&P, 0, sizeof P);
-    P.cells = ctx->cells;
-    P.nx = ctx->nx; P.ny = ctx->ny; P.nz = ctx->nz;
-    P.max_steps = max_steps_for(ctx, ds);
-    ctx->last_max_steps = P.max_steps;
-    const int n3[3] = {ctx->nx, ctx->ny, ctx->nz};
-    P.h = ds / d.n_inf;
-    for (int a = 0; a < 3; ++a) {
-        P.origin[a] = ctx->origin[a];
-        P.spacing[a] = ctx->spacing[a];
-        P.lo[a] = ctx->origin[a];
-        P.hi[a] = ctx->origin[a] + (double)(n3[a] - 1) * ctx->spacing[a];
-        P.step_cell[a] = P.h / ctx->spacing[a];
-    }
-    P.n_inf = d.n_inf;
+    fill_params(ctx, d, ds, &P);
     P.src = (const float4 *)src_dev;
     P.n_src = n_src;
     P.rays_per_src = rays_per_src;
     P.n_rays = n_src * (int64_t)rays_per_src;
     P.seed = seed;
-    P.z_lens = ctx->optics.z_front_vertex;
-    P.a = d.a; P.R = d.R; P.t = d.t; P.clear = d.clear; P.n_glass = ctx->optics.n_glass;
-    P.z_sensor = d.z_sensor;
-    P.accum = ctx->accum;
-    P.W = ctx->sensor.width; P.H = ctx->sensor.height;
-    P.pitch = ctx->sensor.pitch;
-    P.sigma_px = d.sigma_px;
-    P.rfp = d.rfp;
     P.record = (flags & PBR_RECORD_EXITS) && ctx->rec_max > 0 ? 1 : 0;
-    P.rec = ctx->rec;
-    P.rec_first = ctx->rec_first;
-    P.rec_stride = ctx->rec_stride;
-    P.rec_max = ctx->rec_max;
-    P.counters = ctx->counters;
+    ctx->last_max_steps = P.max_steps;
 
+    const int prec = (flags & PBR_PREC_FP64_ALL) ? pbr::PREC_FP64
+                     : ((flags & PBR_PREC_SHOCK_FP64) && ctx->n_fp64_bricks > 0) ? pbr::PREC_MIXED
+                     : pbr::PREC_FP32;
     const int64_t n_chunks = (P.n_rays + ctx->ray_chunk - 1) / ctx->ray_chunk;
     if (stats) {
         while ((int64_t)ctx->box_ev.size() < 2 * n_chunks) {
@@ -438,7 +465,7 @@ int pbr_emit_and_trace(pbr_ctx *ctx, const float *src_dev, int64_t n_src, int32_
     for (int64_t k = 0; k < n_chunks; ++k) {
         const int64_t first = k * ctx->ray_chunk;
         const int64_t n = P.n_rays - first < ctx->ray_chunk ? P.n_rays - first : ctx->ray_chunk;
-        e = pbr::launch_trace_chunk(P, ctx->ray_ws, first, n, (flags & PBR_PREC_FP64_ALL) != 0, ctx->stream,
+        e = pbr::launch_trace_chunk(P, ctx->ray_ws, first, n, prec, ctx->stream,
                                     stats ? ctx->box_ev[2 * k] : nullptr, stats ? ctx->box_ev[2 * k + 1] : nullptr);
         if (e) return hip_fail(ctx, e, "trace launch");
     }
@@ -459,6 +486,7 @@ int pbr_emit_and_trace(pbr_ctx *ctx, const float *src_dev, int64_t n_src, int32_
         for (int k = 0; k < PBR_NUM_STATUS; ++k) stats->status[k] = h[pbr::CNT_STATUS + k];
         stats->entered_volume = h[pbr::CNT_ENTERED];
         stats->rkn_steps = h[pbr::CNT_STEPS];
+        stats->rkn_steps_fp64 = prec == pbr::PREC_FP64 ? h[pbr::CNT_STEPS] : h[pbr::CNT_STEPS64];
         stats->trace_ms = (double)ms;
         double box = 0.0;
         for (int64_t k = 0; k < n_chunks; ++k) {
@@ -469,6 +497,111 @@ int pbr_emit_and_trace(pbr_ctx *ctx, const float *src_dev, int64_t n_src, int32_
         }
         stats->box_ms = box;
         stats->box_launches = (uint64_t)n_chunks;
+    }
+    return PBR_OK;
+    PBR_GUARD_END
+}
+
+int pbr_calibrate_precision(pbr_ctx *ctx, double tol_px, double steep_frac, int32_t rays_per_brick,
+                            uint64_t seed, double ds, pbr_precision_report *out)
+{
+    if (!ctx) return PBR_ERR_ARG;
+    PBR_GUARD_BEGIN
+    Derived d;
+    int r = derive(ctx, &d);
+    if (r) return r;
+    if (!(tol_px >= 0.0) || !std::isfinite(tol_px)) return fail(ctx, PBR_ERR_ARG, "tol_px must be finite and >= 0");
+    if (!(steep_frac >= 0.0 && steep_frac <= 1.0)) return fail(ctx, PBR_ERR_ARG, "steep_frac must lie in [0, 1]");
+    if (rays_per_brick < 1 || rays_per_brick > 256) return fail(ctx, PBR_ERR_ARG, "rays_per_brick must lie in [1, 256]");
+    if (!(ds > 0.0) || !std::isfinite(ds)) return fail(ctx, PBR_ERR_ARG, "ds must be finite and > 0");
+    if (!ctx->ray_ws) return fail(ctx, PBR_ERR_STATE, "no trace workspace set (used as calibration scratch)");
+    const int64_t nb = ctx->layout.n_bricks;
+    if ((size_t)nb * 8 > (size_t)ctx->ray_chunk * sizeof(pbr::RayState))
+        return fail(ctx, PBR_ERR_WORKSPACE, "trace workspace too small for %lld calibration bricks", (long long)nb);
+    if (ctx->device < 0) return fail(ctx, PBR_ERR_STATE, "host-only context: no device work");
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(ctx, PBR_ERR_HIP, "hipSetDevice failed");
+    std::vector<unsigned> gmax((size_t)nb);
+    int e = (int)hipMemcpyAsync(gmax.data(), ctx->brick_gmax, (size_t)nb * 4, hipMemcpyDeviceToHost, ctx->stream);
+    if (!e) e = (int)hipStreamSynchronize(ctx->stream);
+    if (e) return hip_fail(ctx, e, "read brick steepness");
+    float gtop = 0.0f;
+    for (unsigned v : gmax) { float f; std::memcpy(&f, &v, 4); gtop = f > gtop ? f : gtop; }
+    const float thr = (float)(steep_frac * (double)gtop);
+    std::vector<int> steep;
+    for (int64_t b = 0; b < nb; ++b) {
+        float f;
+        std::memcpy(&f, &gmax[(size_t)b], 4);
+        if (f > 0.0f && f >= thr) steep.push_back((int)b);
+    }
+    const int ns = (int)steep.size();
+    double smax = 0.0;
+    for (int a = 0; a < 3; ++a) smax = ctx->spacing[a] > smax ? ctx->spacing[a] : smax;
+    int n_steps = (int)std::ceil((double)pbr::kBrick * smax * 1.7320508075688772 / ds) + 1;
+    n_steps = n_steps > 512 ? 512 : n_steps;
+    std::vector<float> err((size_t)ns, 0.0f);
+    if (ns > 0) {
+        int *dev_list = (int *)ctx->ray_ws;
+        float *dev_err = (float *)((char *)ctx->ray_ws + (size_t)ns * 4);
+        e = (int)hipMemcpyAsync(dev_list, steep.data(), (size_t)ns * 4, hipMemcpyHostToDevice, ctx->stream);
+        if (e) return hip_fail(ctx, e, "upload brick list");
+        pbr::TraceParams P;
+        fill_params(ctx, d, ds, &P);
+        e = pbr::launch_calibrate(P, dev_list, ns, rays_per_brick, n_steps, seed, ctx->optics.z_focus,
+                                  std::fabs(d.M) / ctx->sensor.pitch, dev_err, ctx->stream);
+        if (e) return hip_fail(ctx, e, "calibration launch");
+        e = (int)hipMemcpyAsync(err.data(), dev_err, (size_t)ns * 4, hipMemcpyDeviceToHost, ctx->stream);
+        if (!e) e = (int)hipStreamSynchronize(ctx->stream);
+        if (e) return hip_fail(ctx, e, "calibration");
+    }
+    std::vector<unsigned char> flags((size_t)nb, 0);
+    int64_t nf = 0;
+    double emax = 0.0;
+    for (int k = 0; k < ns; ++k) {
+        emax = err[(size_t)k] > emax ? err[(size_t)k] : emax;
+        if ((double)err[(size_t)k] > tol_px) { flags[(size_t)steep[(size_t)k]] = 1; ++nf; }
+    }
+    e = (int)hipMemcpyAsync(ctx->brick_fp64, flags.data(), (size_t)nb, hipMemcpyHostToDevice, ctx->stream);
+    if (!e) e = (int)hipStreamSynchronize(ctx->stream);
+    if (e) return hip_fail(ctx, e, "write brick flags");
+    ctx->n_fp64_bricks = nf;
+    if (out) {
+        out->n_bricks = nb;
+        out->n_steep = ns;
+        out->n_fp64 = nf;
+        out->grad_threshold = (double)thr;
+        out->grad_max = (double)gtop;
+        out->max_err_px = emax;
+        out->tol_px = tol_px;
+        out->steps_per_sample = n_steps;
+        out->rays_per_brick = rays_per_brick;
+    }
+    return PBR_OK;
+    PBR_GUARD_END
+}
+
+int pbr_brick_flags(pbr_ctx *ctx, uint8_t *inout_host, int64_t n_bricks, int write)
+{
+    if (!ctx) return PBR_ERR_ARG;
+    PBR_GUARD_BEGIN
+    if (!ctx->has_field) return fail(ctx, PBR_ERR_STATE, "no density field set");
+    if (!inout_host || n_bricks != ctx->layout.n_bricks)
+        return fail(ctx, PBR_ERR_ARG, "need a host array of %lld brick flags", (long long)ctx->layout.n_bricks);
+    if (ctx->device < 0) return fail(ctx, PBR_ERR_STATE, "host-only context: no device work");
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(ctx, PBR_ERR_HIP, "hipSetDevice failed");
+    int e;
+    if (write) {
+        int64_t nf = 0;
+        for (int64_t b = 0; b < n_bricks; ++b) nf += inout_host[b] ? 1 : 0;
+        e = (int)hipMemcpyAsync(ctx->brick_fp64, inout_host, (size_t)n_bricks, hipMemcpyHostToDevice, ctx->stream);
+        if (!e) e = (int)hipStreamSynchronize(ctx->stream);
+        if (e) return hip_fail(ctx, e, "write brick flags");
+        ctx->n_fp64_bricks = nf;
+    } else {
+        e = (int)hipMemcpyAsync(inout_host, ctx->brick_fp64, (size_t)n_bricks, hipMemcpyDeviceToHost, ctx->stream);
+        if (!e) e = (int)hipStreamSynchronize(ctx->stream);
+        if (e) return hip_fail(ctx, e, "read brick flags");
     }
     return PBR_OK;
     PBR_GUARD_END

@@ -14,6 +14,7 @@ enum : int {
     CNT_ENTERED = PBR_NUM_STATUS,         // rays that entered the box
     CNT_STEPS = PBR_NUM_STATUS + 1,       // Runge-Kutta steps
     CNT_MAXPIX = PBR_NUM_STATUS + 2,      // largest accumulator value (readout)
+    CNT_STEPS64 = PBR_NUM_STATUS + 3,     // Runge-Kutta steps taken in FP64 (mixed precision)
     CNT_SLOTS = 16
 };
 
@@ -27,9 +28,37 @@ constexpr int kMaxFootprint = 8;          // deposit window half-width limit (si
 // which is the trilinear interpolant of the eight corner values.
 constexpr int kCellFloat4 = 8;
 
+// Bricks of kBrick^3 cells carry the precision policy: the largest |grad n| at their nodes
+// (float bits, for the steepness test) and a flag that selects FP64 integration steps.
+constexpr int kBrick = 8;
+
+// Byte layout of the field workspace: cell records, then per-brick max |grad n| (uint32 float
+// bits), then per-brick FP64 flags (uint8); each part 256-byte aligned.
+struct FieldLayout {
+    size_t cells_off, gmax_off, flags_off, total;
+    int nbx, nby, nbz;
+    int64_t n_bricks;
+};
+inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+inline FieldLayout field_layout(int nx, int ny, int nz)
+{
+    FieldLayout L;
+    L.nbx = (nx - 1 + kBrick - 1) / kBrick;
+    L.nby = (ny - 1 + kBrick - 1) / kBrick;
+    L.nbz = (nz - 1 + kBrick - 1) / kBrick;
+    L.n_bricks = (int64_t)L.nbx * L.nby * L.nbz;
+    L.cells_off = 0;
+    L.gmax_off = align256((size_t)(nx - 1) * (size_t)(ny - 1) * (size_t)(nz - 1) * kCellFloat4 * 16);
+    L.flags_off = align256(L.gmax_off + (size_t)L.n_bricks * 4);
+    L.total = align256(L.flags_off + (size_t)L.n_bricks);
+    return L;
+}
+
 // Everything one trace launch reads.  Passed by value as the kernel argument.
 struct TraceParams {
     const float4 *cells;   // field records (see above)
+    const unsigned char *brick_fp64;  // per-brick FP64 flags (mixed precision)
+    int nbx, nby, nbz;     // brick counts
     int nx, ny, nz;        // node counts
     int max_steps;
     double origin[3], spacing[3];
@@ -76,11 +105,19 @@ enum : int { RS_ENTERED = 1, RS_LIMITED = 2, RS_STEP_SHIFT = 4 };
 constexpr int kTile = 32;  // deposit pre-aggregation tile (pixels per side, in LDS)
 
 // Launchers (defined in the .hip files; enqueue on `stream`, return hipError_t as int).
-int launch_field_prep(const float *rho, float4 *cells, int nx, int ny, int nz,
+// Writes the cell records and (atomically) the per-brick max |grad n|; gmax must be zeroed.
+int launch_field_prep(const float *rho, float4 *cells, unsigned *brick_gmax, int nx, int ny, int nz,
                       const double spacing[3], double K, hipStream_t stream);
+// Precision calibration: for each listed brick, rays_per_brick sample rays integrated over
+// n_steps full steps in FP32 and in FP64 from the same state; err[k] = largest difference of
+// the image point (apparent source on the plane z_focus, times |M| / pitch) in pixels.
+int launch_calibrate(const TraceParams &p, const int *bricks, int n_bricks, int rays_per_brick,
+                     int n_steps, uint64_t seed, double z_focus, double px_per_m, float *err,
+                     hipStream_t stream);
 // Rays [first, first + n) through all four steps; st: n RayState of workspace.
 // box_begin / box_end (may be null) are recorded around the integration kernel.
-int launch_trace_chunk(const TraceParams &p, RayState *st, int64_t first, int64_t n, bool fp64,
+enum PrecMode : int { PREC_FP32 = 0, PREC_FP64 = 1, PREC_MIXED = 2 };
+int launch_trace_chunk(const TraceParams &p, RayState *st, int64_t first, int64_t n, int prec,
                        hipStream_t stream, hipEvent_t box_begin, hipEvent_t box_end);
 int launch_readout(const unsigned long long *accum, int64_t npx, int fmt, void *out,
                    double gain, unsigned long long *counters, hipStream_t stream);

@@ -42,7 +42,7 @@ struct CellCache {
 // Trilinear interpolation of (n - 1, grad n) at the point (cell c, fraction f); the fraction may
 // lie outside [0, 1) (stage points of eq. 5), in which case the point is moved into the cell that
 // holds it and then onto the box.  Returns n, writes D = n grad n (eq. 6).
-template <typename F>
+template <typename F, bool AT_STATE = false>
 __device__ __forceinline__ F sample_D(const TraceParams &P, CellCache &cc, const int c[3],
                                       const F f[3], F D[3])
 {
@@ -51,14 +51,22 @@ __device__ __forceinline__ F sample_D(const TraceParams &P, CellCache &cc, const
     F w[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        F fa = f[a];
-        fa = fa > (F)(-1.0e6) ? fa : (F)(-1.0e6);  // also maps NaN to a finite value
-        fa = fa < (F)(1.0e6) ? fa : (F)(1.0e6);
-        const F o = ffloor<F>(fa);
-        int i = c[a] + (int)o;
-        F t = fa - o;
-        if (i < 0) { i = 0; t = (F)0; }
-        if (i > nmax[a]) { i = nmax[a]; t = (F)1; }
+        int i0;
+        F t;
+        if (AT_STATE) {
+            // the ray's own position: fraction already in [0, 1], cell normally valid
+            i0 = c[a];
+            t = f[a];
+        } else {
+            // stage point: fraction anywhere; NaN becomes finite (fmax/fmin return the number)
+            const F fa = fmin(fmax(f[a], (F)(-1.0e6)), (F)(1.0e6));
+            const F o = ffloor<F>(fa);
+            i0 = c[a] + (int)o;
+            t = fa - o;
+        }
+        const int i = min(max(i0, 0), nmax[a]);
+        t = i0 < 0 ? (F)0 : t;
+        t = i0 > nmax[a] ? (F)1 : t;
         ic[a] = i;
         w[a] = t;
     }
@@ -102,7 +110,7 @@ __device__ __forceinline__ void rkn_step(const TraceParams &P, CellCache &cc, in
     F f[3], gg[3], T[3], A[3], B[3], C[3], q[3], D[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) { f[a] = (F)fd[a]; gg[a] = FULL ? g[a] : lam * g[a]; T[a] = Tr[a] + dT[a]; }
-    sample_D<F>(P, cc, c, f, D);
+    sample_D<F, true>(P, cc, c, f, D);
 #pragma unroll
     for (int a = 0; a < 3; ++a) { A[a] = hh * D[a]; q[a] = f[a] + gg[a] * ((F)0.5 * T[a] + (F)0.125 * A[a]); }
     sample_D<F>(P, cc, c, q, D);
@@ -399,6 +407,215 @@ __global__ void __launch_bounds__(256) k_box64(TraceParams P, RayState *__restri
     box_body<double>(P, st, n);
 }
 
+// ------------------------------------------------------------------ mixed precision
+
+// FP64 flag of the brick holding cell c (cell clamped onto the grid).
+__device__ __forceinline__ bool brick_is_fp64(const TraceParams &P, const int c[3])
+{
+    const int bx = min(max(c[0], 0), P.nx - 2) / kBrick;
+    const int by = min(max(c[1], 0), P.ny - 2) / kBrick;
+    const int bz = min(max(c[2], 0), P.nz - 2) / kBrick;
+    return P.brick_fp64[((size_t)bz * P.nby + by) * P.nbx + bx] != 0;
+}
+
+// One step in FP64 from the FP32 state: T = Tr + dT is carried in double through the step, then
+// split again into a float hi/lo pair.
+template <bool FULL>
+__device__ __forceinline__ void rkn_step_fp64(const TraceParams &P, CellCache &cc, int c[3], double fd[3],
+                                              float Tr[3], float dT[3], double lam)
+{
+    double T64[3], d64[3] = {0.0, 0.0, 0.0};
+    const double g64[3] = {P.step_cell[0], P.step_cell[1], P.step_cell[2]};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) T64[a] = (double)Tr[a] + (double)dT[a];
+    rkn_step<double, FULL>(P, cc, c, fd, T64, d64, g64, P.h, lam);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double T = T64[a] + d64[a];
+        Tr[a] = (float)T;
+        dT[a] = (float)(T - (double)Tr[a]);
+    }
+}
+
+// trace_box<float> with the step precision chosen per step from the brick of the current cell.
+__device__ __forceinline__ int trace_box_mixed(const TraceParams &P, CellCache &cc, int c[3], double fd[3],
+                                               float Tr[3], float dT[3], bool *limited, int *n64)
+{
+    const float g[3] = {(float)P.step_cell[0], (float)P.step_cell[1], (float)P.step_cell[2]};
+    const float hstep = (float)P.h;
+    const int last[3] = {P.nx - 1, P.ny - 1, P.nz - 1};
+    int steps = 0;
+    *limited = false;
+    for (;;) {
+        bool near = false;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const float v = g[a] * (Tr[a] + dT[a]);
+            const float fa = (float)fd[a];
+            near = near || (v > 0.0f && (float)(last[a] - c[a]) - fa <= v) || (v < 0.0f && (float)(-c[a]) - fa >= v);
+        }
+        if (near) {
+            float lam = 3.0e38f;
+            int ax = -1;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const float v = g[a] * (Tr[a] + dT[a]);
+                float l = 3.0e38f;
+                if (v > 0.0f) l = (float)((double)(last[a] - c[a]) - fd[a]) / v;
+                else if (v < 0.0f) l = (float)((double)(-c[a]) - fd[a]) / v;
+                if (l < lam) { lam = l; ax = a; }
+            }
+            if (ax >= 0 && lam <= 1.0f) {
+                const bool up = (pick3<float>(Tr, ax) + pick3<float>(dT, ax)) > 0.0f;
+                if (lam > 0.0f) {
+                    if (brick_is_fp64(P, c)) { rkn_step_fp64<false>(P, cc, c, fd, Tr, dT, (double)lam); ++*n64; }
+                    else rkn_step<float, false>(P, cc, c, fd, Tr, dT, g, hstep, lam);
+                    ++steps;
+                }
+                const float Tn[3] = {Tr[0] + dT[0], Tr[1] + dT[1], Tr[2] + dT[2]};
+                const float Ta = pick3<float>(Tn, ax);
+                if (up ? (Ta > 0.0f) : (Ta < 0.0f)) {
+                    const int la = pick3<int>(last, ax);
+                    const double target = up ? (double)la : 0.0;
+                    const double l2 = (target - ((double)pick3<int>(c, ax) + pick3<double>(fd, ax))) /
+                                      ((double)pick3<float>(g, ax) * (double)Ta);
+#pragma unroll
+                    for (int b = 0; b < 3; ++b) {
+                        if (b == ax) {
+                            c[b] = up ? la - 1 : 0;
+                            fd[b] = up ? 1.0 : 0.0;
+                        } else {
+                            fd[b] += l2 * (double)g[b] * (double)Tn[b];
+                        }
+                    }
+                    return steps;
+                }
+                if (steps > P.max_steps) { *limited = true; return steps; }
+                continue;
+            }
+        }
+        if (brick_is_fp64(P, c)) { rkn_step_fp64<true>(P, cc, c, fd, Tr, dT, 1.0); ++*n64; }
+        else rkn_step<float, true>(P, cc, c, fd, Tr, dT, g, hstep, 1.0f);
+        if (++steps > P.max_steps) { *limited = true; return steps; }
+    }
+}
+
+__global__ void __launch_bounds__(256) k_box_mixed(TraceParams P, RayState *__restrict__ st, int64_t n)
+{
+    __shared__ unsigned long long s64;
+    if (threadIdx.x == 0) s64 = 0ull;
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int n64 = 0;
+    if (i < n) {
+        RayState r = st[i];
+        if (r.info & RS_ENTERED) {
+            float Tr[3] = {r.Tr[0], r.Tr[1], r.Tr[2]}, dT[3] = {r.dT[0], r.dT[1], r.dT[2]};
+            CellCache cc;
+            cc.key = -1;
+            bool limited = false;
+            const int steps = trace_box_mixed(P, cc, r.c, r.fd, Tr, dT, &limited, &n64);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const double T = (double)Tr[a] + (double)dT[a];
+                r.Tr[a] = (float)T;
+                r.dT[a] = (float)(T - (double)r.Tr[a]);
+            }
+            r.info = RS_ENTERED | (limited ? RS_LIMITED : 0) | (steps << RS_STEP_SHIFT);
+            st[i] = r;
+        }
+    }
+    if (n64) atomicAdd(&s64, (unsigned long long)n64);
+    __syncthreads();
+    if (threadIdx.x == 0 && s64) atomic_add_u64(P.counters + CNT_STEPS64, s64);
+}
+
+// Calibration of the precision policy: each block samples one brick.  Sample ray k starts at a
+// uniform point of the brick, aimed at a uniform point of the aperture, and is integrated over
+// n_steps full steps in FP32 and in FP64 from the same state.  The two results are compared where
+// they matter on the sensor: the apparent source point on the focused plane, times |M| / pitch.
+__global__ void __launch_bounds__(256) k_calibrate(TraceParams P, const int *__restrict__ bricks,
+                                                   int n_steps, uint64_t seed, double z_focus,
+                                                   double px_per_m, float *__restrict__ err)
+{
+    __shared__ unsigned s_err;
+    if (threadIdx.x == 0) s_err = 0u;
+    __syncthreads();
+    const int b = bricks[blockIdx.x];
+    const int bb[3] = {b % P.nbx, (b / P.nbx) % P.nby, b / (P.nbx * P.nby)};
+    const int nn[3] = {P.nx, P.ny, P.nz};
+    const uint64_t h1 = splitmix64_at(seed, ((uint64_t)(uint32_t)b << 32) | (2u * threadIdx.x));
+    const uint64_t h2 = splitmix64_at(seed, ((uint64_t)(uint32_t)b << 32) | (2u * threadIdx.x + 1u));
+    const double uu[5] = {(double)(h1 >> 40) * (1.0 / 16777216.0), (double)((h1 >> 16) & 0xFFFFFFull) * (1.0 / 16777216.0),
+                          (double)(h2 >> 40) * (1.0 / 16777216.0), (double)((h2 >> 16) & 0xFFFFFFull) * (1.0 / 16777216.0),
+                          (double)(h1 & 0xFFFFull) * (1.0 / 65536.0)};
+    int c[3];
+    double fd[3], X[3];
+    float f[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        double p = (double)(bb[a] * kBrick) + (double)kBrick * uu[a];
+        p = p > (double)(nn[a] - 1) ? (double)(nn[a] - 1) : p;
+        int ci = (int)floor(p);
+        ci = ci > nn[a] - 2 ? nn[a] - 2 : ci;
+        c[a] = ci;
+        fd[a] = p - (double)ci;
+        f[a] = (float)fd[a];
+        X[a] = P.origin[a] + p * P.spacing[a];
+    }
+    const double rr = P.a * sqrt(uu[3]);
+    double sn, cs;
+    sincos(kTwoPi * uu[4], &sn, &cs);
+    double u[3] = {rr * cs - X[0], rr * sn - X[1], P.z_lens - X[2]};
+    const double il = 1.0 / sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) u[a] *= il;
+    CellCache cc;
+    cc.key = -1;
+    float D0[3];
+    const float n0 = sample_D<float>(P, cc, c, f, D0);
+    // FP32
+    int c32[3] = {c[0], c[1], c[2]};
+    double fd32[3] = {fd[0], fd[1], fd[2]};
+    float Tr[3], dT[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double T0 = (double)n0 * u[a];
+        Tr[a] = (float)T0;
+        dT[a] = (float)(T0 - (double)Tr[a]);
+    }
+    const float g[3] = {(float)P.step_cell[0], (float)P.step_cell[1], (float)P.step_cell[2]};
+    for (int k = 0; k < n_steps; ++k) rkn_step<float, true>(P, cc, c32, fd32, Tr, dT, g, (float)P.h, 1.0f);
+    // FP64
+    int c64[3] = {c[0], c[1], c[2]};
+    double fd64[3] = {fd[0], fd[1], fd[2]};
+    double T64[3], d64[3] = {0.0, 0.0, 0.0};
+    const double g64[3] = {P.step_cell[0], P.step_cell[1], P.step_cell[2]};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) T64[a] = (double)n0 * u[a];
+    cc.key = -1;
+    for (int k = 0; k < n_steps; ++k) rkn_step<double, true>(P, cc, c64, fd64, T64, d64, g64, P.h, 1.0);
+    double q32[2], q64[2];
+    {
+        double Xa[3], Xb[3], da[3], db[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            Xa[a] = P.origin[a] + ((double)c32[a] + fd32[a]) * P.spacing[a];
+            Xb[a] = P.origin[a] + ((double)c64[a] + fd64[a]) * P.spacing[a];
+            da[a] = (double)Tr[a] + (double)dT[a];
+            db[a] = T64[a] + d64[a];
+        }
+        const double ta = (Xa[2] - z_focus) / da[2], tb = (Xb[2] - z_focus) / db[2];
+        q32[0] = Xa[0] - ta * da[0]; q32[1] = Xa[1] - ta * da[1];
+        q64[0] = Xb[0] - tb * db[0]; q64[1] = Xb[1] - tb * db[1];
+    }
+    const double e = px_per_m * sqrt((q32[0] - q64[0]) * (q32[0] - q64[0]) + (q32[1] - q64[1]) * (q32[1] - q64[1]));
+    const float ef = (float)e;
+    if (ef > 0.0f) atomicMax(&s_err, __float_as_uint(ef));
+    __syncthreads();
+    if (threadIdx.x == 0) err[blockIdx.x] = __uint_as_float(s_err);
+}
+
 // ------------------------------------------------------------------ kernel 3: lens, sensor, spot
 
 // Spot of one ray (sec. 3.4): fractions of a Gaussian of sigma_px centred at (x, y) over the
@@ -543,7 +760,17 @@ __global__ void __launch_bounds__(256) k_finish(TraceParams P, const RayState *_
 
 }  // namespace
 
-int launch_trace_chunk(const TraceParams &p, RayState *st, int64_t first, int64_t n, bool fp64,
+int launch_calibrate(const TraceParams &p, const int *bricks, int n_bricks, int rays_per_brick,
+                     int n_steps, uint64_t seed, double z_focus, double px_per_m, float *err,
+                     hipStream_t stream)
+{
+    if (n_bricks <= 0) return 0;
+    hipLaunchKernelGGL(k_calibrate, dim3((unsigned)n_bricks), dim3((unsigned)rays_per_brick), 0, stream, p,
+                       bricks, n_steps, seed, z_focus, px_per_m, err);
+    return (int)hipGetLastError();
+}
+
+int launch_trace_chunk(const TraceParams &p, RayState *st, int64_t first, int64_t n, int prec,
                        hipStream_t stream, hipEvent_t box_begin, hipEvent_t box_end)
 {
     if (n <= 0) return 0;
@@ -552,8 +779,10 @@ int launch_trace_chunk(const TraceParams &p, RayState *st, int64_t first, int64_
     int e = (int)hipGetLastError();
     if (e) return e;
     if (box_begin && (e = (int)hipEventRecord(box_begin, stream))) return e;
-    if (fp64)
+    if (prec == PREC_FP64)
         hipLaunchKernelGGL(k_box64, dim3(blocks), dim3(256), 0, stream, p, st, n);
+    else if (prec == PREC_MIXED)
+        hipLaunchKernelGGL(k_box_mixed, dim3(blocks), dim3(256), 0, stream, p, st, n);
     else
         hipLaunchKernelGGL(k_box32, dim3(blocks), dim3(256), 0, stream, p, st, n);
     e = (int)hipGetLastError();

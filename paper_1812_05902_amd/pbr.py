@@ -23,14 +23,15 @@ PBR_OK, PBR_ERR_ARG, PBR_ERR_STATE, PBR_ERR_HIP, PBR_ERR_WORKSPACE, PBR_ERR_OVER
 (PBR_RAY_DEPOSITED, PBR_RAY_OFF_SENSOR, PBR_RAY_BLOCKED_APERTURE, PBR_RAY_BLOCKED_LENS,
  PBR_RAY_TIR, PBR_RAY_STEP_LIMIT, PBR_RAY_MISSED) = range(7)
 PBR_NUM_STATUS = 7
-PBR_CLEAR_FIRST, PBR_RECORD_EXITS, PBR_PREC_FP64_ALL = 1, 2, 4
+PBR_CLEAR_FIRST, PBR_RECORD_EXITS, PBR_PREC_FP64_ALL, PBR_PREC_SHOCK_FP64 = 1, 2, 4, 8
 PBR_FMT_RAW_U64, PBR_FMT_F32, PBR_FMT_U16 = 0, 1, 2
 
 EXPORTED = ["pbr_create", "pbr_destroy", "pbr_last_error", "pbr_set_stream",
             "pbr_field_workspace_bytes", "pbr_trace_workspace_bytes", "pbr_set_trace_workspace",
             "pbr_set_density_field", "pbr_set_optics",
             "pbr_set_sensor", "pbr_get_derived", "pbr_set_exit_recording",
-            "pbr_emit_and_trace", "pbr_read_image", "pbr_read_ray_exits"]
+            "pbr_emit_and_trace", "pbr_calibrate_precision", "pbr_brick_flags",
+            "pbr_read_image", "pbr_read_ray_exits"]
 
 
 class PbrError(RuntimeError):
@@ -60,8 +61,15 @@ class pbr_derived(C.Structure):
 
 class pbr_stats(C.Structure):
     _fields_ = [("rays", C.c_uint64), ("status", C.c_uint64 * PBR_NUM_STATUS),
-                ("entered_volume", C.c_uint64), ("rkn_steps", C.c_uint64), ("trace_ms", C.c_double),
+                ("entered_volume", C.c_uint64), ("rkn_steps", C.c_uint64),
+                ("rkn_steps_fp64", C.c_uint64), ("trace_ms", C.c_double),
                 ("box_ms", C.c_double), ("box_launches", C.c_uint64)]
+
+
+class pbr_precision_report(C.Structure):
+    _fields_ = [("n_bricks", C.c_int64), ("n_steep", C.c_int64), ("n_fp64", C.c_int64),
+                ("grad_threshold", C.c_double), ("grad_max", C.c_double), ("max_err_px", C.c_double),
+                ("tol_px", C.c_double), ("steps_per_sample", C.c_int32), ("rays_per_brick", C.c_int32)]
 
 
 RAY_EXIT_DTYPE = np.dtype([("ray_id", "<i8"), ("status", "<i4"), ("n_steps", "<i4"),
@@ -96,6 +104,8 @@ def load(path: str = LIB_PATH):
         "pbr_get_derived": (I, [P, C.POINTER(pbr_derived)]),
         "pbr_set_exit_recording": (I, [P, I64, I64, I64, P]),
         "pbr_emit_and_trace": (I, [P, P, I64, C.c_int32, U64, D, U32, C.POINTER(pbr_stats)]),
+        "pbr_calibrate_precision": (I, [P, D, D, C.c_int32, U64, D, C.POINTER(pbr_precision_report)]),
+        "pbr_brick_flags": (I, [P, P, I64, I]),
         "pbr_read_image": (I, [P, I, P, D]),
         "pbr_read_ray_exits": (I, [P, P, I64, I64]),
     }
@@ -182,6 +192,20 @@ def pbr_emit_and_trace(ctx, src, rays_per_src, seed, ds, flags=0, want_stats=Fal
     return st
 
 
+def pbr_calibrate_precision(ctx, tol_px, steep_frac, rays_per_brick, seed, ds) -> pbr_precision_report:
+    rep = pbr_precision_report()
+    _check(ctx, load().pbr_calibrate_precision(ctx, float(tol_px), float(steep_frac), int(rays_per_brick),
+                                               int(seed), float(ds), C.byref(rep)))
+    return rep
+
+
+def pbr_brick_flags(ctx, n_bricks, flags=None) -> np.ndarray:
+    """Reads the per-brick FP64 flags, or writes ``flags`` (uint8 array) when given."""
+    arr = np.zeros(int(n_bricks), dtype=np.uint8) if flags is None else np.ascontiguousarray(flags, dtype=np.uint8)
+    _check(ctx, load().pbr_brick_flags(ctx, arr.ctypes.data_as(C.c_void_p), int(n_bricks), 0 if flags is None else 1))
+    return arr
+
+
 def pbr_read_image(ctx, fmt, out, gain=0.0):
     _check(ctx, load().pbr_read_image(ctx, int(fmt), _dptr(out), float(gain)))
 
@@ -197,6 +221,7 @@ def pbr_read_ray_exits(ctx, first, count) -> np.ndarray:
 def stats_dict(st: pbr_stats) -> dict:
     return dict(rays=int(st.rays), status=[int(x) for x in st.status],
                 entered_volume=int(st.entered_volume), rkn_steps=int(st.rkn_steps),
+                rkn_steps_fp64=int(st.rkn_steps_fp64),
                 trace_ms=float(st.trace_ms), box_ms=float(st.box_ms),
                 box_launches=int(st.box_launches))
 
@@ -237,6 +262,7 @@ class Renderer:
         if self.ws is None or self.ws.numel() * 4 < nb:
             self.ws = torch.empty((nb + 3) // 4, dtype=torch.float32, device=self.device)
         pbr_set_density_field(self.ctx, rho, origin, spacing, K, rho_inf, self.ws)
+        self.grid_shape = (nx, ny, nz)
         self._rho_keepalive = rho  # until the stream passes field preparation
 
     def set_optics(self, z_front_vertex, focal_length, f_number, thickness=0.0, n_glass=1.5,
@@ -271,6 +297,14 @@ class Renderer:
         st = pbr_emit_and_trace(self.ctx, src, rays_per_src, seed, ds, flags, want_stats=stats)
         self._src_keepalive = src
         return stats_dict(st) if st is not None else None
+
+    def calibrate_precision(self, ds, tol_px=1e-3, steep_frac=0.1, rays_per_brick=64, seed=12345) -> dict:
+        rep = pbr_calibrate_precision(self.ctx, tol_px, steep_frac, rays_per_brick, seed, ds)
+        return {k: getattr(rep, k) for k, _ in pbr_precision_report._fields_}
+
+    def brick_flags(self, flags=None) -> np.ndarray:
+        nb = [(n - 1 + 7) // 8 for n in self.grid_shape]
+        return pbr_brick_flags(self.ctx, nb[0] * nb[1] * nb[2], flags)
 
     def read_image(self, fmt=PBR_FMT_RAW_U64, gain=0.0):
         torch = self.torch

@@ -32,7 +32,7 @@ def _declared():
 
 def test_exports_every_declared_function(lib):
     names = _declared()
-    assert len(names) >= 15
+    assert len(names) >= 17
     for n in names:
         assert hasattr(lib, n), n
     assert sorted(pbr.EXPORTED) == names
@@ -43,13 +43,18 @@ def test_struct_sizes_match_header_layout(lib):
     assert pbr.RAY_EXIT_DTYPE.itemsize == 88
     assert C.sizeof(pbr.pbr_optics) == 56
     assert C.sizeof(pbr.pbr_sensor) == 48
-    assert C.sizeof(pbr.pbr_stats) == 8 * (1 + 7 + 2) + 8 * 3
+    assert C.sizeof(pbr.pbr_stats) == 8 * (1 + 7 + 3) + 8 * 3
+    assert C.sizeof(pbr.pbr_precision_report) == 8 * 7 + 8
 
 
 def test_workspace_bytes(lib):
-    # 128 bytes of trilinear coefficients per cell
-    assert pbr.pbr_field_workspace_bytes(32, 32, 32) == 31 ** 3 * 128
-    assert pbr.pbr_field_workspace_bytes(512, 512, 512) == 511 ** 3 * 128
+    # 128 bytes of trilinear coefficients per cell, then 4 + 1 bytes per brick of 8^3 cells,
+    # each part rounded up to 256 bytes
+    up = lambda v: (v + 255) // 256 * 256
+    for n in (32, 512):
+        nb = ((n - 1 + 7) // 8) ** 3
+        want = up(up(up((n - 1) ** 3 * 128) + 4 * nb) + nb)
+        assert pbr.pbr_field_workspace_bytes(n, n, n) == want
     assert pbr.pbr_field_workspace_bytes(1, 4, 4) == 0
     # 64 bytes of ray state per ray of a chunk, at least 256 rays
     assert pbr.pbr_trace_workspace_bytes(1 << 22) == (1 << 22) * 64
