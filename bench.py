@@ -74,6 +74,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="turbulence_bos_128", choices=["turbulence_bos_128", "batch64"],
+                    help="batch64: the 64 uneven images of inputs.batch_scenes in one graph-captured batch")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy a 1 GiB device buffer 4 times (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -95,6 +97,8 @@ def main():
     import torch
     from paper_1812_05902_amd import inputs, pbr
 
+    if args.workload == "batch64":
+        return bench_batch(args)
     scene = inputs.turbulence_bos()
     rho = inputs.density(scene)
     src = inputs.sources(scene)
@@ -153,6 +157,61 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(scene, rho, src)
+    print(json.dumps(out), flush=True)
+
+
+def bench_batch(args):
+    """64 images of uneven particle counts, rays per particle, grids (64^3 / 128^3 / 256^3) and
+    sensors (512^2 .. 2048^2) in one graph-captured batch, tuned by the library's autotuner."""
+    import tempfile
+
+    import torch
+    from paper_1812_05902_amd import inputs, pbr
+
+    scenes = inputs.batch_scenes(64)
+    t0 = time.perf_counter()
+    rs, srcs = [], []
+    for sc in scenes:
+        r = pbr.Renderer(rays_per_chunk=1 << 8)
+        r.set_density_field(inputs.density(sc), sc.origin, sc.spacing, sc.K, sc.rho_inf)
+        r.set_optics(sc.z_lens, sc.focal_length, sc.f_number, sc.thickness, sc.n_glass, sc.clear_radius,
+                     sc.z_focus)
+        r.set_sensor(sc.width, sc.height, sc.pitch, sc.z_sensor, sc.wavelength, sc.sigma_px, sc.dtau_with_pi)
+        rs.append(r)
+        srcs.append(inputs.sources(sc))
+        torch.cuda.synchronize()
+        del r._rho_keepalive
+    setup_s = time.perf_counter() - t0
+    b = pbr.Batch(rs, srcs, [sc.rays_per_src for sc in scenes], [sc.ray_seed for sc in scenes],
+                  [sc.ds for sc in scenes], round_rays=1 << 24)
+    cache = os.path.join(tempfile.gettempdir(), "pbr_batch_tune.txt")
+    cfg, rate = b.autotune(cache_path=cache, probe_rounds=2)
+    for _ in range(args.warmup):
+        b.run(stats=False)
+    torch.cuda.synchronize()
+    steps, run_ms = 0, 0.0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        st = b.run(stats=True)
+        run_ms += st["run_ms"]
+        steps += st["rkn_steps"]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    n_rays = sum(sc.n_rays for sc in scenes)
+    achieved = steps * FLOPS_PER_STEP / (run_ms * 1e-3) / 1e12
+    out = {
+        "metric": "rays/sec on 1 MI355X (trace+lens+sensor)", "value": n_rays * args.steps / wall,
+        "unit": "rays/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "batch64", "images": len(scenes), "rays_per_batch": n_rays,
+                   "rounds": st["rounds"], "autotuned": cfg, "probe_rays_per_ms": rate,
+                   "mean_rkn_steps_per_ray": steps / args.steps / n_rays, "setup_s": setup_s},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "kernel": "whole batch graph (emit + persistent k_box_batch + finish)",
+                     "graph_ms_per_step": run_ms / args.steps, "flops_per_rkn_step": FLOPS_PER_STEP},
+    }
     print(json.dumps(out), flush=True)
 
 

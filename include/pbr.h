@@ -257,6 +257,83 @@ int pbr_read_image(pbr_ctx *ctx, int fmt, void *out_dev, double gain);
  * synchronises the stream.  Errors: ARG (range outside the buffer), STATE (no recording set). */
 int pbr_read_ray_exits(pbr_ctx *ctx, pbr_ray_exit *out_host, int64_t first, int64_t count);
 
+/* ---------------------------------------------------------------- batches of images */
+
+/* Many images (each its own context: field, optics, sensor, accumulator, exit recording, all set
+ * beforehand on one GPU) traced in one graph-captured launch sequence.  The batch snapshots each
+ * context's field, optics, sensor and recording at pbr_batch_create.  Image k of a batch is bit
+ * for bit the image pbr_emit_and_trace would render alone (integer deposits, same per-ray
+ * arithmetic).  Integration is FP32.
+ *
+ * The rays of all images are laid out in rounds (at most round_rays ray states each): images in
+ * decreasing estimated cost per ray (box depth / ds), each split across rounds as needed and
+ * padded to whole blocks of 256 rays.  A round is three kernels: emission, a persistent
+ * integration kernel in which every wave pulls the next unit_rays rays from a global counter, and
+ * lens / sensor / deposit (LDS tile of tile x tile pixels).  The first pbr_batch_run after
+ * creation or pbr_batch_configure captures clears, counters and all rounds into one HIP graph;
+ * later runs replay it. */
+typedef struct pbr_batch pbr_batch;
+
+typedef struct pbr_batch_item {
+    pbr_ctx *ctx;            /* the image's context */
+    const float *src_dev;    /* float32 [n_src][4] sources, 16-byte aligned (as pbr_emit_and_trace) */
+    int64_t n_src;
+    int32_t rays_per_src;
+    uint32_t flags;          /* PBR_CLEAR_FIRST and/or PBR_RECORD_EXITS only */
+    uint64_t seed;
+    double ds;
+} pbr_batch_item;
+
+typedef struct pbr_batch_config {
+    int32_t box_block;       /* threads per block of the persistent integration kernel: 64 or 256 */
+    int32_t unit_rays;       /* rays a wave pulls from the work queue at a time: 64, 128 or 256 */
+    int32_t tile;            /* deposit pre-aggregation tile side in pixels: 16 or 32 */
+    int32_t reserved;
+    int64_t round_rays;      /* ray states per round, multiple of 256 in [min_round_rays, max_round_rays] */
+    int64_t max_round_rays;  /* (out) the largest round the workspace holds */
+    int64_t min_round_rays;  /* (out) the smallest round the segment table allows */
+    int32_t rounds;          /* (out) rounds of the current plan */
+    int32_t pad;
+} pbr_batch_config;
+
+typedef struct pbr_batch_stats {
+    uint64_t rays;
+    uint64_t status[PBR_NUM_STATUS];
+    uint64_t rkn_steps;
+    double run_ms;           /* device time of the graph launch (HIP events) */
+    int32_t rounds;
+    int32_t images;
+} pbr_batch_stats;
+
+/* Workspace bytes for a batch whose rounds hold up to round_rays rays (64 bytes per ray state
+ * plus parameters and segment tables); 0 on bad arguments. */
+size_t pbr_batch_workspace_bytes(const pbr_batch_item *items, int n_items, int64_t round_rays);
+
+/* Validates every item (as pbr_emit_and_trace would), uploads per-image launch parameters into
+ * ws_dev (256-byte aligned, caller-owned, live until pbr_batch_destroy) and plans the rounds with
+ * the default configuration (box_block 64, unit_rays 64, tile 32, largest round).  Launches and
+ * graph replays go to hip_stream.  Errors: ARG, STATE (a context lacks field/optics/sensor),
+ * WORKSPACE, OVERFLOW, HIP; the message is in pbr_batch_last_error(NULL). */
+int pbr_batch_create(pbr_batch **out, const pbr_batch_item *items, int n_items, void *ws_dev,
+                     size_t ws_bytes, void *hip_stream);
+void pbr_batch_destroy(pbr_batch *b);
+const char *pbr_batch_last_error(const pbr_batch *b);
+int pbr_batch_get_config(pbr_batch *b, pbr_batch_config *out);
+/* Re-plans with a new configuration (drops the captured graph).  Errors: ARG. */
+int pbr_batch_configure(pbr_batch *b, const pbr_batch_config *cfg);
+/* Runs the whole batch (graph launch); with stats non-NULL synchronises and sums the counters of
+ * all images.  Errors: OVERFLOW (an accumulating item would exceed 2^32 - 1 rays), HIP. */
+int pbr_batch_run(pbr_batch *b, pbr_batch_stats *stats);
+/* Autotuner of the batched launch.  With cache_path naming a file that holds a choice for this
+ * device and batch shape (architecture, grid and sensor sizes, source and ray counts of every
+ * image), that choice is applied.  Otherwise every combination of box_block {64, 256},
+ * unit_rays {64, 256}, tile {16, 32} and round_rays {largest, half} is timed on the first
+ * probe_rounds rounds (direct launches, HIP events), the fastest (rays per ms) is applied and
+ * appended to cache_path (if given).  Leaves the accumulators and counters of the batch's images
+ * in an unspecified state: run the batch with PBR_CLEAR_FIRST items afterwards.  Synchronises. */
+int pbr_batch_autotune(pbr_batch *b, const char *cache_path, int32_t probe_rounds, pbr_batch_config *chosen,
+                       double *rays_per_ms);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,77 @@
+// Private host-side state of a context, shared by the single-image API and the batch API.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "pbr_internal.h"
+
+struct pbr_ctx {
+    int device = 0;            // -1: host-only context (validation and derived optics, no device work)
+    hipStream_t stream = nullptr;
+    std::string err;
+    unsigned long long *counters = nullptr;  // 4 KiB device block
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    std::vector<hipEvent_t> box_ev;  // pairs around each integration launch (stats only)
+    // field
+    bool has_field = false;
+    const float4 *cells = nullptr;
+    unsigned *brick_gmax = nullptr;        // per-brick max |grad n| (float bits), device
+    unsigned char *brick_fp64 = nullptr;   // per-brick FP64 flags, device
+    pbr::FieldLayout layout{};
+    int64_t n_fp64_bricks = 0;
+    int nx = 0, ny = 0, nz = 0;
+    double origin[3] = {0, 0, 0}, spacing[3] = {0, 0, 0};
+    double K = 0.0, rho_inf = 0.0;
+    // optics
+    bool has_optics = false;
+    pbr_optics optics{};
+    // sensor
+    bool has_sensor = false;
+    pbr_sensor sensor{};
+    unsigned long long *accum = nullptr;
+    double accum_rays = 0.0;  // rays deposited since the last clear (overflow bound)
+    // per-ray state between the trace kernels
+    pbr::RayState *ray_ws = nullptr;
+    int64_t ray_chunk = 0;
+    // exit recording
+    pbr_ray_exit *rec = nullptr;
+    int64_t rec_first = 0, rec_stride = 1, rec_max = 0;
+    int last_max_steps = 0;
+};
+
+namespace pbr {
+namespace host {
+
+// Makes the context's device current for the duration of a call.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard()
+    {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+struct Derived {
+    double n_inf, R, t, a, clear, z_sensor, M, sigma_px;
+    int rfp;
+};
+
+// Records a formatted message on the context (or the creation error when c is null).
+int fail(pbr_ctx *c, int code, const char *fmt, ...);
+int hip_fail(pbr_ctx *c, int e, const char *what);
+// Derived optics of a context whose field, optics and sensor are set (PBR_ERR_STATE otherwise).
+int derive(pbr_ctx *c, Derived *d);
+// Launch parameters shared by the trace and the calibration (sources and rays left empty).
+void fill_params(const pbr_ctx *ctx, const Derived &d, double ds, TraceParams *out);
+
+}  // namespace host
+}  // namespace pbr

@@ -102,7 +102,24 @@ struct RayState {
 static_assert(sizeof(RayState) == 64, "RayState layout");
 enum : int { RS_ENTERED = 1, RS_LIMITED = 2, RS_STEP_SHIFT = 4 };
 
-constexpr int kTile = 32;  // deposit pre-aggregation tile (pixels per side, in LDS)
+constexpr int kTile = 32;  // deposit pre-aggregation tile of single-image traces (pixels per side, in LDS)
+
+// One segment of a batch round (see launch_batch_round).
+struct BatchSeg {
+    int32_t image;
+    int32_t pad;
+    int64_t first_ray;
+    int64_t n_rays;
+    int64_t slot_base;  // first slot (256 rays) of the segment's states in the round
+};
+
+// Tunables of the batched launch.
+struct BatchConfig {
+    int box_block;      // threads per block of the persistent integration kernel: 64 or 256
+    int unit_rays;      // rays a wave pulls from the queue at a time: 64, 128 or 256
+    int tile;           // deposit tile: 16 or 32 pixels per side
+    int64_t round_rays; // rays per round (bounded by the workspace)
+};
 
 // Launchers (defined in the .hip files; enqueue on `stream`, return hipError_t as int).
 // Writes the cell records and (atomically) the per-brick max |grad n|; gmax must be zeroed.
@@ -114,6 +131,11 @@ int launch_field_prep(const float *rho, float4 *cells, unsigned *brick_gmax, int
 int launch_calibrate(const TraceParams &p, const int *bricks, int n_bricks, int rays_per_brick,
                      int n_steps, uint64_t seed, double z_focus, double px_per_m, float *err,
                      hipStream_t stream);
+// One round of a batch: emission over n_slots * 256 ray states, persistent integration with a
+// wave-level work queue (queue: one zeroed counter), finish with per-segment parameters.
+int launch_batch_round(const TraceParams *params, const BatchSeg *segs, int nseg, int64_t n_slots,
+                       RayState *st, unsigned *queue, const BatchConfig &cfg, int n_cu, hipStream_t stream);
+
 // Rays [first, first + n) through all four steps; st: n RayState of workspace.
 // box_begin / box_end (may be null) are recorded around the integration kernel.
 enum PrecMode : int { PREC_FP32 = 0, PREC_FP64 = 1, PREC_MIXED = 2 };

@@ -271,12 +271,8 @@ __device__ __forceinline__ void atomic_add_u64(unsigned long long *p, unsigned l
 // a sqrt(u1) sin 2 pi u2) of the front-vertex plane; (u1, u2) are the two 24-bit fields of
 // SplitMix64 output number (s << 32 | j).  The ray goes straight to the box (slab test) and its
 // state is written cell-local; a ray that never enters keeps its world position and direction.
-__global__ void __launch_bounds__(256) k_emit(TraceParams P, RayState *__restrict__ st, int64_t first,
-                                              int64_t n)
+__device__ __forceinline__ void emit_ray(const TraceParams &P, int64_t rid, RayState &r)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int64_t rid = first + i;
     const int64_t s = rid / P.rays_per_src;
     const int32_t j = (int32_t)(rid - s * P.rays_per_src);
     const float4 sv = P.src[s];
@@ -318,7 +314,6 @@ __global__ void __launch_bounds__(256) k_emit(TraceParams P, RayState *__restric
             for (int a = 0; a < 3; ++a) Rw[a] = S[a] + tn * u[a];
         }
     }
-    RayState r;
     if (!entered) {
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
@@ -328,7 +323,6 @@ __global__ void __launch_bounds__(256) k_emit(TraceParams P, RayState *__restric
             r.c[a] = 0;
         }
         r.info = 0;
-        st[i] = r;
         return;
     }
     const int nn[3] = {P.nx, P.ny, P.nz};
@@ -357,18 +351,23 @@ __global__ void __launch_bounds__(256) k_emit(TraceParams P, RayState *__restric
         r.dT[a] = (float)(T0 - (double)r.Tr[a]);
     }
     r.info = RS_ENTERED;
+}
+
+__global__ void __launch_bounds__(256) k_emit(TraceParams P, RayState *__restrict__ st, int64_t first,
+                                              int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    RayState r;
+    emit_ray(P, first + i, r);
     st[i] = r;
 }
 
 // ------------------------------------------------------------------ kernel 2: the ray equation
 
 template <typename F>
-__device__ __forceinline__ void box_body(const TraceParams &P, RayState *__restrict__ st, int64_t n)
+__device__ __forceinline__ void box_ray(const TraceParams &P, RayState &r)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    RayState r = st[i];
-    if (!(r.info & RS_ENTERED)) return;
     // T = Tr + dT; in FP32 the low part of the entry direction starts the accumulated change
     F Tr[3], dT[3];
 #pragma unroll
@@ -393,6 +392,16 @@ __device__ __forceinline__ void box_body(const TraceParams &P, RayState *__restr
         r.dT[a] = (float)(T - (double)r.Tr[a]);
     }
     r.info = RS_ENTERED | (limited ? RS_LIMITED : 0) | (steps << RS_STEP_SHIFT);
+}
+
+template <typename F>
+__device__ __forceinline__ void box_body(const TraceParams &P, RayState *__restrict__ st, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    RayState r = st[i];
+    if (!(r.info & RS_ENTERED)) return;
+    box_ray<F>(P, r);
     st[i] = r;
 }
 
@@ -622,7 +631,7 @@ __global__ void __launch_bounds__(256) k_calibrate(TraceParams P, const int *__r
 // pixels of the (2R+1)^2 window around the hit pixel, each the product of two erf differences,
 // times the source weight, rounded to Q32.32.  Pixels inside the block's LDS tile are summed
 // there first (integer adds, so the order does not matter); the others go straight to HBM.
-template <int RF>
+template <int RF, int TILE>
 __device__ __forceinline__ void deposit(const TraceParams &P, double x, double y, double w,
                                         unsigned long long *tile, int tx0, int ty0)
 {
@@ -649,113 +658,208 @@ __device__ __forceinline__ void deposit(const TraceParams &P, double x, double y
             const unsigned long long q = (unsigned long long)rint((double)cval * kTwoPow32);
             if (!q) continue;
             const int lx = ii - tx0, ly = jj - ty0;
-            if ((unsigned)lx < (unsigned)kTile && (unsigned)ly < (unsigned)kTile)
-                atomicAdd(tile + ly * kTile + lx, q);
+            if ((unsigned)lx < (unsigned)TILE && (unsigned)ly < (unsigned)TILE)
+                atomicAdd(tile + ly * TILE + lx, q);
             else
                 atomic_add_u64(P.accum + (size_t)jj * (size_t)P.W + ii, q);
         }
     }
 }
 
+// Shared memory of the finish step of one block.
+template <int TILE>
+struct FinishShared {
+    unsigned long long tile[TILE * TILE];
+    unsigned long long cnt[CNT_SLOTS];
+    int lead, tx0, ty0;
+};
+
+// Lens, sensor, spot, records and counters for the rays [first + base, first + base + 256) of one
+// image, whose states are st[base ..]; rays at or beyond n are padding.  All threads of the block
+// take part (barriers inside).
+template <int TILE>
+__device__ __forceinline__ void finish_block(const TraceParams &P, const RayState *__restrict__ st,
+                                             int64_t first, int64_t base, int64_t n, FinishShared<TILE> &sh)
+{
+    for (int q = threadIdx.x; q < TILE * TILE; q += blockDim.x) sh.tile[q] = 0ull;
+    if (threadIdx.x == 0) sh.lead = 0x7fffffff;
+    __syncthreads();
+
+    const int64_t i = base + threadIdx.x;
+    const bool valid = i < n;
+    int status = PBR_RAY_MISSED, nsteps = 0;
+    bool entered = false;
+    double Rw[3] = {0, 0, 0}, dir[3] = {0, 0, 1}, xpx = 0.0, ypx = 0.0;
+    if (valid) {
+        const RayState r = st[i];
+        entered = (r.info & RS_ENTERED) != 0;
+        nsteps = entered ? (r.info >> RS_STEP_SHIFT) : 0;
+        status = PBR_RAY_DEPOSITED;
+        double tn2 = 0.0, T[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            Rw[a] = entered ? P.origin[a] + ((double)r.c[a] + r.fd[a]) * P.spacing[a] : r.fd[a];
+            T[a] = (double)r.Tr[a] + (double)r.dT[a];
+            tn2 += T[a] * T[a];
+        }
+        const double it = 1.0 / sqrt(tn2);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) dir[a] = T[a] * it;
+        if (r.info & RS_LIMITED) status = PBR_RAY_STEP_LIMIT;
+        if (status == PBR_RAY_DEPOSITED) status = optics_to_sensor(P, Rw, dir, &xpx, &ypx);
+        if (status == PBR_RAY_DEPOSITED &&
+            !(xpx >= 0.0 && ypx >= 0.0 && xpx < (double)P.W && ypx < (double)P.H))
+            status = PBR_RAY_OFF_SENSOR;
+        if (status == PBR_RAY_DEPOSITED) atomicMin(&sh.lead, (int)threadIdx.x);
+    }
+    __syncthreads();
+    // the block's first deposited ray anchors the tile: rays of one source land close together
+    if ((int)threadIdx.x == sh.lead) {
+        sh.tx0 = (int)xpx - TILE / 2;
+        sh.ty0 = (int)ypx - TILE / 2;
+    }
+    __syncthreads();
+    if (valid && status == PBR_RAY_DEPOSITED) {
+        const int64_t rid = first + i;
+        const float4 sv = P.src[rid / P.rays_per_src];
+        const double w = sv.w > 0.0f ? (sv.w < 1.0f ? (double)sv.w : 1.0) : 0.0;  // weights in [0, 1]
+        const int tx0 = sh.tx0, ty0 = sh.ty0;
+        switch (P.rfp) {
+            case 1: deposit<1, TILE>(P, xpx, ypx, w, sh.tile, tx0, ty0); break;
+            case 2: deposit<2, TILE>(P, xpx, ypx, w, sh.tile, tx0, ty0); break;
+            case 3: deposit<3, TILE>(P, xpx, ypx, w, sh.tile, tx0, ty0); break;
+            case 4: deposit<4, TILE>(P, xpx, ypx, w, sh.tile, tx0, ty0); break;
+            case 5: deposit<5, TILE>(P, xpx, ypx, w, sh.tile, tx0, ty0); break;
+            case 6: deposit<6, TILE>(P, xpx, ypx, w, sh.tile, tx0, ty0); break;
+            case 7: deposit<7, TILE>(P, xpx, ypx, w, sh.tile, tx0, ty0); break;
+            default: deposit<8, TILE>(P, xpx, ypx, w, sh.tile, tx0, ty0); break;
+        }
+    }
+    if (valid) {
+        const int64_t rid = first + i;
+        if (P.record && rid >= P.rec_first) {
+            const int64_t off = rid - P.rec_first;
+            const int64_t k = off / P.rec_stride;
+            if (k * P.rec_stride == off && k < P.rec_max) {
+                pbr_ray_exit e;
+                e.ray_id = rid;
+                e.status = status;
+                e.n_steps = nsteps;
+                e.entered = entered ? 1 : 0;
+                e.reserved = 0;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) { e.vol_exit_pos[a] = Rw[a]; e.vol_exit_dir[a] = dir[a]; }
+                e.sensor_px[0] = xpx;
+                e.sensor_px[1] = ypx;
+                P.rec[k] = e;
+            }
+        }
+        atomicAdd(&sh.cnt[CNT_STATUS + status], 1ull);
+        if (entered) atomicAdd(&sh.cnt[CNT_ENTERED], 1ull);
+        atomicAdd(&sh.cnt[CNT_STEPS], (unsigned long long)nsteps);
+    }
+    __syncthreads();
+    // flush the tile: one global atomic per touched pixel
+    if (sh.lead != 0x7fffffff) {
+        const int tx0 = sh.tx0, ty0 = sh.ty0;
+        for (int q = threadIdx.x; q < TILE * TILE; q += blockDim.x) {
+            const unsigned long long v = sh.tile[q];
+            if (v) atomic_add_u64(P.accum + (size_t)(ty0 + q / TILE) * (size_t)P.W + (tx0 + q % TILE), v);
+        }
+    }
+    __syncthreads();
+}
+
+template <int TILE>
+__device__ __forceinline__ void flush_counters(const TraceParams &P, FinishShared<TILE> &sh)
+{
+    if (threadIdx.x < CNT_STEPS + 1 && sh.cnt[threadIdx.x] != 0ull)
+        atomic_add_u64(P.counters + threadIdx.x, sh.cnt[threadIdx.x]);
+}
+
+template <int TILE>
 __global__ void __launch_bounds__(256) k_finish(TraceParams P, const RayState *__restrict__ st,
                                                 int64_t first, int64_t n)
 {
-    __shared__ unsigned long long tile[kTile * kTile];
-    __shared__ unsigned long long s_cnt[CNT_SLOTS];
-    __shared__ int s_lead, s_tx0, s_ty0;
-    if (threadIdx.x < CNT_SLOTS) s_cnt[threadIdx.x] = 0ull;
+    __shared__ FinishShared<TILE> sh;
+    if (threadIdx.x < CNT_SLOTS) sh.cnt[threadIdx.x] = 0ull;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += (int64_t)gridDim.x * blockDim.x)
+        finish_block<TILE>(P, st, first, base, n, sh);
+    flush_counters<TILE>(P, sh);
+}
 
-    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += (int64_t)gridDim.x * blockDim.x) {
-        for (int q = threadIdx.x; q < kTile * kTile; q += blockDim.x) tile[q] = 0ull;
-        if (threadIdx.x == 0) s_lead = 0x7fffffff;
-        __syncthreads();
+// ------------------------------------------------------------------ batches of images
 
-        const int64_t i = base + threadIdx.x;
-        const bool valid = i < n;
-        int status = PBR_RAY_MISSED, nsteps = 0;
-        bool entered = false;
-        double Rw[3] = {0, 0, 0}, dir[3] = {0, 0, 1}, xpx = 0.0, ypx = 0.0;
-        if (valid) {
-            const RayState r = st[i];
-            entered = (r.info & RS_ENTERED) != 0;
-            nsteps = entered ? (r.info >> RS_STEP_SHIFT) : 0;
-            status = PBR_RAY_DEPOSITED;
-            double tn2 = 0.0, T[3];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                Rw[a] = entered ? P.origin[a] + ((double)r.c[a] + r.fd[a]) * P.spacing[a] : r.fd[a];
-                T[a] = (double)r.Tr[a] + (double)r.dT[a];
-                tn2 += T[a] * T[a];
-            }
-            const double it = 1.0 / sqrt(tn2);
-#pragma unroll
-            for (int a = 0; a < 3; ++a) dir[a] = T[a] * it;
-            if (r.info & RS_LIMITED) status = PBR_RAY_STEP_LIMIT;
-            if (status == PBR_RAY_DEPOSITED) status = optics_to_sensor(P, Rw, dir, &xpx, &ypx);
-            if (status == PBR_RAY_DEPOSITED &&
-                !(xpx >= 0.0 && ypx >= 0.0 && xpx < (double)P.W && ypx < (double)P.H))
-                status = PBR_RAY_OFF_SENSOR;
-            if (status == PBR_RAY_DEPOSITED) atomicMin(&s_lead, (int)threadIdx.x);
-        }
-        __syncthreads();
-        // the block's first deposited ray anchors the tile: rays of one source land close together
-        if ((int)threadIdx.x == s_lead) {
-            s_tx0 = (int)xpx - kTile / 2;
-            s_ty0 = (int)ypx - kTile / 2;
-        }
-        __syncthreads();
-        if (valid && status == PBR_RAY_DEPOSITED) {
-            const int64_t rid = first + i;
-            const float4 sv = P.src[rid / P.rays_per_src];
-            const double w = sv.w > 0.0f ? (sv.w < 1.0f ? (double)sv.w : 1.0) : 0.0;  // weights in [0, 1]
-            const int tx0 = s_tx0, ty0 = s_ty0;
-            switch (P.rfp) {
-                case 1: deposit<1>(P, xpx, ypx, w, tile, tx0, ty0); break;
-                case 2: deposit<2>(P, xpx, ypx, w, tile, tx0, ty0); break;
-                case 3: deposit<3>(P, xpx, ypx, w, tile, tx0, ty0); break;
-                case 4: deposit<4>(P, xpx, ypx, w, tile, tx0, ty0); break;
-                case 5: deposit<5>(P, xpx, ypx, w, tile, tx0, ty0); break;
-                case 6: deposit<6>(P, xpx, ypx, w, tile, tx0, ty0); break;
-                case 7: deposit<7>(P, xpx, ypx, w, tile, tx0, ty0); break;
-                default: deposit<8>(P, xpx, ypx, w, tile, tx0, ty0); break;
-            }
-        }
-        if (valid) {
-            const int64_t rid = first + i;
-            if (P.record && rid >= P.rec_first) {
-                const int64_t off = rid - P.rec_first;
-                const int64_t k = off / P.rec_stride;
-                if (k * P.rec_stride == off && k < P.rec_max) {
-                    pbr_ray_exit e;
-                    e.ray_id = rid;
-                    e.status = status;
-                    e.n_steps = nsteps;
-                    e.entered = entered ? 1 : 0;
-                    e.reserved = 0;
-#pragma unroll
-                    for (int a = 0; a < 3; ++a) { e.vol_exit_pos[a] = Rw[a]; e.vol_exit_dir[a] = dir[a]; }
-                    e.sensor_px[0] = xpx;
-                    e.sensor_px[1] = ypx;
-                    P.rec[k] = e;
-                }
-            }
-            atomicAdd(&s_cnt[CNT_STATUS + status], 1ull);
-            if (entered) atomicAdd(&s_cnt[CNT_ENTERED], 1ull);
-            atomicAdd(&s_cnt[CNT_STEPS], (unsigned long long)nsteps);
-        }
-        __syncthreads();
-        // flush the tile: one global atomic per touched pixel
-        if (s_lead != 0x7fffffff) {
-            const int tx0 = s_tx0, ty0 = s_ty0;
-            for (int q = threadIdx.x; q < kTile * kTile; q += blockDim.x) {
-                const unsigned long long v = tile[q];
-                if (v) atomic_add_u64(P.accum + (size_t)(ty0 + q / kTile) * (size_t)P.W + (tx0 + q % kTile), v);
-            }
-        }
-        __syncthreads();
+// Segment of one round of a batch: rays [first_ray, first_ray + n_rays) of image `image`, whose
+// states start at slot slot_base (a slot = 256 rays; segments are padded to whole slots).
+__device__ __forceinline__ int find_segment(const BatchSeg *__restrict__ segs, int nseg, int64_t slot)
+{
+    int lo = 0, hi = nseg - 1;
+    while (lo < hi) {  // last segment with slot_base <= slot
+        const int mid = (lo + hi + 1) >> 1;
+        if (segs[mid].slot_base <= slot) lo = mid;
+        else hi = mid - 1;
     }
-    if (threadIdx.x < CNT_STEPS + 1 && s_cnt[threadIdx.x] != 0ull)
-        atomic_add_u64(P.counters + threadIdx.x, s_cnt[threadIdx.x]);
+    return lo;
+}
+
+__global__ void __launch_bounds__(256) k_emit_batch(const TraceParams *__restrict__ params,
+                                                    const BatchSeg *__restrict__ segs, int nseg,
+                                                    RayState *__restrict__ st)
+{
+    const int k = __builtin_amdgcn_readfirstlane(find_segment(segs, nseg, blockIdx.x));
+    const BatchSeg sg = segs[k];
+    const int64_t local = (int64_t)(blockIdx.x - sg.slot_base) * 256 + threadIdx.x;
+    if (local >= sg.n_rays) return;
+    RayState r;
+    emit_ray(params[sg.image], sg.first_ray + local, r);
+    st[(int64_t)blockIdx.x * 256 + threadIdx.x] = r;
+}
+
+// Persistent integration over one round: every wave pulls the next unit of `unit_rays` rays
+// (64, 128 or 256: units never straddle a slot) from a global counter until none is left.
+// Segments are ordered by decreasing estimated cost, so long rays start first.
+template <int BLOCK>
+__global__ void __launch_bounds__(BLOCK, 5) k_box_batch(const TraceParams *__restrict__ params,
+                                                        const BatchSeg *__restrict__ segs, int nseg,
+                                                        RayState *__restrict__ st, unsigned *queue,
+                                                        unsigned n_units, int unit_rays)
+{
+    const int lane = threadIdx.x & 63;
+    for (;;) {
+        unsigned u = 0;
+        if (lane == 0) u = atomicAdd(queue, 1u);
+        u = __builtin_amdgcn_readfirstlane(__shfl(u, 0, 64));
+        if (u >= n_units) break;
+        const int64_t ray0 = (int64_t)u * unit_rays;  // state index of the unit's first ray
+        const int k = __builtin_amdgcn_readfirstlane(find_segment(segs, nseg, ray0 >> 8));
+        const BatchSeg sg = segs[k];
+        const TraceParams &P = params[sg.image];
+        for (int sub = 0; sub < unit_rays; sub += 64) {
+            const int64_t idx = ray0 + sub + lane;
+            if (idx - sg.slot_base * 256 >= sg.n_rays) continue;
+            RayState r = st[idx];
+            if (!(r.info & RS_ENTERED)) continue;
+            box_ray<float>(P, r);
+            st[idx] = r;
+        }
+    }
+}
+
+template <int TILE>
+__global__ void __launch_bounds__(256) k_finish_batch(const TraceParams *__restrict__ params,
+                                                      const BatchSeg *__restrict__ segs, int nseg,
+                                                      const RayState *__restrict__ st)
+{
+    __shared__ FinishShared<TILE> sh;
+    if (threadIdx.x < CNT_SLOTS) sh.cnt[threadIdx.x] = 0ull;
+    const int k = __builtin_amdgcn_readfirstlane(find_segment(segs, nseg, blockIdx.x));
+    const BatchSeg sg = segs[k];
+    const TraceParams &P = params[sg.image];
+    const int64_t base = (int64_t)(blockIdx.x - sg.slot_base) * 256;
+    // states of this segment start at slot_base * 256; ray ids at first_ray
+    finish_block<TILE>(P, st + sg.slot_base * 256, sg.first_ray, base, sg.n_rays, sh);
+    flush_counters<TILE>(P, sh);
 }
 
 }  // namespace
@@ -789,7 +893,33 @@ int launch_trace_chunk(const TraceParams &p, RayState *st, int64_t first, int64_
     if (e) return e;
     if (box_end && (e = (int)hipEventRecord(box_end, stream))) return e;
     unsigned fblocks = blocks < 4096u ? blocks : 4096u;
-    hipLaunchKernelGGL(k_finish, dim3(fblocks), dim3(256), 0, stream, p, (const RayState *)st, first, n);
+    hipLaunchKernelGGL(k_finish<kTile>, dim3(fblocks), dim3(256), 0, stream, p, (const RayState *)st, first, n);
+    return (int)hipGetLastError();
+}
+
+int launch_batch_round(const TraceParams *params, const BatchSeg *segs, int nseg, int64_t n_slots,
+                       RayState *st, unsigned *queue, const BatchConfig &cfg, int n_cu, hipStream_t stream)
+{
+    if (n_slots <= 0) return 0;
+    int e = launch_clear_u64((unsigned long long *)queue, 1, stream);
+    if (e) return e;
+    hipLaunchKernelGGL(k_emit_batch, dim3((unsigned)n_slots), dim3(256), 0, stream, params, segs, nseg, st);
+    if ((e = (int)hipGetLastError())) return e;
+    const unsigned n_units = (unsigned)(n_slots * 256 / cfg.unit_rays);
+    const unsigned waves = (unsigned)n_cu * 4u * 5u;  // five waves per SIMD
+    if (cfg.box_block == 64)
+        hipLaunchKernelGGL(k_box_batch<64>, dim3(waves), dim3(64), 0, stream, params, segs, nseg, st, queue,
+                           n_units, cfg.unit_rays);
+    else
+        hipLaunchKernelGGL(k_box_batch<256>, dim3(waves / 4u), dim3(256), 0, stream, params, segs, nseg, st,
+                           queue, n_units, cfg.unit_rays);
+    if ((e = (int)hipGetLastError())) return e;
+    if (cfg.tile == 16)
+        hipLaunchKernelGGL(k_finish_batch<16>, dim3((unsigned)n_slots), dim3(256), 0, stream, params, segs, nseg,
+                           (const RayState *)st);
+    else
+        hipLaunchKernelGGL(k_finish_batch<32>, dim3((unsigned)n_slots), dim3(256), 0, stream, params, segs, nseg,
+                           (const RayState *)st);
     return (int)hipGetLastError();
 }
 

@@ -31,7 +31,9 @@ EXPORTED = ["pbr_create", "pbr_destroy", "pbr_last_error", "pbr_set_stream",
             "pbr_set_density_field", "pbr_set_optics",
             "pbr_set_sensor", "pbr_get_derived", "pbr_set_exit_recording",
             "pbr_emit_and_trace", "pbr_calibrate_precision", "pbr_brick_flags",
-            "pbr_read_image", "pbr_read_ray_exits"]
+            "pbr_read_image", "pbr_read_ray_exits",
+            "pbr_batch_workspace_bytes", "pbr_batch_create", "pbr_batch_destroy", "pbr_batch_last_error",
+            "pbr_batch_get_config", "pbr_batch_configure", "pbr_batch_run", "pbr_batch_autotune"]
 
 
 class PbrError(RuntimeError):
@@ -72,6 +74,22 @@ class pbr_precision_report(C.Structure):
                 ("tol_px", C.c_double), ("steps_per_sample", C.c_int32), ("rays_per_brick", C.c_int32)]
 
 
+class pbr_batch_item(C.Structure):
+    _fields_ = [("ctx", C.c_void_p), ("src_dev", C.c_void_p), ("n_src", C.c_int64),
+                ("rays_per_src", C.c_int32), ("flags", C.c_uint32), ("seed", C.c_uint64), ("ds", C.c_double)]
+
+
+class pbr_batch_config(C.Structure):
+    _fields_ = [("box_block", C.c_int32), ("unit_rays", C.c_int32), ("tile", C.c_int32),
+                ("reserved", C.c_int32), ("round_rays", C.c_int64), ("max_round_rays", C.c_int64),
+                ("min_round_rays", C.c_int64), ("rounds", C.c_int32), ("pad", C.c_int32)]
+
+
+class pbr_batch_stats(C.Structure):
+    _fields_ = [("rays", C.c_uint64), ("status", C.c_uint64 * PBR_NUM_STATUS), ("rkn_steps", C.c_uint64),
+                ("run_ms", C.c_double), ("rounds", C.c_int32), ("images", C.c_int32)]
+
+
 RAY_EXIT_DTYPE = np.dtype([("ray_id", "<i8"), ("status", "<i4"), ("n_steps", "<i4"),
                            ("entered", "<i4"), ("reserved", "<i4"), ("vol_exit_pos", "<f8", 3),
                            ("vol_exit_dir", "<f8", 3), ("sensor_px", "<f8", 2)])
@@ -107,6 +125,14 @@ def load(path: str = LIB_PATH):
         "pbr_calibrate_precision": (I, [P, D, D, C.c_int32, U64, D, C.POINTER(pbr_precision_report)]),
         "pbr_brick_flags": (I, [P, P, I64, I]),
         "pbr_read_image": (I, [P, I, P, D]),
+        "pbr_batch_workspace_bytes": (C.c_size_t, [P, I, I64]),
+        "pbr_batch_create": (I, [C.POINTER(P), P, I, P, C.c_size_t, P]),
+        "pbr_batch_destroy": (None, [P]),
+        "pbr_batch_last_error": (C.c_char_p, [P]),
+        "pbr_batch_get_config": (I, [P, C.POINTER(pbr_batch_config)]),
+        "pbr_batch_configure": (I, [P, C.POINTER(pbr_batch_config)]),
+        "pbr_batch_run": (I, [P, C.POINTER(pbr_batch_stats)]),
+        "pbr_batch_autotune": (I, [P, C.c_char_p, C.c_int32, C.POINTER(pbr_batch_config), C.POINTER(C.c_double)]),
         "pbr_read_ray_exits": (I, [P, P, I64, I64]),
     }
     for name, (res, args) in sig.items():
@@ -355,3 +381,112 @@ def trace_scene(scene, flags=PBR_CLEAR_FIRST, stats=True, record=None, rho=None,
     st = r.emit_and_trace(src, scene.rays_per_src, scene.ray_seed, scene.ds, flags, stats=stats)
     recs = r.read_ray_exits() if record is not None else None
     return r, st, recs
+
+
+# ------------------------------------------------------------------ batches
+
+def _bcheck(b, code):
+    if code != PBR_OK:
+        msg = _lib.pbr_batch_last_error(b)
+        raise PbrError(code, msg.decode() if msg else "")
+
+
+def pbr_batch_workspace_bytes(items, round_rays) -> int:
+    arr = (pbr_batch_item * len(items))(*items)
+    return int(load().pbr_batch_workspace_bytes(C.cast(arr, C.c_void_p), len(items), int(round_rays)))
+
+
+def pbr_batch_create(items, ws, stream):
+    arr = (pbr_batch_item * len(items))(*items)
+    h = C.c_void_p()
+    code = load().pbr_batch_create(C.byref(h), C.cast(arr, C.c_void_p), len(items), _dptr(ws),
+                                   ws.numel() * ws.element_size(), stream)
+    if code != PBR_OK:
+        raise PbrError(code, _lib.pbr_batch_last_error(None).decode())
+    return h
+
+
+def pbr_batch_destroy(b):
+    load().pbr_batch_destroy(b)
+
+
+def pbr_batch_get_config(b) -> pbr_batch_config:
+    c = pbr_batch_config()
+    _bcheck(b, load().pbr_batch_get_config(b, C.byref(c)))
+    return c
+
+
+def pbr_batch_configure(b, cfg: pbr_batch_config):
+    _bcheck(b, load().pbr_batch_configure(b, C.byref(cfg)))
+
+
+def pbr_batch_run(b, want_stats=True):
+    st = pbr_batch_stats() if want_stats else None
+    _bcheck(b, load().pbr_batch_run(b, C.byref(st) if st is not None else None))
+    return st
+
+
+def pbr_batch_autotune(b, cache_path=None, probe_rounds=1):
+    c = pbr_batch_config()
+    rate = C.c_double()
+    _bcheck(b, load().pbr_batch_autotune(b, None if cache_path is None else str(cache_path).encode(),
+                                         int(probe_rounds), C.byref(c), C.byref(rate)))
+    return c, float(rate.value)
+
+
+def config_dict(c: pbr_batch_config) -> dict:
+    return {k: getattr(c, k) for k, _ in pbr_batch_config._fields_ if k not in ("reserved", "pad")}
+
+
+class Batch:
+    """Many ``Renderer`` images traced in one graph-captured launch sequence."""
+
+    def __init__(self, renderers, sources, rays_per_src, seeds, ds, flags=PBR_CLEAR_FIRST,
+                 round_rays=1 << 22):
+        import torch
+        self.torch = torch
+        self.renderers = list(renderers)
+        dev = self.renderers[0].device
+        self.src = [torch.as_tensor(s, dtype=torch.float32, device=dev).contiguous() for s in sources]
+        n = len(self.renderers)
+        rps = rays_per_src if isinstance(rays_per_src, (list, tuple)) else [rays_per_src] * n
+        seeds = seeds if isinstance(seeds, (list, tuple)) else [seeds] * n
+        dss = ds if isinstance(ds, (list, tuple)) else [ds] * n
+        flg = flags if isinstance(flags, (list, tuple)) else [flags] * n
+        self.items = [pbr_batch_item(r.ctx.value, s.data_ptr() if s.numel() else 0, int(s.shape[0]), int(k),
+                                     int(f), int(sd), float(d))
+                      for r, s, k, sd, d, f in zip(self.renderers, self.src, rps, seeds, dss, flg)]
+        nb = pbr_batch_workspace_bytes(self.items, round_rays)
+        self.ws = torch.empty((nb + 255) // 256 * 32, dtype=torch.int64, device=dev)
+        self.h = pbr_batch_create(self.items, self.ws, C.c_void_p(torch.cuda.current_stream(dev).cuda_stream))
+
+    def run(self, stats=True):
+        st = pbr_batch_run(self.h, stats)
+        if st is None:
+            return None
+        return dict(rays=int(st.rays), status=[int(x) for x in st.status], rkn_steps=int(st.rkn_steps),
+                    run_ms=float(st.run_ms), rounds=int(st.rounds), images=int(st.images))
+
+    def config(self) -> dict:
+        return config_dict(pbr_batch_get_config(self.h))
+
+    def configure(self, **kw):
+        c = pbr_batch_get_config(self.h)
+        for k, v in kw.items():
+            setattr(c, k, v)
+        pbr_batch_configure(self.h, c)
+
+    def autotune(self, cache_path=None, probe_rounds=1):
+        c, rate = pbr_batch_autotune(self.h, cache_path, probe_rounds)
+        return config_dict(c), rate
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            pbr_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -32,7 +32,7 @@ def _declared():
 
 def test_exports_every_declared_function(lib):
     names = _declared()
-    assert len(names) >= 17
+    assert len(names) >= 25
     for n in names:
         assert hasattr(lib, n), n
     assert sorted(pbr.EXPORTED) == names
@@ -45,6 +45,27 @@ def test_struct_sizes_match_header_layout(lib):
     assert C.sizeof(pbr.pbr_sensor) == 48
     assert C.sizeof(pbr.pbr_stats) == 8 * (1 + 7 + 3) + 8 * 3
     assert C.sizeof(pbr.pbr_precision_report) == 8 * 7 + 8
+
+
+def test_batch_structs_and_workspace(lib):
+    assert C.sizeof(pbr.pbr_batch_item) == 48
+    assert C.sizeof(pbr.pbr_batch_config) == 48
+    assert C.sizeof(pbr.pbr_batch_stats) == 8 * 9 + 8 + 8
+    it = pbr.pbr_batch_item(FAKE, FAKE, 1000, 100, 1, 1, 1e-4)
+    nb = pbr.pbr_batch_workspace_bytes([it, it], 1 << 20)
+    assert nb >= (1 << 20) * 64 and nb % 256 == 0
+    assert pbr.pbr_batch_workspace_bytes([it], 10) == 0
+    # creation refuses host-only contexts before touching the device
+    h = _host_ctx(lib)
+    try:
+        it = pbr.pbr_batch_item(h.value, FAKE, 10, 10, 1, 1, 1e-4)
+        arr = (pbr.pbr_batch_item * 1)(it)
+        b = C.c_void_p()
+        assert lib.pbr_batch_create(C.byref(b), C.cast(arr, C.c_void_p), 1, FAKE, 1 << 30, None) == pbr.PBR_ERR_ARG
+        assert "GPU" in lib.pbr_batch_last_error(None).decode()
+        assert lib.pbr_batch_create(C.byref(b), None, 0, FAKE, 1 << 30, None) == pbr.PBR_ERR_ARG
+    finally:
+        lib.pbr_destroy(h)
 
 
 def test_workspace_bytes(lib):
