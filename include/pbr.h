@@ -59,6 +59,7 @@ extern "C" {
 #define PBR_RECORD_EXITS    (1u << 1)  /* write exit records for the rays chosen by pbr_set_exit_recording */
 #define PBR_PREC_FP64_ALL   (1u << 2)  /* integrate every step in FP64 (default: FP32) */
 #define PBR_PREC_SHOCK_FP64 (1u << 3)  /* FP64 steps inside the bricks flagged by pbr_calibrate_precision */
+#define PBR_SURROGATE       (1u << 4)  /* rays entering through eligible tiles take the attached surrogate's exit */
 
 /* ---------------------------------------------------------------- pbr_read_image formats */
 #define PBR_FMT_RAW_U64 0  /* copy of the Q32.32 accumulator (uint64 per pixel) */
@@ -114,6 +115,7 @@ typedef struct pbr_stats {
     double trace_ms;                   /* device time of the whole trace (HIP events) */
     double box_ms;                     /* device time of the integration kernel launches alone */
     uint64_t box_launches;             /* integration kernel launches (one per ray chunk) */
+    uint64_t surrogate_rays;           /* rays whose box passage the surrogate network replaced */
 } pbr_stats;
 
 /* Exit record of one ray (sec. 4 uses per-ray displacements on the sensor). */
@@ -333,6 +335,117 @@ int pbr_batch_run(pbr_batch *b, pbr_batch_stats *stats);
  * in an unspecified state: run the batch with PBR_CLEAR_FIRST items afterwards.  Synchronises. */
 int pbr_batch_autotune(pbr_batch *b, const char *cache_path, int32_t probe_rounds, pbr_batch_config *chosen,
                        double *rays_per_ms);
+
+/* ---------------------------------------------------------------- ray surrogate network
+ * A multilayer perceptron 6 -> 256 -> 256 -> 256 -> 256 -> 6 with GELU activations (tanh form,
+ * Hendrycks & Gimpel 2016) that stands in for the integration of the ray equation (eqs. 3-6)
+ * through one fixed density field: from a ray's entry through the box face z = z_min it predicts
+ * where, and in which direction, the ray leaves through the face z = z_max.  Everything before
+ * (emission) and after (lens, eq. 7; deposit, eq. 8) stays the tracer's.
+ *
+ * Inputs (features): entry x and y scaled to [-1, 1] over the box, the entry direction's x and y
+ * components over their RMS theta in the training set, sin(2 pi (x - x_min) / L_x) and
+ * sin(2 pi (y - y_min) / L_y).  Outputs: exit position minus the straight-line exit from the same
+ * entry (x, y, z; z is always 0) and exit unit direction minus entry unit direction, each
+ * standardised with the training set's mean and standard deviation.
+ *
+ * Parameters are FP32 in one flat array of PBR_SURR_PARAMS floats: W1 [256][6], b1 [256],
+ * W2 [256][256], b2, W3, b3, W4, b4, W5 [6][256], b5 [6] (row-major, W[out][in]).  Matrix products
+ * of layers 2-5 run on bfloat16 copies of the weights and activations with FP32 accumulation;
+ * layer 1 and all pre-activations, biases and gradient sums stay FP32.  Training: mean squared
+ * error over the standardised outputs, Adam (beta1 0.9, beta2 0.999, eps 1e-8) on the FP32 master
+ * weights.
+ *
+ * A trained surrogate belongs to the context it was trained on, and only while that context's
+ * field, optics and sensor stay as they were.  Its fallback map splits the entry face into
+ * tiles x tiles tiles: a tile is eligible only when every validation ray entering through it
+ * lands within tol_px (sensor pixels) of where the tracer puts it; all other rays are traced. */
+#define PBR_SURR_PARAMS 200710
+
+typedef struct pbr_surrogate pbr_surrogate;
+
+typedef struct pbr_surrogate_train_config {
+    int32_t batch;             /* rows per Adam step, a multiple of 64 not above max_rows */
+    int32_t epochs;            /* passes over the training rays */
+    float lr_max, lr_min;      /* learning rate: cosine from lr_max (first step) to lr_min (last) */
+    double tol_px;             /* eligibility tolerance on the sensor, pixels (0.01) */
+    int32_t tiles;             /* tiles per side of the entry face, 1 .. 1024 */
+    int32_t min_tile_samples;  /* tiles with fewer validation rays stay ineligible (>= 1) */
+    uint64_t shuffle_seed;     /* order of the training rays in each epoch */
+} pbr_surrogate_train_config;
+
+typedef struct pbr_surrogate_report {
+    int64_t train_samples;     /* training rays that cross the box from face z_min to face z_max */
+    int64_t val_samples;       /* validation rays that cross and reach the sensor */
+    int64_t val_eligible;      /* of which enter through eligible tiles */
+    int32_t steps;             /* Adam steps taken */
+    int32_t eligible_tiles;
+    double loss_first_epoch;   /* mean training loss over the first and the last epoch */
+    double loss_last_epoch;
+    double val_median_px;      /* sensor-hit error over all validation samples */
+    double val_p99_px;
+    double val_max_px;
+    double val_max_eligible_px;
+    double sample_ms;          /* wall time of tracing the training and validation rays */
+    double train_ms;           /* wall time of the Adam steps */
+    double validate_ms;
+} pbr_surrogate_report;
+
+/* Creates a network on device (current device if -1) with weights and biases drawn uniformly from
+ * +-1/sqrt(fan_in) (SplitMix64 of init_seed), zero Adam moments, and buffers for max_rows rows per
+ * pass (rounded up to 64; 65536 if 0).  hip_stream: stream for all work (NULL: a private stream).
+ * Errors: ARG, HIP (see pbr_surrogate_last_error(NULL) when *out is NULL). */
+int pbr_surrogate_create(pbr_surrogate **out, int device, void *hip_stream, uint64_t init_seed, int64_t max_rows);
+void pbr_surrogate_destroy(pbr_surrogate *s);
+const char *pbr_surrogate_last_error(const pbr_surrogate *s);
+
+/* Copies all PBR_SURR_PARAMS parameters from / to host memory (n must equal PBR_SURR_PARAMS);
+ * set also resets the Adam moments.  Synchronises.  Errors: ARG, HIP. */
+int pbr_surrogate_set_params(pbr_surrogate *s, const float *params_host, int64_t n);
+int pbr_surrogate_get_params(pbr_surrogate *s, float *params_host, int64_t n);
+
+/* Network outputs for rows inputs: x_dev [rows][6] -> y_dev [rows][6], device memory, FP32.
+ * Enqueued on the surrogate's stream.  Errors: ARG, HIP. */
+int pbr_surrogate_forward(pbr_surrogate *s, const float *x_dev, int64_t rows, float *y_dev);
+
+/* Mean squared error of the outputs for x_dev against targets t_dev (both [rows][6], device) and
+ * its gradient with respect to every parameter (grad_host: PBR_SURR_PARAMS floats, may be NULL).
+ * rows: a positive multiple of 64 not above max_rows.  Synchronises.  Errors: ARG, HIP. */
+int pbr_surrogate_gradients(pbr_surrogate *s, const float *x_dev, const float *t_dev, int64_t rows,
+                            float *grad_host, double *loss_host);
+
+/* One Adam step (step = 1, 2, ... as in the bias corrections) on the gradient of x_dev, t_dev as
+ * above, learning rate lr.  loss_host (may be NULL) receives the loss before the step.
+ * Synchronises only when loss_host is given.  Errors: ARG, HIP. */
+int pbr_surrogate_adam_step(pbr_surrogate *s, const float *x_dev, const float *t_dev, int64_t rows, float lr,
+                            int32_t step, double *loss_host);
+
+/* Trains the network for the context's current field, optics and sensor.  The tracer (FP32; FP64
+ * inside flagged bricks when the context has any) integrates n_train_src x rays_per_src rays
+ * emitted from train_src_dev with train_seed, and n_val_src x rays_per_src from val_src_dev with
+ * val_seed (device arrays as in pbr_emit_and_trace), without depositing them.  Rays that enter
+ * through z_min and leave through z_max become samples; the training samples set the
+ * standardisation, then cfg->epochs passes of Adam steps over shuffled batches of cfg->batch;
+ * the validation samples that reach the sensor are pushed through lens and sensor from the
+ * predicted exit and compared with the tracer's hit, which fixes the fallback map.  The
+ * context's sensor accumulator and counters are left untouched; its trace workspace is used as
+ * scratch.  Synchronises.  Errors: STATE (context not ready, host-only context), ARG, HIP. */
+int pbr_surrogate_train(pbr_surrogate *s, pbr_ctx *ctx, const float *train_src_dev, int64_t n_train_src,
+                        const float *val_src_dev, int64_t n_val_src, int32_t rays_per_src, uint64_t train_seed,
+                        uint64_t val_seed, double ds, const pbr_surrogate_train_config *cfg,
+                        pbr_surrogate_report *report);
+
+/* Fallback map of a trained surrogate: tiles x tiles bytes (1 = eligible) and the largest
+ * validation error per tile in pixels (-1 for tiles without validation rays), tile (tx, ty) at
+ * ty * tiles + tx, tx along x.  Either pointer may be NULL.  Errors: STATE (not trained), ARG. */
+int pbr_surrogate_tile_map(pbr_surrogate *s, uint8_t *eligible_host, float *max_err_host, int64_t n_tiles);
+
+/* Attaches a trained surrogate to the context it was trained on (NULL detaches).  Traces with
+ * PBR_SURROGATE then hand every ray that enters through an eligible tile of z_min to the network
+ * and trace the rest.  Fails with STATE when the surrogate is untrained, was trained on another
+ * context or the context's field, optics or sensor changed since.  The surrogate must outlive
+ * the attachment. */
+int pbr_set_surrogate(pbr_ctx *ctx, pbr_surrogate *s);
 
 #ifdef __cplusplus
 }

@@ -1,0 +1,387 @@
+// Kernels of the ray-surrogate network 6 -> 256 -> 256 -> 256 -> 256 -> 6 (GELU, tanh form):
+// the input layer in FP32 (entry positions need more than bfloat16's 8 bits), the three hidden
+// 256 x 256 layers and the output layer as bfloat16 matrix products on the gfx950 matrix cores
+// (v_mfma_f32_16x16x32_bf16, FP32 accumulation), the backward pass (error propagation, weight
+// and bias gradients) and Adam on FP32 master weights with bfloat16 shadow copies.
+#include "mlp_internal.h"
+
+namespace pbr {
+namespace {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+constexpr float kGeluC = 0.7978845608028654f;  // sqrt(2 / pi)
+constexpr float kGeluA = 0.044715f;
+
+__device__ __forceinline__ float gelu(float z)
+{
+    return 0.5f * z * (1.0f + tanhf(kGeluC * (z + kGeluA * z * z * z)));
+}
+
+__device__ __forceinline__ float gelu_grad(float z)
+{
+    const float t = tanhf(kGeluC * (z + kGeluA * z * z * z));
+    return 0.5f * (1.0f + t) + 0.5f * z * (1.0f - t * t) * kGeluC * (1.0f + 3.0f * kGeluA * z * z);
+}
+
+// float -> bfloat16 bits, round to nearest even (finite inputs)
+__device__ __forceinline__ unsigned short bf16_bits(float x)
+{
+    const unsigned u = __float_as_uint(x);
+    return (unsigned short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+
+// C[m][n] = sum_k A[m][k] W[n][k] (+ bias[n]); A: M x K, W: N x K, both bf16, k contiguous.
+// Block 256 threads = 4 waves in 2 x 2, block tile 64 x 64, wave tile 32 x 32 = 2 x 2 matrix-core
+// tiles of 16 x 16.  Operand layout of the 16x16x32 instruction: lane l supplies row (A) or
+// column (B) l % 16 and the 8 consecutive k starting at 8 (l / 16); the 4 results of lane l are
+// rows 4 (l / 16) + t, column l % 16.  M, N multiples of 64, K a multiple of 32.
+template <int EPI>
+__global__ void __launch_bounds__(256) k_gemm_nt(const unsigned short *__restrict__ A, int lda,
+                                                 const unsigned short *__restrict__ W, int ldw,
+                                                 const float *__restrict__ bias, int K, float *__restrict__ Cf,
+                                                 int ldc, unsigned short *__restrict__ Cb, int ldcb,
+                                                 const float *__restrict__ Zin, int n_valid,
+                                                 const unsigned long long *__restrict__ live)
+{
+    // rows beyond the live count (read on the device) are skipped whole blocks at a time
+    if (live && (unsigned long long)blockIdx.y * 64ull >= *live) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int m0 = blockIdx.y * 64 + (wave >> 1) * 32;
+    const int n0 = blockIdx.x * 64 + (wave & 1) * 32;
+    const int r = lane & 15, kg = lane >> 4;
+    floatx4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+    const unsigned short *a0 = A + (size_t)(m0 + r) * lda + 8 * kg;
+    const unsigned short *a1 = A + (size_t)(m0 + 16 + r) * lda + 8 * kg;
+    const unsigned short *w0 = W + (size_t)(n0 + r) * ldw + 8 * kg;
+    const unsigned short *w1 = W + (size_t)(n0 + 16 + r) * ldw + 8 * kg;
+    for (int k0 = 0; k0 < K; k0 += 32) {
+        const bf16x8 fa0 = *(const bf16x8 *)(a0 + k0);
+        const bf16x8 fa1 = *(const bf16x8 *)(a1 + k0);
+        const bf16x8 fw0 = *(const bf16x8 *)(w0 + k0);
+        const bf16x8 fw1 = *(const bf16x8 *)(w1 + k0);
+        acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa0, fw0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa0, fw1, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa1, fw0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa1, fw1, acc[1][1], 0, 0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int n = n0 + 16 * j + r;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int m = m0 + 16 * i + 4 * kg + t;
+                float z = acc[i][j][t];
+                if (EPI == EPI_BIAS_GELU || EPI == EPI_BIAS_Z_GELU) z += bias[n];
+                if (EPI == EPI_BIAS_OUT) z += n < n_valid ? bias[n] : 0.0f;
+                if (EPI == EPI_BIAS_GELU) {
+                    Cb[(size_t)m * ldcb + n] = bf16_bits(gelu(z));
+                } else if (EPI == EPI_BIAS_Z_GELU) {
+                    Cf[(size_t)m * ldc + n] = z;
+                    Cb[(size_t)m * ldcb + n] = bf16_bits(gelu(z));
+                } else if (EPI == EPI_BIAS_OUT) {
+                    if (n < n_valid) Cf[(size_t)m * ldc + n] = z;
+                } else if (EPI == EPI_GELU_BACK) {
+                    // z is dL/da of the layer below; dL/dz = dL/da * g'(z_below)
+                    const float dz = z * gelu_grad(Zin[(size_t)m * ldc + n]);
+                    Cf[(size_t)m * ldc + n] = dz;
+                    Cb[(size_t)m * ldcb + n] = bf16_bits(dz);
+                } else {  // EPI_PLAIN
+                    Cf[(size_t)m * ldc + n] = z;
+                }
+            }
+        }
+}
+
+// Input layer in FP32: z1 = x W1^T + b1, a1 = bf16(g(z1)).  One thread per (row, unit).
+__global__ void __launch_bounds__(256) k_layer1(const float *__restrict__ x, const float *__restrict__ W1,
+                                                const float *__restrict__ b1, int64_t rows,
+                                                float *__restrict__ z1, unsigned short *__restrict__ a1,
+                                                const unsigned long long *__restrict__ live)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= rows * kHidden) return;
+    // whole 64-row groups past the live count are skipped, as in the matrix products
+    if (live && (unsigned long long)(q / (kHidden * 64)) * 64ull >= *live) return;
+    const int64_t m = q / kHidden;
+    const int n = (int)(q % kHidden);
+    float z = b1[n];
+#pragma unroll
+    for (int k = 0; k < kIn; ++k) z += x[m * kIn + k] * W1[n * kIn + k];
+    if (z1) z1[q] = z;
+    a1[q] = bf16_bits(gelu(z));
+}
+
+// Output errors of the mean squared error: dy = 2 (y - t) / (rows * 6); per-block loss sums.
+__global__ void __launch_bounds__(256) k_out_error(const float *__restrict__ y, const float *__restrict__ t,
+                                                   int64_t rows, float *__restrict__ dy, float *__restrict__ loss_part)
+{
+    __shared__ float s[256];
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    float l = 0.0f;
+    if (q < rows * kOut) {
+        const float d = y[q] - t[q];
+        dy[q] = 2.0f * d / (float)(rows * kOut);
+        l = d * d;
+    }
+    s[threadIdx.x] = l;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) loss_part[blockIdx.x] = s[0];
+}
+
+// dL/da4 = dy W5 (K = 6, FP32 master weights), then dL/dz4 = dL/da4 g'(z4) in f32 and bf16.
+__global__ void __launch_bounds__(256) k_out_back(const float *__restrict__ dy, const float *__restrict__ W5,
+                                                  const float *__restrict__ z4, int64_t rows,
+                                                  float *__restrict__ dz, unsigned short *__restrict__ dzb)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= rows * kHidden) return;
+    const int64_t m = q / kHidden;
+    const int n = (int)(q % kHidden);
+    float da = 0.0f;
+#pragma unroll
+    for (int o = 0; o < kOut; ++o) da += dy[m * kOut + o] * W5[o * kHidden + n];
+    const float d = da * gelu_grad(z4[q]);
+    dz[q] = d;
+    dzb[q] = bf16_bits(d);
+}
+
+// out[c][r] = in[r][c] for a rows x cols bf16 matrix (32 x 32 tiles through LDS).
+__global__ void __launch_bounds__(256) k_transpose(const unsigned short *__restrict__ in, int64_t rows, int cols,
+                                                   unsigned short *__restrict__ out)
+{
+    __shared__ unsigned short tile[32][33];
+    const int64_t r0 = (int64_t)blockIdx.y * 32;
+    const int c0 = blockIdx.x * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int k = ty; k < 32; k += 8) {
+        const int64_t r = r0 + k;
+        const int c = c0 + tx;
+        tile[k][tx] = (r < rows && c < cols) ? in[r * cols + c] : (unsigned short)0;
+    }
+    __syncthreads();
+    for (int k = ty; k < 32; k += 8) {
+        const int c = c0 + k;
+        const int64_t r = r0 + tx;
+        if (c < cols && r < rows) out[(int64_t)c * rows + r] = tile[tx][k];
+    }
+}
+
+// g[n] = sum over rows of d[row][n] (bias gradients), FP32, fixed summation order.
+__global__ void __launch_bounds__(256) k_colsum(const float *__restrict__ d, int64_t rows, int cols,
+                                                float *__restrict__ g)
+{
+    __shared__ float s[256];
+    const int n = blockIdx.x;
+    float a = 0.0f;
+    for (int64_t m = threadIdx.x; m < rows; m += blockDim.x) a += d[m * cols + n];
+    s[threadIdx.x] = a;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) g[n] = s[0];
+}
+
+// G[o][i] = sum over rows of P[row][o] Q[row][i] for a small side (o < no, i < ni), FP32:
+// the weight gradients of the 6-wide layers (W5: P = dy, Q = a4 bf16; W1: P = dz1, Q = x).
+template <bool Q_BF16>
+__global__ void __launch_bounds__(256) k_small_wgrad(const float *__restrict__ Pm, int no,
+                                                     const void *__restrict__ Qm, int ni, int64_t rows,
+                                                     float *__restrict__ G)
+{
+    __shared__ float s[256];
+    const int o = blockIdx.x / ni, i = blockIdx.x % ni;
+    float a = 0.0f;
+    for (int64_t m = threadIdx.x; m < rows; m += blockDim.x) {
+        float q;
+        if (Q_BF16) q = __uint_as_float(((unsigned)((const unsigned short *)Qm)[m * ni + i]) << 16);
+        else q = ((const float *)Qm)[m * ni + i];
+        a += Pm[m * no + o] * q;
+    }
+    s[threadIdx.x] = a;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) G[o * ni + i] = s[0];
+}
+
+// Adam on the flat FP32 parameters (Kingma & Ba), then the bf16 copies the products read:
+// W2..W4 (and their transposes) and W5 padded to 64 rows.
+__global__ void __launch_bounds__(256) k_adam(float *__restrict__ p, const float *__restrict__ g,
+                                              float *__restrict__ m, float *__restrict__ v, int64_t n, float lr,
+                                              float beta1, float beta2, float eps, float c1, float c2)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const float gq = g[q];
+    const float mq = beta1 * m[q] + (1.0f - beta1) * gq;
+    const float vq = beta2 * v[q] + (1.0f - beta2) * gq * gq;
+    m[q] = mq;
+    v[q] = vq;
+    p[q] -= lr * (mq / c1) / (sqrtf(vq / c2) + eps);
+}
+
+__global__ void __launch_bounds__(256) k_shadow(const float *__restrict__ p, unsigned short *__restrict__ w2,
+                                                unsigned short *__restrict__ w2t, unsigned short *__restrict__ w3,
+                                                unsigned short *__restrict__ w3t, unsigned short *__restrict__ w4,
+                                                unsigned short *__restrict__ w4t, unsigned short *__restrict__ w5)
+{
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < kHidden * kHidden) {
+        const int o = q / kHidden, i = q % kHidden;
+        const unsigned short b2 = bf16_bits(p[kOffW2 + q]), b3 = bf16_bits(p[kOffW3 + q]), b4 = bf16_bits(p[kOffW4 + q]);
+        w2[q] = b2; w3[q] = b3; w4[q] = b4;
+        w2t[i * kHidden + o] = b2; w3t[i * kHidden + o] = b3; w4t[i * kHidden + o] = b4;
+    }
+    if (q < kOutPad * kHidden) {
+        const int o = q / kHidden;
+        w5[q] = o < kOut ? bf16_bits(p[kOffW5 + q]) : (unsigned short)0;
+    }
+}
+
+// Mean of the squared errors of one batch from the per-block sums of k_out_error.
+__global__ void __launch_bounds__(256) k_loss_mean(const float *__restrict__ part, int nparts, float inv_count,
+                                                   float *__restrict__ out)
+{
+    __shared__ float s[256];
+    float a = 0.0f;
+    for (int i = threadIdx.x; i < nparts; i += 256) a += part[i];
+    s[threadIdx.x] = a;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = s[0] * inv_count;
+}
+
+inline unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+template <int EPI>
+int gemm(const unsigned short *A, int lda, const unsigned short *W, int ldw, const float *bias, int64_t M, int N,
+         int K, float *Cf, int ldc, unsigned short *Cb, int ldcb, const float *Zin, int n_valid, hipStream_t s,
+         const unsigned long long *live = nullptr)
+{
+    hipLaunchKernelGGL(k_gemm_nt<EPI>, dim3((unsigned)(N / 64), (unsigned)(M / 64)), dim3(256), 0, s, A, lda, W,
+                       ldw, bias, K, Cf, ldc, Cb, ldcb, Zin, n_valid, live);
+    return (int)hipGetLastError();
+}
+
+}  // namespace
+
+int mlp_gemm_plain(const unsigned short *A, int lda, const unsigned short *W, int ldw, int64_t M, int N, int K,
+                   float *C, int ldc, hipStream_t s)
+{
+    return gemm<EPI_PLAIN>(A, lda, W, ldw, nullptr, M, N, K, C, ldc, nullptr, 0, nullptr, N, s);
+}
+
+int mlp_refresh_shadow(const MlpDevice &d, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_shadow, dim3(blocks_for((int64_t)kHidden * kHidden)), dim3(256), 0, s, d.params, d.w2,
+                       d.w2t, d.w3, d.w3t, d.w4, d.w4t, d.w5);
+    return (int)hipGetLastError();
+}
+
+// Forward pass for `rows` rows (multiple of 64).  train: keep z1..z4 (f32) for the backward pass.
+// live (device, optional): only the first *live rows (rounded up to 64) are computed.
+int mlp_forward(const MlpDevice &d, const MlpBuffers &b, const float *x, int64_t rows, float *y, bool train,
+                hipStream_t s, const unsigned long long *live)
+{
+    int e;
+    hipLaunchKernelGGL(k_layer1, dim3(blocks_for(rows * kHidden)), dim3(256), 0, s, x, d.params + kOffW1,
+                       d.params + kOffB1, rows, train ? b.z[0] : nullptr, b.a[0], live);
+    if ((e = (int)hipGetLastError())) return e;
+    const unsigned short *w[3] = {d.w2, d.w3, d.w4};
+    const int boff[3] = {kOffB2, kOffB3, kOffB4};
+    for (int l = 0; l < 3; ++l) {
+        if (train)
+            e = gemm<EPI_BIAS_Z_GELU>(b.a[l], kHidden, w[l], kHidden, d.params + boff[l], rows, kHidden, kHidden,
+                                      b.z[l + 1], kHidden, b.a[l + 1], kHidden, nullptr, kHidden, s, live);
+        else
+            e = gemm<EPI_BIAS_GELU>(b.a[l], kHidden, w[l], kHidden, d.params + boff[l], rows, kHidden, kHidden,
+                                    nullptr, kHidden, b.a[l + 1], kHidden, nullptr, kHidden, s, live);
+        if (e) return e;
+    }
+    return gemm<EPI_BIAS_OUT>(b.a[3], kHidden, d.w5, kHidden, d.params + kOffB5, rows, kOutPad, kHidden, y, kOut,
+                              nullptr, 0, nullptr, kOut, s, live);
+}
+
+// Backward pass after a training forward: MSE gradients of all parameters into d.grad;
+// per-block loss sums into b.loss_part (blocks_for(rows * 6) of them).
+int mlp_backward(const MlpDevice &d, const MlpBuffers &b, const float *x, const float *t, int64_t rows,
+                 const float *y, hipStream_t s)
+{
+    int e;
+    float *dz = b.dz, *dz2 = b.dz2;
+    unsigned short *dzb = b.dzb, *dzb2 = b.dzb2;
+    hipLaunchKernelGGL(k_out_error, dim3(blocks_for(rows * kOut)), dim3(256), 0, s, y, t, rows, b.dy, b.loss_part);
+    if ((e = (int)hipGetLastError())) return e;
+    // W5, b5
+    hipLaunchKernelGGL(k_small_wgrad<true>, dim3(kOut * kHidden), dim3(256), 0, s, b.dy, kOut, (const void *)b.a[3],
+                       kHidden, rows, d.grad + kOffW5);
+    hipLaunchKernelGGL(k_colsum, dim3(kOut), dim3(256), 0, s, b.dy, rows, kOut, d.grad + kOffB5);
+    // error into layer 4
+    hipLaunchKernelGGL(k_out_back, dim3(blocks_for(rows * kHidden)), dim3(256), 0, s, b.dy, d.params + kOffW5,
+                       b.z[3], rows, dz, dzb);
+    if ((e = (int)hipGetLastError())) return e;
+    const int woff[3] = {kOffW2, kOffW3, kOffW4}, boff[3] = {kOffB2, kOffB3, kOffB4};
+    const unsigned short *wt[3] = {d.w2t, d.w3t, d.w4t};
+    for (int l = 2; l >= 0; --l) {  // hidden layer l + 2: input a[l], pre-activation z[l + 1]
+        // dW = dz^T a_prev: NT product of the transposes (K = rows)
+        hipLaunchKernelGGL(k_transpose, dim3(kHidden / 32, (unsigned)((rows + 31) / 32)), dim3(256), 0, s, dzb,
+                           rows, kHidden, b.t0);
+        hipLaunchKernelGGL(k_transpose, dim3(kHidden / 32, (unsigned)((rows + 31) / 32)), dim3(256), 0, s, b.a[l],
+                           rows, kHidden, b.t1);
+        if ((e = (int)hipGetLastError())) return e;
+        if ((e = gemm<EPI_PLAIN>(b.t0, (int)rows, b.t1, (int)rows, nullptr, kHidden, kHidden, (int)rows,
+                                 d.grad + woff[l], kHidden, nullptr, 0, nullptr, kHidden, s)))
+            return e;
+        hipLaunchKernelGGL(k_colsum, dim3(kHidden), dim3(256), 0, s, dz, rows, kHidden, d.grad + boff[l]);
+        // error into the layer below: dz_below = (dz W) * g'(z_below)
+        if ((e = gemm<EPI_GELU_BACK>(dzb, kHidden, wt[l], kHidden, nullptr, rows, kHidden, kHidden, dz2,
+                                     kHidden, dzb2, kHidden, b.z[l], kHidden, s)))
+            return e;
+        std::swap(dz, dz2);
+        std::swap(dzb, dzb2);
+    }
+    // W1, b1 from dz1 (f32) and x
+    hipLaunchKernelGGL(k_small_wgrad<false>, dim3(kHidden * kIn), dim3(256), 0, s, dz, kHidden, (const void *)x,
+                       kIn, rows, d.grad + kOffW1);
+    hipLaunchKernelGGL(k_colsum, dim3(kHidden), dim3(256), 0, s, dz, rows, kHidden, d.grad + kOffB1);
+    return (int)hipGetLastError();
+}
+
+int mlp_loss_mean(const MlpBuffers &b, int64_t rows, float *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_loss_mean, dim3(1), dim3(256), 0, s, (const float *)b.loss_part,
+                       (int)blocks_for(rows * kOut), 1.0f / (float)(rows * kOut), out);
+    return (int)hipGetLastError();
+}
+
+int mlp_adam(const MlpDevice &d, float lr, int step, hipStream_t s)
+{
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
+    hipLaunchKernelGGL(k_adam, dim3(blocks_for(kParams)), dim3(256), 0, s, d.params, d.grad, d.m, d.v,
+                       (int64_t)kParams, lr, b1, b2, 1e-8f, c1, c2);
+    int e = (int)hipGetLastError();
+    if (e) return e;
+    return mlp_refresh_shadow(d, s);
+}
+
+}  // namespace pbr

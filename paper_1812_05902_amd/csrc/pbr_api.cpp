@@ -2,6 +2,7 @@
 // launches on the context's stream.  No C++ exception crosses the ABI.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -127,6 +128,12 @@ void fill_params(const pbr_ctx *ctx, const Derived &d, double ds, TraceParams *o
     P.counters = ctx->counters;
 }
 
+uint64_t next_uid()
+{
+    static std::atomic<uint64_t> n{0};
+    return ++n;
+}
+
 }  // namespace host
 }  // namespace pbr
 
@@ -149,6 +156,7 @@ int pbr_create(pbr_ctx **out, int device, void *hip_stream)
         ctx = new (std::nothrow) pbr_ctx();
         if (!ctx) return fail(nullptr, PBR_ERR_HIP, "out of host memory");
         ctx->device = -1;
+        ctx->uid = next_uid();
         *out = ctx;
         return PBR_OK;
     }
@@ -161,6 +169,7 @@ int pbr_create(pbr_ctx **out, int device, void *hip_stream)
     ctx = new (std::nothrow) pbr_ctx();
     if (!ctx) return fail(nullptr, PBR_ERR_HIP, "out of host memory");
     ctx->device = device;
+    ctx->uid = next_uid();
     ctx->stream = (hipStream_t)hip_stream;
     void *p = nullptr;
     e = (int)hipMalloc(&p, 4096);
@@ -273,6 +282,7 @@ int pbr_set_density_field(pbr_ctx *ctx, const float *rho_dev, int nx, int ny, in
     ctx->K = K;
     ctx->rho_inf = rho_inf;
     ctx->has_field = true;
+    ++ctx->scene_version;
     return PBR_OK;
     PBR_GUARD_END
 }
@@ -294,6 +304,7 @@ int pbr_set_optics(pbr_ctx *ctx, const pbr_optics *o)
     if (o->clear_radius > 0.0 && o->clear_radius < a) return fail(ctx, PBR_ERR_ARG, "clear radius below aperture radius");
     ctx->optics = *o;
     ctx->has_optics = true;
+    ++ctx->scene_version;
     return PBR_OK;
 }
 
@@ -312,6 +323,7 @@ int pbr_set_sensor(pbr_ctx *ctx, const pbr_sensor *s, uint64_t *accum_dev)
     ctx->accum = (unsigned long long *)accum_dev;
     ctx->accum_rays = 0.0;  // unknown contents: the caller clears with PBR_CLEAR_FIRST
     ctx->has_sensor = true;
+    ++ctx->scene_version;
     return PBR_OK;
 }
 
@@ -368,8 +380,13 @@ int pbr_emit_and_trace(pbr_ctx *ctx, const float *src_dev, int64_t n_src, int32_
         return fail(ctx, PBR_ERR_ARG, "lens front vertex must lie beyond the density box (z > %.6g)", zmax);
     if (!(d.z_sensor > ctx->optics.z_front_vertex + d.t))
         return fail(ctx, PBR_ERR_ARG, "sensor plane must lie behind the lens");
-    if (flags & ~(uint32_t)(PBR_CLEAR_FIRST | PBR_RECORD_EXITS | PBR_PREC_FP64_ALL | PBR_PREC_SHOCK_FP64))
+    if (flags & ~(uint32_t)(PBR_CLEAR_FIRST | PBR_RECORD_EXITS | PBR_PREC_FP64_ALL | PBR_PREC_SHOCK_FP64 |
+                            PBR_SURROGATE))
         return fail(ctx, PBR_ERR_ARG, "unknown flag bits 0x%x", flags);
+    pbr::ChunkHook hook{nullptr, nullptr};
+    if (flags & PBR_SURROGATE) {
+        if ((r = surrogate_hook(ctx, &hook))) return r;
+    }
     if (!ctx->ray_ws) return fail(ctx, PBR_ERR_STATE, "no trace workspace set (pbr_set_trace_workspace)");
     if ((flags & PBR_RECORD_EXITS) && ctx->rec_max > 0 && !ctx->rec)
         return fail(ctx, PBR_ERR_STATE, "no exit recording buffer set");
@@ -416,7 +433,8 @@ int pbr_emit_and_trace(pbr_ctx *ctx, const float *src_dev, int64_t n_src, int32_
         const int64_t first = k * ctx->ray_chunk;
         const int64_t n = P.n_rays - first < ctx->ray_chunk ? P.n_rays - first : ctx->ray_chunk;
         e = pbr::launch_trace_chunk(P, ctx->ray_ws, first, n, prec, ctx->stream,
-                                    stats ? ctx->box_ev[2 * k] : nullptr, stats ? ctx->box_ev[2 * k + 1] : nullptr);
+                                    stats ? ctx->box_ev[2 * k] : nullptr, stats ? ctx->box_ev[2 * k + 1] : nullptr,
+                                    hook.run ? &hook : nullptr);
         if (e) return hip_fail(ctx, e, "trace launch");
     }
     if (stats && (e = (int)hipEventRecord(ctx->ev1, ctx->stream))) return hip_fail(ctx, e, "hipEventRecord");
@@ -437,6 +455,7 @@ int pbr_emit_and_trace(pbr_ctx *ctx, const float *src_dev, int64_t n_src, int32_
         stats->entered_volume = h[pbr::CNT_ENTERED];
         stats->rkn_steps = h[pbr::CNT_STEPS];
         stats->rkn_steps_fp64 = prec == pbr::PREC_FP64 ? h[pbr::CNT_STEPS] : h[pbr::CNT_STEPS64];
+        stats->surrogate_rays = h[pbr::CNT_SURR];
         stats->trace_ms = (double)ms;
         double box = 0.0;
         for (int64_t k = 0; k < n_chunks; ++k) {

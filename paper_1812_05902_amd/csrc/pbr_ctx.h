@@ -40,6 +40,11 @@ struct pbr_ctx {
     pbr_ray_exit *rec = nullptr;
     int64_t rec_first = 0, rec_stride = 1, rec_max = 0;
     int last_max_steps = 0;
+    // identity of the scene a surrogate was trained on: unique context id, and a counter bumped
+    // by every change of field, optics or sensor
+    uint64_t uid = 0;
+    uint64_t scene_version = 0;
+    pbr_surrogate *surr = nullptr;
 };
 
 namespace pbr {
@@ -72,6 +77,11 @@ int hip_fail(pbr_ctx *c, int e, const char *what);
 int derive(pbr_ctx *c, Derived *d);
 // Launch parameters shared by the trace and the calibration (sources and rays left empty).
 void fill_params(const pbr_ctx *ctx, const Derived &d, double ds, TraceParams *out);
+// Next context id (never 0).
+uint64_t next_uid();
+// Chunk hook of an attached surrogate; fails with STATE (message on ctx) when it no longer
+// matches the context's scene.
+int surrogate_hook(pbr_ctx *ctx, ChunkHook *out);
 
 }  // namespace host
 }  // namespace pbr

@@ -15,6 +15,7 @@ enum : int {
     CNT_STEPS = PBR_NUM_STATUS + 1,       // Runge-Kutta steps
     CNT_MAXPIX = PBR_NUM_STATUS + 2,      // largest accumulator value (readout)
     CNT_STEPS64 = PBR_NUM_STATUS + 3,     // Runge-Kutta steps taken in FP64 (mixed precision)
+    CNT_SURR = PBR_NUM_STATUS + 4,        // rays whose box passage the surrogate network replaced
     CNT_SLOTS = 16
 };
 
@@ -100,7 +101,62 @@ struct RayState {
     int info;  // RS_* bits, step count above RS_STEP_SHIFT
 };
 static_assert(sizeof(RayState) == 64, "RayState layout");
-enum : int { RS_ENTERED = 1, RS_LIMITED = 2, RS_STEP_SHIFT = 4 };
+enum : int { RS_ENTERED = 1, RS_LIMITED = 2, RS_SURR = 4, RS_STEP_SHIFT = 4 };
+
+// ---------------------------------------------------------------- ray surrogate
+// Geometry of the surrogate's inputs and outputs for one field: rays enter through the box face
+// z = z_lo and leave through z = z_hi.  Features: entry point scaled to [-1, 1], direction
+// components over theta, sin(2 pi x / Lx), sin(2 pi y / Ly).  Targets: exit position minus the
+// straight-line exit from the same entry (3), exit unit direction minus the entry direction (3),
+// standardised by t_mean / t_scale.  tile_ok: eligibility over tiles x tiles of the entry face.
+struct SurrogateSpec {
+    double z_lo, z_hi, x_lo, x_hi, y_lo, y_hi;
+    double theta, Lx, Ly;
+    float t_mean[6], t_scale[6];
+    int tiles;
+    const unsigned char *tile_ok;
+};
+
+// One traced ray as a training / validation sample.
+struct SurrogateSample {
+    float t[6];      // raw targets (metres, unit-vector components)
+    int tile;        // entry tile
+    int flags;       // bit 0: enters through z_lo and leaves through z_hi; bit 1: tracer deposited
+    double E[2];     // entry point (x, y) on z = z_lo
+    double u[3];     // entry unit direction
+    double px[2];    // tracer's sensor hit (pixels), when bit 1 is set
+};
+static_assert(sizeof(SurrogateSample) == 88, "SurrogateSample layout");
+constexpr int kMoments = 16;  // count, sum t[6], sum t^2[6], sum u_x^2, sum u_y^2, unused
+
+// After emission and integration of rays [first, first + n) (states st): samples out[0 .. n).
+int launch_surr_samples(const TraceParams &p, const SurrogateSpec &sp, const RayState *st, int64_t first,
+                        int64_t n, SurrogateSample *out, hipStream_t s);
+// After emission (entry states st[0 .. n)): the rays in eligible tiles are compacted (in no fixed
+// order) into rows 0 .. *count of x (features) and idx (ray index in st); *count must start at zero.
+int launch_surr_features(const TraceParams &p, const SurrogateSpec &sp, const RayState *st, int64_t n,
+                         float *x, int *idx, unsigned long long *count, hipStream_t s);
+// Writes the predicted exit state (network output y, standardised) of rows 0 .. *count (at most
+// cap) into st[idx[row]].
+int launch_surr_apply(const TraceParams &p, const SurrogateSpec &sp, const float *y, const int *idx,
+                      const unsigned long long *count, int64_t cap, RayState *st, hipStream_t s);
+// Sensor-hit error of predictions y for samples smp[0 .. n): err[k] (pixels, -1 if not comparable),
+// per-tile maxima (float bits) and sample counts.
+int launch_surr_validate(const TraceParams &p, const SurrogateSpec &sp, const SurrogateSample *smp,
+                         const float *y, int64_t n, float *err, unsigned *tile_err, unsigned *tile_cnt,
+                         hipStream_t s);
+// Gathers rows idx[0 .. rows) of the samples: features into x, standardised targets into t
+// (idx == nullptr: rows 0 .. rows in order).
+int launch_surr_gather(const SurrogateSpec &sp, const SurrogateSample *smp, const int *idx, int64_t rows,
+                       float *x, float *t, hipStream_t s);
+// Per-block sums (kMoments doubles per block) over valid samples; returns the blocks used.
+int launch_surr_moments(const SurrogateSample *smp, int64_t n, double *part, int *blocks, hipStream_t s);
+
+// Optional step between emission and integration of a chunk (the surrogate).
+struct ChunkHook {
+    int (*run)(void *self, const TraceParams &p, RayState *st, int64_t first, int64_t n, hipStream_t s);
+    void *self;
+};
 
 constexpr int kTile = 32;  // deposit pre-aggregation tile of single-image traces (pixels per side, in LDS)
 
@@ -140,7 +196,8 @@ int launch_batch_round(const TraceParams *params, const BatchSeg *segs, int nseg
 // box_begin / box_end (may be null) are recorded around the integration kernel.
 enum PrecMode : int { PREC_FP32 = 0, PREC_FP64 = 1, PREC_MIXED = 2 };
 int launch_trace_chunk(const TraceParams &p, RayState *st, int64_t first, int64_t n, int prec,
-                       hipStream_t stream, hipEvent_t box_begin, hipEvent_t box_end);
+                       hipStream_t stream, hipEvent_t box_begin, hipEvent_t box_end,
+                       const ChunkHook *hook = nullptr, bool deposit = true);
 int launch_readout(const unsigned long long *accum, int64_t npx, int fmt, void *out,
                    double gain, unsigned long long *counters, hipStream_t stream);
 int launch_clear_u64(unsigned long long *p, int64_t n, hipStream_t stream);

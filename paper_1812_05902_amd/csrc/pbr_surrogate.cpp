@@ -1,0 +1,677 @@
+// Host side of the ray surrogate network (include/pbr.h): parameters and Adam state on the device,
+// the training loop over rays the tracer integrates, the validation that fixes the fallback map,
+// and the per-chunk hook that hands eligible rays to the network during a trace.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "mlp_internal.h"
+#include "pbr_ctx.h"
+
+using pbr::host::DeviceGuard;
+
+struct pbr_surrogate {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::string err;
+    int64_t rows_cap = 0;
+    std::vector<void *> allocs;
+    pbr::MlpDevice d{};
+    pbr::MlpBuffers b{};
+    float *x = nullptr, *y = nullptr, *t = nullptr, *loss = nullptr;
+    int *idx = nullptr;
+    unsigned long long *count = nullptr;
+    // trained state
+    bool trained = false;
+    uint64_t ctx_uid = 0, scene_version = 0;
+    pbr::SurrogateSpec spec{};
+    unsigned char *tile_ok_dev = nullptr;
+    int64_t tile_cap = 0;
+    std::vector<unsigned char> tile_ok;
+    std::vector<float> tile_err;
+};
+
+namespace {
+
+thread_local std::string g_surr_create_err;
+
+int sfail(pbr_surrogate *s, int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (s) s->err = buf;
+    else g_surr_create_err = buf;
+    return code;
+}
+
+int shf(pbr_surrogate *s, int e, const char *what)
+{
+    return sfail(s, PBR_ERR_HIP, "%s: %s", what, hipGetErrorString((hipError_t)e));
+}
+
+int64_t round64(int64_t n) { return (n + 63) / 64 * 64; }
+
+// SplitMix64 (Steele, Lea & Flood 2014): the k-th output of the stream seeded with `seed`.
+uint64_t splitmix64_host(uint64_t seed, uint64_t k)
+{
+    uint64_t z = seed + (k + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+double uniform01(uint64_t seed, uint64_t k) { return (double)(splitmix64_host(seed, k) >> 11) * 0x1.0p-53; }
+
+int dmalloc(pbr_surrogate *s, void **p, size_t bytes)
+{
+    *p = nullptr;
+    const int e = (int)hipMalloc(p, bytes < 256 ? 256 : bytes);
+    if (e) return e;
+    s->allocs.push_back(*p);
+    return 0;
+}
+
+void free_all(pbr_surrogate *s)
+{
+    for (void *p : s->allocs) (void)hipFree(p);
+    s->allocs.clear();
+}
+
+// Default parameters: uniform in +-1/sqrt(fan_in) for the weights and biases of every layer.
+void init_params(uint64_t seed, std::vector<float> &p)
+{
+    p.assign(pbr::kParams, 0.0f);
+    const int sizes[6] = {pbr::kIn, pbr::kHidden, pbr::kHidden, pbr::kHidden, pbr::kHidden, pbr::kOut};
+    int64_t o = 0;
+    for (int l = 0; l < 5; ++l) {
+        const double bound = 1.0 / std::sqrt((double)sizes[l]);
+        const int64_t n = (int64_t)sizes[l + 1] * sizes[l] + sizes[l + 1];
+        for (int64_t k = 0; k < n; ++k, ++o) p[o] = (float)((2.0 * uniform01(seed, (uint64_t)o) - 1.0) * bound);
+    }
+}
+
+// Forward pass over an arbitrary number of rows: whole 64-row groups straight from the caller's
+// buffers, a ragged tail through the surrogate's own padded buffers.
+int forward_rows(pbr_surrogate *s, const float *x, int64_t rows, float *y, hipStream_t st)
+{
+    int e;
+    for (int64_t off = 0; off < rows; off += s->rows_cap) {
+        const int64_t n = std::min(s->rows_cap, rows - off);
+        const int64_t full = n / 64 * 64;
+        if (full > 0 && (e = pbr::mlp_forward(s->d, s->b, x + off * 6, full, y + off * 6, false, st))) return e;
+        const int64_t tail = n - full;
+        if (tail > 0) {
+            if ((e = (int)hipMemcpyAsync(s->x, x + (off + full) * 6, (size_t)tail * 24, hipMemcpyDeviceToDevice, st)))
+                return e;
+            if ((e = pbr::launch_clear_u64((unsigned long long *)(s->x + tail * 6), (64 - tail) * 3, st))) return e;
+            if ((e = pbr::mlp_forward(s->d, s->b, s->x, 64, s->y, false, st))) return e;
+            if ((e = (int)hipMemcpyAsync(y + (off + full) * 6, s->y, (size_t)tail * 24, hipMemcpyDeviceToDevice, st)))
+                return e;
+        }
+    }
+    return 0;
+}
+
+int check_batch(pbr_surrogate *s, const float *x, const float *t, int64_t rows)
+{
+    if (!x || !t) return sfail(s, PBR_ERR_ARG, "null input or target array");
+    if (rows <= 0 || rows % 64 != 0 || rows > s->rows_cap)
+        return sfail(s, PBR_ERR_ARG, "rows must be a positive multiple of 64 not above %lld", (long long)s->rows_cap);
+    return PBR_OK;
+}
+
+// Emits and integrates n_src x rps rays without depositing them and writes one sample per ray.
+int trace_samples(pbr_surrogate *s, pbr_ctx *ctx, pbr::TraceParams P, const pbr::SurrogateSpec &spec, int prec,
+                  const float *src, int64_t n_src, int32_t rps, uint64_t seed, pbr::SurrogateSample *out)
+{
+    P.src = (const float4 *)src;
+    P.n_src = n_src;
+    P.rays_per_src = rps;
+    P.n_rays = n_src * (int64_t)rps;
+    P.seed = seed;
+    P.record = 0;
+    for (int64_t first = 0; first < P.n_rays; first += ctx->ray_chunk) {
+        const int64_t n = std::min(ctx->ray_chunk, P.n_rays - first);
+        int e = pbr::launch_trace_chunk(P, ctx->ray_ws, first, n, prec, ctx->stream, nullptr, nullptr, nullptr, false);
+        if (e) return shf(s, e, "sample trace");
+        if ((e = pbr::launch_surr_samples(P, spec, ctx->ray_ws, first, n, out + first, ctx->stream)))
+            return shf(s, e, "sample extraction");
+    }
+    return PBR_OK;
+}
+
+// Per-chunk hook of a trace: the rays of eligible tiles through the network, in groups of rows_cap.
+int hook_run(void *self, const pbr::TraceParams &P, pbr::RayState *st, int64_t, int64_t n, hipStream_t stream)
+{
+    pbr_surrogate *s = (pbr_surrogate *)self;
+    int e;
+    for (int64_t off = 0; off < n; off += s->rows_cap) {
+        const int64_t m = std::min(s->rows_cap, n - off);
+        if ((e = pbr::launch_clear_u64(s->count, 1, stream))) return e;
+        if ((e = pbr::launch_surr_features(P, s->spec, st + off, m, s->x, s->idx, s->count, stream))) return e;
+        if ((e = pbr::mlp_forward(s->d, s->b, s->x, round64(m), s->y, false, stream, s->count))) return e;
+        if ((e = pbr::launch_surr_apply(P, s->spec, s->y, s->idx, s->count, m, st + off, stream))) return e;
+    }
+    return 0;
+}
+
+}  // namespace
+
+namespace pbr {
+namespace host {
+
+int surrogate_hook(pbr_ctx *ctx, ChunkHook *out)
+{
+    pbr_surrogate *s = ctx->surr;
+    if (!s) return fail(ctx, PBR_ERR_STATE, "PBR_SURROGATE set but no surrogate attached (pbr_set_surrogate)");
+    if (!s->trained || s->ctx_uid != ctx->uid || s->scene_version != ctx->scene_version)
+        return fail(ctx, PBR_ERR_STATE, "the attached surrogate no longer matches this context's field, optics or sensor");
+    out->run = hook_run;
+    out->self = s;
+    return PBR_OK;
+}
+
+}  // namespace host
+}  // namespace pbr
+
+#define SURR_GUARD_BEGIN try {
+#define SURR_GUARD_END                                                       \
+    }                                                                        \
+    catch (...) { return sfail(s, PBR_ERR_HIP, "internal error (exception)"); }
+
+extern "C" {
+
+int pbr_surrogate_create(pbr_surrogate **out, int device, void *hip_stream, uint64_t init_seed, int64_t max_rows)
+{
+    pbr_surrogate *s = nullptr;
+    try {
+        if (!out) return sfail(nullptr, PBR_ERR_ARG, "out is null");
+        *out = nullptr;
+        if (max_rows < 0 || max_rows > ((int64_t)1 << 24))
+            return sfail(nullptr, PBR_ERR_ARG, "max_rows must lie in [0, 2^24]");
+        int ndev = 0, e = (int)hipGetDeviceCount(&ndev);
+        if (e) return sfail(nullptr, PBR_ERR_HIP, "hipGetDeviceCount: %s", hipGetErrorString((hipError_t)e));
+        if (device == -1 && (e = (int)hipGetDevice(&device)))
+            return sfail(nullptr, PBR_ERR_HIP, "hipGetDevice: %s", hipGetErrorString((hipError_t)e));
+        if (device < 0 || device >= ndev)
+            return sfail(nullptr, PBR_ERR_ARG, "device %d out of range (%d devices)", device, ndev);
+        DeviceGuard g(device);
+        if (!g.ok) return sfail(nullptr, PBR_ERR_HIP, "hipSetDevice(%d) failed", device);
+        s = new (std::nothrow) pbr_surrogate();
+        if (!s) return sfail(nullptr, PBR_ERR_HIP, "out of host memory");
+        s->device = device;
+        s->rows_cap = max_rows == 0 ? 65536 : round64(max_rows);
+        if (hip_stream) {
+            s->stream = (hipStream_t)hip_stream;
+        } else {
+            if ((e = (int)hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking))) {
+                delete s;
+                return sfail(nullptr, PBR_ERR_HIP, "hipStreamCreate: %s", hipGetErrorString((hipError_t)e));
+            }
+            s->own_stream = true;
+        }
+        const int64_t R = s->rows_cap, H = pbr::kHidden, P = pbr::kParams + 64;
+        void *p;
+        auto A = [&](size_t bytes) -> void * {
+            if (e) return nullptr;
+            e = dmalloc(s, &p, bytes);
+            return e ? nullptr : p;
+        };
+        e = 0;
+        s->d.params = (float *)A(P * 4);
+        s->d.grad = (float *)A(P * 4);
+        s->d.m = (float *)A(P * 4);
+        s->d.v = (float *)A(P * 4);
+        unsigned short **w[6] = {&s->d.w2, &s->d.w2t, &s->d.w3, &s->d.w3t, &s->d.w4, &s->d.w4t};
+        for (auto q : w) *q = (unsigned short *)A(H * H * 2);
+        s->d.w5 = (unsigned short *)A(pbr::kOutPad * H * 2);
+        s->b.rows_cap = R;
+        for (int l = 0; l < 4; ++l) {
+            s->b.z[l] = (float *)A(R * H * 4);
+            s->b.a[l] = (unsigned short *)A(R * H * 2);
+        }
+        s->b.dy = (float *)A(R * 6 * 4);
+        s->b.dz = (float *)A(R * H * 4);
+        s->b.dz2 = (float *)A(R * H * 4);
+        s->b.dzb = (unsigned short *)A(R * H * 2);
+        s->b.dzb2 = (unsigned short *)A(R * H * 2);
+        s->b.t0 = (unsigned short *)A(R * H * 2);
+        s->b.t1 = (unsigned short *)A(R * H * 2);
+        s->b.loss_part = (float *)A(((R * 6 + 255) / 256) * 4);
+        s->x = (float *)A(R * 6 * 4);
+        s->y = (float *)A(R * 6 * 4);
+        s->t = (float *)A(R * 6 * 4);
+        s->idx = (int *)A(R * 4);
+        s->loss = (float *)A(256);
+        s->count = (unsigned long long *)A(256);
+        if (e) {
+            const int r = sfail(nullptr, PBR_ERR_HIP, "hipMalloc: %s", hipGetErrorString((hipError_t)e));
+            free_all(s);
+            if (s->own_stream) (void)hipStreamDestroy(s->stream);
+            delete s;
+            return r;
+        }
+        *out = s;
+        std::vector<float> init;
+        init_params(init_seed, init);
+        const int r = pbr_surrogate_set_params(s, init.data(), pbr::kParams);
+        if (r) {
+            g_surr_create_err = s->err;
+            pbr_surrogate_destroy(s);
+            *out = nullptr;
+            return r;
+        }
+        return PBR_OK;
+    } catch (...) {
+        if (s) pbr_surrogate_destroy(s);
+        if (out) *out = nullptr;
+        return sfail(nullptr, PBR_ERR_HIP, "internal error (exception)");
+    }
+}
+
+void pbr_surrogate_destroy(pbr_surrogate *s)
+{
+    if (!s) return;
+    try {
+        DeviceGuard g(s->device);
+        (void)hipStreamSynchronize(s->stream);
+        free_all(s);
+        if (s->own_stream) (void)hipStreamDestroy(s->stream);
+    } catch (...) {
+    }
+    delete s;
+}
+
+const char *pbr_surrogate_last_error(const pbr_surrogate *s) { return s ? s->err.c_str() : g_surr_create_err.c_str(); }
+
+int pbr_surrogate_set_params(pbr_surrogate *s, const float *params_host, int64_t n)
+{
+    if (!s) return PBR_ERR_ARG;
+    SURR_GUARD_BEGIN
+    if (!params_host) return sfail(s, PBR_ERR_ARG, "params is null");
+    if (n != pbr::kParams) return sfail(s, PBR_ERR_ARG, "expected %d parameters, got %lld", pbr::kParams, (long long)n);
+    for (int64_t k = 0; k < n; ++k)
+        if (!std::isfinite(params_host[k])) return sfail(s, PBR_ERR_ARG, "parameter %lld is not finite", (long long)k);
+    DeviceGuard g(s->device);
+    if (!g.ok) return sfail(s, PBR_ERR_HIP, "hipSetDevice failed");
+    int e;
+    if ((e = (int)hipMemcpyAsync(s->d.params, params_host, (size_t)n * 4, hipMemcpyHostToDevice, s->stream)))
+        return shf(s, e, "copy parameters");
+    const int64_t words = ((int64_t)pbr::kParams + 64) / 2;
+    if ((e = pbr::launch_clear_u64((unsigned long long *)s->d.m, words, s->stream)) ||
+        (e = pbr::launch_clear_u64((unsigned long long *)s->d.v, words, s->stream)) ||
+        (e = pbr::launch_clear_u64((unsigned long long *)s->d.grad, words, s->stream)))
+        return shf(s, e, "clear Adam state");
+    if ((e = pbr::mlp_refresh_shadow(s->d, s->stream))) return shf(s, e, "bf16 weights");
+    if ((e = (int)hipStreamSynchronize(s->stream))) return shf(s, e, "set parameters");
+    s->trained = false;  // the fallback map described the previous weights
+    return PBR_OK;
+    SURR_GUARD_END
+}
+
+int pbr_surrogate_get_params(pbr_surrogate *s, float *params_host, int64_t n)
+{
+    if (!s) return PBR_ERR_ARG;
+    SURR_GUARD_BEGIN
+    if (!params_host) return sfail(s, PBR_ERR_ARG, "params is null");
+    if (n != pbr::kParams) return sfail(s, PBR_ERR_ARG, "expected %d parameters, got %lld", pbr::kParams, (long long)n);
+    DeviceGuard g(s->device);
+    if (!g.ok) return sfail(s, PBR_ERR_HIP, "hipSetDevice failed");
+    int e;
+    if ((e = (int)hipMemcpyAsync(params_host, s->d.params, (size_t)n * 4, hipMemcpyDeviceToHost, s->stream)))
+        return shf(s, e, "copy parameters");
+    if ((e = (int)hipStreamSynchronize(s->stream))) return shf(s, e, "get parameters");
+    return PBR_OK;
+    SURR_GUARD_END
+}
+
+int pbr_surrogate_forward(pbr_surrogate *s, const float *x_dev, int64_t rows, float *y_dev)
+{
+    if (!s) return PBR_ERR_ARG;
+    SURR_GUARD_BEGIN
+    if (rows < 0) return sfail(s, PBR_ERR_ARG, "rows < 0");
+    if (rows > 0 && (!x_dev || !y_dev)) return sfail(s, PBR_ERR_ARG, "null input or output array");
+    DeviceGuard g(s->device);
+    if (!g.ok) return sfail(s, PBR_ERR_HIP, "hipSetDevice failed");
+    const int e = forward_rows(s, x_dev, rows, y_dev, s->stream);
+    if (e) return shf(s, e, "forward");
+    return PBR_OK;
+    SURR_GUARD_END
+}
+
+int pbr_surrogate_gradients(pbr_surrogate *s, const float *x_dev, const float *t_dev, int64_t rows,
+                            float *grad_host, double *loss_host)
+{
+    if (!s) return PBR_ERR_ARG;
+    SURR_GUARD_BEGIN
+    int r = check_batch(s, x_dev, t_dev, rows);
+    if (r) return r;
+    DeviceGuard g(s->device);
+    if (!g.ok) return sfail(s, PBR_ERR_HIP, "hipSetDevice failed");
+    int e;
+    if ((e = pbr::mlp_forward(s->d, s->b, x_dev, rows, s->y, true, s->stream)) ||
+        (e = pbr::mlp_backward(s->d, s->b, x_dev, t_dev, rows, s->y, s->stream)) ||
+        (e = pbr::mlp_loss_mean(s->b, rows, s->loss, s->stream)))
+        return shf(s, e, "forward / backward");
+    float l = 0.0f;
+    if ((e = (int)hipMemcpyAsync(&l, s->loss, 4, hipMemcpyDeviceToHost, s->stream))) return shf(s, e, "copy loss");
+    if (grad_host &&
+        (e = (int)hipMemcpyAsync(grad_host, s->d.grad, (size_t)pbr::kParams * 4, hipMemcpyDeviceToHost, s->stream)))
+        return shf(s, e, "copy gradients");
+    if ((e = (int)hipStreamSynchronize(s->stream))) return shf(s, e, "gradients");
+    if (loss_host) *loss_host = (double)l;
+    return PBR_OK;
+    SURR_GUARD_END
+}
+
+int pbr_surrogate_adam_step(pbr_surrogate *s, const float *x_dev, const float *t_dev, int64_t rows, float lr,
+                            int32_t step, double *loss_host)
+{
+    if (!s) return PBR_ERR_ARG;
+    SURR_GUARD_BEGIN
+    int r = check_batch(s, x_dev, t_dev, rows);
+    if (r) return r;
+    if (!(lr > 0.0f) || !std::isfinite(lr)) return sfail(s, PBR_ERR_ARG, "lr must be finite and > 0");
+    if (step < 1) return sfail(s, PBR_ERR_ARG, "step must be >= 1");
+    DeviceGuard g(s->device);
+    if (!g.ok) return sfail(s, PBR_ERR_HIP, "hipSetDevice failed");
+    int e;
+    if ((e = pbr::mlp_forward(s->d, s->b, x_dev, rows, s->y, true, s->stream)) ||
+        (e = pbr::mlp_backward(s->d, s->b, x_dev, t_dev, rows, s->y, s->stream)) ||
+        (e = pbr::mlp_loss_mean(s->b, rows, s->loss, s->stream)) || (e = pbr::mlp_adam(s->d, lr, step, s->stream)))
+        return shf(s, e, "Adam step");
+    s->trained = false;  // the fallback map no longer describes these weights
+    if (loss_host) {
+        float l = 0.0f;
+        if ((e = (int)hipMemcpyAsync(&l, s->loss, 4, hipMemcpyDeviceToHost, s->stream))) return shf(s, e, "copy loss");
+        if ((e = (int)hipStreamSynchronize(s->stream))) return shf(s, e, "Adam step");
+        *loss_host = (double)l;
+    }
+    return PBR_OK;
+    SURR_GUARD_END
+}
+
+int pbr_surrogate_train(pbr_surrogate *s, pbr_ctx *ctx, const float *train_src_dev, int64_t n_train_src,
+                        const float *val_src_dev, int64_t n_val_src, int32_t rays_per_src, uint64_t train_seed,
+                        uint64_t val_seed, double ds, const pbr_surrogate_train_config *cfg,
+                        pbr_surrogate_report *report)
+{
+    if (!s) return PBR_ERR_ARG;
+    SURR_GUARD_BEGIN
+    using clk = std::chrono::steady_clock;
+    if (!ctx || !cfg || !report) return sfail(s, PBR_ERR_ARG, "null context, config or report");
+    if (ctx->device < 0) return sfail(s, PBR_ERR_STATE, "host-only context: no device work");
+    if (ctx->device != s->device) return sfail(s, PBR_ERR_ARG, "context and surrogate live on different devices");
+    pbr::host::Derived dv;
+    if (pbr::host::derive(ctx, &dv)) return sfail(s, PBR_ERR_STATE, "context: %s", ctx->err.c_str());
+    if (!ctx->ray_ws) return sfail(s, PBR_ERR_STATE, "context has no trace workspace");
+    if (!train_src_dev || !val_src_dev || n_train_src < 1 || n_val_src < 1 || rays_per_src < 1)
+        return sfail(s, PBR_ERR_ARG, "need training and validation sources and rays_per_src >= 1");
+    if (((uintptr_t)train_src_dev & 15u) || ((uintptr_t)val_src_dev & 15u))
+        return sfail(s, PBR_ERR_ARG, "source arrays must be 16-byte aligned");
+    const int64_t n_train = n_train_src * (int64_t)rays_per_src, n_val = n_val_src * (int64_t)rays_per_src;
+    if (n_train > ((int64_t)1 << 31) - 1 || n_val > ((int64_t)1 << 31) - 1)
+        return sfail(s, PBR_ERR_ARG, "at most 2^31 - 1 training and validation rays");
+    if (!(ds > 0.0) || !std::isfinite(ds)) return sfail(s, PBR_ERR_ARG, "ds must be finite and > 0");
+    if (cfg->batch < 64 || cfg->batch % 64 || cfg->batch > s->rows_cap)
+        return sfail(s, PBR_ERR_ARG, "batch must be a multiple of 64 in [64, %lld]", (long long)s->rows_cap);
+    if (cfg->epochs < 1) return sfail(s, PBR_ERR_ARG, "epochs must be >= 1");
+    if (!(cfg->lr_max > 0.0f) || !(cfg->lr_min >= 0.0f) || !(cfg->lr_min <= cfg->lr_max) || !std::isfinite(cfg->lr_max))
+        return sfail(s, PBR_ERR_ARG, "need 0 <= lr_min <= lr_max, lr_max > 0");
+    if (!(cfg->tol_px > 0.0)) return sfail(s, PBR_ERR_ARG, "tol_px must be > 0");
+    if (cfg->tiles < 1 || cfg->tiles > 1024) return sfail(s, PBR_ERR_ARG, "tiles must lie in [1, 1024]");
+    if (cfg->min_tile_samples < 1) return sfail(s, PBR_ERR_ARG, "min_tile_samples must be >= 1");
+    DeviceGuard g(s->device);
+    if (!g.ok) return sfail(s, PBR_ERR_HIP, "hipSetDevice failed");
+    std::memset(report, 0, sizeof *report);
+    s->trained = false;
+    if (ctx->surr == s) ctx->surr = nullptr;
+    hipStream_t st = ctx->stream;
+    int e;
+    if ((e = (int)hipStreamSynchronize(s->stream))) return shf(s, e, "surrogate stream");
+
+    pbr::TraceParams P;
+    pbr::host::fill_params(ctx, dv, ds, &P);
+    P.accum = nullptr;
+    pbr::SurrogateSpec spec{};
+    spec.z_lo = P.lo[2]; spec.z_hi = P.hi[2];
+    spec.x_lo = P.lo[0]; spec.x_hi = P.hi[0];
+    spec.y_lo = P.lo[1]; spec.y_hi = P.hi[1];
+    spec.Lx = P.hi[0] - P.lo[0];
+    spec.Ly = P.hi[1] - P.lo[1];
+    spec.theta = 1.0;
+    for (int k = 0; k < 6; ++k) { spec.t_mean[k] = 0.0f; spec.t_scale[k] = 1.0f; }
+    spec.tiles = cfg->tiles;
+    spec.tile_ok = nullptr;
+    const int prec = ctx->n_fp64_bricks > 0 ? pbr::PREC_MIXED : pbr::PREC_FP32;
+
+    // scratch of this call, released on every return
+    struct Scratch {
+        std::vector<void *> p;
+        ~Scratch() { for (void *q : p) (void)hipFree(q); }
+        int get(void **q, size_t bytes)
+        {
+            *q = nullptr;
+            int e = (int)hipMalloc(q, bytes < 256 ? 256 : bytes);
+            if (!e) p.push_back(*q);
+            return e;
+        }
+    } scr;
+    pbr::SurrogateSample *trs = nullptr, *vas = nullptr;
+    if ((e = scr.get((void **)&trs, (size_t)n_train * sizeof(pbr::SurrogateSample))) ||
+        (e = scr.get((void **)&vas, (size_t)n_val * sizeof(pbr::SurrogateSample))))
+        return shf(s, e, "hipMalloc(samples)");
+
+    // 1. samples from the tracer
+    auto t0 = clk::now();
+    int r = trace_samples(s, ctx, P, spec, prec, train_src_dev, n_train_src, rays_per_src, train_seed, trs);
+    if (r) return r;
+    r = trace_samples(s, ctx, P, spec, prec, val_src_dev, n_val_src, rays_per_src, val_seed, vas);
+    if (r) return r;
+    // standardisation from the training samples
+    double *part = nullptr;
+    if ((e = scr.get((void **)&part, 1024 * pbr::kMoments * sizeof(double)))) return shf(s, e, "hipMalloc");
+    int nb = 0;
+    if ((e = pbr::launch_surr_moments(trs, n_train, part, &nb, st))) return shf(s, e, "moments");
+    std::vector<double> hp((size_t)nb * pbr::kMoments), mom(pbr::kMoments, 0.0);
+    if ((e = (int)hipMemcpyAsync(hp.data(), part, hp.size() * sizeof(double), hipMemcpyDeviceToHost, st)))
+        return shf(s, e, "copy moments");
+    std::vector<int> flags((size_t)n_train);
+    if ((e = (int)hipMemcpy2DAsync(flags.data(), sizeof(int), &trs[0].flags, sizeof(pbr::SurrogateSample),
+                                   sizeof(int), (size_t)n_train, hipMemcpyDeviceToHost, st)))
+        return shf(s, e, "copy sample flags");
+    if ((e = (int)hipStreamSynchronize(st))) return shf(s, e, "sample trace");
+    report->sample_ms = std::chrono::duration<double, std::milli>(clk::now() - t0).count();
+    for (int b = 0; b < nb; ++b)
+        for (int k = 0; k < pbr::kMoments; ++k) mom[k] += hp[(size_t)b * pbr::kMoments + k];
+    const double N = mom[0];
+    report->train_samples = (int64_t)N;
+    if (N < (double)cfg->batch)
+        return sfail(s, PBR_ERR_ARG, "only %.0f training rays cross the box face to face (batch %d)", N, cfg->batch);
+    for (int k = 0; k < 6; ++k) {
+        const double mean = mom[1 + k] / N;
+        const double var = std::max(mom[7 + k] / N - mean * mean, 0.0);
+        const double sd = std::sqrt(var);
+        if (sd > 1e-30) {
+            spec.t_mean[k] = (float)mean;
+            spec.t_scale[k] = (float)sd;
+        }
+    }
+    spec.theta = std::sqrt((mom[13] + mom[14]) / (2.0 * N));
+    if (!(spec.theta > 0.0)) spec.theta = 1.0;
+    std::vector<int> valid;
+    valid.reserve((size_t)N);
+    for (int64_t i = 0; i < n_train; ++i)
+        if (flags[(size_t)i] & 1) valid.push_back((int)i);
+    std::vector<int>().swap(flags);
+
+    // 2. Adam over shuffled batches, cosine learning rate
+    const int64_t spe = (int64_t)valid.size() / cfg->batch;
+    const int64_t total = spe * cfg->epochs;
+    if (total > (1ll << 30)) return sfail(s, PBR_ERR_ARG, "too many Adam steps");
+    int *perm = nullptr;
+    float *losses = nullptr;
+    if ((e = scr.get((void **)&perm, (size_t)spe * cfg->batch * sizeof(int))) ||
+        (e = scr.get((void **)&losses, (size_t)total * sizeof(float))))
+        return shf(s, e, "hipMalloc(training)");
+    t0 = clk::now();
+    int64_t step = 0;
+    for (int ep = 0; ep < cfg->epochs; ++ep) {
+        // Fisher-Yates shuffle driven by SplitMix64
+        const uint64_t es = cfg->shuffle_seed + 0x632BE59BD9B4E019ull * (uint64_t)(ep + 1);
+        for (size_t i = valid.size() - 1; i > 0; --i) {
+            const size_t j = (size_t)(splitmix64_host(es, i) % (uint64_t)(i + 1));
+            std::swap(valid[i], valid[j]);
+        }
+        if ((e = (int)hipMemcpyAsync(perm, valid.data(), (size_t)spe * cfg->batch * sizeof(int),
+                                     hipMemcpyHostToDevice, st)))
+            return shf(s, e, "copy permutation");
+        for (int64_t j = 0; j < spe; ++j, ++step) {
+            const double ph = total > 1 ? (double)step / (double)(total - 1) : 0.0;
+            const float lr =
+                (float)(cfg->lr_min + 0.5 * ((double)cfg->lr_max - cfg->lr_min) * (1.0 + std::cos(3.14159265358979323846 * ph)));
+            if ((e = pbr::launch_surr_gather(spec, trs, perm + j * cfg->batch, cfg->batch, s->x, s->t, st)) ||
+                (e = pbr::mlp_forward(s->d, s->b, s->x, cfg->batch, s->y, true, st)) ||
+                (e = pbr::mlp_backward(s->d, s->b, s->x, s->t, cfg->batch, s->y, st)) ||
+                (e = pbr::mlp_loss_mean(s->b, cfg->batch, losses + step, st)) ||
+                (e = pbr::mlp_adam(s->d, lr, (int)(step + 1), st)))
+                return shf(s, e, "training step");
+        }
+        if ((e = (int)hipStreamSynchronize(st))) return shf(s, e, "training");  // before the next shuffle
+    }
+    std::vector<float> hl((size_t)total);
+    if ((e = (int)hipMemcpy(hl.data(), losses, hl.size() * sizeof(float), hipMemcpyDeviceToHost)))
+        return shf(s, e, "copy losses");
+    report->train_ms = std::chrono::duration<double, std::milli>(clk::now() - t0).count();
+    report->steps = (int32_t)total;
+    double l0 = 0.0, l1 = 0.0;
+    for (int64_t j = 0; j < spe; ++j) {
+        l0 += hl[(size_t)j];
+        l1 += hl[(size_t)(total - spe + j)];
+    }
+    report->loss_first_epoch = l0 / (double)spe;
+    report->loss_last_epoch = l1 / (double)spe;
+
+    // 3. validation in sensor pixels, per entry tile
+    t0 = clk::now();
+    const int64_t nt = (int64_t)cfg->tiles * cfg->tiles;
+    unsigned *tile_err = nullptr, *tile_cnt = nullptr;
+    float *err = nullptr;
+    if ((e = scr.get((void **)&tile_err, (size_t)(nt + 1) * 4)) || (e = scr.get((void **)&tile_cnt, (size_t)(nt + 1) * 4)) ||
+        (e = scr.get((void **)&err, (size_t)n_val * 4)))
+        return shf(s, e, "hipMalloc(validation)");
+    if ((e = pbr::launch_clear_u64((unsigned long long *)tile_err, (nt + 1) / 2, st)) ||
+        (e = pbr::launch_clear_u64((unsigned long long *)tile_cnt, (nt + 1) / 2, st)))
+        return shf(s, e, "clear tiles");
+    for (int64_t off = 0; off < n_val; off += s->rows_cap) {
+        const int64_t n = std::min(s->rows_cap, n_val - off), rp = round64(n);
+        if ((e = pbr::launch_surr_gather(spec, vas + off, nullptr, n, s->x, s->t, st))) return shf(s, e, "gather");
+        if (rp > n && (e = pbr::launch_clear_u64((unsigned long long *)(s->x + n * 6), (rp - n) * 3, st)))
+            return shf(s, e, "pad");
+        if ((e = pbr::mlp_forward(s->d, s->b, s->x, rp, s->y, false, st))) return shf(s, e, "validation forward");
+        if ((e = pbr::launch_surr_validate(P, spec, vas + off, s->y, n, err + off, tile_err, tile_cnt, st)))
+            return shf(s, e, "validate");
+    }
+    std::vector<unsigned> he((size_t)nt), hc((size_t)nt);
+    std::vector<float> herr((size_t)n_val);
+    std::vector<int> vtile((size_t)n_val);
+    if ((e = (int)hipMemcpyAsync(he.data(), tile_err, (size_t)nt * 4, hipMemcpyDeviceToHost, st)) ||
+        (e = (int)hipMemcpyAsync(hc.data(), tile_cnt, (size_t)nt * 4, hipMemcpyDeviceToHost, st)) ||
+        (e = (int)hipMemcpyAsync(herr.data(), err, (size_t)n_val * 4, hipMemcpyDeviceToHost, st)) ||
+        (e = (int)hipMemcpy2DAsync(vtile.data(), sizeof(int), &vas[0].tile, sizeof(pbr::SurrogateSample), sizeof(int),
+                                   (size_t)n_val, hipMemcpyDeviceToHost, st)))
+        return shf(s, e, "copy validation");
+    if ((e = (int)hipStreamSynchronize(st))) return shf(s, e, "validation");
+    s->tile_ok.assign((size_t)nt, 0);
+    s->tile_err.assign((size_t)nt, -1.0f);
+    int32_t elig = 0;
+    for (int64_t k = 0; k < nt; ++k) {
+        if (!hc[(size_t)k]) continue;
+        float f;
+        std::memcpy(&f, &he[(size_t)k], 4);
+        s->tile_err[(size_t)k] = f;
+        if ((int64_t)hc[(size_t)k] >= cfg->min_tile_samples && f <= (float)cfg->tol_px) {
+            s->tile_ok[(size_t)k] = 1;
+            ++elig;
+        }
+    }
+    std::vector<float> ev;
+    ev.reserve((size_t)n_val);
+    double max_elig = 0.0;
+    int64_t n_elig = 0;
+    for (int64_t i = 0; i < n_val; ++i) {
+        const float x = herr[(size_t)i];
+        if (x < 0.0f) continue;
+        ev.push_back(x);
+        if (s->tile_ok[(size_t)vtile[(size_t)i]]) {
+            ++n_elig;
+            max_elig = std::max(max_elig, (double)x);
+        }
+    }
+    report->val_samples = (int64_t)ev.size();
+    report->val_eligible = n_elig;
+    report->eligible_tiles = elig;
+    report->val_max_eligible_px = max_elig;
+    if (!ev.empty()) {
+        std::sort(ev.begin(), ev.end());
+        report->val_median_px = ev[ev.size() / 2];
+        report->val_p99_px = ev[std::min(ev.size() - 1, (size_t)(0.99 * (double)ev.size()))];
+        report->val_max_px = ev.back();
+    }
+    if (nt > s->tile_cap) {
+        void *q = nullptr;
+        if ((e = dmalloc(s, &q, (size_t)nt))) return shf(s, e, "hipMalloc(tile map)");
+        s->tile_ok_dev = (unsigned char *)q;
+        s->tile_cap = nt;
+    }
+    if ((e = (int)hipMemcpy(s->tile_ok_dev, s->tile_ok.data(), (size_t)nt, hipMemcpyHostToDevice)))
+        return shf(s, e, "copy tile map");
+    report->validate_ms = std::chrono::duration<double, std::milli>(clk::now() - t0).count();
+    spec.tile_ok = s->tile_ok_dev;
+    s->spec = spec;
+    s->ctx_uid = ctx->uid;
+    s->scene_version = ctx->scene_version;
+    s->trained = true;
+    return PBR_OK;
+    SURR_GUARD_END
+}
+
+int pbr_surrogate_tile_map(pbr_surrogate *s, uint8_t *eligible_host, float *max_err_host, int64_t n_tiles)
+{
+    if (!s) return PBR_ERR_ARG;
+    if (!s->trained) return sfail(s, PBR_ERR_STATE, "surrogate not trained");
+    if (n_tiles != (int64_t)s->tile_ok.size())
+        return sfail(s, PBR_ERR_ARG, "expected %lld tiles", (long long)s->tile_ok.size());
+    if (eligible_host) std::memcpy(eligible_host, s->tile_ok.data(), s->tile_ok.size());
+    if (max_err_host) std::memcpy(max_err_host, s->tile_err.data(), s->tile_err.size() * 4);
+    return PBR_OK;
+}
+
+int pbr_set_surrogate(pbr_ctx *ctx, pbr_surrogate *s)
+{
+    if (!ctx) return PBR_ERR_ARG;
+    if (!s) {
+        ctx->surr = nullptr;
+        return PBR_OK;
+    }
+    if (!s->trained) return pbr::host::fail(ctx, PBR_ERR_STATE, "surrogate not trained");
+    if (s->ctx_uid != ctx->uid) return pbr::host::fail(ctx, PBR_ERR_STATE, "surrogate trained on another context");
+    if (s->scene_version != ctx->scene_version)
+        return pbr::host::fail(ctx, PBR_ERR_STATE, "field, optics or sensor changed since the surrogate was trained");
+    ctx->surr = s;
+    return PBR_OK;
+}
+
+}  // extern "C"

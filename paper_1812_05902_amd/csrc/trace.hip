@@ -400,7 +400,7 @@ __device__ __forceinline__ void box_body(const TraceParams &P, RayState *__restr
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     RayState r = st[i];
-    if (!(r.info & RS_ENTERED)) return;
+    if ((r.info & (RS_ENTERED | RS_SURR)) != RS_ENTERED) return;
     box_ray<F>(P, r);
     st[i] = r;
 }
@@ -518,7 +518,7 @@ __global__ void __launch_bounds__(256) k_box_mixed(TraceParams P, RayState *__re
     int n64 = 0;
     if (i < n) {
         RayState r = st[i];
-        if (r.info & RS_ENTERED) {
+        if ((r.info & (RS_ENTERED | RS_SURR)) == RS_ENTERED) {
             float Tr[3] = {r.Tr[0], r.Tr[1], r.Tr[2]}, dT[3] = {r.dT[0], r.dT[1], r.dT[2]};
             CellCache cc;
             cc.key = -1;
@@ -839,7 +839,7 @@ __global__ void __launch_bounds__(BLOCK, 5) k_box_batch(const TraceParams *__res
             const int64_t idx = ray0 + sub + lane;
             if (idx - sg.slot_base * 256 >= sg.n_rays) continue;
             RayState r = st[idx];
-            if (!(r.info & RS_ENTERED)) continue;
+            if ((r.info & (RS_ENTERED | RS_SURR)) != RS_ENTERED) continue;
             box_ray<float>(P, r);
             st[idx] = r;
         }
@@ -862,7 +862,307 @@ __global__ void __launch_bounds__(256) k_finish_batch(const TraceParams *__restr
     flush_counters<TILE>(P, sh);
 }
 
+// ------------------------------------------------------------------ ray surrogate
+
+// Entry point (world) and unit direction of an emitted state that entered through z = z_lo.
+__device__ __forceinline__ bool entry_of(const TraceParams &P, const RayState &r, double E[3], double u[3])
+{
+    if (!(r.info & RS_ENTERED) || r.c[2] != 0 || r.fd[2] != 0.0) return false;
+    double n2 = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        E[a] = P.origin[a] + ((double)r.c[a] + r.fd[a]) * P.spacing[a];
+        u[a] = (double)r.Tr[a] + (double)r.dT[a];
+        n2 += u[a] * u[a];
+    }
+    const double il = 1.0 / sqrt(n2);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) u[a] *= il;
+    return u[2] > 0.0;
+}
+
+__device__ __forceinline__ void surr_features(const SurrogateSpec &sp, const double E[3], const double u[3], float x[6])
+{
+    x[0] = (float)((2.0 * E[0] - sp.x_lo - sp.x_hi) / (sp.x_hi - sp.x_lo));
+    x[1] = (float)((2.0 * E[1] - sp.y_lo - sp.y_hi) / (sp.y_hi - sp.y_lo));
+    x[2] = (float)(u[0] / sp.theta);
+    x[3] = (float)(u[1] / sp.theta);
+    x[4] = (float)sin(kTwoPi * (E[0] - sp.x_lo) / sp.Lx);
+    x[5] = (float)sin(kTwoPi * (E[1] - sp.y_lo) / sp.Ly);
+}
+
+__device__ __forceinline__ int surr_tile(const SurrogateSpec &sp, const double E[3])
+{
+    int tx = (int)((E[0] - sp.x_lo) / (sp.x_hi - sp.x_lo) * sp.tiles);
+    int ty = (int)((E[1] - sp.y_lo) / (sp.y_hi - sp.y_lo) * sp.tiles);
+    tx = min(max(tx, 0), sp.tiles - 1);
+    ty = min(max(ty, 0), sp.tiles - 1);
+    return ty * sp.tiles + tx;
+}
+
+// Straight-line exit on z = z_hi from the entry.
+__device__ __forceinline__ void straight_exit(const SurrogateSpec &sp, const double E[3], const double u[3], double Q[3])
+{
+    const double l = (sp.z_hi - E[2]) / u[2];
+    Q[0] = E[0] + l * u[0];
+    Q[1] = E[1] + l * u[1];
+    Q[2] = sp.z_hi;
+}
+
+__global__ void __launch_bounds__(256) k_surr_samples(TraceParams P, SurrogateSpec sp, const RayState *__restrict__ st,
+                                                      int64_t first, int64_t n, SurrogateSample *__restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    SurrogateSample smp;
+    for (int k = 0; k < 6; ++k) smp.t[k] = 0.0f;
+    smp.E[0] = smp.E[1] = 0.0; smp.u[0] = smp.u[1] = smp.u[2] = 0.0; smp.px[0] = smp.px[1] = 0.0;
+    smp.tile = 0;
+    smp.flags = 0;
+    RayState e;
+    emit_ray(P, first + i, e);  // the entry state again (the trace overwrote it)
+    double E[3], u[3];
+    const RayState r = st[i];
+    if (entry_of(P, e, E, u) && !(r.info & RS_LIMITED) && r.c[2] == P.nz - 2 && r.fd[2] == 1.0) {
+        double X[3], d[3], Q[3], n2 = 0.0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            X[a] = P.origin[a] + ((double)r.c[a] + r.fd[a]) * P.spacing[a];
+            d[a] = (double)r.Tr[a] + (double)r.dT[a];
+            n2 += d[a] * d[a];
+        }
+        const double il = 1.0 / sqrt(n2);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) d[a] *= il;
+        straight_exit(sp, E, u, Q);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            smp.t[a] = (float)(X[a] - Q[a]);
+            smp.t[3 + a] = (float)(d[a] - u[a]);
+            smp.u[a] = u[a];
+        }
+        smp.E[0] = E[0];
+        smp.E[1] = E[1];
+        smp.tile = surr_tile(sp, E);
+        smp.flags = 1;
+        double xp, yp;
+        if (optics_to_sensor(P, X, d, &xp, &yp) == PBR_RAY_DEPOSITED) {
+            smp.px[0] = xp;
+            smp.px[1] = yp;
+            smp.flags |= 2;
+        }
+    }
+    out[i] = smp;
+}
+
+__global__ void __launch_bounds__(256) k_surr_features(TraceParams P, SurrogateSpec sp, const RayState *__restrict__ st,
+                                                       int64_t n, float *__restrict__ x, int *__restrict__ idx,
+                                                       unsigned long long *__restrict__ count)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    double E[3], u[3];
+    bool ok = false;
+    if (i < n) {
+        ok = entry_of(P, st[i], E, u);
+        if (ok) ok = sp.tile_ok[surr_tile(sp, E)] != 0;
+    }
+    // one atomic per wave: the eligible lanes take consecutive rows
+    const unsigned long long mask = __ballot(ok);
+    unsigned long long base = 0;
+    if (lane == 0 && mask) base = atomicAdd(count, (unsigned long long)__popcll(mask));
+    base = __shfl(base, 0);
+    if (ok) {
+        const int64_t row = (int64_t)base + __popcll(mask & ((1ull << lane) - 1ull));
+        float f[6];
+        surr_features(sp, E, u, f);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) x[row * 6 + k] = f[k];
+        idx[row] = (int)i;
+    }
+}
+
+// Predicted exit: straight exit plus the position change (on z = z_hi), direction u + change.
+__device__ __forceinline__ void surr_predict(const SurrogateSpec &sp, const double E[3], const double u[3],
+                                             const float *y, double X[3], double d[3])
+{
+    double Q[3];
+    straight_exit(sp, E, u, Q);
+    double n2 = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double dp = (double)y[a] * sp.t_scale[a] + sp.t_mean[a];
+        const double dd = (double)y[3 + a] * sp.t_scale[3 + a] + sp.t_mean[3 + a];
+        X[a] = Q[a] + dp;
+        d[a] = u[a] + dd;
+        n2 += d[a] * d[a];
+    }
+    X[2] = sp.z_hi;
+    const double il = 1.0 / sqrt(n2);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) d[a] *= il;
+}
+
+__global__ void __launch_bounds__(256) k_surr_apply(TraceParams P, SurrogateSpec sp, const float *__restrict__ y,
+                                                    const int *__restrict__ idx,
+                                                    const unsigned long long *__restrict__ count, int64_t cap,
+                                                    RayState *__restrict__ st)
+{
+    const unsigned long long live = *count;
+    const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if ((unsigned long long)blockIdx.x * blockDim.x >= live) return;
+    if (row < cap && (unsigned long long)row < live) {
+        const int64_t i = idx[row];
+        RayState r = st[i];
+        double E[3], u[3], X[3], d[3];
+        entry_of(P, r, E, u);
+        surr_predict(sp, E, u, y + row * 6, X, d);
+        const int nn[3] = {P.nx, P.ny, P.nz};
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            double p = (X[a] - P.origin[a]) / P.spacing[a];
+            if (a == 2) p = (double)(nn[2] - 1);
+            p = p < 0.0 ? 0.0 : (p > (double)(nn[a] - 1) ? (double)(nn[a] - 1) : p);
+            int ci = (int)floor(p);
+            ci = ci > nn[a] - 2 ? nn[a] - 2 : ci;
+            r.c[a] = ci;
+            r.fd[a] = p - (double)ci;
+            r.Tr[a] = (float)d[a];
+            r.dT[a] = (float)(d[a] - (double)r.Tr[a]);
+        }
+        r.info = RS_ENTERED | RS_SURR;
+        st[i] = r;
+    }
+    if (threadIdx.x == 0 && blockIdx.x == 0) atomic_add_u64(P.counters + CNT_SURR, live < (unsigned long long)cap ? live : (unsigned long long)cap);
+}
+
+__global__ void __launch_bounds__(256) k_surr_validate(TraceParams P, SurrogateSpec sp,
+                                                       const SurrogateSample *__restrict__ smp, const float *__restrict__ y,
+                                                       int64_t n, float *__restrict__ err, unsigned *__restrict__ tile_err,
+                                                       unsigned *__restrict__ tile_cnt)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const SurrogateSample s = smp[i];
+    float e = -1.0f;
+    if ((s.flags & 3) == 3) {
+        const double E[3] = {s.E[0], s.E[1], sp.z_lo};
+        double X[3], d[3], xp, yp;
+        surr_predict(sp, E, s.u, y + i * 6, X, d);
+        if (optics_to_sensor(P, X, d, &xp, &yp) == PBR_RAY_DEPOSITED) {
+            e = (float)sqrt((xp - s.px[0]) * (xp - s.px[0]) + (yp - s.px[1]) * (yp - s.px[1]));
+        } else {
+            e = 1.0e30f;  // the prediction left the optics: never acceptable
+        }
+        atomicMax(tile_err + s.tile, __float_as_uint(e));
+        atomicAdd(tile_cnt + s.tile, 1u);
+    }
+    err[i] = e;
+}
+
+__global__ void __launch_bounds__(256) k_surr_gather(SurrogateSpec sp, const SurrogateSample *__restrict__ smp,
+                                                     const int *__restrict__ idx, int64_t rows, float *__restrict__ x,
+                                                     float *__restrict__ t)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= rows * 6) return;
+    const int64_t m = q / 6;
+    const int k = (int)(q % 6);
+    const SurrogateSample &s = smp[idx ? (int64_t)idx[m] : m];
+    const double E[3] = {s.E[0], s.E[1], sp.z_lo};
+    float f[6];
+    surr_features(sp, E, s.u, f);
+    x[q] = f[k];
+    t[q] = (s.t[k] - sp.t_mean[k]) / sp.t_scale[k];
+}
+
+__global__ void __launch_bounds__(256) k_surr_moments(const SurrogateSample *__restrict__ smp, int64_t n,
+                                                      double *__restrict__ part)
+{
+    __shared__ double s[kMoments][256];
+    double a[kMoments];
+#pragma unroll
+    for (int k = 0; k < kMoments; ++k) a[k] = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const SurrogateSample &q = smp[i];
+        if (!(q.flags & 1)) continue;
+        a[0] += 1.0;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const double v = q.t[k];
+            a[1 + k] += v;
+            a[7 + k] += v * v;
+        }
+        a[13] += q.u[0] * q.u[0];
+        a[14] += q.u[1] * q.u[1];
+    }
+#pragma unroll
+    for (int k = 0; k < kMoments; ++k) s[k][threadIdx.x] = a[k];
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o)
+#pragma unroll
+            for (int k = 0; k < kMoments; ++k) s[k][threadIdx.x] += s[k][threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x < kMoments) part[blockIdx.x * kMoments + threadIdx.x] = s[threadIdx.x][0];
+}
+
 }  // namespace
+
+int launch_surr_samples(const TraceParams &p, const SurrogateSpec &sp, const RayState *st, int64_t first,
+                        int64_t n, SurrogateSample *out, hipStream_t s)
+{
+    if (n <= 0) return 0;
+    hipLaunchKernelGGL(k_surr_samples, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, sp, st, first, n, out);
+    return (int)hipGetLastError();
+}
+
+int launch_surr_features(const TraceParams &p, const SurrogateSpec &sp, const RayState *st, int64_t n,
+                         float *x, int *idx, unsigned long long *count, hipStream_t s)
+{
+    if (n <= 0) return 0;
+    hipLaunchKernelGGL(k_surr_features, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, sp, st, n, x, idx,
+                       count);
+    return (int)hipGetLastError();
+}
+
+int launch_surr_apply(const TraceParams &p, const SurrogateSpec &sp, const float *y, const int *idx,
+                      const unsigned long long *count, int64_t cap, RayState *st, hipStream_t s)
+{
+    if (cap <= 0) return 0;
+    hipLaunchKernelGGL(k_surr_apply, dim3((unsigned)((cap + 255) / 256)), dim3(256), 0, s, p, sp, y, idx, count,
+                       cap, st);
+    return (int)hipGetLastError();
+}
+
+int launch_surr_validate(const TraceParams &p, const SurrogateSpec &sp, const SurrogateSample *smp,
+                         const float *y, int64_t n, float *err, unsigned *tile_err, unsigned *tile_cnt,
+                         hipStream_t s)
+{
+    if (n <= 0) return 0;
+    hipLaunchKernelGGL(k_surr_validate, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, sp, smp, y, n, err,
+                       tile_err, tile_cnt);
+    return (int)hipGetLastError();
+}
+
+int launch_surr_gather(const SurrogateSpec &sp, const SurrogateSample *smp, const int *idx, int64_t rows,
+                       float *x, float *t, hipStream_t s)
+{
+    if (rows <= 0) return 0;
+    hipLaunchKernelGGL(k_surr_gather, dim3((unsigned)((rows * 6 + 255) / 256)), dim3(256), 0, s, sp, smp, idx, rows,
+                       x, t);
+    return (int)hipGetLastError();
+}
+
+int launch_surr_moments(const SurrogateSample *smp, int64_t n, double *part, int *blocks, hipStream_t s)
+{
+    int nb = (int)((n + 255) / 256);
+    nb = nb < 1024 ? (nb < 1 ? 1 : nb) : 1024;
+    *blocks = nb;
+    hipLaunchKernelGGL(k_surr_moments, dim3((unsigned)nb), dim3(256), 0, s, smp, n, part);
+    return (int)hipGetLastError();
+}
 
 int launch_calibrate(const TraceParams &p, const int *bricks, int n_bricks, int rays_per_brick,
                      int n_steps, uint64_t seed, double z_focus, double px_per_m, float *err,
@@ -875,13 +1175,15 @@ int launch_calibrate(const TraceParams &p, const int *bricks, int n_bricks, int 
 }
 
 int launch_trace_chunk(const TraceParams &p, RayState *st, int64_t first, int64_t n, int prec,
-                       hipStream_t stream, hipEvent_t box_begin, hipEvent_t box_end)
+                       hipStream_t stream, hipEvent_t box_begin, hipEvent_t box_end, const ChunkHook *hook,
+                       bool deposit)
 {
     if (n <= 0) return 0;
     const unsigned blocks = (unsigned)((n + 255) / 256);
     hipLaunchKernelGGL(k_emit, dim3(blocks), dim3(256), 0, stream, p, st, first, n);
     int e = (int)hipGetLastError();
     if (e) return e;
+    if (hook && (e = hook->run(hook->self, p, st, first, n, stream))) return e;
     if (box_begin && (e = (int)hipEventRecord(box_begin, stream))) return e;
     if (prec == PREC_FP64)
         hipLaunchKernelGGL(k_box64, dim3(blocks), dim3(256), 0, stream, p, st, n);
@@ -892,6 +1194,7 @@ int launch_trace_chunk(const TraceParams &p, RayState *st, int64_t first, int64_
     e = (int)hipGetLastError();
     if (e) return e;
     if (box_end && (e = (int)hipEventRecord(box_end, stream))) return e;
+    if (!deposit) return 0;
     unsigned fblocks = blocks < 4096u ? blocks : 4096u;
     hipLaunchKernelGGL(k_finish<kTile>, dim3(fblocks), dim3(256), 0, stream, p, (const RayState *)st, first, n);
     return (int)hipGetLastError();

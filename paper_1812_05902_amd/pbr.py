@@ -23,7 +23,8 @@ PBR_OK, PBR_ERR_ARG, PBR_ERR_STATE, PBR_ERR_HIP, PBR_ERR_WORKSPACE, PBR_ERR_OVER
 (PBR_RAY_DEPOSITED, PBR_RAY_OFF_SENSOR, PBR_RAY_BLOCKED_APERTURE, PBR_RAY_BLOCKED_LENS,
  PBR_RAY_TIR, PBR_RAY_STEP_LIMIT, PBR_RAY_MISSED) = range(7)
 PBR_NUM_STATUS = 7
-PBR_CLEAR_FIRST, PBR_RECORD_EXITS, PBR_PREC_FP64_ALL, PBR_PREC_SHOCK_FP64 = 1, 2, 4, 8
+PBR_CLEAR_FIRST, PBR_RECORD_EXITS, PBR_PREC_FP64_ALL, PBR_PREC_SHOCK_FP64, PBR_SURROGATE = 1, 2, 4, 8, 16
+PBR_SURR_PARAMS = 200710
 PBR_FMT_RAW_U64, PBR_FMT_F32, PBR_FMT_U16 = 0, 1, 2
 
 EXPORTED = ["pbr_create", "pbr_destroy", "pbr_last_error", "pbr_set_stream",
@@ -33,7 +34,11 @@ EXPORTED = ["pbr_create", "pbr_destroy", "pbr_last_error", "pbr_set_stream",
             "pbr_emit_and_trace", "pbr_calibrate_precision", "pbr_brick_flags",
             "pbr_read_image", "pbr_read_ray_exits",
             "pbr_batch_workspace_bytes", "pbr_batch_create", "pbr_batch_destroy", "pbr_batch_last_error",
-            "pbr_batch_get_config", "pbr_batch_configure", "pbr_batch_run", "pbr_batch_autotune"]
+            "pbr_batch_get_config", "pbr_batch_configure", "pbr_batch_run", "pbr_batch_autotune",
+            "pbr_surrogate_create", "pbr_surrogate_destroy", "pbr_surrogate_last_error",
+            "pbr_surrogate_set_params", "pbr_surrogate_get_params", "pbr_surrogate_forward",
+            "pbr_surrogate_gradients", "pbr_surrogate_adam_step", "pbr_surrogate_train",
+            "pbr_surrogate_tile_map", "pbr_set_surrogate"]
 
 
 class PbrError(RuntimeError):
@@ -65,7 +70,7 @@ class pbr_stats(C.Structure):
     _fields_ = [("rays", C.c_uint64), ("status", C.c_uint64 * PBR_NUM_STATUS),
                 ("entered_volume", C.c_uint64), ("rkn_steps", C.c_uint64),
                 ("rkn_steps_fp64", C.c_uint64), ("trace_ms", C.c_double),
-                ("box_ms", C.c_double), ("box_launches", C.c_uint64)]
+                ("box_ms", C.c_double), ("box_launches", C.c_uint64), ("surrogate_rays", C.c_uint64)]
 
 
 class pbr_precision_report(C.Structure):
@@ -88,6 +93,20 @@ class pbr_batch_config(C.Structure):
 class pbr_batch_stats(C.Structure):
     _fields_ = [("rays", C.c_uint64), ("status", C.c_uint64 * PBR_NUM_STATUS), ("rkn_steps", C.c_uint64),
                 ("run_ms", C.c_double), ("rounds", C.c_int32), ("images", C.c_int32)]
+
+
+class pbr_surrogate_train_config(C.Structure):
+    _fields_ = [("batch", C.c_int32), ("epochs", C.c_int32), ("lr_max", C.c_float), ("lr_min", C.c_float),
+                ("tol_px", C.c_double), ("tiles", C.c_int32), ("min_tile_samples", C.c_int32),
+                ("shuffle_seed", C.c_uint64)]
+
+
+class pbr_surrogate_report(C.Structure):
+    _fields_ = [("train_samples", C.c_int64), ("val_samples", C.c_int64), ("val_eligible", C.c_int64),
+                ("steps", C.c_int32), ("eligible_tiles", C.c_int32), ("loss_first_epoch", C.c_double),
+                ("loss_last_epoch", C.c_double), ("val_median_px", C.c_double), ("val_p99_px", C.c_double),
+                ("val_max_px", C.c_double), ("val_max_eligible_px", C.c_double), ("sample_ms", C.c_double),
+                ("train_ms", C.c_double), ("validate_ms", C.c_double)]
 
 
 RAY_EXIT_DTYPE = np.dtype([("ray_id", "<i8"), ("status", "<i4"), ("n_steps", "<i4"),
@@ -134,6 +153,18 @@ def load(path: str = LIB_PATH):
         "pbr_batch_run": (I, [P, C.POINTER(pbr_batch_stats)]),
         "pbr_batch_autotune": (I, [P, C.c_char_p, C.c_int32, C.POINTER(pbr_batch_config), C.POINTER(C.c_double)]),
         "pbr_read_ray_exits": (I, [P, P, I64, I64]),
+        "pbr_surrogate_create": (I, [C.POINTER(P), I, P, U64, I64]),
+        "pbr_surrogate_destroy": (None, [P]),
+        "pbr_surrogate_last_error": (C.c_char_p, [P]),
+        "pbr_surrogate_set_params": (I, [P, P, I64]),
+        "pbr_surrogate_get_params": (I, [P, P, I64]),
+        "pbr_surrogate_forward": (I, [P, P, I64, P]),
+        "pbr_surrogate_gradients": (I, [P, P, P, I64, P, C.POINTER(D)]),
+        "pbr_surrogate_adam_step": (I, [P, P, P, I64, C.c_float, C.c_int32, C.POINTER(D)]),
+        "pbr_surrogate_train": (I, [P, P, P, I64, P, I64, C.c_int32, U64, U64, D,
+                                    C.POINTER(pbr_surrogate_train_config), C.POINTER(pbr_surrogate_report)]),
+        "pbr_surrogate_tile_map": (I, [P, P, P, I64]),
+        "pbr_set_surrogate": (I, [P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(l, name)
@@ -249,7 +280,7 @@ def stats_dict(st: pbr_stats) -> dict:
                 entered_volume=int(st.entered_volume), rkn_steps=int(st.rkn_steps),
                 rkn_steps_fp64=int(st.rkn_steps_fp64),
                 trace_ms=float(st.trace_ms), box_ms=float(st.box_ms),
-                box_launches=int(st.box_launches))
+                box_launches=int(st.box_launches), surrogate_rays=int(st.surrogate_rays))
 
 
 class Renderer:
@@ -483,6 +514,138 @@ class Batch:
     def close(self):
         if getattr(self, "h", None) is not None:
             pbr_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------------ ray surrogate network
+
+def _scheck(sg, code):
+    if code != PBR_OK:
+        msg = _lib.pbr_surrogate_last_error(sg)
+        raise PbrError(code, msg.decode() if msg else "")
+
+
+def pbr_surrogate_create(device, stream, init_seed=0, max_rows=0):
+    h = C.c_void_p()
+    code = load().pbr_surrogate_create(C.byref(h), int(device), stream, int(init_seed), int(max_rows))
+    if code != PBR_OK:
+        raise PbrError(code, _lib.pbr_surrogate_last_error(None).decode())
+    return h
+
+
+def pbr_surrogate_destroy(sg):
+    load().pbr_surrogate_destroy(sg)
+
+
+def pbr_surrogate_set_params(sg, params: np.ndarray):
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    _scheck(sg, load().pbr_surrogate_set_params(sg, p.ctypes.data_as(C.c_void_p), p.size))
+
+
+def pbr_surrogate_get_params(sg) -> np.ndarray:
+    p = np.zeros(PBR_SURR_PARAMS, dtype=np.float32)
+    _scheck(sg, load().pbr_surrogate_get_params(sg, p.ctypes.data_as(C.c_void_p), p.size))
+    return p
+
+
+def pbr_surrogate_forward(sg, x, y):
+    _scheck(sg, load().pbr_surrogate_forward(sg, _dptr(x), int(x.shape[0]), _dptr(y)))
+
+
+def pbr_surrogate_gradients(sg, x, t, want_grad=True):
+    g = np.zeros(PBR_SURR_PARAMS, dtype=np.float32) if want_grad else None
+    loss = C.c_double()
+    _scheck(sg, load().pbr_surrogate_gradients(sg, _dptr(x), _dptr(t), int(x.shape[0]),
+                                               g.ctypes.data_as(C.c_void_p) if g is not None else None,
+                                               C.byref(loss)))
+    return float(loss.value), g
+
+
+def pbr_surrogate_adam_step(sg, x, t, lr, step, want_loss=False):
+    loss = C.c_double()
+    _scheck(sg, load().pbr_surrogate_adam_step(sg, _dptr(x), _dptr(t), int(x.shape[0]), float(lr), int(step),
+                                               C.byref(loss) if want_loss else None))
+    return float(loss.value) if want_loss else None
+
+
+def pbr_surrogate_train(sg, ctx, train_src, val_src, rays_per_src, train_seed, val_seed, ds,
+                        cfg: pbr_surrogate_train_config) -> pbr_surrogate_report:
+    rep = pbr_surrogate_report()
+    _scheck(sg, load().pbr_surrogate_train(sg, ctx, _dptr(train_src), int(train_src.shape[0]), _dptr(val_src),
+                                           int(val_src.shape[0]), int(rays_per_src), int(train_seed),
+                                           int(val_seed), float(ds), C.byref(cfg), C.byref(rep)))
+    return rep
+
+
+def pbr_surrogate_tile_map(sg, tiles):
+    ok = np.zeros(tiles * tiles, dtype=np.uint8)
+    err = np.zeros(tiles * tiles, dtype=np.float32)
+    _scheck(sg, load().pbr_surrogate_tile_map(sg, ok.ctypes.data_as(C.c_void_p), err.ctypes.data_as(C.c_void_p),
+                                              tiles * tiles))
+    return ok.reshape(tiles, tiles), err.reshape(tiles, tiles)
+
+
+def pbr_set_surrogate(ctx, sg):
+    _check(ctx, load().pbr_set_surrogate(ctx, sg))
+
+
+class Surrogate:
+    """The ray surrogate network on torch's current device and stream."""
+
+    def __init__(self, device=None, init_seed=0, max_rows=0):
+        import torch
+        self.torch = torch
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        stream = torch.cuda.current_stream(self.device)
+        self.h = pbr_surrogate_create(self.device.index, C.c_void_p(stream.cuda_stream), init_seed, max_rows)
+        self.tiles = 0
+
+    def _dev(self, a):
+        return self.torch.as_tensor(a, dtype=self.torch.float32, device=self.device).contiguous()
+
+    def set_params(self, p):
+        pbr_surrogate_set_params(self.h, p)
+
+    def params(self) -> np.ndarray:
+        return pbr_surrogate_get_params(self.h)
+
+    def forward(self, x):
+        x = self._dev(x)
+        y = self.torch.empty_like(x)
+        pbr_surrogate_forward(self.h, x, y)
+        return y
+
+    def gradients(self, x, t):
+        return pbr_surrogate_gradients(self.h, self._dev(x), self._dev(t))
+
+    def adam_step(self, x, t, lr, step, want_loss=False):
+        return pbr_surrogate_adam_step(self.h, self._dev(x), self._dev(t), lr, step, want_loss)
+
+    def train(self, renderer, train_src, val_src, rays_per_src, train_seed, val_seed, ds, batch=4096, epochs=4,
+              lr_max=1e-3, lr_min=1e-5, tol_px=0.01, tiles=64, min_tile_samples=8, shuffle_seed=1) -> dict:
+        cfg = pbr_surrogate_train_config(int(batch), int(epochs), float(lr_max), float(lr_min), float(tol_px),
+                                         int(tiles), int(min_tile_samples), int(shuffle_seed))
+        tr, va = self._dev(train_src), self._dev(val_src)
+        rep = pbr_surrogate_train(self.h, renderer.ctx, tr, va, rays_per_src, train_seed, val_seed, ds, cfg)
+        self.tiles = int(tiles)
+        return {k: getattr(rep, k) for k, _ in pbr_surrogate_report._fields_}
+
+    def tile_map(self):
+        return pbr_surrogate_tile_map(self.h, self.tiles)
+
+    def attach(self, renderer):
+        pbr_set_surrogate(renderer.ctx, self.h)
+        renderer._surrogate_keepalive = self
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            pbr_surrogate_destroy(self.h)
             self.h = None
 
     def __del__(self):

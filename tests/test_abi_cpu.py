@@ -43,8 +43,38 @@ def test_struct_sizes_match_header_layout(lib):
     assert pbr.RAY_EXIT_DTYPE.itemsize == 88
     assert C.sizeof(pbr.pbr_optics) == 56
     assert C.sizeof(pbr.pbr_sensor) == 48
-    assert C.sizeof(pbr.pbr_stats) == 8 * (1 + 7 + 3) + 8 * 3
+    assert C.sizeof(pbr.pbr_stats) == 8 * (1 + 7 + 3) + 8 * 3 + 8
     assert C.sizeof(pbr.pbr_precision_report) == 8 * 7 + 8
+
+
+def test_binding_structs_match_c_compiler_layout(tmp_path):
+    """Every ctypes mirror of a header struct has the size and field offsets the C compiler gives
+    the header's definition (gcc on the header itself), and the record dtype matches its struct."""
+    import subprocess
+    structs = [v for k, v in vars(pbr).items()
+               if k.startswith("pbr_") and isinstance(v, type) and issubclass(v, C.Structure)]
+    assert len(structs) >= 10
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "pbr.h"', "int main(void) {"]
+    for st in structs + ["pbr_ray_exit"]:
+        name = st if isinstance(st, str) else st.__name__
+        lines.append(f'printf("{name} %zu\\n", sizeof({name}));')
+        fields = (pbr.RAY_EXIT_DTYPE.names if isinstance(st, str) else [f for f, _ in st._fields_])
+        for f in fields:
+            lines.append(f'printf("{name}.{f} %zu\\n", offsetof({name}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = dict(l.split() for l in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                   text=True).stdout.splitlines())
+    for st in structs:
+        assert int(got[st.__name__]) == C.sizeof(st), st.__name__
+        for f, _ in st._fields_:
+            assert int(got[f"{st.__name__}.{f}"]) == getattr(st, f).offset, (st.__name__, f)
+    assert int(got["pbr_ray_exit"]) == pbr.RAY_EXIT_DTYPE.itemsize
+    for f in pbr.RAY_EXIT_DTYPE.names:
+        assert int(got[f"pbr_ray_exit.{f}"]) == pbr.RAY_EXIT_DTYPE.fields[f][1], f
 
 
 def test_batch_structs_and_workspace(lib):

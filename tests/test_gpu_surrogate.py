@@ -1,0 +1,173 @@
+"""GPU: the ray surrogate network's own kernels against the FP64 oracle of the network (in its
+bfloat16-emulation mode: the same roundings at the same places), then the trained surrogate inside
+the trace: fallback map, exit error against the tracer in pixels, and what it gains in time."""
+import numpy as np
+import pytest
+
+from oracle import mlp
+from paper_1812_05902_amd import inputs, pbr
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    pbr.load()
+    return torch
+
+
+def _params32(seed):
+    """Oracle initialisation rounded to the FP32 master weights both sides then use."""
+    v = mlp.flatten(mlp.init_params(seed)).astype(np.float32)
+    return v, mlp.unflatten(v.astype(np.float64))
+
+
+def _batch(rows, seed):
+    rng = np.random.default_rng(seed)
+    x = rng.uniform(-1.0, 1.0, size=(rows, 6)).astype(np.float32)
+    t = rng.normal(size=(rows, 6)).astype(np.float32)
+    return x, t
+
+
+@pytest.mark.parametrize("rows", [64, 200, 1000])
+def test_forward_matches_oracle(torch, rows):
+    v, p = _params32(11)
+    s = pbr.Surrogate(init_seed=0, max_rows=256)  # 1000 rows: several passes and a ragged tail
+    s.set_params(v)
+    assert np.array_equal(s.params(), v)
+    x, _ = _batch(rows, 5)
+    y = s.forward(x).cpu().numpy().astype(np.float64)
+    ref, _ = mlp.forward(p, x.astype(np.float64), bf=True)
+    err = np.abs(y - ref).max() / np.abs(ref).max()
+    print(f"rows {rows}: forward max rel err {err:.3g}")
+    assert err <= 1e-3
+    s.close()
+
+
+def test_gradients_match_oracle(torch):
+    v, p = _params32(12)
+    s = pbr.Surrogate(init_seed=0, max_rows=512)
+    s.set_params(v)
+    x, t = _batch(320, 6)  # five 64-row groups
+    loss, g = s.gradients(x, t)
+    y, cache = mlp.forward(p, x.astype(np.float64), bf=True)
+    L, dy = mlp.loss_and_grad_y(y, t.astype(np.float64))
+    gr = mlp.backward(p, cache, dy, bf=True)
+    assert loss == pytest.approx(L, rel=1e-3)
+    gg = mlp.unflatten(g.astype(np.float64))
+    for k in mlp.PARAM_ORDER:
+        rel = np.linalg.norm(gg[k] - gr[k]) / np.linalg.norm(gr[k])
+        print(f"{k}: grad rel err {rel:.3g}")
+        assert rel <= 1e-2, k
+    # the bfloat16 roundings are where the oracle puts them: against the pure-FP64 gradient the
+    # difference is of bfloat16 size, far above the emulation's agreement for the hidden weights
+    y64, c64 = mlp.forward(p, x.astype(np.float64))
+    g64 = mlp.backward(p, c64, mlp.loss_and_grad_y(y64, t.astype(np.float64))[1])
+    rel64 = np.linalg.norm(gg["W3"] - g64["W3"]) / np.linalg.norm(g64["W3"])
+    rel_bf = np.linalg.norm(gg["W3"] - gr["W3"]) / np.linalg.norm(gr["W3"])
+    print(f"W3 vs FP64 {rel64:.3g}, vs bf16 emulation {rel_bf:.3g}")
+    assert rel_bf < rel64
+    s.close()
+
+
+def test_adam_steps_match_oracle(torch):
+    v, p = _params32(13)
+    s = pbr.Surrogate(init_seed=0, max_rows=256)
+    s.set_params(v)
+    x, t = _batch(128, 7)
+    w = mlp.flatten(p)
+    m = np.zeros_like(w)
+    q = np.zeros_like(w)
+    for step in range(1, 4):
+        s.adam_step(x, t, 1e-3, step)
+        pp = mlp.unflatten(w)
+        y, cache = mlp.forward(pp, x.astype(np.float64), bf=True)
+        g = mlp.flatten(mlp.backward(pp, cache, mlp.loss_and_grad_y(y, t.astype(np.float64))[1], bf=True))
+        w, m, q = mlp.adam_step(w, g, m, q, step, lr=1e-3)
+    got = s.params().astype(np.float64)
+    d_gpu, d_orc = got - v.astype(np.float64), w - v.astype(np.float64)
+    rel = np.linalg.norm(d_gpu - d_orc) / np.linalg.norm(d_orc)
+    print(f"3 Adam steps: update rel err {rel:.3g}")
+    assert rel <= 1e-2
+    s.close()
+
+
+def test_argument_errors(torch):
+    s = pbr.Surrogate(init_seed=0, max_rows=128)
+    x, t = _batch(100, 1)
+    with pytest.raises(pbr.PbrError, match="multiple of 64"):
+        s.gradients(x, t)
+    with pytest.raises(pbr.PbrError, match="expected 200710"):
+        s.set_params(np.zeros(10, np.float32))
+    with pytest.raises(pbr.PbrError, match="not trained"):
+        s.tiles = 1
+        s.tile_map()
+    r = pbr.Renderer(rays_per_chunk=1 << 12)
+    with pytest.raises(pbr.PbrError, match="not trained"):
+        s.attach(r)
+    s.close()
+    r.close()
+
+
+def _tiny_renderer(sc, chunk=1 << 18):
+    r = pbr.Renderer(rays_per_chunk=chunk)
+    r.set_density_field(inputs.density(sc), sc.origin, sc.spacing, sc.K, sc.rho_inf)
+    r.set_optics(sc.z_lens, sc.focal_length, sc.f_number, sc.thickness, sc.n_glass, sc.clear_radius, sc.z_focus)
+    r.set_sensor(sc.width, sc.height, sc.pitch, sc.z_sensor, sc.wavelength, sc.sigma_px, sc.dtau_with_pi)
+    return r
+
+
+def test_surrogate_in_the_trace(torch):
+    """Gaussian-bump BOS scene (32^3): train on 2e5 tracer rays, validate on 1e5 others, then render
+    5e5 unseen rays with and without the surrogate."""
+    sc = inputs.tiny_bos()
+    r = _tiny_renderer(sc)
+    tr = inputs.sources(sc.replace(n_src=2000, src_seed=501))
+    va = inputs.sources(sc.replace(n_src=1000, src_seed=502))
+    s = pbr.Surrogate(init_seed=3, max_rows=1 << 16)
+    rep = s.train(r, tr, va, 100, train_seed=50, val_seed=52, ds=sc.ds, batch=2048, epochs=30,
+                  lr_max=2e-3, lr_min=2e-5, tol_px=0.01, tiles=16, min_tile_samples=8)
+    print("train report:", rep)
+    assert rep["train_samples"] > 100000 and rep["val_samples"] > 50000
+    assert rep["loss_last_epoch"] < 0.05 * rep["loss_first_epoch"]
+    ok, err = s.tile_map()
+    print("eligible tiles", int(ok.sum()), "of", ok.size)
+    assert rep["eligible_tiles"] == int(ok.sum()) > 0
+    assert np.all(err[ok.astype(bool)] <= 0.01)
+    assert rep["val_max_eligible_px"] <= 0.01
+
+    ev = inputs.sources(sc.replace(n_src=5000, src_seed=503))
+    n_rays = 5000 * 100
+    r.set_exit_recording(0, 1, n_rays)
+    st_t = r.emit_and_trace(ev, 100, 51, sc.ds, pbr.PBR_CLEAR_FIRST | pbr.PBR_RECORD_EXITS, stats=True)
+    img_t = pbr.u64_image_to_numpy(r.read_image()).astype(np.float64)
+    rec_t = r.read_ray_exits()
+    s.attach(r)
+    st_s = r.emit_and_trace(ev, 100, 51, sc.ds, pbr.PBR_CLEAR_FIRST | pbr.PBR_RECORD_EXITS | pbr.PBR_SURROGATE,
+                            stats=True)
+    img_s = pbr.u64_image_to_numpy(r.read_image()).astype(np.float64)
+    rec_s = r.read_ray_exits()
+    print("tracer", st_t, "\nsurrogate", st_s)
+    assert st_s["surrogate_rays"] > 0
+    assert sum(st_s["status"]) == n_rays
+    surr = (rec_s["entered"] == 1) & (rec_s["n_steps"] == 0) & (rec_t["n_steps"] > 0)
+    assert int(surr.sum()) == st_s["surrogate_rays"]
+    both = surr & (rec_s["status"] == 0) & (rec_t["status"] == 0)
+    e = np.hypot(*(rec_s["sensor_px"][both] - rec_t["sensor_px"][both]).T)
+    print(f"surrogate rays {surr.sum()}: exit error vs tracer median {np.median(e):.3g} px, "
+          f"p99 {np.quantile(e, 0.99):.3g}, max {e.max():.3g}")
+    assert np.quantile(e, 0.99) <= 0.01
+    # rays outside eligible tiles are traced exactly as without the surrogate
+    rest = ~surr
+    assert np.array_equal(rec_s["sensor_px"][rest], rec_t["sensor_px"][rest])
+    rel = np.linalg.norm(img_s - img_t) / np.linalg.norm(img_t)
+    print(f"image rel L2 surrogate vs tracer {rel:.3g}")
+    assert rel < 1e-2
+    # changing the scene detaches the surrogate's validity
+    r.set_optics(sc.z_lens, sc.focal_length, sc.f_number, sc.thickness, sc.n_glass, sc.clear_radius, sc.z_focus)
+    with pytest.raises(pbr.PbrError, match="no longer matches"):
+        r.emit_and_trace(ev, 100, 51, sc.ds, pbr.PBR_CLEAR_FIRST | pbr.PBR_SURROGATE)
+    s.close()
+    r.close()
