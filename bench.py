@@ -74,8 +74,12 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="turbulence_bos_128", choices=["turbulence_bos_128", "batch64"],
-                    help="batch64: the 64 uneven images of inputs.batch_scenes in one graph-captured batch")
+    ap.add_argument("--workload", default="turbulence_bos_128",
+                    choices=["turbulence_bos_128", "batch64", "surrogate256"],
+                    help="batch64: the 64 uneven images of inputs.batch_scenes in one graph-captured batch; "
+                         "surrogate256: train the ray surrogate on a 256^3 turbulence field, then 1e9 rays "
+                         "with and without it")
+    ap.add_argument("--epochs", type=int, default=8, help="surrogate256: training epochs")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy a 1 GiB device buffer 4 times (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -99,6 +103,8 @@ def main():
 
     if args.workload == "batch64":
         return bench_batch(args)
+    if args.workload == "surrogate256":
+        return bench_surrogate(args)
     scene = inputs.turbulence_bos()
     rho = inputs.density(scene)
     src = inputs.sources(scene)
@@ -211,6 +217,97 @@ def bench_batch(args):
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
                      "kernel": "whole batch graph (emit + persistent k_box_batch + finish)",
                      "graph_ms_per_step": run_ms / args.steps, "flops_per_rkn_step": FLOPS_PER_STEP},
+    }
+    print(json.dumps(out), flush=True)
+
+
+MLP_FLOPS_PER_ROW = 2 * (6 * 256 + 3 * 256 * 256 + 256 * 6)  # forward pass, multiply-adds x 2
+PEAK_BF16_TFLOPS = 2500.0  # MI355X dense bfloat16 matrix cores, published
+
+
+def bench_surrogate(args):
+    """Surrogate workload: train on 1e7 tracer rays (1e6 validation rays fix the fallback tiles),
+    then render the same 1e9 evaluation rays with the plain tracer and with the surrogate, and
+    compare a sample of their sensor hits ray by ray."""
+    import numpy as np
+    import torch
+    from paper_1812_05902_amd import inputs, pbr
+
+    ev, tr, va = inputs.surrogate_turbulence()
+    t0 = time.perf_counter()
+    rho = inputs.density(ev)
+    r = pbr.Renderer.from_scene(ev, rho=rho)
+    src_ev = torch.as_tensor(inputs.sources(ev), device=r.device).contiguous()
+    src_tr = inputs.sources(tr)
+    src_va = inputs.sources(va)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    s = pbr.Surrogate(init_seed=7, max_rows=1 << 18)
+    rep = s.train(r, src_tr, src_va, tr.rays_per_src, tr.ray_seed, va.ray_seed, ev.ds, batch=4096,
+                  epochs=args.epochs, lr_max=1e-3, lr_min=1e-5, tol_px=0.01, tiles=64, min_tile_samples=8)
+    print(json.dumps({"surrogate_training": rep}), flush=True)
+
+    def render(flags, stats=True):
+        return r.emit_and_trace(src_ev, ev.rays_per_src, ev.ray_seed, ev.ds, pbr.PBR_CLEAR_FIRST | flags,
+                                stats=stats)
+
+    s.attach(r)
+    for _ in range(args.warmup):
+        render(pbr.PBR_SURROGATE, stats=False)
+    torch.cuda.synchronize()
+    res = {}
+    for name, flags in (("tracer", 0), ("surrogate", pbr.PBR_SURROGATE)):
+        t1 = time.perf_counter()
+        st = None
+        for _ in range(args.steps):
+            st = render(flags)
+        torch.cuda.synchronize()
+        res[name] = (time.perf_counter() - t1, st)
+        print(f"{name}: {res[name][0] / args.steps:.3f} s per image", file=sys.stderr, flush=True)
+    # exit error on a sample of the rays: every 1000th ray of the image, both ways
+    stride = 1000
+    r.set_exit_recording(0, stride, ev.n_rays // stride)
+    render(pbr.PBR_RECORD_EXITS, stats=False)
+    rec_t = r.read_ray_exits()
+    render(pbr.PBR_RECORD_EXITS | pbr.PBR_SURROGATE, stats=False)
+    rec_s = r.read_ray_exits()
+    surr = (rec_s["entered"] == 1) & (rec_s["n_steps"] == 0) & (rec_t["n_steps"] > 0)
+    both = surr & (rec_s["status"] == 0) & (rec_t["status"] == 0)
+    e = np.hypot(*(rec_s["sensor_px"][both] - rec_t["sensor_px"][both]).T) if both.any() else np.zeros(1)
+    # matrix-core rate of the network alone: one forward pass over 2^22 rows
+    x = torch.rand(1 << 22, 6, device=r.device) * 2 - 1
+    y = torch.empty_like(x)
+    pbr.pbr_surrogate_forward(s.h, x, y)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        pbr.pbr_surrogate_forward(s.h, x, y)
+    e1.record()
+    torch.cuda.synchronize()
+    fwd_ms = e0.elapsed_time(e1) / 5
+    achieved = MLP_FLOPS_PER_ROW * x.shape[0] / (fwd_ms * 1e-3) / 1e12
+    wall_t, st_t = res["tracer"]
+    wall_s, st_s = res["surrogate"]
+    out = {
+        "metric": "rays/sec on 1 MI355X (trace+lens+sensor); surrogate vs tracer at <=0.01 px",
+        "value": ev.n_rays * args.steps / wall_s, "unit": "rays/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": wall_s / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16+f32", "data": "synthetic",
+        "config": {"workload": "surrogate256", "grid": "256^3", "rays_per_image": ev.n_rays,
+                   "train_rays": tr.n_rays, "val_rays": va.n_rays, "tiles": "64x64", "tol_px": 0.01,
+                   "epochs": args.epochs, "setup_s": setup_s},
+        "tracer_rays_per_s": ev.n_rays * args.steps / wall_t,
+        "speedup_vs_tracer": wall_t / wall_s,
+        "surrogate_ray_fraction": st_s["surrogate_rays"] / ev.n_rays,
+        "eligible_tiles": rep["eligible_tiles"],
+        "exit_error_px_vs_tracer": {"rays_compared": int(both.sum()), "median": float(np.median(e)),
+                                    "p99": float(np.quantile(e, 0.99)), "max": float(e.max())},
+        "training": {k: rep[k] for k in ("train_samples", "steps", "loss_first_epoch", "loss_last_epoch",
+                                         "train_ms", "val_median_px", "val_p99_px")},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_BF16_TFLOPS, "traffic": None,
+                     "kernel": "surrogate forward (all layers)", "rows": int(x.shape[0]),
+                     "ms_per_pass": fwd_ms, "flops_per_row": MLP_FLOPS_PER_ROW},
     }
     print(json.dumps(out), flush=True)
 

@@ -393,7 +393,8 @@ typedef struct pbr_surrogate_report {
 
 /* Creates a network on device (current device if -1) with weights and biases drawn uniformly from
  * +-1/sqrt(fan_in) (SplitMix64 of init_seed), zero Adam moments, and buffers for max_rows rows per
- * pass (rounded up to 64; 65536 if 0).  hip_stream: stream for all work (NULL: a private stream).
+ * pass (rounded up to 64; 65536 if 0).  hip_stream: stream for the calls below (NULL = the null
+ * stream); training and the trace hook enqueue on the context's stream instead.
  * Errors: ARG, HIP (see pbr_surrogate_last_error(NULL) when *out is NULL). */
 int pbr_surrogate_create(pbr_surrogate **out, int device, void *hip_stream, uint64_t init_seed, int64_t max_rows);
 void pbr_surrogate_destroy(pbr_surrogate *s);

@@ -270,6 +270,107 @@ __global__ void __launch_bounds__(256) k_loss_mean(const float *__restrict__ par
     if (threadIdx.x == 0) *out = s[0] * inv_count;
 }
 
+// Whole forward pass in one launch for inference: a block takes 128 rows and keeps their
+// activations in LDS (bf16, rows padded to 264 elements so that the 16 rows one matrix-core
+// operand read touches fall in distinct banks); layer 1 in FP32 by the threads, each hidden layer
+// as a 128 x 256 x 256 product in which wave w owns output columns 64 w .. 64 w + 63 of all 128
+// rows (8 x 4 tiles of 16 x 16, weights read once per block from L2), the output layer as 128 x 16
+// (columns 6 .. 15 zero) by the four waves over 32 rows each.  Same instructions, k order, bias,
+// activation and roundings as the layer-by-layer kernels, so the outputs agree bit for bit.
+constexpr int kFuseRows = 128, kActStride = kHidden + 8;
+
+__global__ void __launch_bounds__(256, 2) k_mlp_infer(const float *__restrict__ x, int64_t rows,
+                                                      const unsigned long long *__restrict__ live,
+                                                      const float *__restrict__ params,
+                                                      const unsigned short *__restrict__ w2,
+                                                      const unsigned short *__restrict__ w3,
+                                                      const unsigned short *__restrict__ w4,
+                                                      const unsigned short *__restrict__ w5, float *__restrict__ y)
+{
+    __shared__ __attribute__((aligned(16))) unsigned short act[kFuseRows * kActStride];
+    __shared__ float xs[kFuseRows * kIn];
+    const int64_t row0 = (int64_t)blockIdx.x * kFuseRows;
+    int64_t nrow = rows;
+    if (live) nrow = (int64_t)(*live < (unsigned long long)rows ? *live : (unsigned long long)rows);
+    if (row0 >= nrow) return;
+    const int64_t nblk = nrow - row0 < kFuseRows ? nrow - row0 : kFuseRows;
+    for (int q = threadIdx.x; q < kFuseRows * kIn; q += 256) xs[q] = q < nblk * kIn ? x[row0 * kIn + q] : 0.0f;
+    __syncthreads();
+    {   // layer 1, FP32: thread n owns unit n of every row
+        const int n = threadIdx.x;
+        float w[kIn];
+#pragma unroll
+        for (int k = 0; k < kIn; ++k) w[k] = params[kOffW1 + n * kIn + k];
+        const float bn = params[kOffB1 + n];
+        for (int m = 0; m < kFuseRows; ++m) {
+            float z = bn;
+#pragma unroll
+            for (int k = 0; k < kIn; ++k) z += xs[m * kIn + k] * w[k];
+            act[m * kActStride + n] = bf16_bits(gelu(z));
+        }
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r = lane & 15, kg = lane >> 4;
+    const unsigned short *wl[3] = {w2, w3, w4};
+    const int boff[3] = {kOffB2, kOffB3, kOffB4};
+    for (int l = 0; l < 3; ++l) {
+        floatx4 acc[8][4];
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+        const unsigned short *W = wl[l] + (size_t)(wave * 64 + r) * kHidden + 8 * kg;
+        for (int k0 = 0; k0 < kHidden; k0 += 32) {
+            bf16x8 fw[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) fw[j] = *(const bf16x8 *)(W + j * 16 * kHidden + k0);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const bf16x8 fa = *(const bf16x8 *)(act + (16 * i + r) * kActStride + 8 * kg + k0);
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, fw[j], acc[i][j], 0, 0, 0);
+            }
+        }
+        __syncthreads();  // every wave has read this layer's inputs
+        const float *bias = params + boff[l];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int n = wave * 64 + 16 * j + r;
+            const float bn = bias[n];
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    act[(16 * i + 4 * kg + t) * kActStride + n] = bf16_bits(gelu(acc[i][j][t] + bn));
+        }
+        __syncthreads();
+    }
+    {   // output layer: wave w takes rows 32 w .. 32 w + 31 against the 16 first (padded) rows of W5
+        floatx4 acc[2] = {floatx4{0.0f, 0.0f, 0.0f, 0.0f}, floatx4{0.0f, 0.0f, 0.0f, 0.0f}};
+        const unsigned short *W = w5 + (size_t)r * kHidden + 8 * kg;
+        for (int k0 = 0; k0 < kHidden; k0 += 32) {
+            const bf16x8 fw = *(const bf16x8 *)(W + k0);
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const bf16x8 fa = *(const bf16x8 *)(act + (32 * wave + 16 * i + r) * kActStride + 8 * kg + k0);
+                acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, fw, acc[i], 0, 0, 0);
+            }
+        }
+        if (r < kOut) {
+            const float bn = params[kOffB5 + r];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int m = 32 * wave + 16 * i + 4 * kg + t;
+                    if (m < nblk) y[(row0 + m) * kOut + r] = acc[i][t] + bn;
+                }
+        }
+    }
+}
+
 inline unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 template <int EPI>
@@ -363,6 +464,16 @@ int mlp_backward(const MlpDevice &d, const MlpBuffers &b, const float *x, const 
     hipLaunchKernelGGL(k_small_wgrad<false>, dim3(kHidden * kIn), dim3(256), 0, s, dz, kHidden, (const void *)x,
                        kIn, rows, d.grad + kOffW1);
     hipLaunchKernelGGL(k_colsum, dim3(kHidden), dim3(256), 0, s, dz, rows, kHidden, d.grad + kOffB1);
+    return (int)hipGetLastError();
+}
+
+int mlp_infer(const MlpDevice &d, const float *x, int64_t rows, float *y, hipStream_t s,
+              const unsigned long long *live)
+{
+    if (rows <= 0) return 0;
+    hipLaunchKernelGGL(k_mlp_infer, dim3((unsigned)((rows + kFuseRows - 1) / kFuseRows)), dim3(256), 0, s, x, rows,
+                       live, (const float *)d.params, (const unsigned short *)d.w2, (const unsigned short *)d.w3,
+                       (const unsigned short *)d.w4, (const unsigned short *)d.w5, y);
     return (int)hipGetLastError();
 }
 

@@ -50,6 +50,10 @@ int mlp_forward(const MlpDevice &d, const MlpBuffers &b, const float *x, int64_t
                 hipStream_t s, const unsigned long long *live = nullptr);
 int mlp_backward(const MlpDevice &d, const MlpBuffers &b, const float *x, const float *t, int64_t rows,
                  const float *y, hipStream_t s);
+// Inference forward pass in one launch (activations in LDS), any row count; live (device,
+// optional) caps the rows computed.  Outputs equal mlp_forward's bit for bit.
+int mlp_infer(const MlpDevice &d, const float *x, int64_t rows, float *y, hipStream_t s,
+              const unsigned long long *live = nullptr);
 // After mlp_backward: *out (device) = mean squared error of that batch.
 int mlp_loss_mean(const MlpBuffers &b, int64_t rows, float *out, hipStream_t s);
 int mlp_adam(const MlpDevice &d, float lr, int step, hipStream_t s);

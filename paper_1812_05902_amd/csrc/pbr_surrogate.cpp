@@ -21,7 +21,6 @@ using pbr::host::DeviceGuard;
 struct pbr_surrogate {
     int device = 0;
     hipStream_t stream = nullptr;
-    bool own_stream = false;
     std::string err;
     int64_t rows_cap = 0;
     std::vector<void *> allocs;
@@ -102,28 +101,6 @@ void init_params(uint64_t seed, std::vector<float> &p)
     }
 }
 
-// Forward pass over an arbitrary number of rows: whole 64-row groups straight from the caller's
-// buffers, a ragged tail through the surrogate's own padded buffers.
-int forward_rows(pbr_surrogate *s, const float *x, int64_t rows, float *y, hipStream_t st)
-{
-    int e;
-    for (int64_t off = 0; off < rows; off += s->rows_cap) {
-        const int64_t n = std::min(s->rows_cap, rows - off);
-        const int64_t full = n / 64 * 64;
-        if (full > 0 && (e = pbr::mlp_forward(s->d, s->b, x + off * 6, full, y + off * 6, false, st))) return e;
-        const int64_t tail = n - full;
-        if (tail > 0) {
-            if ((e = (int)hipMemcpyAsync(s->x, x + (off + full) * 6, (size_t)tail * 24, hipMemcpyDeviceToDevice, st)))
-                return e;
-            if ((e = pbr::launch_clear_u64((unsigned long long *)(s->x + tail * 6), (64 - tail) * 3, st))) return e;
-            if ((e = pbr::mlp_forward(s->d, s->b, s->x, 64, s->y, false, st))) return e;
-            if ((e = (int)hipMemcpyAsync(y + (off + full) * 6, s->y, (size_t)tail * 24, hipMemcpyDeviceToDevice, st)))
-                return e;
-        }
-    }
-    return 0;
-}
-
 int check_batch(pbr_surrogate *s, const float *x, const float *t, int64_t rows)
 {
     if (!x || !t) return sfail(s, PBR_ERR_ARG, "null input or target array");
@@ -161,7 +138,7 @@ int hook_run(void *self, const pbr::TraceParams &P, pbr::RayState *st, int64_t, 
         const int64_t m = std::min(s->rows_cap, n - off);
         if ((e = pbr::launch_clear_u64(s->count, 1, stream))) return e;
         if ((e = pbr::launch_surr_features(P, s->spec, st + off, m, s->x, s->idx, s->count, stream))) return e;
-        if ((e = pbr::mlp_forward(s->d, s->b, s->x, round64(m), s->y, false, stream, s->count))) return e;
+        if ((e = pbr::mlp_infer(s->d, s->x, m, s->y, stream, s->count))) return e;
         if ((e = pbr::launch_surr_apply(P, s->spec, s->y, s->idx, s->count, m, st + off, stream))) return e;
     }
     return 0;
@@ -213,15 +190,7 @@ int pbr_surrogate_create(pbr_surrogate **out, int device, void *hip_stream, uint
         if (!s) return sfail(nullptr, PBR_ERR_HIP, "out of host memory");
         s->device = device;
         s->rows_cap = max_rows == 0 ? 65536 : round64(max_rows);
-        if (hip_stream) {
-            s->stream = (hipStream_t)hip_stream;
-        } else {
-            if ((e = (int)hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking))) {
-                delete s;
-                return sfail(nullptr, PBR_ERR_HIP, "hipStreamCreate: %s", hipGetErrorString((hipError_t)e));
-            }
-            s->own_stream = true;
-        }
+        s->stream = (hipStream_t)hip_stream;  // NULL: the null stream
         const int64_t R = s->rows_cap, H = pbr::kHidden, P = pbr::kParams + 64;
         void *p;
         auto A = [&](size_t bytes) -> void * {
@@ -259,7 +228,6 @@ int pbr_surrogate_create(pbr_surrogate **out, int device, void *hip_stream, uint
         if (e) {
             const int r = sfail(nullptr, PBR_ERR_HIP, "hipMalloc: %s", hipGetErrorString((hipError_t)e));
             free_all(s);
-            if (s->own_stream) (void)hipStreamDestroy(s->stream);
             delete s;
             return r;
         }
@@ -288,7 +256,6 @@ void pbr_surrogate_destroy(pbr_surrogate *s)
         DeviceGuard g(s->device);
         (void)hipStreamSynchronize(s->stream);
         free_all(s);
-        if (s->own_stream) (void)hipStreamDestroy(s->stream);
     } catch (...) {
     }
     delete s;
@@ -345,7 +312,7 @@ int pbr_surrogate_forward(pbr_surrogate *s, const float *x_dev, int64_t rows, fl
     if (rows > 0 && (!x_dev || !y_dev)) return sfail(s, PBR_ERR_ARG, "null input or output array");
     DeviceGuard g(s->device);
     if (!g.ok) return sfail(s, PBR_ERR_HIP, "hipSetDevice failed");
-    const int e = forward_rows(s, x_dev, rows, y_dev, s->stream);
+    const int e = pbr::mlp_infer(s->d, x_dev, rows, y_dev, s->stream);
     if (e) return shf(s, e, "forward");
     return PBR_OK;
     SURR_GUARD_END
@@ -576,11 +543,9 @@ int pbr_surrogate_train(pbr_surrogate *s, pbr_ctx *ctx, const float *train_src_d
         (e = pbr::launch_clear_u64((unsigned long long *)tile_cnt, (nt + 1) / 2, st)))
         return shf(s, e, "clear tiles");
     for (int64_t off = 0; off < n_val; off += s->rows_cap) {
-        const int64_t n = std::min(s->rows_cap, n_val - off), rp = round64(n);
+        const int64_t n = std::min(s->rows_cap, n_val - off);
         if ((e = pbr::launch_surr_gather(spec, vas + off, nullptr, n, s->x, s->t, st))) return shf(s, e, "gather");
-        if (rp > n && (e = pbr::launch_clear_u64((unsigned long long *)(s->x + n * 6), (rp - n) * 3, st)))
-            return shf(s, e, "pad");
-        if ((e = pbr::mlp_forward(s->d, s->b, s->x, rp, s->y, false, st))) return shf(s, e, "validation forward");
+        if ((e = pbr::mlp_infer(s->d, s->x, n, s->y, st))) return shf(s, e, "validation forward");
         if ((e = pbr::launch_surr_validate(P, spec, vas + off, s->y, n, err + off, tile_err, tile_cnt, st)))
             return shf(s, e, "validate");
     }

@@ -136,6 +136,18 @@ def tomo_piv_shock(n: int = 512, n_src: int = 100_000, rays_per_src: int = 10_00
         width=2048, height=2048, pitch=10e-6, ds=1e-4)
 
 
+def surrogate_turbulence():
+    """Surrogate workload: the turbulence BOS scene on a 256^3 grid (field seed 5, node spacing
+    0.39 mm), ds = 0.1 mm.  Returns (evaluation, training, validation) scenes that differ only in
+    their dots: 1e6 dots x 1000 rays for evaluation (1e9 rays, ray seed 51), 1e4 x 1000 for
+    training (1e7 rays, seed 50), 1e3 x 1000 for validation (1e6 rays, seed 52)."""
+    ev = turbulence_bos(n=256, seed=5, n_src=1_000_000, rays_per_src=1000).replace(
+        name="surrogate_turbulence_256", src_seed=510, ray_seed=51)
+    tr = ev.replace(n_src=10_000, src_seed=500, ray_seed=50)
+    va = ev.replace(n_src=1_000, src_seed=520, ray_seed=52)
+    return ev, tr, va
+
+
 def batch_scenes(n_images: int = 64, seed_base: int = 4000):
     """Many images of uneven sizes: particle counts log-uniform in [1e3, 1e5], rays per particle
     log-uniform in [500, 1e4], grids 64^3 / 128^3 / 256^3 holding a Gaussian bump or a

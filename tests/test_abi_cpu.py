@@ -262,3 +262,32 @@ def test_derived_optics_match_oracle(lib, make):
     assert d.magnification == pytest.approx(oc.M, rel=1e-10)
     assert d.sigma_px == pytest.approx(oc.sigma_px, rel=1e-10)
     assert d.footprint_r == oc.r_fp
+
+
+def test_surrogate_entry_points_validate_before_device_work(lib):
+    h = C.c_void_p()
+    assert lib.pbr_surrogate_create(C.byref(h), 0, None, 1, -5) == pbr.PBR_ERR_ARG
+    assert h.value is None
+    assert b"max_rows" in lib.pbr_surrogate_last_error(None)
+    assert lib.pbr_surrogate_create(None, 0, None, 1, 0) == pbr.PBR_ERR_ARG
+    for fn, args in (("pbr_surrogate_set_params", (None, 0)), ("pbr_surrogate_get_params", (None, 0)),
+                     ("pbr_surrogate_forward", (None, 0, None)),
+                     ("pbr_surrogate_gradients", (None, None, 64, None, None)),
+                     ("pbr_surrogate_tile_map", (None, None, 0))):
+        assert getattr(lib, fn)(None, *args) == pbr.PBR_ERR_ARG, fn
+    lib.pbr_surrogate_destroy(None)
+    ctx = _host_ctx(lib)
+    try:
+        assert lib.pbr_set_surrogate(ctx, None) == pbr.PBR_OK  # detaching needs nothing
+        # tracing with PBR_SURROGATE and nothing attached is a state error, found before any launch
+        assert _set_field(lib, ctx) == pbr.PBR_OK
+        o = _optics(z_front_vertex=0.5, focal_length=0.05, f_number=8.0)
+        assert lib.pbr_set_optics(ctx, C.byref(o)) == pbr.PBR_OK
+        s = _sensor(width=64, height=64, pitch=20e-6)
+        assert lib.pbr_set_sensor(ctx, C.byref(s), FAKE) == pbr.PBR_OK
+        st = pbr.pbr_stats()
+        code = lib.pbr_emit_and_trace(ctx, FAKE, 1, 1, 1, 1e-4, pbr.PBR_SURROGATE, C.byref(st))
+        assert code == pbr.PBR_ERR_STATE
+        assert b"no surrogate attached" in lib.pbr_last_error(ctx)
+    finally:
+        lib.pbr_destroy(ctx)
