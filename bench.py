@@ -75,7 +75,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="turbulence_bos_128",
-                    choices=["turbulence_bos_128", "batch64", "surrogate256"],
+                    choices=["turbulence_bos_128", "batch64", "surrogate256", "tomo_piv_512"],
                     help="batch64: the 64 uneven images of inputs.batch_scenes in one graph-captured batch; "
                          "surrogate256: train the ray surrogate on a 256^3 turbulence field, then 1e9 rays "
                          "with and without it")
@@ -105,6 +105,8 @@ def main():
         return bench_batch(args)
     if args.workload == "surrogate256":
         return bench_surrogate(args)
+    if args.workload == "tomo_piv_512":
+        return bench_tomo(args)
     scene = inputs.turbulence_bos()
     rho = inputs.density(scene)
     src = inputs.sources(scene)
@@ -217,6 +219,64 @@ def bench_batch(args):
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
                      "kernel": "whole batch graph (emit + persistent k_box_batch + finish)",
                      "graph_ms_per_step": run_ms / args.steps, "flops_per_rkn_step": FLOPS_PER_STEP},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_tomo(args):
+    """Tomo-PIV scale: 512^3 shock field, 1e5 particles x 1e4 rays = 1e9 rays, 2048^2 sensor with
+    16-bit readout inside the step; FP32 integration, and again with FP64 steps in the bricks the
+    calibration flags (1e-3 px)."""
+    import torch
+    from paper_1812_05902_amd import inputs, pbr
+
+    sc = inputs.tomo_piv_shock()
+    t0 = time.perf_counter()
+    rho = inputs.density(sc)
+    r = pbr.Renderer.from_scene(sc, rho=rho)
+    del rho
+    src = torch.as_tensor(inputs.sources(sc), device=r.device).contiguous()
+    out16 = torch.empty(sc.height, sc.width, dtype=torch.int16, device=r.device)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    cal = r.calibrate_precision(sc.ds, tol_px=1e-3)
+
+    def step(flags, stats):
+        st = r.emit_and_trace(src, sc.rays_per_src, sc.ray_seed, sc.ds, pbr.PBR_CLEAR_FIRST | flags, stats=stats)
+        pbr.pbr_read_image(r.ctx, pbr.PBR_FMT_U16, out16, 0.0)
+        return st
+
+    res = {}
+    for name, flags in (("fp32", 0), ("shock_fp64", pbr.PBR_PREC_SHOCK_FP64)):
+        for _ in range(args.warmup):
+            step(flags, False)
+        torch.cuda.synchronize()
+        box_ms, launches, steps_total = 0.0, 0, 0
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            st = step(flags, True)
+            box_ms += st["box_ms"]
+            launches += st["box_launches"]
+            steps_total += st["rkn_steps"]
+        torch.cuda.synchronize()
+        res[name] = (time.perf_counter() - t1, box_ms, launches, steps_total, st)
+    wall, box_ms, launches, steps_total, st = res["fp32"]
+    achieved = steps_total * FLOPS_PER_STEP / (box_ms * 1e-3) / 1e12
+    out = {
+        "metric": "rays/sec on 1 MI355X (trace+lens+sensor)", "value": sc.n_rays * args.steps / wall,
+        "unit": "rays/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "tomo_piv_512", "grid": "512^3", "n_src": sc.n_src, "rays_per_src": sc.rays_per_src,
+                   "rays_per_image": sc.n_rays, "sensor": f"{sc.width}x{sc.height} u16", "ds_m": sc.ds,
+                   "mean_rkn_steps_per_ray": steps_total / args.steps / sc.n_rays, "setup_s": setup_s},
+        "shock_fp64": {"rays_per_s": sc.n_rays * args.steps / res["shock_fp64"][0],
+                       "fp64_bricks": cal["n_fp64"], "steep_bricks": cal["n_steep"],
+                       "calibration_max_err_px": cal["max_err_px"],
+                       "rkn_steps_fp64": res["shock_fp64"][4]["rkn_steps_fp64"]},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None, "kernel": "k_box32",
+                     "kernel_ms_per_launch": box_ms / launches, "flops_per_rkn_step": FLOPS_PER_STEP},
     }
     print(json.dumps(out), flush=True)
 

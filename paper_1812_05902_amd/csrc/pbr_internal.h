@@ -133,9 +133,11 @@ constexpr int kMoments = 16;  // count, sum t[6], sum t^2[6], sum u_x^2, sum u_y
 int launch_surr_samples(const TraceParams &p, const SurrogateSpec &sp, const RayState *st, int64_t first,
                         int64_t n, SurrogateSample *out, hipStream_t s);
 // After emission (entry states st[0 .. n)): the rays in eligible tiles are compacted (in no fixed
-// order) into rows 0 .. *count of x (features) and idx (ray index in st); *count must start at zero.
-int launch_surr_features(const TraceParams &p, const SurrogateSpec &sp, const RayState *st, int64_t n,
-                         float *x, int *idx, unsigned long long *count, hipStream_t s);
+// order) into rows 0 .. *count of x (features) and idx (ray index in st); the other rays that
+// entered the box are appended to tlist (index off + i) behind *tcount.  Counters start at zero.
+int launch_surr_features(const TraceParams &p, const SurrogateSpec &sp, const RayState *st, int64_t n, int64_t off,
+                         float *x, int *idx, unsigned long long *count, int *tlist, unsigned long long *tcount,
+                         hipStream_t s);
 // Writes the predicted exit state (network output y, standardised) of rows 0 .. *count (at most
 // cap) into st[idx[row]].
 int launch_surr_apply(const TraceParams &p, const SurrogateSpec &sp, const float *y, const int *idx,
@@ -152,9 +154,17 @@ int launch_surr_gather(const SurrogateSpec &sp, const SurrogateSample *smp, cons
 // Per-block sums (kMoments doubles per block) over valid samples; returns the blocks used.
 int launch_surr_moments(const SurrogateSample *smp, int64_t n, double *part, int *blocks, hipStream_t s);
 
-// Optional step between emission and integration of a chunk (the surrogate).
+// Rays of a chunk left for the integration kernels: st[idx[k]] for k < *count (device values).
+struct TraceList {
+    const int *idx;
+    const unsigned long long *count;
+};
+
+// Optional step between emission and integration of a chunk (the surrogate).  May set *list:
+// then only the listed rays are integrated.
 struct ChunkHook {
-    int (*run)(void *self, const TraceParams &p, RayState *st, int64_t first, int64_t n, hipStream_t s);
+    int (*run)(void *self, const TraceParams &p, RayState *st, int64_t first, int64_t n, hipStream_t s,
+               TraceList *list);
     void *self;
 };
 

@@ -35,6 +35,8 @@ struct pbr_surrogate {
     pbr::SurrogateSpec spec{};
     unsigned char *tile_ok_dev = nullptr;
     int64_t tile_cap = 0;
+    int *tlist = nullptr;  // rays left to the tracer in the current chunk
+    int64_t tlist_cap = 0;
     std::vector<unsigned char> tile_ok;
     std::vector<float> tile_err;
 };
@@ -129,18 +131,26 @@ int trace_samples(pbr_surrogate *s, pbr_ctx *ctx, pbr::TraceParams P, const pbr:
     return PBR_OK;
 }
 
-// Per-chunk hook of a trace: the rays of eligible tiles through the network, in groups of rows_cap.
-int hook_run(void *self, const pbr::TraceParams &P, pbr::RayState *st, int64_t, int64_t n, hipStream_t stream)
+// Per-chunk hook of a trace: the rays of eligible tiles through the network, in groups of rows_cap;
+// the rest of the rays that entered the box are listed for the integration kernel.
+int hook_run(void *self, const pbr::TraceParams &P, pbr::RayState *st, int64_t, int64_t n, hipStream_t stream,
+             pbr::TraceList *list)
 {
     pbr_surrogate *s = (pbr_surrogate *)self;
+    if (n > s->tlist_cap) return (int)hipErrorInvalidValue;  // sized when the trace was validated
     int e;
+    if ((e = pbr::launch_clear_u64(s->count + 1, 1, stream))) return e;
     for (int64_t off = 0; off < n; off += s->rows_cap) {
         const int64_t m = std::min(s->rows_cap, n - off);
         if ((e = pbr::launch_clear_u64(s->count, 1, stream))) return e;
-        if ((e = pbr::launch_surr_features(P, s->spec, st + off, m, s->x, s->idx, s->count, stream))) return e;
+        if ((e = pbr::launch_surr_features(P, s->spec, st + off, m, off, s->x, s->idx, s->count, s->tlist,
+                                           s->count + 1, stream)))
+            return e;
         if ((e = pbr::mlp_infer(s->d, s->x, m, s->y, stream, s->count))) return e;
         if ((e = pbr::launch_surr_apply(P, s->spec, s->y, s->idx, s->count, m, st + off, stream))) return e;
     }
+    list->idx = s->tlist;
+    list->count = s->count + 1;
     return 0;
 }
 
@@ -155,6 +165,14 @@ int surrogate_hook(pbr_ctx *ctx, ChunkHook *out)
     if (!s) return fail(ctx, PBR_ERR_STATE, "PBR_SURROGATE set but no surrogate attached (pbr_set_surrogate)");
     if (!s->trained || s->ctx_uid != ctx->uid || s->scene_version != ctx->scene_version)
         return fail(ctx, PBR_ERR_STATE, "the attached surrogate no longer matches this context's field, optics or sensor");
+    if (ctx->ray_chunk > s->tlist_cap) {
+        DeviceGuard g(s->device);
+        void *q = nullptr;
+        const int e = dmalloc(s, &q, (size_t)ctx->ray_chunk * sizeof(int));
+        if (e) return hip_fail(ctx, e, "hipMalloc(surrogate trace list)");
+        s->tlist = (int *)q;
+        s->tlist_cap = ctx->ray_chunk;
+    }
     out->run = hook_run;
     out->self = s;
     return PBR_OK;

@@ -35,7 +35,7 @@ template <> __device__ __forceinline__ double ffloor<double>(double x) { return 
 // from memory when it lies in another cell (about once per cell crossing, since the three stage
 // points of a step run ahead of the ray).
 struct CellCache {
-    int key;         // linear index of the cached cell, -1 = none
+    int ix, iy, iz;  // the cached cell, ix = -1: none
     float4 c[kCellFloat4];
 };
 
@@ -70,12 +70,15 @@ __device__ __forceinline__ F sample_D(const TraceParams &P, CellCache &cc, const
         ic[a] = i;
         w[a] = t;
     }
-    const int key = (ic[2] * (P.ny - 1) + ic[1]) * (P.nx - 1) + ic[0];
-    if (key != cc.key) {
+    // compare cell coordinates (no index arithmetic unless the cell changed)
+    if ((ic[0] != cc.ix) | (ic[1] != cc.iy) | (ic[2] != cc.iz)) {
+        const int key = (ic[2] * (P.ny - 1) + ic[1]) * (P.nx - 1) + ic[0];
         const float4 *p = P.cells + (size_t)key * kCellFloat4;
 #pragma unroll
         for (int m = 0; m < kCellFloat4; ++m) cc.c[m] = p[m];
-        cc.key = key;
+        cc.ix = ic[0];
+        cc.iy = ic[1];
+        cc.iz = ic[2];
     }
     const F x = w[0], y = w[1], z = w[2];
     F v[4];
@@ -151,12 +154,15 @@ __device__ __forceinline__ int trace_box(const TraceParams &P, CellCache &cc, in
     for (;;) {
         // cheap test first: does the straight line of a full step reach a face?  (distances in
         // cell units against the per-step displacement; no division)
+        // (bitwise, not short-circuit: one branch for the whole test instead of one per clause)
         bool near = false;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             const F v = g[a] * (Tr[a] + dT[a]);
             const F fa = (F)fd[a];
-            near = near || (v > (F)0 && (F)(last[a] - c[a]) - fa <= v) || (v < (F)0 && (F)(-c[a]) - fa >= v);
+            const bool up = (v > (F)0) & ((F)(last[a] - c[a]) - fa <= v);
+            const bool down = (v < (F)0) & ((F)(-c[a]) - fa >= v);
+            near = near | up | down;
         }
         if (near) {
             F lam = (F)3.0e38;
@@ -204,6 +210,7 @@ __device__ __forceinline__ int trace_box(const TraceParams &P, CellCache &cc, in
 __device__ __forceinline__ bool cap_hit(const double Pp[3], const double u[3], double zv,
                                         double Rs, double H[3], double N[3])
 {
+    #pragma clang fp contract(off)
     const double qx = Pp[0], qy = Pp[1], qz = Pp[2] - zv;
     const double b = qx * u[0] + qy * u[1] + qz * u[2] - Rs * u[2];
     const double cc = qx * qx + qy * qy + qz * qz - 2.0 * Rs * qz;
@@ -227,6 +234,7 @@ __device__ __forceinline__ bool cap_hit(const double Pp[3], const double u[3], d
 __device__ __forceinline__ bool snell(const double u[3], const double N[3], double n1, double n2,
                                       double out[3])
 {
+    #pragma clang fp contract(off)
     const double eta = n1 / n2;
     const double ci = -(u[0] * N[0] + u[1] * N[1] + u[2] * N[2]);
     const double k = 1.0 - eta * eta * (1.0 - ci * ci);
@@ -242,6 +250,7 @@ __device__ __forceinline__ bool snell(const double u[3], const double N[3], doub
 __device__ __forceinline__ int optics_to_sensor(const TraceParams &P, const double R[3], const double u[3],
                                 double *xpx, double *ypx)
 {
+    #pragma clang fp contract(off)
     if (!(u[2] > 0.0)) return PBR_RAY_MISSED;
     const double s = (P.z_lens - R[2]) / u[2];
     double A[3] = {R[0] + s * u[0], R[1] + s * u[1], 0.0};
@@ -273,6 +282,9 @@ __device__ __forceinline__ void atomic_add_u64(unsigned long long *p, unsigned l
 // state is written cell-local; a ray that never enters keeps its world position and direction.
 __device__ __forceinline__ void emit_ray(const TraceParams &P, int64_t rid, RayState &r)
 {
+    // FP64 set-up and optics: no contracted multiply-adds, so every kernel that inlines this
+    // (single-image and batched paths) computes the same bits
+    #pragma clang fp contract(off)
     const int64_t s = rid / P.rays_per_src;
     const int32_t j = (int32_t)(rid - s * P.rays_per_src);
     const float4 sv = P.src[s];
@@ -341,7 +353,7 @@ __device__ __forceinline__ void emit_ray(const TraceParams &P, int64_t rid, RayS
     }
     // inside: T = n dR/ds = n u (eq. 4), n interpolated at the entry point
     CellCache cc;
-    cc.key = -1;
+    cc.ix = -1;
     float D0[3];
     const float n0 = sample_D<float>(P, cc, r.c, f, D0);
 #pragma unroll
@@ -381,7 +393,7 @@ __device__ __forceinline__ void box_ray(const TraceParams &P, RayState &r)
         }
     }
     CellCache cc;
-    cc.key = -1;
+    cc.ix = -1;
     bool limited = false;
     const int steps = trace_box<F>(P, cc, r.c, r.fd, Tr, dT, &limited);
     // exit direction as a float hi/lo pair (about 48 significant bits)
@@ -394,11 +406,28 @@ __device__ __forceinline__ void box_ray(const TraceParams &P, RayState &r)
     r.info = RS_ENTERED | (limited ? RS_LIMITED : 0) | (steps << RS_STEP_SHIFT);
 }
 
-template <typename F>
-__device__ __forceinline__ void box_body(const TraceParams &P, RayState *__restrict__ st, int64_t n)
+// Ray i = k, or i = list[k] for k < *count when a list is given (the rays the surrogate left to
+// the tracer, packed densely so that waves are not held by a few scattered rays).
+__device__ __forceinline__ bool box_index(int64_t n, const int *__restrict__ list,
+                                          const unsigned long long *__restrict__ count, int64_t *i)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (list) {
+        const unsigned long long m = *count;
+        if ((unsigned long long)k >= m) return false;
+        *i = list[k];
+        return true;
+    }
+    *i = k;
+    return k < n;
+}
+
+template <typename F>
+__device__ __forceinline__ void box_body(const TraceParams &P, RayState *__restrict__ st, int64_t n,
+                                         const int *__restrict__ list, const unsigned long long *__restrict__ count)
+{
+    int64_t i;
+    if (!box_index(n, list, count, &i)) return;
     RayState r = st[i];
     if ((r.info & (RS_ENTERED | RS_SURR)) != RS_ENTERED) return;
     box_ray<F>(P, r);
@@ -406,14 +435,18 @@ __device__ __forceinline__ void box_body(const TraceParams &P, RayState *__restr
 }
 
 // FP32 integration: 96 VGPRs, five waves per SIMD.
-__global__ void __launch_bounds__(256, 5) k_box32(TraceParams P, RayState *__restrict__ st, int64_t n)
+__global__ void __launch_bounds__(256, 5) k_box32(TraceParams P, RayState *__restrict__ st, int64_t n,
+                                                  const int *__restrict__ list,
+                                                  const unsigned long long *__restrict__ count)
 {
-    box_body<float>(P, st, n);
+    box_body<float>(P, st, n, list, count);
 }
 
-__global__ void __launch_bounds__(256) k_box64(TraceParams P, RayState *__restrict__ st, int64_t n)
+__global__ void __launch_bounds__(256) k_box64(TraceParams P, RayState *__restrict__ st, int64_t n,
+                                               const int *__restrict__ list,
+                                               const unsigned long long *__restrict__ count)
 {
-    box_body<double>(P, st, n);
+    box_body<double>(P, st, n, list, count);
 }
 
 // ------------------------------------------------------------------ mixed precision
@@ -509,19 +542,22 @@ __device__ __forceinline__ int trace_box_mixed(const TraceParams &P, CellCache &
     }
 }
 
-__global__ void __launch_bounds__(256) k_box_mixed(TraceParams P, RayState *__restrict__ st, int64_t n)
+__global__ void __launch_bounds__(256) k_box_mixed(TraceParams P, RayState *__restrict__ st, int64_t n,
+                                                   const int *__restrict__ list,
+                                                   const unsigned long long *__restrict__ count)
 {
     __shared__ unsigned long long s64;
     if (threadIdx.x == 0) s64 = 0ull;
     __syncthreads();
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t i;
+    const bool live = box_index(n, list, count, &i);
     int n64 = 0;
-    if (i < n) {
+    if (live) {
         RayState r = st[i];
         if ((r.info & (RS_ENTERED | RS_SURR)) == RS_ENTERED) {
             float Tr[3] = {r.Tr[0], r.Tr[1], r.Tr[2]}, dT[3] = {r.dT[0], r.dT[1], r.dT[2]};
             CellCache cc;
-            cc.key = -1;
+            cc.ix = -1;
             bool limited = false;
             const int steps = trace_box_mixed(P, cc, r.c, r.fd, Tr, dT, &limited, &n64);
 #pragma unroll
@@ -580,7 +616,7 @@ __global__ void __launch_bounds__(256) k_calibrate(TraceParams P, const int *__r
 #pragma unroll
     for (int a = 0; a < 3; ++a) u[a] *= il;
     CellCache cc;
-    cc.key = -1;
+    cc.ix = -1;
     float D0[3];
     const float n0 = sample_D<float>(P, cc, c, f, D0);
     // FP32
@@ -602,7 +638,7 @@ __global__ void __launch_bounds__(256) k_calibrate(TraceParams P, const int *__r
     const double g64[3] = {P.step_cell[0], P.step_cell[1], P.step_cell[2]};
 #pragma unroll
     for (int a = 0; a < 3; ++a) T64[a] = (double)n0 * u[a];
-    cc.key = -1;
+    cc.ix = -1;
     for (int k = 0; k < n_steps; ++k) rkn_step<double, true>(P, cc, c64, fd64, T64, d64, g64, P.h, 1.0);
     double q32[2], q64[2];
     {
@@ -635,6 +671,7 @@ template <int RF, int TILE>
 __device__ __forceinline__ void deposit(const TraceParams &P, double x, double y, double w,
                                         unsigned long long *tile, int tx0, int ty0)
 {
+    #pragma clang fp contract(off)
     const int i0 = (int)x, j0 = (int)y;
     const double inv = 1.0 / (1.4142135623730950488 * P.sigma_px);
     float ex[2 * RF + 2], ey[2 * RF + 2];
@@ -681,6 +718,7 @@ template <int TILE>
 __device__ __forceinline__ void finish_block(const TraceParams &P, const RayState *__restrict__ st,
                                              int64_t first, int64_t base, int64_t n, FinishShared<TILE> &sh)
 {
+    #pragma clang fp contract(off)
     for (int q = threadIdx.x; q < TILE * TILE; q += blockDim.x) sh.tile[q] = 0ull;
     if (threadIdx.x == 0) sh.lead = 0x7fffffff;
     __syncthreads();
@@ -956,30 +994,37 @@ __global__ void __launch_bounds__(256) k_surr_samples(TraceParams P, SurrogateSp
 }
 
 __global__ void __launch_bounds__(256) k_surr_features(TraceParams P, SurrogateSpec sp, const RayState *__restrict__ st,
-                                                       int64_t n, float *__restrict__ x, int *__restrict__ idx,
-                                                       unsigned long long *__restrict__ count)
+                                                       int64_t n, int64_t off, float *__restrict__ x,
+                                                       int *__restrict__ idx, unsigned long long *__restrict__ count,
+                                                       int *__restrict__ tlist, unsigned long long *__restrict__ tcount)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int lane = threadIdx.x & 63;
     double E[3], u[3];
-    bool ok = false;
+    bool ok = false, traced = false;
     if (i < n) {
-        ok = entry_of(P, st[i], E, u);
+        const RayState r = st[i];
+        ok = entry_of(P, r, E, u);
         if (ok) ok = sp.tile_ok[surr_tile(sp, E)] != 0;
+        traced = !ok && (r.info & RS_ENTERED);
     }
-    // one atomic per wave: the eligible lanes take consecutive rows
-    const unsigned long long mask = __ballot(ok);
-    unsigned long long base = 0;
+    // one atomic per wave and list: the lanes of a wave take consecutive slots
+    const unsigned long long below = (1ull << lane) - 1ull;
+    const unsigned long long mask = __ballot(ok), tmask = __ballot(traced);
+    unsigned long long base = 0, tbase = 0;
     if (lane == 0 && mask) base = atomicAdd(count, (unsigned long long)__popcll(mask));
+    if (lane == 0 && tmask) tbase = atomicAdd(tcount, (unsigned long long)__popcll(tmask));
     base = __shfl(base, 0);
+    tbase = __shfl(tbase, 0);
     if (ok) {
-        const int64_t row = (int64_t)base + __popcll(mask & ((1ull << lane) - 1ull));
+        const int64_t row = (int64_t)base + __popcll(mask & below);
         float f[6];
         surr_features(sp, E, u, f);
 #pragma unroll
         for (int k = 0; k < 6; ++k) x[row * 6 + k] = f[k];
         idx[row] = (int)i;
     }
+    if (traced) tlist[tbase + __popcll(tmask & below)] = (int)(off + i);
 }
 
 // Predicted exit: straight exit plus the position change (on z = z_hi), direction u + change.
@@ -1118,12 +1163,13 @@ int launch_surr_samples(const TraceParams &p, const SurrogateSpec &sp, const Ray
     return (int)hipGetLastError();
 }
 
-int launch_surr_features(const TraceParams &p, const SurrogateSpec &sp, const RayState *st, int64_t n,
-                         float *x, int *idx, unsigned long long *count, hipStream_t s)
+int launch_surr_features(const TraceParams &p, const SurrogateSpec &sp, const RayState *st, int64_t n, int64_t off,
+                         float *x, int *idx, unsigned long long *count, int *tlist, unsigned long long *tcount,
+                         hipStream_t s)
 {
     if (n <= 0) return 0;
-    hipLaunchKernelGGL(k_surr_features, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, sp, st, n, x, idx,
-                       count);
+    hipLaunchKernelGGL(k_surr_features, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, sp, st, n, off, x, idx,
+                       count, tlist, tcount);
     return (int)hipGetLastError();
 }
 
@@ -1183,14 +1229,15 @@ int launch_trace_chunk(const TraceParams &p, RayState *st, int64_t first, int64_
     hipLaunchKernelGGL(k_emit, dim3(blocks), dim3(256), 0, stream, p, st, first, n);
     int e = (int)hipGetLastError();
     if (e) return e;
-    if (hook && (e = hook->run(hook->self, p, st, first, n, stream))) return e;
+    TraceList tl{nullptr, nullptr};
+    if (hook && (e = hook->run(hook->self, p, st, first, n, stream, &tl))) return e;
     if (box_begin && (e = (int)hipEventRecord(box_begin, stream))) return e;
     if (prec == PREC_FP64)
-        hipLaunchKernelGGL(k_box64, dim3(blocks), dim3(256), 0, stream, p, st, n);
+        hipLaunchKernelGGL(k_box64, dim3(blocks), dim3(256), 0, stream, p, st, n, tl.idx, tl.count);
     else if (prec == PREC_MIXED)
-        hipLaunchKernelGGL(k_box_mixed, dim3(blocks), dim3(256), 0, stream, p, st, n);
+        hipLaunchKernelGGL(k_box_mixed, dim3(blocks), dim3(256), 0, stream, p, st, n, tl.idx, tl.count);
     else
-        hipLaunchKernelGGL(k_box32, dim3(blocks), dim3(256), 0, stream, p, st, n);
+        hipLaunchKernelGGL(k_box32, dim3(blocks), dim3(256), 0, stream, p, st, n, tl.idx, tl.count);
     e = (int)hipGetLastError();
     if (e) return e;
     if (box_end && (e = (int)hipEventRecord(box_end, stream))) return e;

@@ -150,6 +150,8 @@ def test_surrogate_in_the_trace(torch):
     img_s = pbr.u64_image_to_numpy(r.read_image()).astype(np.float64)
     rec_s = r.read_ray_exits()
     print("tracer", st_t, "\nsurrogate", st_s)
+    print(f"trace time: tracer {st_t['trace_ms']:.3f} ms, with surrogate {st_s['trace_ms']:.3f} ms "
+          f"(integration {st_t['box_ms']:.3f} -> {st_s['box_ms']:.3f} ms)")
     assert st_s["surrogate_rays"] > 0
     assert sum(st_s["status"]) == n_rays
     surr = (rec_s["entered"] == 1) & (rec_s["n_steps"] == 0) & (rec_t["n_steps"] > 0)
