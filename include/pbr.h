@@ -378,6 +378,8 @@ typedef struct pbr_surrogate_report {
     int64_t train_samples;     /* training rays that cross the box from face z_min to face z_max */
     int64_t val_samples;       /* validation rays that cross and reach the sensor */
     int64_t val_eligible;      /* of which enter through eligible tiles */
+    int64_t val_rim_mismatches; /* validation rays that reach the sensor either from the tracer's or
+                                   from the predicted exit but not both (aperture or lens rim) */
     int32_t steps;             /* Adam steps taken */
     int32_t eligible_tiles;
     double loss_first_epoch;   /* mean training loss over the first and the last epoch */
@@ -422,19 +424,22 @@ int pbr_surrogate_adam_step(pbr_surrogate *s, const float *x_dev, const float *t
                             int32_t step, double *loss_host);
 
 /* Trains the network for the context's current field, optics and sensor.  The tracer (FP32; FP64
- * inside flagged bricks when the context has any) integrates n_train_src x rays_per_src rays
- * emitted from train_src_dev with train_seed, and n_val_src x rays_per_src from val_src_dev with
- * val_seed (device arrays as in pbr_emit_and_trace), without depositing them.  Rays that enter
+ * inside flagged bricks when the context has any) integrates n_train_src x train_rays_per_src rays
+ * emitted from train_src_dev with train_seed, and n_val_src x val_rays_per_src from val_src_dev
+ * with val_seed (device arrays as in pbr_emit_and_trace), without depositing them.  (The rays of
+ * one source enter the box close together: many sources with few rays each cover more tiles.)  Rays that enter
  * through z_min and leave through z_max become samples; the training samples set the
  * standardisation, then cfg->epochs passes of Adam steps over shuffled batches of cfg->batch;
  * the validation samples that reach the sensor are pushed through lens and sensor from the
- * predicted exit and compared with the tracer's hit, which fixes the fallback map.  The
+ * predicted exit and compared with the tracer's hit, which fixes the fallback map (a tile with a
+ * validation ray that enters through z_min but leaves through another face is never eligible;
+ * rays that reach the sensor one way but not the other are counted, not used).  The
  * context's sensor accumulator and counters are left untouched; its trace workspace is used as
  * scratch.  Synchronises.  Errors: STATE (context not ready, host-only context), ARG, HIP. */
 int pbr_surrogate_train(pbr_surrogate *s, pbr_ctx *ctx, const float *train_src_dev, int64_t n_train_src,
-                        const float *val_src_dev, int64_t n_val_src, int32_t rays_per_src, uint64_t train_seed,
-                        uint64_t val_seed, double ds, const pbr_surrogate_train_config *cfg,
-                        pbr_surrogate_report *report);
+                        int32_t train_rays_per_src, const float *val_src_dev, int64_t n_val_src,
+                        int32_t val_rays_per_src, uint64_t train_seed, uint64_t val_seed, double ds,
+                        const pbr_surrogate_train_config *cfg, pbr_surrogate_report *report);
 
 /* Fallback map of a trained surrogate: tiles x tiles bytes (1 = eligible) and the largest
  * validation error per tile in pixels (-1 for tiles without validation rays), tile (tx, ty) at
@@ -445,7 +450,8 @@ int pbr_surrogate_tile_map(pbr_surrogate *s, uint8_t *eligible_host, float *max_
  * PBR_SURROGATE then hand every ray that enters through an eligible tile of z_min to the network
  * and trace the rest.  Fails with STATE when the surrogate is untrained, was trained on another
  * context or the context's field, optics or sensor changed since.  The surrogate must outlive
- * the attachment. */
+ * the attachment.  The first trace with PBR_SURROGATE allocates 53 B per ray of the context's
+ * chunk size for the surrogate (kept until pbr_surrogate_destroy). */
 int pbr_set_surrogate(pbr_ctx *ctx, pbr_surrogate *s);
 
 #ifdef __cplusplus

@@ -14,15 +14,22 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 constexpr float kGeluC = 0.7978845608028654f;  // sqrt(2 / pi)
 constexpr float kGeluA = 0.044715f;
 
-__device__ __forceinline__ float gelu(float z)
+// GELU, tanh form, through the identity (1 + tanh u) / 2 = 1 / (1 + exp(-2 u)): one exponential
+// and one reciprocal (hardware approximations, about 1 ulp each) instead of a branchy tanh.
+// Saturates correctly: exp overflow gives 0, underflow gives z.
+__device__ __forceinline__ float gelu_sig(float z)
 {
-    return 0.5f * z * (1.0f + tanhf(kGeluC * (z + kGeluA * z * z * z)));
+    const float u = kGeluC * z * (1.0f + kGeluA * z * z);
+    return __builtin_amdgcn_rcpf(1.0f + __expf(-2.0f * u));
 }
 
+__device__ __forceinline__ float gelu(float z) { return z * gelu_sig(z); }
+
+// d/dz of z s(z), s = (1 + tanh u) / 2: s + 2 z s (1 - s) u'(z), u' = c (1 + 3 a z^2)
 __device__ __forceinline__ float gelu_grad(float z)
 {
-    const float t = tanhf(kGeluC * (z + kGeluA * z * z * z));
-    return 0.5f * (1.0f + t) + 0.5f * z * (1.0f - t * t) * kGeluC * (1.0f + 3.0f * kGeluA * z * z);
+    const float sg = gelu_sig(z);
+    return sg + 2.0f * z * sg * (1.0f - sg) * kGeluC * (1.0f + 3.0f * kGeluA * z * z);
 }
 
 // float -> bfloat16 bits, round to nearest even (finite inputs)
@@ -47,6 +54,10 @@ __global__ void __launch_bounds__(256) k_gemm_nt(const unsigned short *__restric
 {
     // rows beyond the live count (read on the device) are skipped whole blocks at a time
     if (live && (unsigned long long)blockIdx.y * 64ull >= *live) return;
+    // split K (plain products only): block z takes k in [z K, (z + 1) K) and writes slice z of Cf
+    A += (size_t)blockIdx.z * K;
+    W += (size_t)blockIdx.z * K;
+    if (Cf) Cf += (size_t)blockIdx.z * gridDim.y * 64 * ldc;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int m0 = blockIdx.y * 64 + (wave >> 1) * 32;
     const int n0 = blockIdx.x * 64 + (wave & 1) * 32;
@@ -178,46 +189,88 @@ __global__ void __launch_bounds__(256) k_transpose(const unsigned short *__restr
     }
 }
 
-// g[n] = sum over rows of d[row][n] (bias gradients), FP32, fixed summation order.
-__global__ void __launch_bounds__(256) k_colsum(const float *__restrict__ d, int64_t rows, int cols,
-                                                float *__restrict__ g)
+// Reductions over the rows of a batch against one 256-wide operand (weight gradients of the
+// 6-wide layers and bias gradients), in two passes with a fixed summation order.  Pass 1: block y
+// takes rows [y RB, (y + 1) RB); thread w owns column w of the wide operand (row reads are
+// coalesced) and accumulates, per small column s, wide[m][w] * small[m][s] (ns of them), the
+// plain column sum of wide[.][w] (if ones), and, in thread 0, the column sums of small (if
+// small_sums).  Pass 2 adds the blocks in order and scatters: products to G ([s][w] if
+// small_major, else [w][s]), wide sums to gw, small sums to gs.
+template <bool WIDE_BF16>
+__global__ void __launch_bounds__(256) k_wide_part(const void *__restrict__ wide, int64_t rows,
+                                                   const float *__restrict__ small, int ns, int ones,
+                                                   int small_sums, int64_t rb, float *__restrict__ part)
 {
-    __shared__ float s[256];
-    const int n = blockIdx.x;
-    float a = 0.0f;
-    for (int64_t m = threadIdx.x; m < rows; m += blockDim.x) a += d[m * cols + n];
-    s[threadIdx.x] = a;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
-        __syncthreads();
+    const int w = threadIdx.x;
+    const int64_t m0 = (int64_t)blockIdx.x * rb;
+    const int64_t m1 = m0 + rb < rows ? m0 + rb : rows;
+    float acc[kOut + 1], accs[kOut];
+#pragma unroll
+    for (int q = 0; q <= kOut; ++q) acc[q] = 0.0f;
+#pragma unroll
+    for (int q = 0; q < kOut; ++q) accs[q] = 0.0f;
+#pragma unroll 8
+    for (int64_t m = m0; m < m1; ++m) {
+        float v;
+        if (WIDE_BF16) v = __uint_as_float(((unsigned)((const unsigned short *)wide)[m * kHidden + w]) << 16);
+        else v = ((const float *)wide)[m * kHidden + w];
+#pragma unroll
+        for (int q = 0; q < kOut; ++q)
+            if (q < ns) {
+                const float sv = small[m * ns + q];
+                acc[q] += v * sv;
+                accs[q] += sv;
+            }
+        acc[kOut] += v;
     }
-    if (threadIdx.x == 0) g[n] = s[0];
+    const int stride = kHidden * (ns + ones) + (small_sums ? ns : 0);
+    float *o = part + (size_t)blockIdx.x * stride;
+    for (int q = 0; q < ns; ++q) o[w * (ns + ones) + q] = acc[q];
+    if (ones) o[w * (ns + ones) + ns] = acc[kOut];
+    if (small_sums && w == 0)
+        for (int q = 0; q < ns; ++q) o[kHidden * (ns + ones) + q] = accs[q];
 }
 
-// G[o][i] = sum over rows of P[row][o] Q[row][i] for a small side (o < no, i < ni), FP32:
-// the weight gradients of the 6-wide layers (W5: P = dy, Q = a4 bf16; W1: P = dz1, Q = x).
-template <bool Q_BF16>
-__global__ void __launch_bounds__(256) k_small_wgrad(const float *__restrict__ Pm, int no,
-                                                     const void *__restrict__ Qm, int ni, int64_t rows,
-                                                     float *__restrict__ G)
+// Block: 32 outputs x 8 lanes; lane g sums blocks g, g + 8, ... (loads in flight), then the 8
+// lane sums are added in a fixed tree.
+__global__ void __launch_bounds__(256) k_wide_final(const float *__restrict__ part, int nblocks, int ns, int ones,
+                                                    int small_sums, int small_major, float *__restrict__ G,
+                                                    float *__restrict__ gw, float *__restrict__ gs)
 {
-    __shared__ float s[256];
-    const int o = blockIdx.x / ni, i = blockIdx.x % ni;
+    __shared__ float red[8][32];
+    const int stride = kHidden * (ns + ones) + (small_sums ? ns : 0);
+    const int ql = threadIdx.x & 31, g = threadIdx.x >> 5;
+    const int q = blockIdx.x * 32 + ql;
     float a = 0.0f;
-    for (int64_t m = threadIdx.x; m < rows; m += blockDim.x) {
-        float q;
-        if (Q_BF16) q = __uint_as_float(((unsigned)((const unsigned short *)Qm)[m * ni + i]) << 16);
-        else q = ((const float *)Qm)[m * ni + i];
-        a += Pm[m * no + o] * q;
+    if (q < stride) {
+#pragma unroll 8
+        for (int y = g; y < nblocks; y += 8) a += part[(size_t)y * stride + q];
     }
-    s[threadIdx.x] = a;
+    red[g][ql] = a;
     __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-        if ((int)threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
-        __syncthreads();
+    if (g == 0 && q < stride) {
+        const float t = ((red[0][ql] + red[1][ql]) + (red[2][ql] + red[3][ql])) +
+                        ((red[4][ql] + red[5][ql]) + (red[6][ql] + red[7][ql]));
+        if (q < kHidden * (ns + ones)) {
+            const int w = q / (ns + ones), k = q % (ns + ones);
+            if (k < ns) G[small_major ? k * kHidden + w : w * ns + k] = t;
+            else gw[w] = t;
+        } else {
+            gs[q - kHidden * (ns + ones)] = t;
+        }
     }
-    if (threadIdx.x == 0) G[o * ni + i] = s[0];
+}
+
+// C = sum of the nsplit slices of part (each n floats), in slice order.
+__global__ void __launch_bounds__(256) k_split_sum(const float *__restrict__ part, int nsplit, int64_t n,
+                                                   float *__restrict__ C)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    float a = 0.0f;
+#pragma unroll 16
+    for (int z = 0; z < nsplit; ++z) a += part[(size_t)z * n + q];
+    C[q] = a;
 }
 
 // Adam on the flat FP32 parameters (Kingma & Ba), then the bf16 copies the products read:
@@ -234,6 +287,32 @@ __global__ void __launch_bounds__(256) k_adam(float *__restrict__ p, const float
     m[q] = mq;
     v[q] = vq;
     p[q] -= lr * (mq / c1) / (sqrtf(vq / c2) + eps);
+}
+
+// Adam with the step number read on the device (graph replays): t = *step + 1, learning rate on a
+// cosine from lr_max (first step) to lr_min (step total - 1).
+__global__ void __launch_bounds__(256) k_adam_sched(float *__restrict__ p, const float *__restrict__ g,
+                                                    float *__restrict__ m, float *__restrict__ v, int64_t n,
+                                                    const int *__restrict__ step, int total, float lr_max,
+                                                    float lr_min, float beta1, float beta2, float eps)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const int k = *step;
+    const float ph = total > 1 ? (float)k / (float)(total - 1) : 0.0f;
+    const float lr = lr_min + 0.5f * (lr_max - lr_min) * (1.0f + cosf(3.14159265358979f * ph));
+    const float c1 = 1.0f - powf(beta1, (float)(k + 1)), c2 = 1.0f - powf(beta2, (float)(k + 1));
+    const float gq = g[q];
+    const float mq = beta1 * m[q] + (1.0f - beta1) * gq;
+    const float vq = beta2 * v[q] + (1.0f - beta2) * gq * gq;
+    m[q] = mq;
+    v[q] = vq;
+    p[q] -= lr * (mq / c1) / (sqrtf(vq / c2) + eps);
+}
+
+__global__ void k_step_advance(int *step)
+{
+    if (threadIdx.x == 0) *step += 1;
 }
 
 __global__ void __launch_bounds__(256) k_shadow(const float *__restrict__ p, unsigned short *__restrict__ w2,
@@ -254,10 +333,12 @@ __global__ void __launch_bounds__(256) k_shadow(const float *__restrict__ p, uns
     }
 }
 
-// Mean of the squared errors of one batch from the per-block sums of k_out_error.
+// Mean of the squared errors of one batch from the per-block sums of k_out_error, into out[0]
+// (or out[*step] when step is given).
 __global__ void __launch_bounds__(256) k_loss_mean(const float *__restrict__ part, int nparts, float inv_count,
-                                                   float *__restrict__ out)
+                                                   float *__restrict__ out, const int *__restrict__ step)
 {
+    if (step) out += *step;
     __shared__ float s[256];
     float a = 0.0f;
     for (int i = threadIdx.x; i < nparts; i += 256) a += part[i];
@@ -312,29 +393,45 @@ __global__ void __launch_bounds__(256, 2) k_mlp_infer(const float *__restrict__ 
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int r = lane & 15, kg = lane >> 4;
-    const unsigned short *wl[3] = {w2, w3, w4};
-    const int boff[3] = {kOffB2, kOffB3, kOffB4};
     for (int l = 0; l < 3; ++l) {
         floatx4 acc[8][4];
 #pragma unroll
         for (int i = 0; i < 8; ++i)
 #pragma unroll
             for (int j = 0; j < 4; ++j) acc[i][j] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-        const unsigned short *W = wl[l] + (size_t)(wave * 64 + r) * kHidden + 8 * kg;
+        const unsigned short *W = (l == 0 ? w2 : (l == 1 ? w3 : w4)) + (size_t)(wave * 64 + r) * kHidden + 8 * kg;
+        // weight fragments two k steps ahead: the L2 latency of step k + 2 hides behind the
+        // matrix-core work of steps k and k + 1
+        bf16x8 fw[4], fn[4], fn2[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            fw[j] = *(const bf16x8 *)(W + j * 16 * kHidden);
+            fn[j] = *(const bf16x8 *)(W + j * 16 * kHidden + 32);
+        }
+#pragma unroll
         for (int k0 = 0; k0 < kHidden; k0 += 32) {
-            bf16x8 fw[4];
+            if (k0 + 64 < kHidden) {
 #pragma unroll
-            for (int j = 0; j < 4; ++j) fw[j] = *(const bf16x8 *)(W + j * 16 * kHidden + k0);
+                for (int j = 0; j < 4; ++j) fn2[j] = *(const bf16x8 *)(W + j * 16 * kHidden + k0 + 64);
+            }
+            // all eight activation fragments of this k step first, so that the LDS reads overlap
+            // the matrix-core work instead of each waiting in turn
+            bf16x8 fa[8];
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const bf16x8 fa = *(const bf16x8 *)(act + (16 * i + r) * kActStride + 8 * kg + k0);
+            for (int i = 0; i < 8; ++i) fa[i] = *(const bf16x8 *)(act + (16 * i + r) * kActStride + 8 * kg + k0);
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, fw[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fw[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                fw[j] = fn[j];
+                fn[j] = fn2[j];
             }
         }
         __syncthreads();  // every wave has read this layer's inputs
-        const float *bias = params + boff[l];
+        const float *bias = params + (l == 0 ? kOffB2 : (l == 1 ? kOffB3 : kOffB4));
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int n = wave * 64 + 16 * j + r;
@@ -372,6 +469,27 @@ __global__ void __launch_bounds__(256, 2) k_mlp_infer(const float *__restrict__ 
 }
 
 inline unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+// Rows per block of the wide reductions and the resulting block count (at most kWideBlocks).
+constexpr int kWideBlocks = 256;
+inline int64_t wide_rows_per_block(int64_t rows) { return (rows + kWideBlocks - 1) / kWideBlocks; }
+
+int wide_reduce(const void *wide, bool wide_bf16, int64_t rows, const float *small, int ns, bool ones,
+                bool small_sums, bool small_major, float *G, float *gw, float *gs, float *part, hipStream_t s)
+{
+    const int64_t rb = wide_rows_per_block(rows);
+    const int nb = (int)((rows + rb - 1) / rb);
+    if (wide_bf16)
+        hipLaunchKernelGGL(k_wide_part<true>, dim3((unsigned)nb), dim3(256), 0, s, wide, rows, small, ns, (int)ones,
+                           (int)small_sums, rb, part);
+    else
+        hipLaunchKernelGGL(k_wide_part<false>, dim3((unsigned)nb), dim3(256), 0, s, wide, rows, small, ns, (int)ones,
+                           (int)small_sums, rb, part);
+    const int stride = kHidden * (ns + (ones ? 1 : 0)) + (small_sums ? ns : 0);
+    hipLaunchKernelGGL(k_wide_final, dim3((unsigned)((stride + 31) / 32)), dim3(256), 0, s, (const float *)part, nb, ns,
+                       (int)ones, (int)small_sums, (int)small_major, G, gw, gs);
+    return (int)hipGetLastError();
+}
 
 template <int EPI>
 int gemm(const unsigned short *A, int lda, const unsigned short *W, int ldw, const float *bias, int64_t M, int N,
@@ -432,10 +550,10 @@ int mlp_backward(const MlpDevice &d, const MlpBuffers &b, const float *x, const 
     unsigned short *dzb = b.dzb, *dzb2 = b.dzb2;
     hipLaunchKernelGGL(k_out_error, dim3(blocks_for(rows * kOut)), dim3(256), 0, s, y, t, rows, b.dy, b.loss_part);
     if ((e = (int)hipGetLastError())) return e;
-    // W5, b5
-    hipLaunchKernelGGL(k_small_wgrad<true>, dim3(kOut * kHidden), dim3(256), 0, s, b.dy, kOut, (const void *)b.a[3],
-                       kHidden, rows, d.grad + kOffW5);
-    hipLaunchKernelGGL(k_colsum, dim3(kOut), dim3(256), 0, s, b.dy, rows, kOut, d.grad + kOffB5);
+    // W5 [6][256] = dy^T a4, b5 = column sums of dy
+    if ((e = wide_reduce(b.a[3], true, rows, b.dy, kOut, false, true, true, d.grad + kOffW5, nullptr,
+                         d.grad + kOffB5, b.part, s)))
+        return e;
     // error into layer 4
     hipLaunchKernelGGL(k_out_back, dim3(blocks_for(rows * kHidden)), dim3(256), 0, s, b.dy, d.params + kOffW5,
                        b.z[3], rows, dz, dzb);
@@ -449,10 +567,19 @@ int mlp_backward(const MlpDevice &d, const MlpBuffers &b, const float *x, const 
         hipLaunchKernelGGL(k_transpose, dim3(kHidden / 32, (unsigned)((rows + 31) / 32)), dim3(256), 0, s, b.a[l],
                            rows, kHidden, b.t1);
         if ((e = (int)hipGetLastError())) return e;
-        if ((e = gemm<EPI_PLAIN>(b.t0, (int)rows, b.t1, (int)rows, nullptr, kHidden, kHidden, (int)rows,
-                                 d.grad + woff[l], kHidden, nullptr, 0, nullptr, kHidden, s)))
+        // split over the rows (K) so that the 16 output tiles become 16 x nsplit blocks
+        int nsplit = 16;
+        while (nsplit > 1 && (rows % (32 * nsplit) != 0 || rows / nsplit < 128)) nsplit /= 2;
+        hipLaunchKernelGGL(k_gemm_nt<EPI_PLAIN>, dim3(kHidden / 64, kHidden / 64, (unsigned)nsplit), dim3(256), 0,
+                           s, (const unsigned short *)b.t0, (int)rows, (const unsigned short *)b.t1, (int)rows,
+                           (const float *)nullptr, (int)(rows / nsplit), b.part, kHidden, (unsigned short *)nullptr,
+                           0, (const float *)nullptr, kHidden, (const unsigned long long *)nullptr);
+        hipLaunchKernelGGL(k_split_sum, dim3(blocks_for((int64_t)kHidden * kHidden)), dim3(256), 0, s,
+                           (const float *)b.part, nsplit, (int64_t)kHidden * kHidden, d.grad + woff[l]);
+        if ((e = (int)hipGetLastError())) return e;
+        if ((e = wide_reduce(dz, false, rows, nullptr, 0, true, false, false, nullptr, d.grad + boff[l], nullptr,
+                             b.part2, s)))
             return e;
-        hipLaunchKernelGGL(k_colsum, dim3(kHidden), dim3(256), 0, s, dz, rows, kHidden, d.grad + boff[l]);
         // error into the layer below: dz_below = (dz W) * g'(z_below)
         if ((e = gemm<EPI_GELU_BACK>(dzb, kHidden, wt[l], kHidden, nullptr, rows, kHidden, kHidden, dz2,
                                      kHidden, dzb2, kHidden, b.z[l], kHidden, s)))
@@ -460,11 +587,9 @@ int mlp_backward(const MlpDevice &d, const MlpBuffers &b, const float *x, const 
         std::swap(dz, dz2);
         std::swap(dzb, dzb2);
     }
-    // W1, b1 from dz1 (f32) and x
-    hipLaunchKernelGGL(k_small_wgrad<false>, dim3(kHidden * kIn), dim3(256), 0, s, dz, kHidden, (const void *)x,
-                       kIn, rows, d.grad + kOffW1);
-    hipLaunchKernelGGL(k_colsum, dim3(kHidden), dim3(256), 0, s, dz, rows, kHidden, d.grad + kOffB1);
-    return (int)hipGetLastError();
+    // W1 [256][6] = dz1^T x, b1 = column sums of dz1 (both wide)
+    return wide_reduce(dz, false, rows, x, kIn, true, false, false, d.grad + kOffW1, d.grad + kOffB1, nullptr, b.part,
+                       s);
 }
 
 int mlp_infer(const MlpDevice &d, const float *x, int64_t rows, float *y, hipStream_t s,
@@ -477,10 +602,25 @@ int mlp_infer(const MlpDevice &d, const float *x, int64_t rows, float *y, hipStr
     return (int)hipGetLastError();
 }
 
-int mlp_loss_mean(const MlpBuffers &b, int64_t rows, float *out, hipStream_t s)
+int mlp_loss_mean(const MlpBuffers &b, int64_t rows, float *out, hipStream_t s, const int *step)
 {
     hipLaunchKernelGGL(k_loss_mean, dim3(1), dim3(256), 0, s, (const float *)b.loss_part,
-                       (int)blocks_for(rows * kOut), 1.0f / (float)(rows * kOut), out);
+                       (int)blocks_for(rows * kOut), 1.0f / (float)(rows * kOut), out, step);
+    return (int)hipGetLastError();
+}
+
+int mlp_adam_sched(const MlpDevice &d, const int *step, int total, float lr_max, float lr_min, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_adam_sched, dim3(blocks_for(kParams)), dim3(256), 0, s, d.params, d.grad, d.m, d.v,
+                       (int64_t)kParams, step, total, lr_max, lr_min, 0.9f, 0.999f, 1e-8f);
+    int e = (int)hipGetLastError();
+    if (e) return e;
+    return mlp_refresh_shadow(d, s);
+}
+
+int mlp_step_advance(int *step, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_step_advance, dim3(1), dim3(64), 0, s, step);
     return (int)hipGetLastError();
 }
 

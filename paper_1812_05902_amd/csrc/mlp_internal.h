@@ -43,6 +43,7 @@ struct MlpBuffers {
     float *dz, *dz2;        // [rows][256] f32
     unsigned short *dzb, *dzb2, *t0, *t1;
     float *loss_part;       // ceil(rows * 6 / 256) partial sums
+    float *part, *part2;    // 16 x 256 x 256 floats each: split-K slices and row-block partial sums
 };
 
 int mlp_refresh_shadow(const MlpDevice &d, hipStream_t s);
@@ -54,8 +55,12 @@ int mlp_backward(const MlpDevice &d, const MlpBuffers &b, const float *x, const 
 // optional) caps the rows computed.  Outputs equal mlp_forward's bit for bit.
 int mlp_infer(const MlpDevice &d, const float *x, int64_t rows, float *y, hipStream_t s,
               const unsigned long long *live = nullptr);
-// After mlp_backward: *out (device) = mean squared error of that batch.
-int mlp_loss_mean(const MlpBuffers &b, int64_t rows, float *out, hipStream_t s);
+// After mlp_backward: *out (device) = mean squared error of that batch (out[*step] if step given).
+int mlp_loss_mean(const MlpBuffers &b, int64_t rows, float *out, hipStream_t s, const int *step = nullptr);
+// Adam step with t = *step + 1 and the cosine learning rate of step *step out of total (device step
+// counter, so that one captured graph serves every step), then the bf16 copies.
+int mlp_adam_sched(const MlpDevice &d, const int *step, int total, float lr_max, float lr_min, hipStream_t s);
+int mlp_step_advance(int *step, hipStream_t s);
 int mlp_adam(const MlpDevice &d, float lr, int step, hipStream_t s);
 // C[M][N] = A[M][K] W[N][K]^T in f32 (bf16 operands); M, N multiples of 64, K of 32.
 int mlp_gemm_plain(const unsigned short *A, int lda, const unsigned short *W, int ldw, int64_t M, int N, int K,

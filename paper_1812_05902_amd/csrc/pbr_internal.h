@@ -112,16 +112,29 @@ enum : int { RS_ENTERED = 1, RS_LIMITED = 2, RS_SURR = 4, RS_STEP_SHIFT = 4 };
 struct SurrogateSpec {
     double z_lo, z_hi, x_lo, x_hi, y_lo, y_hi;
     double theta, Lx, Ly;
+    // reciprocals used by the kernels (set by surrogate_spec_finish): 1/(x_hi-x_lo), 1/(y_hi-y_lo),
+    // 1/theta, 2 pi/Lx, 2 pi/Ly
+    double inv_wx, inv_wy, inv_theta, kx, ky;
     float t_mean[6], t_scale[6];
     int tiles;
     const unsigned char *tile_ok;
 };
 
+inline void surrogate_spec_finish(SurrogateSpec &sp)
+{
+    sp.inv_wx = 1.0 / (sp.x_hi - sp.x_lo);
+    sp.inv_wy = 1.0 / (sp.y_hi - sp.y_lo);
+    sp.inv_theta = 1.0 / sp.theta;
+    sp.kx = 6.283185307179586476925286766559 / sp.Lx;
+    sp.ky = 6.283185307179586476925286766559 / sp.Ly;
+}
+
 // One traced ray as a training / validation sample.
 struct SurrogateSample {
     float t[6];      // raw targets (metres, unit-vector components)
     int tile;        // entry tile
-    int flags;       // bit 0: enters through z_lo and leaves through z_hi; bit 1: tracer deposited
+    int flags;       // bit 2: enters through z_lo; bit 0: and leaves through z_hi (a training
+                     // sample); bit 1: the tracer's ray reaches the sensor plane through the optics
     double E[2];     // entry point (x, y) on z = z_lo
     double u[3];     // entry unit direction
     double px[2];    // tracer's sensor hit (pixels), when bit 1 is set
@@ -132,18 +145,19 @@ constexpr int kMoments = 16;  // count, sum t[6], sum t^2[6], sum u_x^2, sum u_y
 // After emission and integration of rays [first, first + n) (states st): samples out[0 .. n).
 int launch_surr_samples(const TraceParams &p, const SurrogateSpec &sp, const RayState *st, int64_t first,
                         int64_t n, SurrogateSample *out, hipStream_t s);
-// After emission (entry states st[0 .. n)): the rays in eligible tiles are compacted (in no fixed
-// order) into rows 0 .. *count of x (features) and idx (ray index in st); the other rays that
-// entered the box are appended to tlist (index off + i) behind *tcount.  Counters start at zero.
-int launch_surr_features(const TraceParams &p, const SurrogateSpec &sp, const RayState *st, int64_t n, int64_t off,
-                         float *x, int *idx, unsigned long long *count, int *tlist, unsigned long long *tcount,
-                         hipStream_t s);
-// Writes the predicted exit state (network output y, standardised) of rows 0 .. *count (at most
-// cap) into st[idx[row]].
-int launch_surr_apply(const TraceParams &p, const SurrogateSpec &sp, const float *y, const int *idx,
-                      const unsigned long long *count, int64_t cap, RayState *st, hipStream_t s);
-// Sensor-hit error of predictions y for samples smp[0 .. n): err[k] (pixels, -1 if not comparable),
-// per-tile maxima (float bits) and sample counts.
+// After emission (entry states st[0 .. n)): features of ray i in row i of x (zero rows and
+// elig[i] = 0 for rays the network does not take); the other rays that entered the box are
+// appended to tlist behind *tcount (which must start at zero).
+int launch_surr_features(const TraceParams &p, const SurrogateSpec &sp, const RayState *st, int64_t n, float *x,
+                         unsigned char *elig, int *tlist, unsigned long long *tcount, hipStream_t s);
+// Writes the predicted exit state (network output row i, standardised) of every ray with elig[i].
+int launch_surr_apply(const TraceParams &p, const SurrogateSpec &sp, const float *y, const unsigned char *elig,
+                      int64_t n, RayState *st, hipStream_t s);
+// Sensor-hit error of predictions y for samples smp[0 .. n): err[k] in pixels; 1e30 for a ray
+// that entered through z_lo and left through another face; -2 when exactly one of prediction and
+// tracer reaches the sensor (a rim case); -1 when neither does or the ray is not a front-face ray.
+// Per-tile maxima (float bits) and counts over the err >= 0 samples.
+int launch_surr_extract(const SurrogateSample *smp, int64_t n, int field, int *out, hipStream_t s);
 int launch_surr_validate(const TraceParams &p, const SurrogateSpec &sp, const SurrogateSample *smp,
                          const float *y, int64_t n, float *err, unsigned *tile_err, unsigned *tile_cnt,
                          hipStream_t s);
@@ -151,6 +165,9 @@ int launch_surr_validate(const TraceParams &p, const SurrogateSpec &sp, const Su
 // (idx == nullptr: rows 0 .. rows in order).
 int launch_surr_gather(const SurrogateSpec &sp, const SurrogateSample *smp, const int *idx, int64_t rows,
                        float *x, float *t, hipStream_t s);
+// The same for training step *step (device): rows perm[(*step mod steps_per_epoch) * rows ..].
+int launch_surr_gather_step(const SurrogateSpec &sp, const SurrogateSample *smp, const int *perm, const int *step,
+                            int64_t steps_per_epoch, int64_t rows, float *x, float *t, hipStream_t s);
 // Per-block sums (kMoments doubles per block) over valid samples; returns the blocks used.
 int launch_surr_moments(const SurrogateSample *smp, int64_t n, double *part, int *blocks, hipStream_t s);
 

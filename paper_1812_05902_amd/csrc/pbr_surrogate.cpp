@@ -27,6 +27,8 @@ struct pbr_surrogate {
     pbr::MlpDevice d{};
     pbr::MlpBuffers b{};
     float *x = nullptr, *y = nullptr, *t = nullptr, *loss = nullptr;
+    int *step = nullptr;                 // training step counter read by the captured step
+    hipStream_t train_stream = nullptr;  // non-blocking stream the training step is captured on
     int *idx = nullptr;
     unsigned long long *count = nullptr;
     // trained state
@@ -35,8 +37,11 @@ struct pbr_surrogate {
     pbr::SurrogateSpec spec{};
     unsigned char *tile_ok_dev = nullptr;
     int64_t tile_cap = 0;
-    int *tlist = nullptr;  // rays left to the tracer in the current chunk
-    int64_t tlist_cap = 0;
+    // inference on whole trace chunks: features, outputs, row -> ray index, rays left to the tracer
+    float *ix = nullptr, *iy = nullptr;
+    unsigned char *ielig = nullptr;
+    int *tlist = nullptr;
+    int64_t chunk_cap = 0;
     std::vector<unsigned char> tile_ok;
     std::vector<float> tile_err;
 };
@@ -137,18 +142,13 @@ int hook_run(void *self, const pbr::TraceParams &P, pbr::RayState *st, int64_t, 
              pbr::TraceList *list)
 {
     pbr_surrogate *s = (pbr_surrogate *)self;
-    if (n > s->tlist_cap) return (int)hipErrorInvalidValue;  // sized when the trace was validated
+    if (n > s->chunk_cap) return (int)hipErrorInvalidValue;  // sized when the trace was validated
     int e;
     if ((e = pbr::launch_clear_u64(s->count + 1, 1, stream))) return e;
-    for (int64_t off = 0; off < n; off += s->rows_cap) {
-        const int64_t m = std::min(s->rows_cap, n - off);
-        if ((e = pbr::launch_clear_u64(s->count, 1, stream))) return e;
-        if ((e = pbr::launch_surr_features(P, s->spec, st + off, m, off, s->x, s->idx, s->count, s->tlist,
-                                           s->count + 1, stream)))
-            return e;
-        if ((e = pbr::mlp_infer(s->d, s->x, m, s->y, stream, s->count))) return e;
-        if ((e = pbr::launch_surr_apply(P, s->spec, s->y, s->idx, s->count, m, st + off, stream))) return e;
-    }
+    if ((e = pbr::launch_surr_features(P, s->spec, st, n, s->ix, s->ielig, s->tlist, s->count + 1, stream)) ||
+        (e = pbr::mlp_infer(s->d, s->ix, n, s->iy, stream)) ||
+        (e = pbr::launch_surr_apply(P, s->spec, s->iy, s->ielig, n, st, stream)))
+        return e;
     list->idx = s->tlist;
     list->count = s->count + 1;
     return 0;
@@ -165,13 +165,20 @@ int surrogate_hook(pbr_ctx *ctx, ChunkHook *out)
     if (!s) return fail(ctx, PBR_ERR_STATE, "PBR_SURROGATE set but no surrogate attached (pbr_set_surrogate)");
     if (!s->trained || s->ctx_uid != ctx->uid || s->scene_version != ctx->scene_version)
         return fail(ctx, PBR_ERR_STATE, "the attached surrogate no longer matches this context's field, optics or sensor");
-    if (ctx->ray_chunk > s->tlist_cap) {
+    if (ctx->ray_chunk > s->chunk_cap) {
+        // buffers for whole chunks (53 B per ray), kept until the surrogate is destroyed
         DeviceGuard g(s->device);
-        void *q = nullptr;
-        const int e = dmalloc(s, &q, (size_t)ctx->ray_chunk * sizeof(int));
-        if (e) return hip_fail(ctx, e, "hipMalloc(surrogate trace list)");
-        s->tlist = (int *)q;
-        s->tlist_cap = ctx->ray_chunk;
+        void *q[4] = {nullptr, nullptr, nullptr, nullptr};
+        const size_t n = (size_t)ctx->ray_chunk;
+        int e = 0;
+        if ((e = dmalloc(s, &q[0], n * 24)) || (e = dmalloc(s, &q[1], n * 24)) || (e = dmalloc(s, &q[2], n)) ||
+            (e = dmalloc(s, &q[3], n * 4)))
+            return hip_fail(ctx, e, "hipMalloc(surrogate chunk buffers)");
+        s->ix = (float *)q[0];
+        s->iy = (float *)q[1];
+        s->ielig = (unsigned char *)q[2];
+        s->tlist = (int *)q[3];
+        s->chunk_cap = ctx->ray_chunk;
     }
     out->run = hook_run;
     out->self = s;
@@ -237,15 +244,20 @@ int pbr_surrogate_create(pbr_surrogate **out, int device, void *hip_stream, uint
         s->b.t0 = (unsigned short *)A(R * H * 2);
         s->b.t1 = (unsigned short *)A(R * H * 2);
         s->b.loss_part = (float *)A(((R * 6 + 255) / 256) * 4);
+        s->b.part = (float *)A((size_t)16 * H * H * 4);
+        s->b.part2 = (float *)A((size_t)16 * H * H * 4);
         s->x = (float *)A(R * 6 * 4);
         s->y = (float *)A(R * 6 * 4);
         s->t = (float *)A(R * 6 * 4);
         s->idx = (int *)A(R * 4);
         s->loss = (float *)A(256);
         s->count = (unsigned long long *)A(256);
+        s->step = (int *)A(256);
+        if (!e) e = (int)hipStreamCreateWithFlags(&s->train_stream, hipStreamNonBlocking);
         if (e) {
-            const int r = sfail(nullptr, PBR_ERR_HIP, "hipMalloc: %s", hipGetErrorString((hipError_t)e));
+            const int r = sfail(nullptr, PBR_ERR_HIP, "device set-up: %s", hipGetErrorString((hipError_t)e));
             free_all(s);
+            if (s->train_stream) (void)hipStreamDestroy(s->train_stream);
             delete s;
             return r;
         }
@@ -273,6 +285,10 @@ void pbr_surrogate_destroy(pbr_surrogate *s)
     try {
         DeviceGuard g(s->device);
         (void)hipStreamSynchronize(s->stream);
+        if (s->train_stream) {
+            (void)hipStreamSynchronize(s->train_stream);
+            (void)hipStreamDestroy(s->train_stream);
+        }
         free_all(s);
     } catch (...) {
     }
@@ -389,7 +405,8 @@ int pbr_surrogate_adam_step(pbr_surrogate *s, const float *x_dev, const float *t
 }
 
 int pbr_surrogate_train(pbr_surrogate *s, pbr_ctx *ctx, const float *train_src_dev, int64_t n_train_src,
-                        const float *val_src_dev, int64_t n_val_src, int32_t rays_per_src, uint64_t train_seed,
+                        int32_t train_rays_per_src, const float *val_src_dev, int64_t n_val_src,
+                        int32_t val_rays_per_src, uint64_t train_seed,
                         uint64_t val_seed, double ds, const pbr_surrogate_train_config *cfg,
                         pbr_surrogate_report *report)
 {
@@ -402,11 +419,12 @@ int pbr_surrogate_train(pbr_surrogate *s, pbr_ctx *ctx, const float *train_src_d
     pbr::host::Derived dv;
     if (pbr::host::derive(ctx, &dv)) return sfail(s, PBR_ERR_STATE, "context: %s", ctx->err.c_str());
     if (!ctx->ray_ws) return sfail(s, PBR_ERR_STATE, "context has no trace workspace");
-    if (!train_src_dev || !val_src_dev || n_train_src < 1 || n_val_src < 1 || rays_per_src < 1)
-        return sfail(s, PBR_ERR_ARG, "need training and validation sources and rays_per_src >= 1");
+    if (!train_src_dev || !val_src_dev || n_train_src < 1 || n_val_src < 1 || train_rays_per_src < 1 ||
+        val_rays_per_src < 1)
+        return sfail(s, PBR_ERR_ARG, "need training and validation sources and rays per source >= 1");
     if (((uintptr_t)train_src_dev & 15u) || ((uintptr_t)val_src_dev & 15u))
         return sfail(s, PBR_ERR_ARG, "source arrays must be 16-byte aligned");
-    const int64_t n_train = n_train_src * (int64_t)rays_per_src, n_val = n_val_src * (int64_t)rays_per_src;
+    const int64_t n_train = n_train_src * (int64_t)train_rays_per_src, n_val = n_val_src * (int64_t)val_rays_per_src;
     if (n_train > ((int64_t)1 << 31) - 1 || n_val > ((int64_t)1 << 31) - 1)
         return sfail(s, PBR_ERR_ARG, "at most 2^31 - 1 training and validation rays");
     if (!(ds > 0.0) || !std::isfinite(ds)) return sfail(s, PBR_ERR_ARG, "ds must be finite and > 0");
@@ -440,6 +458,7 @@ int pbr_surrogate_train(pbr_surrogate *s, pbr_ctx *ctx, const float *train_src_d
     for (int k = 0; k < 6; ++k) { spec.t_mean[k] = 0.0f; spec.t_scale[k] = 1.0f; }
     spec.tiles = cfg->tiles;
     spec.tile_ok = nullptr;
+    pbr::surrogate_spec_finish(spec);
     const int prec = ctx->n_fp64_bricks > 0 ? pbr::PREC_MIXED : pbr::PREC_FP32;
 
     // scratch of this call, released on every return
@@ -461,9 +480,9 @@ int pbr_surrogate_train(pbr_surrogate *s, pbr_ctx *ctx, const float *train_src_d
 
     // 1. samples from the tracer
     auto t0 = clk::now();
-    int r = trace_samples(s, ctx, P, spec, prec, train_src_dev, n_train_src, rays_per_src, train_seed, trs);
+    int r = trace_samples(s, ctx, P, spec, prec, train_src_dev, n_train_src, train_rays_per_src, train_seed, trs);
     if (r) return r;
-    r = trace_samples(s, ctx, P, spec, prec, val_src_dev, n_val_src, rays_per_src, val_seed, vas);
+    r = trace_samples(s, ctx, P, spec, prec, val_src_dev, n_val_src, val_rays_per_src, val_seed, vas);
     if (r) return r;
     // standardisation from the training samples
     double *part = nullptr;
@@ -474,8 +493,10 @@ int pbr_surrogate_train(pbr_surrogate *s, pbr_ctx *ctx, const float *train_src_d
     if ((e = (int)hipMemcpyAsync(hp.data(), part, hp.size() * sizeof(double), hipMemcpyDeviceToHost, st)))
         return shf(s, e, "copy moments");
     std::vector<int> flags((size_t)n_train);
-    if ((e = (int)hipMemcpy2DAsync(flags.data(), sizeof(int), &trs[0].flags, sizeof(pbr::SurrogateSample),
-                                   sizeof(int), (size_t)n_train, hipMemcpyDeviceToHost, st)))
+    int *dflags = nullptr;
+    if ((e = scr.get((void **)&dflags, (size_t)n_train * sizeof(int)))) return shf(s, e, "hipMalloc(flags)");
+    if ((e = pbr::launch_surr_extract(trs, n_train, 0, dflags, st)) ||
+        (e = (int)hipMemcpyAsync(flags.data(), dflags, (size_t)n_train * sizeof(int), hipMemcpyDeviceToHost, st)))
         return shf(s, e, "copy sample flags");
     if ((e = (int)hipStreamSynchronize(st))) return shf(s, e, "sample trace");
     report->sample_ms = std::chrono::duration<double, std::milli>(clk::now() - t0).count();
@@ -496,6 +517,7 @@ int pbr_surrogate_train(pbr_surrogate *s, pbr_ctx *ctx, const float *train_src_d
     }
     spec.theta = std::sqrt((mom[13] + mom[14]) / (2.0 * N));
     if (!(spec.theta > 0.0)) spec.theta = 1.0;
+    pbr::surrogate_spec_finish(spec);
     std::vector<int> valid;
     valid.reserve((size_t)N);
     for (int64_t i = 0; i < n_train; ++i)
@@ -512,7 +534,40 @@ int pbr_surrogate_train(pbr_surrogate *s, pbr_ctx *ctx, const float *train_src_d
         (e = scr.get((void **)&losses, (size_t)total * sizeof(float))))
         return shf(s, e, "hipMalloc(training)");
     t0 = clk::now();
-    int64_t step = 0;
+    // One training step (gather, forward, backward, loss, Adam with the step counter on the
+    // device) is captured once into a graph on the training stream and replayed for every step;
+    // only the shuffled order is uploaded between epochs.
+    if ((e = (int)hipStreamSynchronize(st))) return shf(s, e, "sample trace");
+    hipStream_t ts = s->train_stream;
+    if ((e = pbr::launch_clear_u64((unsigned long long *)s->step, 1, ts))) return shf(s, e, "clear step");
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    struct GraphGuard {
+        hipGraph_t *g;
+        hipGraphExec_t *x;
+        ~GraphGuard()
+        {
+            if (*x) (void)hipGraphExecDestroy(*x);
+            if (*g) (void)hipGraphDestroy(*g);
+        }
+    } gg{&graph, &exec};
+    if ((e = (int)hipStreamBeginCapture(ts, hipStreamCaptureModeRelaxed))) return shf(s, e, "hipStreamBeginCapture");
+    {
+        int ce = 0;
+        if ((ce = pbr::launch_surr_gather_step(spec, trs, perm, s->step, spe, cfg->batch, s->x, s->t, ts)) ||
+            (ce = pbr::mlp_forward(s->d, s->b, s->x, cfg->batch, s->y, true, ts)) ||
+            (ce = pbr::mlp_backward(s->d, s->b, s->x, s->t, cfg->batch, s->y, ts)) ||
+            (ce = pbr::mlp_loss_mean(s->b, cfg->batch, losses, ts, s->step)) ||
+            (ce = pbr::mlp_adam_sched(s->d, s->step, (int)total, cfg->lr_max, cfg->lr_min, ts)) ||
+            (ce = pbr::mlp_step_advance(s->step, ts))) {
+            hipGraph_t g2 = nullptr;
+            (void)hipStreamEndCapture(ts, &g2);
+            if (g2) (void)hipGraphDestroy(g2);
+            return shf(s, ce, "training step capture");
+        }
+    }
+    if ((e = (int)hipStreamEndCapture(ts, &graph))) return shf(s, e, "hipStreamEndCapture");
+    if ((e = (int)hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0))) return shf(s, e, "hipGraphInstantiate");
     for (int ep = 0; ep < cfg->epochs; ++ep) {
         // Fisher-Yates shuffle driven by SplitMix64
         const uint64_t es = cfg->shuffle_seed + 0x632BE59BD9B4E019ull * (uint64_t)(ep + 1);
@@ -521,20 +576,11 @@ int pbr_surrogate_train(pbr_surrogate *s, pbr_ctx *ctx, const float *train_src_d
             std::swap(valid[i], valid[j]);
         }
         if ((e = (int)hipMemcpyAsync(perm, valid.data(), (size_t)spe * cfg->batch * sizeof(int),
-                                     hipMemcpyHostToDevice, st)))
+                                     hipMemcpyHostToDevice, ts)))
             return shf(s, e, "copy permutation");
-        for (int64_t j = 0; j < spe; ++j, ++step) {
-            const double ph = total > 1 ? (double)step / (double)(total - 1) : 0.0;
-            const float lr =
-                (float)(cfg->lr_min + 0.5 * ((double)cfg->lr_max - cfg->lr_min) * (1.0 + std::cos(3.14159265358979323846 * ph)));
-            if ((e = pbr::launch_surr_gather(spec, trs, perm + j * cfg->batch, cfg->batch, s->x, s->t, st)) ||
-                (e = pbr::mlp_forward(s->d, s->b, s->x, cfg->batch, s->y, true, st)) ||
-                (e = pbr::mlp_backward(s->d, s->b, s->x, s->t, cfg->batch, s->y, st)) ||
-                (e = pbr::mlp_loss_mean(s->b, cfg->batch, losses + step, st)) ||
-                (e = pbr::mlp_adam(s->d, lr, (int)(step + 1), st)))
-                return shf(s, e, "training step");
-        }
-        if ((e = (int)hipStreamSynchronize(st))) return shf(s, e, "training");  // before the next shuffle
+        for (int64_t j = 0; j < spe; ++j)
+            if ((e = (int)hipGraphLaunch(exec, ts))) return shf(s, e, "training step");
+        if ((e = (int)hipStreamSynchronize(ts))) return shf(s, e, "training");  // before the next shuffle
     }
     std::vector<float> hl((size_t)total);
     if ((e = (int)hipMemcpy(hl.data(), losses, hl.size() * sizeof(float), hipMemcpyDeviceToHost)))
@@ -570,11 +616,13 @@ int pbr_surrogate_train(pbr_surrogate *s, pbr_ctx *ctx, const float *train_src_d
     std::vector<unsigned> he((size_t)nt), hc((size_t)nt);
     std::vector<float> herr((size_t)n_val);
     std::vector<int> vtile((size_t)n_val);
+    int *dtile = nullptr;
+    if ((e = scr.get((void **)&dtile, (size_t)n_val * sizeof(int))) || (e = pbr::launch_surr_extract(vas, n_val, 1, dtile, st)))
+        return shf(s, e, "validation tiles");
     if ((e = (int)hipMemcpyAsync(he.data(), tile_err, (size_t)nt * 4, hipMemcpyDeviceToHost, st)) ||
         (e = (int)hipMemcpyAsync(hc.data(), tile_cnt, (size_t)nt * 4, hipMemcpyDeviceToHost, st)) ||
         (e = (int)hipMemcpyAsync(herr.data(), err, (size_t)n_val * 4, hipMemcpyDeviceToHost, st)) ||
-        (e = (int)hipMemcpy2DAsync(vtile.data(), sizeof(int), &vas[0].tile, sizeof(pbr::SurrogateSample), sizeof(int),
-                                   (size_t)n_val, hipMemcpyDeviceToHost, st)))
+        (e = (int)hipMemcpyAsync(vtile.data(), dtile, (size_t)n_val * sizeof(int), hipMemcpyDeviceToHost, st)))
         return shf(s, e, "copy validation");
     if ((e = (int)hipStreamSynchronize(st))) return shf(s, e, "validation");
     s->tile_ok.assign((size_t)nt, 0);
@@ -596,6 +644,7 @@ int pbr_surrogate_train(pbr_surrogate *s, pbr_ctx *ctx, const float *train_src_d
     int64_t n_elig = 0;
     for (int64_t i = 0; i < n_val; ++i) {
         const float x = herr[(size_t)i];
+        if (x == -2.0f) ++report->val_rim_mismatches;
         if (x < 0.0f) continue;
         ev.push_back(x);
         if (s->tile_ok[(size_t)vtile[(size_t)i]]) {

@@ -921,18 +921,19 @@ __device__ __forceinline__ bool entry_of(const TraceParams &P, const RayState &r
 
 __device__ __forceinline__ void surr_features(const SurrogateSpec &sp, const double E[3], const double u[3], float x[6])
 {
-    x[0] = (float)((2.0 * E[0] - sp.x_lo - sp.x_hi) / (sp.x_hi - sp.x_lo));
-    x[1] = (float)((2.0 * E[1] - sp.y_lo - sp.y_hi) / (sp.y_hi - sp.y_lo));
-    x[2] = (float)(u[0] / sp.theta);
-    x[3] = (float)(u[1] / sp.theta);
-    x[4] = (float)sin(kTwoPi * (E[0] - sp.x_lo) / sp.Lx);
-    x[5] = (float)sin(kTwoPi * (E[1] - sp.y_lo) / sp.Ly);
+    x[0] = (float)((2.0 * E[0] - sp.x_lo - sp.x_hi) * sp.inv_wx);
+    x[1] = (float)((2.0 * E[1] - sp.y_lo - sp.y_hi) * sp.inv_wy);
+    x[2] = (float)(u[0] * sp.inv_theta);
+    x[3] = (float)(u[1] * sp.inv_theta);
+    // the periodic encodings in single precision (inputs of an FP32 layer)
+    x[4] = sinf((float)((E[0] - sp.x_lo) * sp.kx));
+    x[5] = sinf((float)((E[1] - sp.y_lo) * sp.ky));
 }
 
 __device__ __forceinline__ int surr_tile(const SurrogateSpec &sp, const double E[3])
 {
-    int tx = (int)((E[0] - sp.x_lo) / (sp.x_hi - sp.x_lo) * sp.tiles);
-    int ty = (int)((E[1] - sp.y_lo) / (sp.y_hi - sp.y_lo) * sp.tiles);
+    int tx = (int)((E[0] - sp.x_lo) * sp.inv_wx * sp.tiles);
+    int ty = (int)((E[1] - sp.y_lo) * sp.inv_wy * sp.tiles);
     tx = min(max(tx, 0), sp.tiles - 1);
     ty = min(max(ty, 0), sp.tiles - 1);
     return ty * sp.tiles + tx;
@@ -961,7 +962,14 @@ __global__ void __launch_bounds__(256) k_surr_samples(TraceParams P, SurrogateSp
     emit_ray(P, first + i, e);  // the entry state again (the trace overwrote it)
     double E[3], u[3];
     const RayState r = st[i];
-    if (entry_of(P, e, E, u) && !(r.info & RS_LIMITED) && r.c[2] == P.nz - 2 && r.fd[2] == 1.0) {
+    const bool enters = entry_of(P, e, E, u);
+    if (enters) {
+        smp.E[0] = E[0];
+        smp.E[1] = E[1];
+        smp.tile = surr_tile(sp, E);
+        smp.flags = 4;
+    }
+    if (enters && !(r.info & RS_LIMITED) && r.c[2] == P.nz - 2 && r.fd[2] == 1.0) {
         double X[3], d[3], Q[3], n2 = 0.0;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
@@ -979,10 +987,7 @@ __global__ void __launch_bounds__(256) k_surr_samples(TraceParams P, SurrogateSp
             smp.t[3 + a] = (float)(d[a] - u[a]);
             smp.u[a] = u[a];
         }
-        smp.E[0] = E[0];
-        smp.E[1] = E[1];
-        smp.tile = surr_tile(sp, E);
-        smp.flags = 1;
+        smp.flags |= 1;
         double xp, yp;
         if (optics_to_sensor(P, X, d, &xp, &yp) == PBR_RAY_DEPOSITED) {
             smp.px[0] = xp;
@@ -993,10 +998,13 @@ __global__ void __launch_bounds__(256) k_surr_samples(TraceParams P, SurrogateSp
     out[i] = smp;
 }
 
+// Features of every ray of the chunk in place (row i = ray i; rows of rays the network does not
+// take are zero and flagged 0 in elig), and the list of the other rays that entered the box for
+// the integration kernel (one atomic per wave that has any).
 __global__ void __launch_bounds__(256) k_surr_features(TraceParams P, SurrogateSpec sp, const RayState *__restrict__ st,
-                                                       int64_t n, int64_t off, float *__restrict__ x,
-                                                       int *__restrict__ idx, unsigned long long *__restrict__ count,
-                                                       int *__restrict__ tlist, unsigned long long *__restrict__ tcount)
+                                                       int64_t n, float *__restrict__ x,
+                                                       unsigned char *__restrict__ elig, int *__restrict__ tlist,
+                                                       unsigned long long *__restrict__ tcount)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int lane = threadIdx.x & 63;
@@ -1007,24 +1015,19 @@ __global__ void __launch_bounds__(256) k_surr_features(TraceParams P, SurrogateS
         ok = entry_of(P, r, E, u);
         if (ok) ok = sp.tile_ok[surr_tile(sp, E)] != 0;
         traced = !ok && (r.info & RS_ENTERED);
-    }
-    // one atomic per wave and list: the lanes of a wave take consecutive slots
-    const unsigned long long below = (1ull << lane) - 1ull;
-    const unsigned long long mask = __ballot(ok), tmask = __ballot(traced);
-    unsigned long long base = 0, tbase = 0;
-    if (lane == 0 && mask) base = atomicAdd(count, (unsigned long long)__popcll(mask));
-    if (lane == 0 && tmask) tbase = atomicAdd(tcount, (unsigned long long)__popcll(tmask));
-    base = __shfl(base, 0);
-    tbase = __shfl(tbase, 0);
-    if (ok) {
-        const int64_t row = (int64_t)base + __popcll(mask & below);
-        float f[6];
-        surr_features(sp, E, u, f);
+        float f[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+        if (ok) surr_features(sp, E, u, f);
 #pragma unroll
-        for (int k = 0; k < 6; ++k) x[row * 6 + k] = f[k];
-        idx[row] = (int)i;
+        for (int k = 0; k < 6; ++k) x[i * 6 + k] = f[k];
+        elig[i] = ok ? 1 : 0;
     }
-    if (traced) tlist[tbase + __popcll(tmask & below)] = (int)(off + i);
+    const unsigned long long tmask = __ballot(traced);
+    if (tmask) {
+        unsigned long long tbase = 0;
+        if (lane == 0) tbase = atomicAdd(tcount, (unsigned long long)__popcll(tmask));
+        tbase = __shfl(tbase, 0);
+        if (traced) tlist[tbase + __popcll(tmask & ((1ull << lane) - 1ull))] = (int)i;
+    }
 }
 
 // Predicted exit: straight exit plus the position change (on z = z_hi), direction u + change.
@@ -1049,19 +1052,18 @@ __device__ __forceinline__ void surr_predict(const SurrogateSpec &sp, const doub
 }
 
 __global__ void __launch_bounds__(256) k_surr_apply(TraceParams P, SurrogateSpec sp, const float *__restrict__ y,
-                                                    const int *__restrict__ idx,
-                                                    const unsigned long long *__restrict__ count, int64_t cap,
+                                                    const unsigned char *__restrict__ elig, int64_t n,
                                                     RayState *__restrict__ st)
 {
-    const unsigned long long live = *count;
-    const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if ((unsigned long long)blockIdx.x * blockDim.x >= live) return;
-    if (row < cap && (unsigned long long)row < live) {
-        const int64_t i = idx[row];
+    __shared__ unsigned s_cnt;
+    if (threadIdx.x == 0) s_cnt = 0u;
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && elig[i]) {
         RayState r = st[i];
         double E[3], u[3], X[3], d[3];
         entry_of(P, r, E, u);
-        surr_predict(sp, E, u, y + row * 6, X, d);
+        surr_predict(sp, E, u, y + i * 6, X, d);
         const int nn[3] = {P.nx, P.ny, P.nz};
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
@@ -1077,8 +1079,10 @@ __global__ void __launch_bounds__(256) k_surr_apply(TraceParams P, SurrogateSpec
         }
         r.info = RS_ENTERED | RS_SURR;
         st[i] = r;
+        atomicAdd(&s_cnt, 1u);
     }
-    if (threadIdx.x == 0 && blockIdx.x == 0) atomic_add_u64(P.counters + CNT_SURR, live < (unsigned long long)cap ? live : (unsigned long long)cap);
+    __syncthreads();
+    if (threadIdx.x == 0 && s_cnt) atomic_add_u64(P.counters + CNT_SURR, (unsigned long long)s_cnt);
 }
 
 __global__ void __launch_bounds__(256) k_surr_validate(TraceParams P, SurrogateSpec sp,
@@ -1089,16 +1093,21 @@ __global__ void __launch_bounds__(256) k_surr_validate(TraceParams P, SurrogateS
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const SurrogateSample s = smp[i];
-    float e = -1.0f;
-    if ((s.flags & 3) == 3) {
+    float e = -1.0f;  // not compared
+    if ((s.flags & 5) == 4) {
+        // entered through the front face but left elsewhere: the network cannot represent it
+        e = 1.0e30f;
+    } else if (s.flags & 1) {
         const double E[3] = {s.E[0], s.E[1], sp.z_lo};
         double X[3], d[3], xp, yp;
         surr_predict(sp, E, s.u, y + i * 6, X, d);
-        if (optics_to_sensor(P, X, d, &xp, &yp) == PBR_RAY_DEPOSITED) {
+        const bool dep = optics_to_sensor(P, X, d, &xp, &yp) == PBR_RAY_DEPOSITED;
+        if (dep && (s.flags & 2))
             e = (float)sqrt((xp - s.px[0]) * (xp - s.px[0]) + (yp - s.px[1]) * (yp - s.px[1]));
-        } else {
-            e = 1.0e30f;  // the prediction left the optics: never acceptable
-        }
+        else if (dep != ((s.flags & 2) != 0))
+            e = -2.0f;  // passes an aperture or lens rim on one side and not the other
+    }
+    if (e >= 0.0f) {
         atomicMax(tile_err + s.tile, __float_as_uint(e));
         atomicAdd(tile_cnt + s.tile, 1u);
     }
@@ -1107,10 +1116,12 @@ __global__ void __launch_bounds__(256) k_surr_validate(TraceParams P, SurrogateS
 
 __global__ void __launch_bounds__(256) k_surr_gather(SurrogateSpec sp, const SurrogateSample *__restrict__ smp,
                                                      const int *__restrict__ idx, int64_t rows, float *__restrict__ x,
-                                                     float *__restrict__ t)
+                                                     float *__restrict__ t, const int *__restrict__ step,
+                                                     int64_t steps_per_epoch)
 {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= rows * 6) return;
+    if (step) idx += (int64_t)(*step % steps_per_epoch) * rows;
     const int64_t m = q / 6;
     const int k = (int)(q % 6);
     const SurrogateSample &s = smp[idx ? (int64_t)idx[m] : m];
@@ -1153,7 +1164,21 @@ __global__ void __launch_bounds__(256) k_surr_moments(const SurrogateSample *__r
     if (threadIdx.x < kMoments) part[blockIdx.x * kMoments + threadIdx.x] = s[threadIdx.x][0];
 }
 
+__global__ void __launch_bounds__(256) k_surr_extract(const SurrogateSample *__restrict__ smp, int64_t n, int field,
+                                                      int *__restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = field ? smp[i].tile : smp[i].flags;
+}
+
 }  // namespace
+
+int launch_surr_extract(const SurrogateSample *smp, int64_t n, int field, int *out, hipStream_t s)
+{
+    if (n <= 0) return 0;
+    hipLaunchKernelGGL(k_surr_extract, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, smp, n, field, out);
+    return (int)hipGetLastError();
+}
 
 int launch_surr_samples(const TraceParams &p, const SurrogateSpec &sp, const RayState *st, int64_t first,
                         int64_t n, SurrogateSample *out, hipStream_t s)
@@ -1163,22 +1188,20 @@ int launch_surr_samples(const TraceParams &p, const SurrogateSpec &sp, const Ray
     return (int)hipGetLastError();
 }
 
-int launch_surr_features(const TraceParams &p, const SurrogateSpec &sp, const RayState *st, int64_t n, int64_t off,
-                         float *x, int *idx, unsigned long long *count, int *tlist, unsigned long long *tcount,
-                         hipStream_t s)
+int launch_surr_features(const TraceParams &p, const SurrogateSpec &sp, const RayState *st, int64_t n, float *x,
+                         unsigned char *elig, int *tlist, unsigned long long *tcount, hipStream_t s)
 {
     if (n <= 0) return 0;
-    hipLaunchKernelGGL(k_surr_features, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, sp, st, n, off, x, idx,
-                       count, tlist, tcount);
+    hipLaunchKernelGGL(k_surr_features, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, sp, st, n, x, elig,
+                       tlist, tcount);
     return (int)hipGetLastError();
 }
 
-int launch_surr_apply(const TraceParams &p, const SurrogateSpec &sp, const float *y, const int *idx,
-                      const unsigned long long *count, int64_t cap, RayState *st, hipStream_t s)
+int launch_surr_apply(const TraceParams &p, const SurrogateSpec &sp, const float *y, const unsigned char *elig,
+                      int64_t n, RayState *st, hipStream_t s)
 {
-    if (cap <= 0) return 0;
-    hipLaunchKernelGGL(k_surr_apply, dim3((unsigned)((cap + 255) / 256)), dim3(256), 0, s, p, sp, y, idx, count,
-                       cap, st);
+    if (n <= 0) return 0;
+    hipLaunchKernelGGL(k_surr_apply, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, sp, y, elig, n, st);
     return (int)hipGetLastError();
 }
 
@@ -1197,7 +1220,15 @@ int launch_surr_gather(const SurrogateSpec &sp, const SurrogateSample *smp, cons
 {
     if (rows <= 0) return 0;
     hipLaunchKernelGGL(k_surr_gather, dim3((unsigned)((rows * 6 + 255) / 256)), dim3(256), 0, s, sp, smp, idx, rows,
-                       x, t);
+                       x, t, (const int *)nullptr, (int64_t)1);
+    return (int)hipGetLastError();
+}
+
+int launch_surr_gather_step(const SurrogateSpec &sp, const SurrogateSample *smp, const int *perm, const int *step,
+                            int64_t steps_per_epoch, int64_t rows, float *x, float *t, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_surr_gather, dim3((unsigned)((rows * 6 + 255) / 256)), dim3(256), 0, s, sp, smp, perm, rows,
+                       x, t, step, steps_per_epoch);
     return (int)hipGetLastError();
 }
 

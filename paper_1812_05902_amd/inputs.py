@@ -140,11 +140,12 @@ def surrogate_turbulence():
     """Surrogate workload: the turbulence BOS scene on a 256^3 grid (field seed 5, node spacing
     0.39 mm), ds = 0.1 mm.  Returns (evaluation, training, validation) scenes that differ only in
     their dots: 1e6 dots x 1000 rays for evaluation (1e9 rays, ray seed 51), 1e4 x 1000 for
-    training (1e7 rays, seed 50), 1e3 x 1000 for validation (1e6 rays, seed 52)."""
+    training (1e7 rays, seed 50), 1e5 x 10 for validation (1e6 rays, seed 52; many dots with few
+    rays each, so that every tile of the entry face receives validation rays)."""
     ev = turbulence_bos(n=256, seed=5, n_src=1_000_000, rays_per_src=1000).replace(
         name="surrogate_turbulence_256", src_seed=510, ray_seed=51)
     tr = ev.replace(n_src=10_000, src_seed=500, ray_seed=50)
-    va = ev.replace(n_src=1_000, src_seed=520, ray_seed=52)
+    va = ev.replace(n_src=100_000, rays_per_src=10, src_seed=520, ray_seed=52)
     return ev, tr, va
 
 

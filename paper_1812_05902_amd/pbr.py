@@ -103,7 +103,7 @@ class pbr_surrogate_train_config(C.Structure):
 
 class pbr_surrogate_report(C.Structure):
     _fields_ = [("train_samples", C.c_int64), ("val_samples", C.c_int64), ("val_eligible", C.c_int64),
-                ("steps", C.c_int32), ("eligible_tiles", C.c_int32), ("loss_first_epoch", C.c_double),
+                ("val_rim_mismatches", C.c_int64), ("steps", C.c_int32), ("eligible_tiles", C.c_int32), ("loss_first_epoch", C.c_double),
                 ("loss_last_epoch", C.c_double), ("val_median_px", C.c_double), ("val_p99_px", C.c_double),
                 ("val_max_px", C.c_double), ("val_max_eligible_px", C.c_double), ("sample_ms", C.c_double),
                 ("train_ms", C.c_double), ("validate_ms", C.c_double)]
@@ -161,7 +161,7 @@ def load(path: str = LIB_PATH):
         "pbr_surrogate_forward": (I, [P, P, I64, P]),
         "pbr_surrogate_gradients": (I, [P, P, P, I64, P, C.POINTER(D)]),
         "pbr_surrogate_adam_step": (I, [P, P, P, I64, C.c_float, C.c_int32, C.POINTER(D)]),
-        "pbr_surrogate_train": (I, [P, P, P, I64, P, I64, C.c_int32, U64, U64, D,
+        "pbr_surrogate_train": (I, [P, P, P, I64, C.c_int32, P, I64, C.c_int32, U64, U64, D,
                                     C.POINTER(pbr_surrogate_train_config), C.POINTER(pbr_surrogate_report)]),
         "pbr_surrogate_tile_map": (I, [P, P, P, I64]),
         "pbr_set_surrogate": (I, [P, P]),
@@ -574,12 +574,13 @@ def pbr_surrogate_adam_step(sg, x, t, lr, step, want_loss=False):
     return float(loss.value) if want_loss else None
 
 
-def pbr_surrogate_train(sg, ctx, train_src, val_src, rays_per_src, train_seed, val_seed, ds,
-                        cfg: pbr_surrogate_train_config) -> pbr_surrogate_report:
+def pbr_surrogate_train(sg, ctx, train_src, train_rays_per_src, val_src, val_rays_per_src, train_seed, val_seed,
+                        ds, cfg: pbr_surrogate_train_config) -> pbr_surrogate_report:
     rep = pbr_surrogate_report()
-    _scheck(sg, load().pbr_surrogate_train(sg, ctx, _dptr(train_src), int(train_src.shape[0]), _dptr(val_src),
-                                           int(val_src.shape[0]), int(rays_per_src), int(train_seed),
-                                           int(val_seed), float(ds), C.byref(cfg), C.byref(rep)))
+    _scheck(sg, load().pbr_surrogate_train(sg, ctx, _dptr(train_src), int(train_src.shape[0]),
+                                           int(train_rays_per_src), _dptr(val_src), int(val_src.shape[0]),
+                                           int(val_rays_per_src), int(train_seed), int(val_seed), float(ds),
+                                           C.byref(cfg), C.byref(rep)))
     return rep
 
 
@@ -627,12 +628,14 @@ class Surrogate:
     def adam_step(self, x, t, lr, step, want_loss=False):
         return pbr_surrogate_adam_step(self.h, self._dev(x), self._dev(t), lr, step, want_loss)
 
-    def train(self, renderer, train_src, val_src, rays_per_src, train_seed, val_seed, ds, batch=4096, epochs=4,
-              lr_max=1e-3, lr_min=1e-5, tol_px=0.01, tiles=64, min_tile_samples=8, shuffle_seed=1) -> dict:
+    def train(self, renderer, train_src, train_rays_per_src, val_src, val_rays_per_src, train_seed, val_seed, ds,
+              batch=4096, epochs=4, lr_max=1e-3, lr_min=1e-5, tol_px=0.01, tiles=64, min_tile_samples=8,
+              shuffle_seed=1) -> dict:
         cfg = pbr_surrogate_train_config(int(batch), int(epochs), float(lr_max), float(lr_min), float(tol_px),
                                          int(tiles), int(min_tile_samples), int(shuffle_seed))
         tr, va = self._dev(train_src), self._dev(val_src)
-        rep = pbr_surrogate_train(self.h, renderer.ctx, tr, va, rays_per_src, train_seed, val_seed, ds, cfg)
+        rep = pbr_surrogate_train(self.h, renderer.ctx, tr, train_rays_per_src, va, val_rays_per_src, train_seed,
+                                  val_seed, ds, cfg)
         self.tiles = int(tiles)
         return {k: getattr(rep, k) for k, _ in pbr_surrogate_report._fields_}
 

@@ -127,7 +127,7 @@ def test_surrogate_in_the_trace(torch):
     tr = inputs.sources(sc.replace(n_src=2000, src_seed=501))
     va = inputs.sources(sc.replace(n_src=1000, src_seed=502))
     s = pbr.Surrogate(init_seed=3, max_rows=1 << 16)
-    rep = s.train(r, tr, va, 100, train_seed=50, val_seed=52, ds=sc.ds, batch=2048, epochs=30,
+    rep = s.train(r, tr, 100, va, 100, train_seed=50, val_seed=52, ds=sc.ds, batch=2048, epochs=30,
                   lr_max=2e-3, lr_min=2e-5, tol_px=0.01, tiles=16, min_tile_samples=8)
     print("train report:", rep)
     assert rep["train_samples"] > 100000 and rep["val_samples"] > 50000
