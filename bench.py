@@ -189,6 +189,9 @@ def bench_batch(args):
         srcs.append(inputs.sources(sc))
         torch.cuda.synchronize()
         del r._rho_keepalive
+        if len(rs) % 8 == 0:
+            print(f"set up {len(rs)}/{len(scenes)} images ({time.perf_counter() - t0:.1f} s)", file=sys.stderr,
+                  flush=True)
     setup_s = time.perf_counter() - t0
     b = pbr.Batch(rs, srcs, [sc.rays_per_src for sc in scenes], [sc.ray_seed for sc in scenes],
                   [sc.ds for sc in scenes], round_rays=1 << 24)
@@ -240,6 +243,7 @@ def bench_tomo(args):
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     cal = r.calibrate_precision(sc.ds, tol_px=1e-3)
+    print(f"set up in {setup_s:.1f} s; calibration {cal}", file=sys.stderr, flush=True)
 
     def step(flags, stats):
         st = r.emit_and_trace(src, sc.rays_per_src, sc.ray_seed, sc.ds, pbr.PBR_CLEAR_FIRST | flags, stats=stats)
