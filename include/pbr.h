@@ -60,6 +60,12 @@ extern "C" {
 #define PBR_PREC_FP64_ALL   (1u << 2)  /* integrate every step in FP64 (default: FP32) */
 #define PBR_PREC_SHOCK_FP64 (1u << 3)  /* FP64 steps inside the bricks flagged by pbr_calibrate_precision */
 #define PBR_SURROGATE       (1u << 4)  /* rays entering through eligible tiles take the attached surrogate's exit */
+#define PBR_LANE_REFILL     (1u << 5)  /* FP32 integration by persistent waves whose lanes take a new ray as
+                                          soon as theirs leaves the box, instead of one thread per ray; same
+                                          results bit for bit.  Off by default: lanes then hold rays of
+                                          different sources, which costs more cell gathers than the idle
+                                          lanes it saves (measured 4% slower on the 128^3 BOS scene, 16% on
+                                          the 512^3 Tomo-PIV scene) */
 
 /* ---------------------------------------------------------------- pbr_read_image formats */
 #define PBR_FMT_RAW_U64 0  /* copy of the Q32.32 accumulator (uint64 per pixel) */

@@ -381,7 +381,7 @@ int pbr_emit_and_trace(pbr_ctx *ctx, const float *src_dev, int64_t n_src, int32_
     if (!(d.z_sensor > ctx->optics.z_front_vertex + d.t))
         return fail(ctx, PBR_ERR_ARG, "sensor plane must lie behind the lens");
     if (flags & ~(uint32_t)(PBR_CLEAR_FIRST | PBR_RECORD_EXITS | PBR_PREC_FP64_ALL | PBR_PREC_SHOCK_FP64 |
-                            PBR_SURROGATE))
+                            PBR_SURROGATE | PBR_LANE_REFILL))
         return fail(ctx, PBR_ERR_ARG, "unknown flag bits 0x%x", flags);
     pbr::ChunkHook hook{nullptr, nullptr};
     if (flags & PBR_SURROGATE) {
@@ -434,7 +434,7 @@ int pbr_emit_and_trace(pbr_ctx *ctx, const float *src_dev, int64_t n_src, int32_
         const int64_t n = P.n_rays - first < ctx->ray_chunk ? P.n_rays - first : ctx->ray_chunk;
         e = pbr::launch_trace_chunk(P, ctx->ray_ws, first, n, prec, ctx->stream,
                                     stats ? ctx->box_ev[2 * k] : nullptr, stats ? ctx->box_ev[2 * k + 1] : nullptr,
-                                    hook.run ? &hook : nullptr);
+                                    hook.run ? &hook : nullptr, true, (flags & PBR_LANE_REFILL) != 0);
         if (e) return hip_fail(ctx, e, "trace launch");
     }
     if (stats && (e = (int)hipEventRecord(ctx->ev1, ctx->stream))) return hip_fail(ctx, e, "hipEventRecord");

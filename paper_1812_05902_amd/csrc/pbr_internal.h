@@ -16,7 +16,8 @@ enum : int {
     CNT_MAXPIX = PBR_NUM_STATUS + 2,      // largest accumulator value (readout)
     CNT_STEPS64 = PBR_NUM_STATUS + 3,     // Runge-Kutta steps taken in FP64 (mixed precision)
     CNT_SURR = PBR_NUM_STATUS + 4,        // rays whose box passage the surrogate network replaced
-    CNT_SLOTS = 16
+    CNT_SLOTS = 16,
+    CNT_QUEUE = 32                        // ray queue of the refill integration kernel (not a statistic)
 };
 
 constexpr int kMaxFootprint = 8;          // deposit window half-width limit (sigma <= 2.67 px)
@@ -224,7 +225,7 @@ int launch_batch_round(const TraceParams *params, const BatchSeg *segs, int nseg
 enum PrecMode : int { PREC_FP32 = 0, PREC_FP64 = 1, PREC_MIXED = 2 };
 int launch_trace_chunk(const TraceParams &p, RayState *st, int64_t first, int64_t n, int prec,
                        hipStream_t stream, hipEvent_t box_begin, hipEvent_t box_end,
-                       const ChunkHook *hook = nullptr, bool deposit = true);
+                       const ChunkHook *hook = nullptr, bool deposit = true, bool refill = false);
 int launch_readout(const unsigned long long *accum, int64_t npx, int fmt, void *out,
                    double gain, unsigned long long *counters, hipStream_t stream);
 int launch_clear_u64(unsigned long long *p, int64_t n, hipStream_t stream);

@@ -137,11 +137,73 @@ template <typename T> __device__ __forceinline__ T pick3(const T v[3], int k)
     return k == 0 ? v[0] : (k == 1 ? v[1] : v[2]);
 }
 
-// Integrate from the cell-local state until the ray leaves the box.  Exit rule: before each
-// step find the smallest straight-line step fraction lam at which the ray reaches a face it moves
-// towards; if lam <= 1 take one step of lam (when lam > 0), then move straight along the new T
-// onto that face.  Returns the number of steps; sets *limited when max_steps is exceeded.
-// (Per-axis values are selected with pick3 / unrolled loops: no dynamically indexed arrays.)
+// Exit rule: before each step find the smallest straight-line step fraction lam at which the ray
+// reaches a face it moves towards; if lam <= 1 take one step of lam (when lam > 0), then move
+// straight along the new T onto that face.  (Per-axis values are selected with pick3 / unrolled
+// loops: no dynamically indexed arrays.)
+enum : int { STEP_GO = 0, STEP_EXIT = 1, STEP_LIMIT = 2 };
+
+// One iteration of the integration: a full step, or (when the straight line of a full step reaches
+// a face the ray moves towards) the partial step of fraction lam and, if the ray still heads out,
+// the straight move onto that face.  Returns STEP_EXIT when the ray left the box, STEP_LIMIT when
+// it ran out of steps, STEP_GO otherwise.
+template <typename F>
+__device__ __forceinline__ int trace_step(const TraceParams &P, CellCache &cc, int c[3], double fd[3], const F Tr[3],
+                                          F dT[3], const F g[3], F hstep, const int last[3], int &steps)
+{
+    // cheap test first: does the straight line of a full step reach a face?  (distances in
+    // cell units against the per-step displacement; no division)
+    // (bitwise, not short-circuit: one branch for the whole test instead of one per clause)
+    bool near = false;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const F v = g[a] * (Tr[a] + dT[a]);
+        const F fa = (F)fd[a];
+        const bool up = (v > (F)0) & ((F)(last[a] - c[a]) - fa <= v);
+        const bool down = (v < (F)0) & ((F)(-c[a]) - fa >= v);
+        near = near | up | down;
+    }
+    if (near) {
+        F lam = (F)3.0e38;
+        int ax = -1;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const F v = g[a] * (Tr[a] + dT[a]);
+            F l = (F)3.0e38;
+            if (v > (F)0) l = (F)((double)(last[a] - c[a]) - fd[a]) / v;
+            else if (v < (F)0) l = (F)((double)(-c[a]) - fd[a]) / v;
+            if (l < lam) { lam = l; ax = a; }
+        }
+        if (ax >= 0 && lam <= (F)1) {
+            const bool up = (pick3<F>(Tr, ax) + pick3<F>(dT, ax)) > (F)0;
+            if (lam > (F)0) { rkn_step<F, false>(P, cc, c, fd, Tr, dT, g, hstep, lam); ++steps; }
+            const F Tn[3] = {Tr[0] + dT[0], Tr[1] + dT[1], Tr[2] + dT[2]};
+            const F Ta = pick3<F>(Tn, ax);
+            if (up ? (Ta > (F)0) : (Ta < (F)0)) {
+                const int la = pick3<int>(last, ax);
+                const double target = up ? (double)la : 0.0;
+                const double l2 = (target - ((double)pick3<int>(c, ax) + pick3<double>(fd, ax))) /
+                                  ((double)pick3<F>(g, ax) * (double)Ta);
+#pragma unroll
+                for (int b = 0; b < 3; ++b) {
+                    if (b == ax) {
+                        c[b] = up ? la - 1 : 0;
+                        fd[b] = up ? 1.0 : 0.0;
+                    } else {
+                        fd[b] += l2 * (double)g[b] * (double)Tn[b];
+                    }
+                }
+                return STEP_EXIT;
+            }
+            return steps > P.max_steps ? STEP_LIMIT : STEP_GO;  // turned back within the last step
+        }
+    }
+    rkn_step<F, true>(P, cc, c, fd, Tr, dT, g, hstep, (F)1);
+    return ++steps > P.max_steps ? STEP_LIMIT : STEP_GO;
+}
+
+// Integrate from the cell-local state until the ray leaves the box (see trace_step).  Returns the
+// number of steps; sets *limited when max_steps is exceeded.
 template <typename F>
 __device__ __forceinline__ int trace_box(const TraceParams &P, CellCache &cc, int c[3], double fd[3],
                                          const F Tr[3], F dT[3], bool *limited)
@@ -150,58 +212,12 @@ __device__ __forceinline__ int trace_box(const TraceParams &P, CellCache &cc, in
     const F hstep = (F)P.h;
     const int last[3] = {P.nx - 1, P.ny - 1, P.nz - 1};
     int steps = 0;
-    *limited = false;
     for (;;) {
-        // cheap test first: does the straight line of a full step reach a face?  (distances in
-        // cell units against the per-step displacement; no division)
-        // (bitwise, not short-circuit: one branch for the whole test instead of one per clause)
-        bool near = false;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            const F v = g[a] * (Tr[a] + dT[a]);
-            const F fa = (F)fd[a];
-            const bool up = (v > (F)0) & ((F)(last[a] - c[a]) - fa <= v);
-            const bool down = (v < (F)0) & ((F)(-c[a]) - fa >= v);
-            near = near | up | down;
+        const int r = trace_step<F>(P, cc, c, fd, Tr, dT, g, hstep, last, steps);
+        if (r != STEP_GO) {
+            *limited = r == STEP_LIMIT;
+            return steps;
         }
-        if (near) {
-            F lam = (F)3.0e38;
-            int ax = -1;
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                const F v = g[a] * (Tr[a] + dT[a]);
-                F l = (F)3.0e38;
-                if (v > (F)0) l = (F)((double)(last[a] - c[a]) - fd[a]) / v;
-                else if (v < (F)0) l = (F)((double)(-c[a]) - fd[a]) / v;
-                if (l < lam) { lam = l; ax = a; }
-            }
-            if (ax >= 0 && lam <= (F)1) {
-                const bool up = (pick3<F>(Tr, ax) + pick3<F>(dT, ax)) > (F)0;
-                if (lam > (F)0) { rkn_step<F, false>(P, cc, c, fd, Tr, dT, g, hstep, lam); ++steps; }
-                const F Tn[3] = {Tr[0] + dT[0], Tr[1] + dT[1], Tr[2] + dT[2]};
-                const F Ta = pick3<F>(Tn, ax);
-                if (up ? (Ta > (F)0) : (Ta < (F)0)) {
-                    const int la = pick3<int>(last, ax);
-                    const double target = up ? (double)la : 0.0;
-                    const double l2 = (target - ((double)pick3<int>(c, ax) + pick3<double>(fd, ax))) /
-                                      ((double)pick3<F>(g, ax) * (double)Ta);
-#pragma unroll
-                    for (int b = 0; b < 3; ++b) {
-                        if (b == ax) {
-                            c[b] = up ? la - 1 : 0;
-                            fd[b] = up ? 1.0 : 0.0;
-                        } else {
-                            fd[b] += l2 * (double)g[b] * (double)Tn[b];
-                        }
-                    }
-                    return steps;
-                }
-                if (steps > P.max_steps) { *limited = true; return steps; }
-                continue;  // turned back by the field within the last step
-            }
-        }
-        rkn_step<F, true>(P, cc, c, fd, Tr, dT, g, hstep, (F)1);
-        if (++steps > P.max_steps) { *limited = true; return steps; }
     }
 }
 
@@ -447,6 +463,69 @@ __global__ void __launch_bounds__(256) k_box64(TraceParams P, RayState *__restri
                                                const unsigned long long *__restrict__ count)
 {
     box_body<double>(P, st, n, list, count);
+}
+
+// Persistent FP32 integration with lane refill: a fixed grid of waves (five per SIMD) takes rays
+// from one queue; a lane whose ray has left the box takes the next one at once, one atomic per
+// wave for all lanes that need a ray, so that short and long paths do not leave lanes idle until
+// the longest ray of a wave is done.  Same per-ray arithmetic as k_box32 (bit-identical states).
+// *queue must be zero at launch; every wave leaves once the queue is drained and its lanes idle.
+__global__ void __launch_bounds__(256, 5) k_box32_refill(TraceParams P, RayState *__restrict__ st, int64_t n,
+                                                         const int *__restrict__ list,
+                                                         const unsigned long long *__restrict__ count,
+                                                         unsigned long long *__restrict__ queue)
+{
+    const int lane = threadIdx.x & 63;
+    const unsigned long long total = list ? *count : (unsigned long long)n;
+    const float g[3] = {(float)P.step_cell[0], (float)P.step_cell[1], (float)P.step_cell[2]};
+    const float hstep = (float)P.h;
+    const int last[3] = {P.nx - 1, P.ny - 1, P.nz - 1};
+    int64_t i = -1;  // this lane's ray, -1: none
+    RayState r;
+    float Tr[3], dT[3];
+    CellCache cc;
+    int steps = 0;
+    bool drained = false;  // the queue had nothing left for this wave
+    for (;;) {
+        const bool need = i < 0;
+        const unsigned long long want = __ballot(need);
+        if (want && !drained) {
+            unsigned long long base = 0;
+            if (lane == 0) base = atomicAdd(queue, (unsigned long long)__popcll(want));
+            base = __shfl(base, 0);
+            if (base + (unsigned long long)__popcll(want) >= total) drained = true;
+            if (need) {
+                const unsigned long long k = base + __popcll(want & ((1ull << lane) - 1ull));
+                if (k < total) {
+                    const int64_t j = list ? (int64_t)list[k] : (int64_t)k;
+                    r = st[j];
+                    if ((r.info & (RS_ENTERED | RS_SURR)) == RS_ENTERED) {
+                        i = j;
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) { Tr[a] = r.Tr[a]; dT[a] = r.dT[a]; }
+                        cc.ix = -1;
+                        steps = 0;
+                    }
+                }
+            }
+            continue;  // lanes that drew a ray with nothing to integrate draw again
+        }
+        if (__ballot(i >= 0) == 0) break;  // queue drained and no lane busy
+        if (i >= 0) {
+            const int res = trace_step<float>(P, cc, r.c, r.fd, Tr, dT, g, hstep, last, steps);
+            if (res != STEP_GO) {
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const double T = (double)Tr[a] + (double)dT[a];
+                    r.Tr[a] = (float)T;
+                    r.dT[a] = (float)(T - (double)r.Tr[a]);
+                }
+                r.info = RS_ENTERED | (res == STEP_LIMIT ? RS_LIMITED : 0) | (steps << RS_STEP_SHIFT);
+                st[i] = r;
+                i = -1;
+            }
+        }
+    }
 }
 
 // ------------------------------------------------------------------ mixed precision
@@ -1253,7 +1332,7 @@ int launch_calibrate(const TraceParams &p, const int *bricks, int n_bricks, int 
 
 int launch_trace_chunk(const TraceParams &p, RayState *st, int64_t first, int64_t n, int prec,
                        hipStream_t stream, hipEvent_t box_begin, hipEvent_t box_end, const ChunkHook *hook,
-                       bool deposit)
+                       bool deposit, bool refill)
 {
     if (n <= 0) return 0;
     const unsigned blocks = (unsigned)((n + 255) / 256);
@@ -1267,7 +1346,16 @@ int launch_trace_chunk(const TraceParams &p, RayState *st, int64_t first, int64_
         hipLaunchKernelGGL(k_box64, dim3(blocks), dim3(256), 0, stream, p, st, n, tl.idx, tl.count);
     else if (prec == PREC_MIXED)
         hipLaunchKernelGGL(k_box_mixed, dim3(blocks), dim3(256), 0, stream, p, st, n, tl.idx, tl.count);
-    else
+    else if (refill) {
+        // persistent grid: five 256-thread blocks per compute unit, fewer for small chunks
+        int dev = 0, ncu = 256;
+        if (hipGetDevice(&dev) == hipSuccess)
+            (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+        const unsigned pblocks = (unsigned)ncu * 5u < blocks ? (unsigned)ncu * 5u : blocks;
+        if ((e = launch_clear_u64(p.counters + CNT_QUEUE, 1, stream))) return e;
+        hipLaunchKernelGGL(k_box32_refill, dim3(pblocks), dim3(256), 0, stream, p, st, n, tl.idx, tl.count,
+                           p.counters + CNT_QUEUE);
+    } else
         hipLaunchKernelGGL(k_box32, dim3(blocks), dim3(256), 0, stream, p, st, n, tl.idx, tl.count);
     e = (int)hipGetLastError();
     if (e) return e;

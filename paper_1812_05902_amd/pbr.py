@@ -24,6 +24,7 @@ PBR_OK, PBR_ERR_ARG, PBR_ERR_STATE, PBR_ERR_HIP, PBR_ERR_WORKSPACE, PBR_ERR_OVER
  PBR_RAY_TIR, PBR_RAY_STEP_LIMIT, PBR_RAY_MISSED) = range(7)
 PBR_NUM_STATUS = 7
 PBR_CLEAR_FIRST, PBR_RECORD_EXITS, PBR_PREC_FP64_ALL, PBR_PREC_SHOCK_FP64, PBR_SURROGATE = 1, 2, 4, 8, 16
+PBR_LANE_REFILL = 32
 PBR_SURR_PARAMS = 200710
 PBR_FMT_RAW_U64, PBR_FMT_F32, PBR_FMT_U16 = 0, 1, 2
 

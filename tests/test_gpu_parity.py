@@ -185,3 +185,34 @@ def test_turbulence_bos_full_size_sampled(torch):
     ndep = st["status"][pbr.PBR_RAY_DEPOSITED]
     assert total <= ndep * (1 + 1e-6)
     assert total >= 0.99 * ndep
+
+
+@pytest.mark.parametrize("make", [lambda: inputs.tiny_bos().replace(n_src=333, rays_per_src=37),
+                                  lambda: inputs.tomo_piv_shock(n=48, n_src=3000, rays_per_src=50).replace(
+                                      width=512, height=512, pitch=40e-6)],
+                         ids=["tiny_bos_ragged", "piv_shock_48"])
+def test_lane_refill_equals_one_thread_per_ray(torch, make):
+    """The persistent integration kernel whose lanes take a new ray as soon as theirs leaves the box
+    gives the same exit states, step counts and image, bit for bit, as one thread per ray; with
+    chunks smaller than the image (several launches, each draining its own queue)."""
+    sc = make()
+    src = inputs.sources(sc)
+    out = []
+    for flags in (pbr.PBR_LANE_REFILL, 0):
+        r2 = pbr.Renderer(rays_per_chunk=40000)
+        r2.set_density_field(inputs.density(sc), sc.origin, sc.spacing, sc.K, sc.rho_inf)
+        r2.set_optics(sc.z_lens, sc.focal_length, sc.f_number, sc.thickness, sc.n_glass, sc.clear_radius,
+                      sc.z_focus)
+        r2.set_sensor(sc.width, sc.height, sc.pitch, sc.z_sensor, sc.wavelength, sc.sigma_px, sc.dtau_with_pi)
+        r2.set_exit_recording(0, 1, sc.n_rays)
+        st = r2.emit_and_trace(src, sc.rays_per_src, sc.ray_seed, sc.ds,
+                               pbr.PBR_CLEAR_FIRST | pbr.PBR_RECORD_EXITS | flags, stats=True)
+        out.append((pbr.u64_image_to_numpy(r2.read_image()), r2.read_ray_exits(), st))
+        r2.close()
+    (img_a, rec_a, st_a), (img_b, rec_b, st_b) = out
+    print(f"refill: {st_a['box_ms']:.3f} ms, one thread per ray: {st_b['box_ms']:.3f} ms "
+          f"({st_a['box_launches']} launches, {st_a['rkn_steps']} steps)")
+    assert np.array_equal(img_a, img_b)
+    for f in pbr.RAY_EXIT_DTYPE.names:
+        assert np.array_equal(rec_a[f], rec_b[f]), f
+    assert st_a["status"] == st_b["status"] and st_a["rkn_steps"] == st_b["rkn_steps"]
