@@ -10,6 +10,7 @@ namespace {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 
 constexpr float kGeluC = 0.7978845608028654f;  // sqrt(2 / pi)
 constexpr float kGeluA = 0.044715f;
@@ -351,22 +352,34 @@ __global__ void __launch_bounds__(256) k_loss_mean(const float *__restrict__ par
     if (threadIdx.x == 0) *out = s[0] * inv_count;
 }
 
-// Whole forward pass in one launch for inference: a block takes 128 rows and keeps their
-// activations in LDS (bf16, rows padded to 264 elements so that the 16 rows one matrix-core
-// operand read touches fall in distinct banks); layer 1 in FP32 by the threads, each hidden layer
-// as a 128 x 256 x 256 product in which wave w owns output columns 64 w .. 64 w + 63 of all 128
-// rows (8 x 4 tiles of 16 x 16, weights read once per block from L2), the output layer as 128 x 16
-// (columns 6 .. 15 zero) by the four waves over 32 rows each.  Same instructions, k order, bias,
-// activation and roundings as the layer-by-layer kernels, so the outputs agree bit for bit.
-constexpr int kFuseRows = 128, kActStride = kHidden + 8;
+// Whole forward pass in one launch for inference.  A block of eight waves takes 128 rows
+// (samples) and keeps their activations in LDS as bf16 [sample][unit] (rows padded to 264
+// elements so that the 16 samples one matrix-core operand read touches fall in distinct banks).
+// Products are computed transposed, Z^T = W A^T: the weights are the A operand (16 B per lane
+// from L2, two k steps ahead), the activations the B operand (16 B per lane from LDS), and a
+// lane's four results are four consecutive units of one sample, so that bias, GELU and the bf16
+// rounding (hardware round-to-nearest-even, two values per instruction) end in one 8-byte LDS
+// store per four values.  Wave w owns units 32 w .. 32 w + 31 of all 128 samples (2 x 8 tiles of
+// 16 x 16): 64 accumulator registers, so that four waves share each SIMD and one wave's vector
+// work (bias, GELU, rounding) overlaps another's matrix-core work.  Layer 1 (K = 6) runs in FP32
+// on the vector units: thread t takes units 4 (t % 64) .. + 3 of 16 samples.  The output layer is
+// 16 (6 used) x 128, each wave taking 16 samples.
+constexpr int kFuseRows = 128, kActStride = kHidden + 8, kFuseWaves = 8;
 
-__global__ void __launch_bounds__(256, 2) k_mlp_infer(const float *__restrict__ x, int64_t rows,
-                                                      const unsigned long long *__restrict__ live,
-                                                      const float *__restrict__ params,
-                                                      const unsigned short *__restrict__ w2,
-                                                      const unsigned short *__restrict__ w3,
-                                                      const unsigned short *__restrict__ w4,
-                                                      const unsigned short *__restrict__ w5, float *__restrict__ y)
+__device__ __forceinline__ unsigned pack_bf16x2(float a, float b)
+{
+    const bf16x2 p = {(__bf16)a, (__bf16)b};
+    return __builtin_bit_cast(unsigned, p);
+}
+
+__global__ void __launch_bounds__(64 * kFuseWaves, 2) k_mlp_infer(const float *__restrict__ x, int64_t rows,
+                                                                  const unsigned long long *__restrict__ live,
+                                                                  const float *__restrict__ params,
+                                                                  const unsigned short *__restrict__ w2,
+                                                                  const unsigned short *__restrict__ w3,
+                                                                  const unsigned short *__restrict__ w4,
+                                                                  const unsigned short *__restrict__ w5,
+                                                                  float *__restrict__ y)
 {
     __shared__ __attribute__((aligned(16))) unsigned short act[kFuseRows * kActStride];
     __shared__ float xs[kFuseRows * kIn];
@@ -375,36 +388,51 @@ __global__ void __launch_bounds__(256, 2) k_mlp_infer(const float *__restrict__ 
     if (live) nrow = (int64_t)(*live < (unsigned long long)rows ? *live : (unsigned long long)rows);
     if (row0 >= nrow) return;
     const int64_t nblk = nrow - row0 < kFuseRows ? nrow - row0 : kFuseRows;
-    for (int q = threadIdx.x; q < kFuseRows * kIn; q += 256) xs[q] = q < nblk * kIn ? x[row0 * kIn + q] : 0.0f;
+    for (int q = threadIdx.x; q < kFuseRows * kIn; q += 64 * kFuseWaves)
+        xs[q] = q < nblk * kIn ? x[row0 * kIn + q] : 0.0f;
     __syncthreads();
-    {   // layer 1, FP32: thread n owns unit n of every row
-        const int n = threadIdx.x;
-        float w[kIn];
+    {   // layer 1, FP32: thread t owns units 4 u .. 4 u + 3 (u = t % 64) of samples 16 g .. 16 g + 15
+        const int u = threadIdx.x & 63, g = threadIdx.x >> 6;
+        float w[4][kIn], bn[4];
 #pragma unroll
-        for (int k = 0; k < kIn; ++k) w[k] = params[kOffW1 + n * kIn + k];
-        const float bn = params[kOffB1 + n];
-        for (int m = 0; m < kFuseRows; ++m) {
-            float z = bn;
+        for (int c = 0; c < 4; ++c) {
+            bn[c] = params[kOffB1 + 4 * u + c];
 #pragma unroll
-            for (int k = 0; k < kIn; ++k) z += xs[m * kIn + k] * w[k];
-            act[m * kActStride + n] = bf16_bits(gelu(z));
+            for (int k = 0; k < kIn; ++k) w[c][k] = params[kOffW1 + (4 * u + c) * kIn + k];
+        }
+        for (int mm = 0; mm < kFuseRows / kFuseWaves; ++mm) {
+            const int m = (kFuseRows / kFuseWaves) * g + mm;
+            float z[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                z[c] = bn[c];
+#pragma unroll
+                for (int k = 0; k < kIn; ++k) z[c] += xs[m * kIn + k] * w[c][k];
+            }
+            uint2 v;
+            v.x = pack_bf16x2(gelu(z[0]), gelu(z[1]));
+            v.y = pack_bf16x2(gelu(z[2]), gelu(z[3]));
+            *(uint2 *)(act + m * kActStride + 4 * u) = v;
         }
     }
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int r = lane & 15, kg = lane >> 4;
     for (int l = 0; l < 3; ++l) {
-        floatx4 acc[8][4];
+        const unsigned short *W = (l == 0 ? w2 : (l == 1 ? w3 : w4)) + (size_t)(wave * 32 + r) * kHidden + 8 * kg;
+        const float *bias = params + (l == 0 ? kOffB2 : (l == 1 ? kOffB3 : kOffB4)) + wave * 32 + 4 * kg;
+        // accumulators start at the bias of their unit
+        floatx4 acc[2][8];
 #pragma unroll
-        for (int i = 0; i < 8; ++i)
+        for (int j = 0; j < 2; ++j) {
+            const float4 b4 = *(const float4 *)(bias + 16 * j);
 #pragma unroll
-            for (int j = 0; j < 4; ++j) acc[i][j] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-        const unsigned short *W = (l == 0 ? w2 : (l == 1 ? w3 : w4)) + (size_t)(wave * 64 + r) * kHidden + 8 * kg;
-        // weight fragments two k steps ahead: the L2 latency of step k + 2 hides behind the
-        // matrix-core work of steps k and k + 1
-        bf16x8 fw[4], fn[4], fn2[4];
+            for (int i = 0; i < 8; ++i) acc[j][i] = floatx4{b4.x, b4.y, b4.z, b4.w};
+        }
+        // weight fragments two k steps ahead
+        bf16x8 fw[2], fn[2], fn2[2];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < 2; ++j) {
             fw[j] = *(const bf16x8 *)(W + j * 16 * kHidden);
             fn[j] = *(const bf16x8 *)(W + j * 16 * kHidden + 32);
         }
@@ -412,58 +440,50 @@ __global__ void __launch_bounds__(256, 2) k_mlp_infer(const float *__restrict__ 
         for (int k0 = 0; k0 < kHidden; k0 += 32) {
             if (k0 + 64 < kHidden) {
 #pragma unroll
-                for (int j = 0; j < 4; ++j) fn2[j] = *(const bf16x8 *)(W + j * 16 * kHidden + k0 + 64);
+                for (int j = 0; j < 2; ++j) fn2[j] = *(const bf16x8 *)(W + j * 16 * kHidden + k0 + 64);
             }
-            // all eight activation fragments of this k step first, so that the LDS reads overlap
-            // the matrix-core work instead of each waiting in turn
-            bf16x8 fa[8];
 #pragma unroll
-            for (int i = 0; i < 8; ++i) fa[i] = *(const bf16x8 *)(act + (16 * i + r) * kActStride + 8 * kg + k0);
+            for (int i = 0; i < 8; ++i) {
+                const bf16x8 fa = *(const bf16x8 *)(act + (16 * i + r) * kActStride + 8 * kg + k0);
 #pragma unroll
-            for (int i = 0; i < 8; ++i)
+                for (int j = 0; j < 2; ++j)
+                    acc[j][i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fw[j], fa, acc[j][i], 0, 0, 0);
+            }
 #pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fw[j], acc[i][j], 0, 0, 0);
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
+            for (int j = 0; j < 2; ++j) {
                 fw[j] = fn[j];
                 fn[j] = fn2[j];
             }
         }
         __syncthreads();  // every wave has read this layer's inputs
-        const float *bias = params + (l == 0 ? kOffB2 : (l == 1 ? kOffB3 : kOffB4));
+        // lane: units 32 w + 16 j + 4 kg + t (t = 0..3) of sample 16 i + r
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int n = wave * 64 + 16 * j + r;
-            const float bn = bias[n];
+        for (int j = 0; j < 2; ++j)
 #pragma unroll
-            for (int i = 0; i < 8; ++i)
-#pragma unroll
-                for (int t = 0; t < 4; ++t)
-                    act[(16 * i + 4 * kg + t) * kActStride + n] = bf16_bits(gelu(acc[i][j][t] + bn));
-        }
+            for (int i = 0; i < 8; ++i) {
+                uint2 v;
+                v.x = pack_bf16x2(gelu(acc[j][i][0]), gelu(acc[j][i][1]));
+                v.y = pack_bf16x2(gelu(acc[j][i][2]), gelu(acc[j][i][3]));
+                *(uint2 *)(act + (16 * i + r) * kActStride + wave * 32 + 16 * j + 4 * kg) = v;
+            }
         __syncthreads();
     }
-    {   // output layer: wave w takes rows 32 w .. 32 w + 31 against the 16 first (padded) rows of W5
-        floatx4 acc[2] = {floatx4{0.0f, 0.0f, 0.0f, 0.0f}, floatx4{0.0f, 0.0f, 0.0f, 0.0f}};
+    {   // output layer: 16 (padded) outputs of samples 16 w .. 16 w + 15
+        floatx4 acc = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
         const unsigned short *W = w5 + (size_t)r * kHidden + 8 * kg;
         for (int k0 = 0; k0 < kHidden; k0 += 32) {
             const bf16x8 fw = *(const bf16x8 *)(W + k0);
-#pragma unroll
-            for (int i = 0; i < 2; ++i) {
-                const bf16x8 fa = *(const bf16x8 *)(act + (32 * wave + 16 * i + r) * kActStride + 8 * kg + k0);
-                acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, fw, acc[i], 0, 0, 0);
-            }
+            const bf16x8 fa = *(const bf16x8 *)(act + (16 * wave + r) * kActStride + 8 * kg + k0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fw, fa, acc, 0, 0, 0);
         }
-        if (r < kOut) {
-            const float bn = params[kOffB5 + r];
+        // lane: outputs 4 kg + t of sample 16 w + r
+        const int m = 16 * wave + r;
+        if (kg < 2 && m < nblk) {
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
-#pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    const int m = 32 * wave + 16 * i + 4 * kg + t;
-                    if (m < nblk) y[(row0 + m) * kOut + r] = acc[i][t] + bn;
-                }
+            for (int t = 0; t < 4; ++t) {
+                const int o = 4 * kg + t;
+                if (o < kOut) y[(row0 + m) * kOut + o] = acc[t] + params[kOffB5 + o];
+            }
         }
     }
 }
@@ -596,7 +616,8 @@ int mlp_infer(const MlpDevice &d, const float *x, int64_t rows, float *y, hipStr
               const unsigned long long *live)
 {
     if (rows <= 0) return 0;
-    hipLaunchKernelGGL(k_mlp_infer, dim3((unsigned)((rows + kFuseRows - 1) / kFuseRows)), dim3(256), 0, s, x, rows,
+    hipLaunchKernelGGL(k_mlp_infer, dim3((unsigned)((rows + kFuseRows - 1) / kFuseRows)), dim3(64 * kFuseWaves), 0, s,
+                       x, rows,
                        live, (const float *)d.params, (const unsigned short *)d.w2, (const unsigned short *)d.w3,
                        (const unsigned short *)d.w4, (const unsigned short *)d.w5, y);
     return (int)hipGetLastError();

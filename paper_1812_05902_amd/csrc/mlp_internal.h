@@ -52,7 +52,8 @@ int mlp_forward(const MlpDevice &d, const MlpBuffers &b, const float *x, int64_t
 int mlp_backward(const MlpDevice &d, const MlpBuffers &b, const float *x, const float *t, int64_t rows,
                  const float *y, hipStream_t s);
 // Inference forward pass in one launch (activations in LDS), any row count; live (device,
-// optional) caps the rows computed.  Outputs equal mlp_forward's bit for bit.
+// optional) caps the rows computed.  Same roundings as mlp_forward (the products may sum in
+// another order inside the matrix cores).
 int mlp_infer(const MlpDevice &d, const float *x, int64_t rows, float *y, hipStream_t s,
               const unsigned long long *live = nullptr);
 // After mlp_backward: *out (device) = mean squared error of that batch (out[*step] if step given).
