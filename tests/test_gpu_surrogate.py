@@ -173,3 +173,23 @@ def test_surrogate_in_the_trace(torch):
         r.emit_and_trace(ev, 100, 51, sc.ds, pbr.PBR_CLEAR_FIRST | pbr.PBR_SURROGATE)
     s.close()
     r.close()
+
+
+def test_training_is_deterministic(torch):
+    """Two trainings with the same seeds give the same parameters bit for bit (fixed-order
+    reductions everywhere: split-K slices and row-block partial sums are added in index order)."""
+    sc = inputs.tiny_bos()
+    r = _tiny_renderer(sc)
+    tr = inputs.sources(sc.replace(n_src=300, src_seed=601))
+    va = inputs.sources(sc.replace(n_src=200, src_seed=602))
+    out = []
+    for _ in range(2):
+        s = pbr.Surrogate(init_seed=4, max_rows=1024)
+        rep = s.train(r, tr, 50, va, 20, train_seed=60, val_seed=62, ds=sc.ds, batch=1024, epochs=2,
+                      tiles=8, min_tile_samples=4)
+        out.append((s.params(), rep, s.tile_map()[0]))
+        s.close()
+    assert np.array_equal(out[0][0], out[1][0])
+    assert out[0][1]["loss_last_epoch"] == out[1][1]["loss_last_epoch"]
+    assert np.array_equal(out[0][2], out[1][2])
+    r.close()
