@@ -82,7 +82,16 @@ def main():
     ap.add_argument("--epochs", type=int, default=8, help="surrogate256: training epochs")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy a 1 GiB device buffer 4 times (calibrates HBM byte counters)")
+    ap.add_argument("--atomic-probe", action="store_true",
+                    help="only measure the device's rate of 64-bit atomic additions (sensor-sized buffer)")
     args = ap.parse_args()
+    if args.atomic_probe:
+        from paper_1812_05902_amd import pbr
+        out = {}
+        for slots in (1 << 20, 1 << 22):  # 1024^2 and 2048^2 sensors
+            out[f"u64_atomics_per_s_{slots}_slots"] = pbr.pbr_probe_u64_atomics(0, slots, 1 << 28)
+        print(json.dumps(out))
+        return
     if args.copy_probe:
         import torch
         a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")

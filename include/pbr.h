@@ -460,6 +460,13 @@ int pbr_surrogate_tile_map(pbr_surrogate *s, uint8_t *eligible_host, float *max_
  * chunk size for the surrogate (kept until pbr_surrogate_destroy). */
 int pbr_set_surrogate(pbr_ctx *ctx, pbr_surrogate *s);
 
+/* ---------------------------------------------------------------- calibration probe
+ * Rate of 64-bit integer atomic additions the device sustains: n_updates additions spread over
+ * n_slots 8-byte counters (groups of 256 consecutive updates hit consecutive counters, as the
+ * pixels of a spot do), timed with HIP events on the null stream after one warm-up launch.
+ * Allocates and frees its own buffer; synchronises.  Errors: ARG, HIP. */
+int pbr_probe_u64_atomics(int device, int64_t n_slots, int64_t n_updates, double *updates_per_s);
+
 #ifdef __cplusplus
 }
 #endif

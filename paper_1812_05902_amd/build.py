@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libpbr.so")
 
-SOURCES = ["field_prep.hip", "trace.hip", "readout.hip", "mlp.hip", "pbr_api.cpp", "pbr_batch.cpp",
+SOURCES = ["field_prep.hip", "trace.hip", "readout.hip", "mlp.hip", "probe.hip", "pbr_api.cpp", "pbr_batch.cpp",
            "pbr_surrogate.cpp"]
 
 HIPCC_FLAGS = [

@@ -249,7 +249,6 @@ int pbr_surrogate_create(pbr_surrogate **out, int device, void *hip_stream, uint
         s->x = (float *)A(R * 6 * 4);
         s->y = (float *)A(R * 6 * 4);
         s->t = (float *)A(R * 6 * 4);
-        s->idx = (int *)A(R * 4);
         s->loss = (float *)A(256);
         s->count = (unsigned long long *)A(256);
         s->step = (int *)A(256);

@@ -39,7 +39,7 @@ EXPORTED = ["pbr_create", "pbr_destroy", "pbr_last_error", "pbr_set_stream",
             "pbr_surrogate_create", "pbr_surrogate_destroy", "pbr_surrogate_last_error",
             "pbr_surrogate_set_params", "pbr_surrogate_get_params", "pbr_surrogate_forward",
             "pbr_surrogate_gradients", "pbr_surrogate_adam_step", "pbr_surrogate_train",
-            "pbr_surrogate_tile_map", "pbr_set_surrogate"]
+            "pbr_surrogate_tile_map", "pbr_set_surrogate", "pbr_probe_u64_atomics"]
 
 
 class PbrError(RuntimeError):
@@ -166,6 +166,7 @@ def load(path: str = LIB_PATH):
                                     C.POINTER(pbr_surrogate_train_config), C.POINTER(pbr_surrogate_report)]),
         "pbr_surrogate_tile_map": (I, [P, P, P, I64]),
         "pbr_set_surrogate": (I, [P, P]),
+        "pbr_probe_u64_atomics": (I, [I, I64, I64, C.POINTER(D)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(l, name)
@@ -657,3 +658,12 @@ class Surrogate:
             self.close()
         except Exception:
             pass
+
+
+def pbr_probe_u64_atomics(device=0, n_slots=1 << 20, n_updates=1 << 28) -> float:
+    """Updates per second of 64-bit atomic additions (calibration probe)."""
+    rate = C.c_double()
+    code = load().pbr_probe_u64_atomics(int(device), int(n_slots), int(n_updates), C.byref(rate))
+    if code != PBR_OK:
+        raise PbrError(code, "atomic probe failed")
+    return float(rate.value)
