@@ -36,17 +36,38 @@ def _kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def _traffic_from_profile():
-    """HBM bytes per trace launch from the committed rocprofv3 counter summary, if it was taken
-    on the current kernel source; else None."""
+def _profile():
+    """The committed rocprofv3 counter summary of the integration kernel, if it was taken on the
+    current kernel source; else None."""
     try:
         with open(PMC_FILE) as fh:
             d = json.load(fh)
     except (OSError, ValueError):
         return None
-    if d.get("kernel_source_hash") != _kernel_source_hash():
-        return None
-    return d.get("hbm_bytes_per_launch")
+    return d if d.get("kernel_source_hash") == _kernel_source_hash() else None
+
+
+def _traffic_from_profile():
+    """HBM bytes per trace launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated) or None."""
+    d = _profile()
+    return d.get("hbm_bytes_per_launch") if d else None
+
+
+HBM_PEAK_GBS = 8000.0
+GATHER_BYTES_PER_STEP = 384  # the method's field reads per step: 3 evaluations x 8 corners x float4
+
+
+def memory_roofline(steps_per_launch, kernel_ms):
+    """Memory-side view of the integration kernel: HBM and L2 traffic per launch from the committed
+    counters (when current) over the live kernel time, and the method's algorithmic gather rate."""
+    out = {"algorithmic_gather_bytes_per_step": GATHER_BYTES_PER_STEP,
+           "algorithmic_gather_GBps": steps_per_launch * GATHER_BYTES_PER_STEP / (kernel_ms * 1e-3) / 1e9}
+    d = _profile()
+    if d:
+        hbm = d["hbm_bytes_per_launch"] / (kernel_ms * 1e-3) / 1e9
+        out.update({"hbm_GBps": hbm, "hbm_frac": hbm / HBM_PEAK_GBS,
+                    "l2_read_GBps": d["l2_read_bytes_per_launch"] / (kernel_ms * 1e-3) / 1e9})
+    return out
 
 
 def cpu_baseline(scene, rho, src, target_s: float = 15.0):
@@ -171,6 +192,7 @@ def main():
                      "launches_per_step": box_launches / args.steps,
                      "trace_ms_per_step": trace_ms / args.steps,
                      "flops_per_rkn_step": FLOPS_PER_STEP},
+        "memory": memory_roofline(steps_total / box_launches, avg_ms),
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(scene, rho, src)

@@ -119,17 +119,27 @@ def _tiny_renderer(sc, chunk=1 << 18):
     return r
 
 
-def test_surrogate_in_the_trace(torch):
-    """Gaussian-bump BOS scene (32^3): train on 2e5 tracer rays, validate on 1e5 others, then render
-    5e5 unseen rays with and without the surrogate."""
+@pytest.fixture(scope="module")
+def trained(torch):
+    """Gaussian-bump BOS scene (32^3): a surrogate trained on 2e5 tracer rays, validated on 1e5
+    others."""
     sc = inputs.tiny_bos()
-    r = _tiny_renderer(sc)
+    r = _tiny_renderer(sc, chunk=1 << 22)
     tr = inputs.sources(sc.replace(n_src=2000, src_seed=501))
     va = inputs.sources(sc.replace(n_src=1000, src_seed=502))
     s = pbr.Surrogate(init_seed=3, max_rows=1 << 16)
     rep = s.train(r, tr, 100, va, 100, train_seed=50, val_seed=52, ds=sc.ds, batch=2048, epochs=30,
                   lr_max=2e-3, lr_min=2e-5, tol_px=0.01, tiles=16, min_tile_samples=8)
     print("train report:", rep)
+    yield sc, r, s, rep
+    s.close()
+    r.close()
+
+
+def test_surrogate_in_the_trace(torch, trained):
+    """Render 5e5 unseen rays with and without the surrogate: fallback map, exit error against the
+    tracer ray by ray, untouched rays outside the eligible tiles, image difference."""
+    sc, r, s, rep = trained
     assert rep["train_samples"] > 100000 and rep["val_samples"] > 50000
     assert rep["loss_last_epoch"] < 0.05 * rep["loss_first_epoch"]
     ok, err = s.tile_map()
@@ -150,8 +160,6 @@ def test_surrogate_in_the_trace(torch):
     img_s = pbr.u64_image_to_numpy(r.read_image()).astype(np.float64)
     rec_s = r.read_ray_exits()
     print("tracer", st_t, "\nsurrogate", st_s)
-    print(f"trace time: tracer {st_t['trace_ms']:.3f} ms, with surrogate {st_s['trace_ms']:.3f} ms "
-          f"(integration {st_t['box_ms']:.3f} -> {st_s['box_ms']:.3f} ms)")
     assert st_s["surrogate_rays"] > 0
     assert sum(st_s["status"]) == n_rays
     surr = (rec_s["entered"] == 1) & (rec_s["n_steps"] == 0) & (rec_t["n_steps"] > 0)
@@ -167,12 +175,42 @@ def test_surrogate_in_the_trace(torch):
     rel = np.linalg.norm(img_s - img_t) / np.linalg.norm(img_t)
     print(f"image rel L2 surrogate vs tracer {rel:.3g}")
     assert rel < 1e-2
-    # changing the scene detaches the surrogate's validity
+    r.set_exit_recording(0, 1, 0)
+
+
+def test_surrogate_gain_over_the_tracer(torch, trained):
+    """What the trained network gains: on 5e6 rays (two trace chunks of up to 2^22 rays) the
+    integration steps drop to the rays left to the tracer and the whole trace (emission, network or
+    integration, lens, deposit) takes less time than with the tracer alone.  (The rays left to the
+    tracer in a chunk take as long as their longest path: a fixed cost per chunk, which large
+    chunks amortise.)"""
+    sc, r, s, rep = trained
+    s.attach(r)
+    ev = torch.as_tensor(inputs.sources(sc.replace(n_src=50000, src_seed=504)), device="cuda")
+    t_ms, s_ms = [], []
+    for _ in range(3):
+        st_t = r.emit_and_trace(ev, 100, 51, sc.ds, pbr.PBR_CLEAR_FIRST, stats=True)
+        st_s = r.emit_and_trace(ev, 100, 51, sc.ds, pbr.PBR_CLEAR_FIRST | pbr.PBR_SURROGATE, stats=True)
+        t_ms.append(st_t["trace_ms"])
+        s_ms.append(st_s["trace_ms"])
+    print(f"5e6 rays: tracer {min(t_ms):.2f} ms ({st_t['rkn_steps']} steps), with the surrogate "
+          f"{min(s_ms):.2f} ms ({st_s['rkn_steps']} steps, {st_s['surrogate_rays']} rays through the "
+          f"network): {min(t_ms) / min(s_ms):.2f}x")
+    assert st_s["surrogate_rays"] > 0.9 * st_t["entered_volume"]
+    assert st_s["rkn_steps"] < 0.05 * st_t["rkn_steps"]
+    assert min(s_ms) < 0.8 * min(t_ms)
+
+
+def test_scene_change_invalidates_the_surrogate(torch, trained):
+    sc, r, s, rep = trained
+    s.attach(r)
+    ev = inputs.sources(sc.replace(n_src=10, src_seed=505))
+    r.emit_and_trace(ev, 100, 51, sc.ds, pbr.PBR_CLEAR_FIRST | pbr.PBR_SURROGATE)
     r.set_optics(sc.z_lens, sc.focal_length, sc.f_number, sc.thickness, sc.n_glass, sc.clear_radius, sc.z_focus)
     with pytest.raises(pbr.PbrError, match="no longer matches"):
         r.emit_and_trace(ev, 100, 51, sc.ds, pbr.PBR_CLEAR_FIRST | pbr.PBR_SURROGATE)
-    s.close()
-    r.close()
+    with pytest.raises(pbr.PbrError, match="changed since"):
+        s.attach(r)
 
 
 def test_training_is_deterministic(torch):
