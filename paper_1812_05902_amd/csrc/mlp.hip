@@ -361,9 +361,9 @@ __global__ void __launch_bounds__(256) k_loss_mean(const float *__restrict__ par
 // rounding (hardware round-to-nearest-even, two values per instruction) end in one 8-byte LDS
 // store per four values.  Wave w owns units 32 w .. 32 w + 31 of all 128 samples (2 x 8 tiles of
 // 16 x 16): 64 accumulator registers, so that four waves share each SIMD and one wave's vector
-// work (bias, GELU, rounding) overlaps another's matrix-core work.  Layer 1 (K = 6) runs in FP32
-// on the vector units: thread t takes units 4 (t % 64) .. + 3 of 16 samples.  The output layer is
-// 16 (6 used) x 128, each wave taking 16 samples.
+// work (bias, GELU, rounding) overlaps another's matrix-core work.  Layer 1 (K = 6, padded to 8)
+// runs in FP32 on the matrix cores (v_mfma_f32_16x16x4_f32, same tiles and result layout).  The
+// output layer is 16 (6 used) x 128, each wave taking 16 samples.
 constexpr int kFuseRows = 128, kActStride = kHidden + 8, kFuseWaves = 8;
 
 __device__ __forceinline__ unsigned pack_bf16x2(float a, float b)
@@ -391,33 +391,46 @@ __global__ void __launch_bounds__(64 * kFuseWaves, 2) k_mlp_infer(const float *_
     for (int q = threadIdx.x; q < kFuseRows * kIn; q += 64 * kFuseWaves)
         xs[q] = q < nblk * kIn ? x[row0 * kIn + q] : 0.0f;
     __syncthreads();
-    {   // layer 1, FP32: thread t owns units 4 u .. 4 u + 3 (u = t % 64) of samples 16 g .. 16 g + 15
-        const int u = threadIdx.x & 63, g = threadIdx.x >> 6;
-        float w[4][kIn], bn[4];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            bn[c] = params[kOffB1 + 4 * u + c];
-#pragma unroll
-            for (int k = 0; k < kIn; ++k) w[c][k] = params[kOffW1 + (4 * u + c) * kIn + k];
-        }
-        for (int mm = 0; mm < kFuseRows / kFuseWaves; ++mm) {
-            const int m = (kFuseRows / kFuseWaves) * g + mm;
-            float z[4];
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                z[c] = bn[c];
-#pragma unroll
-                for (int k = 0; k < kIn; ++k) z[c] += xs[m * kIn + k] * w[c][k];
-            }
-            uint2 v;
-            v.x = pack_bf16x2(gelu(z[0]), gelu(z[1]));
-            v.y = pack_bf16x2(gelu(z[2]), gelu(z[3]));
-            *(uint2 *)(act + m * kActStride + 4 * u) = v;
-        }
-    }
-    __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int r = lane & 15, kg = lane >> 4;
+    // lane: units 32 w + 16 j + 4 kg + t (t = 0..3) of sample 16 i + r
+    auto store_act = [&](floatx4 (&acc)[2][8]) {
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                uint2 v;
+                v.x = pack_bf16x2(gelu(acc[j][i][0]), gelu(acc[j][i][1]));
+                v.y = pack_bf16x2(gelu(acc[j][i][2]), gelu(acc[j][i][3]));
+                *(uint2 *)(act + (16 * i + r) * kActStride + wave * 32 + 16 * j + 4 * kg) = v;
+            }
+    };
+    {   // layer 1 in FP32 on the matrix cores (v_mfma_f32_16x16x4_f32, K = 6 padded to 8): lane l
+        // supplies W1[unit][k] and x[sample][k] for k = kk + l / 16
+        floatx4 acc[2][8];
+        const float *bias = params + kOffB1 + wave * 32 + 4 * kg;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const float4 b4 = *(const float4 *)(bias + 16 * j);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) acc[j][i] = floatx4{b4.x, b4.y, b4.z, b4.w};
+        }
+#pragma unroll
+        for (int kk = 0; kk < 8; kk += 4) {
+            const int k = kk + kg;
+            float wa[2];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) wa[j] = k < kIn ? params[kOffW1 + (wave * 32 + 16 * j + r) * kIn + k] : 0.0f;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const float xb = k < kIn ? xs[(16 * i + r) * kIn + k] : 0.0f;
+#pragma unroll
+                for (int j = 0; j < 2; ++j) acc[j][i] = __builtin_amdgcn_mfma_f32_16x16x4f32(wa[j], xb, acc[j][i], 0, 0, 0);
+            }
+        }
+        store_act(acc);
+    }
+    __syncthreads();
     for (int l = 0; l < 3; ++l) {
         const unsigned short *W = (l == 0 ? w2 : (l == 1 ? w3 : w4)) + (size_t)(wave * 32 + r) * kHidden + 8 * kg;
         const float *bias = params + (l == 0 ? kOffB2 : (l == 1 ? kOffB3 : kOffB4)) + wave * 32 + 4 * kg;
@@ -456,16 +469,7 @@ __global__ void __launch_bounds__(64 * kFuseWaves, 2) k_mlp_infer(const float *_
             }
         }
         __syncthreads();  // every wave has read this layer's inputs
-        // lane: units 32 w + 16 j + 4 kg + t (t = 0..3) of sample 16 i + r
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                uint2 v;
-                v.x = pack_bf16x2(gelu(acc[j][i][0]), gelu(acc[j][i][1]));
-                v.y = pack_bf16x2(gelu(acc[j][i][2]), gelu(acc[j][i][3]));
-                *(uint2 *)(act + (16 * i + r) * kActStride + wave * 32 + 16 * j + 4 * kg) = v;
-            }
+        store_act(acc);
         __syncthreads();
     }
     {   // output layer: 16 (padded) outputs of samples 16 w .. 16 w + 15

@@ -793,7 +793,9 @@ struct FinishShared {
 // Lens, sensor, spot, records and counters for the rays [first + base, first + base + 256) of one
 // image, whose states are st[base ..]; rays at or beyond n are padding.  All threads of the block
 // take part (barriers inside).
-template <int TILE>
+// RFX: footprint radius fixed at compile time (1..8), or 0 to switch on P.rfp per call (batches,
+// whose images differ).  A fixed radius keeps the spot arrays, and so the register count, small.
+template <int TILE, int RFX = 0>
 __device__ __forceinline__ void finish_block(const TraceParams &P, const RayState *__restrict__ st,
                                              int64_t first, int64_t base, int64_t n, FinishShared<TILE> &sh)
 {
@@ -841,7 +843,8 @@ __device__ __forceinline__ void finish_block(const TraceParams &P, const RayStat
         const float4 sv = P.src[rid / P.rays_per_src];
         const double w = sv.w > 0.0f ? (sv.w < 1.0f ? (double)sv.w : 1.0) : 0.0;  // weights in [0, 1]
         const int tx0 = sh.tx0, ty0 = sh.ty0;
-        switch (P.rfp) {
+        if (RFX > 0) deposit<(RFX > 0 ? RFX : 1), TILE>(P, xpx, ypx, w, sh.tile, tx0, ty0);
+        else switch (P.rfp) {
             case 1: deposit<1, TILE>(P, xpx, ypx, w, sh.tile, tx0, ty0); break;
             case 2: deposit<2, TILE>(P, xpx, ypx, w, sh.tile, tx0, ty0); break;
             case 3: deposit<3, TILE>(P, xpx, ypx, w, sh.tile, tx0, ty0); break;
@@ -894,14 +897,14 @@ __device__ __forceinline__ void flush_counters(const TraceParams &P, FinishShare
         atomic_add_u64(P.counters + threadIdx.x, sh.cnt[threadIdx.x]);
 }
 
-template <int TILE>
+template <int TILE, int RF>
 __global__ void __launch_bounds__(256) k_finish(TraceParams P, const RayState *__restrict__ st,
                                                 int64_t first, int64_t n)
 {
     __shared__ FinishShared<TILE> sh;
     if (threadIdx.x < CNT_SLOTS) sh.cnt[threadIdx.x] = 0ull;
     for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += (int64_t)gridDim.x * blockDim.x)
-        finish_block<TILE>(P, st, first, base, n, sh);
+        finish_block<TILE, RF>(P, st, first, base, n, sh);
     flush_counters<TILE>(P, sh);
 }
 
@@ -1362,7 +1365,17 @@ int launch_trace_chunk(const TraceParams &p, RayState *st, int64_t first, int64_
     if (box_end && (e = (int)hipEventRecord(box_end, stream))) return e;
     if (!deposit) return 0;
     unsigned fblocks = blocks < 4096u ? blocks : 4096u;
-    hipLaunchKernelGGL(k_finish<kTile>, dim3(fblocks), dim3(256), 0, stream, p, (const RayState *)st, first, n);
+    const RayState *cst = st;
+    switch (p.rfp) {
+        case 1: hipLaunchKernelGGL((k_finish<kTile, 1>), dim3(fblocks), dim3(256), 0, stream, p, cst, first, n); break;
+        case 2: hipLaunchKernelGGL((k_finish<kTile, 2>), dim3(fblocks), dim3(256), 0, stream, p, cst, first, n); break;
+        case 3: hipLaunchKernelGGL((k_finish<kTile, 3>), dim3(fblocks), dim3(256), 0, stream, p, cst, first, n); break;
+        case 4: hipLaunchKernelGGL((k_finish<kTile, 4>), dim3(fblocks), dim3(256), 0, stream, p, cst, first, n); break;
+        case 5: hipLaunchKernelGGL((k_finish<kTile, 5>), dim3(fblocks), dim3(256), 0, stream, p, cst, first, n); break;
+        case 6: hipLaunchKernelGGL((k_finish<kTile, 6>), dim3(fblocks), dim3(256), 0, stream, p, cst, first, n); break;
+        case 7: hipLaunchKernelGGL((k_finish<kTile, 7>), dim3(fblocks), dim3(256), 0, stream, p, cst, first, n); break;
+        default: hipLaunchKernelGGL((k_finish<kTile, 8>), dim3(fblocks), dim3(256), 0, stream, p, cst, first, n); break;
+    }
     return (int)hipGetLastError();
 }
 
