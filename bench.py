@@ -125,7 +125,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the renderer has no "
-              "multi-GPU path in this build", file=sys.stderr)
+              "multi-GPU path", file=sys.stderr)
         sys.exit(2)
 
     import torch
