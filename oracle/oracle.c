@@ -609,3 +609,48 @@ int orc_num_threads(void)
     return 1;
 #endif
 }
+
+/* ---------------------------------------------------------------- BOS theory (sec. 4, eq. 9) */
+
+/* Paraxial image plane and lateral magnification of the object plane z_obj: out = (z, M). */
+void orc_paraxial(const orc_scene *S, double z_obj, double out[2])
+{
+    paraxial_image(S, z_obj, &out[0], &out[1]);
+}
+
+/* Eq. 9 on a regular grid of the dot plane z = z_dots, node (i, j) at (x0 + i dx, y0 + j dy):
+ * the image displacement, in pixels, of a dot seen through the density box,
+ *     dX = |M| Z_D / n0 * integral over the box depth of (dn/dx, dn/dy) dz,
+ * taken along the chief ray from the node to the centre of the aperture stop (the front vertex
+ * on the axis).  M: magnification of the dot plane; Z_D: distance from the dot plane to the mid
+ * plane of the box; n0: ambient index.  The sign is that of the unflipped sensor: a ray bent
+ * towards +x seems to come from a point at -x on the dot plane, whose inverted image lies at +x.
+ * READING: the integral is the midpoint rule with `samples` points over [z_min, z_max] of the
+ * box; points of the chief ray beyond the box's x-y extent lie in the ambient medium and add
+ * nothing.  out: [ny][nx][2]. */
+void orc_bos_theory_map(const orc_scene *S, double x0, double y0, double dx, double dy, int nx,
+                        int ny, double z_dots, int samples, double *out)
+{
+    double zi, M;
+    paraxial_image(S, z_dots, &zi, &M);
+    const double zc = 0.5 * (S->lo[2] + S->hi[2]);
+    const double scale = fabs(M) * (zc - z_dots) / (S->n_inf * S->c.pitch);
+    const double dz = (S->hi[2] - S->lo[2]) / (double)samples;
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            const double X = x0 + (double)i * dx, Y = y0 + (double)j * dy;
+            double sx = 0.0, sy = 0.0;
+            for (int k = 0; k < samples; ++k) {
+                const double z = S->lo[2] + ((double)k + 0.5) * dz;
+                const double f = (z - z_dots) / (S->c.z_lens - z_dots);
+                const double R[3] = {X * (1.0 - f), Y * (1.0 - f), z};
+                if (R[0] < S->lo[0] || R[0] > S->hi[0] || R[1] < S->lo[1] || R[1] > S->hi[1]) continue;
+                double g[4];
+                orc_field_eval(S, R, g);
+                sx += g[1];
+                sy += g[2];
+            }
+            out[2 * ((size_t)j * nx + i)] = scale * sx * dz;
+            out[2 * ((size_t)j * nx + i) + 1] = scale * sy * dz;
+        }
+}

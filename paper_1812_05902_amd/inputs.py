@@ -38,7 +38,7 @@ class Scene:
     nz: int
     origin: tuple
     spacing: tuple
-    field: str  # 'uniform' | 'bump' | 'turbulence' | 'shock' | 'linear'
+    field: str  # 'uniform' | 'bump' | 'turbulence' | 'slice' | 'shock' | 'linear'
     field_params: dict = dataclasses.field(default_factory=dict)
     K: float = K_AIR
     rho_inf: float = 1.2
@@ -149,6 +149,58 @@ def surrogate_turbulence():
     return ev, tr, va
 
 
+def bos_slice(n: int = 257, seed: int = 6, n_src: int = 5200, rays_per_src: int = 1000) -> Scene:
+    """The BOS experiment of section 4 (Fig. 3, Table 1) on a synthetic stand-in for its DNS
+    slice: one 2-D random-phase slice (k^-5/3 energy spectrum, density ratio 1.05, scaled by
+    1.225 kg/m^3) stacked along z, so that the density has no z gradient.  Box 32 x 32 x 10 mm
+    (n x n x nz nodes, 0.125 mm spacing at n = 257), centre at Z_D = 0.25 m from the dot plane
+    z = 0, lens front vertex Z_A = 0.75 m beyond the centre; f = 105 mm at f/11 focused on the
+    dots (magnification about 0.117); 512^2 sensor of 10 um pixels; 20 dots per 32 x 32 pixels
+    over the 44 x 44 mm of the dot plane the sensor sees (5200 dots), 1000 rays each."""
+    h = 0.032 / (n - 1)
+    nz = int(round(0.010 / h)) + 1
+    org = (-0.016, -0.016, 0.25 - 0.5 * (nz - 1) * h)
+    return Scene(
+        name=f"bos_slice_{n}", nx=n, ny=n, nz=nz, origin=org, spacing=(h, h, h),
+        field="slice", field_params=dict(rho0=1.225, ratio=1.05, kmax=16, seed=seed),
+        rho_inf=1.225, source_kind="dots", n_src=n_src,
+        src_region=((-0.022, 0.022), (-0.022, 0.022), (0.0, 0.0)), src_seed=60,
+        rays_per_src=rays_per_src, ray_seed=61,
+        z_lens=1.0, focal_length=0.105, f_number=11.0, z_focus=0.0,
+        width=512, height=512, pitch=10e-6, ds=1e-4)
+
+
+def map_grid(scene: Scene, nodes: int = 64, half_width: float = 0.020):
+    """Regular grid of the displacement maps on the dot plane z = src_region[2][0]: nodes x nodes
+    points spanning [-half_width, half_width]^2.  Returns (x0, y0, dx, dy, nx, ny, z_dots)."""
+    d = 2.0 * half_width / (nodes - 1)
+    return (-half_width, -half_width, d, d, nodes, nodes, float(scene.src_region[2][0]))
+
+
+def synthetic_source_sums(n: int, seed: int, width: int, height: int, max_hits: int = 1000):
+    """Two seeded arrays of per-source hit sums in the layout of the per-source sum records
+    (int64 [n][4] = sum_x, sum_y, hits, 0; sums in units of 2^-24 pixel), as a render with and
+    one without a field would leave them: hit counts in [0, max_hits] (about 3% zero), mean hits
+    uniform on the sensor, the second set shifted by up to 2 pixels.  Sums stay below 2^53."""
+    rng = np.random.default_rng(seed)
+    out = []
+    hits = rng.integers(0, max_hits + 1, size=n)
+    hits[rng.random(n) < 0.03] = 0
+    mx = rng.uniform(0, width, n)
+    my = rng.uniform(0, height, n)
+    for k in range(2):
+        if k:
+            hits = np.where(rng.random(n) < 0.02, 0, hits)
+            mx = mx + rng.uniform(-2, 2, n)
+            my = my + rng.uniform(-2, 2, n)
+        a = np.zeros((n, 4), dtype=np.int64)
+        a[:, 0] = np.rint(mx * hits * 2.0 ** 24).astype(np.int64)
+        a[:, 1] = np.rint(my * hits * 2.0 ** 24).astype(np.int64)
+        a[:, 2] = hits
+        out.append(a)
+    return out[0], out[1]
+
+
 def batch_scenes(n_images: int = 64, seed_base: int = 4000):
     """Many images of uneven sizes: particle counts log-uniform in [1e3, 1e5], rays per particle
     log-uniform in [500, 1e4], grids 64^3 / 128^3 / 256^3 holding a Gaussian bump or a
@@ -207,6 +259,24 @@ def turbulence_psi(n: int, kmax: int, seed: int) -> np.ndarray:
     return psi
 
 
+def turbulence_psi2(n: int, kmax: int, seed: int) -> np.ndarray:
+    """2-D random-phase field psi(x, y) = sum_{k in Z^2, 1 <= |k| <= kmax} |k|^(-4/3)
+    cos(k.x + phi_k) at x = 2*pi*i/n on [0, 2*pi)^2 (energy spectrum k^-5/3 in the plane),
+    phases from ``seed`` in lexicographic (kx, ky) order.  Returned as [iy, ix], float64."""
+    if 2 * kmax >= n:
+        raise ValueError("kmax must be below n/2")
+    rng = np.random.default_rng(seed)
+    r = np.arange(-kmax, kmax + 1)
+    KX, KY = np.meshgrid(r, r, indexing="ij")
+    kk = np.sqrt(KX * KX + KY * KY)
+    m = (kk >= 1) & (kk <= kmax)
+    phases = rng.uniform(0.0, 2.0 * np.pi, size=int(m.sum()))
+    amps = kk[m] ** (-4.0 / 3.0)
+    F = np.zeros((n, n), dtype=np.complex128)
+    F[KY[m] % n, KX[m] % n] = amps * np.exp(1j * phases)
+    return np.fft.ifft2(F).real * float(n) ** 2
+
+
 def density(scene: Scene) -> np.ndarray:
     """Density rho [kg/m^3] at the grid nodes, float32, C-contiguous [nz][ny][nx]."""
     fp = scene.field_params
@@ -228,6 +298,14 @@ def density(scene: Scene) -> np.ndarray:
         psi = turbulence_psi(scene.nx, fp.get("kmax", 16), fp["seed"])
         psi_hat = (psi - psi.min()) / (psi.max() - psi.min())
         rho = fp["rho0"] * (1.0 + (fp["ratio"] - 1.0) * psi_hat)
+    elif scene.field == "slice":
+        # one x-y slice stacked along z: the density has no z gradient
+        if scene.nx != scene.ny:
+            raise ValueError("slice field needs nx == ny")
+        psi = turbulence_psi2(scene.nx, fp.get("kmax", 16), fp["seed"])
+        psi_hat = (psi - psi.min()) / (psi.max() - psi.min())
+        sl = fp["rho0"] * (1.0 + (fp["ratio"] - 1.0) * psi_hat)
+        rho = np.broadcast_to(sl[None, :, :], shape)
     elif scene.field == "shock":
         r1, r2 = fp["rho1"], fp["rho2"]
         prof = r1 + 0.5 * (r2 - r1) * (1.0 + np.tanh((x - fp["x_s"]) / fp["delta"]))
@@ -263,4 +341,5 @@ SCENES = {
     "tiny_bos": tiny_bos,
     "turbulence_bos": turbulence_bos,
     "tomo_piv_shock": tomo_piv_shock,
+    "bos_slice": bos_slice,
 }
