@@ -96,10 +96,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="turbulence_bos_128",
-                    choices=["turbulence_bos_128", "batch64", "surrogate256", "tomo_piv_512"],
+                    choices=["turbulence_bos_128", "batch64", "surrogate256", "tomo_piv_512", "bos_fig4"],
                     help="batch64: the 64 uneven images of inputs.batch_scenes in one graph-captured batch; "
                          "surrogate256: train the ray surrogate on a 256^3 turbulence field, then 1e9 rays "
-                         "with and without it")
+                         "with and without it; bos_fig4: the BOS displacement check of sec. 4 (two renders, "
+                         "per-dot displacement map, eq. 9 map)")
     ap.add_argument("--epochs", type=int, default=8, help="surrogate256: training epochs")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy a 1 GiB device buffer 4 times (calibrates HBM byte counters)")
@@ -137,6 +138,8 @@ def main():
         return bench_surrogate(args)
     if args.workload == "tomo_piv_512":
         return bench_tomo(args)
+    if args.workload == "bos_fig4":
+        return bench_bos_fig4(args)
     scene = inputs.turbulence_bos()
     rho = inputs.density(scene)
     src = inputs.sources(scene)
@@ -312,6 +315,74 @@ def bench_tomo(args):
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None, "kernel": "k_box32",
                      "kernel_ms_per_launch": box_ms / launches, "flops_per_rkn_step": FLOPS_PER_STEP},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_bos_fig4(args):
+    """The BOS experiment of sec. 4 (Fig. 4): a 257 x 257 x 81 z-stacked slice field with the
+    Table 1 geometry, 5200 dots x 1000 rays rendered through the field and through the ambient
+    medium with per-dot hit sums, then the bilinear map of the dot displacements and the eq. 9 map
+    on a 64 x 64 grid.  One step = the whole experiment; value = rays of both renders per second."""
+    import numpy as np
+    import torch
+    from paper_1812_05902_amd import inputs, pbr
+
+    sc = inputs.bos_slice()
+    sc0 = sc.replace(field="uniform", field_params=dict(rho0=sc.rho_inf))
+    grid = inputs.map_grid(sc)
+    # one trace chunk holds a whole render (no ragged second launch)
+    r1 = pbr.Renderer.from_scene(sc, rays_per_chunk=1 << 23)
+    r0 = pbr.Renderer.from_scene(sc0, rays_per_chunk=1 << 23)
+    src = torch.as_tensor(inputs.sources(sc), device=r1.device).contiguous()
+    s1 = r1.set_source_sums(sc.n_src)
+    s0 = r0.set_source_sums(sc.n_src)
+    torch.cuda.synchronize()
+    flags = pbr.PBR_CLEAR_FIRST | pbr.PBR_SOURCE_SUMS
+
+    def step(stats):
+        s1.zero_()
+        s0.zero_()
+        a = r1.emit_and_trace(src, sc.rays_per_src, sc.ray_seed, sc.ds, flags, stats=stats)
+        b = r0.emit_and_trace(src, sc.rays_per_src, sc.ray_seed, sc.ds, flags, stats=stats)
+        sim = r1.dot_displacement_map(s1, s0, src, grid)
+        th = r1.bos_theory_map(grid)
+        return a, b, sim, th
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    box_ms, launches, steps_total = 0.0, 0, 0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        a, b, sim, th = step(True)
+        for st in (a, b):
+            box_ms += st["box_ms"]
+            launches += st["box_launches"]
+            steps_total += st["rkn_steps"]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    sim, th = sim.cpu().numpy().astype(np.float64), th.cpu().numpy().astype(np.float64)
+    f = np.isfinite(sim[:, :, 0])
+    x, y = sim[f].ravel(), th[f].ravel()
+    achieved = steps_total * FLOPS_PER_STEP / (box_ms * 1e-3) / 1e12
+    n_rays = 2 * sc.n_rays
+    out = {
+        "metric": "rays/sec on 1 MI355X (trace+lens+sensor)", "value": n_rays * args.steps / wall,
+        "unit": "rays/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "bos_fig4", "grid": f"{sc.nx}x{sc.ny}x{sc.nz} z-stacked slice",
+                   "n_src": sc.n_src, "rays_per_src": sc.rays_per_src, "renders_per_step": 2,
+                   "rays_per_step": n_rays, "sensor": f"{sc.width}x{sc.height}", "ds_m": sc.ds,
+                   "map": f"{grid[4]}x{grid[5]} nodes, {grid[2] * 1e3:.3f} mm"},
+        "fig4": {"corr_simulated_vs_eq9": float(np.corrcoef(x, y)[0, 1]),
+                 "rms_simulated_over_eq9": float(np.sqrt((x * x).mean() / (y * y).mean())),
+                 "eq9_max_px": float(np.abs(y).max()), "nodes_filled": int(f.sum())},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None, "kernel": "k_box32",
+                     "kernel_ms_per_launch": box_ms / launches, "flops_per_rkn_step": FLOPS_PER_STEP,
+                     "mean_rkn_steps_per_ray": steps_total / args.steps / n_rays},
     }
     print(json.dumps(out), flush=True)
 

@@ -66,6 +66,9 @@ extern "C" {
                                           different sources, which costs more cell gathers than the idle
                                           lanes it saves (measured 4% slower on the 128^3 BOS scene, 16% on
                                           the 512^3 Tomo-PIV scene) */
+#define PBR_SOURCE_SUMS     (1u << 6)  /* add every deposited ray's sensor hit into the per-source sums set by
+                                          pbr_set_source_sums (sec. 4: a dot's displacement is the mean of
+                                          its rays') */
 
 /* ---------------------------------------------------------------- pbr_read_image formats */
 #define PBR_FMT_RAW_U64 0  /* copy of the Q32.32 accumulator (uint64 per pixel) */
@@ -264,6 +267,63 @@ int pbr_read_image(pbr_ctx *ctx, int fmt, void *out_dev, double gain);
 /* Copies records [first, first + count) of the recording buffer to host memory out_host and
  * synchronises the stream.  Errors: ARG (range outside the buffer), STATE (no recording set). */
 int pbr_read_ray_exits(pbr_ctx *ctx, pbr_ray_exit *out_host, int64_t first, int64_t count);
+
+/* ---------------------------------------------------------------- BOS displacement check (sec. 4) */
+
+/* Sums over the deposited rays of one source of their sensor hits (sec. 4 averages the
+ * displacements of the rays of each dot).  Fixed point: sum_x = sum of round_half_even(x_px *
+ * 2^24) over the rays (likewise y), so the sums are exact integers whatever order the rays
+ * arrive in; the mean hit is (sum * 2^-24) / hits. */
+typedef struct pbr_source_sum {
+    int64_t sum_x;     /* pixels * 2^24, summed */
+    int64_t sum_y;
+    uint64_t hits;     /* rays of the source deposited on the sensor */
+    uint64_t reserved; /* left untouched */
+} pbr_source_sum;
+
+/* Sets the per-source sums that traces with PBR_SOURCE_SUMS add into: sums_dev[s] for source s
+ * of the call (caller-owned device array of `capacity` records, 8-byte aligned, which the caller
+ * clears; the library only adds).  The traced call must have n_src <= capacity and
+ * rays_per_src <= 2^25, which keeps each sum below 2^63 (hits below 16384 pixels).
+ * Errors: ARG (null with capacity > 0, capacity < 0, misaligned). */
+int pbr_set_source_sums(pbr_ctx *ctx, pbr_source_sum *sums_dev, int64_t capacity);
+
+/* Regular grid of displacement maps on the dot plane: node (i, j) at (x0 + i dx, y0 + j dy,
+ * z_dots), 0 <= i < nx, 0 <= j < ny.  Maps are float32 [ny][nx][2] (x and y components). */
+typedef struct pbr_map_grid {
+    double x0, y0;     /* position of node (0, 0) (m) */
+    double dx, dy;     /* node spacing (m), > 0 */
+    double z_dots;     /* z of the dot plane (m), in front of the box */
+    int32_t nx, ny;    /* nodes, 1 .. 4096 each */
+} pbr_map_grid;
+
+/* Workspace bytes of pbr_dot_displacement_map: 24 bytes per node (0 on bad sizes). */
+size_t pbr_dot_map_workspace_bytes(int nx, int ny);
+
+/* Map of the per-dot displacements between two renders of the same dots and rays (sec. 4,
+ * Fig. 4): with_dev holds the sums of a render through the field, without_dev those of a render
+ * through the ambient medium.  Dot s (position src_dev[s].xy) has displacement mean_with -
+ * mean_without in pixels when both hit counts are non-zero.  The scattered displacements are
+ * placed on the grid by bilinear weights: a dot with fractional cell position (t, u) gives weight
+ * (1-t)(1-u), t(1-u), (1-t)u, tu to the four nodes around it; a node's value is the weighted mean
+ * of what it received (weights and weighted displacements summed as integers in units of 2^-32,
+ * rounded half to even), NaN where nothing arrived.  ws_dev: pbr_dot_map_workspace_bytes,
+ * 8-byte aligned, scratch.  map_dev: float32 [ny][nx][2].  Asynchronous.
+ * Errors: ARG (null pointers, bad grid, n_src < 0), WORKSPACE, STATE (host-only context), HIP. */
+int pbr_dot_displacement_map(pbr_ctx *ctx, const pbr_source_sum *with_dev,
+                             const pbr_source_sum *without_dev, const float *src_dev, int64_t n_src,
+                             const pbr_map_grid *grid, void *ws_dev, size_t ws_bytes, float *map_dev);
+
+/* Eq. 9 at the grid nodes: the displacement, in pixels, that BOS theory predicts for a dot at the
+ * node, |M| Z_D / n0 times the integral over the box depth of (dn/dx, dn/dy) dz along the chief
+ * ray from the node to the centre of the aperture stop; M is the paraxial magnification of the
+ * dot plane, Z_D the distance from the dot plane to the mid-plane of the box, n0 the ambient
+ * index.  The integral is the midpoint rule with `samples` points over the box's z extent, the
+ * gradient interpolated from the current field; points outside the box's x-y extent add nothing.
+ * The sign is that of the unflipped sensor.  map_dev: float32 [ny][nx][2].  Needs field, optics
+ * and sensor.  Asynchronous.  Errors: ARG (bad grid, samples < 1 or > 65536, dot plane not in
+ * front of the box), STATE, HIP. */
+int pbr_bos_theory_map(pbr_ctx *ctx, const pbr_map_grid *grid, int32_t samples, float *map_dev);
 
 /* ---------------------------------------------------------------- batches of images */
 

@@ -26,12 +26,14 @@ Q24 = float(2 ** 24)
 Q32 = float(2 ** 32)
 
 
-def dot_mean_hits(o, src, rays_per_src, n_threads=0):
-    """Traces every ray of every source with the oracle scene ``o``; returns (mean [n][2] of
-    the sensor hits of the deposited rays in pixels, NaN where none; deposited count [n])."""
+def dot_mean_hits(o, src, rays_per_src, n_threads=0, which=None):
+    """Traces every ray of the sources ``which`` (default: all) with the oracle scene ``o``;
+    returns (mean [n][2] of the sensor hits of the deposited rays in pixels, NaN where none;
+    deposited count [n]) for those sources."""
     src = np.ascontiguousarray(src, dtype=np.float32)
-    n = src.shape[0]
-    ids = np.arange(n * int(rays_per_src), dtype=np.int64)
+    which = np.arange(src.shape[0]) if which is None else np.asarray(which, dtype=np.int64)
+    n = len(which)
+    ids = (which[:, None] * int(rays_per_src) + np.arange(int(rays_per_src))[None, :]).ravel().astype(np.int64)
     r = o.trace_ids(src, rays_per_src, ids, n_threads=n_threads)
     dep = (r["status"] == DEPOSITED).reshape(n, rays_per_src)
     px = r["sensor_px"].reshape(n, rays_per_src, 2)

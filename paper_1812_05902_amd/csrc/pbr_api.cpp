@@ -361,6 +361,17 @@ int pbr_set_exit_recording(pbr_ctx *ctx, int64_t first, int64_t stride, int64_t 
     return PBR_OK;
 }
 
+int pbr_set_source_sums(pbr_ctx *ctx, pbr_source_sum *sums_dev, int64_t capacity)
+{
+    if (!ctx) return PBR_ERR_ARG;
+    if (capacity < 0) return fail(ctx, PBR_ERR_ARG, "capacity < 0");
+    if (capacity > 0 && !sums_dev) return fail(ctx, PBR_ERR_ARG, "sums array is null");
+    if (((uintptr_t)sums_dev & 7u) != 0) return fail(ctx, PBR_ERR_ARG, "sums array must be 8-byte aligned");
+    ctx->src_sums = capacity > 0 ? sums_dev : nullptr;
+    ctx->src_sums_cap = capacity;
+    return PBR_OK;
+}
+
 int pbr_emit_and_trace(pbr_ctx *ctx, const float *src_dev, int64_t n_src, int32_t rays_per_src,
                        uint64_t seed, double ds, uint32_t flags, pbr_stats *stats)
 {
@@ -381,8 +392,16 @@ int pbr_emit_and_trace(pbr_ctx *ctx, const float *src_dev, int64_t n_src, int32_
     if (!(d.z_sensor > ctx->optics.z_front_vertex + d.t))
         return fail(ctx, PBR_ERR_ARG, "sensor plane must lie behind the lens");
     if (flags & ~(uint32_t)(PBR_CLEAR_FIRST | PBR_RECORD_EXITS | PBR_PREC_FP64_ALL | PBR_PREC_SHOCK_FP64 |
-                            PBR_SURROGATE | PBR_LANE_REFILL))
+                            PBR_SURROGATE | PBR_LANE_REFILL | PBR_SOURCE_SUMS))
         return fail(ctx, PBR_ERR_ARG, "unknown flag bits 0x%x", flags);
+    if (flags & PBR_SOURCE_SUMS) {
+        if (!ctx->src_sums) return fail(ctx, PBR_ERR_STATE, "no per-source sums set (pbr_set_source_sums)");
+        if (n_src > ctx->src_sums_cap)
+            return fail(ctx, PBR_ERR_WORKSPACE, "per-source sums hold %lld sources, the call has %lld",
+                        (long long)ctx->src_sums_cap, (long long)n_src);
+        if (rays_per_src > (1 << 25))
+            return fail(ctx, PBR_ERR_ARG, "per-source sums need rays_per_src <= 2^25");
+    }
     pbr::ChunkHook hook{nullptr, nullptr};
     if (flags & PBR_SURROGATE) {
         if ((r = surrogate_hook(ctx, &hook))) return r;
@@ -415,6 +434,7 @@ int pbr_emit_and_trace(pbr_ctx *ctx, const float *src_dev, int64_t n_src, int32_
     P.n_rays = n_src * (int64_t)rays_per_src;
     P.seed = seed;
     P.record = (flags & PBR_RECORD_EXITS) && ctx->rec_max > 0 ? 1 : 0;
+    P.src_sums = (flags & PBR_SOURCE_SUMS) ? ctx->src_sums : nullptr;
     ctx->last_max_steps = P.max_steps;
 
     const int prec = (flags & PBR_PREC_FP64_ALL) ? pbr::PREC_FP64
@@ -593,6 +613,85 @@ int pbr_read_image(pbr_ctx *ctx, int fmt, void *out_dev, double gain)
     const int e = pbr::launch_readout(ctx->accum, (int64_t)ctx->sensor.width * ctx->sensor.height, fmt,
                                       out_dev, gain, ctx->counters, ctx->stream);
     if (e) return hip_fail(ctx, e, "readout launch");
+    return PBR_OK;
+    PBR_GUARD_END
+}
+
+namespace {
+int check_grid(pbr_ctx *ctx, const pbr_map_grid *g)
+{
+    if (!g) return fail(ctx, PBR_ERR_ARG, "grid is null");
+    if (g->nx < 1 || g->ny < 1 || g->nx > 4096 || g->ny > 4096)
+        return fail(ctx, PBR_ERR_ARG, "grid nodes must be 1 .. 4096 per axis");
+    if (!(g->dx > 0.0) || !(g->dy > 0.0) || !std::isfinite(g->dx) || !std::isfinite(g->dy) ||
+        !std::isfinite(g->x0) || !std::isfinite(g->y0) || !std::isfinite(g->z_dots))
+        return fail(ctx, PBR_ERR_ARG, "grid spacing must be finite and > 0, origin finite");
+    return PBR_OK;
+}
+}  // namespace
+
+size_t pbr_dot_map_workspace_bytes(int nx, int ny)
+{
+    if (nx < 1 || ny < 1 || nx > 4096 || ny > 4096) return 0;
+    return (size_t)nx * (size_t)ny * 24u;
+}
+
+int pbr_dot_displacement_map(pbr_ctx *ctx, const pbr_source_sum *with_dev, const pbr_source_sum *without_dev,
+                             const float *src_dev, int64_t n_src, const pbr_map_grid *grid, void *ws_dev,
+                             size_t ws_bytes, float *map_dev)
+{
+    if (!ctx) return PBR_ERR_ARG;
+    PBR_GUARD_BEGIN
+    int r = check_grid(ctx, grid);
+    if (r) return r;
+    if (n_src < 0) return fail(ctx, PBR_ERR_ARG, "n_src < 0");
+    if (n_src > 0 && (!with_dev || !without_dev || !src_dev))
+        return fail(ctx, PBR_ERR_ARG, "sums or source array is null");
+    if (!map_dev || !ws_dev) return fail(ctx, PBR_ERR_ARG, "map or workspace is null");
+    if ((((uintptr_t)with_dev | (uintptr_t)without_dev | (uintptr_t)ws_dev) & 7u) != 0 ||
+        ((uintptr_t)src_dev & 15u) != 0 || ((uintptr_t)map_dev & 3u) != 0)
+        return fail(ctx, PBR_ERR_ARG, "misaligned array (sums and workspace 8, sources 16, map 4 bytes)");
+    if (ws_bytes < pbr_dot_map_workspace_bytes(grid->nx, grid->ny))
+        return fail(ctx, PBR_ERR_WORKSPACE, "map workspace needs %zu bytes",
+                    pbr_dot_map_workspace_bytes(grid->nx, grid->ny));
+    if (ctx->device < 0) return fail(ctx, PBR_ERR_STATE, "host-only context: no device work");
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(ctx, PBR_ERR_HIP, "hipSetDevice failed");
+    const int e = pbr::launch_dot_map(with_dev, without_dev, (const float4 *)src_dev, n_src, *grid,
+                                      (unsigned long long *)ws_dev, map_dev, ctx->stream);
+    if (e) return hip_fail(ctx, e, "displacement map launch");
+    return PBR_OK;
+    PBR_GUARD_END
+}
+
+int pbr_bos_theory_map(pbr_ctx *ctx, const pbr_map_grid *grid, int32_t samples, float *map_dev)
+{
+    if (!ctx) return PBR_ERR_ARG;
+    PBR_GUARD_BEGIN
+    Derived d;
+    int r = derive(ctx, &d);
+    if (r) return r;
+    if ((r = check_grid(ctx, grid))) return r;
+    if (samples < 1 || samples > 65536) return fail(ctx, PBR_ERR_ARG, "samples must be 1 .. 65536");
+    if (!map_dev || ((uintptr_t)map_dev & 3u) != 0) return fail(ctx, PBR_ERR_ARG, "map is null or misaligned");
+    if (!(grid->z_dots < ctx->origin[2])) return fail(ctx, PBR_ERR_ARG, "dot plane must lie in front of the box");
+    // paraxial magnification of the dot plane (system matrix of derive, object at z_dots)
+    const pbr_optics &o = ctx->optics;
+    const double na = d.n_inf, ng = o.n_glass;
+    const double ph1 = (ng - na) / d.R, ph2 = (na - ng) / (-d.R), tau = d.t / ng;
+    const double A = 1.0 - tau * ph1, B = tau, C = -(ph1 + ph2 - tau * ph1 * ph2), D = 1.0 - tau * ph2;
+    const double so = (o.z_front_vertex - grid->z_dots) / na;
+    const double si = -(A * so + B) / (C * so + D);
+    const double M = A + si * C;
+    const double zc = ctx->origin[2] + 0.5 * (double)(ctx->nz - 1) * ctx->spacing[2];
+    const double scale = std::fabs(M) * (zc - grid->z_dots) / (d.n_inf * ctx->sensor.pitch);
+    if (ctx->device < 0) return fail(ctx, PBR_ERR_STATE, "host-only context: no device work");
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(ctx, PBR_ERR_HIP, "hipSetDevice failed");
+    pbr::TraceParams P;
+    fill_params(ctx, d, 1e-4, &P);
+    const int e = pbr::launch_bos_theory(P, *grid, scale, samples, map_dev, ctx->stream);
+    if (e) return hip_fail(ctx, e, "theory map launch");
     return PBR_OK;
     PBR_GUARD_END
 }

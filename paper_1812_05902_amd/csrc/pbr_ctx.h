@@ -18,6 +18,8 @@ struct pbr_ctx {
     // field
     bool has_field = false;
     const float4 *cells = nullptr;
+    pbr_source_sum *src_sums = nullptr;    // per-source hit sums (PBR_SOURCE_SUMS), device
+    int64_t src_sums_cap = 0;
     unsigned *brick_gmax = nullptr;        // per-brick max |grad n| (float bits), device
     unsigned char *brick_fp64 = nullptr;   // per-brick FP64 flags, device
     pbr::FieldLayout layout{};

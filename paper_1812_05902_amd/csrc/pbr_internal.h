@@ -89,6 +89,8 @@ struct TraceParams {
     int64_t rec_first, rec_stride, rec_max;
     // counters
     unsigned long long *counters;
+    // per-source sums of the sensor hits (null: not kept)
+    pbr_source_sum *src_sums;
 };
 
 // Per-ray state between the three trace kernels (emit -> box -> finish), 64 bytes.
@@ -229,5 +231,12 @@ int launch_trace_chunk(const TraceParams &p, RayState *st, int64_t first, int64_
 int launch_readout(const unsigned long long *accum, int64_t npx, int fmt, void *out,
                    double gain, unsigned long long *counters, hipStream_t stream);
 int launch_clear_u64(unsigned long long *p, int64_t n, hipStream_t stream);
+
+// BOS displacement check (sec. 4).  ws: 3 uint64 per node (cleared here).
+int launch_dot_map(const pbr_source_sum *with_sums, const pbr_source_sum *without_sums, const float4 *src,
+                   int64_t n_src, const pbr_map_grid &g, unsigned long long *ws, float *map, hipStream_t stream);
+// Eq. 9 map; scale = |M| Z_D / (n0 pitch) of the dot plane.
+int launch_bos_theory(const TraceParams &p, const pbr_map_grid &g, double scale, int samples, float *map,
+                      hipStream_t stream);
 
 }  // namespace pbr

@@ -782,6 +782,38 @@ __device__ __forceinline__ void deposit(const TraceParams &P, double x, double y
     }
 }
 
+// Adds the sensor hits of this wave's deposited rays (on) into the per-source sums.  The rays of
+// a source are consecutive, so the wave holds a few runs of one source index each: every run is
+// summed across the wave and added by its first lane.  Integer sums (hits in units of 2^-24
+// pixel): the result does not depend on the order in which rays arrive.  Wave-uniform control.
+__device__ __forceinline__ void add_source_sums(const TraceParams &P, bool on, int64_t rid, double xpx,
+                                                double ypx)
+{
+    const int64_t s = rid / P.rays_per_src;
+    const long long qx = on ? (long long)rint(xpx * 16777216.0) : 0ll;
+    const long long qy = on ? (long long)rint(ypx * 16777216.0) : 0ll;
+    unsigned long long pending = __ballot(on);
+    while (pending) {
+        const int lead = __ffsll((unsigned long long)pending) - 1;
+        const int64_t s0 = __shfl(s, lead, 64);
+        const bool mine = on && s == s0;
+        long long vx = mine ? qx : 0ll, vy = mine ? qy : 0ll, c = mine ? 1ll : 0ll;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            vx += __shfl_xor(vx, o, 64);
+            vy += __shfl_xor(vy, o, 64);
+            c += __shfl_xor(c, o, 64);
+        }
+        if ((int)__lane_id() == lead) {
+            pbr_source_sum *d = P.src_sums + s0;
+            atomic_add_u64((unsigned long long *)&d->sum_x, (unsigned long long)vx);
+            atomic_add_u64((unsigned long long *)&d->sum_y, (unsigned long long)vy);
+            atomic_add_u64((unsigned long long *)&d->hits, (unsigned long long)c);
+        }
+        pending &= ~__ballot(mine);
+    }
+}
+
 // Shared memory of the finish step of one block.
 template <int TILE>
 struct FinishShared {
@@ -838,6 +870,7 @@ __device__ __forceinline__ void finish_block(const TraceParams &P, const RayStat
         sh.ty0 = (int)ypx - TILE / 2;
     }
     __syncthreads();
+    if (P.src_sums) add_source_sums(P, valid && status == PBR_RAY_DEPOSITED, first + i, xpx, ypx);
     if (valid && status == PBR_RAY_DEPOSITED) {
         const int64_t rid = first + i;
         const float4 sv = P.src[rid / P.rays_per_src];

@@ -25,6 +25,7 @@ PBR_OK, PBR_ERR_ARG, PBR_ERR_STATE, PBR_ERR_HIP, PBR_ERR_WORKSPACE, PBR_ERR_OVER
 PBR_NUM_STATUS = 7
 PBR_CLEAR_FIRST, PBR_RECORD_EXITS, PBR_PREC_FP64_ALL, PBR_PREC_SHOCK_FP64, PBR_SURROGATE = 1, 2, 4, 8, 16
 PBR_LANE_REFILL = 32
+PBR_SOURCE_SUMS = 64
 PBR_SURR_PARAMS = 200710
 PBR_FMT_RAW_U64, PBR_FMT_F32, PBR_FMT_U16 = 0, 1, 2
 
@@ -39,7 +40,9 @@ EXPORTED = ["pbr_create", "pbr_destroy", "pbr_last_error", "pbr_set_stream",
             "pbr_surrogate_create", "pbr_surrogate_destroy", "pbr_surrogate_last_error",
             "pbr_surrogate_set_params", "pbr_surrogate_get_params", "pbr_surrogate_forward",
             "pbr_surrogate_gradients", "pbr_surrogate_adam_step", "pbr_surrogate_train",
-            "pbr_surrogate_tile_map", "pbr_set_surrogate", "pbr_probe_u64_atomics"]
+            "pbr_surrogate_tile_map", "pbr_set_surrogate", "pbr_probe_u64_atomics",
+            "pbr_set_source_sums", "pbr_dot_map_workspace_bytes", "pbr_dot_displacement_map",
+            "pbr_bos_theory_map"]
 
 
 class PbrError(RuntimeError):
@@ -78,6 +81,15 @@ class pbr_precision_report(C.Structure):
     _fields_ = [("n_bricks", C.c_int64), ("n_steep", C.c_int64), ("n_fp64", C.c_int64),
                 ("grad_threshold", C.c_double), ("grad_max", C.c_double), ("max_err_px", C.c_double),
                 ("tol_px", C.c_double), ("steps_per_sample", C.c_int32), ("rays_per_brick", C.c_int32)]
+
+
+class pbr_source_sum(C.Structure):
+    _fields_ = [("sum_x", C.c_int64), ("sum_y", C.c_int64), ("hits", C.c_uint64), ("reserved", C.c_uint64)]
+
+
+class pbr_map_grid(C.Structure):
+    _fields_ = [("x0", C.c_double), ("y0", C.c_double), ("dx", C.c_double), ("dy", C.c_double),
+                ("z_dots", C.c_double), ("nx", C.c_int32), ("ny", C.c_int32)]
 
 
 class pbr_batch_item(C.Structure):
@@ -167,6 +179,10 @@ def load(path: str = LIB_PATH):
         "pbr_surrogate_tile_map": (I, [P, P, P, I64]),
         "pbr_set_surrogate": (I, [P, P]),
         "pbr_probe_u64_atomics": (I, [I, I64, I64, C.POINTER(D)]),
+        "pbr_set_source_sums": (I, [P, P, I64]),
+        "pbr_dot_map_workspace_bytes": (C.c_size_t, [I, I]),
+        "pbr_dot_displacement_map": (I, [P, P, P, P, I64, C.POINTER(pbr_map_grid), P, C.c_size_t, P]),
+        "pbr_bos_theory_map": (I, [P, C.POINTER(pbr_map_grid), C.c_int32, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(l, name)
@@ -275,6 +291,29 @@ def pbr_read_ray_exits(ctx, first, count) -> np.ndarray:
     return out
 
 
+def pbr_set_source_sums(ctx, sums, capacity):
+    _check(ctx, load().pbr_set_source_sums(ctx, _dptr(sums), int(capacity)))
+
+
+def pbr_dot_map_workspace_bytes(nx, ny) -> int:
+    return int(load().pbr_dot_map_workspace_bytes(int(nx), int(ny)))
+
+
+def map_grid(x0, y0, dx, dy, nx, ny, z_dots) -> pbr_map_grid:
+    return pbr_map_grid(float(x0), float(y0), float(dx), float(dy), float(z_dots), int(nx), int(ny))
+
+
+def pbr_dot_displacement_map(ctx, with_sums, without_sums, src, grid: pbr_map_grid, ws, out):
+    n_src = 0 if src is None else int(src.shape[0])
+    _check(ctx, load().pbr_dot_displacement_map(ctx, _dptr(with_sums), _dptr(without_sums), _dptr(src), n_src,
+                                                C.byref(grid), _dptr(ws), ws.numel() * ws.element_size(),
+                                                _dptr(out)))
+
+
+def pbr_bos_theory_map(ctx, grid: pbr_map_grid, samples, out):
+    _check(ctx, load().pbr_bos_theory_map(ctx, C.byref(grid), int(samples), _dptr(out)))
+
+
 # ------------------------------------------------------------------ convenience wrapper
 
 def stats_dict(st: pbr_stats) -> dict:
@@ -372,16 +411,46 @@ class Renderer:
         pbr_read_image(self.ctx, fmt, out, gain)
         return out
 
+    def set_source_sums(self, n_src):
+        """Allocates and clears per-source hit sums for n_src sources (int64 tensor [n_src][4]:
+        sum_x, sum_y, hits, reserved) and sets them on the context; traces with PBR_SOURCE_SUMS
+        add into them."""
+        self.sums = self.torch.zeros(int(n_src), 4, dtype=self.torch.int64, device=self.device)
+        pbr_set_source_sums(self.ctx, self.sums, n_src)
+        return self.sums
+
+    def dot_displacement_map(self, with_sums, without_sums, src, grid):
+        """Bilinear map of per-dot displacements (float32 tensor [ny][nx][2], pixels);
+        grid = (x0, y0, dx, dy, nx, ny, z_dots)."""
+        torch = self.torch
+        g = map_grid(*grid)
+        src = torch.as_tensor(src, dtype=torch.float32, device=self.device).contiguous()
+        ws = torch.empty(max(pbr_dot_map_workspace_bytes(g.nx, g.ny) // 8, 1), dtype=torch.int64, device=self.device)
+        out = torch.empty(g.ny, g.nx, 2, dtype=torch.float32, device=self.device)
+        pbr_dot_displacement_map(self.ctx, with_sums, without_sums, src, g, ws, out)
+        self._map_keepalive = (src, ws)
+        return out
+
+    def bos_theory_map(self, grid, samples=None):
+        """Eq. 9 on the grid (float32 tensor [ny][nx][2], pixels); samples defaults to four per
+        cell of the box depth."""
+        g = map_grid(*grid)
+        if samples is None:
+            samples = 4 * (self.grid_shape[2] - 1)
+        out = self.torch.empty(g.ny, g.nx, 2, dtype=self.torch.float32, device=self.device)
+        pbr_bos_theory_map(self.ctx, g, samples, out)
+        return out
+
     def read_ray_exits(self, first=0, count=None):
         if count is None:
             count = self.rec_max - first
         return pbr_read_ray_exits(self.ctx, first, count)
 
     @classmethod
-    def from_scene(cls, scene, rho=None, device=None):
+    def from_scene(cls, scene, rho=None, device=None, rays_per_chunk=1 << 22):
         """Renderer with field, optics and sensor of an ``inputs.Scene``."""
         from . import inputs
-        r = cls(device)
+        r = cls(device, rays_per_chunk=rays_per_chunk)
         if rho is None:
             rho = inputs.density(scene)
         r.set_density_field(rho, scene.origin, scene.spacing, scene.K, scene.rho_inf)

@@ -291,3 +291,56 @@ def test_surrogate_entry_points_validate_before_device_work(lib):
         assert b"no surrogate attached" in lib.pbr_last_error(ctx)
     finally:
         lib.pbr_destroy(ctx)
+
+
+def test_bos_check_entry_points_validate_before_device_work(lib):
+    """Per-source sums, the dot displacement map and the eq. 9 map: argument and state errors
+    come before any device work (host-only context)."""
+    assert pbr.pbr_dot_map_workspace_bytes(64, 32) == 64 * 32 * 24
+    assert pbr.pbr_dot_map_workspace_bytes(0, 5) == 0 and pbr.pbr_dot_map_workspace_bytes(5, 4097) == 0
+    h = _host_ctx(lib)
+    try:
+        g = pbr.map_grid(-0.01, -0.01, 1e-3, 1e-3, 21, 21, 0.0)
+        ws = pbr.pbr_dot_map_workspace_bytes(21, 21)
+        # sums: set, errors, and the trace checks that use them
+        assert lib.pbr_set_source_sums(h, None, 4) == pbr.PBR_ERR_ARG
+        assert lib.pbr_set_source_sums(h, FAKE, -1) == pbr.PBR_ERR_ARG
+        assert lib.pbr_set_source_sums(h, FAKE + 4, 4) == pbr.PBR_ERR_ARG
+        assert _set_field(lib, h) == pbr.PBR_OK
+        assert lib.pbr_set_optics(h, C.byref(_optics())) == pbr.PBR_OK
+        assert lib.pbr_set_sensor(h, C.byref(_sensor()), FAKE) == pbr.PBR_OK
+        assert lib.pbr_set_trace_workspace(h, FAKE, 1 << 20) == pbr.PBR_OK
+        assert lib.pbr_emit_and_trace(h, FAKE, 3, 8, 0, 1e-4, pbr.PBR_SOURCE_SUMS, None) == pbr.PBR_ERR_STATE
+        assert "source_sums" in _err(lib, h)
+        assert lib.pbr_set_source_sums(h, FAKE, 2) == pbr.PBR_OK
+        assert lib.pbr_emit_and_trace(h, FAKE, 3, 8, 0, 1e-4, pbr.PBR_SOURCE_SUMS, None) == pbr.PBR_ERR_WORKSPACE
+        assert lib.pbr_emit_and_trace(h, FAKE, 2, (1 << 25) + 1, 0, 1e-4, pbr.PBR_SOURCE_SUMS,
+                                      None) == pbr.PBR_ERR_ARG
+        assert lib.pbr_emit_and_trace(h, FAKE, 2, 8, 0, 1e-4, pbr.PBR_SOURCE_SUMS, None) == pbr.PBR_ERR_STATE
+        assert "host-only" in _err(lib, h)
+        # displacement map
+        dm = lib.pbr_dot_displacement_map
+        assert dm(h, FAKE, FAKE, FAKE, 5, None, FAKE, ws, FAKE) == pbr.PBR_ERR_ARG
+        for bad in (pbr.map_grid(0, 0, 0.0, 1e-3, 4, 4, 0), pbr.map_grid(0, 0, 1e-3, 1e-3, 0, 4, 0),
+                    pbr.map_grid(0, 0, 1e-3, 1e-3, 4, 5000, 0), pbr.map_grid(math.nan, 0, 1e-3, 1e-3, 4, 4, 0)):
+            assert dm(h, FAKE, FAKE, FAKE, 5, C.byref(bad), FAKE, ws, FAKE) == pbr.PBR_ERR_ARG
+        assert dm(h, FAKE, FAKE, FAKE, -1, C.byref(g), FAKE, ws, FAKE) == pbr.PBR_ERR_ARG
+        assert dm(h, None, FAKE, FAKE, 5, C.byref(g), FAKE, ws, FAKE) == pbr.PBR_ERR_ARG
+        assert dm(h, FAKE, FAKE, FAKE + 8, 5, C.byref(g), FAKE, ws, FAKE) == pbr.PBR_ERR_ARG
+        assert dm(h, FAKE, FAKE, FAKE, 5, C.byref(g), FAKE, ws - 1, FAKE) == pbr.PBR_ERR_WORKSPACE
+        assert dm(h, FAKE, FAKE, FAKE, 5, C.byref(g), FAKE, ws, FAKE) == pbr.PBR_ERR_STATE
+        # eq. 9 map
+        tm = lib.pbr_bos_theory_map
+        assert tm(h, C.byref(g), 0, FAKE) == pbr.PBR_ERR_ARG
+        assert tm(h, C.byref(g), 65537, FAKE) == pbr.PBR_ERR_ARG
+        assert tm(h, C.byref(g), 64, None) == pbr.PBR_ERR_ARG
+        assert tm(h, C.byref(pbr.map_grid(0, 0, 1e-3, 1e-3, 4, 4, 0.2)), 64, FAKE) == pbr.PBR_ERR_ARG
+        assert "in front" in _err(lib, h)
+        assert tm(h, C.byref(g), 64, FAKE) == pbr.PBR_ERR_STATE
+    finally:
+        lib.pbr_destroy(h)
+    h = _host_ctx(lib)
+    try:  # the eq. 9 map needs field, optics and sensor
+        assert lib.pbr_bos_theory_map(h, C.byref(g), 64, FAKE) == pbr.PBR_ERR_STATE
+    finally:
+        lib.pbr_destroy(h)
