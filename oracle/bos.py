@@ -110,3 +110,4 @@ def magnification(o, z_obj):
     l.orc_paraxial.argtypes = [C.c_void_p, C.c_double, C.c_void_p]
     l.orc_paraxial(o.h, z_obj, _ptr(out))
     return float(out[1])
+

@@ -201,6 +201,48 @@ def synthetic_source_sums(n: int, seed: int, width: int, height: int, max_hits: 
     return out[0], out[1]
 
 
+def velocity_field(kind: str, n: int = 33, region=((-0.05, 0.05), (-0.05, 0.05), (-0.015, 0.015)),
+                   **p):
+    """A prescribed velocity field sampled on an n^3 grid over ``region`` (PIV frame pairs: the
+    second frame's particles are moved by it).  Returns (vel float32 [n][n][n][3] as [iz][iy][ix]
+    of (u, v, w) in m/s, origin, spacing).  Kinds:
+      'uniform'  u = p['u'] (3-vector);
+      'shear'    u = (gamma * y, 0, 0);
+      'rotation' solid-body rotation about the z axis through p['centre'] at p['omega'] rad/s;
+      'vortex'   Lamb-Oseen vortex about the z axis through p['centre'], circulation p['gamma']
+                 (m^2/s), core radius p['rc'] (m): u_theta = gamma / (2 pi r) (1 - exp(-r^2/rc^2)),
+                 plus a uniform stream p.get('u', 0)."""
+    (x0, x1), (y0, y1), (z0, z1) = region
+    org = (x0, y0, z0)
+    sp = ((x1 - x0) / (n - 1), (y1 - y0) / (n - 1), (z1 - z0) / (n - 1))
+    x = x0 + sp[0] * np.arange(n)
+    y = y0 + sp[1] * np.arange(n)
+    X = np.broadcast_to(x[None, None, :], (n, n, n))
+    Y = np.broadcast_to(y[None, :, None], (n, n, n))
+    vel = np.zeros((n, n, n, 3))
+    if kind == "uniform":
+        vel[...] = np.asarray(p["u"], dtype=np.float64)
+    elif kind == "shear":
+        vel[..., 0] = p["gamma"] * Y
+    elif kind == "rotation":
+        cx, cy = p.get("centre", (0.0, 0.0))
+        vel[..., 0] = -p["omega"] * (Y - cy)
+        vel[..., 1] = p["omega"] * (X - cx)
+    elif kind == "vortex":
+        cx, cy = p.get("centre", (0.0, 0.0))
+        dx, dy = X - cx, Y - cy
+        r2 = dx * dx + dy * dy
+        with np.errstate(divide="ignore", invalid="ignore"):
+            f = np.where(r2 > 0, p["gamma"] / (2 * np.pi * r2) * (1 - np.exp(-r2 / p["rc"] ** 2)),
+                         p["gamma"] / (2 * np.pi * p["rc"] ** 2))
+        vel[..., 0] = -f * dy
+        vel[..., 1] = f * dx
+        vel[...] += np.asarray(p.get("u", (0.0, 0.0, 0.0)), dtype=np.float64)
+    else:
+        raise ValueError(f"unknown velocity field {kind!r}")
+    return np.ascontiguousarray(vel, dtype=np.float32), org, sp
+
+
 def batch_scenes(n_images: int = 64, seed_base: int = 4000):
     """Many images of uneven sizes: particle counts log-uniform in [1e3, 1e5], rays per particle
     log-uniform in [500, 1e4], grids 64^3 / 128^3 / 256^3 holding a Gaussian bump or a
