@@ -325,6 +325,23 @@ int pbr_dot_displacement_map(pbr_ctx *ctx, const pbr_source_sum *with_dev,
  * front of the box), STATE, HIP. */
 int pbr_bos_theory_map(pbr_ctx *ctx, const pbr_map_grid *grid, int32_t samples, float *map_dev);
 
+/* ---------------------------------------------------------------- PIV frame pairs (sec. 1) */
+
+/* Second frame of a PIV pair (sec. 1: velocity is measured from the displacement of the particles
+ * between two frames).  Advances every particle of src_in_dev (float32 [n_src][4] = x, y, z, weight)
+ * by dx/dt = u(x) over dt (s) with `substeps` classical fourth-order Runge-Kutta steps in FP64 and
+ * writes (x', y', z', weight) to src_out_dev (which may be src_in_dev).  vel_dev: float32
+ * [nz][ny][nx][3] velocity (u, v, w in m/s) at nodes origin + (i, j, k) * spacing, interpolated
+ * trilinearly; a point outside the grid takes the value at the nearest point of the grid.
+ * Rendering both frames with the same seed gives every ray of a particle the same aperture point
+ * in both, so the pair differs only by the motion.  Asynchronous.
+ * Errors: ARG (null or misaligned arrays: sources 16 bytes, velocity 4; n_src < 0; dims < 2 or
+ * > 65535 or more than 2^31 nodes; spacing <= 0 or non-finite; non-finite origin or dt; substeps
+ * outside 1 .. 4096), STATE (host-only context), HIP. */
+int pbr_displace_sources(pbr_ctx *ctx, const float *src_in_dev, float *src_out_dev, int64_t n_src,
+                         const float *vel_dev, int nx, int ny, int nz, const double origin[3],
+                         const double spacing[3], double dt, int32_t substeps);
+
 /* ---------------------------------------------------------------- batches of images */
 
 /* Many images (each its own context: field, optics, sensor, accumulator, exit recording, all set

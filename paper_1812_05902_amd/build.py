@@ -16,7 +16,8 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libpbr.so")
 
-SOURCES = ["field_prep.hip", "trace.hip", "readout.hip", "mlp.hip", "probe.hip", "bos_map.hip", "pbr_api.cpp",
+SOURCES = ["field_prep.hip", "trace.hip", "readout.hip", "mlp.hip", "probe.hip", "bos_map.hip", "piv_pair.hip",
+           "pbr_api.cpp",
            "pbr_batch.cpp", "pbr_surrogate.cpp"]
 
 HIPCC_FLAGS = [

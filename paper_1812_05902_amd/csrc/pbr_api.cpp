@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "pbr_ctx.h"
+#include "piv_internal.h"
 
 namespace pbr {
 namespace host {
@@ -692,6 +693,39 @@ int pbr_bos_theory_map(pbr_ctx *ctx, const pbr_map_grid *grid, int32_t samples, 
     fill_params(ctx, d, 1e-4, &P);
     const int e = pbr::launch_bos_theory(P, *grid, scale, samples, map_dev, ctx->stream);
     if (e) return hip_fail(ctx, e, "theory map launch");
+    return PBR_OK;
+    PBR_GUARD_END
+}
+
+int pbr_displace_sources(pbr_ctx *ctx, const float *src_in_dev, float *src_out_dev, int64_t n_src,
+                         const float *vel_dev, int nx, int ny, int nz, const double origin[3],
+                         const double spacing[3], double dt, int32_t substeps)
+{
+    if (!ctx) return PBR_ERR_ARG;
+    PBR_GUARD_BEGIN
+    if (n_src < 0) return fail(ctx, PBR_ERR_ARG, "n_src < 0");
+    if (n_src > 0 && (!src_in_dev || !src_out_dev)) return fail(ctx, PBR_ERR_ARG, "source array is null");
+    if ((((uintptr_t)src_in_dev | (uintptr_t)src_out_dev) & 15u) != 0)
+        return fail(ctx, PBR_ERR_ARG, "source arrays must be 16-byte aligned");
+    if (!vel_dev || ((uintptr_t)vel_dev & 3u) != 0) return fail(ctx, PBR_ERR_ARG, "velocity is null or misaligned");
+    if (!origin || !spacing) return fail(ctx, PBR_ERR_ARG, "origin or spacing is null");
+    if (nx < 2 || ny < 2 || nz < 2 || nx > 65535 || ny > 65535 || nz > 65535 ||
+        (double)nx * ny * nz > 2147483647.0)
+        return fail(ctx, PBR_ERR_ARG, "velocity grid must have 2 .. 65535 nodes per axis, at most 2^31 - 1 nodes");
+    if (!finite3(origin) || !finite3(spacing) || !(spacing[0] > 0.0) || !(spacing[1] > 0.0) || !(spacing[2] > 0.0))
+        return fail(ctx, PBR_ERR_ARG, "velocity grid origin must be finite, spacing finite and > 0");
+    if (!std::isfinite(dt)) return fail(ctx, PBR_ERR_ARG, "dt must be finite");
+    if (substeps < 1 || substeps > 4096) return fail(ctx, PBR_ERR_ARG, "substeps must be 1 .. 4096");
+    if (ctx->device < 0) return fail(ctx, PBR_ERR_STATE, "host-only context: no device work");
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(ctx, PBR_ERR_HIP, "hipSetDevice failed");
+    pbr::VelocityGrid vg;
+    vg.vel = vel_dev;
+    vg.nx = nx; vg.ny = ny; vg.nz = nz;
+    for (int a = 0; a < 3; ++a) { vg.origin[a] = origin[a]; vg.spacing[a] = spacing[a]; }
+    const int e = pbr::launch_displace((const float4 *)src_in_dev, (float4 *)src_out_dev, n_src, vg, dt, substeps,
+                                       ctx->stream);
+    if (e) return hip_fail(ctx, e, "displacement launch");
     return PBR_OK;
     PBR_GUARD_END
 }

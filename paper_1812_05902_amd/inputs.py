@@ -243,6 +243,15 @@ def velocity_field(kind: str, n: int = 33, region=((-0.05, 0.05), (-0.05, 0.05),
     return np.ascontiguousarray(vel, dtype=np.float32), org, sp
 
 
+def piv_pair_flow(n: int = 65):
+    """Velocity of the PIV pair workload: a Lamb-Oseen vortex about the optical axis
+    (circulation 0.05 m^2/s, core radius 1 cm) in a 0.2 m/s stream along x, on an n^3 grid over
+    the Tomo-PIV particle volume; frame interval 0.5 ms (particle images move up to ~7 pixels).
+    Returns (vel, origin, spacing, dt)."""
+    vel, org, sp = velocity_field("vortex", n, gamma=0.05, rc=0.01, u=(0.2, 0.0, 0.0))
+    return vel, org, sp, 5e-4
+
+
 def batch_scenes(n_images: int = 64, seed_base: int = 4000):
     """Many images of uneven sizes: particle counts log-uniform in [1e3, 1e5], rays per particle
     log-uniform in [500, 1e4], grids 64^3 / 128^3 / 256^3 holding a Gaussian bump or a

@@ -42,7 +42,7 @@ EXPORTED = ["pbr_create", "pbr_destroy", "pbr_last_error", "pbr_set_stream",
             "pbr_surrogate_gradients", "pbr_surrogate_adam_step", "pbr_surrogate_train",
             "pbr_surrogate_tile_map", "pbr_set_surrogate", "pbr_probe_u64_atomics",
             "pbr_set_source_sums", "pbr_dot_map_workspace_bytes", "pbr_dot_displacement_map",
-            "pbr_bos_theory_map"]
+            "pbr_bos_theory_map", "pbr_displace_sources"]
 
 
 class PbrError(RuntimeError):
@@ -183,6 +183,7 @@ def load(path: str = LIB_PATH):
         "pbr_dot_map_workspace_bytes": (C.c_size_t, [I, I]),
         "pbr_dot_displacement_map": (I, [P, P, P, P, I64, C.POINTER(pbr_map_grid), P, C.c_size_t, P]),
         "pbr_bos_theory_map": (I, [P, C.POINTER(pbr_map_grid), C.c_int32, P]),
+        "pbr_displace_sources": (I, [P, P, P, I64, P, I, I, I, P, P, D, C.c_int32]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(l, name)
@@ -314,6 +315,15 @@ def pbr_bos_theory_map(ctx, grid: pbr_map_grid, samples, out):
     _check(ctx, load().pbr_bos_theory_map(ctx, C.byref(grid), int(samples), _dptr(out)))
 
 
+def pbr_displace_sources(ctx, src_in, src_out, vel, origin, spacing, dt, substeps):
+    nz, ny, nx = (int(v) for v in vel.shape[:3])
+    o = (C.c_double * 3)(*origin)
+    s = (C.c_double * 3)(*spacing)
+    n_src = 0 if src_in is None else int(src_in.shape[0])
+    _check(ctx, load().pbr_displace_sources(ctx, _dptr(src_in), _dptr(src_out), n_src, _dptr(vel), nx, ny, nz,
+                                            o, s, float(dt), int(substeps)))
+
+
 # ------------------------------------------------------------------ convenience wrapper
 
 def stats_dict(st: pbr_stats) -> dict:
@@ -439,6 +449,17 @@ class Renderer:
             samples = 4 * (self.grid_shape[2] - 1)
         out = self.torch.empty(g.ny, g.nx, 2, dtype=self.torch.float32, device=self.device)
         pbr_bos_theory_map(self.ctx, g, samples, out)
+        return out
+
+    def displace_sources(self, src, vel, origin, spacing, dt, substeps=4):
+        """Sources of the second frame of a PIV pair: src advanced by the velocity field vel
+        (float32 [nz][ny][nx][3], m/s) over dt; returns a new float32 tensor [n][4]."""
+        torch = self.torch
+        src = torch.as_tensor(src, dtype=torch.float32, device=self.device).contiguous()
+        vel = torch.as_tensor(vel, dtype=torch.float32, device=self.device).contiguous()
+        out = torch.empty_like(src)
+        pbr_displace_sources(self.ctx, src, out, vel, origin, spacing, dt, substeps)
+        self._vel_keepalive = (src, vel)
         return out
 
     def read_ray_exits(self, first=0, count=None):

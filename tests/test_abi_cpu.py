@@ -344,3 +344,31 @@ def test_bos_check_entry_points_validate_before_device_work(lib):
         assert lib.pbr_bos_theory_map(h, C.byref(g), 64, FAKE) == pbr.PBR_ERR_STATE
     finally:
         lib.pbr_destroy(h)
+
+
+def test_piv_displacement_validates_before_device_work(lib):
+    h = _host_ctx(lib)
+    try:
+        o = (C.c_double * 3)(0, 0, 0)
+        s = (C.c_double * 3)(1e-3, 1e-3, 1e-3)
+        bad = (C.c_double * 3)(1e-3, 0.0, 1e-3)
+        nan = (C.c_double * 3)(math.nan, 0, 0)
+        f = lib.pbr_displace_sources
+        assert f(None, FAKE, FAKE, 1, FAKE, 4, 4, 4, o, s, 1e-3, 4) == pbr.PBR_ERR_ARG
+        assert f(h, FAKE, FAKE, -1, FAKE, 4, 4, 4, o, s, 1e-3, 4) == pbr.PBR_ERR_ARG
+        assert f(h, None, FAKE, 1, FAKE, 4, 4, 4, o, s, 1e-3, 4) == pbr.PBR_ERR_ARG
+        assert f(h, FAKE + 4, FAKE, 1, FAKE, 4, 4, 4, o, s, 1e-3, 4) == pbr.PBR_ERR_ARG
+        assert f(h, FAKE, FAKE, 1, None, 4, 4, 4, o, s, 1e-3, 4) == pbr.PBR_ERR_ARG
+        assert f(h, FAKE, FAKE, 1, FAKE + 2, 4, 4, 4, o, s, 1e-3, 4) == pbr.PBR_ERR_ARG
+        assert f(h, FAKE, FAKE, 1, FAKE, 1, 4, 4, o, s, 1e-3, 4) == pbr.PBR_ERR_ARG
+        assert f(h, FAKE, FAKE, 1, FAKE, 4, 4, 70000, o, s, 1e-3, 4) == pbr.PBR_ERR_ARG
+        assert f(h, FAKE, FAKE, 1, FAKE, 2000, 2000, 2000, o, s, 1e-3, 4) == pbr.PBR_ERR_ARG
+        assert f(h, FAKE, FAKE, 1, FAKE, 4, 4, 4, o, bad, 1e-3, 4) == pbr.PBR_ERR_ARG
+        assert f(h, FAKE, FAKE, 1, FAKE, 4, 4, 4, nan, s, 1e-3, 4) == pbr.PBR_ERR_ARG
+        assert f(h, FAKE, FAKE, 1, FAKE, 4, 4, 4, o, s, math.inf, 4) == pbr.PBR_ERR_ARG
+        assert f(h, FAKE, FAKE, 1, FAKE, 4, 4, 4, o, s, 1e-3, 0) == pbr.PBR_ERR_ARG
+        assert f(h, FAKE, FAKE, 1, FAKE, 4, 4, 4, o, s, 1e-3, 4097) == pbr.PBR_ERR_ARG
+        assert f(h, FAKE, FAKE, 1, FAKE, 4, 4, 4, o, s, 1e-3, 4) == pbr.PBR_ERR_STATE
+        assert "host-only" in _err(lib, h)
+    finally:
+        lib.pbr_destroy(h)
