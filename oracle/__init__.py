@@ -199,6 +199,24 @@ class OracleScene:
                             int(n_threads))
         return out
 
+    def set_mie(self, table, laser_dir):
+        """Weights every ray by the Mie table at its scattering angle (``orc_set_mie``);
+        table=None clears it."""
+        l = lib()
+        l.orc_set_mie.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]
+        k = np.ascontiguousarray(laser_dir, dtype=np.float64)
+        if table is None:
+            l.orc_set_mie(self.h, None, 0, _ptr(k))
+            return
+        t = np.ascontiguousarray(table, dtype=np.float64)
+        l.orc_set_mie(self.h, _ptr(t), len(t), _ptr(k))
+
+    def mie_weight(self, u):
+        l = lib()
+        l.orc_mie_weight.restype = C.c_double
+        l.orc_mie_weight.argtypes = [C.c_void_p, C.c_void_p]
+        return float(l.orc_mie_weight(self.h, _ptr(np.ascontiguousarray(u, dtype=np.float64))))
+
     def render(self, src, rays_per_src, n_threads=0, want_float=True):
         """Returns (uint64 Q32.32 image [H][W], float64 image or None, counts[8])."""
         src = np.ascontiguousarray(src, dtype=np.float32)

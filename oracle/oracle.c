@@ -83,6 +83,9 @@ typedef struct {
     double sigma_px;             /* Gaussian spot sigma in pixels */
     int r_fp;                    /* footprint half-width in pixels */
     int max_steps;
+    double *mie;                 /* Mie intensity table at theta_k = k pi / (mie_n - 1), or NULL */
+    int mie_n;
+    double laser[3];             /* unit propagation direction of the laser light */
 } orc_scene;
 
 /* ---------------------------------------------------------------- counter-based RNG */
@@ -407,7 +410,7 @@ orc_scene *orc_create(const orc_cfg *cfg, const float *rho)
 void orc_destroy(orc_scene *S)
 {
     if (!S) return;
-    free(S->dn); free(S->gx); free(S->gy); free(S->gz);
+    free(S->dn); free(S->gx); free(S->gy); free(S->gz); free(S->mie);
     free(S);
 }
 
@@ -497,6 +500,40 @@ double orc_pixel_fraction(double x, int i, double sigma)
     return 0.5 * (erf(((double)i + 1.0 - x) / s) - erf(((double)i - x) / s));
 }
 
+/* ---------------------------------------------------------------- Mie radiance (sec. 3.1) */
+
+/* Sets (n >= 2) or clears (n = 0) the Mie weighting of rays: a ray leaving its source along the
+ * unit direction u is weighted by the table's intensity at the scattering angle
+ * theta = acos(u . k) between u and the laser direction k, linearly interpolated between
+ * theta_k = k pi / (n - 1).  READING: the paper weights by the Mie intensity at that angle
+ * (sec. 3.1) without naming a polarisation; the table holds the unpolarised intensity. */
+void orc_set_mie(orc_scene *S, const double *table, int n, const double laser[3])
+{
+    free(S->mie);
+    S->mie = NULL;
+    S->mie_n = 0;
+    if (n < 2) return;
+    S->mie = (double *)malloc((size_t)n * sizeof(double));
+    memcpy(S->mie, table, (size_t)n * sizeof(double));
+    S->mie_n = n;
+    const double k = sqrt(laser[0] * laser[0] + laser[1] * laser[1] + laser[2] * laser[2]);
+    for (int a = 0; a < 3; ++a) S->laser[a] = laser[a] / k;
+}
+
+/* Mie factor of a ray whose initial unit direction is u (1 without a table). */
+double orc_mie_weight(const orc_scene *S, const double u[3])
+{
+    if (!S->mie) return 1.0;
+    double c = u[0] * S->laser[0] + u[1] * S->laser[1] + u[2] * S->laser[2];
+    if (c > 1.0) c = 1.0;
+    if (c < -1.0) c = -1.0;
+    const double t = acos(c) / M_PI * (double)(S->mie_n - 1);
+    int i = (int)floor(t);
+    if (i > S->mie_n - 2) i = S->mie_n - 2;
+    const double f = t - (double)i;
+    return S->mie[i] * (1.0 - f) + S->mie[i + 1] * f;
+}
+
 /* ---------------------------------------------------------------- whole image */
 
 /* Deposits every ray of every source.  img_q: uint64 Q32.32 image (+=), img_f: double image
@@ -529,13 +566,13 @@ int orc_render(const orc_scene *S, const float *src, int64_t n_src, int32_t rays
 #pragma omp for schedule(static, 4)
         for (int64_t s = 0; s < n_src; ++s) {
             const float *sp = src + 4 * s;
-            const double w = sp[3];
             for (int32_t j = 0; j < rays_per_src; ++j) {
                 orc_ray ry;
                 int st = orc_trace_ray(S, sp, s, j, &ry);
                 tc[tid][st] += 1;
                 tc[tid][7] += (uint64_t)ry.n_steps;
                 if (st != ORC_DEPOSITED) continue;
+                const double w = (double)sp[3] * orc_mie_weight(S, ry.dir0);
                 const double x = ry.sensor_px[0], y = ry.sensor_px[1];
                 const int i0 = (int)floor(x), j0 = (int)floor(y);
                 for (int d = -rfp; d <= rfp; ++d) {
