@@ -66,6 +66,7 @@ extern "C" {
                                           different sources, which costs more cell gathers than the idle
                                           lanes it saves (measured 4% slower on the 128^3 BOS scene, 16% on
                                           the 512^3 Tomo-PIV scene) */
+#define PBR_MIE             (1u << 7)  /* weight every ray by the Mie intensity set by pbr_set_mie (sec. 3.1) */
 #define PBR_SOURCE_SUMS     (1u << 6)  /* add every deposited ray's sensor hit into the per-source sums set by
                                           pbr_set_source_sums (sec. 4: a dot's displacement is the mean of
                                           its rays') */
@@ -267,6 +268,39 @@ int pbr_read_image(pbr_ctx *ctx, int fmt, void *out_dev, double gain);
 /* Copies records [first, first + count) of the recording buffer to host memory out_host and
  * synchronises the stream.  Errors: ARG (range outside the buffer), STATE (no recording set). */
 int pbr_read_ray_exits(pbr_ctx *ctx, pbr_ray_exit *out_host, int64_t first, int64_t count);
+
+/* ---------------------------------------------------------------- Mie radiance (sec. 3.1) */
+
+/* Angles of the Mie intensity table: theta_k = k pi / (PBR_MIE_TABLE_SIZE - 1). */
+#define PBR_MIE_TABLE_SIZE 2049
+
+/* Scattering particles and illumination for ray weights (sec. 3.1: the radiance of a ray depends
+ * on the Mie scattering of the particle at the angle between the ray and the laser beam). */
+typedef struct pbr_mie {
+    double diameter;      /* particle diameter (m), > 0 */
+    double m_re, m_im;    /* particle refractive index relative to the ambient medium (m_re > 0, m_im >= 0) */
+    double wavelength;    /* laser wavelength in vacuum (m), > 0 */
+    double laser_dir[3];  /* propagation direction of the laser light (any length > 0) */
+} pbr_mie;
+
+/* The unpolarised Mie intensity (|S1|^2 + |S2|^2) / 2 of the particle at n equally spaced
+ * scattering angles over [0, pi], divided by its largest value, for size parameter
+ * pi diameter n_medium / wavelength (Bohren & Huffman's series).  Host only, no context.
+ * Errors (message in pbr_last_error(NULL)): ARG (null, n < 2, non-finite or out-of-range values,
+ * size parameter above 20000). */
+int pbr_mie_table(const pbr_mie *mie, double n_medium, double *out_host, int32_t n);
+
+/* Bytes of device memory pbr_set_mie needs: PBR_MIE_TABLE_SIZE doubles. */
+size_t pbr_mie_workspace_bytes(void);
+
+/* Computes the intensity table of `mie` in the ambient medium of the current field (n_medium =
+ * 1 + K rho_inf) and copies it to table_dev (caller-owned, 8-byte aligned, >=
+ * pbr_mie_workspace_bytes, alive while traces use it; the call synchronises the stream).  Traces
+ * with PBR_MIE then multiply each ray's source weight by the table at the angle between the ray's
+ * direction at its source and the laser direction (linear between nodes), so weights stay in
+ * [0, 1].  mie = NULL switches the weighting off.  Errors: ARG, STATE (no field; host-only context
+ * after the checks), WORKSPACE, HIP. */
+int pbr_set_mie(pbr_ctx *ctx, const pbr_mie *mie, void *table_dev, size_t ws_bytes);
 
 /* ---------------------------------------------------------------- BOS displacement check (sec. 4) */
 

@@ -393,8 +393,9 @@ int pbr_emit_and_trace(pbr_ctx *ctx, const float *src_dev, int64_t n_src, int32_
     if (!(d.z_sensor > ctx->optics.z_front_vertex + d.t))
         return fail(ctx, PBR_ERR_ARG, "sensor plane must lie behind the lens");
     if (flags & ~(uint32_t)(PBR_CLEAR_FIRST | PBR_RECORD_EXITS | PBR_PREC_FP64_ALL | PBR_PREC_SHOCK_FP64 |
-                            PBR_SURROGATE | PBR_LANE_REFILL | PBR_SOURCE_SUMS))
+                            PBR_SURROGATE | PBR_LANE_REFILL | PBR_SOURCE_SUMS | PBR_MIE))
         return fail(ctx, PBR_ERR_ARG, "unknown flag bits 0x%x", flags);
+    if ((flags & PBR_MIE) && !ctx->mie) return fail(ctx, PBR_ERR_STATE, "no Mie table set (pbr_set_mie)");
     if (flags & PBR_SOURCE_SUMS) {
         if (!ctx->src_sums) return fail(ctx, PBR_ERR_STATE, "no per-source sums set (pbr_set_source_sums)");
         if (n_src > ctx->src_sums_cap)
@@ -436,6 +437,11 @@ int pbr_emit_and_trace(pbr_ctx *ctx, const float *src_dev, int64_t n_src, int32_
     P.seed = seed;
     P.record = (flags & PBR_RECORD_EXITS) && ctx->rec_max > 0 ? 1 : 0;
     P.src_sums = (flags & PBR_SOURCE_SUMS) ? ctx->src_sums : nullptr;
+    if (flags & PBR_MIE) {
+        P.mie = ctx->mie;
+        P.mie_n = PBR_MIE_TABLE_SIZE;
+        for (int a = 0; a < 3; ++a) P.laser[a] = ctx->laser[a];
+    }
     ctx->last_max_steps = P.max_steps;
 
     const int prec = (flags & PBR_PREC_FP64_ALL) ? pbr::PREC_FP64
@@ -726,6 +732,72 @@ int pbr_displace_sources(pbr_ctx *ctx, const float *src_in_dev, float *src_out_d
     const int e = pbr::launch_displace((const float4 *)src_in_dev, (float4 *)src_out_dev, n_src, vg, dt, substeps,
                                        ctx->stream);
     if (e) return hip_fail(ctx, e, "displacement launch");
+    return PBR_OK;
+    PBR_GUARD_END
+}
+
+namespace {
+int check_mie(pbr_ctx *ctx, const pbr_mie *m, double n_medium, double *x)
+{
+    if (!std::isfinite(m->diameter) || !(m->diameter > 0.0) || !std::isfinite(m->wavelength) ||
+        !(m->wavelength > 0.0) || !std::isfinite(m->m_re) || !(m->m_re > 0.0) || !std::isfinite(m->m_im) ||
+        m->m_im < 0.0 || !finite3(m->laser_dir))
+        return fail(ctx, PBR_ERR_ARG, "Mie particle: diameter, wavelength, m_re > 0, m_im >= 0, finite direction");
+    const double k2 = m->laser_dir[0] * m->laser_dir[0] + m->laser_dir[1] * m->laser_dir[1] +
+                      m->laser_dir[2] * m->laser_dir[2];
+    if (!(k2 > 0.0)) return fail(ctx, PBR_ERR_ARG, "laser direction is zero");
+    if (!std::isfinite(n_medium) || !(n_medium > 0.0)) return fail(ctx, PBR_ERR_ARG, "medium index must be > 0");
+    *x = 3.14159265358979323846 * m->diameter * n_medium / m->wavelength;
+    if (*x > 20000.0) return fail(ctx, PBR_ERR_ARG, "size parameter %.6g above 20000", *x);
+    return PBR_OK;
+}
+}  // namespace
+
+int pbr_mie_table(const pbr_mie *mie, double n_medium, double *out_host, int32_t n)
+{
+    pbr_ctx *ctx = nullptr;
+    PBR_GUARD_BEGIN
+    if (!mie || !out_host) return fail(nullptr, PBR_ERR_ARG, "null argument");
+    if (n < 2) return fail(nullptr, PBR_ERR_ARG, "table needs at least 2 angles");
+    double x;
+    int r = check_mie(nullptr, mie, n_medium, &x);
+    if (r) return r;
+    if (!mie_intensity_table(std::complex<double>(mie->m_re, mie->m_im), x, n, out_host))
+        return fail(nullptr, PBR_ERR_ARG, "Mie intensity vanishes or overflows");
+    return PBR_OK;
+    PBR_GUARD_END
+}
+
+size_t pbr_mie_workspace_bytes(void) { return (size_t)PBR_MIE_TABLE_SIZE * sizeof(double); }
+
+int pbr_set_mie(pbr_ctx *ctx, const pbr_mie *mie, void *table_dev, size_t ws_bytes)
+{
+    if (!ctx) return PBR_ERR_ARG;
+    PBR_GUARD_BEGIN
+    if (!mie) {
+        ctx->mie = nullptr;
+        return PBR_OK;
+    }
+    if (!ctx->has_field) return fail(ctx, PBR_ERR_STATE, "set the density field first (ambient index)");
+    double x;
+    int r = check_mie(ctx, mie, 1.0 + ctx->K * ctx->rho_inf, &x);
+    if (r) return r;
+    if (!table_dev || ((uintptr_t)table_dev & 7u) != 0) return fail(ctx, PBR_ERR_ARG, "table is null or misaligned");
+    if (ws_bytes < pbr_mie_workspace_bytes())
+        return fail(ctx, PBR_ERR_WORKSPACE, "Mie table needs %zu bytes", pbr_mie_workspace_bytes());
+    std::vector<double> t(PBR_MIE_TABLE_SIZE);
+    if (!mie_intensity_table(std::complex<double>(mie->m_re, mie->m_im), x, PBR_MIE_TABLE_SIZE, t.data()))
+        return fail(ctx, PBR_ERR_ARG, "Mie intensity vanishes or overflows");
+    if (ctx->device < 0) return fail(ctx, PBR_ERR_STATE, "host-only context: no device work");
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(ctx, PBR_ERR_HIP, "hipSetDevice failed");
+    int e = (int)hipMemcpyAsync(table_dev, t.data(), pbr_mie_workspace_bytes(), hipMemcpyHostToDevice, ctx->stream);
+    if (!e) e = (int)hipStreamSynchronize(ctx->stream);
+    if (e) return hip_fail(ctx, e, "Mie table copy");
+    const double k = std::sqrt(mie->laser_dir[0] * mie->laser_dir[0] + mie->laser_dir[1] * mie->laser_dir[1] +
+                               mie->laser_dir[2] * mie->laser_dir[2]);
+    for (int a = 0; a < 3; ++a) ctx->laser[a] = mie->laser_dir[a] / k;
+    ctx->mie = (const double *)table_dev;
     return PBR_OK;
     PBR_GUARD_END
 }

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <complex>
 #include <string>
 #include <vector>
 
@@ -19,6 +20,8 @@ struct pbr_ctx {
     bool has_field = false;
     const float4 *cells = nullptr;
     pbr_source_sum *src_sums = nullptr;    // per-source hit sums (PBR_SOURCE_SUMS), device
+    const double *mie = nullptr;            // Mie intensity table (PBR_MIE), device
+    double laser[3] = {1.0, 0.0, 0.0};
     int64_t src_sums_cap = 0;
     unsigned *brick_gmax = nullptr;        // per-brick max |grad n| (float bits), device
     unsigned char *brick_fp64 = nullptr;   // per-brick FP64 flags, device
@@ -81,6 +84,8 @@ int derive(pbr_ctx *c, Derived *d);
 void fill_params(const pbr_ctx *ctx, const Derived &d, double ds, TraceParams *out);
 // Next context id (never 0).
 uint64_t next_uid();
+// Normalised unpolarised Mie intensity at n_angles angles over [0, pi] (pbr_mie.cpp).
+bool mie_intensity_table(std::complex<double> m, double x, int n_angles, double *out);
 // Chunk hook of an attached surrogate; fails with STATE (message on ctx) when it no longer
 // matches the context's scene.
 int surrogate_hook(pbr_ctx *ctx, ChunkHook *out);

@@ -91,6 +91,11 @@ struct TraceParams {
     unsigned long long *counters;
     // per-source sums of the sensor hits (null: not kept)
     pbr_source_sum *src_sums;
+    // Mie weighting (null: off): intensity table at theta_k = k pi / (mie_n - 1), laser direction
+    const double *mie;
+    double laser[3];
+    int mie_n;
+    int pad1;
 };
 
 // Per-ray state between the three trace kernels (emit -> box -> finish), 64 bytes.

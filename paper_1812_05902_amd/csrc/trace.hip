@@ -296,26 +296,49 @@ __device__ __forceinline__ void atomic_add_u64(unsigned long long *p, unsigned l
 // a sqrt(u1) sin 2 pi u2) of the front-vertex plane; (u1, u2) are the two 24-bit fields of
 // SplitMix64 output number (s << 32 | j).  The ray goes straight to the box (slab test) and its
 // state is written cell-local; a ray that never enters keeps its world position and direction.
-__device__ __forceinline__ void emit_ray(const TraceParams &P, int64_t rid, RayState &r)
+// Source position S and unit direction u of ray rid as it leaves its source.
+__device__ __forceinline__ void initial_direction(const TraceParams &P, int64_t rid, double S[3], double u[3])
 {
-    // FP64 set-up and optics: no contracted multiply-adds, so every kernel that inlines this
-    // (single-image and batched paths) computes the same bits
     #pragma clang fp contract(off)
     const int64_t s = rid / P.rays_per_src;
     const int32_t j = (int32_t)(rid - s * P.rays_per_src);
     const float4 sv = P.src[s];
-    const double S[3] = {(double)sv.x, (double)sv.y, (double)sv.z};
+    S[0] = (double)sv.x;
+    S[1] = (double)sv.y;
+    S[2] = (double)sv.z;
     const uint64_t hsh = splitmix64_at(P.seed, ((uint64_t)s << 32) | (uint64_t)(uint32_t)j);
     const double u1 = (double)(hsh >> 40) * (1.0 / 16777216.0);
     const double u2 = (double)((hsh >> 16) & 0xFFFFFFull) * (1.0 / 16777216.0);
     const double rr = P.a * sqrt(u1);
     double sn, cs;
     sincos(kTwoPi * u2, &sn, &cs);
-    double u[3] = {rr * cs - S[0], rr * sn - S[1], P.z_lens - S[2]};
-    {
-        const double il = 1.0 / sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-        u[0] *= il; u[1] *= il; u[2] *= il;
-    }
+    u[0] = rr * cs - S[0];
+    u[1] = rr * sn - S[1];
+    u[2] = P.z_lens - S[2];
+    const double il = 1.0 / sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    u[0] *= il; u[1] *= il; u[2] *= il;
+}
+
+// Mie factor of a ray leaving its source along u (sec. 3.1): the intensity table at the
+// scattering angle acos(u . laser), linear between its nodes theta_k = k pi / (mie_n - 1).
+__device__ __forceinline__ double mie_weight(const TraceParams &P, const double u[3])
+{
+    #pragma clang fp contract(off)
+    double c = u[0] * P.laser[0] + u[1] * P.laser[1] + u[2] * P.laser[2];
+    c = fmin(fmax(c, -1.0), 1.0);
+    const double t = acos(c) / 3.14159265358979323846 * (double)(P.mie_n - 1);
+    const int i = min((int)floor(t), P.mie_n - 2);
+    const double f = t - (double)i;
+    return P.mie[i] * (1.0 - f) + P.mie[i + 1] * f;
+}
+
+__device__ __forceinline__ void emit_ray(const TraceParams &P, int64_t rid, RayState &r)
+{
+    // FP64 set-up and optics: no contracted multiply-adds, so every kernel that inlines this
+    // (single-image and batched paths) computes the same bits
+    #pragma clang fp contract(off)
+    double S[3], u[3];
+    initial_direction(P, rid, S, u);
     double Rw[3] = {S[0], S[1], S[2]};
     bool inside = true;
 #pragma unroll
@@ -827,7 +850,8 @@ struct FinishShared {
 // take part (barriers inside).
 // RFX: footprint radius fixed at compile time (1..8), or 0 to switch on P.rfp per call (batches,
 // whose images differ).  A fixed radius keeps the spot arrays, and so the register count, small.
-template <int TILE, int RFX = 0>
+// MIE: the Mie weighting is compiled in only where it is used (it costs ~50 registers).
+template <int TILE, int RFX = 0, bool MIE = false>
 __device__ __forceinline__ void finish_block(const TraceParams &P, const RayState *__restrict__ st,
                                              int64_t first, int64_t base, int64_t n, FinishShared<TILE> &sh)
 {
@@ -874,7 +898,12 @@ __device__ __forceinline__ void finish_block(const TraceParams &P, const RayStat
     if (valid && status == PBR_RAY_DEPOSITED) {
         const int64_t rid = first + i;
         const float4 sv = P.src[rid / P.rays_per_src];
-        const double w = sv.w > 0.0f ? (sv.w < 1.0f ? (double)sv.w : 1.0) : 0.0;  // weights in [0, 1]
+        double w = sv.w > 0.0f ? (sv.w < 1.0f ? (double)sv.w : 1.0) : 0.0;  // weights in [0, 1]
+        if (MIE && P.mie) {  // the ray's Mie factor, from its direction at the source
+            double S0[3], u0[3];
+            initial_direction(P, rid, S0, u0);
+            w *= mie_weight(P, u0);
+        }
         const int tx0 = sh.tx0, ty0 = sh.ty0;
         if (RFX > 0) deposit<(RFX > 0 ? RFX : 1), TILE>(P, xpx, ypx, w, sh.tile, tx0, ty0);
         else switch (P.rfp) {
@@ -930,14 +959,14 @@ __device__ __forceinline__ void flush_counters(const TraceParams &P, FinishShare
         atomic_add_u64(P.counters + threadIdx.x, sh.cnt[threadIdx.x]);
 }
 
-template <int TILE, int RF>
+template <int TILE, int RF, bool MIE = false>
 __global__ void __launch_bounds__(256) k_finish(TraceParams P, const RayState *__restrict__ st,
                                                 int64_t first, int64_t n)
 {
     __shared__ FinishShared<TILE> sh;
     if (threadIdx.x < CNT_SLOTS) sh.cnt[threadIdx.x] = 0ull;
     for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += (int64_t)gridDim.x * blockDim.x)
-        finish_block<TILE, RF>(P, st, first, base, n, sh);
+        finish_block<TILE, RF, MIE>(P, st, first, base, n, sh);
     flush_counters<TILE>(P, sh);
 }
 
@@ -1399,7 +1428,13 @@ int launch_trace_chunk(const TraceParams &p, RayState *st, int64_t first, int64_
     if (!deposit) return 0;
     unsigned fblocks = blocks < 4096u ? blocks : 4096u;
     const RayState *cst = st;
-    switch (p.rfp) {
+    if (p.mie) switch (p.rfp) {  // spot radii of 1-3 pixels cover focused PIV particles
+        case 1: hipLaunchKernelGGL((k_finish<kTile, 1, true>), dim3(fblocks), dim3(256), 0, stream, p, cst, first, n); break;
+        case 2: hipLaunchKernelGGL((k_finish<kTile, 2, true>), dim3(fblocks), dim3(256), 0, stream, p, cst, first, n); break;
+        case 3: hipLaunchKernelGGL((k_finish<kTile, 3, true>), dim3(fblocks), dim3(256), 0, stream, p, cst, first, n); break;
+        default: hipLaunchKernelGGL((k_finish<kTile, 0, true>), dim3(fblocks), dim3(256), 0, stream, p, cst, first, n); break;
+    }
+    else switch (p.rfp) {
         case 1: hipLaunchKernelGGL((k_finish<kTile, 1>), dim3(fblocks), dim3(256), 0, stream, p, cst, first, n); break;
         case 2: hipLaunchKernelGGL((k_finish<kTile, 2>), dim3(fblocks), dim3(256), 0, stream, p, cst, first, n); break;
         case 3: hipLaunchKernelGGL((k_finish<kTile, 3>), dim3(fblocks), dim3(256), 0, stream, p, cst, first, n); break;

@@ -26,6 +26,8 @@ PBR_NUM_STATUS = 7
 PBR_CLEAR_FIRST, PBR_RECORD_EXITS, PBR_PREC_FP64_ALL, PBR_PREC_SHOCK_FP64, PBR_SURROGATE = 1, 2, 4, 8, 16
 PBR_LANE_REFILL = 32
 PBR_SOURCE_SUMS = 64
+PBR_MIE = 128
+PBR_MIE_TABLE_SIZE = 2049
 PBR_SURR_PARAMS = 200710
 PBR_FMT_RAW_U64, PBR_FMT_F32, PBR_FMT_U16 = 0, 1, 2
 
@@ -42,7 +44,8 @@ EXPORTED = ["pbr_create", "pbr_destroy", "pbr_last_error", "pbr_set_stream",
             "pbr_surrogate_gradients", "pbr_surrogate_adam_step", "pbr_surrogate_train",
             "pbr_surrogate_tile_map", "pbr_set_surrogate", "pbr_probe_u64_atomics",
             "pbr_set_source_sums", "pbr_dot_map_workspace_bytes", "pbr_dot_displacement_map",
-            "pbr_bos_theory_map", "pbr_displace_sources"]
+            "pbr_bos_theory_map", "pbr_displace_sources", "pbr_mie_table", "pbr_mie_workspace_bytes",
+            "pbr_set_mie"]
 
 
 class PbrError(RuntimeError):
@@ -85,6 +88,11 @@ class pbr_precision_report(C.Structure):
 
 class pbr_source_sum(C.Structure):
     _fields_ = [("sum_x", C.c_int64), ("sum_y", C.c_int64), ("hits", C.c_uint64), ("reserved", C.c_uint64)]
+
+
+class pbr_mie(C.Structure):
+    _fields_ = [("diameter", C.c_double), ("m_re", C.c_double), ("m_im", C.c_double), ("wavelength", C.c_double),
+                ("laser_dir", C.c_double * 3)]
 
 
 class pbr_map_grid(C.Structure):
@@ -184,6 +192,9 @@ def load(path: str = LIB_PATH):
         "pbr_dot_displacement_map": (I, [P, P, P, P, I64, C.POINTER(pbr_map_grid), P, C.c_size_t, P]),
         "pbr_bos_theory_map": (I, [P, C.POINTER(pbr_map_grid), C.c_int32, P]),
         "pbr_displace_sources": (I, [P, P, P, I64, P, I, I, I, P, P, D, C.c_int32]),
+        "pbr_mie_table": (I, [C.POINTER(pbr_mie), D, P, C.c_int32]),
+        "pbr_mie_workspace_bytes": (C.c_size_t, []),
+        "pbr_set_mie": (I, [P, C.POINTER(pbr_mie), P, C.c_size_t]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(l, name)
@@ -324,6 +335,28 @@ def pbr_displace_sources(ctx, src_in, src_out, vel, origin, spacing, dt, substep
                                             o, s, float(dt), int(substeps)))
 
 
+def mie_params(diameter, m, wavelength, laser_dir) -> pbr_mie:
+    m = complex(m)
+    return pbr_mie(float(diameter), m.real, m.imag, float(wavelength), (C.c_double * 3)(*laser_dir))
+
+
+def pbr_mie_table(mie: pbr_mie, n_medium, n=PBR_MIE_TABLE_SIZE) -> np.ndarray:
+    out = np.zeros(int(n))
+    code = load().pbr_mie_table(C.byref(mie), float(n_medium), out.ctypes.data_as(C.c_void_p), int(n))
+    if code != PBR_OK:
+        raise PbrError(code, _lib.pbr_last_error(None).decode())
+    return out
+
+
+def pbr_mie_workspace_bytes() -> int:
+    return int(load().pbr_mie_workspace_bytes())
+
+
+def pbr_set_mie(ctx, mie, table):
+    nbytes = 0 if table is None else table.numel() * table.element_size()
+    _check(ctx, load().pbr_set_mie(ctx, None if mie is None else C.byref(mie), _dptr(table), nbytes))
+
+
 # ------------------------------------------------------------------ convenience wrapper
 
 def stats_dict(st: pbr_stats) -> dict:
@@ -450,6 +483,15 @@ class Renderer:
         out = self.torch.empty(g.ny, g.nx, 2, dtype=self.torch.float32, device=self.device)
         pbr_bos_theory_map(self.ctx, g, samples, out)
         return out
+
+    def set_mie(self, diameter, m, wavelength, laser_dir):
+        """Mie weighting of later traces with PBR_MIE (sec. 3.1): particle diameter (m), relative
+        index m (complex), laser wavelength (m) and propagation direction; None clears it."""
+        if diameter is None:
+            pbr_set_mie(self.ctx, None, None)
+            return
+        self.mie_table = self.torch.empty(PBR_MIE_TABLE_SIZE, dtype=self.torch.float64, device=self.device)
+        pbr_set_mie(self.ctx, mie_params(diameter, m, wavelength, laser_dir), self.mie_table)
 
     def displace_sources(self, src, vel, origin, spacing, dt, substeps=4):
         """Sources of the second frame of a PIV pair: src advanced by the velocity field vel

@@ -210,7 +210,7 @@ def test_call_order_and_trace_validation(lib):
         assert lib.pbr_emit_and_trace(h, FAKE, 1, 1, 0, 0.0, 0, None) == pbr.PBR_ERR_ARG
         assert lib.pbr_emit_and_trace(h, FAKE, 1, 1, 0, math.nan, 0, None) == pbr.PBR_ERR_ARG
         assert lib.pbr_emit_and_trace(h, None, 5, 1, 0, 1e-4, 0, None) == pbr.PBR_ERR_ARG
-        assert lib.pbr_emit_and_trace(h, FAKE, 1, 1, 0, 1e-4, 1 << 7, None) == pbr.PBR_ERR_ARG
+        assert lib.pbr_emit_and_trace(h, FAKE, 1, 1, 0, 1e-4, 1 << 8, None) == pbr.PBR_ERR_ARG
         # 2^32 rays could overflow one pixel of the Q32.32 sensor
         assert lib.pbr_emit_and_trace(h, FAKE, 1 << 20, 1 << 12, 0, 1e-4, 1, C.byref(st)) == pbr.PBR_ERR_OVERFLOW
         assert lib.pbr_emit_and_trace(h, FAKE, 1, 1, 0, 1e-4, 0, None) == pbr.PBR_ERR_STATE
@@ -370,5 +370,52 @@ def test_piv_displacement_validates_before_device_work(lib):
         assert f(h, FAKE, FAKE, 1, FAKE, 4, 4, 4, o, s, 1e-3, 4097) == pbr.PBR_ERR_ARG
         assert f(h, FAKE, FAKE, 1, FAKE, 4, 4, 4, o, s, 1e-3, 4) == pbr.PBR_ERR_STATE
         assert "host-only" in _err(lib, h)
+    finally:
+        lib.pbr_destroy(h)
+
+
+@pytest.mark.parametrize("d,m,lam", [(1e-6, 1.47 + 0j, 532e-9), (10e-6, 1.59 + 0.002j, 532e-9),
+                                     (50e-9, 1.5 + 0j, 532e-9), (3e-6, 2.0 + 1.0j, 1064e-9)])
+def test_mie_table_matches_oracle(lib, d, m, lam):
+    """The library's host Mie series (C++) against the oracle's (numpy), both from Bohren &
+    Huffman's formulas: the normalised intensity table agrees to 1e-9."""
+    from oracle import mie
+    n_med = 1.000277
+    got = pbr.pbr_mie_table(pbr.mie_params(d, m, lam, (1, 0, 0)), n_med)
+    want = mie.intensity_table(m, mie.size_parameter(d, lam, n_med), pbr.PBR_MIE_TABLE_SIZE)
+    assert got.max() == 1.0
+    np.testing.assert_allclose(got, want, rtol=1e-9, atol=1e-12)
+
+
+def test_mie_entry_points_validate(lib):
+    with pytest.raises(pbr.PbrError):
+        pbr.pbr_mie_table(pbr.mie_params(-1e-6, 1.5, 532e-9, (1, 0, 0)), 1.0)
+    with pytest.raises(pbr.PbrError):
+        pbr.pbr_mie_table(pbr.mie_params(1e-6, 1.5 - 0.1j, 532e-9, (1, 0, 0)), 1.0)
+    with pytest.raises(pbr.PbrError):
+        pbr.pbr_mie_table(pbr.mie_params(1e-6, 1.5, 532e-9, (0, 0, 0)), 1.0)
+    with pytest.raises(pbr.PbrError):
+        pbr.pbr_mie_table(pbr.mie_params(1e-2, 1.5, 532e-9, (1, 0, 0)), 1.0)  # x ~ 6e4
+    with pytest.raises(pbr.PbrError):
+        pbr.pbr_mie_table(pbr.mie_params(1e-6, 1.5, 532e-9, (1, 0, 0)), 1.0, n=1)
+    assert pbr.pbr_mie_workspace_bytes() == 8 * pbr.PBR_MIE_TABLE_SIZE
+    h = _host_ctx(lib)
+    try:
+        good = pbr.mie_params(1e-6, 1.47, 532e-9, (1, 0, 0))
+        ws = pbr.pbr_mie_workspace_bytes()
+        assert lib.pbr_set_mie(h, C.byref(good), FAKE, ws) == pbr.PBR_ERR_STATE  # no field yet
+        assert _set_field(lib, h) == pbr.PBR_OK
+        assert lib.pbr_set_mie(h, C.byref(pbr.mie_params(1e-6, 0.0, 532e-9, (1, 0, 0))), FAKE, ws) == pbr.PBR_ERR_ARG
+        assert lib.pbr_set_mie(h, C.byref(good), None, ws) == pbr.PBR_ERR_ARG
+        assert lib.pbr_set_mie(h, C.byref(good), FAKE + 4, ws) == pbr.PBR_ERR_ARG
+        assert lib.pbr_set_mie(h, C.byref(good), FAKE, ws - 8) == pbr.PBR_ERR_WORKSPACE
+        assert lib.pbr_set_mie(h, C.byref(good), FAKE, ws) == pbr.PBR_ERR_STATE
+        assert "host-only" in _err(lib, h)
+        assert lib.pbr_set_mie(h, None, None, 0) == pbr.PBR_OK  # off
+        assert lib.pbr_set_optics(h, C.byref(_optics())) == pbr.PBR_OK
+        assert lib.pbr_set_sensor(h, C.byref(_sensor()), FAKE) == pbr.PBR_OK
+        assert lib.pbr_set_trace_workspace(h, FAKE, 1 << 20) == pbr.PBR_OK
+        assert lib.pbr_emit_and_trace(h, FAKE, 1, 1, 0, 1e-4, pbr.PBR_MIE, None) == pbr.PBR_ERR_STATE
+        assert "Mie" in _err(lib, h)
     finally:
         lib.pbr_destroy(h)
