@@ -58,6 +58,14 @@ class Ray(C.Structure):
     ]
 
 
+class Surface(C.Structure):
+    _fields_ = [("type", C.c_int32), ("reserved", C.c_int32), ("z", C.c_double), ("radius", C.c_double),
+                ("clear", C.c_double), ("n_after", C.c_double), ("pitch", C.c_double)]
+
+
+SURF_REFRACT, SURF_MIRROR, SURF_APERTURE, SURF_LENSLETS = range(4)
+
+
 RAY_DTYPE = np.dtype([
     ("ray_id", "<i8"), ("status", "<i4"), ("n_steps", "<i4"), ("entered", "<i4"), ("pad", "<i4"),
     ("lens_point", "<f8", 2), ("dir0", "<f8", 3), ("vol_exit_pos", "<f8", 3),
@@ -198,6 +206,26 @@ class OracleScene:
         lib().orc_trace_ids(self.h, _ptr(src), int(rays_per_src), _ptr(ids), len(ids), _ptr(out),
                             int(n_threads))
         return out
+
+    def set_chain(self, surfaces, aim_z, aim_r):
+        """General optical chain (``orc_set_chain``): surfaces = list of (type, z, radius, clear,
+        n_after, pitch); [] restores the built-in singlet."""
+        arr = (Surface * max(len(surfaces), 1))()
+        for k, (t, z, r, c, n, p) in enumerate(surfaces):
+            arr[k] = Surface(int(t), 0, float(z), float(r), float(c), float(n), float(p))
+        l = lib()
+        l.orc_set_chain.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_double, C.c_double]
+        l.orc_set_chain(self.h, C.cast(arr, C.c_void_p), len(surfaces), float(aim_z), float(aim_r))
+
+    def chain_to_sensor(self, P, u):
+        P = np.ascontiguousarray(P, dtype=np.float64)
+        u = np.ascontiguousarray(u, dtype=np.float64)
+        px = np.zeros(2)
+        l = lib()
+        l.orc_chain_to_sensor.restype = C.c_int
+        l.orc_chain_to_sensor.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+        st = l.orc_chain_to_sensor(self.h, _ptr(P), _ptr(u), _ptr(px))
+        return st, px
 
     def set_mie(self, table, laser_dir):
         """Weights every ray by the Mie table at its scattering angle (``orc_set_mie``);

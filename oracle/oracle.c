@@ -68,6 +68,18 @@ typedef struct {
     double sensor_px[2];         /* sensor hit in pixel coordinates */
 } orc_ray;
 
+/* One surface of a general optical chain (sec. 3.3), rotationally symmetric about the axis. */
+enum { ORC_SURF_REFRACT = 0, ORC_SURF_MIRROR = 1, ORC_SURF_APERTURE = 2, ORC_SURF_LENSLETS = 3 };
+typedef struct {
+    int32_t type, reserved;
+    double z;          /* vertex on the axis */
+    double radius;     /* signed radius of curvature (centre at z + radius); 0 = plane */
+    double clear;      /* rays meeting the surface farther than this from the axis are blocked */
+    double n_after;    /* index after a refracting surface; <= 0 = ambient */
+    double pitch;      /* lenslet pitch (square grid centred on the axis) */
+} orc_surface;
+#define ORC_MAX_SURFACES 16
+
 typedef struct {
     orc_cfg c;
     double *dn, *gx, *gy, *gz;   /* node values: n - 1 and grad n (grid mode) */
@@ -83,6 +95,9 @@ typedef struct {
     double sigma_px;             /* Gaussian spot sigma in pixels */
     int r_fp;                    /* footprint half-width in pixels */
     int max_steps;
+    orc_surface chain[ORC_MAX_SURFACES];  /* general optical chain (n_chain > 0) replacing the singlet */
+    int n_chain;
+    double aim_z, aim_r;         /* with a chain: rays aim at this disk (sec. 3.1) */
     double *mie;                 /* Mie intensity table at theta_k = k pi / (mie_n - 1), or NULL */
     int mie_n;
     double laser[3];             /* unit propagation direction of the laser light */
@@ -344,6 +359,107 @@ int orc_lens_to_sensor(const orc_scene *S, const double P[3], const double u[3],
     return ORC_DEPOSITED;
 }
 
+/* ---------------------------------------------------------------- general optical chain (sec. 3.3) */
+
+/* First intersection, at s > 1e-12 along P + s u, of the ray with the sphere of signed radius Rs
+ * whose vertex is (cx, cy, zv), on the cap around the vertex (the half of the sphere facing its
+ * vertex); Rs = 0 is the plane z = zv.  Writes the hit and the geometric normal (H - C) / Rs
+ * ((0, 0, -1) for a plane), which faces -z at the vertex.  Returns 0 on a hit. */
+static int chain_hit(const double P[3], const double u[3], double cx, double cy, double zv, double Rs,
+                     double H[3], double N[3])
+{
+    const double eps = 1e-12;
+    if (Rs == 0.0) {
+        if (u[2] == 0.0) return 1;
+        const double s = (zv - P[2]) / u[2];
+        if (!(s > eps)) return 1;
+        H[0] = P[0] + s * u[0]; H[1] = P[1] + s * u[1]; H[2] = zv;
+        N[0] = 0.0; N[1] = 0.0; N[2] = -1.0;
+        return 0;
+    }
+    const double C[3] = {cx, cy, zv + Rs};
+    const double d[3] = {P[0] - C[0], P[1] - C[1], P[2] - C[2]};
+    const double b = d[0] * u[0] + d[1] * u[1] + d[2] * u[2];
+    const double c = d[0] * d[0] + d[1] * d[1] + d[2] * d[2] - Rs * Rs;
+    const double disc = b * b - c;
+    if (disc < 0.0) return 1;
+    const double sq = sqrt(disc);
+    const double q = -(b + (b >= 0.0 ? sq : -sq));     /* stable pair of roots: q and c / q */
+    double r1 = q, r2 = (q != 0.0) ? c / q : q;
+    if (r1 > r2) { double t = r1; r1 = r2; r2 = t; }
+    const double roots[2] = {r1, r2};
+    for (int k = 0; k < 2; ++k) {
+        const double s = roots[k];
+        if (!(s > eps)) continue;
+        const double h[3] = {P[0] + s * u[0], P[1] + s * u[1], P[2] + s * u[2]};
+        if ((h[2] - C[2]) * Rs > 0.0) continue;        /* far half of the sphere */
+        for (int a = 0; a < 3; ++a) { H[a] = h[a]; N[a] = (h[a] - C[a]) / Rs; }
+        return 0;
+    }
+    return 1;
+}
+
+/* The ray from P (world) along unit u through the surfaces of the chain in order, then onto the
+ * sensor plane.  Refraction by Snell's law (eq. 7) with total internal reflection, reflection by
+ * the law of reflection about the local normal, apertures and surface rims block (sec. 3.3, items
+ * 1-3); a lenslet array refracts at the spherical cap of the lenslet whose square cell the ray
+ * meets (crossing into a neighbouring cell blocks it).  READING: sequential tracing; a ray that
+ * would have to travel backwards to reach the next surface is blocked. */
+int orc_chain_to_sensor(const orc_scene *S, const double P0[3], const double u0[3], double px[2])
+{
+    double P[3] = {P0[0], P0[1], P0[2]}, u[3] = {u0[0], u0[1], u0[2]};
+    double n_cur = S->n_inf;
+    for (int k = 0; k < S->n_chain; ++k) {
+        const orc_surface *f = &S->chain[k];
+        double H[3], N[3];
+        double cx = 0.0, cy = 0.0, Rs = f->radius;
+        if (f->type == ORC_SURF_APERTURE) Rs = 0.0;
+        if (f->type == ORC_SURF_LENSLETS) {
+            double A[3], NA[3];                           /* cell from the plane of the array */
+            if (chain_hit(P, u, 0.0, 0.0, f->z, 0.0, A, NA)) return ORC_BLOCKED_LENS;
+            cx = f->pitch * floor(A[0] / f->pitch + 0.5);
+            cy = f->pitch * floor(A[1] / f->pitch + 0.5);
+        }
+        if (chain_hit(P, u, cx, cy, f->z, Rs, H, N))
+            return f->type == ORC_SURF_APERTURE ? ORC_BLOCKED_APERTURE : ORC_BLOCKED_LENS;
+        if (H[0] * H[0] + H[1] * H[1] > f->clear * f->clear)
+            return f->type == ORC_SURF_APERTURE ? ORC_BLOCKED_APERTURE : ORC_BLOCKED_LENS;
+        if (f->type == ORC_SURF_LENSLETS &&
+            (fabs(H[0] - cx) > 0.5 * f->pitch || fabs(H[1] - cy) > 0.5 * f->pitch))
+            return ORC_BLOCKED_LENS;
+        const double un = u[0] * N[0] + u[1] * N[1] + u[2] * N[2];
+        if (un > 0.0) for (int a = 0; a < 3; ++a) N[a] = -N[a];   /* normal against the ray */
+        if (f->type == ORC_SURF_MIRROR) {
+            const double d = u[0] * N[0] + u[1] * N[1] + u[2] * N[2];
+            for (int a = 0; a < 3; ++a) u[a] = u[a] - 2.0 * d * N[a];
+        } else if (f->type == ORC_SURF_REFRACT || f->type == ORC_SURF_LENSLETS) {
+            const double n_next = f->n_after > 0.0 ? f->n_after : S->n_inf;
+            double v[3];
+            if (orc_refract(u, N, n_cur, n_next, v)) return ORC_TIR;
+            const double vn = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+            for (int a = 0; a < 3; ++a) u[a] = v[a] / vn;
+            n_cur = n_next;
+        }
+        for (int a = 0; a < 3; ++a) P[a] = H[a];
+    }
+    if (u[2] == 0.0) return ORC_MISSED;
+    const double s = (S->z_sensor - P[2]) / u[2];
+    if (!(s > 0.0)) return ORC_MISSED;
+    px[0] = (P[0] + s * u[0]) / S->c.pitch + 0.5 * S->c.width;
+    px[1] = (P[1] + s * u[1]) / S->c.pitch + 0.5 * S->c.height;
+    return ORC_DEPOSITED;
+}
+
+/* Sets (n >= 1) or clears (n = 0) the general chain; rays then aim at the disk of radius aim_r in
+ * the plane z = aim_z. */
+void orc_set_chain(orc_scene *S, const orc_surface *surf, int n, double aim_z, double aim_r)
+{
+    S->n_chain = n < 0 ? 0 : (n > ORC_MAX_SURFACES ? ORC_MAX_SURFACES : n);
+    for (int k = 0; k < S->n_chain; ++k) S->chain[k] = surf[k];
+    S->aim_z = aim_z;
+    S->aim_r = aim_r;
+}
+
 /* Paraxial marginal-ray trace (y, n*u) from the on-axis object point z_obj through the two
  * surfaces: gives the image plane and the lateral magnification M = (n u)_obj / (n u)_img. */
 static void paraxial_image(const orc_scene *S, double z_obj, double *z_img, double *M)
@@ -433,8 +549,9 @@ int orc_trace_ray(const orc_scene *S, const float src[4], int64_t s, int32_t j, 
     /* sec. 3.1: aperture point sampled uniformly by area on the disk of radius a */
     double uu[2];
     orc_ray_uniforms(S->c.seed, s, j, uu);
-    double r = S->a * sqrt(uu[0]), phi = 2.0 * M_PI * uu[1];
-    double L[3] = {r * cos(phi), r * sin(phi), S->c.z_lens};
+    const double aim_r = S->n_chain ? S->aim_r : S->a, aim_z = S->n_chain ? S->aim_z : S->c.z_lens;
+    double r = aim_r * sqrt(uu[0]), phi = 2.0 * M_PI * uu[1];
+    double L[3] = {r * cos(phi), r * sin(phi), aim_z};
     out->lens_point[0] = L[0]; out->lens_point[1] = L[1];
     double u[3] = {L[0] - P0[0], L[1] - P0[1], L[2] - P0[2]};
     double nu = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
@@ -482,7 +599,8 @@ int orc_trace_ray(const orc_scene *S, const float src[4], int64_t s, int32_t j, 
         for (int a = 0; a < 3; ++a) dir[a] = T[a] / tn;
     }
     for (int a = 0; a < 3; ++a) { out->vol_exit_pos[a] = R[a]; out->vol_exit_dir[a] = dir[a]; }
-    out->status = orc_lens_to_sensor(S, R, dir, out->sensor_px);
+    out->status = S->n_chain ? orc_chain_to_sensor(S, R, dir, out->sensor_px)
+                             : orc_lens_to_sensor(S, R, dir, out->sensor_px);
     if (out->status == ORC_DEPOSITED) {
         int i0 = (int)floor(out->sensor_px[0]), j0 = (int)floor(out->sensor_px[1]);
         if (out->sensor_px[0] < 0.0 || out->sensor_px[1] < 0.0 ||
