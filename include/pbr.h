@@ -17,7 +17,7 @@
  *   - "_dev" pointers are device memory of the context's GPU, owned by the caller.  The library
  *     never allocates large buffers: the caller provides the field workspace, the trace
  *     workspace, the sensor accumulator and the ray-exit record buffer.  pbr_create allocates one 4 KiB device block
- *     for counters, freed by pbr_destroy.
+ *     for counters and the optical chain, freed by pbr_destroy.
  *   - All device work is enqueued on the context's HIP stream and is asynchronous unless a
  *     function says it synchronises.  The caller keeps its buffers alive until the stream has
  *     passed the work that uses them.
@@ -158,7 +158,7 @@ typedef struct pbr_precision_report {
 typedef struct pbr_ctx pbr_ctx;
 
 /* Creates a context on HIP device `device` that enqueues on `hip_stream` (a hipStream_t; NULL =
- * the null stream).  Allocates a 4 KiB device block for counters.  *out is NULL on failure.
+ * the null stream).  Allocates a 4 KiB device block for counters and the optical chain.  *out is NULL on failure.
  * device = -1 creates a host-only context: every input is validated and pbr_get_derived works,
  * but no device memory is touched (pbr_set_density_field records the grid without launching) and
  * calls that need device work (trace, readout, record copies) return PBR_ERR_STATE after their
@@ -268,6 +268,50 @@ int pbr_read_image(pbr_ctx *ctx, int fmt, void *out_dev, double gain);
 /* Copies records [first, first + count) of the recording buffer to host memory out_host and
  * synchronises the stream.  Errors: ARG (range outside the buffer), STATE (no recording set). */
 int pbr_read_ray_exits(pbr_ctx *ctx, pbr_ray_exit *out_host, int64_t first, int64_t count);
+
+/* ---------------------------------------------------------------- general optical chain (sec. 3.3) */
+
+#define PBR_MAX_SURFACES  16
+#define PBR_SURF_REFRACT  0  /* sphere or plane between two media: Snell's law (eq. 7), total internal reflection */
+#define PBR_SURF_MIRROR   1  /* reflecting sphere or plane: law of reflection about the local normal */
+#define PBR_SURF_APERTURE 2  /* plane stop: rays crossing it farther than `clear` from the axis are blocked */
+#define PBR_SURF_LENSLETS 3  /* plane array of spherical lenslets on a square grid of `pitch` centred on the
+                                axis (a plenoptic camera's lens array), refracting into n_after; a ray
+                                that would meet the cap outside the cell it entered is blocked */
+
+/* One surface, rotationally symmetric about the optical axis (z). */
+typedef struct pbr_surface {
+    int32_t type;      /* PBR_SURF_* */
+    int32_t reserved;
+    double z;          /* vertex on the axis (m) */
+    double radius;     /* signed radius of curvature (m), centre at z + radius; 0 = plane (ignored for stops) */
+    double clear;      /* rays meeting the surface farther than this from the axis are blocked (m), > 0 */
+    double n_after;    /* refractive index after the surface (REFRACT, LENSLETS); <= 0 = the ambient index */
+    double pitch;      /* LENSLETS: lenslet pitch (m), > 0 */
+} pbr_surface;
+
+/* A sequence of surfaces traced in order after the density box (sec. 3.3: mirrors, lenses,
+ * windows, apertures and lens arrays), replacing the singlet of pbr_set_optics.  Rays are emitted
+ * towards uniform points of the disk of radius aim_radius in the plane z = aim_z (sec. 3.1), then
+ * meet each surface at the first intersection ahead of them on the cap around its vertex (a ray
+ * that would have to travel backwards is blocked), and finally the sensor plane, which must be
+ * given explicitly (pbr_sensor.z_sensor) together with the spot (pbr_sensor.sigma_px > 0): the
+ * magnification and f-number of eq. 8 are not defined for a general chain. */
+typedef struct pbr_optical_chain {
+    int32_t n_surfaces;  /* 1 .. PBR_MAX_SURFACES */
+    int32_t reserved;
+    double aim_z;        /* plane of the emission target disk, beyond the density box (m) */
+    double aim_radius;   /* its radius (m), > 0 */
+    pbr_surface s[PBR_MAX_SURFACES];
+} pbr_optical_chain;
+
+/* Copies the chain (it may be released on return; the call synchronises the stream) into the
+ * context's device block; later traces use it instead of the singlet.  chain = NULL returns to the
+ * singlet of pbr_set_optics.  With a chain set, pbr_calibrate_precision, pbr_bos_theory_map,
+ * surrogate training and batches (which rely on the singlet's paraxial optics) return STATE.
+ * Errors: ARG (bad counts, types, non-finite values, clear <= 0, lenslet pitch <= 0 or a lenslet
+ * radius smaller than half the pitch, aim_radius <= 0), HIP. */
+int pbr_set_optical_chain(pbr_ctx *ctx, const pbr_optical_chain *chain);
 
 /* ---------------------------------------------------------------- Mie radiance (sec. 3.1) */
 

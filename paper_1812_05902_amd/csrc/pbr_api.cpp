@@ -43,11 +43,25 @@ bool finite3(const double *v) { return std::isfinite(v[0]) && std::isfinite(v[1]
 // plane of z_focus and the lateral magnification, and the spot sigma from eq. 8.
 int derive(pbr_ctx *c, Derived *d)
 {
-    if (!c->has_field || !c->has_optics || !c->has_sensor)
+    if (!c->has_field || !(c->has_optics || c->has_chain) || !c->has_sensor)
         return fail(c, PBR_ERR_STATE, "field, optics and sensor must be set first");
     const pbr_optics &o = c->optics;
     const pbr_sensor &s = c->sensor;
     d->n_inf = 1.0 + c->K * c->rho_inf;
+    if (c->has_chain) {
+        // a general chain has no singlet: explicit sensor plane and spot
+        if (!std::isfinite(s.z_sensor) || !(s.sigma_px > 0.0))
+            return fail(c, PBR_ERR_STATE, "an optical chain needs an explicit sensor plane and sigma_px > 0");
+        d->R = d->t = d->clear = d->M = std::nan("");
+        d->a = c->chain.aim_radius;
+        d->z_sensor = s.z_sensor;
+        d->sigma_px = s.sigma_px;
+        d->rfp = std::max(1, (int)std::ceil(3.0 * d->sigma_px));
+        if (d->rfp > pbr::kMaxFootprint)
+            return fail(c, PBR_ERR_ARG, "spot sigma %.3g px needs a window wider than %d px", d->sigma_px,
+                        2 * pbr::kMaxFootprint + 1);
+        return PBR_OK;
+    }
     const double f = o.focal_length, ng = o.n_glass;
     d->t = o.thickness > 0.0 ? o.thickness : 0.1 * f;
     // (ng-1) [2/R - (ng-1) t / (ng R^2)] = 1/f  <=>  R^2 - 2 (ng-1) f R + (ng-1)^2 f t / ng = 0
@@ -114,7 +128,7 @@ void fill_params(const pbr_ctx *ctx, const Derived &d, double ds, TraceParams *o
         P.step_cell[a] = P.h / ctx->spacing[a];
     }
     P.n_inf = d.n_inf;
-    P.z_lens = ctx->optics.z_front_vertex;
+    P.z_lens = ctx->has_chain ? ctx->chain.aim_z : ctx->optics.z_front_vertex;
     P.a = d.a; P.R = d.R; P.t = d.t; P.clear = d.clear; P.n_glass = ctx->optics.n_glass;
     P.z_sensor = d.z_sensor;
     P.accum = ctx->accum;
@@ -127,6 +141,7 @@ void fill_params(const pbr_ctx *ctx, const Derived &d, double ds, TraceParams *o
     P.rec_stride = ctx->rec_stride;
     P.rec_max = ctx->rec_max;
     P.counters = ctx->counters;
+    P.chain = ctx->has_chain ? (const pbr_optical_chain *)((const char *)ctx->counters + pbr::kChainOffset) : nullptr;
 }
 
 uint64_t next_uid()
@@ -388,10 +403,16 @@ int pbr_emit_and_trace(pbr_ctx *ctx, const float *src_dev, int64_t n_src, int32_
     if (!(ds > 0.0) || !std::isfinite(ds)) return fail(ctx, PBR_ERR_ARG, "ds must be finite and > 0");
     if (n_src > (int64_t)1 << 31) return fail(ctx, PBR_ERR_ARG, "n_src above 2^31");
     const double zmax = ctx->origin[2] + (double)(ctx->nz - 1) * ctx->spacing[2];
-    if (!(ctx->optics.z_front_vertex > zmax))
-        return fail(ctx, PBR_ERR_ARG, "lens front vertex must lie beyond the density box (z > %.6g)", zmax);
-    if (!(d.z_sensor > ctx->optics.z_front_vertex + d.t))
-        return fail(ctx, PBR_ERR_ARG, "sensor plane must lie behind the lens");
+    if (ctx->has_chain) {
+        if (!(ctx->chain.aim_z > zmax))
+            return fail(ctx, PBR_ERR_ARG, "the chain's emission target must lie beyond the density box (z > %.6g)",
+                        zmax);
+    } else {
+        if (!(ctx->optics.z_front_vertex > zmax))
+            return fail(ctx, PBR_ERR_ARG, "lens front vertex must lie beyond the density box (z > %.6g)", zmax);
+        if (!(d.z_sensor > ctx->optics.z_front_vertex + d.t))
+            return fail(ctx, PBR_ERR_ARG, "sensor plane must lie behind the lens");
+    }
     if (flags & ~(uint32_t)(PBR_CLEAR_FIRST | PBR_RECORD_EXITS | PBR_PREC_FP64_ALL | PBR_PREC_SHOCK_FP64 |
                             PBR_SURROGATE | PBR_LANE_REFILL | PBR_SOURCE_SUMS | PBR_MIE))
         return fail(ctx, PBR_ERR_ARG, "unknown flag bits 0x%x", flags);
@@ -506,6 +527,7 @@ int pbr_calibrate_precision(pbr_ctx *ctx, double tol_px, double steep_frac, int3
     Derived d;
     int r = derive(ctx, &d);
     if (r) return r;
+    if (ctx->has_chain) return fail(ctx, PBR_ERR_STATE, "precision calibration needs the singlet (an optical chain is set)");
     if (!(tol_px >= 0.0) || !std::isfinite(tol_px)) return fail(ctx, PBR_ERR_ARG, "tol_px must be finite and >= 0");
     if (!(steep_frac >= 0.0 && steep_frac <= 1.0)) return fail(ctx, PBR_ERR_ARG, "steep_frac must lie in [0, 1]");
     if (rays_per_brick < 1 || rays_per_brick > 256) return fail(ctx, PBR_ERR_ARG, "rays_per_brick must lie in [1, 256]");
@@ -678,6 +700,7 @@ int pbr_bos_theory_map(pbr_ctx *ctx, const pbr_map_grid *grid, int32_t samples, 
     Derived d;
     int r = derive(ctx, &d);
     if (r) return r;
+    if (ctx->has_chain) return fail(ctx, PBR_ERR_STATE, "the eq. 9 map needs the singlet's magnification (an optical chain is set)");
     if ((r = check_grid(ctx, grid))) return r;
     if (samples < 1 || samples > 65536) return fail(ctx, PBR_ERR_ARG, "samples must be 1 .. 65536");
     if (!map_dev || ((uintptr_t)map_dev & 3u) != 0) return fail(ctx, PBR_ERR_ARG, "map is null or misaligned");
@@ -798,6 +821,44 @@ int pbr_set_mie(pbr_ctx *ctx, const pbr_mie *mie, void *table_dev, size_t ws_byt
                                mie->laser_dir[2] * mie->laser_dir[2]);
     for (int a = 0; a < 3; ++a) ctx->laser[a] = mie->laser_dir[a] / k;
     ctx->mie = (const double *)table_dev;
+    return PBR_OK;
+    PBR_GUARD_END
+}
+
+int pbr_set_optical_chain(pbr_ctx *ctx, const pbr_optical_chain *chain)
+{
+    if (!ctx) return PBR_ERR_ARG;
+    PBR_GUARD_BEGIN
+    if (!chain) {
+        ctx->has_chain = false;
+        ctx->scene_version++;
+        return PBR_OK;
+    }
+    if (chain->n_surfaces < 1 || chain->n_surfaces > PBR_MAX_SURFACES)
+        return fail(ctx, PBR_ERR_ARG, "chain needs 1 .. %d surfaces", PBR_MAX_SURFACES);
+    if (!std::isfinite(chain->aim_z) || !std::isfinite(chain->aim_radius) || !(chain->aim_radius > 0.0))
+        return fail(ctx, PBR_ERR_ARG, "emission target: finite plane and radius > 0");
+    for (int k = 0; k < chain->n_surfaces; ++k) {
+        const pbr_surface &f = chain->s[k];
+        if (f.type < PBR_SURF_REFRACT || f.type > PBR_SURF_LENSLETS)
+            return fail(ctx, PBR_ERR_ARG, "surface %d: unknown type %d", k, f.type);
+        if (!std::isfinite(f.z) || !std::isfinite(f.radius) || !std::isfinite(f.clear) || !(f.clear > 0.0) ||
+            !std::isfinite(f.n_after) || !std::isfinite(f.pitch))
+            return fail(ctx, PBR_ERR_ARG, "surface %d: finite z, radius, index, pitch and clear > 0", k);
+        if (f.type == PBR_SURF_LENSLETS && (!(f.pitch > 0.0) || (f.radius != 0.0 && std::fabs(f.radius) < 0.5 * f.pitch)))
+            return fail(ctx, PBR_ERR_ARG, "surface %d: lenslet pitch > 0 and |radius| >= pitch / 2", k);
+    }
+    if (ctx->device >= 0) {
+        DeviceGuard g(ctx->device);
+        if (!g.ok) return fail(ctx, PBR_ERR_HIP, "hipSetDevice failed");
+        int e = (int)hipMemcpyAsync((char *)ctx->counters + pbr::kChainOffset, chain, sizeof(pbr_optical_chain),
+                                    hipMemcpyHostToDevice, ctx->stream);
+        if (!e) e = (int)hipStreamSynchronize(ctx->stream);
+        if (e) return hip_fail(ctx, e, "optical chain copy");
+    }
+    ctx->chain = *chain;
+    ctx->has_chain = true;
+    ctx->scene_version++;
     return PBR_OK;
     PBR_GUARD_END
 }

@@ -32,6 +32,8 @@ struct pbr_ctx {
     double K = 0.0, rho_inf = 0.0;
     // optics
     bool has_optics = false;
+    bool has_chain = false;                 // a general optical chain replaces the singlet
+    pbr_optical_chain chain{};
     pbr_optics optics{};
     // sensor
     bool has_sensor = false;

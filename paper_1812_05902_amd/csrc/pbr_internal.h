@@ -96,7 +96,14 @@ struct TraceParams {
     double laser[3];
     int mie_n;
     int pad1;
+    // general optical chain (null: the singlet above)
+    const pbr_optical_chain *chain;
 };
+
+// Offset of the optical chain inside the context's 4 KiB device block (counters come first).
+constexpr size_t kChainOffset = 2048;
+static_assert(kChainOffset + sizeof(pbr_optical_chain) <= 4096, "optical chain fits the device block");
+static_assert(kChainOffset >= 8 * (CNT_QUEUE + 1), "optical chain after the counters");
 
 // Per-ray state between the three trace kernels (emit -> box -> finish), 64 bytes.
 // In the box: cell index c, cell fractions fd (FP64), direction T = Tr + dT (Tr at entry).

@@ -417,6 +417,7 @@ int pbr_surrogate_train(pbr_surrogate *s, pbr_ctx *ctx, const float *train_src_d
     if (ctx->device != s->device) return sfail(s, PBR_ERR_ARG, "context and surrogate live on different devices");
     pbr::host::Derived dv;
     if (pbr::host::derive(ctx, &dv)) return sfail(s, PBR_ERR_STATE, "context: %s", ctx->err.c_str());
+    if (ctx->has_chain) return sfail(s, PBR_ERR_STATE, "surrogate training uses the singlet (an optical chain is set)");
     if (!ctx->ray_ws) return sfail(s, PBR_ERR_STATE, "context has no trace workspace");
     if (!train_src_dev || !val_src_dev || n_train_src < 1 || n_val_src < 1 || train_rays_per_src < 1 ||
         val_rays_per_src < 1)

@@ -290,6 +290,98 @@ __device__ __forceinline__ void atomic_add_u64(unsigned long long *p, unsigned l
     __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// ------------------------------------------------------------------ general optical chain (sec. 3.3)
+
+// First intersection at s > 1e-12 along P + s u with the sphere of signed radius Rs whose vertex
+// is (cx, cy, zv), on the half of the sphere facing its vertex; Rs = 0: the plane z = zv.  Writes
+// the hit and the geometric normal (H - C) / Rs ((0, 0, -1) for a plane).
+__device__ __forceinline__ bool chain_hit(const double P[3], const double u[3], double cx, double cy, double zv,
+                                          double Rs, double H[3], double N[3])
+{
+    #pragma clang fp contract(off)
+    const double eps = 1e-12;
+    if (Rs == 0.0) {
+        if (u[2] == 0.0) return false;
+        const double s = (zv - P[2]) / u[2];
+        if (!(s > eps)) return false;
+        H[0] = P[0] + s * u[0];
+        H[1] = P[1] + s * u[1];
+        H[2] = zv;
+        N[0] = 0.0; N[1] = 0.0; N[2] = -1.0;
+        return true;
+    }
+    const double C[3] = {cx, cy, zv + Rs};
+    const double d[3] = {P[0] - C[0], P[1] - C[1], P[2] - C[2]};
+    const double b = d[0] * u[0] + d[1] * u[1] + d[2] * u[2];
+    const double c = d[0] * d[0] + d[1] * d[1] + d[2] * d[2] - Rs * Rs;
+    const double disc = b * b - c;
+    if (disc < 0.0) return false;
+    const double sq = sqrt(disc);
+    const double q = -(b + (b >= 0.0 ? sq : -sq));  // roots q and c / q without cancellation
+    const double ra = q, rb = q != 0.0 ? c / q : q;
+    const double r1 = fmin(ra, rb), r2 = fmax(ra, rb);
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const double s = k ? r2 : r1;
+        if (!(s > eps)) continue;
+        const double h[3] = {P[0] + s * u[0], P[1] + s * u[1], P[2] + s * u[2]};
+        if ((h[2] - C[2]) * Rs > 0.0) continue;  // the far half of the sphere
+#pragma unroll
+        for (int a = 0; a < 3; ++a) { H[a] = h[a]; N[a] = (h[a] - C[a]) / Rs; }
+        return true;
+    }
+    return false;
+}
+
+// The ray from R along unit u through the chain's surfaces in order, then onto the sensor plane
+// (refraction by eq. 7 with total internal reflection, reflection about the local normal, stops
+// and rims blocking; a lenslet array refracts at the cap of the lenslet whose cell the ray meets).
+__device__ int chain_to_sensor(const TraceParams &P, const double R[3], const double u0[3], double *xpx,
+                               double *ypx)
+{
+    #pragma clang fp contract(off)
+    const pbr_optical_chain &ch = *P.chain;
+    double X[3] = {R[0], R[1], R[2]}, u[3] = {u0[0], u0[1], u0[2]};
+    double n_cur = P.n_inf;
+    for (int k = 0; k < ch.n_surfaces; ++k) {
+        const pbr_surface f = ch.s[k];
+        const bool stop = f.type == PBR_SURF_APERTURE;
+        const int blocked = stop ? PBR_RAY_BLOCKED_APERTURE : PBR_RAY_BLOCKED_LENS;
+        double cx = 0.0, cy = 0.0, H[3], N[3];
+        if (f.type == PBR_SURF_LENSLETS) {  // the lenslet whose square cell the ray enters
+            if (!chain_hit(X, u, 0.0, 0.0, f.z, 0.0, H, N)) return PBR_RAY_BLOCKED_LENS;
+            cx = f.pitch * floor(H[0] / f.pitch + 0.5);
+            cy = f.pitch * floor(H[1] / f.pitch + 0.5);
+        }
+        if (!chain_hit(X, u, cx, cy, f.z, stop ? 0.0 : f.radius, H, N)) return blocked;
+        if (H[0] * H[0] + H[1] * H[1] > f.clear * f.clear) return blocked;
+        if (f.type == PBR_SURF_LENSLETS && (fabs(H[0] - cx) > 0.5 * f.pitch || fabs(H[1] - cy) > 0.5 * f.pitch))
+            return PBR_RAY_BLOCKED_LENS;
+        if (u[0] * N[0] + u[1] * N[1] + u[2] * N[2] > 0.0) { N[0] = -N[0]; N[1] = -N[1]; N[2] = -N[2]; }
+        if (f.type == PBR_SURF_MIRROR) {
+            const double dn = u[0] * N[0] + u[1] * N[1] + u[2] * N[2];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) u[a] = u[a] - 2.0 * dn * N[a];
+        } else if (!stop) {
+            const double n_next = f.n_after > 0.0 ? f.n_after : P.n_inf;
+            double v[3];
+            if (!snell(u, N, n_cur, n_next, v)) return PBR_RAY_TIR;
+            const double vl = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) u[a] = v[a] / vl;
+            n_cur = n_next;
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a) X[a] = H[a];
+    }
+    if (u[2] == 0.0) return PBR_RAY_MISSED;
+    const double s = (P.z_sensor - X[2]) / u[2];
+    if (!(s > 0.0)) return PBR_RAY_MISSED;
+    *xpx = (X[0] + s * u[0]) / P.pitch + 0.5 * (double)P.W;
+    *ypx = (X[1] + s * u[1]) / P.pitch + 0.5 * (double)P.H;
+    return PBR_RAY_DEPOSITED;
+}
+
 // ------------------------------------------------------------------ kernel 1: emission, entry
 
 // sec. 3.1: ray j of source s aims at the aperture point (a sqrt(u1) cos 2 pi u2,
@@ -850,8 +942,10 @@ struct FinishShared {
 // take part (barriers inside).
 // RFX: footprint radius fixed at compile time (1..8), or 0 to switch on P.rfp per call (batches,
 // whose images differ).  A fixed radius keeps the spot arrays, and so the register count, small.
-// MIE: the Mie weighting is compiled in only where it is used (it costs ~50 registers).
-template <int TILE, int RFX = 0, bool MIE = false>
+// FEAT: optional steps compiled in only where used (each costs registers): bit 0 the Mie weighting,
+// bit 1 a general optical chain in place of the singlet.
+enum : int { FEAT_MIE = 1, FEAT_CHAIN = 2 };
+template <int TILE, int RFX = 0, int FEAT = 0>
 __device__ __forceinline__ void finish_block(const TraceParams &P, const RayState *__restrict__ st,
                                              int64_t first, int64_t base, int64_t n, FinishShared<TILE> &sh)
 {
@@ -881,7 +975,9 @@ __device__ __forceinline__ void finish_block(const TraceParams &P, const RayStat
 #pragma unroll
         for (int a = 0; a < 3; ++a) dir[a] = T[a] * it;
         if (r.info & RS_LIMITED) status = PBR_RAY_STEP_LIMIT;
-        if (status == PBR_RAY_DEPOSITED) status = optics_to_sensor(P, Rw, dir, &xpx, &ypx);
+        if (status == PBR_RAY_DEPOSITED)
+            status = ((FEAT & FEAT_CHAIN) && P.chain) ? chain_to_sensor(P, Rw, dir, &xpx, &ypx)
+                                                      : optics_to_sensor(P, Rw, dir, &xpx, &ypx);
         if (status == PBR_RAY_DEPOSITED &&
             !(xpx >= 0.0 && ypx >= 0.0 && xpx < (double)P.W && ypx < (double)P.H))
             status = PBR_RAY_OFF_SENSOR;
@@ -899,7 +995,7 @@ __device__ __forceinline__ void finish_block(const TraceParams &P, const RayStat
         const int64_t rid = first + i;
         const float4 sv = P.src[rid / P.rays_per_src];
         double w = sv.w > 0.0f ? (sv.w < 1.0f ? (double)sv.w : 1.0) : 0.0;  // weights in [0, 1]
-        if (MIE && P.mie) {  // the ray's Mie factor, from its direction at the source
+        if ((FEAT & FEAT_MIE) && P.mie) {  // the ray's Mie factor, from its direction at the source
             double S0[3], u0[3];
             initial_direction(P, rid, S0, u0);
             w *= mie_weight(P, u0);
@@ -959,14 +1055,14 @@ __device__ __forceinline__ void flush_counters(const TraceParams &P, FinishShare
         atomic_add_u64(P.counters + threadIdx.x, sh.cnt[threadIdx.x]);
 }
 
-template <int TILE, int RF, bool MIE = false>
+template <int TILE, int RF, int FEAT = 0>
 __global__ void __launch_bounds__(256) k_finish(TraceParams P, const RayState *__restrict__ st,
                                                 int64_t first, int64_t n)
 {
     __shared__ FinishShared<TILE> sh;
     if (threadIdx.x < CNT_SLOTS) sh.cnt[threadIdx.x] = 0ull;
     for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += (int64_t)gridDim.x * blockDim.x)
-        finish_block<TILE, RF, MIE>(P, st, first, base, n, sh);
+        finish_block<TILE, RF, FEAT>(P, st, first, base, n, sh);
     flush_counters<TILE>(P, sh);
 }
 
@@ -1428,11 +1524,21 @@ int launch_trace_chunk(const TraceParams &p, RayState *st, int64_t first, int64_
     if (!deposit) return 0;
     unsigned fblocks = blocks < 4096u ? blocks : 4096u;
     const RayState *cst = st;
-    if (p.mie) switch (p.rfp) {  // spot radii of 1-3 pixels cover focused PIV particles
-        case 1: hipLaunchKernelGGL((k_finish<kTile, 1, true>), dim3(fblocks), dim3(256), 0, stream, p, cst, first, n); break;
-        case 2: hipLaunchKernelGGL((k_finish<kTile, 2, true>), dim3(fblocks), dim3(256), 0, stream, p, cst, first, n); break;
-        case 3: hipLaunchKernelGGL((k_finish<kTile, 3, true>), dim3(fblocks), dim3(256), 0, stream, p, cst, first, n); break;
-        default: hipLaunchKernelGGL((k_finish<kTile, 0, true>), dim3(fblocks), dim3(256), 0, stream, p, cst, first, n); break;
+    const int feat = (p.mie ? FEAT_MIE : 0) | (p.chain ? FEAT_CHAIN : 0);
+    if (feat) {
+        // spot radii of 1-3 pixels cover focused particles; wider spots take the run-time radius
+        const int rf = p.rfp <= 3 ? p.rfp : 0;
+#define PBR_FINISH_FEAT(F)                                                                                          \
+        switch (rf) {                                                                                               \
+            case 1: hipLaunchKernelGGL((k_finish<kTile, 1, F>), dim3(fblocks), dim3(256), 0, stream, p, cst, first, n); break; \
+            case 2: hipLaunchKernelGGL((k_finish<kTile, 2, F>), dim3(fblocks), dim3(256), 0, stream, p, cst, first, n); break; \
+            case 3: hipLaunchKernelGGL((k_finish<kTile, 3, F>), dim3(fblocks), dim3(256), 0, stream, p, cst, first, n); break; \
+            default: hipLaunchKernelGGL((k_finish<kTile, 0, F>), dim3(fblocks), dim3(256), 0, stream, p, cst, first, n); break; \
+        }
+        if (feat == FEAT_MIE) { PBR_FINISH_FEAT(FEAT_MIE) }
+        else if (feat == FEAT_CHAIN) { PBR_FINISH_FEAT(FEAT_CHAIN) }
+        else { PBR_FINISH_FEAT(FEAT_MIE | FEAT_CHAIN) }
+#undef PBR_FINISH_FEAT
     }
     else switch (p.rfp) {
         case 1: hipLaunchKernelGGL((k_finish<kTile, 1>), dim3(fblocks), dim3(256), 0, stream, p, cst, first, n); break;

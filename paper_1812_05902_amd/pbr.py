@@ -27,6 +27,8 @@ PBR_CLEAR_FIRST, PBR_RECORD_EXITS, PBR_PREC_FP64_ALL, PBR_PREC_SHOCK_FP64, PBR_S
 PBR_LANE_REFILL = 32
 PBR_SOURCE_SUMS = 64
 PBR_MIE = 128
+PBR_MAX_SURFACES = 16
+PBR_SURF_REFRACT, PBR_SURF_MIRROR, PBR_SURF_APERTURE, PBR_SURF_LENSLETS = 0, 1, 2, 3
 PBR_MIE_TABLE_SIZE = 2049
 PBR_SURR_PARAMS = 200710
 PBR_FMT_RAW_U64, PBR_FMT_F32, PBR_FMT_U16 = 0, 1, 2
@@ -45,7 +47,7 @@ EXPORTED = ["pbr_create", "pbr_destroy", "pbr_last_error", "pbr_set_stream",
             "pbr_surrogate_tile_map", "pbr_set_surrogate", "pbr_probe_u64_atomics",
             "pbr_set_source_sums", "pbr_dot_map_workspace_bytes", "pbr_dot_displacement_map",
             "pbr_bos_theory_map", "pbr_displace_sources", "pbr_mie_table", "pbr_mie_workspace_bytes",
-            "pbr_set_mie"]
+            "pbr_set_mie", "pbr_set_optical_chain"]
 
 
 class PbrError(RuntimeError):
@@ -88,6 +90,16 @@ class pbr_precision_report(C.Structure):
 
 class pbr_source_sum(C.Structure):
     _fields_ = [("sum_x", C.c_int64), ("sum_y", C.c_int64), ("hits", C.c_uint64), ("reserved", C.c_uint64)]
+
+
+class pbr_surface(C.Structure):
+    _fields_ = [("type", C.c_int32), ("reserved", C.c_int32), ("z", C.c_double), ("radius", C.c_double),
+                ("clear", C.c_double), ("n_after", C.c_double), ("pitch", C.c_double)]
+
+
+class pbr_optical_chain(C.Structure):
+    _fields_ = [("n_surfaces", C.c_int32), ("reserved", C.c_int32), ("aim_z", C.c_double),
+                ("aim_radius", C.c_double), ("s", pbr_surface * PBR_MAX_SURFACES)]
 
 
 class pbr_mie(C.Structure):
@@ -195,6 +207,7 @@ def load(path: str = LIB_PATH):
         "pbr_mie_table": (I, [C.POINTER(pbr_mie), D, P, C.c_int32]),
         "pbr_mie_workspace_bytes": (C.c_size_t, []),
         "pbr_set_mie": (I, [P, C.POINTER(pbr_mie), P, C.c_size_t]),
+        "pbr_set_optical_chain": (I, [P, C.POINTER(pbr_optical_chain)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(l, name)
@@ -333,6 +346,20 @@ def pbr_displace_sources(ctx, src_in, src_out, vel, origin, spacing, dt, substep
     n_src = 0 if src_in is None else int(src_in.shape[0])
     _check(ctx, load().pbr_displace_sources(ctx, _dptr(src_in), _dptr(src_out), n_src, _dptr(vel), nx, ny, nz,
                                             o, s, float(dt), int(substeps)))
+
+
+def optical_chain(surfaces, aim_z, aim_radius) -> pbr_optical_chain:
+    """surfaces: list of (type, z, radius, clear, n_after, pitch)."""
+    ch = pbr_optical_chain()
+    ch.n_surfaces = len(surfaces)
+    ch.aim_z, ch.aim_radius = float(aim_z), float(aim_radius)
+    for k, (t, z, r, c, n, p) in enumerate(surfaces):
+        ch.s[k] = pbr_surface(int(t), 0, float(z), float(r), float(c), float(n), float(p))
+    return ch
+
+
+def pbr_set_optical_chain(ctx, chain):
+    _check(ctx, load().pbr_set_optical_chain(ctx, None if chain is None else C.byref(chain)))
 
 
 def mie_params(diameter, m, wavelength, laser_dir) -> pbr_mie:
@@ -483,6 +510,11 @@ class Renderer:
         out = self.torch.empty(g.ny, g.nx, 2, dtype=self.torch.float32, device=self.device)
         pbr_bos_theory_map(self.ctx, g, samples, out)
         return out
+
+    def set_optical_chain(self, surfaces, aim_z=0.0, aim_radius=0.0):
+        """General optical chain (sec. 3.3) in place of the singlet; surfaces = list of
+        (type, z, radius, clear, n_after, pitch); None restores the singlet."""
+        pbr_set_optical_chain(self.ctx, None if surfaces is None else optical_chain(surfaces, aim_z, aim_radius))
 
     def set_mie(self, diameter, m, wavelength, laser_dir):
         """Mie weighting of later traces with PBR_MIE (sec. 3.1): particle diameter (m), relative

@@ -419,3 +419,47 @@ def test_mie_entry_points_validate(lib):
         assert "Mie" in _err(lib, h)
     finally:
         lib.pbr_destroy(h)
+
+
+def test_optical_chain_validates(lib):
+    R = pbr.PBR_SURF_REFRACT
+    h = _host_ctx(lib)
+    try:
+        def setc(surfs, aim_z=0.5, aim_r=0.003):
+            ch = pbr.optical_chain(surfs, aim_z, aim_r)
+            return lib.pbr_set_optical_chain(h, C.byref(ch))
+        assert lib.pbr_set_optical_chain(None, None) == pbr.PBR_ERR_ARG
+        assert setc([]) == pbr.PBR_ERR_ARG
+        bad = pbr.optical_chain([(R, 0.5, 0.0, 0.01, 1.5, 0.0)], 0.5, 0.003)
+        bad.n_surfaces = 17
+        assert lib.pbr_set_optical_chain(h, C.byref(bad)) == pbr.PBR_ERR_ARG
+        assert setc([(7, 0.5, 0.0, 0.01, 1.5, 0.0)]) == pbr.PBR_ERR_ARG
+        assert setc([(R, 0.5, 0.0, 0.0, 1.5, 0.0)]) == pbr.PBR_ERR_ARG
+        assert setc([(R, math.nan, 0.0, 0.01, 1.5, 0.0)]) == pbr.PBR_ERR_ARG
+        assert setc([(pbr.PBR_SURF_LENSLETS, 0.5, 1e-4, 0.01, 1.5, 0.0)]) == pbr.PBR_ERR_ARG
+        assert setc([(pbr.PBR_SURF_LENSLETS, 0.5, 4e-5, 0.01, 1.5, 1e-4)]) == pbr.PBR_ERR_ARG
+        assert setc([(R, 0.5, 0.0, 0.01, 1.5, 0.0)], aim_r=0.0) == pbr.PBR_ERR_ARG
+        assert setc([(R, 0.5, 0.05, 0.01, 1.5, 0.0), (R, 0.505, -0.05, 0.01, 0.0, 0.0)]) == pbr.PBR_OK
+        # a chain needs an explicit sensor plane and spot
+        assert _set_field(lib, h) == pbr.PBR_OK
+        assert lib.pbr_set_sensor(h, C.byref(_sensor()), FAKE) == pbr.PBR_OK
+        d = pbr.pbr_derived()
+        assert lib.pbr_get_derived(h, C.byref(d)) == pbr.PBR_ERR_STATE
+        assert lib.pbr_set_sensor(h, C.byref(_sensor(z_sensor=0.6, sigma_px=0.5)), FAKE) == pbr.PBR_OK
+        assert lib.pbr_get_derived(h, C.byref(d)) == pbr.PBR_OK
+        assert d.footprint_r == 2 and d.z_sensor == 0.6 and math.isnan(d.magnification)
+        assert d.aperture_radius == 0.003
+        # singlet-only calls refuse the chain
+        assert lib.pbr_set_trace_workspace(h, FAKE, 1 << 20) == pbr.PBR_OK
+        rep = pbr.pbr_precision_report()
+        assert lib.pbr_calibrate_precision(h, 1e-3, 0.1, 8, 1, 1e-4, C.byref(rep)) == pbr.PBR_ERR_STATE
+        g = pbr.map_grid(-0.01, -0.01, 1e-3, 1e-3, 4, 4, 0.0)
+        assert lib.pbr_bos_theory_map(h, C.byref(g), 16, FAKE) == pbr.PBR_ERR_STATE
+        # emission target before the box
+        assert setc([(R, 0.5, 0.0, 0.01, 1.5, 0.0)], aim_z=0.12) == pbr.PBR_OK
+        assert lib.pbr_emit_and_trace(h, FAKE, 1, 1, 0, 1e-4, 0, None) == pbr.PBR_ERR_ARG
+        # back to the singlet
+        assert lib.pbr_set_optical_chain(h, None) == pbr.PBR_OK
+        assert lib.pbr_get_derived(h, C.byref(d)) == pbr.PBR_ERR_STATE  # no pbr_set_optics yet
+    finally:
+        lib.pbr_destroy(h)
