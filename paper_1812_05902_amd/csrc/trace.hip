@@ -42,7 +42,11 @@ struct CellCache {
 // Trilinear interpolation of (n - 1, grad n) at the point (cell c, fraction f); the fraction may
 // lie outside [0, 1) (stage points of eq. 5), in which case the point is moved into the cell that
 // holds it and then onto the box.  Returns n, writes D = n grad n (eq. 6).
-template <typename F, bool AT_STATE = false>
+// INSIDE: the caller has shown that the point lies inside the box (see trace_step), so the edge
+// extension is left out; the cell index is still clamped to the grid, which keeps every gather in
+// bounds whatever the values (a state on the upper face, cell n - 1 at fraction 0, is read as
+// fraction 1 of cell n - 2).
+template <typename F, bool AT_STATE = false, bool INSIDE = false>
 __device__ __forceinline__ F sample_D(const TraceParams &P, CellCache &cc, const int c[3],
                                       const F f[3], F D[3])
 {
@@ -65,8 +69,12 @@ __device__ __forceinline__ F sample_D(const TraceParams &P, CellCache &cc, const
             t = fa - o;
         }
         const int i = min(max(i0, 0), nmax[a]);
-        t = i0 < 0 ? (F)0 : t;
-        t = i0 > nmax[a] ? (F)1 : t;
+        if (INSIDE) {
+            if (AT_STATE) t = t + (F)(i0 - i);
+        } else {
+            t = i0 < 0 ? (F)0 : t;
+            t = i0 > nmax[a] ? (F)1 : t;
+        }
         ic[a] = i;
         w[a] = t;
     }
@@ -105,7 +113,8 @@ __device__ __forceinline__ F sample_D(const TraceParams &P, CellCache &cc, const
 // cell units: g[a] = h / spacing[a].  The cell fraction fd is accumulated in FP64: its increment
 // is nearly the same every step, so FP32 rounding of the running sum would err the same way
 // every step and grow linearly with the step count.  Stage points are formed in F.
-template <typename F, bool FULL>
+// INSIDE: every point of the step is known to lie inside the box (full steps only).
+template <typename F, bool FULL, bool INSIDE = false>
 __device__ __forceinline__ void rkn_step(const TraceParams &P, CellCache &cc, int c[3], double fd[3],
                                          const F Tr[3], F dT[3], const F g[3], F hstep, F lam)
 {
@@ -113,13 +122,13 @@ __device__ __forceinline__ void rkn_step(const TraceParams &P, CellCache &cc, in
     F f[3], gg[3], T[3], A[3], B[3], C[3], q[3], D[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) { f[a] = (F)fd[a]; gg[a] = FULL ? g[a] : lam * g[a]; T[a] = Tr[a] + dT[a]; }
-    sample_D<F, true>(P, cc, c, f, D);
+    sample_D<F, true, INSIDE>(P, cc, c, f, D);
 #pragma unroll
     for (int a = 0; a < 3; ++a) { A[a] = hh * D[a]; q[a] = f[a] + gg[a] * ((F)0.5 * T[a] + (F)0.125 * A[a]); }
-    sample_D<F>(P, cc, c, q, D);
+    sample_D<F, false, INSIDE>(P, cc, c, q, D);
 #pragma unroll
     for (int a = 0; a < 3; ++a) { B[a] = hh * D[a]; q[a] = f[a] + gg[a] * (T[a] + (F)0.5 * B[a]); }
-    sample_D<F>(P, cc, c, q, D);
+    sample_D<F, false, INSIDE>(P, cc, c, q, D);
     const F sixth = (F)1 / (F)6;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -147,59 +156,66 @@ enum : int { STEP_GO = 0, STEP_EXIT = 1, STEP_LIMIT = 2 };
 // a face the ray moves towards) the partial step of fraction lam and, if the ray still heads out,
 // the straight move onto that face.  Returns STEP_EXIT when the ray left the box, STEP_LIMIT when
 // it ran out of steps, STEP_GO otherwise.
+// A full step whose straight line ends more than kFaceMargin cells inside every face is taken
+// without the edge extension: its stage points stay inside the box (they leave the straight line
+// by h^2 |D| / 2 in the step parameter, about 1e-7 cells at the fields here).  Every other step goes
+// through the exit rule and the edge-extended sampling (a full step there, at fraction 1, gives
+// the same bits as the inside one wherever both apply).
+constexpr float kFaceMargin = 1.0e-3f;
+
 template <typename F>
 __device__ __forceinline__ int trace_step(const TraceParams &P, CellCache &cc, int c[3], double fd[3], const F Tr[3],
                                           F dT[3], const F g[3], F hstep, const int last[3], int &steps)
 {
-    // cheap test first: does the straight line of a full step reach a face?  (distances in
-    // cell units against the per-step displacement; no division)
-    // (bitwise, not short-circuit: one branch for the whole test instead of one per clause)
-    bool near = false;
+    // cheap test first: does the straight line of a full step end inside the box with margin?
+    // (bitwise, not short-circuit: one branch for the whole test; a NaN counts as outside)
+    bool inside = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const F e = ((F)c[a] + (F)fd[a]) + g[a] * (Tr[a] + dT[a]);
+        inside = inside & (e > (F)kFaceMargin) & (e < (F)last[a] - (F)kFaceMargin);
+    }
+    if (inside) {
+        rkn_step<F, true, true>(P, cc, c, fd, Tr, dT, g, hstep, (F)1);
+        return ++steps > P.max_steps ? STEP_LIMIT : STEP_GO;
+    }
+    F lam = (F)3.0e38;
+    int ax = -1;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const F v = g[a] * (Tr[a] + dT[a]);
-        const F fa = (F)fd[a];
-        const bool up = (v > (F)0) & ((F)(last[a] - c[a]) - fa <= v);
-        const bool down = (v < (F)0) & ((F)(-c[a]) - fa >= v);
-        near = near | up | down;
+        F l = (F)3.0e38;
+        if (v > (F)0) l = (F)((double)(last[a] - c[a]) - fd[a]) / v;
+        else if (v < (F)0) l = (F)((double)(-c[a]) - fd[a]) / v;
+        if (l < lam) { lam = l; ax = a; }
     }
-    if (near) {
-        F lam = (F)3.0e38;
-        int ax = -1;
+    const bool hit = ax >= 0 && lam <= (F)1;
+    const bool up = hit && (pick3<F>(Tr, ax) + pick3<F>(dT, ax)) > (F)0;
+    // one call site for both the partial step and the edge-extended full step
+    if (!hit || lam > (F)0) {
+        rkn_step<F, false>(P, cc, c, fd, Tr, dT, g, hstep, hit ? lam : (F)1);
+        ++steps;
+    }
+    if (!hit) return steps > P.max_steps ? STEP_LIMIT : STEP_GO;
+    const F Tn[3] = {Tr[0] + dT[0], Tr[1] + dT[1], Tr[2] + dT[2]};
+    const F Ta = pick3<F>(Tn, ax);
+    if (up ? (Ta > (F)0) : (Ta < (F)0)) {
+        const int la = pick3<int>(last, ax);
+        const double target = up ? (double)la : 0.0;
+        const double l2 = (target - ((double)pick3<int>(c, ax) + pick3<double>(fd, ax))) /
+                          ((double)pick3<F>(g, ax) * (double)Ta);
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            const F v = g[a] * (Tr[a] + dT[a]);
-            F l = (F)3.0e38;
-            if (v > (F)0) l = (F)((double)(last[a] - c[a]) - fd[a]) / v;
-            else if (v < (F)0) l = (F)((double)(-c[a]) - fd[a]) / v;
-            if (l < lam) { lam = l; ax = a; }
-        }
-        if (ax >= 0 && lam <= (F)1) {
-            const bool up = (pick3<F>(Tr, ax) + pick3<F>(dT, ax)) > (F)0;
-            if (lam > (F)0) { rkn_step<F, false>(P, cc, c, fd, Tr, dT, g, hstep, lam); ++steps; }
-            const F Tn[3] = {Tr[0] + dT[0], Tr[1] + dT[1], Tr[2] + dT[2]};
-            const F Ta = pick3<F>(Tn, ax);
-            if (up ? (Ta > (F)0) : (Ta < (F)0)) {
-                const int la = pick3<int>(last, ax);
-                const double target = up ? (double)la : 0.0;
-                const double l2 = (target - ((double)pick3<int>(c, ax) + pick3<double>(fd, ax))) /
-                                  ((double)pick3<F>(g, ax) * (double)Ta);
-#pragma unroll
-                for (int b = 0; b < 3; ++b) {
-                    if (b == ax) {
-                        c[b] = up ? la - 1 : 0;
-                        fd[b] = up ? 1.0 : 0.0;
-                    } else {
-                        fd[b] += l2 * (double)g[b] * (double)Tn[b];
-                    }
-                }
-                return STEP_EXIT;
+        for (int b = 0; b < 3; ++b) {
+            if (b == ax) {
+                c[b] = up ? la - 1 : 0;
+                fd[b] = up ? 1.0 : 0.0;
+            } else {
+                fd[b] += l2 * (double)g[b] * (double)Tn[b];
             }
-            return steps > P.max_steps ? STEP_LIMIT : STEP_GO;  // turned back within the last step
         }
+        return STEP_EXIT;
     }
-    rkn_step<F, true>(P, cc, c, fd, Tr, dT, g, hstep, (F)1);
-    return ++steps > P.max_steps ? STEP_LIMIT : STEP_GO;
+    return steps > P.max_steps ? STEP_LIMIT : STEP_GO;  // turned back within the last step
 }
 
 // Integrate from the cell-local state until the ray leaves the box (see trace_step).  Returns the
