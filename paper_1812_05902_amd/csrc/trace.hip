@@ -31,6 +31,15 @@ template <typename F> __device__ __forceinline__ F ffloor(F x);
 template <> __device__ __forceinline__ float ffloor<float>(float x) { return floorf(x); }
 template <> __device__ __forceinline__ double ffloor<double>(double x) { return floor(x); }
 
+// x clamped to [0, hi] in one instruction (for a bound that is not a constant the compiler emits a
+// max and a min); hi is uniform across the wave.
+__device__ __forceinline__ int clamp_index(int x, int hi)
+{
+    int r;
+    asm("v_med3_i32 %0, %1, 0, %2" : "=v"(r) : "v"(x), "s"(hi));
+    return r;
+}
+
 // The coefficients of the cell the ray is in, held in registers: a stage point only gathers
 // from memory when it lies in another cell (about once per cell crossing, since the three stage
 // points of a step run ahead of the ray).
@@ -42,10 +51,9 @@ struct CellCache {
 // Trilinear interpolation of (n - 1, grad n) at the point (cell c, fraction f); the fraction may
 // lie outside [0, 1) (stage points of eq. 5), in which case the point is moved into the cell that
 // holds it and then onto the box.  Returns n, writes D = n grad n (eq. 6).
-// INSIDE: the caller has shown that the point lies inside the box (see trace_step), so the edge
-// extension is left out; the cell index is still clamped to the grid, which keeps every gather in
-// bounds whatever the values (a state on the upper face, cell n - 1 at fraction 0, is read as
-// fraction 1 of cell n - 2).
+// INSIDE: the caller has shown that the point lies inside the box and that the ray's own cell index
+// is a cell of the grid (see trace_step), so the edge extension is left out; the cell index is still
+// clamped to the grid, which keeps every gather in bounds whatever the values.
 template <typename F, bool AT_STATE = false, bool INSIDE = false>
 __device__ __forceinline__ F sample_D(const TraceParams &P, CellCache &cc, const int c[3],
                                       const F f[3], F D[3])
@@ -68,10 +76,8 @@ __device__ __forceinline__ F sample_D(const TraceParams &P, CellCache &cc, const
             i0 = c[a] + (int)o;
             t = fa - o;
         }
-        const int i = min(max(i0, 0), nmax[a]);
-        if (INSIDE) {
-            if (AT_STATE) t = t + (F)(i0 - i);
-        } else {
+        const int i = INSIDE ? clamp_index(i0, nmax[a]) : min(max(i0, 0), nmax[a]);
+        if (!INSIDE) {
             t = i0 < 0 ? (F)0 : t;
             t = i0 > nmax[a] ? (F)1 : t;
         }
@@ -195,6 +201,14 @@ __device__ __forceinline__ int trace_step(const TraceParams &P, CellCache &cc, i
     if (!hit || lam > (F)0) {
         rkn_step<F, false>(P, cc, c, fd, Tr, dT, g, hstep, hit ? lam : (F)1);
         ++steps;
+        // a step ending on or a hair beyond the upper face leaves cell n - 1 at fraction ~0: keep the
+        // index a cell of the grid (same position), as the inside steps assume
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const int i = min(max(c[a], 0), last[a] - 1);
+            fd[a] += (double)(c[a] - i);
+            c[a] = i;
+        }
     }
     if (!hit) return steps > P.max_steps ? STEP_LIMIT : STEP_GO;
     const F Tn[3] = {Tr[0] + dT[0], Tr[1] + dT[1], Tr[2] + dT[2]};
