@@ -104,6 +104,8 @@ def main():
                          "per-dot displacement map, eq. 9 map); piv_pair_512: both frames of a Tomo-PIV pair "
                          "(particles moved by a vortex between them)")
     ap.add_argument("--epochs", type=int, default=8, help="surrogate256: training epochs")
+    ap.add_argument("--rays-per-chunk", type=int, default=1 << 24,
+                    help="turbulence_bos_128: rays per trace chunk (64 bytes of ray state each)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy a 1 GiB device buffer 4 times (calibrates HBM byte counters)")
     ap.add_argument("--atomic-probe", action="store_true",
@@ -147,7 +149,7 @@ def main():
     scene = inputs.turbulence_bos()
     rho = inputs.density(scene)
     src = inputs.sources(scene)
-    r = pbr.Renderer.from_scene(scene, rho=rho)
+    r = pbr.Renderer.from_scene(scene, rho=rho, rays_per_chunk=args.rays_per_chunk)
     src_dev = torch.as_tensor(src, device=r.device).contiguous()
     torch.cuda.synchronize()
 
@@ -191,6 +193,7 @@ def main():
         "config": {"workload": "turbulence_bos_128", "grid": "128^3", "n_src": scene.n_src,
                    "rays_per_src": scene.rays_per_src, "rays_per_image": n_rays,
                    "sensor": f"{scene.width}x{scene.height}", "ds_m": scene.ds,
+                   "rays_per_chunk": args.rays_per_chunk,
                    "mean_rkn_steps_per_ray": steps_total / args.steps / n_rays},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
