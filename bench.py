@@ -104,6 +104,9 @@ def main():
                          "per-dot displacement map, eq. 9 map); piv_pair_512: both frames of a Tomo-PIV pair "
                          "(particles moved by a vortex between them)")
     ap.add_argument("--epochs", type=int, default=8, help="surrogate256: training epochs")
+    ap.add_argument("--field-layout", choices=["auto", "cells", "nodes"], default="auto",
+                    help="field stored per cell (128 B) or per node (16 B); auto takes the faster measured "
+                         "one per workload")
     ap.add_argument("--rays-per-chunk", type=int, default=1 << 24,
                     help="turbulence_bos_128: rays per trace chunk (64 bytes of ray state each)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -149,7 +152,8 @@ def main():
     scene = inputs.turbulence_bos()
     rho = inputs.density(scene)
     src = inputs.sources(scene)
-    r = pbr.Renderer.from_scene(scene, rho=rho, rays_per_chunk=args.rays_per_chunk)
+    r = pbr.Renderer.from_scene(scene, rho=rho, rays_per_chunk=args.rays_per_chunk,
+                                nodes=args.field_layout == "nodes")
     src_dev = torch.as_tensor(src, device=r.device).contiguous()
     torch.cuda.synchronize()
 
@@ -194,6 +198,7 @@ def main():
                    "rays_per_src": scene.rays_per_src, "rays_per_image": n_rays,
                    "sensor": f"{scene.width}x{scene.height}", "ds_m": scene.ds,
                    "rays_per_chunk": args.rays_per_chunk,
+                   "field_layout": "nodes" if args.field_layout == "nodes" else "cells",
                    "mean_rkn_steps_per_ray": steps_total / args.steps / n_rays},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
@@ -339,8 +344,9 @@ def bench_bos_fig4(args):
     sc0 = sc.replace(field="uniform", field_params=dict(rho0=sc.rho_inf))
     grid = inputs.map_grid(sc)
     # one trace chunk holds a whole render (no ragged second launch)
-    r1 = pbr.Renderer.from_scene(sc, rays_per_chunk=1 << 23)
-    r0 = pbr.Renderer.from_scene(sc0, rays_per_chunk=1 << 23)
+    nodes = args.field_layout != "cells"
+    r1 = pbr.Renderer.from_scene(sc, rays_per_chunk=1 << 23, nodes=nodes)
+    r0 = pbr.Renderer.from_scene(sc0, rays_per_chunk=1 << 23, nodes=nodes)
     src = torch.as_tensor(inputs.sources(sc), device=r1.device).contiguous()
     s1 = r1.set_source_sums(sc.n_src)
     s0 = r0.set_source_sums(sc.n_src)
@@ -382,7 +388,8 @@ def bench_bos_fig4(args):
         "config": {"workload": "bos_fig4", "grid": f"{sc.nx}x{sc.ny}x{sc.nz} z-stacked slice",
                    "n_src": sc.n_src, "rays_per_src": sc.rays_per_src, "renders_per_step": 2,
                    "rays_per_step": n_rays, "sensor": f"{sc.width}x{sc.height}", "ds_m": sc.ds,
-                   "map": f"{grid[4]}x{grid[5]} nodes, {grid[2] * 1e3:.3f} mm"},
+                   "map": f"{grid[4]}x{grid[5]} nodes, {grid[2] * 1e3:.3f} mm",
+                   "field_layout": "nodes" if nodes else "cells"},
         "fig4": {"corr_simulated_vs_eq9": float(np.corrcoef(x, y)[0, 1]),
                  "rms_simulated_over_eq9": float(np.sqrt((x * x).mean() / (y * y).mean())),
                  "eq9_max_px": float(np.abs(y).max()), "nodes_filled": int(f.sum())},
@@ -405,7 +412,8 @@ def bench_piv_pair(args):
     sc = inputs.tomo_piv_shock()
     t0 = time.perf_counter()
     rho = inputs.density(sc)
-    r = pbr.Renderer.from_scene(sc, rho=rho)
+    nodes = args.field_layout != "cells"
+    r = pbr.Renderer.from_scene(sc, rho=rho, nodes=nodes)
     del rho
     src = torch.as_tensor(inputs.sources(sc), device=r.device).contiguous()
     vel, org, sp, dt = inputs.piv_pair_flow()
@@ -446,7 +454,8 @@ def bench_piv_pair(args):
         "config": {"workload": "piv_pair_512", "grid": "512^3", "n_src": sc.n_src, "rays_per_src": sc.rays_per_src,
                    "frames_per_step": 2, "rays_per_step": n_rays, "sensor": f"{sc.width}x{sc.height} u16",
                    "flow": "Lamb-Oseen vortex (0.05 m^2/s, core 1 cm) in a 0.2 m/s stream, 65^3 grid",
-                   "frame_interval_s": dt, "max_particle_move_mm": moved * 1e3, "setup_s": setup_s},
+                   "frame_interval_s": dt, "max_particle_move_mm": moved * 1e3, "setup_s": setup_s,
+                   "field_layout": "nodes" if nodes else "cells"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None, "kernel": "k_box32",
                      "kernel_ms_per_launch": box_ms / launches, "flops_per_rkn_step": FLOPS_PER_STEP,

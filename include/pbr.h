@@ -196,6 +196,20 @@ int pbr_set_density_field(pbr_ctx *ctx, const float *rho_dev, int nx, int ny, in
                           const double origin[3], const double spacing[3], double K,
                           double rho_inf, void *ws_dev, size_t ws_bytes);
 
+/* Node layout for fine grids: the same field stored as one float4 (n - 1, grad n) per node (16 bytes
+ * per node instead of 128 per cell, so the field of a grid whose cells are about one step long can
+ * stay in the GPU's caches); the integration kernel forms each cell's interpolation coefficients
+ * from its eight corners when a ray enters the cell (a dedicated kernel variant at four waves per
+ * SIMD).  Same arguments, validation and results (to float32 rounding of the coefficients) as
+ * pbr_set_density_field; workspace pbr_field_workspace_bytes_nodes: 16 bytes per node plus the
+ * brick tables, each part rounded up to 256 bytes.  Lane refill (PBR_LANE_REFILL), shock FP64 steps
+ * (PBR_PREC_SHOCK_FP64, pbr_calibrate_precision) and batches need the per-cell field and return
+ * STATE with a node-layout field. */
+size_t pbr_field_workspace_bytes_nodes(int nx, int ny, int nz);
+int pbr_set_density_field_nodes(pbr_ctx *ctx, const float *rho_dev, int nx, int ny, int nz,
+                                const double origin[3], const double spacing[3], double K,
+                                double rho_inf, void *ws_dev, size_t ws_bytes);
+
 /* Bytes of trace workspace for chunks of rays_per_chunk rays (64 bytes per ray, at least 256
  * rays).  The trace runs the rays of a call in chunks of this size through three kernels
  * (emission and box entry, ray-equation integration, lens / sensor / deposit) that hand the ray

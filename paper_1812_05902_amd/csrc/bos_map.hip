@@ -92,10 +92,26 @@ __device__ __forceinline__ void grad_xy(const TraceParams &P, const double R[3],
         c[a] = i;
         w[a] = f - (double)i;
     }
-    const float4 *q = P.cells + ((size_t)(c[2] * (P.ny - 1) + c[1]) * (size_t)(P.nx - 1) + (size_t)c[0]) * kCellFloat4;
     float4 k[kCellFloat4];
+    if (P.node_layout) {  // corners (n - 1, grad n) -> the coefficients of the cell records
+        const size_t sy = (size_t)P.nx, sz = (size_t)P.nx * (size_t)P.ny;
+        const float4 *b = P.cells + (size_t)c[2] * sz + (size_t)c[1] * sy + (size_t)c[0];
+        const float4 v000 = b[0], v100 = b[1], v010 = b[sy], v110 = b[sy + 1];
+        const float4 v001 = b[sz], v101 = b[sz + 1], v011 = b[sz + sy], v111 = b[sz + sy + 1];
+        k[0] = v000;
+        k[1] = v100 - v000;
+        k[2] = v010 - v000;
+        k[3] = v001 - v000;
+        k[4] = (v110 - v010) - k[1];
+        k[5] = (v101 - v001) - k[1];
+        k[6] = (v011 - v001) - k[2];
+        k[7] = (((v111 - v011) - (v110 - v010)) - (v101 - v001)) + k[1];
+    } else {
+        const float4 *q =
+            P.cells + ((size_t)(c[2] * (P.ny - 1) + c[1]) * (size_t)(P.nx - 1) + (size_t)c[0]) * kCellFloat4;
 #pragma unroll
-    for (int m = 0; m < kCellFloat4; ++m) k[m] = q[m];
+        for (int m = 0; m < kCellFloat4; ++m) k[m] = q[m];
+    }
     const double x = w[0], y = w[1], z = w[2];
     // v = c0 + z c3 + y (c2 + z c6) + x (c1 + y (c4 + z c7) + z c5)
     *gx = (double)k[0].y + z * (double)k[3].y + y * ((double)k[2].y + z * (double)k[6].y) +

@@ -1,7 +1,7 @@
 // Field preparation (sec. 3.2): Gladstone-Dale n = K rho + 1 (eq. 1) and the refractive-index
 // gradient at the grid nodes (central differences inside, second-order one-sided differences on
 // the faces), stored per cell as the coefficients of the trilinear interpolant of
-// (n - 1, grad n) over the cell's eight corners (layout in pbr_internal.h).
+// (n - 1, grad n) over the cell's eight corners (layout in pbr_internal.h), or per node.
 //
 // One thread per cell; all arithmetic in FP64, rounded once to float32 on output.  The kernel
 // streams rho (4 B per node, neighbours from cache) and writes 128 B per cell: HBM-bound.
@@ -27,6 +27,23 @@ __device__ __forceinline__ double index_derivative(const float *__restrict__ rho
     return 0.5 * ((double)rho[q + stride] - (double)rho[q - stride]);
 }
 
+// Per-node values (n - 1, dn/dx, dn/dy, dn/dz) for the node layout: one thread per node.
+__global__ void __launch_bounds__(256)
+k_field_nodes(const float *__restrict__ rho, float4 *__restrict__ nodes, int nx, int ny, int nz, double kx,
+              double ky, double kz, double K)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    const int k = blockIdx.z;
+    if (i >= nx) return;
+    const size_t sy = (size_t)nx, sz = (size_t)nx * (size_t)ny;
+    const size_t q = (size_t)k * sz + (size_t)j * sy + (size_t)i;
+    nodes[q] = make_float4((float)(K * (double)rho[q]), (float)(kx * index_derivative(rho, q, 1, i, nx)),
+                           (float)(ky * index_derivative(rho, q, sy, j, ny)),
+                           (float)(kz * index_derivative(rho, q, sz, k, nz)));
+}
+
+// cells = null: only the per-brick steepness (node layout).
 __global__ void __launch_bounds__(256)
 k_field_prep(const float *__restrict__ rho, float4 *__restrict__ cells, unsigned *__restrict__ brick_gmax,
              int nx, int ny, int nz, double kx, double ky, double kz, double K)
@@ -58,6 +75,7 @@ k_field_prep(const float *__restrict__ rho, float4 *__restrict__ cells, unsigned
         const float gf = (float)gm;
         if (gf > 0.0f) atomicMax(brick_gmax + b, __float_as_uint(gf));  // non-negative floats order as uints
     }
+    if (!cells) return;
     double c[8][4];
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
@@ -88,12 +106,17 @@ __global__ void __launch_bounds__(256) k_clear_u64(unsigned long long *p, int64_
 }  // namespace
 
 int launch_field_prep(const float *rho, float4 *cells, unsigned *brick_gmax, int nx, int ny, int nz,
-                      const double spacing[3], double K, hipStream_t stream)
+                      const double spacing[3], double K, hipStream_t stream, bool nodes)
 {
     dim3 block(256);
     dim3 grid((unsigned)((nx - 1 + 255) / 256), (unsigned)(ny - 1), (unsigned)(nz - 1));
-    hipLaunchKernelGGL(k_field_prep, grid, block, 0, stream, rho, cells, brick_gmax, nx, ny, nz,
+    hipLaunchKernelGGL(k_field_prep, grid, block, 0, stream, rho, nodes ? nullptr : cells, brick_gmax, nx, ny, nz,
                        K / spacing[0], K / spacing[1], K / spacing[2], K);
+    if (nodes) {
+        dim3 ngrid((unsigned)((nx + 255) / 256), (unsigned)ny, (unsigned)nz);
+        hipLaunchKernelGGL(k_field_nodes, ngrid, block, 0, stream, rho, cells, nx, ny, nz, K / spacing[0],
+                           K / spacing[1], K / spacing[2], K);
+    }
     return (int)hipGetLastError();
 }
 

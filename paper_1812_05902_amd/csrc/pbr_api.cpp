@@ -136,6 +136,7 @@ void fill_params(const pbr_ctx *ctx, const Derived &d, double ds, TraceParams *o
     P.pitch = ctx->sensor.pitch;
     P.sigma_px = d.sigma_px;
     P.rfp = d.rfp;
+    P.node_layout = ctx->layout.nodes;
     P.rec = ctx->rec;
     P.rec_first = ctx->rec_first;
     P.rec_stride = ctx->rec_stride;
@@ -257,9 +258,34 @@ int pbr_set_trace_workspace(pbr_ctx *ctx, void *ws_dev, size_t ws_bytes)
     return PBR_OK;
 }
 
+namespace {
+int set_field(pbr_ctx *ctx, const float *rho_dev, int nx, int ny, int nz, const double origin[3],
+              const double spacing[3], double K, double rho_inf, void *ws_dev, size_t ws_bytes, bool nodes);
+}  // namespace
+
 int pbr_set_density_field(pbr_ctx *ctx, const float *rho_dev, int nx, int ny, int nz,
                           const double origin[3], const double spacing[3], double K,
                           double rho_inf, void *ws_dev, size_t ws_bytes)
+{
+    return set_field(ctx, rho_dev, nx, ny, nz, origin, spacing, K, rho_inf, ws_dev, ws_bytes, false);
+}
+
+int pbr_set_density_field_nodes(pbr_ctx *ctx, const float *rho_dev, int nx, int ny, int nz,
+                                const double origin[3], const double spacing[3], double K,
+                                double rho_inf, void *ws_dev, size_t ws_bytes)
+{
+    return set_field(ctx, rho_dev, nx, ny, nz, origin, spacing, K, rho_inf, ws_dev, ws_bytes, true);
+}
+
+size_t pbr_field_workspace_bytes_nodes(int nx, int ny, int nz)
+{
+    if (nx < 2 || ny < 2 || nz < 2) return 0;
+    return pbr::field_layout(nx, ny, nz, true).total;
+}
+
+namespace {
+int set_field(pbr_ctx *ctx, const float *rho_dev, int nx, int ny, int nz, const double origin[3],
+              const double spacing[3], double K, double rho_inf, void *ws_dev, size_t ws_bytes, bool nodes)
 {
     if (!ctx) return PBR_ERR_ARG;
     PBR_GUARD_BEGIN
@@ -272,10 +298,10 @@ int pbr_set_density_field(pbr_ctx *ctx, const float *rho_dev, int nx, int ny, in
     if (!(spacing[0] > 0 && spacing[1] > 0 && spacing[2] > 0)) return fail(ctx, PBR_ERR_ARG, "spacing must be > 0");
     if (!std::isfinite(K) || K < 0.0) return fail(ctx, PBR_ERR_ARG, "K must be finite and >= 0");
     if (!std::isfinite(rho_inf)) return fail(ctx, PBR_ERR_ARG, "rho_inf not finite");
-    const size_t need = pbr_field_workspace_bytes(nx, ny, nz);
+    const size_t need = nodes ? pbr_field_workspace_bytes_nodes(nx, ny, nz) : pbr_field_workspace_bytes(nx, ny, nz);
     if (ws_bytes < need) return fail(ctx, PBR_ERR_WORKSPACE, "field workspace %zu bytes < %zu needed", ws_bytes, need);
     if (((uintptr_t)ws_dev & 15u) != 0) return fail(ctx, PBR_ERR_ARG, "field workspace must be 16-byte aligned");
-    const pbr::FieldLayout L = pbr::field_layout(nx, ny, nz);
+    const pbr::FieldLayout L = pbr::field_layout(nx, ny, nz, nodes);
     char *base = (char *)ws_dev;
     if (ctx->device >= 0) {
         DeviceGuard g(ctx->device);
@@ -285,7 +311,7 @@ int pbr_set_density_field(pbr_ctx *ctx, const float *rho_dev, int nx, int ny, in
                                       (int64_t)((L.total - L.gmax_off) / 8), ctx->stream);
         if (e) return hip_fail(ctx, e, "clear brick tables");
         e = pbr::launch_field_prep(rho_dev, (float4 *)(base + L.cells_off), (unsigned *)(base + L.gmax_off),
-                                   nx, ny, nz, spacing, K, ctx->stream);
+                                   nx, ny, nz, spacing, K, ctx->stream, nodes);
         if (e) return hip_fail(ctx, e, "field preparation launch");
     }
     ctx->layout = L;
@@ -302,6 +328,7 @@ int pbr_set_density_field(pbr_ctx *ctx, const float *rho_dev, int nx, int ny, in
     return PBR_OK;
     PBR_GUARD_END
 }
+}  // namespace
 
 int pbr_set_optics(pbr_ctx *ctx, const pbr_optics *o)
 {
@@ -417,6 +444,8 @@ int pbr_emit_and_trace(pbr_ctx *ctx, const float *src_dev, int64_t n_src, int32_
                             PBR_SURROGATE | PBR_LANE_REFILL | PBR_SOURCE_SUMS | PBR_MIE))
         return fail(ctx, PBR_ERR_ARG, "unknown flag bits 0x%x", flags);
     if ((flags & PBR_MIE) && !ctx->mie) return fail(ctx, PBR_ERR_STATE, "no Mie table set (pbr_set_mie)");
+    if (ctx->layout.nodes && (flags & (PBR_LANE_REFILL | PBR_PREC_SHOCK_FP64)))
+        return fail(ctx, PBR_ERR_STATE, "lane refill and shock FP64 steps need the per-cell field (pbr_set_density_field)");
     if (flags & PBR_SOURCE_SUMS) {
         if (!ctx->src_sums) return fail(ctx, PBR_ERR_STATE, "no per-source sums set (pbr_set_source_sums)");
         if (n_src > ctx->src_sums_cap)
@@ -528,6 +557,7 @@ int pbr_calibrate_precision(pbr_ctx *ctx, double tol_px, double steep_frac, int3
     int r = derive(ctx, &d);
     if (r) return r;
     if (ctx->has_chain) return fail(ctx, PBR_ERR_STATE, "precision calibration needs the singlet (an optical chain is set)");
+    if (ctx->layout.nodes) return fail(ctx, PBR_ERR_STATE, "precision calibration needs the per-cell field");
     if (!(tol_px >= 0.0) || !std::isfinite(tol_px)) return fail(ctx, PBR_ERR_ARG, "tol_px must be finite and >= 0");
     if (!(steep_frac >= 0.0 && steep_frac <= 1.0)) return fail(ctx, PBR_ERR_ARG, "steep_frac must lie in [0, 1]");
     if (rays_per_brick < 1 || rays_per_brick > 256) return fail(ctx, PBR_ERR_ARG, "rays_per_brick must lie in [1, 256]");

@@ -264,6 +264,11 @@ int pbr_batch_create(pbr_batch **out, const pbr_batch_item *items, int n_items, 
             pbr::host::Derived d;
             const int r = pbr::host::derive(c, &d);
             if (r) { g_batch_create_err = std::string("item ") + std::to_string(i) + ": " + c->err; delete b; return r; }
+            if (c->layout.nodes) {
+                g_batch_create_err = "item " + std::to_string(i) + ": batches need the per-cell field";
+                delete b;
+                return PBR_ERR_STATE;
+            }
             if (c->has_chain) {
                 g_batch_create_err = "item " + std::to_string(i) + ": batches use the singlet (an optical chain is set)";
                 delete b;

@@ -36,21 +36,26 @@ constexpr int kBrick = 8;
 
 // Byte layout of the field workspace: cell records, then per-brick max |grad n| (uint32 float
 // bits), then per-brick FP64 flags (uint8); each part 256-byte aligned.
+// nodes = 0: per-cell records (128 B per cell); nodes = 1: per-node float4 (n - 1, grad n), 16 B per
+// node, from which a gather forms the same coefficients (8x less memory for fine grids).
 struct FieldLayout {
     size_t cells_off, gmax_off, flags_off, total;
     int nbx, nby, nbz;
+    int nodes;
     int64_t n_bricks;
 };
 inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
-inline FieldLayout field_layout(int nx, int ny, int nz)
+inline FieldLayout field_layout(int nx, int ny, int nz, bool nodes = false)
 {
     FieldLayout L;
     L.nbx = (nx - 1 + kBrick - 1) / kBrick;
     L.nby = (ny - 1 + kBrick - 1) / kBrick;
     L.nbz = (nz - 1 + kBrick - 1) / kBrick;
+    L.nodes = nodes ? 1 : 0;
     L.n_bricks = (int64_t)L.nbx * L.nby * L.nbz;
     L.cells_off = 0;
-    L.gmax_off = align256((size_t)(nx - 1) * (size_t)(ny - 1) * (size_t)(nz - 1) * kCellFloat4 * 16);
+    L.gmax_off = nodes ? align256((size_t)nx * (size_t)ny * (size_t)nz * 16)
+                       : align256((size_t)(nx - 1) * (size_t)(ny - 1) * (size_t)(nz - 1) * kCellFloat4 * 16);
     L.flags_off = align256(L.gmax_off + (size_t)L.n_bricks * 4);
     L.total = align256(L.flags_off + (size_t)L.n_bricks);
     return L;
@@ -83,7 +88,7 @@ struct TraceParams {
     double pitch;
     double sigma_px;
     int rfp;
-    int pad0;
+    int node_layout;       // field stored per node (see FieldLayout) instead of per cell
     // exit records
     pbr_ray_exit *rec;
     int64_t rec_first, rec_stride, rec_max;
@@ -222,7 +227,7 @@ struct BatchConfig {
 // Launchers (defined in the .hip files; enqueue on `stream`, return hipError_t as int).
 // Writes the cell records and (atomically) the per-brick max |grad n|; gmax must be zeroed.
 int launch_field_prep(const float *rho, float4 *cells, unsigned *brick_gmax, int nx, int ny, int nz,
-                      const double spacing[3], double K, hipStream_t stream);
+                      const double spacing[3], double K, hipStream_t stream, bool nodes = false);
 // Precision calibration: for each listed brick, rays_per_brick sample rays integrated over
 // n_steps full steps in FP32 and in FP64 from the same state; err[k] = largest difference of
 // the image point (apparent source on the plane z_focus, times |M| / pitch) in pixels.

@@ -40,6 +40,25 @@ __device__ __forceinline__ int clamp_index(int x, int hi)
     return r;
 }
 
+// Node layout: the eight corners (n - 1, grad n) of cell ic, turned into the coefficients of the
+// cell records (c0 + x c1 + y c2 + z c3 + xy c4 + xz c5 + yz c6 + xyz c7 per quantity).
+__device__ __forceinline__ void gather_nodes(const TraceParams &P, const int ic[3], float4 c[8])
+{
+    const size_t sy = (size_t)P.nx, sz = (size_t)P.nx * (size_t)P.ny;
+    const float4 *b = P.cells + (size_t)ic[2] * sz + (size_t)ic[1] * sy + (size_t)ic[0];
+    // corners straight into the coefficient slots (000, 100, 010, 001, 110, 101, 011, 111), then
+    // differenced in place: no registers beyond the cache itself
+    c[0] = b[0]; c[1] = b[1]; c[2] = b[sy]; c[3] = b[sz];
+    c[4] = b[sy + 1]; c[5] = b[sz + 1]; c[6] = b[sz + sy]; c[7] = b[sz + sy + 1];
+    c[7] = c[7] - c[6] - c[5] - c[4] + c[1] + c[2] + c[3] - c[0];
+    c[4] = c[4] - c[1] - c[2] + c[0];
+    c[5] = c[5] - c[1] - c[3] + c[0];
+    c[6] = c[6] - c[2] - c[3] + c[0];
+    c[1] = c[1] - c[0];
+    c[2] = c[2] - c[0];
+    c[3] = c[3] - c[0];
+}
+
 // The coefficients of the cell the ray is in, held in registers: a stage point only gathers
 // from memory when it lies in another cell (about once per cell crossing, since the three stage
 // points of a step run ahead of the ray).
@@ -54,7 +73,8 @@ struct CellCache {
 // INSIDE: the caller has shown that the point lies inside the box and that the ray's own cell index
 // is a cell of the grid (see trace_step), so the edge extension is left out; the cell index is still
 // clamped to the grid, which keeps every gather in bounds whatever the values.
-template <typename F, bool AT_STATE = false, bool INSIDE = false>
+// NODES: the field is stored per node (see gather_nodes); compiled into dedicated kernels only.
+template <typename F, bool AT_STATE = false, bool INSIDE = false, bool NODES = false>
 __device__ __forceinline__ F sample_D(const TraceParams &P, CellCache &cc, const int c[3],
                                       const F f[3], F D[3])
 {
@@ -86,10 +106,13 @@ __device__ __forceinline__ F sample_D(const TraceParams &P, CellCache &cc, const
     }
     // compare cell coordinates (no index arithmetic unless the cell changed)
     if ((ic[0] != cc.ix) | (ic[1] != cc.iy) | (ic[2] != cc.iz)) {
-        const int key = (ic[2] * (P.ny - 1) + ic[1]) * (P.nx - 1) + ic[0];
-        const float4 *p = P.cells + (size_t)key * kCellFloat4;
+        if (NODES) gather_nodes(P, ic, cc.c);
+        else {
+            const int key = (ic[2] * (P.ny - 1) + ic[1]) * (P.nx - 1) + ic[0];
+            const float4 *p = P.cells + (size_t)key * kCellFloat4;
 #pragma unroll
-        for (int m = 0; m < kCellFloat4; ++m) cc.c[m] = p[m];
+            for (int m = 0; m < kCellFloat4; ++m) cc.c[m] = p[m];
+        }
         cc.ix = ic[0];
         cc.iy = ic[1];
         cc.iz = ic[2];
@@ -120,7 +143,7 @@ __device__ __forceinline__ F sample_D(const TraceParams &P, CellCache &cc, const
 // is nearly the same every step, so FP32 rounding of the running sum would err the same way
 // every step and grow linearly with the step count.  Stage points are formed in F.
 // INSIDE: every point of the step is known to lie inside the box (full steps only).
-template <typename F, bool FULL, bool INSIDE = false>
+template <typename F, bool FULL, bool INSIDE = false, bool NODES = false>
 __device__ __forceinline__ void rkn_step(const TraceParams &P, CellCache &cc, int c[3], double fd[3],
                                          const F Tr[3], F dT[3], const F g[3], F hstep, F lam)
 {
@@ -128,13 +151,13 @@ __device__ __forceinline__ void rkn_step(const TraceParams &P, CellCache &cc, in
     F f[3], gg[3], T[3], A[3], B[3], C[3], q[3], D[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) { f[a] = (F)fd[a]; gg[a] = FULL ? g[a] : lam * g[a]; T[a] = Tr[a] + dT[a]; }
-    sample_D<F, true, INSIDE>(P, cc, c, f, D);
+    sample_D<F, true, INSIDE, NODES>(P, cc, c, f, D);
 #pragma unroll
     for (int a = 0; a < 3; ++a) { A[a] = hh * D[a]; q[a] = f[a] + gg[a] * ((F)0.5 * T[a] + (F)0.125 * A[a]); }
-    sample_D<F, false, INSIDE>(P, cc, c, q, D);
+    sample_D<F, false, INSIDE, NODES>(P, cc, c, q, D);
 #pragma unroll
     for (int a = 0; a < 3; ++a) { B[a] = hh * D[a]; q[a] = f[a] + gg[a] * (T[a] + (F)0.5 * B[a]); }
-    sample_D<F, false, INSIDE>(P, cc, c, q, D);
+    sample_D<F, false, INSIDE, NODES>(P, cc, c, q, D);
     const F sixth = (F)1 / (F)6;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -169,7 +192,7 @@ enum : int { STEP_GO = 0, STEP_EXIT = 1, STEP_LIMIT = 2 };
 // the same bits as the inside one wherever both apply).
 constexpr float kFaceMargin = 1.0e-3f;
 
-template <typename F>
+template <typename F, bool NODES = false>
 __device__ __forceinline__ int trace_step(const TraceParams &P, CellCache &cc, int c[3], double fd[3], const F Tr[3],
                                           F dT[3], const F g[3], F hstep, const int last[3], int &steps)
 {
@@ -182,7 +205,7 @@ __device__ __forceinline__ int trace_step(const TraceParams &P, CellCache &cc, i
         inside = inside & (e > (F)kFaceMargin) & (e < (F)last[a] - (F)kFaceMargin);
     }
     if (inside) {
-        rkn_step<F, true, true>(P, cc, c, fd, Tr, dT, g, hstep, (F)1);
+        rkn_step<F, true, true, NODES>(P, cc, c, fd, Tr, dT, g, hstep, (F)1);
         return ++steps > P.max_steps ? STEP_LIMIT : STEP_GO;
     }
     F lam = (F)3.0e38;
@@ -199,7 +222,7 @@ __device__ __forceinline__ int trace_step(const TraceParams &P, CellCache &cc, i
     const bool up = hit && (pick3<F>(Tr, ax) + pick3<F>(dT, ax)) > (F)0;
     // one call site for both the partial step and the edge-extended full step
     if (!hit || lam > (F)0) {
-        rkn_step<F, false>(P, cc, c, fd, Tr, dT, g, hstep, hit ? lam : (F)1);
+        rkn_step<F, false, false, NODES>(P, cc, c, fd, Tr, dT, g, hstep, hit ? lam : (F)1);
         ++steps;
         // a step ending on or a hair beyond the upper face leaves cell n - 1 at fraction ~0: keep the
         // index a cell of the grid (same position), as the inside steps assume
@@ -234,7 +257,7 @@ __device__ __forceinline__ int trace_step(const TraceParams &P, CellCache &cc, i
 
 // Integrate from the cell-local state until the ray leaves the box (see trace_step).  Returns the
 // number of steps; sets *limited when max_steps is exceeded.
-template <typename F>
+template <typename F, bool NODES = false>
 __device__ __forceinline__ int trace_box(const TraceParams &P, CellCache &cc, int c[3], double fd[3],
                                          const F Tr[3], F dT[3], bool *limited)
 {
@@ -243,7 +266,7 @@ __device__ __forceinline__ int trace_box(const TraceParams &P, CellCache &cc, in
     const int last[3] = {P.nx - 1, P.ny - 1, P.nz - 1};
     int steps = 0;
     for (;;) {
-        const int r = trace_step<F>(P, cc, c, fd, Tr, dT, g, hstep, last, steps);
+        const int r = trace_step<F, NODES>(P, cc, c, fd, Tr, dT, g, hstep, last, steps);
         if (r != STEP_GO) {
             *limited = r == STEP_LIMIT;
             return steps;
@@ -516,7 +539,8 @@ __device__ __forceinline__ void emit_ray(const TraceParams &P, int64_t rid, RayS
     CellCache cc;
     cc.ix = -1;
     float D0[3];
-    const float n0 = sample_D<float>(P, cc, r.c, f, D0);
+    const float n0 = P.node_layout ? sample_D<float, false, false, true>(P, cc, r.c, f, D0)
+                                   : sample_D<float>(P, cc, r.c, f, D0);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {  // T0 as a float hi/lo pair: no rounding of the entry direction
         const double T0 = (double)n0 * u[a];
@@ -538,7 +562,7 @@ __global__ void __launch_bounds__(256) k_emit(TraceParams P, RayState *__restric
 
 // ------------------------------------------------------------------ kernel 2: the ray equation
 
-template <typename F>
+template <typename F, bool NODES = false>
 __device__ __forceinline__ void box_ray(const TraceParams &P, RayState &r)
 {
     // T = Tr + dT; in FP32 the low part of the entry direction starts the accumulated change
@@ -556,7 +580,7 @@ __device__ __forceinline__ void box_ray(const TraceParams &P, RayState &r)
     CellCache cc;
     cc.ix = -1;
     bool limited = false;
-    const int steps = trace_box<F>(P, cc, r.c, r.fd, Tr, dT, &limited);
+    const int steps = trace_box<F, NODES>(P, cc, r.c, r.fd, Tr, dT, &limited);
     // exit direction as a float hi/lo pair (about 48 significant bits)
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -583,7 +607,7 @@ __device__ __forceinline__ bool box_index(int64_t n, const int *__restrict__ lis
     return k < n;
 }
 
-template <typename F>
+template <typename F, bool NODES = false>
 __device__ __forceinline__ void box_body(const TraceParams &P, RayState *__restrict__ st, int64_t n,
                                          const int *__restrict__ list, const unsigned long long *__restrict__ count)
 {
@@ -591,23 +615,26 @@ __device__ __forceinline__ void box_body(const TraceParams &P, RayState *__restr
     if (!box_index(n, list, count, &i)) return;
     RayState r = st[i];
     if ((r.info & (RS_ENTERED | RS_SURR)) != RS_ENTERED) return;
-    box_ray<F>(P, r);
+    box_ray<F, NODES>(P, r);
     st[i] = r;
 }
 
-// FP32 integration: 96 VGPRs, five waves per SIMD.
-__global__ void __launch_bounds__(256, 5) k_box32(TraceParams P, RayState *__restrict__ st, int64_t n,
+// FP32 integration: 95 VGPRs, five waves per SIMD.  NODES: field stored per node (the corner gather
+// needs more registers: four waves per SIMD).
+template <bool NODES = false>
+__global__ void __launch_bounds__(256, NODES ? 4 : 5) k_box32(TraceParams P, RayState *__restrict__ st, int64_t n,
                                                   const int *__restrict__ list,
                                                   const unsigned long long *__restrict__ count)
 {
-    box_body<float>(P, st, n, list, count);
+    box_body<float, NODES>(P, st, n, list, count);
 }
 
+template <bool NODES = false>
 __global__ void __launch_bounds__(256) k_box64(TraceParams P, RayState *__restrict__ st, int64_t n,
                                                const int *__restrict__ list,
                                                const unsigned long long *__restrict__ count)
 {
-    box_body<double>(P, st, n, list, count);
+    box_body<double, NODES>(P, st, n, list, count);
 }
 
 // Persistent FP32 integration with lane refill: a fixed grid of waves (five per SIMD) takes rays
@@ -620,6 +647,7 @@ __global__ void __launch_bounds__(256, 5) k_box32_refill(TraceParams P, RayState
                                                          const unsigned long long *__restrict__ count,
                                                          unsigned long long *__restrict__ queue)
 {
+    if (P.node_layout) return;  // cell records only (the host never launches it otherwise)
     const int lane = threadIdx.x & 63;
     const unsigned long long total = list ? *count : (unsigned long long)n;
     const float g[3] = {(float)P.step_cell[0], (float)P.step_cell[1], (float)P.step_cell[2]};
@@ -770,6 +798,7 @@ __global__ void __launch_bounds__(256) k_box_mixed(TraceParams P, RayState *__re
                                                    const int *__restrict__ list,
                                                    const unsigned long long *__restrict__ count)
 {
+    if (P.node_layout) return;  // cell records only (the host never launches it otherwise)
     __shared__ unsigned long long s64;
     if (threadIdx.x == 0) s64 = 0ull;
     __syncthreads();
@@ -807,6 +836,7 @@ __global__ void __launch_bounds__(256) k_calibrate(TraceParams P, const int *__r
                                                    int n_steps, uint64_t seed, double z_focus,
                                                    double px_per_m, float *__restrict__ err)
 {
+    if (P.node_layout) return;  // cell records only (the host never launches it otherwise)
     __shared__ unsigned s_err;
     if (threadIdx.x == 0) s_err = 0u;
     __syncthreads();
@@ -1143,6 +1173,7 @@ __global__ void __launch_bounds__(BLOCK, 5) k_box_batch(const TraceParams *__res
         const int k = __builtin_amdgcn_readfirstlane(find_segment(segs, nseg, ray0 >> 8));
         const BatchSeg sg = segs[k];
         const TraceParams &P = params[sg.image];
+        if (P.node_layout) continue;  // cell records only (batches refuse node-layout fields)
         for (int sub = 0; sub < unit_rays; sub += 64) {
             const int64_t idx = ray0 + sub + lane;
             if (idx - sg.slot_base * 256 >= sg.n_rays) continue;
@@ -1533,8 +1564,10 @@ int launch_trace_chunk(const TraceParams &p, RayState *st, int64_t first, int64_
     TraceList tl{nullptr, nullptr};
     if (hook && (e = hook->run(hook->self, p, st, first, n, stream, &tl))) return e;
     if (box_begin && (e = (int)hipEventRecord(box_begin, stream))) return e;
-    if (prec == PREC_FP64)
-        hipLaunchKernelGGL(k_box64, dim3(blocks), dim3(256), 0, stream, p, st, n, tl.idx, tl.count);
+    if (prec == PREC_FP64) {
+        if (p.node_layout) hipLaunchKernelGGL(k_box64<true>, dim3(blocks), dim3(256), 0, stream, p, st, n, tl.idx, tl.count);
+        else hipLaunchKernelGGL(k_box64<false>, dim3(blocks), dim3(256), 0, stream, p, st, n, tl.idx, tl.count);
+    }
     else if (prec == PREC_MIXED)
         hipLaunchKernelGGL(k_box_mixed, dim3(blocks), dim3(256), 0, stream, p, st, n, tl.idx, tl.count);
     else if (refill) {
@@ -1546,8 +1579,10 @@ int launch_trace_chunk(const TraceParams &p, RayState *st, int64_t first, int64_
         if ((e = launch_clear_u64(p.counters + CNT_QUEUE, 1, stream))) return e;
         hipLaunchKernelGGL(k_box32_refill, dim3(pblocks), dim3(256), 0, stream, p, st, n, tl.idx, tl.count,
                            p.counters + CNT_QUEUE);
-    } else
-        hipLaunchKernelGGL(k_box32, dim3(blocks), dim3(256), 0, stream, p, st, n, tl.idx, tl.count);
+    } else if (p.node_layout)
+        hipLaunchKernelGGL(k_box32<true>, dim3(blocks), dim3(256), 0, stream, p, st, n, tl.idx, tl.count);
+    else
+        hipLaunchKernelGGL(k_box32<false>, dim3(blocks), dim3(256), 0, stream, p, st, n, tl.idx, tl.count);
     e = (int)hipGetLastError();
     if (e) return e;
     if (box_end && (e = (int)hipEventRecord(box_end, stream))) return e;

@@ -47,7 +47,8 @@ EXPORTED = ["pbr_create", "pbr_destroy", "pbr_last_error", "pbr_set_stream",
             "pbr_surrogate_tile_map", "pbr_set_surrogate", "pbr_probe_u64_atomics",
             "pbr_set_source_sums", "pbr_dot_map_workspace_bytes", "pbr_dot_displacement_map",
             "pbr_bos_theory_map", "pbr_displace_sources", "pbr_mie_table", "pbr_mie_workspace_bytes",
-            "pbr_set_mie", "pbr_set_optical_chain"]
+            "pbr_set_mie", "pbr_set_optical_chain", "pbr_field_workspace_bytes_nodes",
+            "pbr_set_density_field_nodes"]
 
 
 class PbrError(RuntimeError):
@@ -169,6 +170,8 @@ def load(path: str = LIB_PATH):
         "pbr_trace_workspace_bytes": (C.c_size_t, [I64]),
         "pbr_set_trace_workspace": (I, [P, P, C.c_size_t]),
         "pbr_set_density_field": (I, [P, P, I, I, I, P, P, D, D, P, C.c_size_t]),
+        "pbr_set_density_field_nodes": (I, [P, P, I, I, I, P, P, D, D, P, C.c_size_t]),
+        "pbr_field_workspace_bytes_nodes": (C.c_size_t, [I, I, I]),
         "pbr_set_optics": (I, [P, C.POINTER(pbr_optics)]),
         "pbr_set_sensor": (I, [P, C.POINTER(pbr_sensor), P]),
         "pbr_get_derived": (I, [P, C.POINTER(pbr_derived)]),
@@ -258,12 +261,17 @@ def pbr_set_trace_workspace(ctx, ws):
     _check(ctx, load().pbr_set_trace_workspace(ctx, _dptr(ws), ws.numel() * ws.element_size()))
 
 
-def pbr_set_density_field(ctx, rho, origin, spacing, K, rho_inf, ws):
+def pbr_set_density_field(ctx, rho, origin, spacing, K, rho_inf, ws, nodes=False):
     nz, ny, nx = rho.shape
     o = (C.c_double * 3)(*origin)
     s = (C.c_double * 3)(*spacing)
-    _check(ctx, load().pbr_set_density_field(ctx, _dptr(rho), nx, ny, nz, o, s, float(K),
-                                             float(rho_inf), _dptr(ws), ws.numel() * ws.element_size()))
+    fn = load().pbr_set_density_field_nodes if nodes else load().pbr_set_density_field
+    _check(ctx, fn(ctx, _dptr(rho), nx, ny, nz, o, s, float(K), float(rho_inf), _dptr(ws),
+                   ws.numel() * ws.element_size()))
+
+
+def pbr_field_workspace_bytes_nodes(nx, ny, nz) -> int:
+    return int(load().pbr_field_workspace_bytes_nodes(nx, ny, nz))
 
 
 def pbr_set_optics(ctx, optics: pbr_optics):
@@ -422,14 +430,15 @@ class Renderer:
         except Exception:
             pass
 
-    def set_density_field(self, rho, origin, spacing, K, rho_inf):
+    def set_density_field(self, rho, origin, spacing, K, rho_inf, nodes=False):
+        """nodes=True: the node layout (16 B per node) for fine grids."""
         torch = self.torch
         rho = torch.as_tensor(rho, dtype=torch.float32, device=self.device).contiguous()
         nz, ny, nx = rho.shape
-        nb = pbr_field_workspace_bytes(nx, ny, nz)
+        nb = pbr_field_workspace_bytes_nodes(nx, ny, nz) if nodes else pbr_field_workspace_bytes(nx, ny, nz)
         if self.ws is None or self.ws.numel() * 4 < nb:
             self.ws = torch.empty((nb + 3) // 4, dtype=torch.float32, device=self.device)
-        pbr_set_density_field(self.ctx, rho, origin, spacing, K, rho_inf, self.ws)
+        pbr_set_density_field(self.ctx, rho, origin, spacing, K, rho_inf, self.ws, nodes=nodes)
         self.grid_shape = (nx, ny, nz)
         self._rho_keepalive = rho  # until the stream passes field preparation
 
@@ -542,13 +551,13 @@ class Renderer:
         return pbr_read_ray_exits(self.ctx, first, count)
 
     @classmethod
-    def from_scene(cls, scene, rho=None, device=None, rays_per_chunk=1 << 22):
-        """Renderer with field, optics and sensor of an ``inputs.Scene``."""
+    def from_scene(cls, scene, rho=None, device=None, rays_per_chunk=1 << 22, nodes=False):
+        """Renderer with field, optics and sensor of an ``inputs.Scene`` (nodes: node layout)."""
         from . import inputs
         r = cls(device, rays_per_chunk=rays_per_chunk)
         if rho is None:
             rho = inputs.density(scene)
-        r.set_density_field(rho, scene.origin, scene.spacing, scene.K, scene.rho_inf)
+        r.set_density_field(rho, scene.origin, scene.spacing, scene.K, scene.rho_inf, nodes=nodes)
         r.set_optics(scene.z_lens, scene.focal_length, scene.f_number, scene.thickness,
                      scene.n_glass, scene.clear_radius, scene.z_focus)
         r.set_sensor(scene.width, scene.height, scene.pitch, scene.z_sensor, scene.wavelength,
@@ -565,11 +574,11 @@ def u16_image_to_numpy(t) -> np.ndarray:
     return t.cpu().numpy().view(np.uint16)
 
 
-def trace_scene(scene, flags=PBR_CLEAR_FIRST, stats=True, record=None, rho=None, src=None):
+def trace_scene(scene, flags=PBR_CLEAR_FIRST, stats=True, record=None, rho=None, src=None, nodes=False):
     """Convenience: render a scene; ``record`` = (first, stride, max) for exit records.
     Returns (renderer, stats dict, records or None)."""
     from . import inputs
-    r = Renderer.from_scene(scene, rho=rho)
+    r = Renderer.from_scene(scene, rho=rho, nodes=nodes)
     if record is not None:
         r.set_exit_recording(*record)
         flags |= PBR_RECORD_EXITS

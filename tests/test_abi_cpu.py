@@ -463,3 +463,37 @@ def test_optical_chain_validates(lib):
         assert lib.pbr_get_derived(h, C.byref(d)) == pbr.PBR_ERR_STATE  # no pbr_set_optics yet
     finally:
         lib.pbr_destroy(h)
+
+
+def test_node_layout_workspace_and_limits(lib):
+    """Node layout: 16 bytes per node, then the brick tables; the paths that need per-cell records
+    refuse it before any device work."""
+    up = lambda v: (v + 255) // 256 * 256
+    for n in (32, 257):
+        nb = ((n - 1 + 7) // 8) ** 3
+        assert pbr.pbr_field_workspace_bytes_nodes(n, n, n) == up(up(up(n ** 3 * 16) + 4 * nb) + nb)
+    assert pbr.pbr_field_workspace_bytes_nodes(1, 4, 4) == 0
+    assert pbr.pbr_field_workspace_bytes_nodes(64, 64, 64) < pbr.pbr_field_workspace_bytes(64, 64, 64) / 7
+    h = _host_ctx(lib)
+    try:
+        o = (C.c_double * 3)(0, 0, 0.1)
+        sp = (C.c_double * 3)(1e-3, 1e-3, 1e-3)
+        need = pbr.pbr_field_workspace_bytes_nodes(32, 32, 32)
+        f = lib.pbr_set_density_field_nodes
+        assert f(h, FAKE, 32, 32, 32, o, sp, 2.26e-4, 1.2, FAKE, need - 1) == pbr.PBR_ERR_WORKSPACE
+        assert f(h, FAKE, 1, 32, 32, o, sp, 2.26e-4, 1.2, FAKE, need) == pbr.PBR_ERR_ARG
+        assert f(h, FAKE, 32, 32, 32, o, sp, 2.26e-4, 1.2, FAKE, need) == pbr.PBR_OK
+        assert lib.pbr_set_optics(h, C.byref(_optics())) == pbr.PBR_OK
+        assert lib.pbr_set_sensor(h, C.byref(_sensor()), FAKE) == pbr.PBR_OK
+        assert lib.pbr_set_trace_workspace(h, FAKE, 1 << 20) == pbr.PBR_OK
+        for flag in (pbr.PBR_LANE_REFILL, pbr.PBR_PREC_SHOCK_FP64):
+            assert lib.pbr_emit_and_trace(h, FAKE, 1, 1, 0, 1e-4, flag, None) == pbr.PBR_ERR_STATE
+            assert "per-cell" in _err(lib, h)
+        rep = pbr.pbr_precision_report()
+        assert lib.pbr_calibrate_precision(h, 1e-3, 0.1, 8, 1, 1e-4, C.byref(rep)) == pbr.PBR_ERR_STATE
+        # the per-cell field lifts the restriction
+        assert _set_field(lib, h) == pbr.PBR_OK
+        assert lib.pbr_emit_and_trace(h, FAKE, 1, 1, 0, 1e-4, pbr.PBR_LANE_REFILL, None) == pbr.PBR_ERR_STATE
+        assert "host-only" in _err(lib, h)
+    finally:
+        lib.pbr_destroy(h)
