@@ -621,6 +621,17 @@ int pbr_surrogate_train(pbr_surrogate *s, pbr_ctx *ctx, const float *train_src_d
  * ty * tiles + tx, tx along x.  Either pointer may be NULL.  Errors: STATE (not trained), ARG. */
 int pbr_surrogate_tile_map(pbr_surrogate *s, uint8_t *eligible_host, float *max_err_host, int64_t n_tiles);
 
+/* Persisting a trained surrogate (weights, Adam state, input/output scaling, tile map) as a
+ * self-checking host blob.  pbr_surrogate_blob_bytes: its size (0 unless trained).
+ * pbr_surrogate_save writes it (synchronises; errors: STATE untrained, WORKSPACE cap too small, HIP).
+ * pbr_surrogate_load restores it into `s` and binds it to `ctx`, which must hold the scene it was
+ * trained on: the same stored field (geometry and a device checksum of the field), optics, sensor
+ * and optical chain; traces must use the training step length ds.  Errors: ARG (not a blob,
+ * damaged, another version or network), STATE (the scene differs, host-only context), HIP. */
+size_t pbr_surrogate_blob_bytes(pbr_surrogate *s);
+int pbr_surrogate_save(pbr_surrogate *s, void *buf_host, size_t cap);
+int pbr_surrogate_load(pbr_surrogate *s, pbr_ctx *ctx, const void *buf_host, size_t size);
+
 /* Attaches a trained surrogate to the context it was trained on (NULL detaches).  Traces with
  * PBR_SURROGATE then hand every ray that enters through an eligible tile of z_min to the network
  * and trace the rest.  Fails with STATE when the surrogate is untrained, was trained on another

@@ -97,6 +97,26 @@ k_field_prep(const float *__restrict__ rho, float4 *__restrict__ cells, unsigned
         out[m] = make_float4((float)c[m][0], (float)c[m][1], (float)c[m][2], (float)c[m][3]);
 }
 
+// Fingerprint of a field: sum over its 32-bit words w_k of SplitMix64's finaliser applied to
+// (k << 32 | w_k), wrapping mod 2^64 (integer atomics: independent of the order of the blocks).
+__global__ void __launch_bounds__(256) k_checksum(const unsigned *__restrict__ w, int64_t n,
+                                                  unsigned long long *__restrict__ out)
+{
+    unsigned long long acc = 0ull;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) {
+        unsigned long long z = ((unsigned long long)k << 32) ^ (unsigned long long)w[k];
+        z += 0x9E3779B97F4A7C15ull;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        acc += z ^ (z >> 31);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if ((threadIdx.x & 63u) == 0)
+        __hip_atomic_fetch_add(out, acc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __global__ void __launch_bounds__(256) k_clear_u64(unsigned long long *p, int64_t n)
 {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -117,6 +137,17 @@ int launch_field_prep(const float *rho, float4 *cells, unsigned *brick_gmax, int
         hipLaunchKernelGGL(k_field_nodes, ngrid, block, 0, stream, rho, cells, nx, ny, nz, K / spacing[0],
                            K / spacing[1], K / spacing[2], K);
     }
+    return (int)hipGetLastError();
+}
+
+int launch_field_checksum(const void *field, size_t bytes, unsigned long long *out, hipStream_t stream)
+{
+    const int64_t n = (int64_t)(bytes / 4);
+    int e = launch_clear_u64(out, 1, stream);
+    if (e || n == 0) return e;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_checksum, dim3((unsigned)blocks), dim3(256), 0, stream, (const unsigned *)field, n, out);
     return (int)hipGetLastError();
 }
 

@@ -145,6 +145,23 @@ void fill_params(const pbr_ctx *ctx, const Derived &d, double ds, TraceParams *o
     P.chain = ctx->has_chain ? (const pbr_optical_chain *)((const char *)ctx->counters + pbr::kChainOffset) : nullptr;
 }
 
+int field_fingerprint(pbr_ctx *ctx, uint64_t *out)
+{
+    if (!ctx->has_field) return fail(ctx, PBR_ERR_STATE, "no field set");
+    if (ctx->device < 0) return fail(ctx, PBR_ERR_STATE, "host-only context: no device work");
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(ctx, PBR_ERR_HIP, "hipSetDevice failed");
+    // the counter block's spare slot after the queue holds the sum
+    unsigned long long *slot = ctx->counters + pbr::CNT_QUEUE + 1;
+    int e = pbr::launch_field_checksum(ctx->cells, ctx->layout.gmax_off, slot, ctx->stream);
+    unsigned long long h = 0;
+    if (!e) e = (int)hipMemcpyAsync(&h, slot, 8, hipMemcpyDeviceToHost, ctx->stream);
+    if (!e) e = (int)hipStreamSynchronize(ctx->stream);
+    if (e) return hip_fail(ctx, e, "field checksum");
+    *out = (uint64_t)h;
+    return PBR_OK;
+}
+
 uint64_t next_uid()
 {
     static std::atomic<uint64_t> n{0};
@@ -456,7 +473,7 @@ int pbr_emit_and_trace(pbr_ctx *ctx, const float *src_dev, int64_t n_src, int32_
     }
     pbr::ChunkHook hook{nullptr, nullptr};
     if (flags & PBR_SURROGATE) {
-        if ((r = surrogate_hook(ctx, &hook))) return r;
+        if ((r = surrogate_hook(ctx, ds, &hook))) return r;
     }
     if (!ctx->ray_ws) return fail(ctx, PBR_ERR_STATE, "no trace workspace set (pbr_set_trace_workspace)");
     if ((flags & PBR_RECORD_EXITS) && ctx->rec_max > 0 && !ctx->rec)

@@ -90,7 +90,13 @@ uint64_t next_uid();
 bool mie_intensity_table(std::complex<double> m, double x, int n_angles, double *out);
 // Chunk hook of an attached surrogate; fails with STATE (message on ctx) when it no longer
 // matches the context's scene.
-int surrogate_hook(pbr_ctx *ctx, ChunkHook *out);
+int surrogate_hook(pbr_ctx *ctx, double ds, ChunkHook *out);
+// Fingerprint of the context's stored field (device checksum of the field's words; synchronises).
+int field_fingerprint(pbr_ctx *ctx, uint64_t *out);
 
 }  // namespace host
+
+// Order-independent checksum of a device buffer's 32-bit words into *out (device), field_prep.hip.
+int launch_field_checksum(const void *field, size_t bytes, unsigned long long *out, hipStream_t stream);
+
 }  // namespace pbr

@@ -44,11 +44,68 @@ struct pbr_surrogate {
     int64_t chunk_cap = 0;
     std::vector<unsigned char> tile_ok;
     std::vector<float> tile_err;
+    // what the trained state depends on (checked when a saved surrogate is loaded)
+    double ds = 0.0;
+    struct SceneKey {
+        int32_t nx, ny, nz, node_layout;
+        double origin[3], spacing[3], K, rho_inf, ds;
+        uint64_t field_sum, optics_hash;
+    } key{};
 };
 
 namespace {
 
 thread_local std::string g_surr_create_err;
+
+uint64_t fnv1a(const void *p, size_t n, uint64_t h = 0xcbf29ce484222325ull)
+{
+    const unsigned char *b = (const unsigned char *)p;
+    for (size_t k = 0; k < n; ++k) h = (h ^ b[k]) * 0x100000001b3ull;
+    return h;
+}
+
+// Host-side fingerprint of the optics, sensor and optical chain (field by field: no padding bytes).
+uint64_t optics_hash(const pbr_ctx *c)
+{
+    uint64_t h = fnv1a(nullptr, 0);
+    const pbr_optics &o = c->optics;
+    const double od[7] = {o.z_front_vertex, o.focal_length, o.f_number, o.thickness, o.n_glass, o.clear_radius,
+                          o.z_focus};
+    h = fnv1a(od, sizeof od, h);
+    const pbr_sensor &q = c->sensor;
+    const int32_t si[3] = {q.width, q.height, q.dtau_with_pi};
+    const double sd[4] = {q.pitch, q.z_sensor, q.wavelength, q.sigma_px};
+    h = fnv1a(si, sizeof si, h);
+    h = fnv1a(sd, sizeof sd, h);
+    const int32_t chain = c->has_chain ? c->chain.n_surfaces : 0;
+    h = fnv1a(&chain, sizeof chain, h);
+    if (chain) {
+        const double aim[2] = {c->chain.aim_z, c->chain.aim_radius};
+        h = fnv1a(aim, sizeof aim, h);
+        for (int k = 0; k < chain; ++k) {
+            const pbr_surface &f = c->chain.s[k];
+            const double fd[5] = {f.z, f.radius, f.clear, f.n_after, f.pitch};
+            h = fnv1a(&f.type, sizeof f.type, h);
+            h = fnv1a(fd, sizeof fd, h);
+        }
+    }
+    return h;
+}
+
+// What a trained surrogate depends on: the stored field (geometry and a device checksum of its
+// words), the optics and sensor it was validated through, and the step length.
+int scene_key(pbr_ctx *ctx, double ds, pbr_surrogate::SceneKey *k)
+{
+    std::memset(k, 0, sizeof *k);
+    k->nx = ctx->nx; k->ny = ctx->ny; k->nz = ctx->nz;
+    k->node_layout = ctx->layout.nodes;
+    for (int a = 0; a < 3; ++a) { k->origin[a] = ctx->origin[a]; k->spacing[a] = ctx->spacing[a]; }
+    k->K = ctx->K;
+    k->rho_inf = ctx->rho_inf;
+    k->ds = ds;
+    k->optics_hash = optics_hash(ctx);
+    return pbr::host::field_fingerprint(ctx, &k->field_sum);
+}
 
 int sfail(pbr_surrogate *s, int code, const char *fmt, ...)
 {
@@ -159,12 +216,14 @@ int hook_run(void *self, const pbr::TraceParams &P, pbr::RayState *st, int64_t, 
 namespace pbr {
 namespace host {
 
-int surrogate_hook(pbr_ctx *ctx, ChunkHook *out)
+int surrogate_hook(pbr_ctx *ctx, double ds, ChunkHook *out)
 {
     pbr_surrogate *s = ctx->surr;
     if (!s) return fail(ctx, PBR_ERR_STATE, "PBR_SURROGATE set but no surrogate attached (pbr_set_surrogate)");
     if (!s->trained || s->ctx_uid != ctx->uid || s->scene_version != ctx->scene_version)
         return fail(ctx, PBR_ERR_STATE, "the attached surrogate no longer matches this context's field, optics or sensor");
+    if (ds != s->ds)
+        return fail(ctx, PBR_ERR_STATE, "the surrogate was trained for steps of %.6g m, the trace asks for %.6g m", s->ds, ds);
     if (ctx->ray_chunk > s->chunk_cap) {
         // buffers for whole chunks (53 B per ray), kept until the surrogate is destroyed
         DeviceGuard g(s->device);
@@ -673,6 +732,177 @@ int pbr_surrogate_train(pbr_surrogate *s, pbr_ctx *ctx, const float *train_src_d
     report->validate_ms = std::chrono::duration<double, std::milli>(clk::now() - t0).count();
     spec.tile_ok = s->tile_ok_dev;
     s->spec = spec;
+    s->ds = ds;
+    if (int r = scene_key(ctx, ds, &s->key)) return sfail(s, r, "field fingerprint: %s", ctx->err.c_str());
+    s->ctx_uid = ctx->uid;
+    s->scene_version = ctx->scene_version;
+    s->trained = true;
+    return PBR_OK;
+    SURR_GUARD_END
+}
+
+// ------------------------------------------------------------------ save / load
+
+}  // extern "C"
+
+namespace {
+
+const char kBlobMagic[8] = {'P', 'B', 'R', 'S', 'U', 'R', 'R', '1'};
+constexpr uint32_t kBlobVersion = 1;
+
+struct BlobWriter {
+    std::vector<unsigned char> b;
+    void put(const void *p, size_t n) { b.insert(b.end(), (const unsigned char *)p, (const unsigned char *)p + n); }
+    template <typename T> void val(const T &v) { put(&v, sizeof v); }
+};
+
+struct BlobReader {
+    const unsigned char *p;
+    size_t n, at = 0;
+    bool get(void *out, size_t k)
+    {
+        if (k > n - at) return false;
+        std::memcpy(out, p + at, k);
+        at += k;
+        return true;
+    }
+    template <typename T> bool val(T *v) { return get(v, sizeof *v); }
+};
+
+int64_t adam_step(pbr_surrogate *s, int *out)
+{
+    return (int64_t)hipMemcpy(out, s->step, sizeof(int), hipMemcpyDeviceToHost);
+}
+
+// The blob: magic, version, parameter count, scene key, scaling and tile geometry, Adam step, tile
+// map, per-tile validation errors, parameters, Adam moments m and v, then an FNV-1a checksum of all
+// the preceding bytes.
+int build_blob(pbr_surrogate *s, std::vector<unsigned char> *out)
+{
+    const size_t N = (size_t)pbr::kParams;
+    std::vector<float> params(N), m(N), v(N);
+    int step = 0;
+    int e;
+    if ((e = (int)hipStreamSynchronize(s->stream)) ||
+        (e = (int)hipMemcpy(params.data(), s->d.params, N * 4, hipMemcpyDeviceToHost)) ||
+        (e = (int)hipMemcpy(m.data(), s->d.m, N * 4, hipMemcpyDeviceToHost)) ||
+        (e = (int)hipMemcpy(v.data(), s->d.v, N * 4, hipMemcpyDeviceToHost)) || (e = (int)adam_step(s, &step)))
+        return shf(s, e, "copy the trained state");
+    BlobWriter w;
+    w.put(kBlobMagic, 8);
+    w.val(kBlobVersion);
+    w.val((uint32_t)N);
+    w.val(s->key);
+    const pbr::SurrogateSpec &sp = s->spec;
+    const double g[9] = {sp.z_lo, sp.z_hi, sp.x_lo, sp.x_hi, sp.y_lo, sp.y_hi, sp.theta, sp.Lx, sp.Ly};
+    w.put(g, sizeof g);
+    w.put(sp.t_mean, sizeof sp.t_mean);
+    w.put(sp.t_scale, sizeof sp.t_scale);
+    w.val((int32_t)sp.tiles);
+    w.val((int32_t)step);
+    w.put(s->tile_ok.data(), s->tile_ok.size());
+    w.put(s->tile_err.data(), s->tile_err.size() * 4);
+    w.put(params.data(), N * 4);
+    w.put(m.data(), N * 4);
+    w.put(v.data(), N * 4);
+    w.val(fnv1a(w.b.data(), w.b.size()));
+    *out = std::move(w.b);
+    return PBR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t pbr_surrogate_blob_bytes(pbr_surrogate *s)
+{
+    if (!s || !s->trained) return 0;
+    const size_t nt = s->tile_ok.size();
+    return 8 + 4 + 4 + sizeof(s->key) + 9 * 8 + 12 * 4 + 4 + 4 + nt * 5 + 3 * (size_t)pbr::kParams * 4 + 8;
+}
+
+int pbr_surrogate_save(pbr_surrogate *s, void *buf_host, size_t cap)
+{
+    if (!s) return PBR_ERR_ARG;
+    SURR_GUARD_BEGIN
+    if (!s->trained) return sfail(s, PBR_ERR_STATE, "surrogate not trained");
+    if (!buf_host) return sfail(s, PBR_ERR_ARG, "buffer is null");
+    if (cap < pbr_surrogate_blob_bytes(s))
+        return sfail(s, PBR_ERR_WORKSPACE, "blob needs %zu bytes", pbr_surrogate_blob_bytes(s));
+    DeviceGuard g(s->device);
+    if (!g.ok) return sfail(s, PBR_ERR_HIP, "hipSetDevice failed");
+    std::vector<unsigned char> b;
+    if (int r = build_blob(s, &b)) return r;
+    if (b.size() != pbr_surrogate_blob_bytes(s)) return sfail(s, PBR_ERR_HIP, "internal error: blob size");
+    std::memcpy(buf_host, b.data(), b.size());
+    return PBR_OK;
+    SURR_GUARD_END
+}
+
+int pbr_surrogate_load(pbr_surrogate *s, pbr_ctx *ctx, const void *buf_host, size_t size)
+{
+    if (!s) return PBR_ERR_ARG;
+    SURR_GUARD_BEGIN
+    if (!ctx || !buf_host) return sfail(s, PBR_ERR_ARG, "null context or buffer");
+    if (ctx->device < 0) return sfail(s, PBR_ERR_STATE, "host-only context: no device work");
+    if (ctx->device != s->device) return sfail(s, PBR_ERR_ARG, "context and surrogate live on different devices");
+    if (size < 16) return sfail(s, PBR_ERR_ARG, "blob too short");
+    const unsigned char *p = (const unsigned char *)buf_host;
+    uint64_t sum;
+    std::memcpy(&sum, p + size - 8, 8);
+    if (std::memcmp(p, kBlobMagic, 8) != 0) return sfail(s, PBR_ERR_ARG, "not a surrogate blob");
+    if (fnv1a(p, size - 8) != sum) return sfail(s, PBR_ERR_ARG, "blob checksum mismatch (damaged or truncated)");
+    BlobReader r{p, size - 8, 8};
+    uint32_t version = 0, n_params = 0;
+    pbr_surrogate::SceneKey key{};
+    double g[9];
+    pbr::SurrogateSpec sp{};
+    int32_t tiles = 0, step = 0;
+    if (!r.val(&version) || version != kBlobVersion) return sfail(s, PBR_ERR_ARG, "unsupported blob version");
+    if (!r.val(&n_params) || n_params != (uint32_t)pbr::kParams) return sfail(s, PBR_ERR_ARG, "blob holds another network");
+    if (!r.val(&key) || !r.get(g, sizeof g) || !r.get(sp.t_mean, sizeof sp.t_mean) ||
+        !r.get(sp.t_scale, sizeof sp.t_scale) || !r.val(&tiles) || !r.val(&step))
+        return sfail(s, PBR_ERR_ARG, "blob truncated");
+    if (tiles < 1 || tiles > 4096) return sfail(s, PBR_ERR_ARG, "blob: bad tile count");
+    const size_t nt = (size_t)tiles * (size_t)tiles, N = (size_t)pbr::kParams;
+    std::vector<unsigned char> tok(nt);
+    std::vector<float> terr(nt), params(N), m(N), v(N);
+    if (!r.get(tok.data(), nt) || !r.get(terr.data(), nt * 4) || !r.get(params.data(), N * 4) ||
+        !r.get(m.data(), N * 4) || !r.get(v.data(), N * 4) || r.at != r.n)
+        return sfail(s, PBR_ERR_ARG, "blob size does not match its contents");
+    // the context must hold the scene the surrogate was trained on
+    pbr_surrogate::SceneKey here{};
+    if (int rc = scene_key(ctx, key.ds, &here)) return sfail(s, rc, "field fingerprint: %s", ctx->err.c_str());
+    if (std::memcmp(&here, &key, sizeof key) != 0)
+        return sfail(s, PBR_ERR_STATE, "the context's field, optics or sensor differ from the surrogate's training scene");
+    DeviceGuard dg(s->device);
+    if (!dg.ok) return sfail(s, PBR_ERR_HIP, "hipSetDevice failed");
+    int e;
+    if ((e = (int)hipStreamSynchronize(s->stream)) ||
+        (e = (int)hipMemcpy(s->d.params, params.data(), N * 4, hipMemcpyHostToDevice)) ||
+        (e = (int)hipMemcpy(s->d.m, m.data(), N * 4, hipMemcpyHostToDevice)) ||
+        (e = (int)hipMemcpy(s->d.v, v.data(), N * 4, hipMemcpyHostToDevice)) ||
+        (e = (int)hipMemcpy(s->step, &step, sizeof step, hipMemcpyHostToDevice)))
+        return shf(s, e, "copy the trained state");
+    if ((e = pbr::mlp_refresh_shadow(s->d, s->stream)) || (e = (int)hipStreamSynchronize(s->stream)))
+        return shf(s, e, "bf16 weights");
+    if ((int64_t)nt > s->tile_cap) {
+        void *q = nullptr;
+        if ((e = dmalloc(s, &q, nt))) return shf(s, e, "hipMalloc(tile map)");
+        s->tile_ok_dev = (unsigned char *)q;
+        s->tile_cap = (int64_t)nt;
+    }
+    if ((e = (int)hipMemcpy(s->tile_ok_dev, tok.data(), nt, hipMemcpyHostToDevice))) return shf(s, e, "copy tile map");
+    sp.z_lo = g[0]; sp.z_hi = g[1]; sp.x_lo = g[2]; sp.x_hi = g[3]; sp.y_lo = g[4]; sp.y_hi = g[5];
+    sp.theta = g[6]; sp.Lx = g[7]; sp.Ly = g[8];
+    sp.tiles = tiles;
+    pbr::surrogate_spec_finish(sp);
+    sp.tile_ok = s->tile_ok_dev;
+    s->spec = sp;
+    s->tile_ok = std::move(tok);
+    s->tile_err = std::move(terr);
+    s->ds = key.ds;
+    s->key = key;
     s->ctx_uid = ctx->uid;
     s->scene_version = ctx->scene_version;
     s->trained = true;

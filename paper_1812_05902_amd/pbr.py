@@ -48,7 +48,8 @@ EXPORTED = ["pbr_create", "pbr_destroy", "pbr_last_error", "pbr_set_stream",
             "pbr_set_source_sums", "pbr_dot_map_workspace_bytes", "pbr_dot_displacement_map",
             "pbr_bos_theory_map", "pbr_displace_sources", "pbr_mie_table", "pbr_mie_workspace_bytes",
             "pbr_set_mie", "pbr_set_optical_chain", "pbr_field_workspace_bytes_nodes",
-            "pbr_set_density_field_nodes"]
+            "pbr_set_density_field_nodes", "pbr_surrogate_blob_bytes", "pbr_surrogate_save",
+            "pbr_surrogate_load"]
 
 
 class PbrError(RuntimeError):
@@ -201,6 +202,9 @@ def load(path: str = LIB_PATH):
                                     C.POINTER(pbr_surrogate_train_config), C.POINTER(pbr_surrogate_report)]),
         "pbr_surrogate_tile_map": (I, [P, P, P, I64]),
         "pbr_set_surrogate": (I, [P, P]),
+        "pbr_surrogate_blob_bytes": (C.c_size_t, [P]),
+        "pbr_surrogate_save": (I, [P, P, C.c_size_t]),
+        "pbr_surrogate_load": (I, [P, P, P, C.c_size_t]),
         "pbr_probe_u64_atomics": (I, [I, I64, I64, C.POINTER(D)]),
         "pbr_set_source_sums": (I, [P, P, I64]),
         "pbr_dot_map_workspace_bytes": (C.c_size_t, [I, I]),
@@ -767,6 +771,18 @@ def pbr_surrogate_tile_map(sg, tiles):
     return ok.reshape(tiles, tiles), err.reshape(tiles, tiles)
 
 
+def pbr_surrogate_save(sg) -> bytes:
+    n = int(load().pbr_surrogate_blob_bytes(sg))
+    buf = C.create_string_buffer(max(n, 1))
+    _scheck(sg, load().pbr_surrogate_save(sg, buf, n))
+    return buf.raw[:n]
+
+
+def pbr_surrogate_load(sg, ctx, blob: bytes):
+    buf = C.create_string_buffer(bytes(blob), len(blob))
+    _scheck(sg, load().pbr_surrogate_load(sg, ctx, buf, len(blob)))
+
+
 def pbr_set_surrogate(ctx, sg):
     _check(ctx, load().pbr_set_surrogate(ctx, sg))
 
@@ -816,6 +832,19 @@ class Surrogate:
 
     def tile_map(self):
         return pbr_surrogate_tile_map(self.h, self.tiles)
+
+    # offset of the int32 tile count in the blob: magic 8, version 4, parameter count 4, scene key 104,
+    # geometry 9 x 8, scaling 12 x 4
+    _BLOB_TILES_AT = 8 + 4 + 4 + 104 + 72 + 48
+
+    def save(self) -> bytes:
+        """The trained surrogate as a self-checking blob (weights, Adam state, scaling, tile map)."""
+        return pbr_surrogate_save(self.h)
+
+    def load(self, renderer, blob: bytes):
+        """Restores a saved surrogate for ``renderer``, which must hold its training scene."""
+        pbr_surrogate_load(self.h, renderer.ctx, blob)
+        self.tiles = int(np.frombuffer(blob, dtype="<i4", count=1, offset=self._BLOB_TILES_AT)[0])
 
     def attach(self, renderer):
         pbr_set_surrogate(renderer.ctx, self.h)

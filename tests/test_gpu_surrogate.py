@@ -201,6 +201,43 @@ def test_surrogate_gain_over_the_tracer(torch, trained):
     assert min(s_ms) < 0.8 * min(t_ms)
 
 
+def test_save_and_load(torch, trained):
+    """A saved surrogate loaded into a fresh context of the same scene gives the same parameters,
+    tile map and image bit for bit; another field, a damaged blob or another step length is refused."""
+    sc, r, s, rep = trained
+    blob = s.save()
+    r2 = _tiny_renderer(sc, chunk=1 << 22)
+    s2 = pbr.Surrogate(max_rows=1 << 16)
+    s2.load(r2, blob)
+    assert np.array_equal(s2.params(), s.params())
+    assert np.array_equal(s2.tile_map()[0], s.tile_map()[0])
+    assert np.array_equal(s2.tile_map()[1], s.tile_map()[1])
+    assert s2.save() == blob
+    s.attach(r)
+    s2.attach(r2)
+    ev = inputs.sources(sc.replace(n_src=2000, src_seed=506))
+    st1 = r.emit_and_trace(ev, 100, 51, sc.ds, pbr.PBR_CLEAR_FIRST | pbr.PBR_SURROGATE, stats=True)
+    st2 = r2.emit_and_trace(ev, 100, 51, sc.ds, pbr.PBR_CLEAR_FIRST | pbr.PBR_SURROGATE, stats=True)
+    assert st1["surrogate_rays"] == st2["surrogate_rays"] > 0
+    assert np.array_equal(r.read_image().cpu().numpy(), r2.read_image().cpu().numpy())
+    print(f"blob {len(blob)} bytes; {st2['surrogate_rays']} rays through the loaded surrogate, same image")
+    with pytest.raises(pbr.PbrError, match="steps of"):
+        r2.emit_and_trace(ev, 100, 51, 2 * sc.ds, pbr.PBR_CLEAR_FIRST | pbr.PBR_SURROGATE)
+    bad = bytearray(blob)
+    bad[len(bad) // 2] ^= 1
+    s3 = pbr.Surrogate(max_rows=1024)
+    with pytest.raises(pbr.PbrError, match="checksum"):
+        s3.load(r2, bytes(bad))
+    with pytest.raises(pbr.PbrError, match="not a surrogate"):
+        s3.load(r2, b"x" * 64)
+    other = sc.replace(field_params=dict(sc.field_params, amp=0.11))
+    r3 = _tiny_renderer(other)
+    with pytest.raises(pbr.PbrError, match="differ"):
+        s3.load(r3, blob)
+    for x in (s2, s3, r2, r3):
+        x.close()
+
+
 def test_scene_change_invalidates_the_surrogate(torch, trained):
     sc, r, s, rep = trained
     s.attach(r)
