@@ -189,9 +189,10 @@ size_t pbr_field_workspace_bytes(int nx, int ny, int nz);
  * of the trilinear interpolant of these four quantities (128 bytes per cell) into ws_dev
  * (ws_bytes >= pbr_field_workspace_bytes, 16-byte aligned).  rho_dev may be released once the
  * stream has passed this call; ws_dev must live as long as the context traces with this field.
- * Outside the box the index is 1 + K rho_inf with no gradient.
+ * Outside the box the index is 1 + K rho_inf with no gradient.  The density values are checked on
+ * the device first (the call synchronises the stream for that check).
  * Errors: ARG (null, dims < 2 or > 65535, more than 2^31 - 1 cells, spacing <= 0, K < 0,
- * non-finite origin/spacing/K/rho_inf), WORKSPACE. */
+ * non-finite origin/spacing/K/rho_inf, a non-finite density value), WORKSPACE, HIP. */
 int pbr_set_density_field(pbr_ctx *ctx, const float *rho_dev, int nx, int ny, int nz,
                           const double origin[3], const double spacing[3], double K,
                           double rho_inf, void *ws_dev, size_t ws_bytes);

@@ -117,6 +117,17 @@ __global__ void __launch_bounds__(256) k_checksum(const unsigned *__restrict__ w
         __hip_atomic_fetch_add(out, acc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Sets *bad when any density value is not finite.
+__global__ void __launch_bounds__(256) k_check_finite(const float *__restrict__ rho, int64_t n,
+                                                      unsigned long long *__restrict__ bad)
+{
+    bool ok = true;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) ok = ok && isfinite(rho[k]);
+    if (__ballot(!ok) != 0ull && (threadIdx.x & 63u) == 0)
+        __hip_atomic_fetch_add(bad, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __global__ void __launch_bounds__(256) k_clear_u64(unsigned long long *p, int64_t n)
 {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -148,6 +159,16 @@ int launch_field_checksum(const void *field, size_t bytes, unsigned long long *o
     int64_t blocks = (n + 255) / 256;
     if (blocks > 8192) blocks = 8192;
     hipLaunchKernelGGL(k_checksum, dim3((unsigned)blocks), dim3(256), 0, stream, (const unsigned *)field, n, out);
+    return (int)hipGetLastError();
+}
+
+int launch_check_finite(const float *rho, int64_t n, unsigned long long *bad, hipStream_t stream)
+{
+    int e = launch_clear_u64(bad, 1, stream);
+    if (e || n <= 0) return e;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_check_finite, dim3((unsigned)blocks), dim3(256), 0, stream, rho, n, bad);
     return (int)hipGetLastError();
 }
 

@@ -151,9 +151,13 @@ int field_fingerprint(pbr_ctx *ctx, uint64_t *out)
     if (ctx->device < 0) return fail(ctx, PBR_ERR_STATE, "host-only context: no device work");
     DeviceGuard g(ctx->device);
     if (!g.ok) return fail(ctx, PBR_ERR_HIP, "hipSetDevice failed");
-    // the counter block's spare slot after the queue holds the sum
+    // the counter block's spare slot after the queue holds the sum; only the bytes the field
+    // preparation writes (not the alignment padding of the caller's workspace)
     unsigned long long *slot = ctx->counters + pbr::CNT_QUEUE + 1;
-    int e = pbr::launch_field_checksum(ctx->cells, ctx->layout.gmax_off, slot, ctx->stream);
+    const size_t bytes = ctx->layout.nodes ? (size_t)ctx->nx * (size_t)ctx->ny * (size_t)ctx->nz * 16
+                                           : (size_t)(ctx->nx - 1) * (size_t)(ctx->ny - 1) * (size_t)(ctx->nz - 1) *
+                                                 pbr::kCellFloat4 * 16;
+    int e = pbr::launch_field_checksum(ctx->cells, bytes, slot, ctx->stream);
     unsigned long long h = 0;
     if (!e) e = (int)hipMemcpyAsync(&h, slot, 8, hipMemcpyDeviceToHost, ctx->stream);
     if (!e) e = (int)hipStreamSynchronize(ctx->stream);
@@ -323,6 +327,15 @@ int set_field(pbr_ctx *ctx, const float *rho_dev, int nx, int ny, int nz, const 
     if (ctx->device >= 0) {
         DeviceGuard g(ctx->device);
         if (!g.ok) return fail(ctx, PBR_ERR_HIP, "hipSetDevice failed");
+        // every density value must be finite: checked on the device before anything is prepared
+        {
+            unsigned long long *slot = ctx->counters + pbr::CNT_QUEUE + 2, bad = 0;
+            int e = pbr::launch_check_finite(rho_dev, (int64_t)nx * ny * nz, slot, ctx->stream);
+            if (!e) e = (int)hipMemcpyAsync(&bad, slot, 8, hipMemcpyDeviceToHost, ctx->stream);
+            if (!e) e = (int)hipStreamSynchronize(ctx->stream);
+            if (e) return hip_fail(ctx, e, "density check");
+            if (bad) return fail(ctx, PBR_ERR_ARG, "the density grid holds non-finite values");
+        }
         // brick max |grad n| and FP64 flags start at zero (fill kernel, no memset node)
         int e = pbr::launch_clear_u64((unsigned long long *)(base + L.gmax_off),
                                       (int64_t)((L.total - L.gmax_off) / 8), ctx->stream);

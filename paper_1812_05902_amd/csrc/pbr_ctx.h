@@ -96,6 +96,8 @@ int field_fingerprint(pbr_ctx *ctx, uint64_t *out);
 
 }  // namespace host
 
+// Counts into *bad (device) the waves that saw a non-finite density value, field_prep.hip.
+int launch_check_finite(const float *rho, int64_t n, unsigned long long *bad, hipStream_t stream);
 // Order-independent checksum of a device buffer's 32-bit words into *out (device), field_prep.hip.
 int launch_field_checksum(const void *field, size_t bytes, unsigned long long *out, hipStream_t stream);
 

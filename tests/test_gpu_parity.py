@@ -216,3 +216,19 @@ def test_lane_refill_equals_one_thread_per_ray(torch, make):
     for f in pbr.RAY_EXIT_DTYPE.names:
         assert np.array_equal(rec_a[f], rec_b[f]), f
     assert st_a["status"] == st_b["status"] and st_a["rkn_steps"] == st_b["rkn_steps"]
+
+
+def test_non_finite_density_is_refused(torch):
+    """A NaN or an infinity anywhere in the density grid fails pbr_set_density_field (both
+    layouts) and leaves no field set."""
+    sc = inputs.tiny_bos()
+    for bad in (float("nan"), float("inf")):
+        rho = inputs.density(sc).copy()
+        rho[17, 3, 29] = bad
+        for nodes in (False, True):
+            r = pbr.Renderer()
+            with pytest.raises(pbr.PbrError, match="non-finite"):
+                r.set_density_field(rho, sc.origin, sc.spacing, sc.K, sc.rho_inf, nodes=nodes)
+            with pytest.raises(pbr.PbrError):
+                r.derived()
+            r.close()
