@@ -108,7 +108,7 @@ def main():
                     help="field stored per cell (128 B) or per node (16 B); auto takes the faster measured "
                          "one per workload")
     ap.add_argument("--rays-per-chunk", type=int, default=1 << 24,
-                    help="turbulence_bos_128: rays per trace chunk (64 bytes of ray state each)")
+                    help="turbulence_bos_128 / surrogate256: rays per trace chunk (64 bytes of ray state each)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy a 1 GiB device buffer 4 times (calibrates HBM byte counters)")
     ap.add_argument("--atomic-probe", action="store_true",
@@ -485,7 +485,7 @@ def bench_surrogate(args):
     ev, tr, va = inputs.surrogate_turbulence()
     t0 = time.perf_counter()
     rho = inputs.density(ev)
-    r = pbr.Renderer.from_scene(ev, rho=rho)
+    r = pbr.Renderer.from_scene(ev, rho=rho, rays_per_chunk=args.rays_per_chunk)
     src_ev = torch.as_tensor(inputs.sources(ev), device=r.device).contiguous()
     src_tr = inputs.sources(tr)
     src_va = inputs.sources(va)
