@@ -27,10 +27,6 @@ __device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t k)
     return z ^ (z >> 31);
 }
 
-template <typename F> __device__ __forceinline__ F ffloor(F x);
-template <> __device__ __forceinline__ float ffloor<float>(float x) { return floorf(x); }
-template <> __device__ __forceinline__ double ffloor<double>(double x) { return floor(x); }
-
 // x clamped to [0, hi] in one instruction (for a bound that is not a constant the compiler emits a
 // max and a min); hi is uniform across the wave.
 __device__ __forceinline__ int clamp_index(int x, int hi)
@@ -38,6 +34,24 @@ __device__ __forceinline__ int clamp_index(int x, int hi)
     int r;
     asm("v_med3_i32 %0, %1, 0, %2" : "=v"(r) : "v"(x), "s"(hi));
     return r;
+}
+
+// A stage-point coordinate x (cell units, relative to the ray's cell) split into the whole cells it
+// lies ahead, floor(x), and the fraction x - floor(x) inside that cell.  For float two instructions
+// (v_cvt_flr_i32_f32 saturates out-of-range values; v_fract_f32 keeps the fraction below 1).
+template <typename F> __device__ __forceinline__ int split_cell(F x, F &t);
+template <> __device__ __forceinline__ int split_cell<float>(float x, float &t)
+{
+    int o;
+    asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(o) : "v"(x));
+    t = __builtin_amdgcn_fractf(x);
+    return o;
+}
+template <> __device__ __forceinline__ int split_cell<double>(double x, double &t)
+{
+    const double o = floor(x);
+    t = x - o;
+    return (int)o;
 }
 
 // Node layout: the eight corners (n - 1, grad n) of cell ic, turned into the coefficients of the
@@ -69,14 +83,15 @@ struct CellCache {
 
 // Trilinear interpolation of (n - 1, grad n) at the point (cell c, fraction f); the fraction may
 // lie outside [0, 1) (stage points of eq. 5), in which case the point is moved into the cell that
-// holds it and then onto the box.  Returns n, writes D = n grad n (eq. 6).
+// holds it and then onto the box.  Returns n, writes G = grad n (D = n G, eq. 6, is formed by the
+// caller, folded into the step's sums).
 // INSIDE: the caller has shown that the point lies inside the box and that the ray's own cell index
 // is a cell of the grid (see trace_step), so the edge extension is left out; the cell index is still
 // clamped to the grid, which keeps every gather in bounds whatever the values.
 // NODES: the field is stored per node (see gather_nodes); compiled into dedicated kernels only.
 template <typename F, bool AT_STATE = false, bool INSIDE = false, bool NODES = false>
-__device__ __forceinline__ F sample_D(const TraceParams &P, CellCache &cc, const int c[3],
-                                      const F f[3], F D[3])
+__device__ __forceinline__ F sample_field(const TraceParams &P, CellCache &cc, const int c[3],
+                                          const F f[3], F G[3])
 {
     const int nmax[3] = {P.nx - 2, P.ny - 2, P.nz - 2};
     int ic[3];
@@ -90,11 +105,10 @@ __device__ __forceinline__ F sample_D(const TraceParams &P, CellCache &cc, const
             i0 = c[a];
             t = f[a];
         } else {
-            // stage point: fraction anywhere; NaN becomes finite (fmax/fmin return the number)
-            const F fa = fmin(fmax(f[a], (F)(-1.0e6)), (F)(1.0e6));
-            const F o = ffloor<F>(fa);
-            i0 = c[a] + (int)o;
-            t = fa - o;
+            // stage point: fraction anywhere.  Inside the box the point is finite (see trace_step);
+            // elsewhere NaN becomes finite first (fmax/fmin return the number)
+            const F fa = INSIDE ? f[a] : fmin(fmax(f[a], (F)(-1.0e6)), (F)(1.0e6));
+            i0 = c[a] + split_cell<F>(fa, t);
         }
         const int i = INSIDE ? clamp_index(i0, nmax[a]) : min(max(i0, 0), nmax[a]);
         if (!INSIDE) {
@@ -131,39 +145,50 @@ __device__ __forceinline__ F sample_D(const TraceParams &P, CellCache &cc, const
     PBR_TRI(z, v[2]);
     PBR_TRI(w, v[3]);
 #undef PBR_TRI
-    const F n = (F)1 + v[0];
-    D[0] = n * v[1];
-    D[1] = n * v[2];
-    D[2] = n * v[3];
-    return n;
+    G[0] = v[1];
+    G[1] = v[2];
+    G[2] = v[3];
+    return (F)1 + v[0];
 }
 
 // One step of eqs. 3 and 5 of length lam * h in the parameter t (dR/dt = T, dT/dt = D), in
 // cell units: g[a] = h / spacing[a].  The cell fraction fd is accumulated in FP64: its increment
 // is nearly the same every step, so FP32 rounding of the running sum would err the same way
 // every step and grow linearly with the step count.  Stage points are formed in F.
+// With D_A, D_B, D_C the values of D = n grad n at the three stage points, so that eq. 5's
+// A = h D_A, B = h D_B, C = h D_C, the sums are regrouped without forming A, B, C:
+//   stage B point  R + (h/2) (T + (h/4) D_A)        (= R + h (T/2 + A/8))
+//   stage C point  R + h (T + (h/2) D_B)            (= R + h (T + B/2))
+//   R'             R + h (T + (h/6) (D_A + 2 D_B))  (= R + h (T + (A + 2B)/6))
+//   T'             T + (h/6) (D_A + 4 D_B + D_C)    (= T + (A + 4B + C)/6)
+// A partial step (lam = 1) and a full step form the same constants and give the same bits.
 // INSIDE: every point of the step is known to lie inside the box (full steps only).
 template <typename F, bool FULL, bool INSIDE = false, bool NODES = false>
 __device__ __forceinline__ void rkn_step(const TraceParams &P, CellCache &cc, int c[3], double fd[3],
                                          const F Tr[3], F dT[3], const F g[3], F hstep, F lam)
 {
     const F hh = FULL ? hstep : lam * hstep;
-    F f[3], gg[3], T[3], A[3], B[3], C[3], q[3], D[3];
+    const F h4 = (F)0.25 * hh, h2 = (F)0.5 * hh, h6 = hh * ((F)1 / (F)6);
+    F f[3], gg[3], T[3], G[3], q[3], DA[3], DB[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) { f[a] = (F)fd[a]; gg[a] = FULL ? g[a] : lam * g[a]; T[a] = Tr[a] + dT[a]; }
-    sample_D<F, true, INSIDE, NODES>(P, cc, c, f, D);
-#pragma unroll
-    for (int a = 0; a < 3; ++a) { A[a] = hh * D[a]; q[a] = f[a] + gg[a] * ((F)0.5 * T[a] + (F)0.125 * A[a]); }
-    sample_D<F, false, INSIDE, NODES>(P, cc, c, q, D);
-#pragma unroll
-    for (int a = 0; a < 3; ++a) { B[a] = hh * D[a]; q[a] = f[a] + gg[a] * (T[a] + (F)0.5 * B[a]); }
-    sample_D<F, false, INSIDE, NODES>(P, cc, c, q, D);
-    const F sixth = (F)1 / (F)6;
+    F n = sample_field<F, true, INSIDE, NODES>(P, cc, c, f, G);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        C[a] = hh * D[a];
-        fd[a] += (double)(gg[a] * (T[a] + (A[a] + (F)2 * B[a]) * sixth));
-        dT[a] = dT[a] + (A[a] + (F)4 * B[a] + C[a]) * sixth;
+        DA[a] = n * G[a];
+        q[a] = f[a] + ((F)0.5 * gg[a]) * (T[a] + h4 * DA[a]);
+    }
+    n = sample_field<F, false, INSIDE, NODES>(P, cc, c, q, G);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        DB[a] = n * G[a];
+        q[a] = f[a] + gg[a] * (T[a] + h2 * DB[a]);
+    }
+    n = sample_field<F, false, INSIDE, NODES>(P, cc, c, q, G);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        fd[a] += (double)(gg[a] * (T[a] + h6 * (DA[a] + (F)2 * DB[a])));
+        dT[a] = dT[a] + h6 * (n * G[a] + (DA[a] + (F)4 * DB[a]));
         const double o = floor(fd[a]);
         c[a] += (int)o;
         fd[a] -= o;
@@ -185,25 +210,55 @@ enum : int { STEP_GO = 0, STEP_EXIT = 1, STEP_LIMIT = 2 };
 // a face the ray moves towards) the partial step of fraction lam and, if the ray still heads out,
 // the straight move onto that face.  Returns STEP_EXIT when the ray left the box, STEP_LIMIT when
 // it ran out of steps, STEP_GO otherwise.
-// A full step whose straight line ends more than kFaceMargin cells inside every face is taken
-// without the edge extension: its stage points stay inside the box (they leave the straight line
-// by h^2 |D| / 2 in the step parameter, about 1e-7 cells at the fields here).  Every other step goes
-// through the exit rule and the edge-extended sampling (a full step there, at fraction 1, gives
-// the same bits as the inside one wherever both apply).
+// A full step taken by a ray in an interior cell (index 1 .. n-3 on every axis; there the fraction
+// is in [0, 1], as emission and both step paths leave it) that moves it less than
+// 1 - 4 kFaceMargin cells on every axis (|T| components <= tlim) ends at least 2 kFaceMargin cells
+// inside every face, so it is taken without the edge extension: its stage points stay inside the
+// box (they leave the straight line by h^2 |D| / 2 in the step parameter, about 1e-7 cells at the
+// fields here).  The test is integer compares and one maximum.  Every other step (a ray in a cell
+// on the boundary of the grid) goes through the exit rule and the edge-extended sampling; a full
+// step there, at fraction 1, gives the same bits as the inside one wherever both apply.
 constexpr float kFaceMargin = 1.0e-3f;
+
+// Per-launch constants of the integration loop.
+template <typename F> struct StepGeom {
+    F g[3];            // h / spacing
+    F hstep;           // h
+    int last[3];       // n - 1 per axis (the upper face, in cells)
+    unsigned bnd[3];   // max(n - 3, 0): interior cells are 1 <= c < 1 + bnd
+    F tlim;            // largest |T| component for which a full step stays under 1 - 4 kFaceMargin cells
+};
+
+template <typename F> __device__ __forceinline__ StepGeom<F> step_geom(const TraceParams &P)
+{
+    StepGeom<F> s;
+    const int nn[3] = {P.nx, P.ny, P.nz};
+    F gmax = (F)0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        s.g[a] = (F)P.step_cell[a];
+        s.last[a] = nn[a] - 1;
+        s.bnd[a] = (unsigned)max(nn[a] - 3, 0);
+        gmax = fmax(gmax, s.g[a]);
+    }
+    s.hstep = (F)P.h;
+    s.tlim = gmax > (F)0 ? ((F)1 - (F)4 * (F)kFaceMargin) / gmax : (F)0;
+    return s;
+}
 
 template <typename F, bool NODES = false>
 __device__ __forceinline__ int trace_step(const TraceParams &P, CellCache &cc, int c[3], double fd[3], const F Tr[3],
-                                          F dT[3], const F g[3], F hstep, const int last[3], int &steps)
+                                          F dT[3], const StepGeom<F> &sg, int &steps)
 {
-    // cheap test first: does the straight line of a full step end inside the box with margin?
-    // (bitwise, not short-circuit: one branch for the whole test; a NaN counts as outside)
-    bool inside = true;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const F e = ((F)c[a] + (F)fd[a]) + g[a] * (Tr[a] + dT[a]);
-        inside = inside & (e > (F)kFaceMargin) & (e < (F)last[a] - (F)kFaceMargin);
-    }
+    const F *g = sg.g;
+    const F hstep = sg.hstep;
+    const int *last = sg.last;
+    // bitwise, not short-circuit: one branch for the whole test.  A direction that is all NaN fails;
+    // one with a NaN next to finite components may pass (fmax returns the number), and its step then
+    // stays in bounds through the clamped cell indices.
+    const F Tm = fmax(fmax(fabs(Tr[0] + dT[0]), fabs(Tr[1] + dT[1])), fabs(Tr[2] + dT[2]));
+    const bool inside = ((unsigned)(c[0] - 1) < sg.bnd[0]) & ((unsigned)(c[1] - 1) < sg.bnd[1]) &
+                        ((unsigned)(c[2] - 1) < sg.bnd[2]) & (Tm <= sg.tlim);
     if (inside) {
         rkn_step<F, true, true, NODES>(P, cc, c, fd, Tr, dT, g, hstep, (F)1);
         return ++steps > P.max_steps ? STEP_LIMIT : STEP_GO;
@@ -261,12 +316,10 @@ template <typename F, bool NODES = false>
 __device__ __forceinline__ int trace_box(const TraceParams &P, CellCache &cc, int c[3], double fd[3],
                                          const F Tr[3], F dT[3], bool *limited)
 {
-    const F g[3] = {(F)P.step_cell[0], (F)P.step_cell[1], (F)P.step_cell[2]};
-    const F hstep = (F)P.h;
-    const int last[3] = {P.nx - 1, P.ny - 1, P.nz - 1};
+    const StepGeom<F> sg = step_geom<F>(P);
     int steps = 0;
     for (;;) {
-        const int r = trace_step<F, NODES>(P, cc, c, fd, Tr, dT, g, hstep, last, steps);
+        const int r = trace_step<F, NODES>(P, cc, c, fd, Tr, dT, sg, steps);
         if (r != STEP_GO) {
             *limited = r == STEP_LIMIT;
             return steps;
@@ -538,9 +591,9 @@ __device__ __forceinline__ void emit_ray(const TraceParams &P, int64_t rid, RayS
     // inside: T = n dR/ds = n u (eq. 4), n interpolated at the entry point
     CellCache cc;
     cc.ix = -1;
-    float D0[3];
-    const float n0 = P.node_layout ? sample_D<float, false, false, true>(P, cc, r.c, f, D0)
-                                   : sample_D<float>(P, cc, r.c, f, D0);
+    float G0[3];
+    const float n0 = P.node_layout ? sample_field<float, false, false, true>(P, cc, r.c, f, G0)
+                                   : sample_field<float>(P, cc, r.c, f, G0);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {  // T0 as a float hi/lo pair: no rounding of the entry direction
         const double T0 = (double)n0 * u[a];
@@ -650,9 +703,7 @@ __global__ void __launch_bounds__(256, 5) k_box32_refill(TraceParams P, RayState
     if (P.node_layout) return;  // cell records only (the host never launches it otherwise)
     const int lane = threadIdx.x & 63;
     const unsigned long long total = list ? *count : (unsigned long long)n;
-    const float g[3] = {(float)P.step_cell[0], (float)P.step_cell[1], (float)P.step_cell[2]};
-    const float hstep = (float)P.h;
-    const int last[3] = {P.nx - 1, P.ny - 1, P.nz - 1};
+    const StepGeom<float> sg = step_geom<float>(P);
     int64_t i = -1;  // this lane's ray, -1: none
     RayState r;
     float Tr[3], dT[3];
@@ -685,7 +736,7 @@ __global__ void __launch_bounds__(256, 5) k_box32_refill(TraceParams P, RayState
         }
         if (__ballot(i >= 0) == 0) break;  // queue drained and no lane busy
         if (i >= 0) {
-            const int res = trace_step<float>(P, cc, r.c, r.fd, Tr, dT, g, hstep, last, steps);
+            const int res = trace_step<float>(P, cc, r.c, r.fd, Tr, dT, sg, steps);
             if (res != STEP_GO) {
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
@@ -871,8 +922,8 @@ __global__ void __launch_bounds__(256) k_calibrate(TraceParams P, const int *__r
     for (int a = 0; a < 3; ++a) u[a] *= il;
     CellCache cc;
     cc.ix = -1;
-    float D0[3];
-    const float n0 = sample_D<float>(P, cc, c, f, D0);
+    float G0[3];
+    const float n0 = sample_field<float>(P, cc, c, f, G0);
     // FP32
     int c32[3] = {c[0], c[1], c[2]};
     double fd32[3] = {fd[0], fd[1], fd[2]};
