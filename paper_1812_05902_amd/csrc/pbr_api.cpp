@@ -127,6 +127,19 @@ void fill_params(const pbr_ctx *ctx, const Derived &d, double ds, TraceParams *o
         P.hi[a] = ctx->origin[a] + (double)(n3[a] - 1) * ctx->spacing[a];
         P.step_cell[a] = P.h / ctx->spacing[a];
     }
+    // FP32 step constants (see TraceParams): each a float operation on float values, so that a
+    // partial step of fraction 1 forms the same bits on the device
+    float gmax = 0.0f;
+    for (int a = 0; a < 3; ++a) {
+        P.g32[a] = (float)P.step_cell[a];
+        P.gh32[a] = 0.5f * P.g32[a];
+        gmax = P.g32[a] > gmax ? P.g32[a] : gmax;
+    }
+    P.h32 = (float)P.h;
+    P.h4_32 = 0.25f * P.h32;
+    P.h2_32 = 0.5f * P.h32;
+    P.h6_32 = P.h32 * (1.0f / 6.0f);
+    P.tlim32 = gmax > 0.0f ? (1.0f - 4.0e-3f) / gmax : 0.0f;
     P.n_inf = d.n_inf;
     P.z_lens = ctx->has_chain ? ctx->chain.aim_z : ctx->optics.z_front_vertex;
     P.a = d.a; P.R = d.R; P.t = d.t; P.clear = d.clear; P.n_glass = ctx->optics.n_glass;

@@ -110,7 +110,8 @@ __device__ __forceinline__ F sample_field(const TraceParams &P, CellCache &cc, c
             const F fa = INSIDE ? f[a] : fmin(fmax(f[a], (F)(-1.0e6)), (F)(1.0e6));
             i0 = c[a] + split_cell<F>(fa, t);
         }
-        const int i = INSIDE ? clamp_index(i0, nmax[a]) : min(max(i0, 0), nmax[a]);
+        // (an inside step starts in an interior cell, so its own index needs no clamp)
+        const int i = INSIDE ? (AT_STATE ? i0 : clamp_index(i0, nmax[a])) : min(max(i0, 0), nmax[a]);
         if (!INSIDE) {
             t = i0 < 0 ? (F)0 : t;
             t = i0 > nmax[a] ? (F)1 : t;
@@ -151,6 +152,59 @@ __device__ __forceinline__ F sample_field(const TraceParams &P, CellCache &cc, c
     return (F)1 + v[0];
 }
 
+// Margin (cells) that a full step taken without the edge extension keeps from every face.
+constexpr float kFaceMargin = 1.0e-3f;
+
+// Per-launch constants of the integration loop.
+template <typename F> struct StepGeom {
+    F g[3], gh[3];     // h / spacing (cell units per unit of T in a full step), half of it
+    F hstep, h4, h2, h6;  // h, h / 4, h / 2, h * (1/6)
+    int last[3];       // n - 1 per axis (the upper face, in cells)
+    unsigned bnd[3];   // max(n - 3, 0): interior cells are 1 <= c < 1 + bnd
+    F tlim;            // largest |T| component for which a full step stays under 1 - 4 kFaceMargin cells
+};
+
+template <typename F> __device__ __forceinline__ StepGeom<F> step_geom(const TraceParams &P);
+// FP32: the constants the host rounded once (uniform: scalar registers)
+template <> __device__ __forceinline__ StepGeom<float> step_geom<float>(const TraceParams &P)
+{
+    StepGeom<float> s;
+    const int nn[3] = {P.nx, P.ny, P.nz};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        s.g[a] = P.g32[a];
+        s.gh[a] = P.gh32[a];
+        s.last[a] = nn[a] - 1;
+        s.bnd[a] = (unsigned)max(nn[a] - 3, 0);
+    }
+    s.hstep = P.h32;
+    s.h4 = P.h4_32;
+    s.h2 = P.h2_32;
+    s.h6 = P.h6_32;
+    s.tlim = P.tlim32;
+    return s;
+}
+template <> __device__ __forceinline__ StepGeom<double> step_geom<double>(const TraceParams &P)
+{
+    StepGeom<double> s;
+    const int nn[3] = {P.nx, P.ny, P.nz};
+    double gmax = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        s.g[a] = P.step_cell[a];
+        s.gh[a] = 0.5 * s.g[a];
+        s.last[a] = nn[a] - 1;
+        s.bnd[a] = (unsigned)max(nn[a] - 3, 0);
+        gmax = fmax(gmax, s.g[a]);
+    }
+    s.hstep = P.h;
+    s.h4 = 0.25 * P.h;
+    s.h2 = 0.5 * P.h;
+    s.h6 = P.h * (1.0 / 6.0);
+    s.tlim = gmax > 0.0 ? (1.0 - 4.0 * (double)kFaceMargin) / gmax : 0.0;
+    return s;
+}
+
 // One step of eqs. 3 and 5 of length lam * h in the parameter t (dR/dt = T, dT/dt = D), in
 // cell units: g[a] = h / spacing[a].  The cell fraction fd is accumulated in FP64: its increment
 // is nearly the same every step, so FP32 rounding of the running sum would err the same way
@@ -165,18 +219,24 @@ __device__ __forceinline__ F sample_field(const TraceParams &P, CellCache &cc, c
 // INSIDE: every point of the step is known to lie inside the box (full steps only).
 template <typename F, bool FULL, bool INSIDE = false, bool NODES = false>
 __device__ __forceinline__ void rkn_step(const TraceParams &P, CellCache &cc, int c[3], double fd[3],
-                                         const F Tr[3], F dT[3], const F g[3], F hstep, F lam)
+                                         const F Tr[3], F dT[3], const StepGeom<F> &sg, F lam)
 {
-    const F hh = FULL ? hstep : lam * hstep;
-    const F h4 = (F)0.25 * hh, h2 = (F)0.5 * hh, h6 = hh * ((F)1 / (F)6);
-    F f[3], gg[3], T[3], G[3], q[3], DA[3], DB[3];
+    const F hh = FULL ? sg.hstep : lam * sg.hstep;
+    const F h4 = FULL ? sg.h4 : (F)0.25 * hh, h2 = FULL ? sg.h2 : (F)0.5 * hh;
+    const F h6 = FULL ? sg.h6 : hh * ((F)1 / (F)6);
+    F f[3], gg[3], gh[3], T[3], G[3], q[3], DA[3], DB[3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) { f[a] = (F)fd[a]; gg[a] = FULL ? g[a] : lam * g[a]; T[a] = Tr[a] + dT[a]; }
+    for (int a = 0; a < 3; ++a) {
+        f[a] = (F)fd[a];
+        gg[a] = FULL ? sg.g[a] : lam * sg.g[a];
+        gh[a] = FULL ? sg.gh[a] : (F)0.5 * gg[a];
+        T[a] = Tr[a] + dT[a];
+    }
     F n = sample_field<F, true, INSIDE, NODES>(P, cc, c, f, G);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         DA[a] = n * G[a];
-        q[a] = f[a] + ((F)0.5 * gg[a]) * (T[a] + h4 * DA[a]);
+        q[a] = f[a] + gh[a] * (T[a] + h4 * DA[a]);
     }
     n = sample_field<F, false, INSIDE, NODES>(P, cc, c, q, G);
 #pragma unroll
@@ -218,40 +278,11 @@ enum : int { STEP_GO = 0, STEP_EXIT = 1, STEP_LIMIT = 2 };
 // fields here).  The test is integer compares and one maximum.  Every other step (a ray in a cell
 // on the boundary of the grid) goes through the exit rule and the edge-extended sampling; a full
 // step there, at fraction 1, gives the same bits as the inside one wherever both apply.
-constexpr float kFaceMargin = 1.0e-3f;
-
-// Per-launch constants of the integration loop.
-template <typename F> struct StepGeom {
-    F g[3];            // h / spacing
-    F hstep;           // h
-    int last[3];       // n - 1 per axis (the upper face, in cells)
-    unsigned bnd[3];   // max(n - 3, 0): interior cells are 1 <= c < 1 + bnd
-    F tlim;            // largest |T| component for which a full step stays under 1 - 4 kFaceMargin cells
-};
-
-template <typename F> __device__ __forceinline__ StepGeom<F> step_geom(const TraceParams &P)
-{
-    StepGeom<F> s;
-    const int nn[3] = {P.nx, P.ny, P.nz};
-    F gmax = (F)0;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        s.g[a] = (F)P.step_cell[a];
-        s.last[a] = nn[a] - 1;
-        s.bnd[a] = (unsigned)max(nn[a] - 3, 0);
-        gmax = fmax(gmax, s.g[a]);
-    }
-    s.hstep = (F)P.h;
-    s.tlim = gmax > (F)0 ? ((F)1 - (F)4 * (F)kFaceMargin) / gmax : (F)0;
-    return s;
-}
-
 template <typename F, bool NODES = false>
 __device__ __forceinline__ int trace_step(const TraceParams &P, CellCache &cc, int c[3], double fd[3], const F Tr[3],
                                           F dT[3], const StepGeom<F> &sg, int &steps)
 {
     const F *g = sg.g;
-    const F hstep = sg.hstep;
     const int *last = sg.last;
     // bitwise, not short-circuit: one branch for the whole test.  A direction that is all NaN fails;
     // one with a NaN next to finite components may pass (fmax returns the number), and its step then
@@ -259,8 +290,8 @@ __device__ __forceinline__ int trace_step(const TraceParams &P, CellCache &cc, i
     const F Tm = fmax(fmax(fabs(Tr[0] + dT[0]), fabs(Tr[1] + dT[1])), fabs(Tr[2] + dT[2]));
     const bool inside = ((unsigned)(c[0] - 1) < sg.bnd[0]) & ((unsigned)(c[1] - 1) < sg.bnd[1]) &
                         ((unsigned)(c[2] - 1) < sg.bnd[2]) & (Tm <= sg.tlim);
-    if (inside) {
-        rkn_step<F, true, true, NODES>(P, cc, c, fd, Tr, dT, g, hstep, (F)1);
+    if (__builtin_expect(inside, 1)) {
+        rkn_step<F, true, true, NODES>(P, cc, c, fd, Tr, dT, sg, (F)1);
         return ++steps > P.max_steps ? STEP_LIMIT : STEP_GO;
     }
     F lam = (F)3.0e38;
@@ -277,7 +308,7 @@ __device__ __forceinline__ int trace_step(const TraceParams &P, CellCache &cc, i
     const bool up = hit && (pick3<F>(Tr, ax) + pick3<F>(dT, ax)) > (F)0;
     // one call site for both the partial step and the edge-extended full step
     if (!hit || lam > (F)0) {
-        rkn_step<F, false, false, NODES>(P, cc, c, fd, Tr, dT, g, hstep, hit ? lam : (F)1);
+        rkn_step<F, false, false, NODES>(P, cc, c, fd, Tr, dT, sg, hit ? lam : (F)1);
         ++steps;
         // a step ending on or a hair beyond the upper face leaves cell n - 1 at fraction ~0: keep the
         // index a cell of the grid (same position), as the inside steps assume
@@ -770,10 +801,10 @@ __device__ __forceinline__ void rkn_step_fp64(const TraceParams &P, CellCache &c
                                               float Tr[3], float dT[3], double lam)
 {
     double T64[3], d64[3] = {0.0, 0.0, 0.0};
-    const double g64[3] = {P.step_cell[0], P.step_cell[1], P.step_cell[2]};
+    const StepGeom<double> sg64 = step_geom<double>(P);
 #pragma unroll
     for (int a = 0; a < 3; ++a) T64[a] = (double)Tr[a] + (double)dT[a];
-    rkn_step<double, FULL>(P, cc, c, fd, T64, d64, g64, P.h, lam);
+    rkn_step<double, FULL>(P, cc, c, fd, T64, d64, sg64, lam);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const double T = T64[a] + d64[a];
@@ -786,9 +817,9 @@ __device__ __forceinline__ void rkn_step_fp64(const TraceParams &P, CellCache &c
 __device__ __forceinline__ int trace_box_mixed(const TraceParams &P, CellCache &cc, int c[3], double fd[3],
                                                float Tr[3], float dT[3], bool *limited, int *n64)
 {
-    const float g[3] = {(float)P.step_cell[0], (float)P.step_cell[1], (float)P.step_cell[2]};
-    const float hstep = (float)P.h;
-    const int last[3] = {P.nx - 1, P.ny - 1, P.nz - 1};
+    const StepGeom<float> sg = step_geom<float>(P);
+    const float *g = sg.g;
+    const int *last = sg.last;
     int steps = 0;
     *limited = false;
     for (;;) {
@@ -814,7 +845,7 @@ __device__ __forceinline__ int trace_box_mixed(const TraceParams &P, CellCache &
                 const bool up = (pick3<float>(Tr, ax) + pick3<float>(dT, ax)) > 0.0f;
                 if (lam > 0.0f) {
                     if (brick_is_fp64(P, c)) { rkn_step_fp64<false>(P, cc, c, fd, Tr, dT, (double)lam); ++*n64; }
-                    else rkn_step<float, false>(P, cc, c, fd, Tr, dT, g, hstep, lam);
+                    else rkn_step<float, false>(P, cc, c, fd, Tr, dT, sg, lam);
                     ++steps;
                 }
                 const float Tn[3] = {Tr[0] + dT[0], Tr[1] + dT[1], Tr[2] + dT[2]};
@@ -840,7 +871,7 @@ __device__ __forceinline__ int trace_box_mixed(const TraceParams &P, CellCache &
             }
         }
         if (brick_is_fp64(P, c)) { rkn_step_fp64<true>(P, cc, c, fd, Tr, dT, 1.0); ++*n64; }
-        else rkn_step<float, true>(P, cc, c, fd, Tr, dT, g, hstep, 1.0f);
+        else rkn_step<float, true>(P, cc, c, fd, Tr, dT, sg, 1.0f);
         if (++steps > P.max_steps) { *limited = true; return steps; }
     }
 }
@@ -934,17 +965,17 @@ __global__ void __launch_bounds__(256) k_calibrate(TraceParams P, const int *__r
         Tr[a] = (float)T0;
         dT[a] = (float)(T0 - (double)Tr[a]);
     }
-    const float g[3] = {(float)P.step_cell[0], (float)P.step_cell[1], (float)P.step_cell[2]};
-    for (int k = 0; k < n_steps; ++k) rkn_step<float, true>(P, cc, c32, fd32, Tr, dT, g, (float)P.h, 1.0f);
+    const StepGeom<float> sg = step_geom<float>(P);
+    for (int k = 0; k < n_steps; ++k) rkn_step<float, true>(P, cc, c32, fd32, Tr, dT, sg, 1.0f);
     // FP64
     int c64[3] = {c[0], c[1], c[2]};
     double fd64[3] = {fd[0], fd[1], fd[2]};
     double T64[3], d64[3] = {0.0, 0.0, 0.0};
-    const double g64[3] = {P.step_cell[0], P.step_cell[1], P.step_cell[2]};
+    const StepGeom<double> sg64 = step_geom<double>(P);
 #pragma unroll
     for (int a = 0; a < 3; ++a) T64[a] = (double)n0 * u[a];
     cc.ix = -1;
-    for (int k = 0; k < n_steps; ++k) rkn_step<double, true>(P, cc, c64, fd64, T64, d64, g64, P.h, 1.0);
+    for (int k = 0; k < n_steps; ++k) rkn_step<double, true>(P, cc, c64, fd64, T64, d64, sg64, 1.0);
     double q32[2], q64[2];
     {
         double Xa[3], Xb[3], da[3], db[3];
