@@ -129,17 +129,20 @@ void fill_params(const pbr_ctx *ctx, const Derived &d, double ds, TraceParams *o
     }
     // FP32 step constants (see TraceParams): each a float operation on float values, so that a
     // partial step of fraction 1 forms the same bits on the device
-    float gmax = 0.0f;
+    float tlim = 3.0e38f;
     for (int a = 0; a < 3; ++a) {
         P.g32[a] = (float)P.step_cell[a];
         P.gh32[a] = 0.5f * P.g32[a];
-        gmax = P.g32[a] > gmax ? P.g32[a] : gmax;
+        const double k = std::ceil(1.05 * (double)P.g32[a] + 4.0e-3);
+        P.kin[a] = k < 1.0 ? 1 : (k > 1.0e6 ? 1000000 : (int)k);
+        const float t = ((float)P.kin[a] - 4.0e-3f) / P.g32[a];
+        tlim = t < tlim ? t : tlim;
     }
     P.h32 = (float)P.h;
     P.h4_32 = 0.25f * P.h32;
     P.h2_32 = 0.5f * P.h32;
     P.h6_32 = P.h32 * (1.0f / 6.0f);
-    P.tlim32 = gmax > 0.0f ? (1.0f - 4.0e-3f) / gmax : 0.0f;
+    P.tlim32 = tlim;
     P.n_inf = d.n_inf;
     P.z_lens = ctx->has_chain ? ctx->chain.aim_z : ctx->optics.z_front_vertex;
     P.a = d.a; P.R = d.R; P.t = d.t; P.clear = d.clear; P.n_glass = ctx->optics.n_glass;

@@ -105,11 +105,14 @@ struct TraceParams {
     const pbr_optical_chain *chain;
     // FP32 constants of a full integration step, rounded once on the host from h and step_cell so
     // that the kernels hold them in scalar registers: g = h / spacing, g / 2, h, h / 4, h / 2,
-    // h * (1/6) (float products, as the partial steps form them), and the largest |T| component for
-    // which a full step moves less than 1 - 4e-3 cells on every axis
+    // h * (1/6) (float products, as the partial steps form them).  kin: per axis the cells a full
+    // step may cross when |T| <= 1.05 (any gas), ceil(1.05 g + 4e-3) and at least 1; tlim32: min
+    // over the axes of (kin - 4e-3) / g, the largest |T| component for which a full step from a
+    // cell at least kin cells from both faces ends 4e-3 cells inside the box (see the integration
+    // kernel)
     float g32[3], gh32[3];
     float h32, h4_32, h2_32, h6_32, tlim32;
-    int pad2;
+    int kin[3];
 };
 
 // Offset of the optical chain inside the context's 4 KiB device block (counters come first).

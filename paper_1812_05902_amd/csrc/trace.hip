@@ -110,7 +110,7 @@ __device__ __forceinline__ F sample_field(const TraceParams &P, CellCache &cc, c
             const F fa = INSIDE ? f[a] : fmin(fmax(f[a], (F)(-1.0e6)), (F)(1.0e6));
             i0 = c[a] + split_cell<F>(fa, t);
         }
-        // (an inside step starts in an interior cell, so its own index needs no clamp)
+        // (every step starts in a cell of the grid, so an inside step's own index needs no clamp)
         const int i = INSIDE ? (AT_STATE ? i0 : clamp_index(i0, nmax[a])) : min(max(i0, 0), nmax[a]);
         if (!INSIDE) {
             t = i0 < 0 ? (F)0 : t;
@@ -160,8 +160,9 @@ template <typename F> struct StepGeom {
     F g[3], gh[3];     // h / spacing (cell units per unit of T in a full step), half of it
     F hstep, h4, h2, h6;  // h, h / 4, h / 2, h * (1/6)
     int last[3];       // n - 1 per axis (the upper face, in cells)
-    unsigned bnd[3];   // max(n - 3, 0): interior cells are 1 <= c < 1 + bnd
-    F tlim;            // largest |T| component for which a full step stays under 1 - 4 kFaceMargin cells
+    int lo[3];         // interior margin k: cells a full step may cross
+    unsigned bnd[3];   // max(n - 1 - 2k, 0): interior cells are k <= c < k + bnd
+    F tlim;            // largest |T| component for which a full step crosses fewer than k - 4 kFaceMargin cells
 };
 
 template <typename F> __device__ __forceinline__ StepGeom<F> step_geom(const TraceParams &P);
@@ -175,7 +176,8 @@ template <> __device__ __forceinline__ StepGeom<float> step_geom<float>(const Tr
         s.g[a] = P.g32[a];
         s.gh[a] = P.gh32[a];
         s.last[a] = nn[a] - 1;
-        s.bnd[a] = (unsigned)max(nn[a] - 3, 0);
+        s.lo[a] = P.kin[a];
+        s.bnd[a] = (unsigned)max(nn[a] - 1 - 2 * P.kin[a], 0);
     }
     s.hstep = P.h32;
     s.h4 = P.h4_32;
@@ -188,20 +190,20 @@ template <> __device__ __forceinline__ StepGeom<double> step_geom<double>(const 
 {
     StepGeom<double> s;
     const int nn[3] = {P.nx, P.ny, P.nz};
-    double gmax = 0.0;
+    s.tlim = 3.0e38;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         s.g[a] = P.step_cell[a];
         s.gh[a] = 0.5 * s.g[a];
         s.last[a] = nn[a] - 1;
-        s.bnd[a] = (unsigned)max(nn[a] - 3, 0);
-        gmax = fmax(gmax, s.g[a]);
+        s.lo[a] = P.kin[a];
+        s.bnd[a] = (unsigned)max(nn[a] - 1 - 2 * P.kin[a], 0);
+        s.tlim = fmin(s.tlim, ((double)P.kin[a] - 4.0 * (double)kFaceMargin) / s.g[a]);
     }
     s.hstep = P.h;
     s.h4 = 0.25 * P.h;
     s.h2 = 0.5 * P.h;
     s.h6 = P.h * (1.0 / 6.0);
-    s.tlim = gmax > 0.0 ? (1.0 - 4.0 * (double)kFaceMargin) / gmax : 0.0;
     return s;
 }
 
@@ -270,14 +272,16 @@ enum : int { STEP_GO = 0, STEP_EXIT = 1, STEP_LIMIT = 2 };
 // a face the ray moves towards) the partial step of fraction lam and, if the ray still heads out,
 // the straight move onto that face.  Returns STEP_EXIT when the ray left the box, STEP_LIMIT when
 // it ran out of steps, STEP_GO otherwise.
-// A full step taken by a ray in an interior cell (index 1 .. n-3 on every axis; there the fraction
-// is in [0, 1], as emission and both step paths leave it) that moves it less than
-// 1 - 4 kFaceMargin cells on every axis (|T| components <= tlim) ends at least 2 kFaceMargin cells
-// inside every face, so it is taken without the edge extension: its stage points stay inside the
-// box (they leave the straight line by h^2 |D| / 2 in the step parameter, about 1e-7 cells at the
-// fields here).  The test is integer compares and one maximum.  Every other step (a ray in a cell
-// on the boundary of the grid) goes through the exit rule and the edge-extended sampling; a full
-// step there, at fraction 1, gives the same bits as the inside one wherever both apply.
+// A full step taken by a ray in an interior cell (at least k cells from both faces on every axis,
+// k = the cells a full step may cross, at least 1; there the fraction is in [0, 1], as emission and
+// every step path leave it) whose |T| components are at most tlim ends at least 4 kFaceMargin
+// cells inside every face, so it is taken without the edge extension: its stage points stay
+// inside the box (they leave the straight line by h^2 |D| / 2 in the step parameter, about 1e-7
+// cells at the fields here).  That test is integer compares and one maximum.  A ray in a cell near
+// the faces is tested on the straight end point of a full step: more than kFaceMargin inside, the
+// full step is taken the same way; otherwise the exit rule decides, through the edge-extended
+// sampling (a full step there, at fraction 1, gives the same bits as the inside one wherever both
+// apply).  Every step leaves the state in a cell of the grid (the exit-rule path renormalises it).
 template <typename F, bool NODES = false>
 __device__ __forceinline__ int trace_step(const TraceParams &P, CellCache &cc, int c[3], double fd[3], const F Tr[3],
                                           F dT[3], const StepGeom<F> &sg, int &steps)
@@ -288,9 +292,20 @@ __device__ __forceinline__ int trace_step(const TraceParams &P, CellCache &cc, i
     // one with a NaN next to finite components may pass (fmax returns the number), and its step then
     // stays in bounds through the clamped cell indices.
     const F Tm = fmax(fmax(fabs(Tr[0] + dT[0]), fabs(Tr[1] + dT[1])), fabs(Tr[2] + dT[2]));
-    const bool inside = ((unsigned)(c[0] - 1) < sg.bnd[0]) & ((unsigned)(c[1] - 1) < sg.bnd[1]) &
-                        ((unsigned)(c[2] - 1) < sg.bnd[2]) & (Tm <= sg.tlim);
+    const bool inside = ((unsigned)(c[0] - sg.lo[0]) < sg.bnd[0]) & ((unsigned)(c[1] - sg.lo[1]) < sg.bnd[1]) &
+                        ((unsigned)(c[2] - sg.lo[2]) < sg.bnd[2]) & (Tm <= sg.tlim);
     if (__builtin_expect(inside, 1)) {
+        rkn_step<F, true, true, NODES>(P, cc, c, fd, Tr, dT, sg, (F)1);
+        return ++steps > P.max_steps ? STEP_LIMIT : STEP_GO;
+    }
+    // near the faces: the straight end point of a full step (a NaN counts as outside)
+    bool far = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const F e = ((F)c[a] + (F)fd[a]) + g[a] * (Tr[a] + dT[a]);
+        far = far & (e > (F)kFaceMargin) & (e < (F)last[a] - (F)kFaceMargin);
+    }
+    if (far) {
         rkn_step<F, true, true, NODES>(P, cc, c, fd, Tr, dT, sg, (F)1);
         return ++steps > P.max_steps ? STEP_LIMIT : STEP_GO;
     }
