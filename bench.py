@@ -108,7 +108,7 @@ def main():
                     help="field stored per cell (128 B) or per node (16 B); auto takes the faster measured "
                          "one per workload")
     ap.add_argument("--rays-per-chunk", type=int, default=1 << 24,
-                    help="turbulence_bos_128 / surrogate256: rays per trace chunk (64 bytes of ray state each)")
+                    help="rays per trace chunk (64 bytes of ray state each; the bos_fig4 renders use one chunk)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy a 1 GiB device buffer 4 times (calibrates HBM byte counters)")
     ap.add_argument("--atomic-probe", action="store_true",
@@ -284,9 +284,9 @@ def bench_tomo(args):
     rho = inputs.density(sc)
     # the precision calibration and the shock-FP64 leg need the per-cell field; the FP32 leg takes
     # the node layout unless told otherwise (faster on this fine grid)
-    r = pbr.Renderer.from_scene(sc, rho=rho)
+    r = pbr.Renderer.from_scene(sc, rho=rho, rays_per_chunk=args.rays_per_chunk)
     nodes = args.field_layout != "cells"
-    rn = pbr.Renderer.from_scene(sc, rho=rho, nodes=True) if nodes else r
+    rn = pbr.Renderer.from_scene(sc, rho=rho, nodes=True, rays_per_chunk=args.rays_per_chunk) if nodes else r
     del rho
     src = torch.as_tensor(inputs.sources(sc), device=r.device).contiguous()
     out16 = torch.empty(sc.height, sc.width, dtype=torch.int16, device=r.device)
@@ -322,7 +322,7 @@ def bench_tomo(args):
         "unit": "rays/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "tomo_piv_512", "grid": "512^3", "n_src": sc.n_src, "rays_per_src": sc.rays_per_src,
+        "config": {"workload": "tomo_piv_512", "grid": "512^3", "rays_per_chunk": args.rays_per_chunk, "n_src": sc.n_src, "rays_per_src": sc.rays_per_src,
                    "rays_per_image": sc.n_rays, "sensor": f"{sc.width}x{sc.height} u16", "ds_m": sc.ds,
                    "mean_rkn_steps_per_ray": steps_total / args.steps / sc.n_rays, "setup_s": setup_s,
                    "field_layout": "nodes" if nodes else "cells"},
@@ -419,7 +419,7 @@ def bench_piv_pair(args):
     t0 = time.perf_counter()
     rho = inputs.density(sc)
     nodes = args.field_layout != "cells"
-    r = pbr.Renderer.from_scene(sc, rho=rho, nodes=nodes)
+    r = pbr.Renderer.from_scene(sc, rho=rho, nodes=nodes, rays_per_chunk=args.rays_per_chunk)
     del rho
     src = torch.as_tensor(inputs.sources(sc), device=r.device).contiguous()
     vel, org, sp, dt = inputs.piv_pair_flow()
@@ -457,7 +457,7 @@ def bench_piv_pair(args):
         "unit": "rays/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "piv_pair_512", "grid": "512^3", "n_src": sc.n_src, "rays_per_src": sc.rays_per_src,
+        "config": {"workload": "piv_pair_512", "grid": "512^3", "rays_per_chunk": args.rays_per_chunk, "n_src": sc.n_src, "rays_per_src": sc.rays_per_src,
                    "frames_per_step": 2, "rays_per_step": n_rays, "sensor": f"{sc.width}x{sc.height} u16",
                    "flow": "Lamb-Oseen vortex (0.05 m^2/s, core 1 cm) in a 0.2 m/s stream, 65^3 grid",
                    "frame_interval_s": dt, "max_particle_move_mm": moved * 1e3, "setup_s": setup_s,
@@ -542,7 +542,7 @@ def bench_surrogate(args):
         "value": ev.n_rays * args.steps / wall_s, "unit": "rays/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": wall_s / args.steps * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "bf16+f32", "data": "synthetic",
-        "config": {"workload": "surrogate256", "grid": "256^3", "rays_per_image": ev.n_rays,
+        "config": {"workload": "surrogate256", "grid": "256^3", "rays_per_chunk": args.rays_per_chunk, "rays_per_image": ev.n_rays,
                    "train_rays": tr.n_rays, "val_rays": va.n_rays, "tiles": "64x64", "tol_px": 0.01,
                    "epochs": args.epochs, "setup_s": setup_s},
         "tracer_rays_per_s": ev.n_rays * args.steps / wall_t,
