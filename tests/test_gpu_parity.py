@@ -119,6 +119,25 @@ def test_ragged_sizes_and_empty(torch):
     assert int(pbr.u64_image_to_numpy(r.read_image()).sum()) == 0
 
 
+@pytest.mark.parametrize("ds, half", [(4.0e-3, 0.024), (1.2e-3, 0.040)])
+def test_long_steps_and_rays_along_the_faces_match_oracle(torch, ds, half):
+    """Steps longer than a cell (ds = 4 mm on 1.6 mm cells: up to 2.5 cells per step, so the
+    interior margin is three cells on every axis) and, with ds = 1.2 mm, dots spread beyond the box
+    so that many rays enter or leave through the side faces and travel next to them: both the
+    integer interior test and the end-point test near the faces are exercised, in FP32 and FP64."""
+    sc = inputs.tiny_bos().replace(n_src=300, rays_per_src=40, ds=ds,
+                                   src_region=((-half, half), (-half, half), (0.0, 0.0)))
+    r, st, recs, src = _render_all(torch, sc)
+    ref = oracle.scene_oracle(sc).trace_ids(src, sc.rays_per_src, np.arange(sc.n_rays))
+    err, mism = _compare_records(recs, ref, TOL_PX, label=f"ds {ds}")
+    n_in = int((ref["entered"] == 1).sum())
+    print(f"ds {ds * 1e3:.1f} mm, dots +-{half * 1e3:.0f} mm: {n_in} of {sc.n_rays} rays entered, "
+          f"max |dpx| = {err:.3e}, status mismatches = {mism}")
+    assert n_in > sc.n_rays // 4
+    _, _, recs64, _ = _render_all(torch, sc, flags=pbr.PBR_PREC_FP64_ALL, src=src)
+    _compare_records(recs64, ref, TOL_PX_FP64, label=f"ds {ds} fp64")
+
+
 def test_single_ray_and_sources_inside_box(torch):
     """PIV: particles inside the density box (shock field on a 48^3 grid), plus the one-ray case."""
     sc = inputs.tomo_piv_shock(n=48, n_src=300, rays_per_src=40).replace(width=512, height=512,
