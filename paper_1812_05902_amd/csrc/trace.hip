@@ -718,7 +718,7 @@ __device__ __forceinline__ void box_body(const TraceParams &P, RayState *__restr
     st[i] = r;
 }
 
-// FP32 integration: 95 VGPRs, five waves per SIMD.  NODES: field stored per node (the corner gather
+// FP32 integration: 88 VGPRs, five waves per SIMD.  NODES: field stored per node (the corner gather
 // needs more registers: four waves per SIMD).
 template <bool NODES = false>
 __global__ void __launch_bounds__(256, NODES ? 4 : 5) k_box32(TraceParams P, RayState *__restrict__ st, int64_t n,
