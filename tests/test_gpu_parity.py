@@ -119,10 +119,11 @@ def test_ragged_sizes_and_empty(torch):
     assert int(pbr.u64_image_to_numpy(r.read_image()).sum()) == 0
 
 
-@pytest.mark.parametrize("ds, half", [(4.0e-3, 0.024), (1.2e-3, 0.040)])
+@pytest.mark.parametrize("ds, half", [(4.0e-3, 0.024), (1.2e-3, 0.040), (2.0e-2, 0.024)])
 def test_long_steps_and_rays_along_the_faces_match_oracle(torch, ds, half):
     """Steps longer than a cell (ds = 4 mm on 1.6 mm cells: up to 2.5 cells per step, so the
-    interior margin is three cells on every axis) and, with ds = 1.2 mm, dots spread beyond the box
+    interior margin is three cells on every axis; ds = 20 mm: about 12 cells per step, five
+    interior cells per axis, three steps per ray) and, with ds = 1.2 mm, dots spread beyond the box
     so that many rays enter or leave through the side faces and travel next to them: both the
     integer interior test and the end-point test near the faces are exercised, in FP32 and FP64."""
     sc = inputs.tiny_bos().replace(n_src=300, rays_per_src=40, ds=ds,
