@@ -54,26 +54,20 @@ template <> __device__ __forceinline__ int split_cell<double>(double x, double &
     return (int)o;
 }
 
-// Node layout: the eight corners (n - 1, grad n) of cell ic, turned into the coefficients of the
-// cell records (c0 + x c1 + y c2 + z c3 + xy c4 + xz c5 + yz c6 + xyz c7 per quantity).
+// Node layout: the eight corners (n - 1, grad n) of cell ic, in the order 000, 100, 010, 001, 110,
+// 101, 011, 111 (x, y, z offsets).  They are interpolated as they are (see sample_field): steps
+// in the fine grids this layout serves cross a cell every one or two samples, so a per-gather
+// transform into polynomial coefficients would cost more than it saves.
 __device__ __forceinline__ void gather_nodes(const TraceParams &P, const int ic[3], float4 c[8])
 {
     const size_t sy = (size_t)P.nx, sz = (size_t)P.nx * (size_t)P.ny;
     const float4 *b = P.cells + (size_t)ic[2] * sz + (size_t)ic[1] * sy + (size_t)ic[0];
-    // corners straight into the coefficient slots (000, 100, 010, 001, 110, 101, 011, 111), then
-    // differenced in place: no registers beyond the cache itself
     c[0] = b[0]; c[1] = b[1]; c[2] = b[sy]; c[3] = b[sz];
     c[4] = b[sy + 1]; c[5] = b[sz + 1]; c[6] = b[sz + sy]; c[7] = b[sz + sy + 1];
-    c[7] = c[7] - c[6] - c[5] - c[4] + c[1] + c[2] + c[3] - c[0];
-    c[4] = c[4] - c[1] - c[2] + c[0];
-    c[5] = c[5] - c[1] - c[3] + c[0];
-    c[6] = c[6] - c[2] - c[3] + c[0];
-    c[1] = c[1] - c[0];
-    c[2] = c[2] - c[0];
-    c[3] = c[3] - c[0];
 }
 
-// The coefficients of the cell the ray is in, held in registers: a stage point only gathers
+// The coefficients (cell layout) or corner values (node layout) of the cell the ray is in, held
+// in registers: a stage point only gathers
 // from memory when it lies in another cell (about once per cell crossing, since the three stage
 // points of a step run ahead of the ray).
 struct CellCache {
@@ -134,6 +128,26 @@ __device__ __forceinline__ F sample_field(const TraceParams &P, CellCache &cc, c
     }
     const F x = w[0], y = w[1], z = w[2];
     F v[4];
+    if (NODES) {
+        // seven linear interpolations per quantity from the corners: along x on the four edges,
+        // then y, then z
+#define PBR_LERP(a, b, t) ((a) + (t) * ((b) - (a)))
+#define PBR_TRI(ch, out)                                                                   \
+    {                                                                                      \
+        const F e00 = PBR_LERP((F)cc.c[0].ch, (F)cc.c[1].ch, x);                           \
+        const F e10 = PBR_LERP((F)cc.c[2].ch, (F)cc.c[4].ch, x);                           \
+        const F e01 = PBR_LERP((F)cc.c[3].ch, (F)cc.c[5].ch, x);                           \
+        const F e11 = PBR_LERP((F)cc.c[6].ch, (F)cc.c[7].ch, x);                           \
+        out = PBR_LERP(PBR_LERP(e00, e10, y), PBR_LERP(e01, e11, y), z);                   \
+    }
+        PBR_TRI(x, v[0]);
+        PBR_TRI(y, v[1]);
+        PBR_TRI(z, v[2]);
+        PBR_TRI(w, v[3]);
+#undef PBR_TRI
+#undef PBR_LERP
+    } else {
+        // the cell's polynomial c0 + x c1 + y c2 + z c3 + xy c4 + xz c5 + yz c6 + xyz c7, Horner form
 #define PBR_TRI(ch, out)                                                                   \
     {                                                                                      \
         const F t1 = (F)cc.c[4].ch + z * (F)cc.c[7].ch;                                    \
@@ -141,11 +155,12 @@ __device__ __forceinline__ F sample_field(const TraceParams &P, CellCache &cc, c
         const F t3 = (F)cc.c[2].ch + z * (F)cc.c[6].ch;                                    \
         out = (F)cc.c[0].ch + z * (F)cc.c[3].ch + y * t3 + x * t2;                         \
     }
-    PBR_TRI(x, v[0]);
-    PBR_TRI(y, v[1]);
-    PBR_TRI(z, v[2]);
-    PBR_TRI(w, v[3]);
+        PBR_TRI(x, v[0]);
+        PBR_TRI(y, v[1]);
+        PBR_TRI(z, v[2]);
+        PBR_TRI(w, v[3]);
 #undef PBR_TRI
+    }
     G[0] = v[1];
     G[1] = v[2];
     G[2] = v[3];
