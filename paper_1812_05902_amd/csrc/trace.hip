@@ -54,18 +54,6 @@ template <> __device__ __forceinline__ int split_cell<double>(double x, double &
     return (int)o;
 }
 
-// Node layout: the eight corners (n - 1, grad n) of cell ic, in the order 000, 100, 010, 001, 110,
-// 101, 011, 111 (x, y, z offsets).  They are interpolated as they are (see sample_field): steps
-// in the fine grids this layout serves cross a cell every one or two samples, so a per-gather
-// transform into polynomial coefficients would cost more than it saves.
-__device__ __forceinline__ void gather_nodes(const TraceParams &P, const int ic[3], float4 c[8])
-{
-    const size_t sy = (size_t)P.nx, sz = (size_t)P.nx * (size_t)P.ny;
-    const float4 *b = P.cells + (size_t)ic[2] * sz + (size_t)ic[1] * sy + (size_t)ic[0];
-    c[0] = b[0]; c[1] = b[1]; c[2] = b[sy]; c[3] = b[sz];
-    c[4] = b[sy + 1]; c[5] = b[sz + 1]; c[6] = b[sz + sy]; c[7] = b[sz + sy + 1];
-}
-
 // The coefficients (cell layout) or corner values (node layout) of the cell the ray is in, held
 // in registers: a stage point only gathers
 // from memory when it lies in another cell (about once per cell crossing, since the three stage
@@ -74,6 +62,43 @@ struct CellCache {
     int ix, iy, iz;  // the cached cell, ix = -1: none
     float4 c[kCellFloat4];
 };
+
+// Node layout: the eight corners (n - 1, grad n) of cell ic, in the order 000, 100, 010, 001, 110,
+// 101, 011, 111 (x, y, z offsets), loaded into the cache.  They are interpolated as they are (see
+// sample_field): steps in the fine grids this layout serves cross a cell every one or two
+// samples, so a per-gather transform into polynomial coefficients would cost more than it saves.
+// A move to a face neighbour of the cached cell keeps the four corners of the shared face and
+// loads the other four: half the gather traffic on most crossings.
+__device__ __forceinline__ void gather_nodes(const TraceParams &P, const int ic[3], CellCache &cc)
+{
+    const size_t sy = (size_t)P.nx, sz = (size_t)P.nx * (size_t)P.ny;
+    const float4 *b = P.cells + (size_t)ic[2] * sz + (size_t)ic[1] * sy + (size_t)ic[0];
+    float4 *c = cc.c;
+    const int dx = ic[0] - cc.ix, dy = ic[1] - cc.iy, dz = ic[2] - cc.iz;
+    const bool one = cc.ix >= 0 && abs(dx) + abs(dy) + abs(dz) == 1;  // ix = -1: nothing cached
+    if (one && dz == 1) {
+        c[0] = c[3]; c[1] = c[5]; c[2] = c[6]; c[4] = c[7];
+        c[3] = b[sz]; c[5] = b[sz + 1]; c[6] = b[sz + sy]; c[7] = b[sz + sy + 1];
+    } else if (one && dz == -1) {
+        c[3] = c[0]; c[5] = c[1]; c[6] = c[2]; c[7] = c[4];
+        c[0] = b[0]; c[1] = b[1]; c[2] = b[sy]; c[4] = b[sy + 1];
+    } else if (one && dx == 1) {
+        c[0] = c[1]; c[2] = c[4]; c[3] = c[5]; c[6] = c[7];
+        c[1] = b[1]; c[4] = b[sy + 1]; c[5] = b[sz + 1]; c[7] = b[sz + sy + 1];
+    } else if (one && dx == -1) {
+        c[1] = c[0]; c[4] = c[2]; c[5] = c[3]; c[7] = c[6];
+        c[0] = b[0]; c[2] = b[sy]; c[3] = b[sz]; c[6] = b[sz + sy];
+    } else if (one && dy == 1) {
+        c[0] = c[2]; c[1] = c[4]; c[3] = c[6]; c[5] = c[7];
+        c[2] = b[sy]; c[4] = b[sy + 1]; c[6] = b[sz + sy]; c[7] = b[sz + sy + 1];
+    } else if (one && dy == -1) {
+        c[2] = c[0]; c[4] = c[1]; c[6] = c[3]; c[7] = c[5];
+        c[0] = b[0]; c[1] = b[1]; c[3] = b[sz]; c[5] = b[sz + 1];
+    } else {
+        c[0] = b[0]; c[1] = b[1]; c[2] = b[sy]; c[3] = b[sz];
+        c[4] = b[sy + 1]; c[5] = b[sz + 1]; c[6] = b[sz + sy]; c[7] = b[sz + sy + 1];
+    }
+}
 
 // Trilinear interpolation of (n - 1, grad n) at the point (cell c, fraction f); the fraction may
 // lie outside [0, 1) (stage points of eq. 5), in which case the point is moved into the cell that
@@ -115,7 +140,7 @@ __device__ __forceinline__ F sample_field(const TraceParams &P, CellCache &cc, c
     }
     // compare cell coordinates (no index arithmetic unless the cell changed)
     if ((ic[0] != cc.ix) | (ic[1] != cc.iy) | (ic[2] != cc.iz)) {
-        if (NODES) gather_nodes(P, ic, cc.c);
+        if (NODES) gather_nodes(P, ic, cc);
         else {
             const int key = (ic[2] * (P.ny - 1) + ic[1]) * (P.nx - 1) + ic[0];
             const float4 *p = P.cells + (size_t)key * kCellFloat4;
