@@ -105,8 +105,8 @@ __device__ __forceinline__ void gather_nodes(const TraceParams &P, const int ic[
 // holds it and then onto the box.  Returns n, writes G = grad n (D = n G, eq. 6, is formed by the
 // caller, folded into the step's sums).
 // INSIDE: the caller has shown that the point lies inside the box and that the ray's own cell index
-// is a cell of the grid (see trace_step), so the edge extension is left out; the cell index is still
-// clamped to the grid, which keeps every gather in bounds whatever the values.
+// is a cell of the grid (see trace_step), so the edge extension is left out; a stage point's cell
+// index is still clamped to the grid, which keeps every gather in bounds whatever the values.
 // NODES: the field is stored per node (see gather_nodes); compiled into dedicated kernels only.
 template <typename F, bool AT_STATE = false, bool INSIDE = false, bool NODES = false>
 __device__ __forceinline__ F sample_field(const TraceParams &P, CellCache &cc, const int c[3],
