@@ -654,6 +654,14 @@ double orc_mie_weight(const orc_scene *S, const double u[3])
 
 /* ---------------------------------------------------------------- whole image */
 
+/* Weight of a source's rays.  READING: the paper weights rays by the source's brightness without
+ * bounds; here a weight is a fraction in [0, 1] (ray intensities then stay within one unit of the
+ * fixed-point sensor), a weight beyond the range counts as the nearer end and a NaN weight as 0. */
+static double source_weight(float w)
+{
+    return w > 0.0f ? (w < 1.0f ? (double)w : 1.0) : 0.0;
+}
+
 /* Deposits every ray of every source.  img_q: uint64 Q32.32 image (+=), img_f: double image
  * (+=), counts[8]: per-status ray counts (+=) then total RKN steps at counts[7].
  * Per-thread images are summed in thread order, so the result is deterministic for a given
@@ -690,7 +698,7 @@ int orc_render(const orc_scene *S, const float *src, int64_t n_src, int32_t rays
                 tc[tid][st] += 1;
                 tc[tid][7] += (uint64_t)ry.n_steps;
                 if (st != ORC_DEPOSITED) continue;
-                const double w = (double)sp[3] * orc_mie_weight(S, ry.dir0);
+                const double w = source_weight(sp[3]) * orc_mie_weight(S, ry.dir0);
                 const double x = ry.sensor_px[0], y = ry.sensor_px[1];
                 const int i0 = (int)floor(x), j0 = (int)floor(y);
                 for (int d = -rfp; d <= rfp; ++d) {

@@ -89,3 +89,74 @@ def test_render_weights_each_ray_by_its_scattering_angle():
     # uniform field and a 3-sigma window: nearly all of each spot lands in the window
     assert f2.sum() == pytest.approx(w.sum(), rel=2e-3)
     assert f2.sum() < 0.5 * f0.sum()
+
+
+@pytest.mark.parametrize("m,x", [(1.33 + 0j, 3.0), (1.59 + 0.01j, 8.0), (1.5 + 0.1j, 0.7), (1.47 + 0j, 25.0)])
+def test_series_against_spherical_bessel_and_legendre_functions(m, x):
+    """The recurrences of the oracle against the closed definitions, evaluated another way:
+    a_n, b_n from Riccati-Bessel functions psi_n(z) = z j_n(z), xi_n(x) = x h_n^(1)(x) (scipy's
+    spherical Bessel functions, complex argument m x), and pi_n = P_n'(mu),
+    tau_n = mu P_n'(mu) - (1 - mu^2) P_n''(mu) from numpy's Legendre polynomials."""
+    from numpy.polynomial import legendre as L
+    from scipy.special import spherical_jn, spherical_yn
+    a, b = mie.coefficients(m, x)
+    n = np.arange(1, len(a) + 1)
+
+    def psi(z):
+        return z * spherical_jn(n, z)
+
+    def dpsi(z):
+        return spherical_jn(n, z) + z * spherical_jn(n, z, derivative=True)
+
+    h = spherical_jn(n, x) + 1j * spherical_yn(n, x)
+    dh = spherical_jn(n, x, derivative=True) + 1j * spherical_yn(n, x, derivative=True)
+    xi, dxi = x * h, h + x * dh
+    mx = m * x
+    A = (m * psi(mx) * dpsi(x) - psi(x) * dpsi(mx)) / (m * psi(mx) * dxi - xi * dpsi(mx))
+    B = (psi(mx) * dpsi(x) - m * psi(x) * dpsi(mx)) / (psi(mx) * dxi - m * xi * dpsi(mx))
+    big = max(np.abs(a).max(), np.abs(b).max())
+    assert np.abs(A - a).max() <= 1e-10 * big
+    assert np.abs(B - b).max() <= 1e-10 * big
+    mu = np.cos(np.linspace(0.0, np.pi, 37))
+    S1 = np.zeros(mu.shape, complex)
+    S2 = np.zeros(mu.shape, complex)
+    for k in n:
+        P = L.Legendre.basis(int(k))
+        pk = P.deriv(1)(mu)
+        tk = mu * pk - (1 - mu * mu) * P.deriv(2)(mu)
+        f = (2 * k + 1) / (k * (k + 1))
+        S1 += f * (A[k - 1] * pk + B[k - 1] * tk)
+        S2 += f * (A[k - 1] * tk + B[k - 1] * pk)
+    s1, s2 = mie.amplitudes(m, x, mu)
+    scale = max(np.abs(S1).max(), np.abs(S2).max())
+    assert np.abs(S1 - s1).max() <= 1e-9 * scale
+    assert np.abs(S2 - s2).max() <= 1e-9 * scale
+
+
+def test_weight_is_linear_in_the_scattering_angle_between_nodes():
+    """orc_mie_weight between table nodes: a table linear in theta (t_k = theta_k / pi) gives
+    exactly theta / pi at any angle, and a table of theta_k^2 gives the chord value
+    theta^2 + (theta - theta_k)(theta_k+1 - theta) at points between nodes; an interpolation in
+    cos(theta), or an index off by one, fails both."""
+    import oracle
+    from paper_1812_05902_amd import inputs
+    oracle.build()
+    sc = inputs.tiny_bos().replace(n_src=1, rays_per_src=1)
+    o = oracle.scene_oracle(sc)
+    n = 33
+    nodes = np.arange(n) * (np.pi / (n - 1))
+    rng = np.random.default_rng(4)
+    th = np.concatenate([rng.uniform(0, np.pi, 200), [0.0, np.pi, nodes[5] + 1e-9, nodes[31] - 1e-9]])
+    laser = np.array([0.3, -0.5, 0.8]) / np.linalg.norm([0.3, -0.5, 0.8])
+    e1 = np.cross(laser, [1.0, 0.0, 0.0])
+    e1 /= np.linalg.norm(e1)
+    o.set_mie(nodes / np.pi, laser * 3.0)
+    for t in th:
+        u = np.cos(t) * laser + np.sin(t) * e1
+        assert o.mie_weight(u) == pytest.approx(t / np.pi, abs=1e-12)
+    o.set_mie(nodes ** 2, laser)
+    for t in th[:200]:
+        k = min(int(t / (np.pi / (n - 1))), n - 2)
+        want = t * t + (t - nodes[k]) * (nodes[k + 1] - t)
+        u = np.cos(t) * laser + np.sin(t) * e1
+        assert o.mie_weight(u) == pytest.approx(want, abs=1e-10)

@@ -519,3 +519,54 @@ def test_bos_displacement_eq9_grid_converges(oracle_lib):
     e63, p63 = _bos_case("grid", 63)
     assert e32 <= 0.03 and p32 <= 0.04
     assert e63 <= 0.35 * e32, (e32, e63)
+
+
+def test_readout_u16_hand_worked_cases(oracle_lib):
+    """The 16-bit readout (sec. 3.4) on hand-built Q32.32 values: u16 = min(65535,
+    round_half_even(v * gain)) with v = q / 2^32, and gain = 65535 / max(v) when none is given.
+    Values are chosen so that a wrong tie rule, a missing saturation or a gain computed from
+    anything but the largest pixel gives a different integer."""
+    one = 1 << 32
+    half = 1 << 31
+    # explicit gain 1: ties go to the even neighbour, fractions round to nearest, clip at 65535
+    q = np.array([0, half, one + half, 2 * one + half, 3 * one + half, one + half + 1, 1,
+                  65535 * one, 65535 * one + half, 70000 * one, (1 << 64) - 1], dtype=np.uint64)
+    want = np.array([0, 0, 2, 2, 4, 2, 0, 65535, 65535, 65535, 65535], dtype=np.uint16)
+    assert np.array_equal(oracle_lib.readout_u16(q, 1.0), want)
+    # gain 1024 on v = 1/2048, 3/2048, 5/2048: 0.5 -> 0, 1.5 -> 2, 2.5 -> 2
+    q2 = np.array([one // 2048, 3 * one // 2048, 5 * one // 2048], dtype=np.uint64)
+    assert np.array_equal(oracle_lib.readout_u16(q2, 1024.0), np.array([0, 2, 2], dtype=np.uint16))
+    # automatic gain: the largest pixel maps to 65535; half of it is 32767.5 -> 32768 (even);
+    # a quarter 16383.75 -> 16384; zero stays zero
+    q3 = np.array([2 * one, one, one // 2, 0], dtype=np.uint64)
+    assert np.array_equal(oracle_lib.readout_u16(q3), np.array([65535, 32768, 16384, 0], dtype=np.uint16))
+    # an all-zero image reads out as zeros (no division by a zero maximum)
+    assert not oracle_lib.readout_u16(np.zeros(17, dtype=np.uint64)).any()
+    # a gain given explicitly is used as is, whatever the maximum
+    assert np.array_equal(oracle_lib.readout_u16(q3, 3.0), np.array([6, 3, 2, 0], dtype=np.uint16))
+
+
+def test_source_weights_are_fractions(oracle_lib):
+    """A source weight scales every spot of its rays; weights beyond [0, 1] count as the nearer
+    end of the range and NaN as 0 (reading of sec. 3.1's source brightness as a fraction): the
+    image of weights (1.7, -0.3, NaN, 0.25, 1) equals that of (1, 0, 0, 0.25, 1), and a weight
+    of 0.25 carries a quarter of the light of weight 1 (integer image within rounding)."""
+    from paper_1812_05902_amd import inputs
+    sc = inputs.tiny_bos().replace(n_src=5, rays_per_src=64, field="uniform", field_params=dict(rho0=1.2))
+    src = inputs.sources(sc)
+    o = oracle_lib.scene_oracle(sc)
+    a = src.copy()
+    a[:, 3] = np.array([1.7, -0.3, np.nan, 0.25, 1.0], dtype=np.float32)
+    b = src.copy()
+    b[:, 3] = np.array([1.0, 0.0, 0.0, 0.25, 1.0], dtype=np.float32)
+    qa, fa, _ = o.render(a, sc.rays_per_src)
+    qb, fb, _ = o.render(b, sc.rays_per_src)
+    assert np.array_equal(qa, qb) and np.array_equal(fa, fb)
+    c = src.copy()
+    c[:, 3] = np.array([0.0, 0.0, 0.0, 1.0, 0.0], dtype=np.float32)
+    d = src.copy()
+    d[:, 3] = np.array([0.0, 0.0, 0.0, 0.25, 0.0], dtype=np.float32)
+    _, fc, _ = o.render(c, sc.rays_per_src)
+    _, fd, _ = o.render(d, sc.rays_per_src)
+    assert fc.sum() > 10.0
+    np.testing.assert_allclose(fd, 0.25 * fc, rtol=1e-12, atol=1e-300)
