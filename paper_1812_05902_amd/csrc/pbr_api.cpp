@@ -371,6 +371,7 @@ int set_field(pbr_ctx *ctx, const float *rho_dev, int nx, int ny, int nz, const 
     ctx->rho_inf = rho_inf;
     ctx->has_field = true;
     ++ctx->scene_version;
+    ++ctx->param_version;
     return PBR_OK;
     PBR_GUARD_END
 }
@@ -394,6 +395,7 @@ int pbr_set_optics(pbr_ctx *ctx, const pbr_optics *o)
     ctx->optics = *o;
     ctx->has_optics = true;
     ++ctx->scene_version;
+    ++ctx->param_version;
     return PBR_OK;
 }
 
@@ -413,6 +415,7 @@ int pbr_set_sensor(pbr_ctx *ctx, const pbr_sensor *s, uint64_t *accum_dev)
     ctx->accum_rays = 0.0;  // unknown contents: the caller clears with PBR_CLEAR_FIRST
     ctx->has_sensor = true;
     ++ctx->scene_version;
+    ++ctx->param_version;
     return PBR_OK;
 }
 
@@ -447,6 +450,7 @@ int pbr_set_exit_recording(pbr_ctx *ctx, int64_t first, int64_t stride, int64_t 
     ctx->rec_first = first;
     ctx->rec_stride = stride;
     ctx->rec_max = max_records;
+    ++ctx->param_version;
     return PBR_OK;
 }
 
@@ -466,6 +470,19 @@ int pbr_emit_and_trace(pbr_ctx *ctx, const float *src_dev, int64_t n_src, int32_
 {
     if (!ctx) return PBR_ERR_ARG;
     PBR_GUARD_BEGIN
+    return emit_and_trace_impl(ctx, src_dev, n_src, rays_per_src, seed, ds, flags, stats, false, nullptr, 0);
+    PBR_GUARD_END
+}
+
+}  // extern "C"
+
+namespace pbr {
+namespace host {
+
+int emit_and_trace_impl(pbr_ctx *ctx, const float *src_dev, int64_t n_src, int32_t rays_per_src, uint64_t seed,
+                        double ds, uint32_t flags, pbr_stats *stats, bool noalloc, RayState *static_ws,
+                        int64_t static_chunk)
+{
     Derived d;
     int r = derive(ctx, &d);
     if (r) return r;
@@ -504,7 +521,9 @@ int pbr_emit_and_trace(pbr_ctx *ctx, const float *src_dev, int64_t n_src, int32_
     if (flags & PBR_SURROGATE) {
         if ((r = surrogate_hook(ctx, ds, &hook))) return r;
     }
-    if (!ctx->ray_ws) return fail(ctx, PBR_ERR_STATE, "no trace workspace set (pbr_set_trace_workspace)");
+    pbr::RayState *ray_ws = noalloc ? static_ws : ctx->ray_ws;
+    const int64_t ray_chunk = noalloc ? static_chunk : ctx->ray_chunk;
+    if (!noalloc && !ray_ws) return fail(ctx, PBR_ERR_STATE, "no trace workspace set (pbr_set_trace_workspace)");
     if ((flags & PBR_RECORD_EXITS) && ctx->rec_max > 0 && !ctx->rec)
         return fail(ctx, PBR_ERR_STATE, "no exit recording buffer set");
     const double n_rays_d = (double)n_src * (double)rays_per_src;
@@ -514,6 +533,7 @@ int pbr_emit_and_trace(pbr_ctx *ctx, const float *src_dev, int64_t n_src, int32_
         return fail(ctx, PBR_ERR_OVERFLOW, "more than 2^32 - 1 rays per accumulation; clear the sensor");
 
     if (ctx->device < 0) return fail(ctx, PBR_ERR_STATE, "host-only context: no device work");
+    if (!ray_ws) return fail(ctx, PBR_ERR_STATE, "no static ray-state array on device %d", ctx->device);
     DeviceGuard g(ctx->device);
     if (!g.ok) return fail(ctx, PBR_ERR_HIP, "hipSetDevice failed");
     int e;
@@ -543,7 +563,7 @@ int pbr_emit_and_trace(pbr_ctx *ctx, const float *src_dev, int64_t n_src, int32_
     const int prec = (flags & PBR_PREC_FP64_ALL) ? pbr::PREC_FP64
                      : ((flags & PBR_PREC_SHOCK_FP64) && ctx->n_fp64_bricks > 0) ? pbr::PREC_MIXED
                      : pbr::PREC_FP32;
-    const int64_t n_chunks = (P.n_rays + ctx->ray_chunk - 1) / ctx->ray_chunk;
+    const int64_t n_chunks = (P.n_rays + ray_chunk - 1) / ray_chunk;
     if (stats) {
         while ((int64_t)ctx->box_ev.size() < 2 * n_chunks) {
             hipEvent_t ev;
@@ -553,9 +573,9 @@ int pbr_emit_and_trace(pbr_ctx *ctx, const float *src_dev, int64_t n_src, int32_
         if ((e = (int)hipEventRecord(ctx->ev0, ctx->stream))) return hip_fail(ctx, e, "hipEventRecord");
     }
     for (int64_t k = 0; k < n_chunks; ++k) {
-        const int64_t first = k * ctx->ray_chunk;
-        const int64_t n = P.n_rays - first < ctx->ray_chunk ? P.n_rays - first : ctx->ray_chunk;
-        e = pbr::launch_trace_chunk(P, ctx->ray_ws, first, n, prec, ctx->stream,
+        const int64_t first = k * ray_chunk;
+        const int64_t n = P.n_rays - first < ray_chunk ? P.n_rays - first : ray_chunk;
+        e = pbr::launch_trace_chunk(P, ray_ws, first, n, prec, ctx->stream,
                                     stats ? ctx->box_ev[2 * k] : nullptr, stats ? ctx->box_ev[2 * k + 1] : nullptr,
                                     hook.run ? &hook : nullptr, true, (flags & PBR_LANE_REFILL) != 0);
         if (e) return hip_fail(ctx, e, "trace launch");
@@ -591,8 +611,12 @@ int pbr_emit_and_trace(pbr_ctx *ctx, const float *src_dev, int64_t n_src, int32_
         stats->box_launches = (uint64_t)n_chunks;
     }
     return PBR_OK;
-    PBR_GUARD_END
 }
+
+}  // namespace host
+}  // namespace pbr
+
+extern "C" {
 
 int pbr_calibrate_precision(pbr_ctx *ctx, double tol_px, double steep_frac, int32_t rays_per_brick,
                             uint64_t seed, double ds, pbr_precision_report *out)
@@ -908,6 +932,7 @@ int pbr_set_optical_chain(pbr_ctx *ctx, const pbr_optical_chain *chain)
     if (!chain) {
         ctx->has_chain = false;
         ctx->scene_version++;
+        ctx->param_version++;
         return PBR_OK;
     }
     if (chain->n_surfaces < 1 || chain->n_surfaces > PBR_MAX_SURFACES)
@@ -935,6 +960,7 @@ int pbr_set_optical_chain(pbr_ctx *ctx, const pbr_optical_chain *chain)
     ctx->chain = *chain;
     ctx->has_chain = true;
     ctx->scene_version++;
+    ctx->param_version++;
     return PBR_OK;
     PBR_GUARD_END
 }

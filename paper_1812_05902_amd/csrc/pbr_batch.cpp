@@ -24,6 +24,7 @@ struct pbr_batch {
     std::string err;
     std::vector<pbr_batch_item> items;
     std::vector<pbr::TraceParams> params;      // host copies, one per image
+    std::vector<uint64_t> versions;            // each context's param_version at the snapshot
     std::vector<double> est_steps;             // cost estimate per ray, per image
     // device workspace
     char *ws = nullptr;
@@ -228,6 +229,21 @@ size_t pbr_batch_workspace_bytes(const pbr_batch_item *items, int n_items, int64
     return batch_layout(n_items, seg_capacity_for(n_items, rays.data(), min_round), round_rays).total;
 }
 
+namespace {
+// The launch parameters a batch replays were taken from its contexts at creation: a context whose
+// field, optics, sensor, chain or exit recording changed since then would be traced through stale
+// pointers and sizes.
+int check_snapshot(pbr_batch *b)
+{
+    for (size_t i = 0; i < b->items.size(); ++i)
+        if (b->items[i].ctx->param_version != b->versions[i])
+            return bfail(b, PBR_ERR_STATE,
+                         "item %zu: its context's field, optics, sensor, chain or exit recording changed since "
+                         "pbr_batch_create; create the batch again", i);
+    return PBR_OK;
+}
+}  // namespace
+
 int pbr_batch_create(pbr_batch **out, const pbr_batch_item *items, int n_items, void *ws_dev, size_t ws_bytes,
                      void *hip_stream)
 {
@@ -295,6 +311,7 @@ int pbr_batch_create(pbr_batch **out, const pbr_batch_item *items, int n_items, 
             P.seed = it.seed;
             P.record = (it.flags & PBR_RECORD_EXITS) && c->rec_max > 0 ? 1 : 0;
             b->params.push_back(P);
+            b->versions.push_back(c->param_version);
             b->est_steps.push_back((zmax - c->origin[2]) / it.ds);  // depth of the box in steps
         }
         DeviceGuard g(b->device);
@@ -408,6 +425,7 @@ int pbr_batch_run(pbr_batch *b, pbr_batch_stats *stats)
 {
     if (!b) return PBR_ERR_ARG;
     try {
+        if (int r = check_snapshot(b)) return r;
         DeviceGuard g(b->device);
         if (!g.ok) return bfail(b, PBR_ERR_HIP, "hipSetDevice failed");
         for (size_t i = 0; i < b->items.size(); ++i) {  // overflow bound of accumulating items
@@ -469,6 +487,7 @@ int pbr_batch_autotune(pbr_batch *b, const char *cache_path, int32_t probe_round
 {
     if (!b) return PBR_ERR_ARG;
     try {
+        if (int r = check_snapshot(b)) return r;
         const std::string key = tune_key(b);
         if (cache_path) {  // cached choice for this device and batch shape
             std::ifstream in(cache_path);

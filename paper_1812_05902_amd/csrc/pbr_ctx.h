@@ -51,6 +51,9 @@ struct pbr_ctx {
     // by every change of field, optics or sensor
     uint64_t uid = 0;
     uint64_t scene_version = 0;
+    // bumped by every call that changes what a trace launch reads from the context (field, optics,
+    // sensor, optical chain, exit recording): batches check it before replaying their snapshot
+    uint64_t param_version = 0;
     pbr_surrogate *surr = nullptr;
 };
 
@@ -93,6 +96,12 @@ bool mie_intensity_table(std::complex<double> m, double x, int n_angles, double 
 int surrogate_hook(pbr_ctx *ctx, double ds, ChunkHook *out);
 // Fingerprint of the context's stored field (device checksum of the field's words; synchronises).
 int field_fingerprint(pbr_ctx *ctx, uint64_t *out);
+// pbr_emit_and_trace after the null-context check.  noalloc: the ray states of the chunks go to
+// static_ws (the static array of this device; null when there is none), static_chunk rays at a
+// time, instead of the context's trace workspace.
+int emit_and_trace_impl(pbr_ctx *ctx, const float *src_dev, int64_t n_src, int32_t rays_per_src, uint64_t seed,
+                        double ds, uint32_t flags, pbr_stats *stats, bool noalloc, RayState *static_ws,
+                        int64_t static_chunk);
 
 }  // namespace host
 

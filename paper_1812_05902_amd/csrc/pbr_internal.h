@@ -186,7 +186,8 @@ int launch_surr_apply(const TraceParams &p, const SurrogateSpec &sp, const float
 // Sensor-hit error of predictions y for samples smp[0 .. n): err[k] in pixels; 1e30 for a ray
 // that entered through z_lo and left through another face; -2 when exactly one of prediction and
 // tracer reaches the sensor (a rim case); -1 when neither does or the ray is not a front-face ray.
-// Per-tile maxima (float bits) and counts over the err >= 0 samples.
+// Per-tile maxima (float bits) and counts over the err >= 0 samples, a rim case (-2) entering
+// its tile as 1e30 (never eligible).
 int launch_surr_extract(const SurrogateSample *smp, int64_t n, int field, int *out, hipStream_t s);
 int launch_surr_validate(const TraceParams &p, const SurrogateSpec &sp, const SurrogateSample *smp,
                          const float *y, int64_t n, float *err, unsigned *tile_err, unsigned *tile_cnt,

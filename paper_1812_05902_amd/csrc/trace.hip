@@ -321,7 +321,11 @@ enum : int { STEP_GO = 0, STEP_EXIT = 1, STEP_LIMIT = 2 };
 // the faces is tested on the straight end point of a full step: more than kFaceMargin inside, the
 // full step is taken the same way; otherwise the exit rule decides, through the edge-extended
 // sampling (a full step there, at fraction 1, gives the same bits as the inside one wherever both
-// apply).  Every step leaves the state in a cell of the grid (the exit-rule path renormalises it).
+// apply).  The exit-rule path leaves the state in a cell of the grid; a full step taken without the
+// edge extension does so unless its path bends more than kFaceMargin cells off the straight line
+// (a field far steeper than any here), and a state left outside the grid takes the exit rule next
+// (both tests above check the cell index first), so the ray's own cell index is in the grid
+// whenever it is used unclamped.
 template <typename F, bool NODES = false>
 __device__ __forceinline__ int trace_step(const TraceParams &P, CellCache &cc, int c[3], double fd[3], const F Tr[3],
                                           F dT[3], const StepGeom<F> &sg, int &steps)
@@ -338,12 +342,15 @@ __device__ __forceinline__ int trace_step(const TraceParams &P, CellCache &cc, i
         rkn_step<F, true, true, NODES>(P, cc, c, fd, Tr, dT, sg, (F)1);
         return ++steps > P.max_steps ? STEP_LIMIT : STEP_GO;
     }
-    // near the faces: the straight end point of a full step (a NaN counts as outside)
+    // near the faces: the straight end point of a full step (a NaN counts as outside), from a
+    // state whose cell is a cell of the grid.  (A step whose path bends more than kFaceMargin
+    // cells off its straight line can end a hair outside the box with the index one past a face;
+    // such a state takes the exit rule, whose sampling clamps every index.)
     bool far = true;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const F e = ((F)c[a] + (F)fd[a]) + g[a] * (Tr[a] + dT[a]);
-        far = far & (e > (F)kFaceMargin) & (e < (F)last[a] - (F)kFaceMargin);
+        far = far & (e > (F)kFaceMargin) & (e < (F)last[a] - (F)kFaceMargin) & ((unsigned)c[a] < (unsigned)last[a]);
     }
     if (far) {
         rkn_step<F, true, true, NODES>(P, cc, c, fd, Tr, dT, sg, (F)1);
@@ -1545,8 +1552,10 @@ __global__ void __launch_bounds__(256) k_surr_validate(TraceParams P, SurrogateS
         else if (dep != ((s.flags & 2) != 0))
             e = -2.0f;  // passes an aperture or lens rim on one side and not the other
     }
-    if (e >= 0.0f) {
-        atomicMax(tile_err + s.tile, __float_as_uint(e));
+    // a rim case would add or drop a whole ray: its tile is never eligible (the tracer keeps it)
+    const float te = e == -2.0f ? 1.0e30f : e;
+    if (te >= 0.0f) {
+        atomicMax(tile_err + s.tile, __float_as_uint(te));
         atomicAdd(tile_cnt + s.tile, 1u);
     }
     err[i] = e;
