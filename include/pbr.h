@@ -258,6 +258,7 @@ int pbr_set_exit_recording(pbr_ctx *ctx, int64_t first, int64_t stride, int64_t 
 int pbr_emit_and_trace(pbr_ctx *ctx, const float *src_dev, int64_t n_src, int32_t rays_per_src,
                        uint64_t seed, double ds, uint32_t flags, pbr_stats *stats_host);
 
+
 /* Precision policy for steep-gradient (shock) cells.  Finds the steep bricks of the current field
  * (largest node |grad n| >= steep_frac times the grid maximum), and in each traces rays_per_brick
  * sample rays (uniform start in the brick, aimed at a uniform aperture point) over enough full
@@ -609,7 +610,8 @@ int pbr_surrogate_adam_step(pbr_surrogate *s, const float *x_dev, const float *t
  * the validation samples that reach the sensor are pushed through lens and sensor from the
  * predicted exit and compared with the tracer's hit, which fixes the fallback map (a tile with a
  * validation ray that enters through z_min but leaves through another face is never eligible;
- * rays that reach the sensor one way but not the other are counted, not used).  The
+ * rays that reach the sensor one way but not the other are counted and make their tile
+ * ineligible too).  The
  * context's sensor accumulator and counters are left untouched; its trace workspace is used as
  * scratch.  Synchronises.  Errors: STATE (context not ready, host-only context), ARG, HIP. */
 int pbr_surrogate_train(pbr_surrogate *s, pbr_ctx *ctx, const float *train_src_dev, int64_t n_train_src,
@@ -647,6 +649,27 @@ int pbr_set_surrogate(pbr_ctx *ctx, pbr_surrogate *s);
  * pixels of a spot do), timed with HIP events on the null stream after one warm-up launch.
  * Allocates and frees its own buffer; synchronises.  Errors: ARG, HIP. */
 int pbr_probe_u64_atomics(int device, int64_t n_slots, int64_t n_updates, double *updates_per_s);
+
+/* Vector fused multiply-add rate of the device in FLOP/s (2 per FMA): FP32 (fp64 = 0; plain
+ * single-lane instructions, the library being built with packed FP32 instructions disabled) or
+ * FP64, eight independent chains per lane, four 256-thread blocks per SIMD, timed as above after
+ * a warm-up launch.  The ceiling of the integration kernels' arithmetic.  Allocates and frees its own
+ * output buffer; synchronises.  Errors: ARG, HIP. */
+int pbr_probe_fma_rate(int device, int fp64, double *flop_per_s);
+
+/* Read bandwidth in bytes/s: total_bytes read as float4 from a buffer of buffer_bytes (a power of
+ * two, >= 64 KiB, zero-filled; read repeatedly when smaller than total_bytes).  A buffer that fits
+ * the L2 caches (a few MiB) measures L2 bandwidth, one far above the 256 MB Infinity Cache measures
+ * HBM.  scattered = 0: consecutive lanes read consecutive 16-byte words (fully used lines);
+ * scattered = 1: every lane reads one 16-byte word of its own 128-byte line (the shape of a field
+ * gather whose lanes sit in different cells).  Allocates and frees its buffers; synchronises.
+ * Errors: ARG (sizes), HIP. */
+int pbr_probe_read_bandwidth(int device, int64_t buffer_bytes, int64_t total_bytes, int scattered,
+                             double *bytes_per_s);
+
+/* LDS read bandwidth in bytes/s (16-byte reads without bank conflicts, four 256-thread blocks per
+ * SIMD).  Synchronises.  Errors: ARG, HIP. */
+int pbr_probe_lds_bandwidth(int device, double *bytes_per_s);
 
 #ifdef __cplusplus
 }

@@ -49,7 +49,8 @@ EXPORTED = ["pbr_create", "pbr_destroy", "pbr_last_error", "pbr_set_stream",
             "pbr_bos_theory_map", "pbr_displace_sources", "pbr_mie_table", "pbr_mie_workspace_bytes",
             "pbr_set_mie", "pbr_set_optical_chain", "pbr_field_workspace_bytes_nodes",
             "pbr_set_density_field_nodes", "pbr_surrogate_blob_bytes", "pbr_surrogate_save",
-            "pbr_surrogate_load"]
+            "pbr_surrogate_load", "pbr_probe_fma_rate",
+            "pbr_probe_read_bandwidth", "pbr_probe_lds_bandwidth"]
 
 
 class PbrError(RuntimeError):
@@ -206,6 +207,9 @@ def load(path: str = LIB_PATH):
         "pbr_surrogate_save": (I, [P, P, C.c_size_t]),
         "pbr_surrogate_load": (I, [P, P, P, C.c_size_t]),
         "pbr_probe_u64_atomics": (I, [I, I64, I64, C.POINTER(D)]),
+        "pbr_probe_fma_rate": (I, [I, I, C.POINTER(D)]),
+        "pbr_probe_read_bandwidth": (I, [I, I64, I64, I, C.POINTER(D)]),
+        "pbr_probe_lds_bandwidth": (I, [I, C.POINTER(D)]),
         "pbr_set_source_sums": (I, [P, P, I64]),
         "pbr_dot_map_workspace_bytes": (C.c_size_t, [I, I]),
         "pbr_dot_displacement_map": (I, [P, P, P, P, I64, C.POINTER(pbr_map_grid), P, C.c_size_t, P]),
@@ -578,11 +582,12 @@ def u16_image_to_numpy(t) -> np.ndarray:
     return t.cpu().numpy().view(np.uint16)
 
 
-def trace_scene(scene, flags=PBR_CLEAR_FIRST, stats=True, record=None, rho=None, src=None, nodes=False):
+def trace_scene(scene, flags=PBR_CLEAR_FIRST, stats=True, record=None, rho=None, src=None, nodes=False,
+                rays_per_chunk=1 << 22):
     """Convenience: render a scene; ``record`` = (first, stride, max) for exit records.
     Returns (renderer, stats dict, records or None)."""
     from . import inputs
-    r = Renderer.from_scene(scene, rho=rho, nodes=nodes)
+    r = Renderer.from_scene(scene, rho=rho, nodes=nodes, rays_per_chunk=rays_per_chunk)
     if record is not None:
         r.set_exit_recording(*record)
         flags |= PBR_RECORD_EXITS
@@ -869,3 +874,31 @@ def pbr_probe_u64_atomics(device=0, n_slots=1 << 20, n_updates=1 << 28) -> float
     if code != PBR_OK:
         raise PbrError(code, "atomic probe failed")
     return float(rate.value)
+
+
+def pbr_probe_fma_rate(device=0, fp64=False) -> float:
+    """Vector FMA rate of the device, FLOP/s (FP32 without packed instructions, or FP64)."""
+    v = C.c_double()
+    code = load().pbr_probe_fma_rate(int(device), int(bool(fp64)), C.byref(v))
+    if code != PBR_OK:
+        raise PbrError(code, "FMA-rate probe failed")
+    return float(v.value)
+
+
+def pbr_probe_read_bandwidth(device=0, buffer_bytes=1 << 20, total_bytes=1 << 34, scattered=False) -> float:
+    """Read bandwidth, bytes/s, from a buffer of buffer_bytes (L2-resident when small, HBM when large)."""
+    v = C.c_double()
+    code = load().pbr_probe_read_bandwidth(int(device), int(buffer_bytes), int(total_bytes), int(bool(scattered)),
+                                           C.byref(v))
+    if code != PBR_OK:
+        raise PbrError(code, "read-bandwidth probe failed")
+    return float(v.value)
+
+
+def pbr_probe_lds_bandwidth(device=0) -> float:
+    """LDS read bandwidth, bytes/s."""
+    v = C.c_double()
+    code = load().pbr_probe_lds_bandwidth(int(device), C.byref(v))
+    if code != PBR_OK:
+        raise PbrError(code, "LDS-bandwidth probe failed")
+    return float(v.value)
