@@ -1,11 +1,17 @@
 """Benchmark: rays per second of the full per-ray pipeline (emit -> index-grid integration ->
-thick lens -> sensor deposit) on one MI355X, on the BOS-through-turbulence workload:
-128^3 k^-5/3 random-phase density field (ratio 1.05) over a 10 cm box, 50 000 dots x 1000 rays
-(5e7 rays per image), f = 105 mm f/11 lens, 1024^2 sensor of 10 um pixels, ds = 0.1 mm.
+thick lens -> sensor deposit) on one MI355X.
 
-One step = one pbr_emit_and_trace call over the whole image (sensor cleared on the device first);
-the density field, sources and buffers are resident in HBM before timing starts.  Prints one JSON
-line.  The CPU baseline is the FP64 oracle timed on a bounded prefix of the same sources.
+Default workload (tomo_piv_512): a Tomo-PIV image through a normal shock, 512^3 grid over
+10 x 10 x 3 cm (tanh density step 1.2 -> 3.0 kg/m^3 over 0.2 mm), 1e5 particles inside the box
+x 1e4 rays = 1e9 rays per image, f = 105 mm f/11 lens focused on the mid-plane, 2048^2 sensor of
+10 um pixels read out as 16-bit, ds = 0.1 mm, FP32 integration; the same image again with FP64
+steps in the bricks the precision calibration flags (at 1e-3 px).  The BOS-through-turbulence
+workload (128^3 field, 5e7 rays) is reported beside it.
+
+One step = one pbr_emit_and_trace call over the whole image (sensor cleared on the device first)
+plus the 16-bit readout; the density field, sources and buffers are resident in HBM before timing
+starts.  Prints one JSON line.  The CPU baseline is the FP64 oracle timed on a bounded prefix of
+the same sources, on all host threads and on one.
 """
 from __future__ import annotations
 
@@ -19,13 +25,19 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# FP32 operations of one Runge-Kutta step of the method (eqs. 3, 5, 6): three evaluations of D,
-# each a trilinear interpolation of four quantities (4 x 7 lerps x 3 ops) plus n = 1 + dn and
-# D = n grad n (4 ops) = 88; the stage points and updates: A, B, C = h D (9), stage B point (15),
-# stage C point (12), R update (18), T update (15).  3 * 88 + 69 = 333.
-FLOPS_PER_STEP = 333
+# FP32 operations of one Runge-Kutta step of the method (eqs. 3, 5, 6), per field layout.  Three
+# evaluations of D = n grad n, each a trilinear interpolation of four quantities plus n = 1 + dn
+# and D = n grad n (4 operations), and 69 for the stage points and updates: A, B, C = h D (9),
+# stage B point (15), stage C point (12), R update (18), T update (15).
+#   cells: the interpolant from the cell's polynomial coefficients, 7 multiply-adds (14 operations)
+#          per quantity: 3 * (4 * 14 + 4) + 69 = 249;
+#   nodes: from the eight corner values, 7 linear interpolations a + t (b - a) (3 operations) per
+#          quantity: 3 * (4 * 21 + 4) + 69 = 333.
+FLOPS_PER_STEP = {"cells": 249, "nodes": 333}
 PEAK_FP32_TFLOPS = 157.3  # MI355X vector FP32, published
-PMC_FILE = os.path.join(ROOT, "profiles", "trace_turbulence_bos_128_pmc.json")
+PMC_FILES = {"turbulence_bos_128": os.path.join(ROOT, "profiles", "trace_turbulence_bos_128_pmc.json"),
+             "tomo_piv_512": os.path.join(ROOT, "profiles", "tomo_piv_512_pmc.json")}
+PMC_FILE = PMC_FILES["turbulence_bos_128"]
 
 
 def _kernel_source_hash() -> str:
@@ -36,20 +48,20 @@ def _kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def _profile():
-    """The committed rocprofv3 counter summary of the integration kernel, if it was taken on the
-    current kernel source; else None."""
+def _profile(workload="turbulence_bos_128"):
+    """The committed rocprofv3 counter summary of the workload's integration kernel, if it was taken
+    on the current kernel source; else None."""
     try:
-        with open(PMC_FILE) as fh:
+        with open(PMC_FILES[workload]) as fh:
             d = json.load(fh)
-    except (OSError, ValueError):
+    except (OSError, ValueError, KeyError):
         return None
     return d if d.get("kernel_source_hash") == _kernel_source_hash() else None
 
 
-def _traffic_from_profile():
+def _traffic_from_profile(workload="turbulence_bos_128"):
     """HBM bytes per trace launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated) or None."""
-    d = _profile()
+    d = _profile(workload)
     return d.get("hbm_bytes_per_launch") if d else None
 
 
@@ -57,48 +69,87 @@ HBM_PEAK_GBS = 8000.0
 GATHER_BYTES_PER_STEP = 384  # the method's field reads per step: 3 evaluations x 8 corners x float4
 
 
-def memory_roofline(steps_per_launch, kernel_ms):
+def memory_roofline(steps_per_launch, kernel_ms, workload="turbulence_bos_128", peaks=None):
     """Memory-side view of the integration kernel: HBM and L2 traffic per launch from the committed
-    counters (when current) over the live kernel time, and the method's algorithmic gather rate."""
-    out = {"algorithmic_gather_bytes_per_step": GATHER_BYTES_PER_STEP,
-           "algorithmic_gather_GBps": steps_per_launch * GATHER_BYTES_PER_STEP / (kernel_ms * 1e-3) / 1e9}
-    d = _profile()
+    counters (when current) over the live kernel time, and the method's algorithmic gather rate
+    against the measured L2 read peak."""
+    g = steps_per_launch * GATHER_BYTES_PER_STEP / (kernel_ms * 1e-3) / 1e9
+    out = {"algorithmic_gather_bytes_per_step": GATHER_BYTES_PER_STEP, "algorithmic_gather_GBps": g}
+    if peaks and peaks.get("l2_read_GBps"):
+        out["algorithmic_gather_over_measured_l2_peak"] = g / peaks["l2_read_GBps"]
+    d = _profile(workload)
     if d:
         hbm = d["hbm_bytes_per_launch"] / (kernel_ms * 1e-3) / 1e9
-        out.update({"hbm_GBps": hbm, "hbm_frac": hbm / HBM_PEAK_GBS,
-                    "l2_read_GBps": d["l2_read_bytes_per_launch"] / (kernel_ms * 1e-3) / 1e9})
+        out.update({"hbm_GBps": hbm, "hbm_frac": hbm / HBM_PEAK_GBS})
+        if "l2_read_bytes_per_launch" in d:
+            out["l2_read_GBps"] = d["l2_read_bytes_per_launch"] / (kernel_ms * 1e-3) / 1e9
     return out
 
 
-def cpu_baseline(scene, rho, src, target_s: float = 15.0):
-    """FP64 oracle on a prefix of the sources, all host threads; rays/s."""
-    import oracle
-    o = oracle.scene_oracle(scene, rho=rho)
-    threads = oracle.num_threads()
-    n_cal = 4 * threads
+def measured_peaks():
+    """The device's ceilings measured by the library's probes (a few ms each)."""
+    from paper_1812_05902_amd import pbr
+    return {"fp32_fma_TFLOPs": pbr.pbr_probe_fma_rate(0, False) / 1e12,
+            "fp64_fma_TFLOPs": pbr.pbr_probe_fma_rate(0, True) / 1e12,
+            "l2_read_GBps": pbr.pbr_probe_read_bandwidth(0, 1 << 20, 1 << 35, False) / 1e9,
+            "l2_scattered_read_GBps": pbr.pbr_probe_read_bandwidth(0, 1 << 20, 1 << 33, True) / 1e9,
+            "hbm_read_GBps": pbr.pbr_probe_read_bandwidth(0, 1 << 33, 1 << 33, False) / 1e9,
+            "lds_read_GBps": pbr.pbr_probe_lds_bandwidth(0) / 1e9,
+            "u64_atomics_per_s": pbr.pbr_probe_u64_atomics(0, 1 << 22, 1 << 28)}
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_rate(o, scene, src, threads, target_s):
+    """Rays/s of the oracle over the first sources of src on `threads` threads, about target_s of work."""
+    n_cal = max(1, threads)
     t0 = time.perf_counter()
-    o.render(src[:n_cal], scene.rays_per_src, want_float=False)
+    o.render(src[:n_cal], scene.rays_per_src, n_threads=threads, want_float=False)
     t_cal = time.perf_counter() - t0
     n = int(min(len(src), max(n_cal, n_cal * target_s / max(t_cal, 1e-3))))
     t0 = time.perf_counter()
-    o.render(src[:n], scene.rays_per_src, want_float=False)
+    o.render(src[:n], scene.rays_per_src, n_threads=threads, want_float=False)
     dt = time.perf_counter() - t0
     rays = n * scene.rays_per_src
-    return {"value": rays / dt, "unit": "rays/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {n} of {len(src)} sources x {scene.rays_per_src} rays "
-                      f"({rays} rays, {dt:.1f} s, FP64 oracle, OpenMP over sources)"}
+    return rays / dt, (f"first {n} of {len(src)} sources x {scene.rays_per_src} rays ({rays} rays, {dt:.1f} s, "
+                       f"{threads} thread{'s' if threads > 1 else ''})")
+
+
+def cpu_baseline(scene, rho, src, target_s: float = 15.0, single_s: float = 8.0):
+    """FP64 oracle on a prefix of the sources: all host threads (OpenMP over sources), then one."""
+    import oracle
+    o = oracle.scene_oracle(scene, rho=rho)
+    threads = oracle.num_threads()
+    v, sample = _oracle_rate(o, scene, src, threads, target_s)
+    v1, sample1 = _oracle_rate(o, scene, src, 1, single_s)
+    return {"value": v, "unit": "rays/s", "cores": threads, "kind": "oracle",
+            "sample": sample + "; FP64 oracle, same scene and sources as the GPU step",
+            "single_core": {"value": v1, "sample": sample1},
+            "cpu_model": _cpu_model(), "nproc": os.cpu_count(),
+            "affinity_cpus": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="turbulence_bos_128",
-                    choices=["turbulence_bos_128", "batch64", "surrogate256", "tomo_piv_512", "bos_fig4",
+    ap.add_argument("--workload", default="tomo_piv_512",
+                    choices=["tomo_piv_512", "turbulence_bos_128", "batch64", "surrogate256", "bos_fig4",
                              "piv_pair_512"],
-                    help="batch64: the 64 uneven images of inputs.batch_scenes in one graph-captured batch; "
+                    help="tomo_piv_512 (default): the 1e9-ray Tomo-PIV image through a 512^3 shock field, with "
+                         "the 128^3 BOS workload reported beside it; turbulence_bos_128: that BOS workload alone; "
+                         "batch64: the 64 uneven images of inputs.batch_scenes in one graph-captured batch; "
                          "surrogate256: train the ray surrogate on a 256^3 turbulence field, then 1e9 rays "
                          "with and without it; bos_fig4: the BOS displacement check of sec. 4 (two renders, "
                          "per-dot displacement map, eq. 9 map); piv_pair_512: both frames of a Tomo-PIV pair "
@@ -109,10 +160,14 @@ def main():
                          "one per workload")
     ap.add_argument("--rays-per-chunk", type=int, default=1 << 24,
                     help="rays per trace chunk (64 bytes of ray state each; the bos_fig4 renders use one chunk)")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="tomo_piv_512: leave out the shock-FP64 leg, the 128^3 BOS workload and the peak probes "
+                         "(for profiling runs; the headline value is unchanged)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy a 1 GiB device buffer 4 times (calibrates HBM byte counters)")
     ap.add_argument("--atomic-probe", action="store_true",
                     help="only measure the device's rate of 64-bit atomic additions (sensor-sized buffer)")
+    ap.add_argument("--peaks", action="store_true", help="only run the library's peak probes")
     args = ap.parse_args()
     if args.atomic_probe:
         from paper_1812_05902_amd import pbr
@@ -135,9 +190,9 @@ def main():
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the renderer has no "
               "multi-GPU path", file=sys.stderr)
         sys.exit(2)
-
-    import torch
-    from paper_1812_05902_amd import inputs, pbr
+    if args.peaks:
+        print(json.dumps(measured_peaks()), flush=True)
+        return
 
     if args.workload == "batch64":
         return bench_batch(args)
@@ -149,11 +204,27 @@ def main():
         return bench_bos_fig4(args)
     if args.workload == "piv_pair_512":
         return bench_piv_pair(args)
+    out = bench_turbulence(args)
+    if not args.no_cpu_baseline:
+        from paper_1812_05902_amd import inputs
+        scene = inputs.turbulence_bos()
+        out["cpu_baseline"] = cpu_baseline(scene, inputs.density(scene), inputs.sources(scene))
+    print(json.dumps(out), flush=True)
+
+
+def bench_turbulence(args, steps=None, warmup=None, peaks=None):
+    """The BOS-through-turbulence workload: 128^3 k^-5/3 random-phase field (ratio 1.05) over a
+    10 cm box, 50 000 dots x 1000 rays (5e7 rays per image), f = 105 mm f/11, 1024^2 sensor of
+    10 um pixels, ds = 0.1 mm, per-cell field records.  Returns the bench record (no CPU baseline)."""
+    import torch
+    from paper_1812_05902_amd import inputs, pbr
+    steps = args.steps if steps is None else steps
+    warmup = args.warmup if warmup is None else warmup
+    layout = "nodes" if args.field_layout == "nodes" else "cells"
     scene = inputs.turbulence_bos()
     rho = inputs.density(scene)
     src = inputs.sources(scene)
-    r = pbr.Renderer.from_scene(scene, rho=rho, rays_per_chunk=args.rays_per_chunk,
-                                nodes=args.field_layout == "nodes")
+    r = pbr.Renderer.from_scene(scene, rho=rho, rays_per_chunk=args.rays_per_chunk, nodes=layout == "nodes")
     src_dev = torch.as_tensor(src, device=r.device).contiguous()
     torch.cuda.synchronize()
 
@@ -161,12 +232,12 @@ def main():
         return r.emit_and_trace(src_dev, scene.rays_per_src, scene.ray_seed, scene.ds,
                                 pbr.PBR_CLEAR_FIRST, stats=stats)
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         step(False)
     torch.cuda.synchronize()
     box_ms, box_launches, trace_ms, steps_total = 0.0, 0, 0.0, 0
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         # HIP events on the launch stream around each integration launch and around the trace
         st = step(True)
         box_ms += st["box_ms"]
@@ -175,20 +246,21 @@ def main():
         steps_total += st["rkn_steps"]
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    r.close()
 
     n_rays = scene.n_rays
-    value = n_rays * args.steps / wall
+    value = n_rays * steps / wall
     avg_ms = box_ms / box_launches
-    flops_per_launch = steps_total * FLOPS_PER_STEP / box_launches
-    achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12
-    out = {
+    fps = FLOPS_PER_STEP[layout]
+    achieved = steps_total * fps / box_launches / (avg_ms * 1e-3) / 1e12
+    return {
         "metric": "rays/sec on 1 MI355X (trace+lens+sensor)",
         "value": value,
         "unit": "rays/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": wall / args.steps * 1e3,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": wall / steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -197,21 +269,18 @@ def main():
         "config": {"workload": "turbulence_bos_128", "grid": "128^3", "n_src": scene.n_src,
                    "rays_per_src": scene.rays_per_src, "rays_per_image": n_rays,
                    "sensor": f"{scene.width}x{scene.height}", "ds_m": scene.ds,
-                   "rays_per_chunk": args.rays_per_chunk,
-                   "field_layout": "nodes" if args.field_layout == "nodes" else "cells",
-                   "mean_rkn_steps_per_ray": steps_total / args.steps / n_rays},
+                   "rays_per_chunk": args.rays_per_chunk, "field_layout": layout,
+                   "mean_rkn_steps_per_ray": steps_total / steps / n_rays},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
-                     "traffic": _traffic_from_profile(),
-                     "kernel": "k_box32", "kernel_ms_per_launch": avg_ms,
-                     "launches_per_step": box_launches / args.steps,
-                     "trace_ms_per_step": trace_ms / args.steps,
-                     "flops_per_rkn_step": FLOPS_PER_STEP},
-        "memory": memory_roofline(steps_total / box_launches, avg_ms),
+                     "traffic": _traffic_from_profile("turbulence_bos_128"),
+                     "kernel": f"k_box32<{'true' if layout == 'nodes' else 'false'}>",
+                     "kernel_ms_per_launch": avg_ms,
+                     "launches_per_step": box_launches / steps,
+                     "trace_ms_per_step": trace_ms / steps,
+                     "flops_per_rkn_step": fps},
+        "memory": memory_roofline(steps_total / box_launches, avg_ms, "turbulence_bos_128", peaks),
     }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(scene, rho, src)
-    print(json.dumps(out), flush=True)
 
 
 def bench_batch(args):
@@ -255,7 +324,7 @@ def bench_batch(args):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     n_rays = sum(sc.n_rays for sc in scenes)
-    achieved = steps * FLOPS_PER_STEP / (run_ms * 1e-3) / 1e12
+    achieved = steps * FLOPS_PER_STEP["cells"] / (run_ms * 1e-3) / 1e12
     out = {
         "metric": "rays/sec on 1 MI355X (trace+lens+sensor)", "value": n_rays * args.steps / wall,
         "unit": "rays/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -267,73 +336,100 @@ def bench_batch(args):
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
                      "kernel": "whole batch graph (emit + persistent k_box_batch + finish)",
-                     "graph_ms_per_step": run_ms / args.steps, "flops_per_rkn_step": FLOPS_PER_STEP},
+                     "graph_ms_per_step": run_ms / args.steps, "flops_per_rkn_step": FLOPS_PER_STEP["cells"]},
     }
     print(json.dumps(out), flush=True)
 
 
 def bench_tomo(args):
-    """Tomo-PIV scale: 512^3 shock field, 1e5 particles x 1e4 rays = 1e9 rays, 2048^2 sensor with
-    16-bit readout inside the step; FP32 integration, and again with FP64 steps in the bricks the
-    calibration flags (1e-3 px)."""
+    """Tomo-PIV scale (the default): 512^3 shock field, 1e5 particles x 1e4 rays = 1e9 rays, 2048^2
+    sensor with 16-bit readout inside the step; FP32 integration (the value), and again with FP64
+    steps in the bricks the calibration flags (1e-3 px).  The dominant kernel is the integration of
+    the FP32 leg: its average launch duration comes from HIP events recorded on the launch stream
+    around every launch of the timed steps."""
     import torch
     from paper_1812_05902_amd import inputs, pbr
 
+    extra = not args.no_extra
     sc = inputs.tomo_piv_shock()
     t0 = time.perf_counter()
     rho = inputs.density(sc)
-    # the precision calibration and the shock-FP64 leg need the per-cell field; the FP32 leg takes
-    # the node layout unless told otherwise (faster on this fine grid)
-    r = pbr.Renderer.from_scene(sc, rho=rho, rays_per_chunk=args.rays_per_chunk)
-    nodes = args.field_layout != "cells"
-    rn = pbr.Renderer.from_scene(sc, rho=rho, nodes=True, rays_per_chunk=args.rays_per_chunk) if nodes else r
+    # the FP32 leg takes the node layout unless told otherwise (faster on this fine grid); the
+    # precision calibration and the shock-FP64 leg need the per-cell field
+    layout = "cells" if args.field_layout == "cells" else "nodes"
+    rn = pbr.Renderer.from_scene(sc, rho=rho, nodes=layout == "nodes", rays_per_chunk=args.rays_per_chunk)
+    rc = None
+    if extra:
+        rc = rn if layout == "cells" else pbr.Renderer.from_scene(sc, rho=rho, rays_per_chunk=args.rays_per_chunk)
+    rho_cpu = rho if not args.no_cpu_baseline else None
     del rho
-    src = torch.as_tensor(inputs.sources(sc), device=r.device).contiguous()
-    out16 = torch.empty(sc.height, sc.width, dtype=torch.int16, device=r.device)
+    src_np = inputs.sources(sc)
+    src = torch.as_tensor(src_np, device=rn.device).contiguous()
+    out16 = torch.empty(sc.height, sc.width, dtype=torch.int16, device=rn.device)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
-    cal = r.calibrate_precision(sc.ds, tol_px=1e-3)
+    cal = rc.calibrate_precision(sc.ds, tol_px=1e-3) if extra else None
     print(f"set up in {setup_s:.1f} s; calibration {cal}", file=sys.stderr, flush=True)
 
-    def step(flags, stats):
-        rr = r if flags else rn
-        st = rr.emit_and_trace(src, sc.rays_per_src, sc.ray_seed, sc.ds, pbr.PBR_CLEAR_FIRST | flags, stats=stats)
-        pbr.pbr_read_image(rr.ctx, pbr.PBR_FMT_U16, out16, 0.0)
+    def step(r, flags, stats):
+        st = r.emit_and_trace(src, sc.rays_per_src, sc.ray_seed, sc.ds, pbr.PBR_CLEAR_FIRST | flags, stats=stats)
+        pbr.pbr_read_image(r.ctx, pbr.PBR_FMT_U16, out16, 0.0)
         return st
 
+    legs = [("fp32", rn, 0)] + ([("shock_fp64", rc, pbr.PBR_PREC_SHOCK_FP64)] if extra else [])
     res = {}
-    for name, flags in (("fp32", 0), ("shock_fp64", pbr.PBR_PREC_SHOCK_FP64)):
+    for name, r, flags in legs:
         for _ in range(args.warmup):
-            step(flags, False)
+            step(r, flags, False)
         torch.cuda.synchronize()
         box_ms, launches, steps_total = 0.0, 0, 0
         t1 = time.perf_counter()
         for _ in range(args.steps):
-            st = step(flags, True)
+            st = step(r, flags, True)
             box_ms += st["box_ms"]
             launches += st["box_launches"]
             steps_total += st["rkn_steps"]
         torch.cuda.synchronize()
         res[name] = (time.perf_counter() - t1, box_ms, launches, steps_total, st)
+        print(f"{name}: {res[name][0] / args.steps * 1e3:.1f} ms per image", file=sys.stderr, flush=True)
     wall, box_ms, launches, steps_total, st = res["fp32"]
-    achieved = steps_total * FLOPS_PER_STEP / (box_ms * 1e-3) / 1e12
+    for r in {id(x): x for x in (rn, rc) if x is not None}.values():
+        r.close()
+    del rn, rc
+    torch.cuda.empty_cache()
+    fps = FLOPS_PER_STEP[layout]
+    avg_ms = box_ms / launches
+    achieved = steps_total * fps / launches / (avg_ms * 1e-3) / 1e12
+    peaks = measured_peaks() if extra else None
     out = {
         "metric": "rays/sec on 1 MI355X (trace+lens+sensor)", "value": sc.n_rays * args.steps / wall,
         "unit": "rays/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "tomo_piv_512", "grid": "512^3", "rays_per_chunk": args.rays_per_chunk, "n_src": sc.n_src, "rays_per_src": sc.rays_per_src,
+        "config": {"workload": "tomo_piv_512", "grid": "512^3 over 10 x 10 x 3 cm, tanh shock 1.2 -> 3.0 kg/m^3",
+                   "rays_per_chunk": args.rays_per_chunk, "n_src": sc.n_src, "rays_per_src": sc.rays_per_src,
                    "rays_per_image": sc.n_rays, "sensor": f"{sc.width}x{sc.height} u16", "ds_m": sc.ds,
                    "mean_rkn_steps_per_ray": steps_total / args.steps / sc.n_rays, "setup_s": setup_s,
-                   "field_layout": "nodes" if nodes else "cells"},
-        "shock_fp64": {"rays_per_s": sc.n_rays * args.steps / res["shock_fp64"][0],
-                       "fp64_bricks": cal["n_fp64"], "steep_bricks": cal["n_steep"],
-                       "calibration_max_err_px": cal["max_err_px"],
-                       "rkn_steps_fp64": res["shock_fp64"][4]["rkn_steps_fp64"]},
+                   "field_layout": layout},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None, "kernel": "k_box32",
-                     "kernel_ms_per_launch": box_ms / launches, "flops_per_rkn_step": FLOPS_PER_STEP},
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": _traffic_from_profile("tomo_piv_512"),
+                     "kernel": f"k_box32<{'true' if layout == 'nodes' else 'false'}>",
+                     "kernel_ms_per_launch": avg_ms, "launches_per_step": launches / args.steps,
+                     "rkn_steps_per_launch": steps_total / launches, "flops_per_rkn_step": fps},
+        "memory": memory_roofline(steps_total / launches, avg_ms, "tomo_piv_512", peaks),
     }
+    if extra:
+        out["shock_fp64"] = {"rays_per_s": sc.n_rays * args.steps / res["shock_fp64"][0],
+                             "field_layout": "cells", "fp64_bricks": cal["n_fp64"], "steep_bricks": cal["n_steep"],
+                             "calibration_max_err_px": cal["max_err_px"],
+                             "rkn_steps_fp64": res["shock_fp64"][4]["rkn_steps_fp64"]}
+        out["measured_peaks"] = peaks
+        out["roofline"]["frac_of_measured_fp32_fma_rate"] = achieved / peaks["fp32_fma_TFLOPs"]
+        tb = bench_turbulence(args, steps=10, warmup=2, peaks=peaks)
+        out["turbulence_bos_128"] = {"rays_per_s": tb["value"], "ms_per_step": tb["ms_per_step"],
+                                     "config": tb["config"], "roofline": tb["roofline"], "memory": tb["memory"]}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(sc, rho_cpu, src_np)
     print(json.dumps(out), flush=True)
 
 
@@ -384,7 +480,7 @@ def bench_bos_fig4(args):
     sim, th = sim.cpu().numpy().astype(np.float64), th.cpu().numpy().astype(np.float64)
     f = np.isfinite(sim[:, :, 0])
     x, y = sim[f].ravel(), th[f].ravel()
-    achieved = steps_total * FLOPS_PER_STEP / (box_ms * 1e-3) / 1e12
+    achieved = steps_total * FLOPS_PER_STEP["nodes" if nodes else "cells"] / (box_ms * 1e-3) / 1e12
     n_rays = 2 * sc.n_rays
     out = {
         "metric": "rays/sec on 1 MI355X (trace+lens+sensor)", "value": n_rays * args.steps / wall,
@@ -401,7 +497,8 @@ def bench_bos_fig4(args):
                  "eq9_max_px": float(np.abs(y).max()), "nodes_filled": int(f.sum())},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None, "kernel": "k_box32",
-                     "kernel_ms_per_launch": box_ms / launches, "flops_per_rkn_step": FLOPS_PER_STEP,
+                     "kernel_ms_per_launch": box_ms / launches,
+                     "flops_per_rkn_step": FLOPS_PER_STEP["nodes" if nodes else "cells"],
                      "mean_rkn_steps_per_ray": steps_total / args.steps / n_rays},
     }
     print(json.dumps(out), flush=True)
@@ -450,7 +547,7 @@ def bench_piv_pair(args):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t1
     moved = (src_b[:, :2] - src[:, :2]).abs().max().item()
-    achieved = steps_total * FLOPS_PER_STEP / (box_ms * 1e-3) / 1e12
+    achieved = steps_total * FLOPS_PER_STEP["nodes" if nodes else "cells"] / (box_ms * 1e-3) / 1e12
     n_rays = 2 * sc.n_rays
     out = {
         "metric": "rays/sec on 1 MI355X (trace+lens+sensor)", "value": n_rays * args.steps / wall,
@@ -464,7 +561,8 @@ def bench_piv_pair(args):
                    "field_layout": "nodes" if nodes else "cells"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None, "kernel": "k_box32",
-                     "kernel_ms_per_launch": box_ms / launches, "flops_per_rkn_step": FLOPS_PER_STEP,
+                     "kernel_ms_per_launch": box_ms / launches,
+                     "flops_per_rkn_step": FLOPS_PER_STEP["nodes" if nodes else "cells"],
                      "mean_rkn_steps_per_ray": steps_total / args.steps / n_rays},
     }
     print(json.dumps(out), flush=True)

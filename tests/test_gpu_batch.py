@@ -128,3 +128,85 @@ def test_autotune_and_cache(torch, tmp_path):
         r.emit_and_trace(s, sc.rays_per_src, sc.ray_seed, sc.ds, pbr.PBR_CLEAR_FIRST)
         assert np.array_equal(pbr.u64_image_to_numpy(rs[k].read_image()), pbr.u64_image_to_numpy(r.read_image()))
     assert st["rays"] == sum(sc.n_rays for sc in scenes)
+
+
+def test_batch_refuses_contexts_changed_since_creation(torch):
+    """A batch replays launch parameters taken from its contexts at creation: after a context's
+    sensor or exit recording changes, running (or tuning) the batch fails with STATE instead of
+    tracing through stale pointers; a new batch over the changed contexts runs."""
+    scenes = _small_batch(2)
+    srcs = [inputs.sources(sc) for sc in scenes]
+    rs = _renderers(scenes)
+    mk = lambda: pbr.Batch(rs, srcs, [sc.rays_per_src for sc in scenes], [sc.ray_seed for sc in scenes],
+                           [sc.ds for sc in scenes], round_rays=1 << 16)
+    b = mk()
+    b.run()
+    sc = scenes[1]
+    rs[1].set_sensor(sc.width // 2, sc.height // 2, sc.pitch, sc.z_sensor, sc.wavelength, sc.sigma_px,
+                     sc.dtau_with_pi)
+    for call in (b.run, lambda: b.autotune(probe_rounds=1)):
+        with pytest.raises(pbr.PbrError) as ei:
+            call()
+        assert ei.value.code == pbr.PBR_ERR_STATE
+    b.close()
+    b = mk()
+    b.run()
+    rs[0].set_exit_recording(0, 1, 10)
+    with pytest.raises(pbr.PbrError) as ei:
+        b.run()
+    assert ei.value.code == pbr.PBR_ERR_STATE
+    b.close()
+
+
+def _batch_vs_oracle(scenes, k, stride, tol_px=1e-4):
+    """Renders the scenes as one batch with exit records on image k (every stride-th ray) and
+    compares image k's records and image with the oracle's."""
+    import oracle
+    srcs = [inputs.sources(sc) for sc in scenes]
+    rs = _renderers(scenes)
+    sc = scenes[k]
+    nrec = (sc.n_rays + stride - 1) // stride
+    rs[k].set_exit_recording(0, stride, nrec)
+    flags = [pbr.PBR_CLEAR_FIRST | (pbr.PBR_RECORD_EXITS if i == k else 0) for i in range(len(scenes))]
+    b = pbr.Batch(rs, srcs, [s.rays_per_src for s in scenes], [s.ray_seed for s in scenes],
+                  [s.ds for s in scenes], flags=flags, round_rays=1 << 20)
+    st = b.run()
+    rec = rs[k].read_ray_exits()
+    img = pbr.u64_image_to_numpy(rs[k].read_image()).astype(np.float64)
+    o = oracle.scene_oracle(sc)
+    ids = np.arange(0, sc.n_rays, stride)
+    ref = o.trace_ids(srcs[k], sc.rays_per_src, ids)
+    assert np.array_equal(rec["ray_id"], ids)
+    same = rec["status"] == ref["status"]
+    dep = same & (ref["status"] == oracle.DEPOSITED)
+    err = np.abs(rec["sensor_px"][dep] - ref["sensor_px"][dep]).max()
+    print(f"\nbatch of {len(scenes)} ({st['rounds']} rounds), image {k}: {sc.nx}^3 grid, {sc.width}^2 sensor, "
+          f"{sc.n_rays} rays; {dep.sum()} sampled deposited rays, max |dpx| vs oracle {err:.2e}, "
+          f"status mismatches {(~same).sum()}", flush=True)
+    assert same.mean() > 0.999
+    assert dep.sum() > 0.5 * len(ids)
+    assert err <= tol_px
+    b.close()
+    return img, o, srcs[k]
+
+
+def test_batch_image_and_records_match_oracle(torch):
+    """Image 1 of a small uneven batch: every ray's record against the oracle's trace (1e-4 px),
+    and the image against the oracle's Q32.32 render (rel. L2 1e-3)."""
+    import oracle
+    scenes = _small_batch(3)
+    img, o, src = _batch_vs_oracle(scenes, 1, 1)
+    q, _, _ = o.render(src, scenes[1].rays_per_src, want_float=False)
+    rel = oracle.rel_l2(img, q.astype(np.float64))
+    print(f"image rel L2 vs oracle {rel:.2e}")
+    assert rel <= 1e-3
+
+
+def test_full_size_batch64_image_matches_oracle_on_sampled_rays(torch):
+    """Three images of the 64-image workload at full size (their grids, sensors, particle and
+    ray counts) in one batch; the largest is checked against the oracle on about 1500 strided
+    rays."""
+    scenes = inputs.batch_scenes(64)[:3]
+    k = int(np.argmax([sc.nx * 1000 + sc.width for sc in scenes]))
+    stride = max(1, scenes[k].n_rays // 1500)
+    _batch_vs_oracle(scenes, k, stride)

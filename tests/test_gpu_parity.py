@@ -45,12 +45,12 @@ def _compare_records(gpu, ref, tol_px, max_boundary_frac=1e-4, label=""):
     return float(err), mism
 
 
-def _render_all(torch, scene, flags=0, src=None):
+def _render_all(torch, scene, flags=0, src=None, nodes=False):
     if src is None:
         src = inputs.sources(scene)
     n = scene.n_rays
     r, st, recs = pbr.trace_scene(scene, flags=pbr.PBR_CLEAR_FIRST | flags, stats=True,
-                                  record=(0, 1, max(n, 1)), src=src)
+                                  record=(0, 1, max(n, 1)), src=src, nodes=nodes)
     return r, st, recs, src
 
 
@@ -85,10 +85,14 @@ def test_render_is_bitwise_deterministic(torch):
         r.emit_and_trace(src, sc.rays_per_src, sc.ray_seed, sc.ds, pbr.PBR_CLEAR_FIRST)
         imgs.append(pbr.u64_image_to_numpy(r.read_image()))
     assert np.array_equal(imgs[0], imgs[1]) and np.array_equal(imgs[0], imgs[2])
-    # accumulating two half renders equals one full render (integer deposits)
+    # integer deposits accumulate exactly: the first half of the sources rendered twice without
+    # clearing is twice the half image, and differs from the full image
     r.emit_and_trace(src[:500], sc.rays_per_src, sc.ray_seed, sc.ds, pbr.PBR_CLEAR_FIRST)
     half = pbr.u64_image_to_numpy(r.read_image())
-    assert not np.array_equal(half, imgs[0])
+    r.emit_and_trace(src[:500], sc.rays_per_src, sc.ray_seed, sc.ds, 0)
+    twice = pbr.u64_image_to_numpy(r.read_image())
+    assert half.sum() > 0 and not np.array_equal(half, imgs[0])
+    assert np.array_equal(twice, half * np.uint64(2))
 
 
 def test_fp64_path_matches_oracle_tightly(torch):
@@ -119,8 +123,9 @@ def test_ragged_sizes_and_empty(torch):
     assert int(pbr.u64_image_to_numpy(r.read_image()).sum()) == 0
 
 
+@pytest.mark.parametrize("nodes", [False, True], ids=["cells", "nodes"])
 @pytest.mark.parametrize("ds, half", [(4.0e-3, 0.024), (1.2e-3, 0.040), (2.0e-2, 0.024)])
-def test_long_steps_and_rays_along_the_faces_match_oracle(torch, ds, half):
+def test_long_steps_and_rays_along_the_faces_match_oracle(torch, ds, half, nodes):
     """Steps longer than a cell (ds = 4 mm on 1.6 mm cells: up to 2.5 cells per step, so the
     interior margin is three cells on every axis; ds = 20 mm: about 12 cells per step, five
     interior cells per axis, three steps per ray) and, with ds = 1.2 mm, dots spread beyond the box
@@ -128,32 +133,33 @@ def test_long_steps_and_rays_along_the_faces_match_oracle(torch, ds, half):
     integer interior test and the end-point test near the faces are exercised, in FP32 and FP64."""
     sc = inputs.tiny_bos().replace(n_src=300, rays_per_src=40, ds=ds,
                                    src_region=((-half, half), (-half, half), (0.0, 0.0)))
-    r, st, recs, src = _render_all(torch, sc)
+    r, st, recs, src = _render_all(torch, sc, nodes=nodes)
     ref = oracle.scene_oracle(sc).trace_ids(src, sc.rays_per_src, np.arange(sc.n_rays))
     err, mism = _compare_records(recs, ref, TOL_PX, label=f"ds {ds}")
     n_in = int((ref["entered"] == 1).sum())
-    print(f"ds {ds * 1e3:.1f} mm, dots +-{half * 1e3:.0f} mm: {n_in} of {sc.n_rays} rays entered, "
-          f"max |dpx| = {err:.3e}, status mismatches = {mism}")
+    print(f"{'nodes' if nodes else 'cells'}, ds {ds * 1e3:.1f} mm, dots +-{half * 1e3:.0f} mm: {n_in} of "
+          f"{sc.n_rays} rays entered, max |dpx| = {err:.3e}, status mismatches = {mism}")
     assert n_in > sc.n_rays // 4
-    _, _, recs64, _ = _render_all(torch, sc, flags=pbr.PBR_PREC_FP64_ALL, src=src)
-    _compare_records(recs64, ref, TOL_PX_FP64, label=f"ds {ds} fp64")
+    _, _, recs64, _ = _render_all(torch, sc, flags=pbr.PBR_PREC_FP64_ALL, src=src, nodes=nodes)
+    _compare_records(recs64, ref, 1e-6 if nodes else TOL_PX_FP64, label=f"ds {ds} fp64")
 
 
-def test_single_ray_and_sources_inside_box(torch):
+@pytest.mark.parametrize("nodes", [False, True], ids=["cells", "nodes"])
+def test_single_ray_and_sources_inside_box(torch, nodes):
     """PIV: particles inside the density box (shock field on a 48^3 grid), plus the one-ray case."""
     sc = inputs.tomo_piv_shock(n=48, n_src=300, rays_per_src=40).replace(width=512, height=512,
                                                                          pitch=40e-6)
-    r, st, recs, src = _render_all(torch, sc)
+    r, st, recs, src = _render_all(torch, sc, nodes=nodes)
     ref = oracle.scene_oracle(sc).trace_ids(src, sc.rays_per_src, np.arange(sc.n_rays))
     both = (recs["status"] == ref["status"]) & (recs["status"] == 0)
     d = np.abs(recs["sensor_px"][both] - ref["sensor_px"][both]).max(axis=1)
     print(f"piv shock 48^3: max {d.max():.3e} px, p99.9 {np.quantile(d, 0.999):.3e} px")
     assert np.quantile(d, 0.999) <= TOL_PX
     assert d.max() <= 1e-2
-    r64, _, recs64, _ = _render_all(torch, sc, flags=pbr.PBR_PREC_FP64_ALL, src=src)
+    r64, _, recs64, _ = _render_all(torch, sc, flags=pbr.PBR_PREC_FP64_ALL, src=src, nodes=nodes)
     _compare_records(recs64, ref, 1e-6, label="piv fp64")
     one = sc.replace(n_src=1, rays_per_src=1)
-    _, st1, rec1, src1 = _render_all(torch, one, src=src[:1])
+    _, st1, rec1, src1 = _render_all(torch, one, src=src[:1], nodes=nodes)
     ref1 = oracle.scene_oracle(one).trace_ids(src1, 1, np.arange(1))
     _compare_records(rec1, ref1, TOL_PX, label="one ray")
 
@@ -194,7 +200,8 @@ def test_turbulence_bos_full_size_sampled(torch):
     rho = inputs.density(sc)
     src = inputs.sources(sc)
     stride = sc.n_rays // 1000 - 1
-    r, st, recs = pbr.trace_scene(sc, rho=rho, src=src, record=(17, stride, 1000))
+    r, st, recs = pbr.trace_scene(sc, rho=rho, src=src, record=(17, stride, 1000), rays_per_chunk=1 << 24)
+    assert st["box_launches"] == 3  # 16 777 216-ray chunks, as the benchmark runs them
     assert st["rays"] == sc.n_rays == sum(st["status"])
     o = oracle.scene_oracle(sc, rho=rho)
     ref = o.trace_ids(src, sc.rays_per_src, recs["ray_id"])
@@ -252,3 +259,50 @@ def test_non_finite_density_is_refused(torch):
             with pytest.raises(pbr.PbrError):
                 r.derived()
             r.close()
+
+
+@pytest.mark.parametrize("ds", [1.6e-3, 0.8e-3])
+def test_node_layout_cell_by_cell_moves_match_oracle(torch, ds):
+    """Node layout with steps of about one cell (1.6 mm cells) through a strong bump (ten times
+    the tiny scene's amplitude), dots spread over +-40 mm so that rays cross x and y faces in both
+    directions: the integration moves to a face neighbour on most stage points, reusing the four
+    corners of the shared face, and steps jump cells diagonally too.  Every ray against the oracle
+    at 1e-4 px (FP32) and 1e-6 px (FP64)."""
+    sc = inputs.tiny_bos().replace(n_src=600, rays_per_src=40, ds=ds,
+                                   src_region=((-0.04, 0.04), (-0.04, 0.04), (0.0, 0.0)),
+                                   field_params=dict(inputs.tiny_bos().field_params, amp=1.0))
+    r, st, recs, src = _render_all(torch, sc, nodes=True)
+    ref = oracle.scene_oracle(sc).trace_ids(src, sc.rays_per_src, np.arange(sc.n_rays))
+    err, mism = _compare_records(recs, ref, TOL_PX, label=f"nodes ds {ds}")
+    ent = ref["entered"] == 1
+    d = ref["dir0"][ent]
+    print(f"nodes, ds {ds * 1e3:.1f} mm: {int(ent.sum())} rays entered ({(d[:, 0] > 0).sum()} towards +x, "
+          f"{(d[:, 0] < 0).sum()} -x, {(d[:, 1] > 0).sum()} +y, {(d[:, 1] < 0).sum()} -y), max |dpx| {err:.3e}, "
+          f"status mismatches {mism}")
+    assert (d[:, 0] > 0.02).sum() > 1000 and (d[:, 0] < -0.02).sum() > 1000
+    assert (d[:, 1] > 0.02).sum() > 1000 and (d[:, 1] < -0.02).sum() > 1000
+    _, _, recs64, _ = _render_all(torch, sc, flags=pbr.PBR_PREC_FP64_ALL, src=src, nodes=True)
+    _compare_records(recs64, ref, 1e-6, label=f"nodes ds {ds} fp64")
+
+
+def test_source_weights_outside_the_unit_range(torch):
+    """Weights beyond [0, 1] count as the nearer end and NaN as 0 on the device as in the oracle:
+    the image of weights (1.7, -0.3, NaN, 0.25, ...) equals that of (1, 0, 0, 0.25, ...) bit for
+    bit and matches the oracle's render of the out-of-range weights."""
+    sc = inputs.tiny_bos().replace(n_src=200, rays_per_src=50)
+    src = inputs.sources(sc)
+    w = np.resize(np.array([1.7, -0.3, np.nan, 0.25, 1.0, 0.6], dtype=np.float32), sc.n_src)
+    a = src.copy()
+    a[:, 3] = w
+    b = src.copy()
+    b[:, 3] = np.where(np.isnan(w), 0.0, np.clip(w, 0.0, 1.0)).astype(np.float32)
+    r = pbr.Renderer.from_scene(sc)
+    imgs = []
+    for s in (a, b):
+        r.emit_and_trace(s, sc.rays_per_src, sc.ray_seed, sc.ds, pbr.PBR_CLEAR_FIRST)
+        imgs.append(pbr.u64_image_to_numpy(r.read_image()))
+    assert np.array_equal(imgs[0], imgs[1])
+    q, _, _ = oracle.scene_oracle(sc).render(a, sc.rays_per_src, want_float=False)
+    rel = oracle.rel_l2(imgs[0].astype(np.float64), q.astype(np.float64))
+    print(f"out-of-range weights: image rel L2 vs oracle {rel:.2e}")
+    assert rel <= 1e-3

@@ -108,5 +108,40 @@ def test_tomo_piv_shock_full_grid_sampled(torch):
     d = np.abs(rec["sensor_px"][both] - ref["sensor_px"][both]).max(axis=1)
     print(f"tomo_piv_shock 512^3 ({both.sum()} rays): max {d.max():.3e} px, p99 {np.quantile(d, 0.99):.3e} px; "
           f"{st['rays'] / st['trace_ms'] * 1e3:.3e} rays/s, fp64 steps {st['rkn_steps_fp64']}")
-    assert np.quantile(d, 0.99) <= 1e-4
-    assert d.max() <= 1e-3
+    assert np.quantile(d, 0.99) <= 2e-5
+    assert d.max() <= 1e-4
+
+
+def test_tomo_piv_full_image_node_layout_sampled(torch):
+    """The benchmarked Tomo-PIV image as the benchmark renders it: all 1e5 particles x 1e4 rays on
+    the 512^3 node-layout field, 16 777 216-ray chunks, 2048^2 sensor read out as 16-bit; 1000
+    strided rays against the oracle (the same bars as the per-cell test above), the 16-bit image
+    against the oracle's readout of the device's Q32.32 image (an exact integer transform), and the
+    light of the image against the deposited ray count."""
+    sc = inputs.tomo_piv_shock()
+    rho = inputs.density(sc)
+    src = inputs.sources(sc)
+    r = pbr.Renderer.from_scene(sc, rho=rho, nodes=True, rays_per_chunk=1 << 24)
+    stride = sc.n_rays // 1000
+    r.set_exit_recording(7, stride, 1000)
+    st = r.emit_and_trace(src, sc.rays_per_src, sc.ray_seed, sc.ds, pbr.PBR_CLEAR_FIRST | pbr.PBR_RECORD_EXITS,
+                          stats=True)
+    assert st["box_launches"] == 60 and st["rays"] == sc.n_rays == sum(st["status"])
+    rec = r.read_ray_exits()
+    q = pbr.u64_image_to_numpy(r.read_image())
+    u16 = pbr.u16_image_to_numpy(r.read_image(pbr.PBR_FMT_U16))
+    assert np.array_equal(u16, oracle.readout_u16(q)) and u16.max() == 65535
+    total = q.astype(np.float64).sum() / 2 ** 32
+    ndep = st["status"][pbr.PBR_RAY_DEPOSITED]
+    assert 0.99 * ndep <= total <= ndep * (1 + 1e-6)
+    o = oracle.scene_oracle(sc, rho=rho)
+    ref = o.trace_ids(src, sc.rays_per_src, rec["ray_id"])
+    same = rec["status"] == ref["status"]
+    assert (~same).sum() <= 1
+    both = same & (rec["status"] == 0)
+    d = np.abs(rec["sensor_px"][both] - ref["sensor_px"][both]).max(axis=1)
+    print(f"tomo_piv 512^3 nodes, full image ({both.sum()} sampled rays): max {d.max():.3e} px, "
+          f"p99 {np.quantile(d, 0.99):.3e} px; {st['rays'] / st['trace_ms'] * 1e3:.3e} rays/s")
+    assert both.sum() > 800
+    assert np.quantile(d, 0.99) <= 2e-5
+    assert d.max() <= 1e-4

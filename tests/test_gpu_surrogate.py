@@ -59,8 +59,14 @@ def test_gradients_match_oracle(torch):
     gg = mlp.unflatten(g.astype(np.float64))
     for k in mlp.PARAM_ORDER:
         rel = np.linalg.norm(gg[k] - gr[k]) / np.linalg.norm(gr[k])
-        print(f"{k}: grad rel err {rel:.3g}")
+        # element by element: within 2% of the element or 1e-3 of the tensor's largest entry (the
+        # bfloat16 roundings match the oracle's, only the FP32 summation order differs)
+        d = np.abs(gg[k] - gr[k])
+        bound = 2e-2 * np.abs(gr[k]) + 1e-3 * np.abs(gr[k]).max()
+        worst = float((d / bound).max())
+        print(f"{k}: grad rel err {rel:.3g}, worst element at {worst:.3g} of its bound")
         assert rel <= 1e-2, k
+        assert worst <= 1.0, k
     # the bfloat16 roundings are where the oracle puts them: against the pure-FP64 gradient the
     # difference is of bfloat16 size, far above the emulation's agreement for the hidden weights
     y64, c64 = mlp.forward(p, x.astype(np.float64))
@@ -166,9 +172,13 @@ def test_surrogate_in_the_trace(torch, trained):
     assert int(surr.sum()) == st_s["surrogate_rays"]
     both = surr & (rec_s["status"] == 0) & (rec_t["status"] == 0)
     e = np.hypot(*(rec_s["sensor_px"][both] - rec_t["sensor_px"][both]).T)
+    rim = int((surr & (rec_s["status"] != rec_t["status"])).sum())
     print(f"surrogate rays {surr.sum()}: exit error vs tracer median {np.median(e):.3g} px, "
-          f"p99 {np.quantile(e, 0.99):.3g}, max {e.max():.3g}")
-    assert np.quantile(e, 0.99) <= 0.01
+          f"p99 {np.quantile(e, 0.99):.3g}, max {e.max():.3g}; status differs on {rim}")
+    # every ray through the network lands within 0.01 px of the tracer's hit, and rays whose
+    # aperture or lens status would change stay with the tracer (rim tiles are never eligible)
+    assert e.max() <= 0.01
+    assert rim <= max(1, int(1e-4 * surr.sum()))
     # rays outside eligible tiles are traced exactly as without the surrogate
     rest = ~surr
     assert np.array_equal(rec_s["sensor_px"][rest], rec_t["sensor_px"][rest])
