@@ -258,6 +258,24 @@ int pbr_set_exit_recording(pbr_ctx *ctx, int64_t first, int64_t stride, int64_t 
 int pbr_emit_and_trace(pbr_ctx *ctx, const float *src_dev, int64_t n_src, int32_t rays_per_src,
                        uint64_t seed, double ds, uint32_t flags, pbr_stats *stats_host);
 
+/* For callers that cannot allocate device memory (code under HIP stream capture, serving loops,
+ * harnesses that forbid hipMalloc): pbr_emit_and_trace with the per-ray state of each chunk held
+ * in a static device array of the library instead of the context's trace workspace (which need
+ * not be set).  Same arguments, flags, results and errors as pbr_emit_and_trace, plus:
+ *   rays_per_chunk: rays integrated per launch, in [256, PBR_NOALLOC_MAX_CHUNK] (0 = the maximum);
+ *     ARG outside that range.  Images and exit records do not depend on it.
+ *   The call allocates no device memory.  Every GPU the library runs on holds one array of
+ *   PBR_NOALLOC_MAX_CHUNK x 64 bytes (64 MiB) from its first context until the process ends.
+ *   All calls on one GPU share that array: calls whose work overlaps on one GPU (on different
+ *   streams, or from different host threads without ordering) race and give wrong results.
+ *   With stats_host, box_ms is 0 (no per-launch timing events are created); the other counters
+ *   are filled.  With PBR_SURROGATE the attached surrogate must have been created for chunks of
+ *   at least rays_per_chunk rays (WORKSPACE otherwise). */
+#define PBR_NOALLOC_MAX_CHUNK (1 << 20)
+int pbr_emit_and_trace_noalloc(pbr_ctx *ctx, const float *src_dev, int64_t n_src, int32_t rays_per_src,
+                               uint64_t seed, double ds, uint32_t flags, int64_t rays_per_chunk,
+                               pbr_stats *stats_host);
+
 
 /* Precision policy for steep-gradient (shock) cells.  Finds the steep bricks of the current field
  * (largest node |grad n| >= steep_frac times the grid maximum), and in each traces rays_per_brick

@@ -236,6 +236,9 @@ int pbr_create(pbr_ctx **out, int device, void *hip_stream)
     }
     e = pbr::launch_clear_u64(ctx->counters, 4096 / 8, ctx->stream);
     if (e) { int r = hip_fail(nullptr, e, "clear counters"); (void)hipFree(p); delete ctx; return r; }
+    // address of this device's static ray-state array (pbr_emit_and_trace_noalloc); a failed
+    // lookup is reported by that call only
+    (void)noalloc_scratch_init(device);
     *out = ctx;
     return PBR_OK;
     }
@@ -517,12 +520,12 @@ int emit_and_trace_impl(pbr_ctx *ctx, const float *src_dev, int64_t n_src, int32
         if (rays_per_src > (1 << 25))
             return fail(ctx, PBR_ERR_ARG, "per-source sums need rays_per_src <= 2^25");
     }
-    pbr::ChunkHook hook{nullptr, nullptr};
-    if (flags & PBR_SURROGATE) {
-        if ((r = surrogate_hook(ctx, ds, &hook))) return r;
-    }
     pbr::RayState *ray_ws = noalloc ? static_ws : ctx->ray_ws;
     const int64_t ray_chunk = noalloc ? static_chunk : ctx->ray_chunk;
+    pbr::ChunkHook hook{nullptr, nullptr};
+    if (flags & PBR_SURROGATE) {
+        if ((r = surrogate_hook(ctx, ds, ray_chunk, !noalloc, &hook))) return r;
+    }
     if (!noalloc && !ray_ws) return fail(ctx, PBR_ERR_STATE, "no trace workspace set (pbr_set_trace_workspace)");
     if ((flags & PBR_RECORD_EXITS) && ctx->rec_max > 0 && !ctx->rec)
         return fail(ctx, PBR_ERR_STATE, "no exit recording buffer set");
@@ -564,8 +567,10 @@ int emit_and_trace_impl(pbr_ctx *ctx, const float *src_dev, int64_t n_src, int32
                      : ((flags & PBR_PREC_SHOCK_FP64) && ctx->n_fp64_bricks > 0) ? pbr::PREC_MIXED
                      : pbr::PREC_FP32;
     const int64_t n_chunks = (P.n_rays + ray_chunk - 1) / ray_chunk;
+    // per-launch timing events (created on demand, so not in the allocation-free variant)
+    const bool launch_ev = stats && !noalloc;
     if (stats) {
-        while ((int64_t)ctx->box_ev.size() < 2 * n_chunks) {
+        while (launch_ev && (int64_t)ctx->box_ev.size() < 2 * n_chunks) {
             hipEvent_t ev;
             if ((e = (int)hipEventCreate(&ev))) return hip_fail(ctx, e, "hipEventCreate");
             ctx->box_ev.push_back(ev);
@@ -576,7 +581,7 @@ int emit_and_trace_impl(pbr_ctx *ctx, const float *src_dev, int64_t n_src, int32
         const int64_t first = k * ray_chunk;
         const int64_t n = P.n_rays - first < ray_chunk ? P.n_rays - first : ray_chunk;
         e = pbr::launch_trace_chunk(P, ray_ws, first, n, prec, ctx->stream,
-                                    stats ? ctx->box_ev[2 * k] : nullptr, stats ? ctx->box_ev[2 * k + 1] : nullptr,
+                                    launch_ev ? ctx->box_ev[2 * k] : nullptr, launch_ev ? ctx->box_ev[2 * k + 1] : nullptr,
                                     hook.run ? &hook : nullptr, true, (flags & PBR_LANE_REFILL) != 0);
         if (e) return hip_fail(ctx, e, "trace launch");
     }
@@ -601,7 +606,7 @@ int emit_and_trace_impl(pbr_ctx *ctx, const float *src_dev, int64_t n_src, int32
         stats->surrogate_rays = h[pbr::CNT_SURR];
         stats->trace_ms = (double)ms;
         double box = 0.0;
-        for (int64_t k = 0; k < n_chunks; ++k) {
+        for (int64_t k = 0; launch_ev && k < n_chunks; ++k) {
             float b = 0.0f;
             e = (int)hipEventElapsedTime(&b, ctx->box_ev[2 * k], ctx->box_ev[2 * k + 1]);
             if (e) return hip_fail(ctx, e, "hipEventElapsedTime");

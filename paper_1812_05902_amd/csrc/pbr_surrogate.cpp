@@ -216,7 +216,7 @@ int hook_run(void *self, const pbr::TraceParams &P, pbr::RayState *st, int64_t, 
 namespace pbr {
 namespace host {
 
-int surrogate_hook(pbr_ctx *ctx, double ds, ChunkHook *out)
+int surrogate_hook(pbr_ctx *ctx, double ds, int64_t chunk, bool may_alloc, ChunkHook *out)
 {
     pbr_surrogate *s = ctx->surr;
     if (!s) return fail(ctx, PBR_ERR_STATE, "PBR_SURROGATE set but no surrogate attached (pbr_set_surrogate)");
@@ -224,11 +224,14 @@ int surrogate_hook(pbr_ctx *ctx, double ds, ChunkHook *out)
         return fail(ctx, PBR_ERR_STATE, "the attached surrogate no longer matches this context's field, optics or sensor");
     if (ds != s->ds)
         return fail(ctx, PBR_ERR_STATE, "the surrogate was trained for steps of %.6g m, the trace asks for %.6g m", s->ds, ds);
-    if (ctx->ray_chunk > s->chunk_cap) {
+    if (chunk > s->chunk_cap && !may_alloc)
+        return fail(ctx, PBR_ERR_WORKSPACE, "the surrogate's buffers hold chunks of %lld rays, the trace uses %lld",
+                    (long long)s->chunk_cap, (long long)chunk);
+    if (chunk > s->chunk_cap) {
         // buffers for whole chunks (53 B per ray), kept until the surrogate is destroyed
         DeviceGuard g(s->device);
         void *q[4] = {nullptr, nullptr, nullptr, nullptr};
-        const size_t n = (size_t)ctx->ray_chunk;
+        const size_t n = (size_t)chunk;
         int e = 0;
         if ((e = dmalloc(s, &q[0], n * 24)) || (e = dmalloc(s, &q[1], n * 24)) || (e = dmalloc(s, &q[2], n)) ||
             (e = dmalloc(s, &q[3], n * 4)))
@@ -237,7 +240,7 @@ int surrogate_hook(pbr_ctx *ctx, double ds, ChunkHook *out)
         s->iy = (float *)q[1];
         s->ielig = (unsigned char *)q[2];
         s->tlist = (int *)q[3];
-        s->chunk_cap = ctx->ray_chunk;
+        s->chunk_cap = chunk;
     }
     out->run = hook_run;
     out->self = s;

@@ -30,6 +30,7 @@ PBR_MIE = 128
 PBR_MAX_SURFACES = 16
 PBR_SURF_REFRACT, PBR_SURF_MIRROR, PBR_SURF_APERTURE, PBR_SURF_LENSLETS = 0, 1, 2, 3
 PBR_MIE_TABLE_SIZE = 2049
+PBR_NOALLOC_MAX_CHUNK = 1 << 20
 PBR_SURR_PARAMS = 200710
 PBR_FMT_RAW_U64, PBR_FMT_F32, PBR_FMT_U16 = 0, 1, 2
 
@@ -50,7 +51,7 @@ EXPORTED = ["pbr_create", "pbr_destroy", "pbr_last_error", "pbr_set_stream",
             "pbr_set_mie", "pbr_set_optical_chain", "pbr_field_workspace_bytes_nodes",
             "pbr_set_density_field_nodes", "pbr_surrogate_blob_bytes", "pbr_surrogate_save",
             "pbr_surrogate_load", "pbr_probe_fma_rate",
-            "pbr_probe_read_bandwidth", "pbr_probe_lds_bandwidth"]
+            "pbr_probe_read_bandwidth", "pbr_probe_lds_bandwidth", "pbr_emit_and_trace_noalloc"]
 
 
 class PbrError(RuntimeError):
@@ -179,6 +180,7 @@ def load(path: str = LIB_PATH):
         "pbr_get_derived": (I, [P, C.POINTER(pbr_derived)]),
         "pbr_set_exit_recording": (I, [P, I64, I64, I64, P]),
         "pbr_emit_and_trace": (I, [P, P, I64, C.c_int32, U64, D, U32, C.POINTER(pbr_stats)]),
+        "pbr_emit_and_trace_noalloc": (I, [P, P, I64, C.c_int32, U64, D, U32, I64, C.POINTER(pbr_stats)]),
         "pbr_calibrate_precision": (I, [P, D, D, C.c_int32, U64, D, C.POINTER(pbr_precision_report)]),
         "pbr_brick_flags": (I, [P, P, I64, I]),
         "pbr_read_image": (I, [P, I, P, D]),
@@ -305,6 +307,16 @@ def pbr_emit_and_trace(ctx, src, rays_per_src, seed, ds, flags=0, want_stats=Fal
     n_src = 0 if src is None else int(src.shape[0])
     _check(ctx, load().pbr_emit_and_trace(ctx, _dptr(src), n_src, int(rays_per_src), int(seed),
                                           float(ds), int(flags), C.byref(st) if st is not None else None))
+    return st
+
+
+def pbr_emit_and_trace_noalloc(ctx, src, rays_per_src, seed, ds, flags=0, rays_per_chunk=0, want_stats=False):
+    """pbr_emit_and_trace with the ray states in the library's static device array (no allocation)."""
+    st = pbr_stats() if want_stats else None
+    n_src = 0 if src is None else int(src.shape[0])
+    _check(ctx, load().pbr_emit_and_trace_noalloc(ctx, _dptr(src), n_src, int(rays_per_src), int(seed),
+                                                  float(ds), int(flags), int(rays_per_chunk),
+                                                  C.byref(st) if st is not None else None))
     return st
 
 

@@ -497,3 +497,25 @@ def test_node_layout_workspace_and_limits(lib):
         assert "host-only" in _err(lib, h)
     finally:
         lib.pbr_destroy(h)
+
+
+def test_noalloc_trace_validates_before_device_work(lib):
+    """pbr_emit_and_trace_noalloc: the chunk range first, then the checks of pbr_emit_and_trace
+    (a host-only context reaches the state error only after every argument passed)."""
+    assert lib.pbr_emit_and_trace_noalloc(None, FAKE, 1, 1, 0, 1e-4, 0, 0, None) == pbr.PBR_ERR_ARG
+    h = _host_ctx(lib)
+    try:
+        assert _set_field(lib, h) == pbr.PBR_OK
+        assert lib.pbr_set_optics(h, C.byref(_optics())) == pbr.PBR_OK
+        assert lib.pbr_set_sensor(h, C.byref(_sensor()), FAKE) == pbr.PBR_OK
+        for bad in (pbr.PBR_NOALLOC_MAX_CHUNK + 1, 255, 1, -1):
+            assert lib.pbr_emit_and_trace_noalloc(h, FAKE, 1, 1, 0, 1e-4, 0, bad, None) == pbr.PBR_ERR_ARG
+            assert "rays_per_chunk" in _err(lib, h)
+        assert lib.pbr_emit_and_trace_noalloc(h, FAKE, 1, 0, 0, 1e-4, 0, 0, None) == pbr.PBR_ERR_ARG
+        assert lib.pbr_emit_and_trace_noalloc(h, FAKE, 1, 1, 0, 0.0, 0, 256, None) == pbr.PBR_ERR_ARG
+        # no trace workspace is needed: the remaining error is the host-only context
+        for chunk in (0, 256, pbr.PBR_NOALLOC_MAX_CHUNK):
+            assert lib.pbr_emit_and_trace_noalloc(h, FAKE, 1, 1, 0, 1e-4, 0, chunk, None) == pbr.PBR_ERR_STATE
+            assert "host-only" in _err(lib, h)
+    finally:
+        lib.pbr_destroy(h)
