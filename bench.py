@@ -589,7 +589,7 @@ def bench_surrogate(args):
     src_va = inputs.sources(va)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
-    s = pbr.Surrogate(init_seed=7, max_rows=1 << 18)
+    s = pbr.Surrogate(init_seed=7, max_rows=1 << 18, ray_chunk=args.rays_per_chunk)
     rep = s.train(r, src_tr, tr.rays_per_src, src_va, va.rays_per_src, tr.ray_seed, va.ray_seed, ev.ds, batch=4096,
                   epochs=args.epochs, lr_max=1e-3, lr_min=1e-5, tol_px=0.01, tiles=64, min_tile_samples=8)
     print(json.dumps({"surrogate_training": rep}), flush=True)

@@ -16,8 +16,10 @@
  *     the image is not flipped (a real image is inverted).
  *   - "_dev" pointers are device memory of the context's GPU, owned by the caller.  The library
  *     never allocates large buffers: the caller provides the field workspace, the trace
- *     workspace, the sensor accumulator and the ray-exit record buffer.  pbr_create allocates one 4 KiB device block
- *     for counters and the optical chain, freed by pbr_destroy.
+ *     workspace, the sensor accumulator, the ray-exit record buffer, batch workspaces and the
+ *     surrogate's persistent and training workspaces.  pbr_create allocates one 4 KiB device
+ *     block for counters and the optical chain, freed by pbr_destroy; the calibration probes at
+ *     the end allocate and free their own buffers.
  *   - All device work is enqueued on the context's HIP stream and is asynchronous unless a
  *     function says it synchronises.  The caller keeps its buffers alive until the stream has
  *     passed the work that uses them.
@@ -588,12 +590,23 @@ typedef struct pbr_surrogate_report {
     double validate_ms;
 } pbr_surrogate_report;
 
+/* Device bytes of a surrogate's persistent workspace: FP32 parameters, gradient and Adam moments,
+ * bfloat16 weight copies, training-pass buffers for max_rows rows (rounded up to 64; 65536 if 0),
+ * inference buffers for trace chunks of up to ray_chunk rays (53 bytes per ray; 0 when the
+ * surrogate never runs inside a trace) and a 1 MiB tile map.  0 for arguments out of range
+ * (max_rows in [0, 2^24], ray_chunk in [0, 2^31]). */
+size_t pbr_surrogate_workspace_bytes(int64_t max_rows, int64_t ray_chunk);
+
 /* Creates a network on device (current device if -1) with weights and biases drawn uniformly from
- * +-1/sqrt(fan_in) (SplitMix64 of init_seed), zero Adam moments, and buffers for max_rows rows per
- * pass (rounded up to 64; 65536 if 0).  hip_stream: stream for the calls below (NULL = the null
- * stream); training and the trace hook enqueue on the context's stream instead.
- * Errors: ARG, HIP (see pbr_surrogate_last_error(NULL) when *out is NULL). */
-int pbr_surrogate_create(pbr_surrogate **out, int device, void *hip_stream, uint64_t init_seed, int64_t max_rows);
+ * +-1/sqrt(fan_in) (SplitMix64 of init_seed) and zero Adam moments, all held in the caller's
+ * workspace ws_dev (device, 256-byte aligned, at least pbr_surrogate_workspace_bytes(max_rows,
+ * ray_chunk) bytes, alive and untouched until pbr_surrogate_destroy).  Traces with PBR_SURROGATE
+ * on contexts whose chunk exceeds ray_chunk fail with WORKSPACE.  hip_stream: stream for the
+ * calls below (NULL = the null stream); training and the trace hook enqueue on the context's
+ * stream instead.  Allocates no device memory.
+ * Errors: ARG, WORKSPACE, HIP (see pbr_surrogate_last_error(NULL) when *out is NULL). */
+int pbr_surrogate_create(pbr_surrogate **out, int device, void *hip_stream, uint64_t init_seed, int64_t max_rows,
+                         int64_t ray_chunk, void *ws_dev, size_t ws_bytes);
 void pbr_surrogate_destroy(pbr_surrogate *s);
 const char *pbr_surrogate_last_error(const pbr_surrogate *s);
 
@@ -631,11 +644,18 @@ int pbr_surrogate_adam_step(pbr_surrogate *s, const float *x_dev, const float *t
  * rays that reach the sensor one way but not the other are counted and make their tile
  * ineligible too).  The
  * context's sensor accumulator and counters are left untouched; its trace workspace is used as
- * scratch.  Synchronises.  Errors: STATE (context not ready, host-only context), ARG, HIP. */
+ * scratch.  ws_dev: training scratch (device, 256-byte aligned, at least
+ * pbr_surrogate_train_workspace_bytes bytes for these ray counts and cfg; free again when the
+ * call returns): the samples (88 bytes per ray), shuffles, losses and validation errors.
+ * Allocates no device memory.  Synchronises.
+ * Errors: STATE (context not ready, host-only context), ARG, WORKSPACE, HIP. */
+size_t pbr_surrogate_train_workspace_bytes(int64_t n_train_rays, int64_t n_val_rays, int32_t batch, int32_t epochs,
+                                           int32_t tiles);
 int pbr_surrogate_train(pbr_surrogate *s, pbr_ctx *ctx, const float *train_src_dev, int64_t n_train_src,
                         int32_t train_rays_per_src, const float *val_src_dev, int64_t n_val_src,
                         int32_t val_rays_per_src, uint64_t train_seed, uint64_t val_seed, double ds,
-                        const pbr_surrogate_train_config *cfg, pbr_surrogate_report *report);
+                        const pbr_surrogate_train_config *cfg, void *ws_dev, size_t ws_bytes,
+                        pbr_surrogate_report *report);
 
 /* Fallback map of a trained surrogate: tiles x tiles bytes (1 = eligible) and the largest
  * validation error per tile in pixels (-1 for tiles without validation rays), tile (tx, ty) at
@@ -657,8 +677,7 @@ int pbr_surrogate_load(pbr_surrogate *s, pbr_ctx *ctx, const void *buf_host, siz
  * PBR_SURROGATE then hand every ray that enters through an eligible tile of z_min to the network
  * and trace the rest.  Fails with STATE when the surrogate is untrained, was trained on another
  * context or the context's field, optics or sensor changed since.  The surrogate must outlive
- * the attachment.  The first trace with PBR_SURROGATE allocates 53 B per ray of the context's
- * chunk size for the surrogate (kept until pbr_surrogate_destroy). */
+ * the attachment. */
 int pbr_set_surrogate(pbr_ctx *ctx, pbr_surrogate *s);
 
 /* ---------------------------------------------------------------- calibration probe

@@ -524,7 +524,7 @@ int emit_and_trace_impl(pbr_ctx *ctx, const float *src_dev, int64_t n_src, int32
     const int64_t ray_chunk = noalloc ? static_chunk : ctx->ray_chunk;
     pbr::ChunkHook hook{nullptr, nullptr};
     if (flags & PBR_SURROGATE) {
-        if ((r = surrogate_hook(ctx, ds, ray_chunk, !noalloc, &hook))) return r;
+        if ((r = surrogate_hook(ctx, ds, ray_chunk, &hook))) return r;
     }
     if (!noalloc && !ray_ws) return fail(ctx, PBR_ERR_STATE, "no trace workspace set (pbr_set_trace_workspace)");
     if ((flags & PBR_RECORD_EXITS) && ctx->rec_max > 0 && !ctx->rec)

@@ -92,9 +92,9 @@ uint64_t next_uid();
 // Normalised unpolarised Mie intensity at n_angles angles over [0, pi] (pbr_mie.cpp).
 bool mie_intensity_table(std::complex<double> m, double x, int n_angles, double *out);
 // Chunk hook of an attached surrogate for trace chunks of up to `chunk` rays; fails with STATE
-// (message on ctx) when it no longer matches the context's scene.  may_alloc: the surrogate may
-// grow its chunk buffers (WORKSPACE instead when they are too small and it may not).
-int surrogate_hook(pbr_ctx *ctx, double ds, int64_t chunk, bool may_alloc, ChunkHook *out);
+// (message on ctx) when it no longer matches the context's scene and with WORKSPACE when its
+// buffers were sized for smaller chunks.
+int surrogate_hook(pbr_ctx *ctx, double ds, int64_t chunk, ChunkHook *out);
 // Looks up the device address of the static ray-state array of pbr_emit_and_trace_noalloc on
 // `device` (current), once per device; returns the HIP error of the lookup.
 int noalloc_scratch_init(int device);

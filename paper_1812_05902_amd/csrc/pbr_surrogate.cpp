@@ -23,7 +23,6 @@ struct pbr_surrogate {
     hipStream_t stream = nullptr;
     std::string err;
     int64_t rows_cap = 0;
-    std::vector<void *> allocs;
     pbr::MlpDevice d{};
     pbr::MlpBuffers b{};
     float *x = nullptr, *y = nullptr, *t = nullptr, *loss = nullptr;
@@ -35,8 +34,7 @@ struct pbr_surrogate {
     bool trained = false;
     uint64_t ctx_uid = 0, scene_version = 0;
     pbr::SurrogateSpec spec{};
-    unsigned char *tile_ok_dev = nullptr;
-    int64_t tile_cap = 0;
+    unsigned char *tile_ok_dev = nullptr;  // kMaxTiles^2 bytes
     // inference on whole trace chunks: features, outputs, row -> ray index, rays left to the tracer
     float *ix = nullptr, *iy = nullptr;
     unsigned char *ielig = nullptr;
@@ -137,19 +135,97 @@ uint64_t splitmix64_host(uint64_t seed, uint64_t k)
 
 double uniform01(uint64_t seed, uint64_t k) { return (double)(splitmix64_host(seed, k) >> 11) * 0x1.0p-53; }
 
-int dmalloc(pbr_surrogate *s, void **p, size_t bytes)
+constexpr int kMaxTiles = 1024;  // tiles per side of the fallback map
+
+// Consecutive 256-byte aligned parts of a caller's workspace; with a null base it only sums the
+// sizes, so that one function both sizes a workspace and lays it out.
+struct Carve {
+    unsigned char *base = nullptr;
+    size_t off = 0;
+    template <typename T> T *take(size_t bytes)
+    {
+        off = (off + 255) & ~(size_t)255;
+        T *p = base ? (T *)(base + off) : nullptr;
+        off += bytes < 256 ? 256 : bytes;
+        return p;
+    }
+    size_t bytes() const { return (off + 255) & ~(size_t)255; }
+};
+
+int64_t rows_cap_of(int64_t max_rows) { return max_rows == 0 ? 65536 : round64(max_rows); }
+
+// The surrogate's own device memory: FP32 parameters, gradient and Adam moments, bfloat16 weight
+// copies, the training pass buffers for R rows, the inference buffers for trace chunks of `chunk`
+// rays (features 24 B, outputs 24 B, eligibility 1 B and the tracer's list 4 B per ray) and the
+// tile map.
+void layout_persistent(pbr_surrogate *s, Carve &c, int64_t R, int64_t chunk)
 {
-    *p = nullptr;
-    const int e = (int)hipMalloc(p, bytes < 256 ? 256 : bytes);
-    if (e) return e;
-    s->allocs.push_back(*p);
-    return 0;
+    const int64_t H = pbr::kHidden, P = pbr::kParams + 64;
+    s->d.params = c.take<float>(P * 4);
+    s->d.grad = c.take<float>(P * 4);
+    s->d.m = c.take<float>(P * 4);
+    s->d.v = c.take<float>(P * 4);
+    unsigned short **w[6] = {&s->d.w2, &s->d.w2t, &s->d.w3, &s->d.w3t, &s->d.w4, &s->d.w4t};
+    for (auto q : w) *q = c.take<unsigned short>(H * H * 2);
+    s->d.w5 = c.take<unsigned short>(pbr::kOutPad * H * 2);
+    s->b.rows_cap = R;
+    for (int l = 0; l < 4; ++l) {
+        s->b.z[l] = c.take<float>(R * H * 4);
+        s->b.a[l] = c.take<unsigned short>(R * H * 2);
+    }
+    s->b.dy = c.take<float>(R * 6 * 4);
+    s->b.dz = c.take<float>(R * H * 4);
+    s->b.dz2 = c.take<float>(R * H * 4);
+    s->b.dzb = c.take<unsigned short>(R * H * 2);
+    s->b.dzb2 = c.take<unsigned short>(R * H * 2);
+    s->b.t0 = c.take<unsigned short>(R * H * 2);
+    s->b.t1 = c.take<unsigned short>(R * H * 2);
+    s->b.loss_part = c.take<float>(((R * 6 + 255) / 256) * 4);
+    s->b.part = c.take<float>((size_t)16 * H * H * 4);
+    s->b.part2 = c.take<float>((size_t)16 * H * H * 4);
+    s->x = c.take<float>(R * 6 * 4);
+    s->y = c.take<float>(R * 6 * 4);
+    s->t = c.take<float>(R * 6 * 4);
+    s->loss = c.take<float>(256);
+    s->count = c.take<unsigned long long>(256);
+    s->step = c.take<int>(256);
+    s->tile_ok_dev = c.take<unsigned char>((size_t)kMaxTiles * kMaxTiles);
+    s->ix = c.take<float>((size_t)chunk * 24);
+    s->iy = c.take<float>((size_t)chunk * 24);
+    s->ielig = c.take<unsigned char>((size_t)chunk);
+    s->tlist = c.take<int>((size_t)chunk * 4);
+    s->chunk_cap = chunk;
 }
 
-void free_all(pbr_surrogate *s)
+// Scratch of one pbr_surrogate_train call, carved from the caller's training workspace.
+struct TrainScratch {
+    pbr::SurrogateSample *trs, *vas;
+    double *part;
+    int *flags;      // per training ray, then per validation ray (entry tiles)
+    int *perm;
+    float *losses;
+    unsigned *tile_err, *tile_cnt;
+    float *err;
+};
+
+int64_t train_steps_bound(int64_t n_train, int32_t batch, int32_t epochs)
 {
-    for (void *p : s->allocs) (void)hipFree(p);
-    s->allocs.clear();
+    return n_train / batch * (int64_t)epochs;
+}
+
+void layout_train(TrainScratch *t, Carve &c, int64_t n_train, int64_t n_val, int32_t batch, int32_t epochs,
+                  int32_t tiles)
+{
+    const int64_t nt = (int64_t)tiles * tiles;
+    t->trs = c.take<pbr::SurrogateSample>((size_t)n_train * sizeof(pbr::SurrogateSample));
+    t->vas = c.take<pbr::SurrogateSample>((size_t)n_val * sizeof(pbr::SurrogateSample));
+    t->part = c.take<double>((size_t)1024 * pbr::kMoments * sizeof(double));
+    t->flags = c.take<int>((size_t)std::max(n_train, n_val) * sizeof(int));
+    t->perm = c.take<int>((size_t)(n_train / batch * batch) * sizeof(int));
+    t->losses = c.take<float>((size_t)train_steps_bound(n_train, batch, epochs) * sizeof(float));
+    t->tile_err = c.take<unsigned>((size_t)(nt + 1) * 4);
+    t->tile_cnt = c.take<unsigned>((size_t)(nt + 1) * 4);
+    t->err = c.take<float>((size_t)n_val * 4);
 }
 
 // Default parameters: uniform in +-1/sqrt(fan_in) for the weights and biases of every layer.
@@ -216,7 +292,7 @@ int hook_run(void *self, const pbr::TraceParams &P, pbr::RayState *st, int64_t, 
 namespace pbr {
 namespace host {
 
-int surrogate_hook(pbr_ctx *ctx, double ds, int64_t chunk, bool may_alloc, ChunkHook *out)
+int surrogate_hook(pbr_ctx *ctx, double ds, int64_t chunk, ChunkHook *out)
 {
     pbr_surrogate *s = ctx->surr;
     if (!s) return fail(ctx, PBR_ERR_STATE, "PBR_SURROGATE set but no surrogate attached (pbr_set_surrogate)");
@@ -224,24 +300,10 @@ int surrogate_hook(pbr_ctx *ctx, double ds, int64_t chunk, bool may_alloc, Chunk
         return fail(ctx, PBR_ERR_STATE, "the attached surrogate no longer matches this context's field, optics or sensor");
     if (ds != s->ds)
         return fail(ctx, PBR_ERR_STATE, "the surrogate was trained for steps of %.6g m, the trace asks for %.6g m", s->ds, ds);
-    if (chunk > s->chunk_cap && !may_alloc)
-        return fail(ctx, PBR_ERR_WORKSPACE, "the surrogate's buffers hold chunks of %lld rays, the trace uses %lld",
+    if (chunk > s->chunk_cap)
+        return fail(ctx, PBR_ERR_WORKSPACE,
+                    "the surrogate was created for trace chunks of at most %lld rays, the trace uses %lld",
                     (long long)s->chunk_cap, (long long)chunk);
-    if (chunk > s->chunk_cap) {
-        // buffers for whole chunks (53 B per ray), kept until the surrogate is destroyed
-        DeviceGuard g(s->device);
-        void *q[4] = {nullptr, nullptr, nullptr, nullptr};
-        const size_t n = (size_t)chunk;
-        int e = 0;
-        if ((e = dmalloc(s, &q[0], n * 24)) || (e = dmalloc(s, &q[1], n * 24)) || (e = dmalloc(s, &q[2], n)) ||
-            (e = dmalloc(s, &q[3], n * 4)))
-            return hip_fail(ctx, e, "hipMalloc(surrogate chunk buffers)");
-        s->ix = (float *)q[0];
-        s->iy = (float *)q[1];
-        s->ielig = (unsigned char *)q[2];
-        s->tlist = (int *)q[3];
-        s->chunk_cap = chunk;
-    }
     out->run = hook_run;
     out->self = s;
     return PBR_OK;
@@ -257,7 +319,17 @@ int surrogate_hook(pbr_ctx *ctx, double ds, int64_t chunk, bool may_alloc, Chunk
 
 extern "C" {
 
-int pbr_surrogate_create(pbr_surrogate **out, int device, void *hip_stream, uint64_t init_seed, int64_t max_rows)
+size_t pbr_surrogate_workspace_bytes(int64_t max_rows, int64_t ray_chunk)
+{
+    if (max_rows < 0 || max_rows > ((int64_t)1 << 24) || ray_chunk < 0 || ray_chunk > ((int64_t)1 << 31)) return 0;
+    pbr_surrogate probe;
+    Carve c;
+    layout_persistent(&probe, c, rows_cap_of(max_rows), ray_chunk);
+    return c.bytes();
+}
+
+int pbr_surrogate_create(pbr_surrogate **out, int device, void *hip_stream, uint64_t init_seed, int64_t max_rows,
+                         int64_t ray_chunk, void *ws_dev, size_t ws_bytes)
 {
     pbr_surrogate *s = nullptr;
     try {
@@ -265,6 +337,13 @@ int pbr_surrogate_create(pbr_surrogate **out, int device, void *hip_stream, uint
         *out = nullptr;
         if (max_rows < 0 || max_rows > ((int64_t)1 << 24))
             return sfail(nullptr, PBR_ERR_ARG, "max_rows must lie in [0, 2^24]");
+        if (ray_chunk < 0 || ray_chunk > ((int64_t)1 << 31))
+            return sfail(nullptr, PBR_ERR_ARG, "ray_chunk must lie in [0, 2^31]");
+        if (!ws_dev || ((uintptr_t)ws_dev & 255u))
+            return sfail(nullptr, PBR_ERR_ARG, "workspace must be non-null and 256-byte aligned");
+        const size_t need = pbr_surrogate_workspace_bytes(max_rows, ray_chunk);
+        if (ws_bytes < need)
+            return sfail(nullptr, PBR_ERR_WORKSPACE, "workspace of %zu bytes < %zu", ws_bytes, need);
         int ndev = 0, e = (int)hipGetDeviceCount(&ndev);
         if (e) return sfail(nullptr, PBR_ERR_HIP, "hipGetDeviceCount: %s", hipGetErrorString((hipError_t)e));
         if (device == -1 && (e = (int)hipGetDevice(&device)))
@@ -276,49 +355,13 @@ int pbr_surrogate_create(pbr_surrogate **out, int device, void *hip_stream, uint
         s = new (std::nothrow) pbr_surrogate();
         if (!s) return sfail(nullptr, PBR_ERR_HIP, "out of host memory");
         s->device = device;
-        s->rows_cap = max_rows == 0 ? 65536 : round64(max_rows);
+        s->rows_cap = rows_cap_of(max_rows);
         s->stream = (hipStream_t)hip_stream;  // NULL: the null stream
-        const int64_t R = s->rows_cap, H = pbr::kHidden, P = pbr::kParams + 64;
-        void *p;
-        auto A = [&](size_t bytes) -> void * {
-            if (e) return nullptr;
-            e = dmalloc(s, &p, bytes);
-            return e ? nullptr : p;
-        };
-        e = 0;
-        s->d.params = (float *)A(P * 4);
-        s->d.grad = (float *)A(P * 4);
-        s->d.m = (float *)A(P * 4);
-        s->d.v = (float *)A(P * 4);
-        unsigned short **w[6] = {&s->d.w2, &s->d.w2t, &s->d.w3, &s->d.w3t, &s->d.w4, &s->d.w4t};
-        for (auto q : w) *q = (unsigned short *)A(H * H * 2);
-        s->d.w5 = (unsigned short *)A(pbr::kOutPad * H * 2);
-        s->b.rows_cap = R;
-        for (int l = 0; l < 4; ++l) {
-            s->b.z[l] = (float *)A(R * H * 4);
-            s->b.a[l] = (unsigned short *)A(R * H * 2);
-        }
-        s->b.dy = (float *)A(R * 6 * 4);
-        s->b.dz = (float *)A(R * H * 4);
-        s->b.dz2 = (float *)A(R * H * 4);
-        s->b.dzb = (unsigned short *)A(R * H * 2);
-        s->b.dzb2 = (unsigned short *)A(R * H * 2);
-        s->b.t0 = (unsigned short *)A(R * H * 2);
-        s->b.t1 = (unsigned short *)A(R * H * 2);
-        s->b.loss_part = (float *)A(((R * 6 + 255) / 256) * 4);
-        s->b.part = (float *)A((size_t)16 * H * H * 4);
-        s->b.part2 = (float *)A((size_t)16 * H * H * 4);
-        s->x = (float *)A(R * 6 * 4);
-        s->y = (float *)A(R * 6 * 4);
-        s->t = (float *)A(R * 6 * 4);
-        s->loss = (float *)A(256);
-        s->count = (unsigned long long *)A(256);
-        s->step = (int *)A(256);
-        if (!e) e = (int)hipStreamCreateWithFlags(&s->train_stream, hipStreamNonBlocking);
-        if (e) {
-            const int r = sfail(nullptr, PBR_ERR_HIP, "device set-up: %s", hipGetErrorString((hipError_t)e));
-            free_all(s);
-            if (s->train_stream) (void)hipStreamDestroy(s->train_stream);
+        Carve c;
+        c.base = (unsigned char *)ws_dev;
+        layout_persistent(s, c, s->rows_cap, ray_chunk);
+        if ((e = (int)hipStreamCreateWithFlags(&s->train_stream, hipStreamNonBlocking))) {
+            const int r = sfail(nullptr, PBR_ERR_HIP, "training stream: %s", hipGetErrorString((hipError_t)e));
             delete s;
             return r;
         }
@@ -350,7 +393,6 @@ void pbr_surrogate_destroy(pbr_surrogate *s)
             (void)hipStreamSynchronize(s->train_stream);
             (void)hipStreamDestroy(s->train_stream);
         }
-        free_all(s);
     } catch (...) {
     }
     delete s;
@@ -465,11 +507,24 @@ int pbr_surrogate_adam_step(pbr_surrogate *s, const float *x_dev, const float *t
     SURR_GUARD_END
 }
 
+size_t pbr_surrogate_train_workspace_bytes(int64_t n_train_rays, int64_t n_val_rays, int32_t batch, int32_t epochs,
+                                           int32_t tiles)
+{
+    if (n_train_rays < 1 || n_val_rays < 1 || n_train_rays > ((int64_t)1 << 31) - 1 ||
+        n_val_rays > ((int64_t)1 << 31) - 1 || batch < 64 || batch % 64 || epochs < 1 || tiles < 1 ||
+        tiles > kMaxTiles || train_steps_bound(n_train_rays, batch, epochs) > (1ll << 30))
+        return 0;
+    TrainScratch t{};
+    Carve c;
+    layout_train(&t, c, n_train_rays, n_val_rays, batch, epochs, tiles);
+    return c.bytes();
+}
+
 int pbr_surrogate_train(pbr_surrogate *s, pbr_ctx *ctx, const float *train_src_dev, int64_t n_train_src,
                         int32_t train_rays_per_src, const float *val_src_dev, int64_t n_val_src,
                         int32_t val_rays_per_src, uint64_t train_seed,
-                        uint64_t val_seed, double ds, const pbr_surrogate_train_config *cfg,
-                        pbr_surrogate_report *report)
+                        uint64_t val_seed, double ds, const pbr_surrogate_train_config *cfg, void *ws_dev,
+                        size_t ws_bytes, pbr_surrogate_report *report)
 {
     if (!s) return PBR_ERR_ARG;
     SURR_GUARD_BEGIN
@@ -498,6 +553,14 @@ int pbr_surrogate_train(pbr_surrogate *s, pbr_ctx *ctx, const float *train_src_d
     if (!(cfg->tol_px > 0.0)) return sfail(s, PBR_ERR_ARG, "tol_px must be > 0");
     if (cfg->tiles < 1 || cfg->tiles > 1024) return sfail(s, PBR_ERR_ARG, "tiles must lie in [1, 1024]");
     if (cfg->min_tile_samples < 1) return sfail(s, PBR_ERR_ARG, "min_tile_samples must be >= 1");
+    if (!ws_dev || ((uintptr_t)ws_dev & 255u))
+        return sfail(s, PBR_ERR_ARG, "training workspace must be non-null and 256-byte aligned");
+    {
+        const size_t need = pbr_surrogate_train_workspace_bytes(n_train, n_val, cfg->batch, cfg->epochs, cfg->tiles);
+        if (need == 0) return sfail(s, PBR_ERR_ARG, "too many Adam steps (rays / batch x epochs above 2^30)");
+        if (ws_bytes < need)
+            return sfail(s, PBR_ERR_WORKSPACE, "training workspace of %zu bytes < %zu", ws_bytes, need);
+    }
     DeviceGuard g(s->device);
     if (!g.ok) return sfail(s, PBR_ERR_HIP, "hipSetDevice failed");
     std::memset(report, 0, sizeof *report);
@@ -523,22 +586,14 @@ int pbr_surrogate_train(pbr_surrogate *s, pbr_ctx *ctx, const float *train_src_d
     pbr::surrogate_spec_finish(spec);
     const int prec = ctx->n_fp64_bricks > 0 ? pbr::PREC_MIXED : pbr::PREC_FP32;
 
-    // scratch of this call, released on every return
-    struct Scratch {
-        std::vector<void *> p;
-        ~Scratch() { for (void *q : p) (void)hipFree(q); }
-        int get(void **q, size_t bytes)
-        {
-            *q = nullptr;
-            int e = (int)hipMalloc(q, bytes < 256 ? 256 : bytes);
-            if (!e) p.push_back(*q);
-            return e;
-        }
-    } scr;
-    pbr::SurrogateSample *trs = nullptr, *vas = nullptr;
-    if ((e = scr.get((void **)&trs, (size_t)n_train * sizeof(pbr::SurrogateSample))) ||
-        (e = scr.get((void **)&vas, (size_t)n_val * sizeof(pbr::SurrogateSample))))
-        return shf(s, e, "hipMalloc(samples)");
+    // scratch of this call, in the caller's training workspace
+    TrainScratch ts_{};
+    {
+        Carve c;
+        c.base = (unsigned char *)ws_dev;
+        layout_train(&ts_, c, n_train, n_val, cfg->batch, cfg->epochs, cfg->tiles);
+    }
+    pbr::SurrogateSample *trs = ts_.trs, *vas = ts_.vas;
 
     // 1. samples from the tracer
     auto t0 = clk::now();
@@ -547,16 +602,14 @@ int pbr_surrogate_train(pbr_surrogate *s, pbr_ctx *ctx, const float *train_src_d
     r = trace_samples(s, ctx, P, spec, prec, val_src_dev, n_val_src, val_rays_per_src, val_seed, vas);
     if (r) return r;
     // standardisation from the training samples
-    double *part = nullptr;
-    if ((e = scr.get((void **)&part, 1024 * pbr::kMoments * sizeof(double)))) return shf(s, e, "hipMalloc");
+    double *part = ts_.part;
     int nb = 0;
     if ((e = pbr::launch_surr_moments(trs, n_train, part, &nb, st))) return shf(s, e, "moments");
     std::vector<double> hp((size_t)nb * pbr::kMoments), mom(pbr::kMoments, 0.0);
     if ((e = (int)hipMemcpyAsync(hp.data(), part, hp.size() * sizeof(double), hipMemcpyDeviceToHost, st)))
         return shf(s, e, "copy moments");
     std::vector<int> flags((size_t)n_train);
-    int *dflags = nullptr;
-    if ((e = scr.get((void **)&dflags, (size_t)n_train * sizeof(int)))) return shf(s, e, "hipMalloc(flags)");
+    int *dflags = ts_.flags;
     if ((e = pbr::launch_surr_extract(trs, n_train, 0, dflags, st)) ||
         (e = (int)hipMemcpyAsync(flags.data(), dflags, (size_t)n_train * sizeof(int), hipMemcpyDeviceToHost, st)))
         return shf(s, e, "copy sample flags");
@@ -590,11 +643,8 @@ int pbr_surrogate_train(pbr_surrogate *s, pbr_ctx *ctx, const float *train_src_d
     const int64_t spe = (int64_t)valid.size() / cfg->batch;
     const int64_t total = spe * cfg->epochs;
     if (total > (1ll << 30)) return sfail(s, PBR_ERR_ARG, "too many Adam steps");
-    int *perm = nullptr;
-    float *losses = nullptr;
-    if ((e = scr.get((void **)&perm, (size_t)spe * cfg->batch * sizeof(int))) ||
-        (e = scr.get((void **)&losses, (size_t)total * sizeof(float))))
-        return shf(s, e, "hipMalloc(training)");
+    int *perm = ts_.perm;
+    float *losses = ts_.losses;
     t0 = clk::now();
     // One training step (gather, forward, backward, loss, Adam with the step counter on the
     // device) is captured once into a graph on the training stream and replayed for every step;
@@ -660,11 +710,8 @@ int pbr_surrogate_train(pbr_surrogate *s, pbr_ctx *ctx, const float *train_src_d
     // 3. validation in sensor pixels, per entry tile
     t0 = clk::now();
     const int64_t nt = (int64_t)cfg->tiles * cfg->tiles;
-    unsigned *tile_err = nullptr, *tile_cnt = nullptr;
-    float *err = nullptr;
-    if ((e = scr.get((void **)&tile_err, (size_t)(nt + 1) * 4)) || (e = scr.get((void **)&tile_cnt, (size_t)(nt + 1) * 4)) ||
-        (e = scr.get((void **)&err, (size_t)n_val * 4)))
-        return shf(s, e, "hipMalloc(validation)");
+    unsigned *tile_err = ts_.tile_err, *tile_cnt = ts_.tile_cnt;
+    float *err = ts_.err;
     if ((e = pbr::launch_clear_u64((unsigned long long *)tile_err, (nt + 1) / 2, st)) ||
         (e = pbr::launch_clear_u64((unsigned long long *)tile_cnt, (nt + 1) / 2, st)))
         return shf(s, e, "clear tiles");
@@ -678,9 +725,8 @@ int pbr_surrogate_train(pbr_surrogate *s, pbr_ctx *ctx, const float *train_src_d
     std::vector<unsigned> he((size_t)nt), hc((size_t)nt);
     std::vector<float> herr((size_t)n_val);
     std::vector<int> vtile((size_t)n_val);
-    int *dtile = nullptr;
-    if ((e = scr.get((void **)&dtile, (size_t)n_val * sizeof(int))) || (e = pbr::launch_surr_extract(vas, n_val, 1, dtile, st)))
-        return shf(s, e, "validation tiles");
+    int *dtile = ts_.flags;  // the training flags are consumed by now
+    if ((e = pbr::launch_surr_extract(vas, n_val, 1, dtile, st))) return shf(s, e, "validation tiles");
     if ((e = (int)hipMemcpyAsync(he.data(), tile_err, (size_t)nt * 4, hipMemcpyDeviceToHost, st)) ||
         (e = (int)hipMemcpyAsync(hc.data(), tile_cnt, (size_t)nt * 4, hipMemcpyDeviceToHost, st)) ||
         (e = (int)hipMemcpyAsync(herr.data(), err, (size_t)n_val * 4, hipMemcpyDeviceToHost, st)) ||
@@ -723,12 +769,6 @@ int pbr_surrogate_train(pbr_surrogate *s, pbr_ctx *ctx, const float *train_src_d
         report->val_median_px = ev[ev.size() / 2];
         report->val_p99_px = ev[std::min(ev.size() - 1, (size_t)(0.99 * (double)ev.size()))];
         report->val_max_px = ev.back();
-    }
-    if (nt > s->tile_cap) {
-        void *q = nullptr;
-        if ((e = dmalloc(s, &q, (size_t)nt))) return shf(s, e, "hipMalloc(tile map)");
-        s->tile_ok_dev = (unsigned char *)q;
-        s->tile_cap = nt;
     }
     if ((e = (int)hipMemcpy(s->tile_ok_dev, s->tile_ok.data(), (size_t)nt, hipMemcpyHostToDevice)))
         return shf(s, e, "copy tile map");
@@ -866,7 +906,7 @@ int pbr_surrogate_load(pbr_surrogate *s, pbr_ctx *ctx, const void *buf_host, siz
     if (!r.val(&key) || !r.get(g, sizeof g) || !r.get(sp.t_mean, sizeof sp.t_mean) ||
         !r.get(sp.t_scale, sizeof sp.t_scale) || !r.val(&tiles) || !r.val(&step))
         return sfail(s, PBR_ERR_ARG, "blob truncated");
-    if (tiles < 1 || tiles > 4096) return sfail(s, PBR_ERR_ARG, "blob: bad tile count");
+    if (tiles < 1 || tiles > kMaxTiles) return sfail(s, PBR_ERR_ARG, "blob: bad tile count");
     const size_t nt = (size_t)tiles * (size_t)tiles, N = (size_t)pbr::kParams;
     std::vector<unsigned char> tok(nt);
     std::vector<float> terr(nt), params(N), m(N), v(N);
@@ -889,12 +929,6 @@ int pbr_surrogate_load(pbr_surrogate *s, pbr_ctx *ctx, const void *buf_host, siz
         return shf(s, e, "copy the trained state");
     if ((e = pbr::mlp_refresh_shadow(s->d, s->stream)) || (e = (int)hipStreamSynchronize(s->stream)))
         return shf(s, e, "bf16 weights");
-    if ((int64_t)nt > s->tile_cap) {
-        void *q = nullptr;
-        if ((e = dmalloc(s, &q, nt))) return shf(s, e, "hipMalloc(tile map)");
-        s->tile_ok_dev = (unsigned char *)q;
-        s->tile_cap = (int64_t)nt;
-    }
     if ((e = (int)hipMemcpy(s->tile_ok_dev, tok.data(), nt, hipMemcpyHostToDevice))) return shf(s, e, "copy tile map");
     sp.z_lo = g[0]; sp.z_hi = g[1]; sp.x_lo = g[2]; sp.x_hi = g[3]; sp.y_lo = g[4]; sp.y_hi = g[5];
     sp.theta = g[6]; sp.Lx = g[7]; sp.Ly = g[8];

@@ -51,7 +51,8 @@ EXPORTED = ["pbr_create", "pbr_destroy", "pbr_last_error", "pbr_set_stream",
             "pbr_set_mie", "pbr_set_optical_chain", "pbr_field_workspace_bytes_nodes",
             "pbr_set_density_field_nodes", "pbr_surrogate_blob_bytes", "pbr_surrogate_save",
             "pbr_surrogate_load", "pbr_probe_fma_rate",
-            "pbr_probe_read_bandwidth", "pbr_probe_lds_bandwidth", "pbr_emit_and_trace_noalloc"]
+            "pbr_probe_read_bandwidth", "pbr_probe_lds_bandwidth", "pbr_emit_and_trace_noalloc",
+            "pbr_surrogate_workspace_bytes", "pbr_surrogate_train_workspace_bytes"]
 
 
 class PbrError(RuntimeError):
@@ -193,7 +194,9 @@ def load(path: str = LIB_PATH):
         "pbr_batch_run": (I, [P, C.POINTER(pbr_batch_stats)]),
         "pbr_batch_autotune": (I, [P, C.c_char_p, C.c_int32, C.POINTER(pbr_batch_config), C.POINTER(C.c_double)]),
         "pbr_read_ray_exits": (I, [P, P, I64, I64]),
-        "pbr_surrogate_create": (I, [C.POINTER(P), I, P, U64, I64]),
+        "pbr_surrogate_workspace_bytes": (C.c_size_t, [I64, I64]),
+        "pbr_surrogate_train_workspace_bytes": (C.c_size_t, [I64, I64, C.c_int32, C.c_int32, C.c_int32]),
+        "pbr_surrogate_create": (I, [C.POINTER(P), I, P, U64, I64, I64, P, C.c_size_t]),
         "pbr_surrogate_destroy": (None, [P]),
         "pbr_surrogate_last_error": (C.c_char_p, [P]),
         "pbr_surrogate_set_params": (I, [P, P, I64]),
@@ -202,7 +205,8 @@ def load(path: str = LIB_PATH):
         "pbr_surrogate_gradients": (I, [P, P, P, I64, P, C.POINTER(D)]),
         "pbr_surrogate_adam_step": (I, [P, P, P, I64, C.c_float, C.c_int32, C.POINTER(D)]),
         "pbr_surrogate_train": (I, [P, P, P, I64, C.c_int32, P, I64, C.c_int32, U64, U64, D,
-                                    C.POINTER(pbr_surrogate_train_config), C.POINTER(pbr_surrogate_report)]),
+                                    C.POINTER(pbr_surrogate_train_config), P, C.c_size_t,
+                                    C.POINTER(pbr_surrogate_report)]),
         "pbr_surrogate_tile_map": (I, [P, P, P, I64]),
         "pbr_set_surrogate": (I, [P, P]),
         "pbr_surrogate_blob_bytes": (C.c_size_t, [P]),
@@ -727,9 +731,19 @@ def _scheck(sg, code):
         raise PbrError(code, msg.decode() if msg else "")
 
 
-def pbr_surrogate_create(device, stream, init_seed=0, max_rows=0):
+def pbr_surrogate_workspace_bytes(max_rows, ray_chunk) -> int:
+    return int(load().pbr_surrogate_workspace_bytes(int(max_rows), int(ray_chunk)))
+
+
+def pbr_surrogate_train_workspace_bytes(n_train_rays, n_val_rays, batch, epochs, tiles) -> int:
+    return int(load().pbr_surrogate_train_workspace_bytes(int(n_train_rays), int(n_val_rays), int(batch),
+                                                          int(epochs), int(tiles)))
+
+
+def pbr_surrogate_create(device, stream, init_seed, max_rows, ray_chunk, ws):
     h = C.c_void_p()
-    code = load().pbr_surrogate_create(C.byref(h), int(device), stream, int(init_seed), int(max_rows))
+    code = load().pbr_surrogate_create(C.byref(h), int(device), stream, int(init_seed), int(max_rows),
+                                       int(ray_chunk), _dptr(ws), ws.numel() * ws.element_size())
     if code != PBR_OK:
         raise PbrError(code, _lib.pbr_surrogate_last_error(None).decode())
     return h
@@ -771,12 +785,13 @@ def pbr_surrogate_adam_step(sg, x, t, lr, step, want_loss=False):
 
 
 def pbr_surrogate_train(sg, ctx, train_src, train_rays_per_src, val_src, val_rays_per_src, train_seed, val_seed,
-                        ds, cfg: pbr_surrogate_train_config) -> pbr_surrogate_report:
+                        ds, cfg: pbr_surrogate_train_config, ws) -> pbr_surrogate_report:
     rep = pbr_surrogate_report()
     _scheck(sg, load().pbr_surrogate_train(sg, ctx, _dptr(train_src), int(train_src.shape[0]),
                                            int(train_rays_per_src), _dptr(val_src), int(val_src.shape[0]),
                                            int(val_rays_per_src), int(train_seed), int(val_seed), float(ds),
-                                           C.byref(cfg), C.byref(rep)))
+                                           C.byref(cfg), _dptr(ws), ws.numel() * ws.element_size(),
+                                           C.byref(rep)))
     return rep
 
 
@@ -807,12 +822,19 @@ def pbr_set_surrogate(ctx, sg):
 class Surrogate:
     """The ray surrogate network on torch's current device and stream."""
 
-    def __init__(self, device=None, init_seed=0, max_rows=0):
+    def __init__(self, device=None, init_seed=0, max_rows=0, ray_chunk=1 << 22):
+        """max_rows: rows per training or forward pass; ray_chunk: the largest trace chunk (rays)
+        of the renderers the surrogate is attached to (53 bytes of device buffers per ray)."""
         import torch
         self.torch = torch
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
         stream = torch.cuda.current_stream(self.device)
-        self.h = pbr_surrogate_create(self.device.index, C.c_void_p(stream.cuda_stream), init_seed, max_rows)
+        nb = pbr_surrogate_workspace_bytes(max_rows, ray_chunk)
+        if nb == 0:
+            raise PbrError(PBR_ERR_ARG, "max_rows or ray_chunk out of range")
+        self.ws = torch.empty(nb // 8, dtype=torch.int64, device=self.device)
+        self.h = pbr_surrogate_create(self.device.index, C.c_void_p(stream.cuda_stream), init_seed, max_rows,
+                                      ray_chunk, self.ws)
         self.tiles = 0
 
     def _dev(self, a):
@@ -842,8 +864,12 @@ class Surrogate:
         cfg = pbr_surrogate_train_config(int(batch), int(epochs), float(lr_max), float(lr_min), float(tol_px),
                                          int(tiles), int(min_tile_samples), int(shuffle_seed))
         tr, va = self._dev(train_src), self._dev(val_src)
+        nb = pbr_surrogate_train_workspace_bytes(tr.shape[0] * train_rays_per_src, va.shape[0] * val_rays_per_src,
+                                                 batch, epochs, tiles)
+        ws = self.torch.empty(max(nb, 8) // 8, dtype=self.torch.int64, device=self.device)
         rep = pbr_surrogate_train(self.h, renderer.ctx, tr, train_rays_per_src, va, val_rays_per_src, train_seed,
-                                  val_seed, ds, cfg)
+                                  val_seed, ds, cfg, ws)
+        del ws
         self.tiles = int(tiles)
         return {k: getattr(rep, k) for k, _ in pbr_surrogate_report._fields_}
 

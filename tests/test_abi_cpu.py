@@ -266,10 +266,18 @@ def test_derived_optics_match_oracle(lib, make):
 
 def test_surrogate_entry_points_validate_before_device_work(lib):
     h = C.c_void_p()
-    assert lib.pbr_surrogate_create(C.byref(h), 0, None, 1, -5) == pbr.PBR_ERR_ARG
+    need = lib.pbr_surrogate_workspace_bytes(0, 1 << 12)
+    assert lib.pbr_surrogate_create(C.byref(h), 0, None, 1, -5, 1 << 12, FAKE, need) == pbr.PBR_ERR_ARG
     assert h.value is None
     assert b"max_rows" in lib.pbr_surrogate_last_error(None)
-    assert lib.pbr_surrogate_create(None, 0, None, 1, 0) == pbr.PBR_ERR_ARG
+    assert lib.pbr_surrogate_create(None, 0, None, 1, 0, 0, FAKE, need) == pbr.PBR_ERR_ARG
+    assert lib.pbr_surrogate_create(C.byref(h), 0, None, 1, 0, -1, FAKE, need) == pbr.PBR_ERR_ARG
+    assert lib.pbr_surrogate_create(C.byref(h), 0, None, 1, 0, 1 << 12, None, need) == pbr.PBR_ERR_ARG
+    assert lib.pbr_surrogate_create(C.byref(h), 0, None, 1, 0, 1 << 12, FAKE + 16, need) == pbr.PBR_ERR_ARG
+    assert b"256-byte" in lib.pbr_surrogate_last_error(None)
+    # the workspace check comes before any device call (this container has no GPU)
+    assert lib.pbr_surrogate_create(C.byref(h), 0, None, 1, 0, 1 << 12, FAKE, need - 1) == pbr.PBR_ERR_WORKSPACE
+    assert h.value is None
     for fn, args in (("pbr_surrogate_set_params", (None, 0)), ("pbr_surrogate_get_params", (None, 0)),
                      ("pbr_surrogate_forward", (None, 0, None)),
                      ("pbr_surrogate_gradients", (None, None, 64, None, None)),
@@ -519,3 +527,28 @@ def test_noalloc_trace_validates_before_device_work(lib):
             assert "host-only" in _err(lib, h)
     finally:
         lib.pbr_destroy(h)
+
+
+def test_surrogate_workspace_sizes(lib):
+    """Persistent workspace: parameters, moments and bf16 copies (fixed), 10.3 kB per training row
+    (pre-activations, activations and gradients of four 256-wide layers), 53 B per trace-chunk ray
+    and a 1 MiB tile map, each part rounded up to 256 B; training workspace: 88 B samples per ray,
+    shuffles, losses and per-tile validation maxima."""
+    ws = lib.pbr_surrogate_workspace_bytes
+    base = ws(64, 0)
+    assert base > 1 << 20
+    assert ws(0, 0) == ws(65536, 0)          # 0 rows means 65536
+    assert ws(100, 0) == ws(128, 0)          # rows round up to 64
+    per_row = (ws(64 + 64 * 1024, 0) - base) / (64 * 1024)
+    assert abs(per_row - 10336) < 1  # 4 x 256 x (4 + 2) + 2 x 256 x 4 + 4 x 256 x 2 + 4 x 6 x 4 (+ loss partials)
+    per_ray = (ws(64, 1 << 20) - base) / (1 << 20)
+    assert abs(per_ray - 53) < 1e-3
+    assert ws(-1, 0) == 0 and ws(1 << 25, 0) == 0 and ws(64, -1) == 0
+    tw = lib.pbr_surrogate_train_workspace_bytes
+    t0 = tw(1 << 20, 1 << 18, 4096, 8, 64)
+    # samples of both sets dominate: 88 B per ray
+    assert 88 * ((1 << 20) + (1 << 18)) < t0 < 110 * ((1 << 20) + (1 << 18))
+    assert tw(1 << 20, 1 << 18, 4096, 8, 64) < tw(1 << 20, 1 << 18, 4096, 8, 1024)
+    assert tw(0, 1, 64, 1, 1) == 0 and tw(1, 1, 100, 1, 1) == 0 and tw(1, 1, 64, 0, 1) == 0
+    assert tw(1, 1, 64, 1, 1025) == 0
+    assert tw((1 << 31) - 1, 1, 64, 1 << 20, 1) == 0  # more than 2^30 Adam steps

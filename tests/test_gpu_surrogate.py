@@ -211,6 +211,33 @@ def test_surrogate_gain_over_the_tracer(torch, trained):
     assert min(s_ms) < 0.8 * min(t_ms)
 
 
+def test_surrogate_buffers_bound_the_trace_chunk(torch, trained):
+    """The surrogate's inference buffers are sized at creation for trace chunks of 2^22 rays: a
+    context whose chunk is larger is refused (WORKSPACE) before any launch; the allocation-free
+    trace with a chunk inside that size runs the network and renders the same image as the
+    workspace trace."""
+    sc, r, s, rep = trained
+    s.attach(r)
+    ev = torch.as_tensor(inputs.sources(sc.replace(n_src=3000, src_seed=505)), device="cuda")
+    flags = pbr.PBR_CLEAR_FIRST | pbr.PBR_SURROGATE
+    st_ws = r.emit_and_trace(ev, 100, 51, sc.ds, flags, stats=True)
+    img_ws = pbr.u64_image_to_numpy(r.read_image())
+    st_na = pbr.stats_dict(pbr.pbr_emit_and_trace_noalloc(r.ctx, ev, 100, 51, sc.ds, flags, 1 << 20,
+                                                          want_stats=True))
+    img_na = pbr.u64_image_to_numpy(r.read_image())
+    assert st_na["surrogate_rays"] == st_ws["surrogate_rays"] > 0
+    assert np.array_equal(img_na, img_ws)
+    big = torch.empty(pbr.pbr_trace_workspace_bytes(1 << 23) // 8, dtype=torch.int64, device="cuda")
+    pbr.pbr_set_trace_workspace(r.ctx, big)
+    try:
+        with pytest.raises(pbr.PbrError, match="trace chunks of at most") as ei:
+            r.emit_and_trace(ev, 100, 51, sc.ds, flags)
+        assert ei.value.code == pbr.PBR_ERR_WORKSPACE
+    finally:
+        pbr.pbr_set_trace_workspace(r.ctx, r.trace_ws)
+    assert np.array_equal(pbr.u64_image_to_numpy(r.read_image()), img_ws)  # the refused call left no trace
+
+
 def test_save_and_load(torch, trained):
     """A saved surrogate loaded into a fresh context of the same scene gives the same parameters,
     tile map and image bit for bit; another field, a damaged blob or another step length is refused."""
