@@ -201,13 +201,13 @@ int pbr_set_density_field(pbr_ctx *ctx, const float *rho_dev, int nx, int ny, in
 
 /* Node layout for fine grids: the same field stored as one float4 (n - 1, grad n) per node (16 bytes
  * per node instead of 128 per cell, so the field of a grid whose cells are about one step long can
- * stay in the GPU's caches); the integration kernel forms each cell's interpolation coefficients
- * from its eight corners when a ray enters the cell (a dedicated kernel variant at four waves per
- * SIMD).  Same arguments, validation and results (to float32 rounding of the coefficients) as
- * pbr_set_density_field; workspace pbr_field_workspace_bytes_nodes: 16 bytes per node plus the
- * brick tables, each part rounded up to 256 bytes.  Lane refill (PBR_LANE_REFILL), shock FP64 steps
- * (PBR_PREC_SHOCK_FP64, pbr_calibrate_precision) and batches need the per-cell field and return
- * STATE with a node-layout field. */
+ * stay in the GPU's caches); the integration kernel interpolates the eight corners of the cell a
+ * sample lies in directly (a dedicated kernel variant at four waves per SIMD).  Same arguments,
+ * validation and results (to float32 rounding) as pbr_set_density_field; workspace
+ * pbr_field_workspace_bytes_nodes: 16 bytes per node plus the brick tables, each part rounded up to
+ * 256 bytes.  Lane refill (PBR_LANE_REFILL) and shock FP64 steps (PBR_PREC_SHOCK_FP64,
+ * pbr_calibrate_precision) need the per-cell field and return STATE with a node-layout field;
+ * batches take either layout, image by image. */
 size_t pbr_field_workspace_bytes_nodes(int nx, int ny, int nz);
 int pbr_set_density_field_nodes(pbr_ctx *ctx, const float *rho_dev, int nx, int ny, int nz,
                                 const double origin[3], const double spacing[3], double K,
@@ -502,6 +502,7 @@ typedef struct pbr_batch_stats {
     double run_ms;           /* device time of the graph launch (HIP events) */
     int32_t rounds;
     int32_t images;
+    uint64_t rkn_steps_nodes; /* of rkn_steps, those of images with a node-layout field */
 } pbr_batch_stats;
 
 /* Workspace bytes for a batch whose rounds hold up to round_rays rays (64 bytes per ray state
@@ -524,11 +525,12 @@ int pbr_batch_configure(pbr_batch *b, const pbr_batch_config *cfg);
  * all images.  Errors: OVERFLOW (an accumulating item would exceed 2^32 - 1 rays), HIP. */
 int pbr_batch_run(pbr_batch *b, pbr_batch_stats *stats);
 /* Autotuner of the batched launch.  With cache_path naming a file that holds a choice for this
- * device and batch shape (architecture, grid and sensor sizes, source and ray counts of every
- * image), that choice is applied.  Otherwise every combination of box_block {64, 256},
+ * device and batch shape (architecture, grid and sensor sizes, field layout, source and ray counts
+ * of every image), that choice is applied.  Otherwise every combination of box_block {64, 256},
  * unit_rays {64, 256}, tile {16, 32} and round_rays {largest, half} is timed on the first
- * probe_rounds rounds (direct launches, HIP events), the fastest (rays per ms) is applied and
- * appended to cache_path (if given).  Leaves the accumulators and counters of the batch's images
+ * probe_rounds rounds (direct launches, HIP events; median of three passes after a warm-up), the
+ * three fastest are timed again (median of five) and the fastest of those (rays per ms) is applied
+ * and appended to cache_path (if given).  Leaves the accumulators and counters of the batch's images
  * in an unspecified state: run the batch with PBR_CLEAR_FIRST items afterwards.  Synchronises. */
 int pbr_batch_autotune(pbr_batch *b, const char *cache_path, int32_t probe_rounds, pbr_batch_config *chosen,
                        double *rays_per_ms);

@@ -41,6 +41,7 @@ struct pbr_batch {
     std::vector<pbr::BatchSeg> segs;
     std::vector<int> round_begin;              // segment index of each round, plus the end
     std::vector<int64_t> round_slots;
+    std::vector<unsigned char> round_layouts;  // per round: bit 0 per-cell images, bit 1 node images
     // graph
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -65,7 +66,8 @@ int bfail(pbr_batch *b, int code, const char *fmt, ...)
 
 thread_local std::string g_batch_create_err;
 
-// Workspace layout of a batch: per-image parameters, segment table, queue counter, ray states.
+// Workspace layout of a batch: per-image parameters, segment table, two queue counters (one per
+// field layout), ray states.
 struct BatchLayout {
     size_t params_off, segs_off, queue_off, state_off, total;
 };
@@ -101,6 +103,7 @@ void plan(pbr_batch *b)
     b->segs.clear();
     b->round_begin.assign(1, 0);
     b->round_slots.clear();
+    b->round_layouts.clear();
     const int64_t cap_slots = b->cfg.round_rays / 256;
     int64_t used = 0;  // slots used in the current round
     for (int i : order) {
@@ -112,6 +115,8 @@ void plan(pbr_batch *b)
                 b->round_begin.push_back((int)b->segs.size());
                 used = 0;
             }
+            if (used == 0) b->round_layouts.push_back(0);
+            b->round_layouts.back() |= b->params[(size_t)i].node_layout ? 2 : 1;
             const int64_t take = std::min(remaining, (cap_slots - used) * 256);
             pbr::BatchSeg sg;
             sg.image = i;
@@ -150,8 +155,10 @@ int enqueue_rounds(pbr_batch *b, int r0, int r1)
     for (int r = r0; r < r1; ++r) {
         const int s0 = b->round_begin[(size_t)r];
         const int ns = b->round_begin[(size_t)r + 1] - s0;
+        const unsigned char lay = b->round_layouts[(size_t)r];
         const int e = pbr::launch_batch_round(b->d_params, b->d_segs + s0, ns, b->round_slots[(size_t)r],
-                                              b->d_state, b->d_queue, b->cfg, b->n_cu, b->enq);
+                                              b->d_state, b->d_queue, b->cfg, b->n_cu, b->enq, (lay & 1) != 0,
+                                              (lay & 2) != 0);
         if (e) return bfail(b, PBR_ERR_HIP, "batch round %d: %s", r, hipGetErrorString((hipError_t)e));
     }
     return PBR_OK;
@@ -199,15 +206,15 @@ uint64_t fnv1a(const void *p, size_t n, uint64_t h)
     return h;
 }
 
-// Key of the tuning cache: device architecture and the shape of every image.
+// Key of the tuning cache: device architecture and the shape (and field layout) of every image.
 std::string tune_key(pbr_batch *b)
 {
     hipDeviceProp_t prop;
     uint64_t h = 0xcbf29ce484222325ull;
     if (hipGetDeviceProperties(&prop, b->device) == hipSuccess) h = fnv1a(prop.gcnArchName, strlen(prop.gcnArchName), h);
     for (const pbr_batch_item &it : b->items) {
-        const int64_t v[7] = {it.ctx->nx, it.ctx->ny, it.ctx->nz, it.ctx->sensor.width, it.ctx->sensor.height,
-                              it.n_src, it.rays_per_src};
+        const int64_t v[8] = {it.ctx->nx, it.ctx->ny, it.ctx->nz, it.ctx->sensor.width, it.ctx->sensor.height,
+                              it.n_src, it.rays_per_src, it.ctx->layout.nodes ? 1 : 0};
         h = fnv1a(v, sizeof v, h);
     }
     char buf[32];
@@ -280,11 +287,6 @@ int pbr_batch_create(pbr_batch **out, const pbr_batch_item *items, int n_items, 
             pbr::host::Derived d;
             const int r = pbr::host::derive(c, &d);
             if (r) { g_batch_create_err = std::string("item ") + std::to_string(i) + ": " + c->err; delete b; return r; }
-            if (c->layout.nodes) {
-                g_batch_create_err = "item " + std::to_string(i) + ": batches need the per-cell field";
-                delete b;
-                return PBR_ERR_STATE;
-            }
             if (c->has_chain) {
                 g_batch_create_err = "item " + std::to_string(i) + ": batches use the singlet (an optical chain is set)";
                 delete b;
@@ -474,6 +476,7 @@ int pbr_batch_run(pbr_batch *b, pbr_batch_stats *stats)
                 stats->rays += (uint64_t)b->params[i].n_rays;
                 for (int k = 0; k < PBR_NUM_STATUS; ++k) stats->status[k] += h[pbr::CNT_STATUS + k];
                 stats->rkn_steps += h[pbr::CNT_STEPS];
+                if (b->params[i].node_layout) stats->rkn_steps_nodes += h[pbr::CNT_STEPS];
             }
         }
         return PBR_OK;
@@ -513,8 +516,38 @@ int pbr_batch_autotune(pbr_batch *b, const char *cache_path, int32_t probe_round
         std::vector<int64_t> rounds_rays{b->max_round_rays};
         const int64_t half = b->max_round_rays / 2 / 256 * 256;
         if (half >= b->min_round_rays && half >= 65536) rounds_rays.push_back(half);
-        pbr_batch_config best{};
-        double best_rate = -1.0;
+        // every candidate: one warm-up pass over the probe rounds, then the median rate of three
+        // timed passes; the three best are timed again (median of five) and the best of those kept,
+        // so that one noisy timing does not decide
+        struct Cand {
+            pbr_batch_config c;
+            double rate;
+        };
+        std::vector<Cand> cands;
+        auto time_config = [&](const pbr_batch_config &c, int repeats, double *rate) -> int {
+            int r = pbr_batch_configure(b, &c);
+            if (r) return r;
+            const int nr = std::min<int>(probe_rounds, (int)b->round_slots.size());
+            int64_t rays = 0;
+            for (int q = 0; q < nr; ++q)
+                for (int s2 = b->round_begin[(size_t)q]; s2 < b->round_begin[(size_t)q + 1]; ++s2)
+                    rays += b->segs[(size_t)s2].n_rays;
+            if ((r = enqueue_rounds(b, 0, nr))) return r;  // warm-up (direct launches)
+            std::vector<double> rates;
+            for (int t = 0; t < repeats; ++t) {
+                int e = (int)hipEventRecord(b->ev0, b->stream);
+                if (!e && (r = enqueue_rounds(b, 0, nr))) return r;
+                if (!e) e = (int)hipEventRecord(b->ev1, b->stream);
+                if (!e) e = (int)hipEventSynchronize(b->ev1);
+                float ms = 0.0f;
+                if (!e) e = (int)hipEventElapsedTime(&ms, b->ev0, b->ev1);
+                if (e) return bfail(b, PBR_ERR_HIP, "autotune timing: %s", hipGetErrorString((hipError_t)e));
+                rates.push_back(ms > 0.0f ? (double)rays / (double)ms : 0.0);
+            }
+            std::sort(rates.begin(), rates.end());
+            *rate = rates[rates.size() / 2];
+            return PBR_OK;
+        };
         for (int64_t rr : rounds_rays)
             for (int bb : {64, 256})
                 for (int ur : {64, 256})
@@ -524,25 +557,18 @@ int pbr_batch_autotune(pbr_batch *b, const char *cache_path, int32_t probe_round
                         c.unit_rays = ur;
                         c.tile = tl;
                         c.round_rays = rr;
-                        int r = pbr_batch_configure(b, &c);
-                        if (r) return r;
-                        const int nr = std::min<int>(probe_rounds, (int)b->round_slots.size());
-                        int64_t rays = 0;
-                        for (int q = 0; q < nr; ++q)
-                            for (int s = b->round_begin[(size_t)q]; s < b->round_begin[(size_t)q + 1]; ++s)
-                                rays += b->segs[(size_t)s].n_rays;
-                        // warm-up, then one timed pass over the probe rounds (direct launches)
-                        if ((r = enqueue_rounds(b, 0, nr))) return r;
-                        int e = (int)hipEventRecord(b->ev0, b->stream);
-                        if (!e && (r = enqueue_rounds(b, 0, nr))) return r;
-                        if (!e) e = (int)hipEventRecord(b->ev1, b->stream);
-                        if (!e) e = (int)hipEventSynchronize(b->ev1);
-                        float ms = 0.0f;
-                        if (!e) e = (int)hipEventElapsedTime(&ms, b->ev0, b->ev1);
-                        if (e) return bfail(b, PBR_ERR_HIP, "autotune timing: %s", hipGetErrorString((hipError_t)e));
-                        const double rate = ms > 0.0f ? (double)rays / (double)ms : 0.0;
-                        if (rate > best_rate) { best_rate = rate; best = c; }
+                        double rate = 0.0;
+                        if (int r = time_config(c, 3, &rate)) return r;
+                        cands.push_back({c, rate});
                     }
+        std::stable_sort(cands.begin(), cands.end(), [](const Cand &x, const Cand &y) { return x.rate > y.rate; });
+        pbr_batch_config best = cands[0].c;
+        double best_rate = -1.0;
+        for (size_t k = 0; k < std::min<size_t>(3, cands.size()); ++k) {
+            double rate = 0.0;
+            if (int r = time_config(cands[k].c, 5, &rate)) return r;
+            if (rate > best_rate) { best_rate = rate; best = cands[k].c; }
+        }
         int r = pbr_batch_configure(b, &best);
         if (r) return r;
         if (cache_path) {

@@ -246,9 +246,11 @@ int launch_calibrate(const TraceParams &p, const int *bricks, int n_bricks, int 
                      int n_steps, uint64_t seed, double z_focus, double px_per_m, float *err,
                      hipStream_t stream);
 // One round of a batch: emission over n_slots * 256 ray states, persistent integration with a
-// wave-level work queue (queue: one zeroed counter), finish with per-segment parameters.
+// wave-level work queue (queue: two counters, zeroed by the round, one per field layout; cells /
+// nodes: the round holds images of that layout), finish with per-segment parameters.
 int launch_batch_round(const TraceParams *params, const BatchSeg *segs, int nseg, int64_t n_slots,
-                       RayState *st, unsigned *queue, const BatchConfig &cfg, int n_cu, hipStream_t stream);
+                       RayState *st, unsigned *queue, const BatchConfig &cfg, int n_cu, hipStream_t stream,
+                       bool cells, bool nodes);
 
 // Rays [first, first + n) through all four steps; st: n RayState of workspace.
 // box_begin / box_end (may be null) are recorded around the integration kernel.

@@ -1300,30 +1300,32 @@ __global__ void __launch_bounds__(256) k_emit_batch(const TraceParams *__restric
 
 // Persistent integration over one round: every wave pulls the next unit of `unit_rays` rays
 // (64, 128 or 256: units never straddle a slot) from a global counter until none is left.
-// Segments are ordered by decreasing estimated cost, so long rays start first.
-template <int BLOCK>
-__global__ void __launch_bounds__(BLOCK, 5) k_box_batch(const TraceParams *__restrict__ params,
-                                                        const BatchSeg *__restrict__ segs, int nseg,
-                                                        RayState *__restrict__ st, unsigned *queue,
-                                                        unsigned n_units, int unit_rays)
+// Segments are ordered by decreasing estimated cost, so long rays start first.  NODES: the
+// images whose field is stored per node (their own counter, queue[1]; the per-cell images use
+// queue[0]); each kernel passes over the other layout's units.
+template <int BLOCK, bool NODES>
+__global__ void __launch_bounds__(BLOCK, NODES ? 4 : 5) k_box_batch(const TraceParams *__restrict__ params,
+                                                                    const BatchSeg *__restrict__ segs, int nseg,
+                                                                    RayState *__restrict__ st, unsigned *queue,
+                                                                    unsigned n_units, int unit_rays)
 {
     const int lane = threadIdx.x & 63;
     for (;;) {
         unsigned u = 0;
-        if (lane == 0) u = atomicAdd(queue, 1u);
+        if (lane == 0) u = atomicAdd(queue + (NODES ? 1 : 0), 1u);
         u = __builtin_amdgcn_readfirstlane(__shfl(u, 0, 64));
         if (u >= n_units) break;
         const int64_t ray0 = (int64_t)u * unit_rays;  // state index of the unit's first ray
         const int k = __builtin_amdgcn_readfirstlane(find_segment(segs, nseg, ray0 >> 8));
         const BatchSeg sg = segs[k];
         const TraceParams &P = params[sg.image];
-        if (P.node_layout) continue;  // cell records only (batches refuse node-layout fields)
+        if ((P.node_layout != 0) != NODES) continue;  // the other kernel's image
         for (int sub = 0; sub < unit_rays; sub += 64) {
             const int64_t idx = ray0 + sub + lane;
             if (idx - sg.slot_base * 256 >= sg.n_rays) continue;
             RayState r = st[idx];
             if ((r.info & (RS_ENTERED | RS_SURR)) != RS_ENTERED) continue;
-            box_ray<float>(P, r);
+            box_ray<float, NODES>(P, r);
             st[idx] = r;
         }
     }
@@ -1765,22 +1767,36 @@ int launch_trace_chunk(const TraceParams &p, RayState *st, int64_t first, int64_
 }
 
 int launch_batch_round(const TraceParams *params, const BatchSeg *segs, int nseg, int64_t n_slots,
-                       RayState *st, unsigned *queue, const BatchConfig &cfg, int n_cu, hipStream_t stream)
+                       RayState *st, unsigned *queue, const BatchConfig &cfg, int n_cu, hipStream_t stream,
+                       bool cells, bool nodes)
 {
     if (n_slots <= 0) return 0;
-    int e = launch_clear_u64((unsigned long long *)queue, 1, stream);
+    int e = launch_clear_u64((unsigned long long *)queue, 1, stream);  // both counters
     if (e) return e;
     hipLaunchKernelGGL(k_emit_batch, dim3((unsigned)n_slots), dim3(256), 0, stream, params, segs, nseg, st);
     if ((e = (int)hipGetLastError())) return e;
     const unsigned n_units = (unsigned)(n_slots * 256 / cfg.unit_rays);
-    const unsigned waves = (unsigned)n_cu * 4u * 5u;  // five waves per SIMD
-    if (cfg.box_block == 64)
-        hipLaunchKernelGGL(k_box_batch<64>, dim3(waves), dim3(64), 0, stream, params, segs, nseg, st, queue,
-                           n_units, cfg.unit_rays);
-    else
-        hipLaunchKernelGGL(k_box_batch<256>, dim3(waves / 4u), dim3(256), 0, stream, params, segs, nseg, st,
-                           queue, n_units, cfg.unit_rays);
-    if ((e = (int)hipGetLastError())) return e;
+    // a persistent grid per field layout present in the round: five waves per SIMD for the
+    // per-cell kernel, four for the node kernel (its register budget)
+    const unsigned w_cells = (unsigned)n_cu * 4u * 5u, w_nodes = (unsigned)n_cu * 4u * 4u;
+    if (cells) {
+        if (cfg.box_block == 64)
+            hipLaunchKernelGGL((k_box_batch<64, false>), dim3(w_cells), dim3(64), 0, stream, params, segs, nseg, st,
+                               queue, n_units, cfg.unit_rays);
+        else
+            hipLaunchKernelGGL((k_box_batch<256, false>), dim3(w_cells / 4u), dim3(256), 0, stream, params, segs,
+                               nseg, st, queue, n_units, cfg.unit_rays);
+        if ((e = (int)hipGetLastError())) return e;
+    }
+    if (nodes) {
+        if (cfg.box_block == 64)
+            hipLaunchKernelGGL((k_box_batch<64, true>), dim3(w_nodes), dim3(64), 0, stream, params, segs, nseg, st,
+                               queue, n_units, cfg.unit_rays);
+        else
+            hipLaunchKernelGGL((k_box_batch<256, true>), dim3(w_nodes / 4u), dim3(256), 0, stream, params, segs,
+                               nseg, st, queue, n_units, cfg.unit_rays);
+        if ((e = (int)hipGetLastError())) return e;
+    }
     if (cfg.tile == 16)
         hipLaunchKernelGGL(k_finish_batch<16>, dim3((unsigned)n_slots), dim3(256), 0, stream, params, segs, nseg,
                            (const RayState *)st);

@@ -130,7 +130,8 @@ class pbr_batch_config(C.Structure):
 
 class pbr_batch_stats(C.Structure):
     _fields_ = [("rays", C.c_uint64), ("status", C.c_uint64 * PBR_NUM_STATUS), ("rkn_steps", C.c_uint64),
-                ("run_ms", C.c_double), ("rounds", C.c_int32), ("images", C.c_int32)]
+                ("run_ms", C.c_double), ("rounds", C.c_int32), ("images", C.c_int32),
+                ("rkn_steps_nodes", C.c_uint64)]
 
 
 class pbr_surrogate_train_config(C.Structure):
@@ -696,7 +697,8 @@ class Batch:
         if st is None:
             return None
         return dict(rays=int(st.rays), status=[int(x) for x in st.status], rkn_steps=int(st.rkn_steps),
-                    run_ms=float(st.run_ms), rounds=int(st.rounds), images=int(st.images))
+                    run_ms=float(st.run_ms), rounds=int(st.rounds), images=int(st.images),
+                    rkn_steps_nodes=int(st.rkn_steps_nodes))
 
     def config(self) -> dict:
         return config_dict(pbr_batch_get_config(self.h))

@@ -80,7 +80,7 @@ def test_binding_structs_match_c_compiler_layout(tmp_path):
 def test_batch_structs_and_workspace(lib):
     assert C.sizeof(pbr.pbr_batch_item) == 48
     assert C.sizeof(pbr.pbr_batch_config) == 48
-    assert C.sizeof(pbr.pbr_batch_stats) == 8 * 9 + 8 + 8
+    assert C.sizeof(pbr.pbr_batch_stats) == 8 * 9 + 8 + 8 + 8
     it = pbr.pbr_batch_item(FAKE, FAKE, 1000, 100, 1, 1, 1e-4)
     nb = pbr.pbr_batch_workspace_bytes([it, it], 1 << 20)
     assert nb >= (1 << 20) * 64 and nb % 256 == 0

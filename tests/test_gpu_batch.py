@@ -37,11 +37,12 @@ def _small_batch(n=6):
     return out
 
 
-def _renderers(scenes):
+def _renderers(scenes, nodes=None):
     rs = []
-    for sc in scenes:
+    for i, sc in enumerate(scenes):
         r = pbr.Renderer(rays_per_chunk=1 << 16)
-        r.set_density_field(inputs.density(sc), sc.origin, sc.spacing, sc.K, sc.rho_inf)
+        r.set_density_field(inputs.density(sc), sc.origin, sc.spacing, sc.K, sc.rho_inf,
+                            nodes=bool(nodes[i]) if nodes is not None else False)
         r.set_optics(sc.z_lens, sc.focal_length, sc.f_number, sc.thickness, sc.n_glass, sc.clear_radius,
                      sc.z_focus)
         r.set_sensor(sc.width, sc.height, sc.pitch, sc.z_sensor, sc.wavelength, sc.sigma_px, sc.dtau_with_pi)
@@ -155,6 +156,45 @@ def test_batch_refuses_contexts_changed_since_creation(torch):
     with pytest.raises(pbr.PbrError) as ei:
         b.run()
     assert ei.value.code == pbr.PBR_ERR_STATE
+    b.close()
+
+
+def test_batch_mixes_field_layouts(torch):
+    """Images stored per node and per cell in one batch (two persistent integration kernels per
+    round, one queue each): every image equals its single render in the same layout bit for bit,
+    before and after tuning, and a node image's records match the oracle (1e-4 px)."""
+    import oracle
+    scenes = _small_batch(5)
+    nodes = [False, True, True, False, True]
+    srcs = [inputs.sources(sc) for sc in scenes]
+    singles = _renderers(scenes, nodes)
+    ref = []
+    for r, sc, s in zip(singles, scenes, srcs):
+        r.emit_and_trace(s, sc.rays_per_src, sc.ray_seed, sc.ds, pbr.PBR_CLEAR_FIRST)
+        ref.append(pbr.u64_image_to_numpy(r.read_image()))
+    rs = _renderers(scenes, nodes)
+    k = 1
+    rs[k].set_exit_recording(0, 1, scenes[k].n_rays)
+    flags = [pbr.PBR_CLEAR_FIRST | (pbr.PBR_RECORD_EXITS if i == k else 0) for i in range(len(scenes))]
+    b = pbr.Batch(rs, srcs, [s.rays_per_src for s in scenes], [s.ray_seed for s in scenes],
+                  [s.ds for s in scenes], flags=flags, round_rays=1 << 16)
+    st = b.run()
+    print(f"\nmixed-layout batch: {st['rounds']} rounds, config {b.config()}")
+    assert st["rounds"] > 1
+    for i, r in enumerate(rs):
+        assert np.array_equal(pbr.u64_image_to_numpy(r.read_image()), ref[i]), f"image {i} (nodes={nodes[i]})"
+    rec = rs[k].read_ray_exits()
+    ids = np.arange(scenes[k].n_rays)
+    o = oracle.scene_oracle(scenes[k]).trace_ids(srcs[k], scenes[k].rays_per_src, ids)
+    same = rec["status"] == o["status"]
+    dep = same & (o["status"] == oracle.DEPOSITED)
+    err = np.abs(rec["sensor_px"][dep] - o["sensor_px"][dep]).max()
+    print(f"node image {k}: {dep.sum()} deposited rays, max |dpx| vs oracle {err:.2e}")
+    assert same.mean() > 0.999 and dep.sum() > 0.5 * len(ids) and err <= 1e-4
+    b.autotune(probe_rounds=1)
+    b.run()
+    for i, r in enumerate(rs):
+        assert np.array_equal(pbr.u64_image_to_numpy(r.read_image()), ref[i]), f"tuned image {i}"
     b.close()
 
 
