@@ -110,11 +110,16 @@ def _cpu_model() -> str:
 
 
 def _oracle_rate(o, scene, src, threads, target_s):
-    """Rays/s of the oracle over the first sources of src on `threads` threads, about target_s of work."""
+    """Rays/s of the oracle over the first sources of src on `threads` threads, about target_s of work
+    (the prefix is doubled until a calibration render takes a tenth of that, then scaled)."""
     n_cal = max(1, threads)
-    t0 = time.perf_counter()
-    o.render(src[:n_cal], scene.rays_per_src, n_threads=threads, want_float=False)
-    t_cal = time.perf_counter() - t0
+    while True:
+        t0 = time.perf_counter()
+        o.render(src[:n_cal], scene.rays_per_src, n_threads=threads, want_float=False)
+        t_cal = time.perf_counter() - t0
+        if t_cal >= 0.1 * target_s or n_cal >= len(src):
+            break
+        n_cal = min(len(src), 2 * n_cal)
     n = int(min(len(src), max(n_cal, n_cal * target_s / max(t_cal, 1e-3))))
     t0 = time.perf_counter()
     o.render(src[:n], scene.rays_per_src, n_threads=threads, want_float=False)
@@ -124,7 +129,7 @@ def _oracle_rate(o, scene, src, threads, target_s):
                        f"{threads} thread{'s' if threads > 1 else ''})")
 
 
-def cpu_baseline(scene, rho, src, target_s: float = 15.0, single_s: float = 8.0):
+def cpu_baseline(scene, rho, src, target_s: float = 15.0, single_s: float = 10.0):
     """FP64 oracle on a prefix of the sources: all host threads (OpenMP over sources), then one."""
     import oracle
     o = oracle.scene_oracle(scene, rho=rho)

@@ -15,13 +15,16 @@ typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 constexpr float kGeluC = 0.7978845608028654f;  // sqrt(2 / pi)
 constexpr float kGeluA = 0.044715f;
 
-// GELU, tanh form, through the identity (1 + tanh u) / 2 = 1 / (1 + exp(-2 u)): one exponential
-// and one reciprocal (hardware approximations, about 1 ulp each) instead of a branchy tanh.
-// Saturates correctly: exp overflow gives 0, underflow gives z.
+// GELU, tanh form, through the identity (1 + tanh u) / 2 = 1 / (1 + exp(-2 u)) with
+// -2 u = z (k1 + k3 z^2) log2(e)-scaled, so that one hardware 2^x and one reciprocal (about 1 ulp
+// each) and three multiply(-add)s replace a branchy tanh.  Saturates correctly: 2^x overflow gives
+// 0, underflow gives z.
+constexpr float kGeluK1 = -2.0f * 0.7978845608028654f * 1.4426950408889634f;             // -2 c log2 e
+constexpr float kGeluK3 = -2.0f * 0.7978845608028654f * 0.044715f * 1.4426950408889634f;  // -2 c a log2 e
 __device__ __forceinline__ float gelu_sig(float z)
 {
-    const float u = kGeluC * z * (1.0f + kGeluA * z * z);
-    return __builtin_amdgcn_rcpf(1.0f + __expf(-2.0f * u));
+    const float e = __builtin_amdgcn_exp2f(z * __builtin_fmaf(z * z, kGeluK3, kGeluK1));
+    return __builtin_amdgcn_rcpf(1.0f + e);
 }
 
 __device__ __forceinline__ float gelu(float z) { return z * gelu_sig(z); }
