@@ -661,8 +661,9 @@ def bench_surrogate(args):
         "eligible_tiles": rep["eligible_tiles"],
         "exit_error_px_vs_tracer": {"rays_compared": int(both.sum()), "median": float(np.median(e)),
                                     "p99": float(np.quantile(e, 0.99)), "max": float(e.max())},
-        "training": {k: rep[k] for k in ("train_samples", "steps", "loss_first_epoch", "loss_last_epoch",
-                                         "train_ms", "val_median_px", "val_p99_px")},
+        "training": dict({k: rep[k] for k in ("train_samples", "steps", "loss_first_epoch", "loss_last_epoch",
+                                              "train_ms", "val_median_px", "val_p99_px")},
+                         us_per_adam_step=rep["train_ms"] / max(rep["steps"], 1) * 1e3, batch=4096),
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_BF16_TFLOPS, "traffic": None,
                      "kernel": "surrogate forward (all layers)", "rows": int(x.shape[0]),

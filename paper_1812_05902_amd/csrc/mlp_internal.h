@@ -25,8 +25,6 @@ constexpr int kOffB5 = kOffW5 + kOut * kHidden;
 constexpr int kParams = kOffB5 + kOut;
 static_assert(kParams == 200710, "parameter count");
 
-enum : int { EPI_PLAIN = 0, EPI_BIAS_GELU = 1, EPI_BIAS_Z_GELU = 2, EPI_BIAS_OUT = 3, EPI_GELU_BACK = 4 };
-
 // Parameters, gradients, Adam moments (FP32) and the bf16 copies read by the matrix products.
 struct MlpDevice {
     float *params, *grad, *m, *v;
@@ -34,37 +32,31 @@ struct MlpDevice {
     unsigned short *w5;                              // [64][256], rows 6..63 zero
 };
 
-// Per-batch buffers for up to rows_cap rows (a multiple of 64).
-struct MlpBuffers {
+// Buffers of a training step for batches of up to rows_cap rows (a multiple of 64).
+constexpr int kTrainPartStride = 4224;  // floats per 64-row block record (row sums of the small gradients)
+constexpr int kMaxDwSplits = 16;        // row slices of the weight-gradient products
+struct MlpTrain {
     int64_t rows_cap;
-    float *z[4];            // pre-activations of layers 1..4 (f32)
-    unsigned short *a[4];   // activations of layers 1..4 (bf16)
-    float *dy;              // [rows][6]
-    float *dz, *dz2;        // [rows][256] f32
-    unsigned short *dzb, *dzb2, *t0, *t1;
-    float *loss_part;       // ceil(rows * 6 / 256) partial sums
-    float *part, *part2;    // 16 x 256 x 256 floats each: split-K slices and row-block partial sums
+    unsigned short *aT[3];   // activations a1, a2, a3 (bf16) transposed: [256][rows_cap]
+    unsigned short *dzT[3];  // errors dz2, dz3, dz4 (bf16) transposed: [256][rows_cap]
+    float *rowpart;          // [rows_cap / 64][kTrainPartStride]
+    float *dwpart;           // [3][kMaxDwSplits][256][256]
 };
 
 int mlp_refresh_shadow(const MlpDevice &d, hipStream_t s);
-int mlp_forward(const MlpDevice &d, const MlpBuffers &b, const float *x, int64_t rows, float *y, bool train,
-                hipStream_t s, const unsigned long long *live = nullptr);
-int mlp_backward(const MlpDevice &d, const MlpBuffers &b, const float *x, const float *t, int64_t rows,
-                 const float *y, hipStream_t s);
 // Inference forward pass in one launch (activations in LDS), any row count; live (device,
-// optional) caps the rows computed.  Same roundings as mlp_forward (the products may sum in
-// another order inside the matrix cores).
+// optional) caps the rows computed.
 int mlp_infer(const MlpDevice &d, const float *x, int64_t rows, float *y, hipStream_t s,
               const unsigned long long *live = nullptr);
-// After mlp_backward: *out (device) = mean squared error of that batch (out[*step] if step given).
-int mlp_loss_mean(const MlpBuffers &b, int64_t rows, float *out, hipStream_t s, const int *step = nullptr);
-// Adam step with t = *step + 1 and the cosine learning rate of step *step out of total (device step
-// counter, so that one captured graph serves every step), then the bf16 copies.
-int mlp_adam_sched(const MlpDevice &d, const int *step, int total, float lr_max, float lr_min, hipStream_t s);
-int mlp_step_advance(int *step, hipStream_t s);
-int mlp_adam(const MlpDevice &d, float lr, int step, hipStream_t s);
-// C[M][N] = A[M][K] W[N][K]^T in f32 (bf16 operands); M, N multiples of 64, K of 32.
-int mlp_gemm_plain(const unsigned short *A, int lda, const unsigned short *W, int ldw, int64_t M, int N, int K,
-                   float *C, int ldc, hipStream_t s);
+// One training step on x, t ([rows][6] device, rows a multiple of 64 up to rows_cap): forward,
+// mean squared error, gradients of every parameter into d.grad, and
+//   mode 0: nothing more (loss_out[0] = the loss);
+//   mode 1: Adam with learning rate lr at step number `step` (1-based), bf16 copies refreshed;
+//   mode 2: Adam at step *step_dev + 1 with the cosine learning rate from lr_max (step 0) to lr_min
+//           (step total - 1), the counter advanced, loss_out[*step_dev] = the loss (one captured
+//           graph serves every step).
+int mlp_train_step(const MlpDevice &d, const MlpTrain &tb, const float *x, const float *t, int64_t rows, int mode,
+                   float lr, int step, int *step_dev, int total, float lr_max, float lr_min, float *loss_out,
+                   hipStream_t s);
 
 }  // namespace pbr

@@ -24,7 +24,7 @@ struct pbr_surrogate {
     std::string err;
     int64_t rows_cap = 0;
     pbr::MlpDevice d{};
-    pbr::MlpBuffers b{};
+    pbr::MlpTrain tb{};
     float *x = nullptr, *y = nullptr, *t = nullptr, *loss = nullptr;
     int *step = nullptr;                 // training step counter read by the captured step
     hipStream_t train_stream = nullptr;  // non-blocking stream the training step is captured on
@@ -168,21 +168,13 @@ void layout_persistent(pbr_surrogate *s, Carve &c, int64_t R, int64_t chunk)
     unsigned short **w[6] = {&s->d.w2, &s->d.w2t, &s->d.w3, &s->d.w3t, &s->d.w4, &s->d.w4t};
     for (auto q : w) *q = c.take<unsigned short>(H * H * 2);
     s->d.w5 = c.take<unsigned short>(pbr::kOutPad * H * 2);
-    s->b.rows_cap = R;
-    for (int l = 0; l < 4; ++l) {
-        s->b.z[l] = c.take<float>(R * H * 4);
-        s->b.a[l] = c.take<unsigned short>(R * H * 2);
+    s->tb.rows_cap = R;
+    for (int l = 0; l < 3; ++l) {
+        s->tb.aT[l] = c.take<unsigned short>(H * R * 2);
+        s->tb.dzT[l] = c.take<unsigned short>(H * R * 2);
     }
-    s->b.dy = c.take<float>(R * 6 * 4);
-    s->b.dz = c.take<float>(R * H * 4);
-    s->b.dz2 = c.take<float>(R * H * 4);
-    s->b.dzb = c.take<unsigned short>(R * H * 2);
-    s->b.dzb2 = c.take<unsigned short>(R * H * 2);
-    s->b.t0 = c.take<unsigned short>(R * H * 2);
-    s->b.t1 = c.take<unsigned short>(R * H * 2);
-    s->b.loss_part = c.take<float>(((R * 6 + 255) / 256) * 4);
-    s->b.part = c.take<float>((size_t)16 * H * H * 4);
-    s->b.part2 = c.take<float>((size_t)16 * H * H * 4);
+    s->tb.rowpart = c.take<float>((size_t)(R / 64) * pbr::kTrainPartStride * 4);
+    s->tb.dwpart = c.take<float>((size_t)3 * pbr::kMaxDwSplits * H * H * 4);
     s->x = c.take<float>(R * 6 * 4);
     s->y = c.take<float>(R * 6 * 4);
     s->t = c.take<float>(R * 6 * 4);
@@ -465,9 +457,8 @@ int pbr_surrogate_gradients(pbr_surrogate *s, const float *x_dev, const float *t
     DeviceGuard g(s->device);
     if (!g.ok) return sfail(s, PBR_ERR_HIP, "hipSetDevice failed");
     int e;
-    if ((e = pbr::mlp_forward(s->d, s->b, x_dev, rows, s->y, true, s->stream)) ||
-        (e = pbr::mlp_backward(s->d, s->b, x_dev, t_dev, rows, s->y, s->stream)) ||
-        (e = pbr::mlp_loss_mean(s->b, rows, s->loss, s->stream)))
+    if ((e = pbr::mlp_train_step(s->d, s->tb, x_dev, t_dev, rows, 0, 0.0f, 0, nullptr, 0, 0.0f, 0.0f, s->loss,
+                                 s->stream)))
         return shf(s, e, "forward / backward");
     float l = 0.0f;
     if ((e = (int)hipMemcpyAsync(&l, s->loss, 4, hipMemcpyDeviceToHost, s->stream))) return shf(s, e, "copy loss");
@@ -492,9 +483,8 @@ int pbr_surrogate_adam_step(pbr_surrogate *s, const float *x_dev, const float *t
     DeviceGuard g(s->device);
     if (!g.ok) return sfail(s, PBR_ERR_HIP, "hipSetDevice failed");
     int e;
-    if ((e = pbr::mlp_forward(s->d, s->b, x_dev, rows, s->y, true, s->stream)) ||
-        (e = pbr::mlp_backward(s->d, s->b, x_dev, t_dev, rows, s->y, s->stream)) ||
-        (e = pbr::mlp_loss_mean(s->b, rows, s->loss, s->stream)) || (e = pbr::mlp_adam(s->d, lr, step, s->stream)))
+    if ((e = pbr::mlp_train_step(s->d, s->tb, x_dev, t_dev, rows, 1, lr, step, nullptr, 0, 0.0f, 0.0f, s->loss,
+                                 s->stream)))
         return shf(s, e, "Adam step");
     s->trained = false;  // the fallback map no longer describes these weights
     if (loss_host) {
@@ -667,11 +657,8 @@ int pbr_surrogate_train(pbr_surrogate *s, pbr_ctx *ctx, const float *train_src_d
     {
         int ce = 0;
         if ((ce = pbr::launch_surr_gather_step(spec, trs, perm, s->step, spe, cfg->batch, s->x, s->t, ts)) ||
-            (ce = pbr::mlp_forward(s->d, s->b, s->x, cfg->batch, s->y, true, ts)) ||
-            (ce = pbr::mlp_backward(s->d, s->b, s->x, s->t, cfg->batch, s->y, ts)) ||
-            (ce = pbr::mlp_loss_mean(s->b, cfg->batch, losses, ts, s->step)) ||
-            (ce = pbr::mlp_adam_sched(s->d, s->step, (int)total, cfg->lr_max, cfg->lr_min, ts)) ||
-            (ce = pbr::mlp_step_advance(s->step, ts))) {
+            (ce = pbr::mlp_train_step(s->d, s->tb, s->x, s->t, cfg->batch, 2, 0.0f, 0, s->step, (int)total,
+                                      cfg->lr_max, cfg->lr_min, losses, ts))) {
             hipGraph_t g2 = nullptr;
             (void)hipStreamEndCapture(ts, &g2);
             if (g2) (void)hipGraphDestroy(g2);

@@ -530,8 +530,8 @@ def test_noalloc_trace_validates_before_device_work(lib):
 
 
 def test_surrogate_workspace_sizes(lib):
-    """Persistent workspace: parameters, moments and bf16 copies (fixed), 10.3 kB per training row
-    (pre-activations, activations and gradients of four 256-wide layers), 53 B per trace-chunk ray
+    """Persistent workspace: parameters, moments and bf16 copies (fixed), 3.4 kB per training row
+    (transposed bf16 activations and errors of three layers, row-block sums), 53 B per trace-chunk ray
     and a 1 MiB tile map, each part rounded up to 256 B; training workspace: 88 B samples per ray,
     shuffles, losses and per-tile validation maxima."""
     ws = lib.pbr_surrogate_workspace_bytes
@@ -540,7 +540,7 @@ def test_surrogate_workspace_sizes(lib):
     assert ws(0, 0) == ws(65536, 0)          # 0 rows means 65536
     assert ws(100, 0) == ws(128, 0)          # rows round up to 64
     per_row = (ws(64 + 64 * 1024, 0) - base) / (64 * 1024)
-    assert abs(per_row - 10336) < 1  # 4 x 256 x (4 + 2) + 2 x 256 x 4 + 4 x 256 x 2 + 4 x 6 x 4 (+ loss partials)
+    assert abs(per_row - 3408) < 1  # 6 x 256 x 2 (transposed bf16 activations and errors) + 4224 x 4 / 64 (row sums) + 3 x 6 x 4
     per_ray = (ws(64, 1 << 20) - base) / (1 << 20)
     assert abs(per_ray - 53) < 1e-3
     assert ws(-1, 0) == 0 and ws(1 << 25, 0) == 0 and ws(64, -1) == 0
