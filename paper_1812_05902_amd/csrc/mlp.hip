@@ -207,9 +207,10 @@ __global__ void __launch_bounds__(64 * kFuseWaves, 2) k_mlp_infer(const float *_
 // ---------------------------------------------------------------- training step
 //
 // One step over a batch of `rows` rows (a multiple of 64) in three launches:
-//   k_train_rows   one block per 64 rows: layer 1 .. output forward with every pre-activation kept
-//                  in registers, the loss and dL/dy, the back-propagated errors down to layer 1, and
-//                  per block the row sums the small gradients need (biases, W1, W5, b5, the loss);
+//   k_train_rows   one block per 64 rows: layer 1 .. output forward with every pre-activation parked
+//                  in an L2-resident buffer, the loss and dL/dy, the back-propagated errors down to
+//                  layer 1, and per block the row sums the small gradients need (biases, W1, W5, b5,
+//                  the loss), the small ones as FP32 matrix-core products;
 //                  writes the bf16 activations a1..a3 and errors dz2..dz4 transposed ([unit][row],
 //                  the layout the weight-gradient products read);
 //   k_train_dw     dW_l = bf16(dz_l)^T a_(l-1) for the three hidden layers, the rows split into S
@@ -236,74 +237,96 @@ struct Slab {
     floatx4 v[2][4];
 };
 
-// Z^T = W A^T over K = 256 for this wave's 32 units and the 64 rows in `act` (LDS [row][unit]
-// bf16), W: [256][256] bf16 rows of the output units (k contiguous), accumulators starting at
-// `bias` (or 0).
-__device__ __forceinline__ void slab_product(Slab &acc, const unsigned short *__restrict__ W,
-                                             const float *__restrict__ bias, const unsigned short *act, int wave,
-                                             int r, int kg)
+// The wave's 32 rows of a [256][256] bf16 weight matrix (output units wave * 32 .. + 31, k
+// contiguous) as the A operands of all eight k steps of a slab product, and the matching biases
+// (zero without a bias).
+struct WFrag {
+    bf16x8 f[8][2];
+    floatx4 b[2];
+};
+
+__device__ __forceinline__ void load_wfrag(WFrag &w, const unsigned short *__restrict__ W,
+                                           const float *__restrict__ bias, int wave, int r, int kg)
 {
+    const unsigned short *Wr = W + (size_t)(wave * 32 + r) * kHidden + 8 * kg;
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) w.f[k][j] = *(const bf16x8 *)(Wr + j * 16 * kHidden + 32 * k);
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
-        floatx4 b0 = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+        w.b[j] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
         if (bias) {
             const float4 b4 = *(const float4 *)(bias + wave * 32 + 16 * j + 4 * kg);
-            b0 = floatx4{b4.x, b4.y, b4.z, b4.w};
+            w.b[j] = floatx4{b4.x, b4.y, b4.z, b4.w};
         }
-#pragma unroll
-        for (int i = 0; i < 4; ++i) acc.v[j][i] = b0;
     }
-    const unsigned short *Wr = W + (size_t)(wave * 32 + r) * kHidden + 8 * kg;
-    bf16x8 fw[2], fn[2], fn2[2];
+}
+
+// Z^T = W A^T (+ bias) over K = 256 for this wave's 32 units and the 64 rows in `act` (LDS
+// [row][unit] bf16), with the weights already in `w`.
+__device__ __forceinline__ void slab_product(Slab &acc, const WFrag &w, const unsigned short *act, int r, int kg)
+{
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-        fw[j] = *(const bf16x8 *)(Wr + j * 16 * kHidden);
-        fn[j] = *(const bf16x8 *)(Wr + j * 16 * kHidden + 32);
-    }
+    for (int j = 0; j < 2; ++j)
 #pragma unroll
-    for (int k0 = 0; k0 < kHidden; k0 += 32) {
-        if (k0 + 64 < kHidden) {
+        for (int i = 0; i < 4; ++i) acc.v[j][i] = w.b[j];
 #pragma unroll
-            for (int j = 0; j < 2; ++j) fn2[j] = *(const bf16x8 *)(Wr + j * 16 * kHidden + k0 + 64);
-        }
+    for (int k = 0; k < 8; ++k) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const bf16x8 fa = *(const bf16x8 *)(act + (16 * i + r) * kActStride + 8 * kg + k0);
+            const bf16x8 fa = *(const bf16x8 *)(act + (16 * i + r) * kActStride + 8 * kg + 32 * k);
 #pragma unroll
             for (int j = 0; j < 2; ++j)
-                acc.v[j][i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fw[j], fa, acc.v[j][i], 0, 0, 0);
-        }
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            fw[j] = fn[j];
-            fn[j] = fn2[j];
+                acc.v[j][i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w.f[k][j], fa, acc.v[j][i], 0, 0, 0);
         }
     }
 }
 
 // bf16 values of a slab (of g applied to it when GELU) into LDS [row][unit] and, when T is given,
-// into T [unit][ldt] at column row0 + row (the transposed layout of the weight-gradient products).
+// into T [unit][ldt] (the transposed layout of the weight-gradient products).  Within each block
+// of 64 rows, T holds row 16 i + r at column 4 r + i, so that a lane's four row tiles are one
+// 8-byte store; the weight-gradient products sum over rows and read both of their operands in this
+// same order, so the permutation only reorders the terms of their sums.
 template <bool GELU>
 __device__ __forceinline__ void slab_store(const Slab &v, unsigned short *act, unsigned short *__restrict__ T,
                                            int64_t ldt, int64_t row0, int wave, int r, int kg)
 {
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < 2; ++j) {
+        unsigned short b[4][4];  // [row tile i][unit t]
+        const int u = wave * 32 + 16 * j + 4 * kg;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            unsigned short b[4];
 #pragma unroll
-            for (int t = 0; t < 4; ++t) b[t] = bf16_bits(GELU ? gelu(v.v[j][i][t]) : v.v[j][i][t]);
+            for (int t = 0; t < 4; ++t) b[i][t] = bf16_bits(GELU ? gelu(v.v[j][i][t]) : v.v[j][i][t]);
             uint2 w;
-            w.x = (unsigned)b[0] | ((unsigned)b[1] << 16);
-            w.y = (unsigned)b[2] | ((unsigned)b[3] << 16);
-            const int u = wave * 32 + 16 * j + 4 * kg, m = 16 * i + r;
-            *(uint2 *)(act + m * kActStride + u) = w;
-            if (T) {
+            w.x = (unsigned)b[i][0] | ((unsigned)b[i][1] << 16);
+            w.y = (unsigned)b[i][2] | ((unsigned)b[i][3] << 16);
+            *(uint2 *)(act + (16 * i + r) * kActStride + u) = w;
+        }
+        if (T) {
 #pragma unroll
-                for (int t = 0; t < 4; ++t) T[(size_t)(u + t) * ldt + row0 + m] = b[t];
+            for (int t = 0; t < 4; ++t) {
+                uint2 w;
+                w.x = (unsigned)b[0][t] | ((unsigned)b[1][t] << 16);
+                w.y = (unsigned)b[2][t] | ((unsigned)b[3][t] << 16);
+                *(uint2 *)(T + (size_t)(u + t) * ldt + row0 + 4 * r) = w;
             }
         }
+    }
+}
+
+// Sum over the 16 lanes of a DPP row (lanes r = 0..15 of one kg): xor-1 and xor-2 exchanges inside
+// each quad, then the half-row and row mirrors; every lane ends with the same value as a
+// butterfly of xor shuffles gives.
+__device__ __forceinline__ float row16_sum(float s)
+{
+    s += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(s), 0xB1, 0xF, 0xF, false));   // quad_perm 1,0,3,2
+    s += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(s), 0x4E, 0xF, 0xF, false));   // quad_perm 2,3,0,1
+    s += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(s), 0x141, 0xF, 0xF, false));  // row_half_mirror
+    s += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(s), 0x140, 0xF, 0xF, false));  // row_mirror
+    return s;
 }
 
 // Sum of a slab over its 64 rows, per unit: lanes r = 0 of each kg end with the sums of units
@@ -314,13 +337,20 @@ __device__ __forceinline__ void slab_row_sums(const Slab &v, float *__restrict__
     for (int j = 0; j < 2; ++j)
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-            float s = ((v.v[j][0][t] + v.v[j][1][t]) + (v.v[j][2][t] + v.v[j][3][t]));
-#pragma unroll
-            for (int o = 1; o < 16; o <<= 1) s += __shfl_xor(s, o, 64);
+            const float s = row16_sum((v.v[j][0][t] + v.v[j][1][t]) + (v.v[j][2][t] + v.v[j][3][t]));
             if (r == 0) out[wave * 32 + 16 * j + 4 * kg + t] = s;
         }
 }
 
+// LDS of k_train_rows: two bf16 [64][kActStride] activation / error buffers, later reused for
+// layer 1's FP32 error as [unit][kDz1Stride] (the stride keeps the W1 product's reads free of bank
+// conflicts).
+constexpr int kDz1Stride = kTrRows + 4;
+constexpr int kK1ActBytes = 2 * kTrRows * kActStride * 2;
+constexpr int kK1LdsBytes = kK1ActBytes > kHidden * kDz1Stride * 4 ? kK1ActBytes : kHidden * kDz1Stride * 4;
+
+// Every global load is issued as early as its registers allow: vector memory operations complete
+// in issue order, so a load queued behind another layer's stores or weight fetch waits for them.
 __global__ void __launch_bounds__(512, 1) k_train_rows(const float *__restrict__ params,
                                                        const unsigned short *__restrict__ w2,
                                                        const unsigned short *__restrict__ w3,
@@ -332,69 +362,120 @@ __global__ void __launch_bounds__(512, 1) k_train_rows(const float *__restrict__
                                                        const float *__restrict__ x, const float *__restrict__ tgt,
                                                        int64_t rows, int64_t ldt, MlpTrain tb)
 {
-    __shared__ __attribute__((aligned(16))) unsigned short act[2][kTrRows * kActStride];
+    __shared__ __attribute__((aligned(16))) unsigned char lds[kK1LdsBytes];
     __shared__ float xs[kTrRows * kIn], ts[kTrRows * kIn], dys[kTrRows * kOut];
     __shared__ float red[kTrRows];
-    // layer 1's pre-activations until the last error (each lane reads back what it wrote)
-    __shared__ __attribute__((aligned(16))) float z1s[kTrRows * kHidden];
+    auto act = [&](int b) { return (unsigned short *)lds + b * (kTrRows * kActStride); };
     const int64_t row0 = (int64_t)blockIdx.x * kTrRows;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int r = lane & 15, kg = lane >> 4;
     float *rp = tb.rowpart + (size_t)blockIdx.x * kTrainPartStride;
-    for (int q = threadIdx.x; q < kTrRows * kIn; q += 512) {
-        xs[q] = x[row0 * kIn + q];
-        ts[q] = tgt[row0 * kIn + q];
+    // pre-activations of layers 1..3, parked in L2-resident memory until the backward pass needs
+    // them (each lane reads back exactly what it wrote); layer 4's stay in registers
+    auto zp = [&](int l, int j, int i) {
+        return tb.zbuf + ((size_t)l * ldt + row0 + 16 * i + r) * kHidden + wave * 32 + 16 * j + 4 * kg;
+    };
+    auto park = [&](const Slab &v, int l) {
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) *(floatx4 *)zp(l, j, i) = v.v[j][i];
+    };
+    auto unpark = [&](Slab &v, int l) {
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) v.v[j][i] = *(const floatx4 *)zp(l, j, i);
+    };
+    // inputs, targets and layer 1's parameters first, then the weights of layer 2
+    float xv = 0.0f, tv = 0.0f;
+    if (threadIdx.x < kTrRows * kIn) {
+        xv = x[row0 * kIn + threadIdx.x];
+        tv = tgt[row0 * kIn + threadIdx.x];
     }
-    __syncthreads();
-    Slab z[4];  // pre-activations of layers 1..4 (layer 1's parked in LDS during layers 2..4)
-    {   // layer 1 in FP32 on the matrix cores (v_mfma_f32_16x16x4_f32, K = 6 padded to 8)
-        const float *bias = params + kOffB1 + wave * 32 + 4 * kg;
+    float w1a[2][2];
+    floatx4 b1[2];
+#pragma unroll
+    for (int kk = 0; kk < 2; ++kk)
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
-            const float4 b4 = *(const float4 *)(bias + 16 * j);
-#pragma unroll
-            for (int i = 0; i < 4; ++i) z[0].v[j][i] = floatx4{b4.x, b4.y, b4.z, b4.w};
+            const int k = 4 * kk + kg;
+            w1a[kk][j] = k < kIn ? params[kOffW1 + (wave * 32 + 16 * j + r) * kIn + k] : 0.0f;
         }
 #pragma unroll
-        for (int kk = 0; kk < 8; kk += 4) {
-            const int k = kk + kg;
-            float wa[2];
+    for (int j = 0; j < 2; ++j) {
+        const float4 b4 = *(const float4 *)(params + kOffB1 + wave * 32 + 16 * j + 4 * kg);
+        b1[j] = floatx4{b4.x, b4.y, b4.z, b4.w};
+    }
+    WFrag fw;
+    load_wfrag(fw, w2, params + kOffB2, wave, r, kg);
+    if (threadIdx.x < kTrRows * kIn) {
+        xs[threadIdx.x] = xv;
+        ts[threadIdx.x] = tv;
+    }
+    __syncthreads();
+    {   // layer 1 in FP32 on the matrix cores (v_mfma_f32_16x16x4_f32, K = 6 padded to 8)
+        Slab z;
 #pragma unroll
-            for (int j = 0; j < 2; ++j) wa[j] = k < kIn ? params[kOffW1 + (wave * 32 + 16 * j + r) * kIn + k] : 0.0f;
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) z.v[j][i] = b1[j];
+#pragma unroll
+        for (int kk = 0; kk < 2; ++kk) {
+            const int k = 4 * kk + kg;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const float xb = k < kIn ? xs[(16 * i + r) * kIn + k] : 0.0f;
 #pragma unroll
                 for (int j = 0; j < 2; ++j)
-                    z[0].v[j][i] = __builtin_amdgcn_mfma_f32_16x16x4f32(wa[j], xb, z[0].v[j][i], 0, 0, 0);
+                    z.v[j][i] = __builtin_amdgcn_mfma_f32_16x16x4f32(w1a[kk][j], xb, z.v[j][i], 0, 0, 0);
             }
         }
+        // a1 = bf16(g(z1)) into act(0) (the input of layer 2) and transposed for dW2
+        park(z, 0);
+        slab_store<true>(z, act(0), tb.aT[0], ldt, row0, wave, r, kg);
     }
-    // forward: a_l = bf16(g(z_l)); inputs of layer l + 1 in act[(l - 1) & 1]
-    slab_store<true>(z[0], act[0], tb.aT[0], ldt, row0, wave, r, kg);
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-            *(floatx4 *)(z1s + (16 * i + r) * kHidden + wave * 32 + 16 * j + 4 * kg) = z[0].v[j][i];
     __syncthreads();
-    const unsigned short *Wf[3] = {w2, w3, w4};
-    const int boff[3] = {kOffB2, kOffB3, kOffB4};
-#pragma unroll
-    for (int l = 0; l < 3; ++l) {
-        slab_product(z[l + 1], Wf[l], params + boff[l], act[l & 1], wave, r, kg);
-        slab_store<true>(z[l + 1], act[(l + 1) & 1], l < 2 ? tb.aT[l + 1] : nullptr, ldt, row0, wave, r, kg);
+    // layers 2 and 3: z = a W^T + b, a = bf16(g(z)); inputs in act(l & 1), outputs to act((l + 1) & 1)
+#pragma unroll 1
+    for (int l = 0; l < 2; ++l) {
+        Slab z;
+        slab_product(z, fw, act(l & 1), r, kg);
+        load_wfrag(fw, l == 0 ? w3 : w4, params + (l == 0 ? kOffB3 : kOffB4), wave, r, kg);
+        park(z, l + 1);
+        slab_store<true>(z, act((l + 1) & 1), tb.aT[l + 1], ldt, row0, wave, r, kg);
         __syncthreads();
     }
-    // a4 in act[1].  Output layer (16 padded outputs x 16 rows per wave, waves 0..3), loss, dL/dy.
+    // layer 4 (input a3 in act(0), output a4 to act(1)); then the loads of the output layer and of
+    // dz4 (the bf16 W5 fragments, FP32 W5 and b5) ahead of the first backward weights, W4^T
+    Slab dz;  // z4, then dz4
+    slab_product(dz, fw, act(0), r, kg);
+    bf16x8 f5[8];
+    float b5v[4];
+    if (wave < 4) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) f5[k] = *(const bf16x8 *)(w5 + (size_t)r * kHidden + 8 * kg + 32 * k);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) b5v[t] = (kg < 2 && 4 * kg + t < kOut) ? params[kOffB5 + 4 * kg + t] : 0.0f;
+    }
+    float w5a[2][2];
+#pragma unroll
+    for (int kk = 0; kk < 2; ++kk)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int o = 4 * kk + kg;
+            w5a[kk][j] = o < kOut ? params[kOffW5 + o * kHidden + wave * 32 + 16 * j + r] : 0.0f;
+        }
+    load_wfrag(fw, w4t, nullptr, wave, r, kg);
+    slab_store<true>(dz, act(1), nullptr, ldt, row0, wave, r, kg);
+    __syncthreads();
+    // output layer (16 padded outputs x 16 rows per wave, waves 0..3), loss, dL/dy
     if (wave < 4) {
         floatx4 acc = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-        const unsigned short *W = w5 + (size_t)r * kHidden + 8 * kg;
 #pragma unroll
-        for (int k0 = 0; k0 < kHidden; k0 += 32) {
-            const bf16x8 fw = *(const bf16x8 *)(W + k0);
-            const bf16x8 fa = *(const bf16x8 *)(act[1] + (16 * wave + r) * kActStride + 8 * kg + k0);
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fw, fa, acc, 0, 0, 0);
+        for (int k = 0; k < 8; ++k) {
+            const bf16x8 fa = *(const bf16x8 *)(act(1) + (16 * wave + r) * kActStride + 8 * kg + 32 * k);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f5[k], fa, acc, 0, 0, 0);
         }
         const int m = 16 * wave + r;
         const float scale = 2.0f / (float)(rows * kOut);
@@ -403,7 +484,7 @@ __global__ void __launch_bounds__(512, 1) k_train_rows(const float *__restrict__
         for (int t = 0; t < 4; ++t) {
             const int o = 4 * kg + t;
             if (kg < 2 && o < kOut) {
-                const float d = (acc[t] + params[kOffB5 + o]) - ts[m * kIn + o];
+                const float d = (acc[t] + b5v[t]) - ts[m * kIn + o];
                 dys[m * kOut + o] = scale * d;
                 se += d * d;
             }
@@ -414,76 +495,108 @@ __global__ void __launch_bounds__(512, 1) k_train_rows(const float *__restrict__
     }
     __syncthreads();
     if (threadIdx.x == 0) rp[kRpLoss] = (red[0] + red[1]) + (red[2] + red[3]);
-    // W5 gradient (dy^T a4, a4 as stored in bf16) and b5 over the block's rows
-    for (int q = threadIdx.x; q < kOut * kHidden; q += 512) {
-        const int o = q / kHidden, u = q % kHidden;
-        float s = 0.0f;
-        for (int m = 0; m < kTrRows; ++m)
-            s += dys[m * kOut + o] * __uint_as_float((unsigned)act[1][m * kActStride + u] << 16);
-        rp[kRpW5 + q] = s;
-    }
-    if (threadIdx.x < kOut) {
-        float s = 0.0f;
-        for (int m = 0; m < kTrRows; ++m) s += dys[m * kOut + threadIdx.x];
-        rp[kRpB5 + threadIdx.x] = s;
-    }
-    // error of layer 4 from dy and the FP32 W5: dz4 = (dy W5) g'(z4)
-    Slab dz;
+    Slab zn;  // the next backward layer's pre-activations, z3
+    unpark(zn, 2);
+    {   // W5 and b5 gradients, C[o][u] = sum over rows of dy[m][o] a4[m][u] (a4 as stored in bf16),
+        // on v_mfma_f32_16x16x4_f32 with o padded to 16; b5 as the product with a column of ones
+        floatx4 g[2] = {floatx4{0.0f, 0.0f, 0.0f, 0.0f}, floatx4{0.0f, 0.0f, 0.0f, 0.0f}};
+        floatx4 gb = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+        for (int s4 = 0; s4 < kTrRows; s4 += 4) {
+            const int m = s4 + kg;
+            const float a = r < kOut ? dys[m * kOut + r] : 0.0f;
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const int u = wave * 32 + 16 * j + 4 * kg + t, m = 16 * i + r;
-                float da = 0.0f;
-#pragma unroll
-                for (int o = 0; o < kOut; ++o) da += dys[m * kOut + o] * params[kOffW5 + o * kHidden + u];
-                dz.v[j][i][t] = da * gelu_grad(z[3].v[j][i][t]);
+            for (int j = 0; j < 2; ++j) {
+                const float b = __uint_as_float((unsigned)act(1)[m * kActStride + wave * 32 + 16 * j + r] << 16);
+                g[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, g[j], 0, 0, 0);
             }
-    slab_row_sums(dz, rp + kRpB + 3 * kHidden, wave, r, kg);
-    slab_store<false>(dz, act[0], tb.dzT[2], ldt, row0, wave, r, kg);  // a3 in act[0] is no longer read
-    __syncthreads();
-    // layers 3, 2: dz_(l-1) = (bf16(dz_l) W_l) g'(z_(l-1)), with W_l^T rows as the A operand
-    const unsigned short *Wt[3] = {w2t, w3t, w4t};
+            if (wave == 0) gb = __builtin_amdgcn_mfma_f32_16x16x4f32(a, r == 0 ? 1.0f : 0.0f, gb, 0, 0, 0);
+        }
 #pragma unroll
-    for (int l = 2; l >= 1; --l) {  // output: layer l + 1's error (l = 2: dz3, l = 1: dz2)
-        slab_product(dz, Wt[l], nullptr, act[l & 1], wave, r, kg);
+        for (int t = 0; t < 4; ++t) {
+            const int o = 4 * kg + t;
+            if (o < kOut) {
+#pragma unroll
+                for (int j = 0; j < 2; ++j) rp[kRpW5 + o * kHidden + wave * 32 + 16 * j + r] = g[j][t];
+                if (wave == 0 && r == 0) rp[kRpB5 + o] = gb[t];
+            }
+        }
+    }
+    {   // error of layer 4 from dy and the FP32 W5: dz4 = (dy W5) g'(z4), the product on
+        // v_mfma_f32_16x16x4_f32 (units x rows, K = 6 outputs padded to 8)
+        Slab da;
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) da.v[j][i] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int kk = 0; kk < 2; ++kk) {
+            const int o = 4 * kk + kg;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float yb = o < kOut ? dys[(16 * i + r) * kOut + o] : 0.0f;
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    da.v[j][i] = __builtin_amdgcn_mfma_f32_16x16x4f32(w5a[kk][j], yb, da.v[j][i], 0, 0, 0);
+            }
+        }
 #pragma unroll
         for (int j = 0; j < 2; ++j)
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll
-                for (int t = 0; t < 4; ++t) dz.v[j][i][t] *= gelu_grad(z[l].v[j][i][t]);
+                for (int t = 0; t < 4; ++t) dz.v[j][i][t] = da.v[j][i][t] * gelu_grad(dz.v[j][i][t]);
+    }
+    slab_row_sums(dz, rp + kRpB + 3 * kHidden, wave, r, kg);
+    slab_store<false>(dz, act(0), tb.dzT[2], ldt, row0, wave, r, kg);  // a3 in act(0) is no longer read
+    __syncthreads();
+    // errors of layers 3, 2, 1: dz_(l+1) = (bf16(dz_(l+2)) W_(l+2)) g'(z_(l+1)), with W^T rows as the A
+    // operand; layer l + 2's error in act(l & 1); the next weights and pre-activations are fetched
+    // before this layer's stores
+#pragma unroll 1
+    for (int l = 2; l >= 0; --l) {
+        const Slab zl = zn;
+        slab_product(dz, fw, act(l & 1), r, kg);
+        if (l > 0) {
+            load_wfrag(fw, l == 2 ? w3t : w2t, nullptr, wave, r, kg);
+            unpark(zn, l - 1);
+        }
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int t = 0; t < 4; ++t) dz.v[j][i][t] *= gelu_grad(zl.v[j][i][t]);
         slab_row_sums(dz, rp + kRpB + l * kHidden, wave, r, kg);
-        slab_store<false>(dz, act[(l + 1) & 1], tb.dzT[l - 1], ldt, row0, wave, r, kg);
+        if (l > 0) slab_store<false>(dz, act((l + 1) & 1), tb.dzT[l - 1], ldt, row0, wave, r, kg);
         __syncthreads();
     }
-    // layer 1: dz1 = (bf16(dz2) W2) g'(z1); b1 and W1 (dz1^T x, FP32) over the block's rows
-    {
-        slab_product(dz, Wt[0], nullptr, act[0], wave, r, kg);
+    // W1 gradient, C[k][u] = sum over rows of x[m][k] dz1[m][u] in FP32 on v_mfma_f32_16x16x4_f32
+    // (k padded to 16): dz1 goes through LDS as [unit][row] to put the rows on the K operand lanes
+    float *dzf = (float *)lds;
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) dzf[(wave * 32 + 16 * j + 4 * kg + t) * kDz1Stride + 16 * i + r] = dz.v[j][i][t];
+    __syncthreads();
+    floatx4 g1[2] = {floatx4{0.0f, 0.0f, 0.0f, 0.0f}, floatx4{0.0f, 0.0f, 0.0f, 0.0f}};
+#pragma unroll
+    for (int s4 = 0; s4 < kTrRows; s4 += 4) {
+        const int m = s4 + kg;
+        const float a = r < kIn ? xs[m * kIn + r] : 0.0f;
 #pragma unroll
         for (int j = 0; j < 2; ++j)
+            g1[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, dzf[(wave * 32 + 16 * j + r) * kDz1Stride + m], g1[j], 0, 0, 0);
+    }
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const floatx4 zz = *(const floatx4 *)(z1s + (16 * i + r) * kHidden + wave * 32 + 16 * j + 4 * kg);
+    for (int t = 0; t < 4; ++t) {
+        const int k = 4 * kg + t;
+        if (k < kIn) {
 #pragma unroll
-                for (int t = 0; t < 4; ++t) dz.v[j][i][t] *= gelu_grad(zz[t]);
-            }
-        slab_row_sums(dz, rp + kRpB, wave, r, kg);
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-#pragma unroll
-            for (int t = 0; t < 4; ++t)
-#pragma unroll
-                for (int k = 0; k < kIn; ++k) {
-                    float s = 0.0f;
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) s += dz.v[j][i][t] * xs[(16 * i + r) * kIn + k];
-#pragma unroll
-                    for (int o = 1; o < 16; o <<= 1) s += __shfl_xor(s, o, 64);
-                    if (r == 0) rp[kRpW1 + (wave * 32 + 16 * j + 4 * kg + t) * kIn + k] = s;
-                }
+            for (int j = 0; j < 2; ++j) rp[kRpW1 + (wave * 32 + 16 * j + r) * kIn + k] = g1[j][t];
+        }
     }
 }
 
@@ -512,15 +625,32 @@ __global__ void __launch_bounds__(256) k_train_dw(MlpTrain tb, int64_t ldt, int6
     const unsigned short *a1 = A + (size_t)(m0 + 16 + r) * ldt + 8 * kg;
     const unsigned short *b0 = W + (size_t)(n0 + r) * ldt + 8 * kg;
     const unsigned short *b1 = W + (size_t)(n0 + 16 + r) * ldt + 8 * kg;
-    for (int64_t k0 = 0; k0 < chunk; k0 += 32) {
-        const bf16x8 fa0 = *(const bf16x8 *)(a0 + k0);
-        const bf16x8 fa1 = *(const bf16x8 *)(a1 + k0);
-        const bf16x8 fb0 = *(const bf16x8 *)(b0 + k0);
-        const bf16x8 fb1 = *(const bf16x8 *)(b1 + k0);
-        acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa0, fb0, acc[0][0], 0, 0, 0);
-        acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa0, fb1, acc[0][1], 0, 0, 0);
-        acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa1, fb0, acc[1][0], 0, 0, 0);
-        acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa1, fb1, acc[1][1], 0, 0, 0);
+    // chunk is a multiple of 64: two k steps per iteration, the next two loaded ahead
+    bf16x8 f[4], g[4];
+    f[0] = *(const bf16x8 *)a0; f[1] = *(const bf16x8 *)a1; f[2] = *(const bf16x8 *)b0; f[3] = *(const bf16x8 *)b1;
+    g[0] = *(const bf16x8 *)(a0 + 32); g[1] = *(const bf16x8 *)(a1 + 32);
+    g[2] = *(const bf16x8 *)(b0 + 32); g[3] = *(const bf16x8 *)(b1 + 32);
+    for (int64_t k0 = 0; k0 < chunk; k0 += 64) {
+        bf16x8 fn[4], gn[4];
+        const bool more = k0 + 64 < chunk;
+        if (more) {
+            fn[0] = *(const bf16x8 *)(a0 + k0 + 64); fn[1] = *(const bf16x8 *)(a1 + k0 + 64);
+            fn[2] = *(const bf16x8 *)(b0 + k0 + 64); fn[3] = *(const bf16x8 *)(b1 + k0 + 64);
+            gn[0] = *(const bf16x8 *)(a0 + k0 + 96); gn[1] = *(const bf16x8 *)(a1 + k0 + 96);
+            gn[2] = *(const bf16x8 *)(b0 + k0 + 96); gn[3] = *(const bf16x8 *)(b1 + k0 + 96);
+        }
+        acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f[0], f[2], acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f[0], f[3], acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f[1], f[2], acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f[1], f[3], acc[1][1], 0, 0, 0);
+        acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(g[0], g[2], acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(g[0], g[3], acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(g[1], g[2], acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(g[1], g[3], acc[1][1], 0, 0, 0);
+        if (more) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) { f[c] = fn[c]; g[c] = gn[c]; }
+        }
     }
     // lane: rows 4 kg + t (n), column r (k) of each 16 x 16 tile
 #pragma unroll
@@ -545,10 +675,12 @@ __global__ void __launch_bounds__(256) k_train_update(MlpDevice d, MlpTrain tb, 
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     int t = t_fixed;
     if (mode == 2) t = *step;
-    if (q == 0) {
+    if (blockIdx.x == 0 && threadIdx.x < 64) {  // the loss: lane-strided partial sums, then a fixed tree
         float s = 0.0f;
-        for (int b = 0; b < nblocks; ++b) s += tb.rowpart[(size_t)b * kTrainPartStride + kRpLoss];
-        loss_out[mode == 2 ? t - 1 : 0] = s * inv_count;
+        for (int b = threadIdx.x; b < nblocks; b += 64) s += tb.rowpart[(size_t)b * kTrainPartStride + kRpLoss];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+        if (threadIdx.x == 0) loss_out[mode == 2 ? t - 1 : 0] = s * inv_count;
     }
     if (q >= kParams) return;
     float g = 0.0f;
@@ -567,9 +699,12 @@ __global__ void __launch_bounds__(256) k_train_update(MlpDevice d, MlpTrain tb, 
     if (wl >= 0) {
         const int off = q - (wl == 0 ? kOffW2 : (wl == 1 ? kOffW3 : kOffW4));
         const float *p = tb.dwpart + (size_t)wl * kMaxDwSplits * kHidden * kHidden + off;
+#pragma unroll 16
         for (int z = 0; z < nsplit; ++z) g += p[(size_t)z * kHidden * kHidden];
     } else {
-        for (int b = 0; b < nblocks; ++b) g += tb.rowpart[(size_t)b * kTrainPartStride + rec];
+        const float *p = tb.rowpart + rec;
+#pragma unroll 16
+        for (int b = 0; b < nblocks; ++b) g += p[(size_t)b * kTrainPartStride];
     }
     d.grad[q] = g;
     if (mode == 0) return;

@@ -39,6 +39,7 @@ struct MlpTrain {
     int64_t rows_cap;
     unsigned short *aT[3];   // activations a1, a2, a3 (bf16) transposed: [256][rows_cap]
     unsigned short *dzT[3];  // errors dz2, dz3, dz4 (bf16) transposed: [256][rows_cap]
+    float *zbuf;             // pre-activations of layers 1..4: [4][rows_cap][256] f32
     float *rowpart;          // [rows_cap / 64][kTrainPartStride]
     float *dwpart;           // [3][kMaxDwSplits][256][256]
 };

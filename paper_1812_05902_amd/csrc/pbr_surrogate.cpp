@@ -28,6 +28,7 @@ struct pbr_surrogate {
     float *x = nullptr, *y = nullptr, *t = nullptr, *loss = nullptr;
     int *step = nullptr;                 // training step counter read by the captured step
     hipStream_t train_stream = nullptr;  // non-blocking stream the training step is captured on
+    hipStream_t copy_stream = nullptr;   // uploads of the next epoch's order while an epoch runs
     int *idx = nullptr;
     unsigned long long *count = nullptr;
     // trained state
@@ -173,6 +174,7 @@ void layout_persistent(pbr_surrogate *s, Carve &c, int64_t R, int64_t chunk)
         s->tb.aT[l] = c.take<unsigned short>(H * R * 2);
         s->tb.dzT[l] = c.take<unsigned short>(H * R * 2);
     }
+    s->tb.zbuf = c.take<float>((size_t)4 * R * H * 4);
     s->tb.rowpart = c.take<float>((size_t)(R / 64) * pbr::kTrainPartStride * 4);
     s->tb.dwpart = c.take<float>((size_t)3 * pbr::kMaxDwSplits * H * H * 4);
     s->x = c.take<float>(R * 6 * 4);
@@ -194,7 +196,7 @@ struct TrainScratch {
     pbr::SurrogateSample *trs, *vas;
     double *part;
     int *flags;      // per training ray, then per validation ray (entry tiles)
-    int *perm;
+    int *perm[2];    // shuffled sample order of alternate epochs
     float *losses;
     unsigned *tile_err, *tile_cnt;
     float *err;
@@ -213,7 +215,7 @@ void layout_train(TrainScratch *t, Carve &c, int64_t n_train, int64_t n_val, int
     t->vas = c.take<pbr::SurrogateSample>((size_t)n_val * sizeof(pbr::SurrogateSample));
     t->part = c.take<double>((size_t)1024 * pbr::kMoments * sizeof(double));
     t->flags = c.take<int>((size_t)std::max(n_train, n_val) * sizeof(int));
-    t->perm = c.take<int>((size_t)(n_train / batch * batch) * sizeof(int));
+    for (int b = 0; b < 2; ++b) t->perm[b] = c.take<int>((size_t)(n_train / batch * batch) * sizeof(int));
     t->losses = c.take<float>((size_t)train_steps_bound(n_train, batch, epochs) * sizeof(float));
     t->tile_err = c.take<unsigned>((size_t)(nt + 1) * 4);
     t->tile_cnt = c.take<unsigned>((size_t)(nt + 1) * 4);
@@ -352,8 +354,10 @@ int pbr_surrogate_create(pbr_surrogate **out, int device, void *hip_stream, uint
         Carve c;
         c.base = (unsigned char *)ws_dev;
         layout_persistent(s, c, s->rows_cap, ray_chunk);
-        if ((e = (int)hipStreamCreateWithFlags(&s->train_stream, hipStreamNonBlocking))) {
-            const int r = sfail(nullptr, PBR_ERR_HIP, "training stream: %s", hipGetErrorString((hipError_t)e));
+        if ((e = (int)hipStreamCreateWithFlags(&s->train_stream, hipStreamNonBlocking)) ||
+            (e = (int)hipStreamCreateWithFlags(&s->copy_stream, hipStreamNonBlocking))) {
+            const int r = sfail(nullptr, PBR_ERR_HIP, "training streams: %s", hipGetErrorString((hipError_t)e));
+            if (s->train_stream) (void)hipStreamDestroy(s->train_stream);
             delete s;
             return r;
         }
@@ -381,10 +385,11 @@ void pbr_surrogate_destroy(pbr_surrogate *s)
     try {
         DeviceGuard g(s->device);
         (void)hipStreamSynchronize(s->stream);
-        if (s->train_stream) {
-            (void)hipStreamSynchronize(s->train_stream);
-            (void)hipStreamDestroy(s->train_stream);
-        }
+        for (hipStream_t q : {s->train_stream, s->copy_stream})
+            if (q) {
+                (void)hipStreamSynchronize(q);
+                (void)hipStreamDestroy(q);
+            }
     } catch (...) {
     }
     delete s;
@@ -633,54 +638,90 @@ int pbr_surrogate_train(pbr_surrogate *s, pbr_ctx *ctx, const float *train_src_d
     const int64_t spe = (int64_t)valid.size() / cfg->batch;
     const int64_t total = spe * cfg->epochs;
     if (total > (1ll << 30)) return sfail(s, PBR_ERR_ARG, "too many Adam steps");
-    int *perm = ts_.perm;
     float *losses = ts_.losses;
     t0 = clk::now();
-    // One training step (gather, forward, backward, loss, Adam with the step counter on the
-    // device) is captured once into a graph on the training stream and replayed for every step;
-    // only the shuffled order is uploaded between epochs.
+    // Training steps (gather, forward, backward, loss, Adam with the step counter on the device)
+    // are captured into graphs of kGraphSteps steps (and of one step for the rest of an epoch) on
+    // the training stream, one set per order buffer.  The host shuffles and uploads the order of
+    // epoch e + 1 on the copy stream while epoch e runs; events keep the upload behind the epoch
+    // that last read its buffer and the epoch behind its upload.
+    constexpr int64_t kGraphSteps = 16;
     if ((e = (int)hipStreamSynchronize(st))) return shf(s, e, "sample trace");
-    hipStream_t ts = s->train_stream;
+    hipStream_t ts = s->train_stream, cs = s->copy_stream;
     if ((e = pbr::launch_clear_u64((unsigned long long *)s->step, 1, ts))) return shf(s, e, "clear step");
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    struct GraphGuard {
-        hipGraph_t *g;
-        hipGraphExec_t *x;
-        ~GraphGuard()
+    struct Resources {
+        hipGraphExec_t exec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [order buffer][many, one]
+        hipEvent_t copied[2] = {nullptr, nullptr}, done[2] = {nullptr, nullptr};
+        hipStream_t ts = nullptr, cs = nullptr;
+        ~Resources()
         {
-            if (*x) (void)hipGraphExecDestroy(*x);
-            if (*g) (void)hipGraphDestroy(*g);
+            // nothing may still read or write the order buffers when the call returns
+            if (ts) (void)hipStreamSynchronize(ts);
+            if (cs) (void)hipStreamSynchronize(cs);
+            for (auto &row : exec)
+                for (hipGraphExec_t x : row)
+                    if (x) (void)hipGraphExecDestroy(x);
+            for (int b = 0; b < 2; ++b) {
+                if (copied[b]) (void)hipEventDestroy(copied[b]);
+                if (done[b]) (void)hipEventDestroy(done[b]);
+            }
         }
-    } gg{&graph, &exec};
-    if ((e = (int)hipStreamBeginCapture(ts, hipStreamCaptureModeRelaxed))) return shf(s, e, "hipStreamBeginCapture");
-    {
-        int ce = 0;
-        if ((ce = pbr::launch_surr_gather_step(spec, trs, perm, s->step, spe, cfg->batch, s->x, s->t, ts)) ||
-            (ce = pbr::mlp_train_step(s->d, s->tb, s->x, s->t, cfg->batch, 2, 0.0f, 0, s->step, (int)total,
-                                      cfg->lr_max, cfg->lr_min, losses, ts))) {
-            hipGraph_t g2 = nullptr;
-            (void)hipStreamEndCapture(ts, &g2);
-            if (g2) (void)hipGraphDestroy(g2);
-            return shf(s, ce, "training step capture");
-        }
+    } rs;
+    rs.ts = ts;
+    rs.cs = cs;
+    for (int b = 0; b < 2; ++b)
+        if ((e = (int)hipEventCreateWithFlags(&rs.copied[b], hipEventDisableTiming)) ||
+            (e = (int)hipEventCreateWithFlags(&rs.done[b], hipEventDisableTiming)))
+            return shf(s, e, "hipEventCreate");
+    const int64_t gsteps = std::min(kGraphSteps, spe);
+    auto capture = [&](const int *perm, int64_t nsteps, hipGraphExec_t *exec) -> int {
+        hipGraph_t graph = nullptr;
+        int ce = (int)hipStreamBeginCapture(ts, hipStreamCaptureModeRelaxed);
+        if (ce) return shf(s, ce, "hipStreamBeginCapture");
+        for (int64_t k = 0; k < nsteps && !ce; ++k)
+            if (!(ce = pbr::launch_surr_gather_step(spec, trs, perm, s->step, spe, cfg->batch, s->x, s->t, ts)))
+                ce = pbr::mlp_train_step(s->d, s->tb, s->x, s->t, cfg->batch, 2, 0.0f, 0, s->step, (int)total,
+                                         cfg->lr_max, cfg->lr_min, losses, ts);
+        const int ee = (int)hipStreamEndCapture(ts, &graph);
+        if (!ce && !ee) ce = (int)hipGraphInstantiate(exec, graph, nullptr, nullptr, 0);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (ce || ee) return shf(s, ce ? ce : ee, "training step capture");
+        return 0;
+    };
+    for (int b = 0; b < 2; ++b) {
+        if ((e = capture(ts_.perm[b], gsteps, &rs.exec[b][0]))) return e;
+        if (spe % gsteps && (e = capture(ts_.perm[b], 1, &rs.exec[b][1]))) return e;
     }
-    if ((e = (int)hipStreamEndCapture(ts, &graph))) return shf(s, e, "hipStreamEndCapture");
-    if ((e = (int)hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0))) return shf(s, e, "hipGraphInstantiate");
-    for (int ep = 0; ep < cfg->epochs; ++ep) {
-        // Fisher-Yates shuffle driven by SplitMix64
+    const size_t order_bytes = (size_t)spe * cfg->batch * sizeof(int);
+    auto shuffle = [&](int ep) {  // Fisher-Yates driven by SplitMix64, continuing from the last order
         const uint64_t es = cfg->shuffle_seed + 0x632BE59BD9B4E019ull * (uint64_t)(ep + 1);
         for (size_t i = valid.size() - 1; i > 0; --i) {
             const size_t j = (size_t)(splitmix64_host(es, i) % (uint64_t)(i + 1));
             std::swap(valid[i], valid[j]);
         }
-        if ((e = (int)hipMemcpyAsync(perm, valid.data(), (size_t)spe * cfg->batch * sizeof(int),
-                                     hipMemcpyHostToDevice, ts)))
-            return shf(s, e, "copy permutation");
-        for (int64_t j = 0; j < spe; ++j)
-            if ((e = (int)hipGraphLaunch(exec, ts))) return shf(s, e, "training step");
-        if ((e = (int)hipStreamSynchronize(ts))) return shf(s, e, "training");  // before the next shuffle
+    };
+    shuffle(0);
+    if ((e = (int)hipMemcpyAsync(ts_.perm[0], valid.data(), order_bytes, hipMemcpyHostToDevice, cs)) ||
+        (e = (int)hipEventRecord(rs.copied[0], cs)))
+        return shf(s, e, "copy order");
+    for (int ep = 0; ep < cfg->epochs; ++ep) {
+        const int b = ep & 1;
+        if ((e = (int)hipStreamWaitEvent(ts, rs.copied[b], 0))) return shf(s, e, "hipStreamWaitEvent");
+        for (int64_t j = 0; j + gsteps <= spe; j += gsteps)
+            if ((e = (int)hipGraphLaunch(rs.exec[b][0], ts))) return shf(s, e, "training steps");
+        for (int64_t j = 0; j < spe % gsteps; ++j)
+            if ((e = (int)hipGraphLaunch(rs.exec[b][1], ts))) return shf(s, e, "training step");
+        if ((e = (int)hipEventRecord(rs.done[b], ts))) return shf(s, e, "hipEventRecord");
+        if (ep + 1 == cfg->epochs) break;
+        // the host order is free once its last upload has been read
+        if ((e = (int)hipEventSynchronize(rs.copied[b]))) return shf(s, e, "copy order");
+        shuffle(ep + 1);
+        if ((e = (int)hipStreamWaitEvent(cs, rs.done[b ^ 1], 0)) ||
+            (e = (int)hipMemcpyAsync(ts_.perm[b ^ 1], valid.data(), order_bytes, hipMemcpyHostToDevice, cs)) ||
+            (e = (int)hipEventRecord(rs.copied[b ^ 1], cs)))
+            return shf(s, e, "copy order");
     }
+    if ((e = (int)hipStreamSynchronize(ts))) return shf(s, e, "training");
     std::vector<float> hl((size_t)total);
     if ((e = (int)hipMemcpy(hl.data(), losses, hl.size() * sizeof(float), hipMemcpyDeviceToHost)))
         return shf(s, e, "copy losses");

@@ -540,7 +540,7 @@ def test_surrogate_workspace_sizes(lib):
     assert ws(0, 0) == ws(65536, 0)          # 0 rows means 65536
     assert ws(100, 0) == ws(128, 0)          # rows round up to 64
     per_row = (ws(64 + 64 * 1024, 0) - base) / (64 * 1024)
-    assert abs(per_row - 3408) < 1  # 6 x 256 x 2 (transposed bf16 activations and errors) + 4224 x 4 / 64 (row sums) + 3 x 6 x 4
+    assert abs(per_row - 7504) < 1  # 6 x 256 x 2 (transposed bf16 activations and errors) + 4 x 256 x 4 (pre-activations) + 4224 x 4 / 64 (row sums) + 3 x 6 x 4
     per_ray = (ws(64, 1 << 20) - base) / (1 << 20)
     assert abs(per_ray - 53) < 1e-3
     assert ws(-1, 0) == 0 and ws(1 << 25, 0) == 0 and ws(64, -1) == 0
