@@ -165,6 +165,9 @@ def main():
                          "one per workload")
     ap.add_argument("--rays-per-chunk", type=int, default=1 << 24,
                     help="rays per trace chunk (64 bytes of ray state each; the bos_fig4 renders use one chunk)")
+    ap.add_argument("--source-order", choices=["morton", "index"], default="morton",
+                    help="tomo_piv_512: trace the particles in Morton order of their positions (computed in "
+                         "every step; same image bit for bit) or in index order")
     ap.add_argument("--no-extra", action="store_true",
                     help="tomo_piv_512: leave out the shock-FP64 leg, the 128^3 BOS workload and the peak probes "
                          "(for profiling runs; the headline value is unchanged)")
@@ -383,7 +386,20 @@ def bench_tomo(args):
     cal = rc.calibrate_precision(sc.ds, tol_px=1e-3) if extra else None
     print(f"set up in {setup_s:.1f} s; calibration {cal}", file=sys.stderr, flush=True)
 
+    # sources traced in Morton order of their positions (the order is computed inside every step;
+    # rays keep their keys, so the image is the same bit for bit)
+    morton = args.source_order == "morton"
+    n_src = src.shape[0]
+    order = torch.empty(n_src, dtype=torch.int64, device=rn.device)
+    order_ws = torch.empty(max(pbr.pbr_source_order_morton_workspace_bytes(n_src), 8) // 8, dtype=torch.int64,
+                           device=rn.device)
+    for r in {id(x): x for x in (rn, rc) if x is not None}.values():
+        pbr.pbr_set_source_order(r.ctx, order, n_src)
+
     def step(r, flags, stats):
+        if morton:
+            pbr.pbr_source_order_morton(r.ctx, src, n_src, order, order_ws)
+            flags |= pbr.PBR_SOURCE_ORDER
         st = r.emit_and_trace(src, sc.rays_per_src, sc.ray_seed, sc.ds, pbr.PBR_CLEAR_FIRST | flags, stats=stats)
         pbr.pbr_read_image(r.ctx, pbr.PBR_FMT_U16, out16, 0.0)
         return st
@@ -422,7 +438,7 @@ def bench_tomo(args):
                    "rays_per_chunk": args.rays_per_chunk, "n_src": sc.n_src, "rays_per_src": sc.rays_per_src,
                    "rays_per_image": sc.n_rays, "sensor": f"{sc.width}x{sc.height} u16", "ds_m": sc.ds,
                    "mean_rkn_steps_per_ray": steps_total / args.steps / sc.n_rays, "setup_s": setup_s,
-                   "field_layout": layout},
+                   "field_layout": layout, "source_order": args.source_order},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": _traffic_from_profile("tomo_piv_512"),
                      "kernel": f"k_box32<{'true' if layout == 'nodes' else 'false'}>",

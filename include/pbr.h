@@ -72,6 +72,8 @@ extern "C" {
 #define PBR_SOURCE_SUMS     (1u << 6)  /* add every deposited ray's sensor hit into the per-source sums set by
                                           pbr_set_source_sums (sec. 4: a dot's displacement is the mean of
                                           its rays') */
+#define PBR_SOURCE_ORDER    (1u << 8)  /* trace the sources in the order set by pbr_set_source_order; every
+                                          ray keeps its key, so the results are the same bit for bit */
 
 /* ---------------------------------------------------------------- pbr_read_image formats */
 #define PBR_FMT_RAW_U64 0  /* copy of the Q32.32 accumulator (uint64 per pixel) */
@@ -394,6 +396,36 @@ typedef struct pbr_source_sum {
     uint64_t hits;     /* rays of the source deposited on the sensor */
     uint64_t reserved; /* left untouched */
 } pbr_source_sum;
+
+/* Order in which a trace with PBR_SOURCE_ORDER takes its sources (sec. 3.5: a source's rays run
+ * together and share the cells they cross; neighbouring sources running together share more).
+ * order_dev: caller-owned device array of n_src int64 source indices, a permutation of
+ * 0 .. n_src - 1, read by every such trace (whose n_src must equal this n_src).  Position q of the
+ * processing order is ray q mod rays_per_src of source order_dev[q / rays_per_src], and it keeps
+ * that source's key: its random numbers (the SplitMix64 counter of pbr_emit_and_trace), weight,
+ * exit-record index and per-source sums are those of the call without an order, so image,
+ * records, sums and counters are the same bit for bit; only the order in which rays meet the
+ * field, and so the cache reuse between rays in flight together, changes.  An entry outside
+ * [0, n_src) is clamped into range (a non-permutation then traces some sources twice and others
+ * not at all).  NULL with n_src = 0 clears the order.
+ * Errors: ARG (n_src < 0, null with n_src > 0, misaligned). */
+int pbr_set_source_order(pbr_ctx *ctx, const int64_t *order_dev, int64_t n_src);
+
+/* Device scratch (bytes) pbr_source_order_morton needs for n_src sources; 0 if n_src < 0 or
+ * n_src > 2^31 - 1. */
+size_t pbr_source_order_morton_workspace_bytes(int64_t n_src);
+
+/* Writes to order_dev (caller-owned device array of n_src int64) the permutation that sorts the
+ * sources of src_dev (float32 [n_src][4] as in pbr_emit_and_trace) by the Morton (Z-order) code of
+ * their position in the field's box: 21 bits per axis, positions clamped onto the box, x in the
+ * lowest bit; equal codes keep their index order.  Traced in this order, sources that run
+ * together lie close together in the field.  Asynchronous on the context's stream.  ws_dev:
+ * caller-owned device scratch of at least pbr_source_order_morton_workspace_bytes(n_src) bytes,
+ * 256-byte aligned.  Allocates no device memory.
+ * Errors: STATE (no field; host-only context), ARG (n_src out of range, null arrays),
+ * WORKSPACE, HIP. */
+int pbr_source_order_morton(pbr_ctx *ctx, const float *src_dev, int64_t n_src, int64_t *order_dev, void *ws_dev,
+                            size_t ws_bytes);
 
 /* Sets the per-source sums that traces with PBR_SOURCE_SUMS add into: sums_dev[s] for source s
  * of the call (caller-owned device array of `capacity` records, 8-byte aligned, which the caller

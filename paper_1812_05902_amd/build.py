@@ -17,7 +17,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libpbr.so")
 
 SOURCES = ["field_prep.hip", "trace.hip", "readout.hip", "mlp.hip", "probe.hip", "bos_map.hip", "piv_pair.hip",
-           "pbr_api.cpp", "pbr_mie.cpp", "pbr_batch.cpp", "pbr_surrogate.cpp", "pbr_noalloc.cpp"]
+           "pbr_api.cpp", "pbr_mie.cpp", "pbr_batch.cpp", "pbr_surrogate.cpp", "pbr_noalloc.cpp", "source_order.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function",

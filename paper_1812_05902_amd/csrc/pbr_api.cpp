@@ -468,6 +468,47 @@ int pbr_set_source_sums(pbr_ctx *ctx, pbr_source_sum *sums_dev, int64_t capacity
     return PBR_OK;
 }
 
+int pbr_set_source_order(pbr_ctx *ctx, const int64_t *order_dev, int64_t n_src)
+{
+    if (!ctx) return PBR_ERR_ARG;
+    if (n_src < 0) return fail(ctx, PBR_ERR_ARG, "n_src < 0");
+    if (n_src > 0 && !order_dev) return fail(ctx, PBR_ERR_ARG, "order array is null");
+    if (((uintptr_t)order_dev & 7u) != 0) return fail(ctx, PBR_ERR_ARG, "order array must be 8-byte aligned");
+    ctx->src_order = n_src > 0 ? order_dev : nullptr;
+    ctx->src_order_n = n_src;
+    return PBR_OK;
+}
+
+size_t pbr_source_order_morton_workspace_bytes(int64_t n_src) { return pbr::morton_order_scratch_bytes(n_src); }
+
+int pbr_source_order_morton(pbr_ctx *ctx, const float *src_dev, int64_t n_src, int64_t *order_dev, void *ws_dev,
+                            size_t ws_bytes)
+{
+    if (!ctx) return PBR_ERR_ARG;
+    PBR_GUARD_BEGIN
+    if (n_src < 0 || n_src > 2147483647) return fail(ctx, PBR_ERR_ARG, "n_src must lie in [0, 2^31 - 1]");
+    if (n_src > 0 && (!src_dev || !order_dev)) return fail(ctx, PBR_ERR_ARG, "null source or order array");
+    if (((uintptr_t)src_dev & 15u) != 0 || ((uintptr_t)order_dev & 7u) != 0)
+        return fail(ctx, PBR_ERR_ARG, "misaligned source or order array");
+    if (!ctx->has_field) return fail(ctx, PBR_ERR_STATE, "no field set");
+    if (ctx->device < 0) return fail(ctx, PBR_ERR_STATE, "host-only context: no device work");
+    const size_t need = pbr::morton_order_scratch_bytes(n_src);
+    if (!ws_dev || ws_bytes < need)
+        return fail(ctx, PBR_ERR_WORKSPACE, "order workspace of %zu bytes < %zu", ws_bytes, need);
+    if (((uintptr_t)ws_dev & 255u) != 0) return fail(ctx, PBR_ERR_ARG, "order workspace must be 256-byte aligned");
+    if (n_src == 0) return PBR_OK;
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(ctx, PBR_ERR_HIP, "hipSetDevice failed");
+    const int n3[3] = {ctx->nx, ctx->ny, ctx->nz};
+    double ext[3];
+    for (int a = 0; a < 3; ++a) ext[a] = (double)(n3[a] - 1) * ctx->spacing[a];
+    const int e = pbr::launch_morton_order((const float4 *)src_dev, n_src, ctx->origin, ext, order_dev, ws_dev,
+                                           ctx->stream);
+    if (e) return hip_fail(ctx, e, "source order");
+    return PBR_OK;
+    PBR_GUARD_END
+}
+
 int pbr_emit_and_trace(pbr_ctx *ctx, const float *src_dev, int64_t n_src, int32_t rays_per_src,
                        uint64_t seed, double ds, uint32_t flags, pbr_stats *stats)
 {
@@ -507,7 +548,7 @@ int emit_and_trace_impl(pbr_ctx *ctx, const float *src_dev, int64_t n_src, int32
             return fail(ctx, PBR_ERR_ARG, "sensor plane must lie behind the lens");
     }
     if (flags & ~(uint32_t)(PBR_CLEAR_FIRST | PBR_RECORD_EXITS | PBR_PREC_FP64_ALL | PBR_PREC_SHOCK_FP64 |
-                            PBR_SURROGATE | PBR_LANE_REFILL | PBR_SOURCE_SUMS | PBR_MIE))
+                            PBR_SURROGATE | PBR_LANE_REFILL | PBR_SOURCE_SUMS | PBR_MIE | PBR_SOURCE_ORDER))
         return fail(ctx, PBR_ERR_ARG, "unknown flag bits 0x%x", flags);
     if ((flags & PBR_MIE) && !ctx->mie) return fail(ctx, PBR_ERR_STATE, "no Mie table set (pbr_set_mie)");
     if (ctx->layout.nodes && (flags & (PBR_LANE_REFILL | PBR_PREC_SHOCK_FP64)))
@@ -523,6 +564,12 @@ int emit_and_trace_impl(pbr_ctx *ctx, const float *src_dev, int64_t n_src, int32
     pbr::RayState *ray_ws = noalloc ? static_ws : ctx->ray_ws;
     const int64_t ray_chunk = noalloc ? static_chunk : ctx->ray_chunk;
     pbr::ChunkHook hook{nullptr, nullptr};
+    if ((flags & PBR_SOURCE_ORDER) && n_src > 0) {
+        if (!ctx->src_order) return fail(ctx, PBR_ERR_STATE, "no source order set (pbr_set_source_order)");
+        if (ctx->src_order_n != n_src)
+            return fail(ctx, PBR_ERR_ARG, "source order is for %lld sources, the call has %lld",
+                        (long long)ctx->src_order_n, (long long)n_src);
+    }
     if (flags & PBR_SURROGATE) {
         if ((r = surrogate_hook(ctx, ds, ray_chunk, &hook))) return r;
     }
@@ -556,6 +603,7 @@ int emit_and_trace_impl(pbr_ctx *ctx, const float *src_dev, int64_t n_src, int32
     P.seed = seed;
     P.record = (flags & PBR_RECORD_EXITS) && ctx->rec_max > 0 ? 1 : 0;
     P.src_sums = (flags & PBR_SOURCE_SUMS) ? ctx->src_sums : nullptr;
+    P.order = (flags & PBR_SOURCE_ORDER) && n_src > 0 ? ctx->src_order : nullptr;
     if (flags & PBR_MIE) {
         P.mie = ctx->mie;
         P.mie_n = PBR_MIE_TABLE_SIZE;

@@ -23,6 +23,8 @@ struct pbr_ctx {
     const double *mie = nullptr;            // Mie intensity table (PBR_MIE), device
     double laser[3] = {1.0, 0.0, 0.0};
     int64_t src_sums_cap = 0;
+    const int64_t *src_order = nullptr;     // processing order of the sources (PBR_SOURCE_ORDER), device
+    int64_t src_order_n = 0;
     unsigned *brick_gmax = nullptr;        // per-brick max |grad n| (float bits), device
     unsigned char *brick_fp64 = nullptr;   // per-brick FP64 flags, device
     pbr::FieldLayout layout{};

@@ -75,6 +75,7 @@ struct TraceParams {
     double n_inf;
     // sources and rays
     const float4 *src;
+    const int64_t *order;  // processing order of the sources (null: index order); rays keep their keys
     int64_t n_src;
     int64_t n_rays;
     int32_t rays_per_src;
@@ -261,6 +262,13 @@ int launch_trace_chunk(const TraceParams &p, RayState *st, int64_t first, int64_
 int launch_readout(const unsigned long long *accum, int64_t npx, int fmt, void *out,
                    double gain, unsigned long long *counters, hipStream_t stream);
 int launch_clear_u64(unsigned long long *p, int64_t n, hipStream_t stream);
+// Device scratch of launch_morton_order for n sources (0 when n is out of [0, 2^31 - 1]).
+size_t morton_order_scratch_bytes(int64_t n);
+// order = the permutation sorting the n sources by the Morton code of their position in the box
+// [lo, lo + ext] (21 bits per axis, clamped onto the box), ties in index order; ws: scratch of
+// morton_order_scratch_bytes(n) bytes.
+int launch_morton_order(const float4 *src, int64_t n, const double lo[3], const double ext[3], int64_t *order,
+                        void *ws, hipStream_t stream);
 
 // BOS displacement check (sec. 4).  ws: 3 uint64 per node (cleared here).
 int launch_dot_map(const pbr_source_sum *with_sums, const pbr_source_sum *without_sums, const float4 *src,

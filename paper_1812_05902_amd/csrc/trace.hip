@@ -623,6 +623,19 @@ __device__ __forceinline__ double mie_weight(const TraceParams &P, const double 
     return P.mie[i] * (1.0 - f) + P.mie[i + 1] * f;
 }
 
+// Key of the ray at position q of the processing order.  With a source order, position q is ray
+// q mod rays_per_src of source order[q / rays_per_src] (clamped into range), and the key is that
+// ray's position without the order: everything the ray is (random numbers, weight, record index,
+// per-source sums) follows from the key, so the order changes nothing but the schedule.
+__device__ __forceinline__ int64_t ray_key(const TraceParams &P, int64_t q)
+{
+    if (!P.order) return q;
+    const int64_t k = q / P.rays_per_src;
+    int64_t s = P.order[k];
+    s = s < 0 ? 0 : (s >= P.n_src ? P.n_src - 1 : s);
+    return s * P.rays_per_src + (q - k * P.rays_per_src);
+}
+
 __device__ __forceinline__ void emit_ray(const TraceParams &P, int64_t rid, RayState &r)
 {
     // FP64 set-up and optics: no contracted multiply-adds, so every kernel that inlines this
@@ -702,7 +715,7 @@ __global__ void __launch_bounds__(256) k_emit(TraceParams P, RayState *__restric
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     RayState r;
-    emit_ray(P, first + i, r);
+    emit_ray(P, ray_key(P, first + i), r);
     st[i] = r;
 }
 
@@ -1194,9 +1207,9 @@ __device__ __forceinline__ void finish_block(const TraceParams &P, const RayStat
         sh.ty0 = (int)ypx - TILE / 2;
     }
     __syncthreads();
-    if (P.src_sums) add_source_sums(P, valid && status == PBR_RAY_DEPOSITED, first + i, xpx, ypx);
+    const int64_t rid = valid ? ray_key(P, first + i) : first + i;
+    if (P.src_sums) add_source_sums(P, valid && status == PBR_RAY_DEPOSITED, rid, xpx, ypx);
     if (valid && status == PBR_RAY_DEPOSITED) {
-        const int64_t rid = first + i;
         const float4 sv = P.src[rid / P.rays_per_src];
         double w = sv.w > 0.0f ? (sv.w < 1.0f ? (double)sv.w : 1.0) : 0.0;  // weights in [0, 1]
         if ((FEAT & FEAT_MIE) && P.mie) {  // the ray's Mie factor, from its direction at the source
@@ -1218,7 +1231,6 @@ __device__ __forceinline__ void finish_block(const TraceParams &P, const RayStat
         }
     }
     if (valid) {
-        const int64_t rid = first + i;
         if (P.record && rid >= P.rec_first) {
             const int64_t off = rid - P.rec_first;
             const int64_t k = off / P.rec_stride;
@@ -1294,7 +1306,7 @@ __global__ void __launch_bounds__(256) k_emit_batch(const TraceParams *__restric
     const int64_t local = (int64_t)(blockIdx.x - sg.slot_base) * 256 + threadIdx.x;
     if (local >= sg.n_rays) return;
     RayState r;
-    emit_ray(params[sg.image], sg.first_ray + local, r);
+    emit_ray(params[sg.image], ray_key(params[sg.image], sg.first_ray + local), r);
     st[(int64_t)blockIdx.x * 256 + threadIdx.x] = r;
 }
 
@@ -1406,7 +1418,7 @@ __global__ void __launch_bounds__(256) k_surr_samples(TraceParams P, SurrogateSp
     smp.tile = 0;
     smp.flags = 0;
     RayState e;
-    emit_ray(P, first + i, e);  // the entry state again (the trace overwrote it)
+    emit_ray(P, ray_key(P, first + i), e);  // the entry state again (the trace overwrote it)
     double E[3], u[3];
     const RayState r = st[i];
     const bool enters = entry_of(P, e, E, u);

@@ -27,6 +27,7 @@ PBR_CLEAR_FIRST, PBR_RECORD_EXITS, PBR_PREC_FP64_ALL, PBR_PREC_SHOCK_FP64, PBR_S
 PBR_LANE_REFILL = 32
 PBR_SOURCE_SUMS = 64
 PBR_MIE = 128
+PBR_SOURCE_ORDER = 256
 PBR_MAX_SURFACES = 16
 PBR_SURF_REFRACT, PBR_SURF_MIRROR, PBR_SURF_APERTURE, PBR_SURF_LENSLETS = 0, 1, 2, 3
 PBR_MIE_TABLE_SIZE = 2049
@@ -52,7 +53,8 @@ EXPORTED = ["pbr_create", "pbr_destroy", "pbr_last_error", "pbr_set_stream",
             "pbr_set_density_field_nodes", "pbr_surrogate_blob_bytes", "pbr_surrogate_save",
             "pbr_surrogate_load", "pbr_probe_fma_rate",
             "pbr_probe_read_bandwidth", "pbr_probe_lds_bandwidth", "pbr_emit_and_trace_noalloc",
-            "pbr_surrogate_workspace_bytes", "pbr_surrogate_train_workspace_bytes"]
+            "pbr_surrogate_workspace_bytes", "pbr_surrogate_train_workspace_bytes",
+            "pbr_set_source_order", "pbr_source_order_morton_workspace_bytes", "pbr_source_order_morton"]
 
 
 class PbrError(RuntimeError):
@@ -218,6 +220,9 @@ def load(path: str = LIB_PATH):
         "pbr_probe_read_bandwidth": (I, [I, I64, I64, I, C.POINTER(D)]),
         "pbr_probe_lds_bandwidth": (I, [I, C.POINTER(D)]),
         "pbr_set_source_sums": (I, [P, P, I64]),
+        "pbr_set_source_order": (I, [P, P, I64]),
+        "pbr_source_order_morton_workspace_bytes": (C.c_size_t, [I64]),
+        "pbr_source_order_morton": (I, [P, P, I64, P, P, C.c_size_t]),
         "pbr_dot_map_workspace_bytes": (C.c_size_t, [I, I]),
         "pbr_dot_displacement_map": (I, [P, P, P, P, I64, C.POINTER(pbr_map_grid), P, C.c_size_t, P]),
         "pbr_bos_theory_map": (I, [P, C.POINTER(pbr_map_grid), C.c_int32, P]),
@@ -351,6 +356,19 @@ def pbr_read_ray_exits(ctx, first, count) -> np.ndarray:
 
 def pbr_set_source_sums(ctx, sums, capacity):
     _check(ctx, load().pbr_set_source_sums(ctx, _dptr(sums), int(capacity)))
+
+
+def pbr_set_source_order(ctx, order, n_src):
+    _check(ctx, load().pbr_set_source_order(ctx, _dptr(order), int(n_src)))
+
+
+def pbr_source_order_morton_workspace_bytes(n_src) -> int:
+    return int(load().pbr_source_order_morton_workspace_bytes(int(n_src)))
+
+
+def pbr_source_order_morton(ctx, src, n_src, order, ws):
+    _check(ctx, load().pbr_source_order_morton(ctx, _dptr(src), int(n_src), _dptr(order), _dptr(ws),
+                                               ws.numel() * ws.element_size()))
 
 
 def pbr_dot_map_workspace_bytes(nx, ny) -> int:
@@ -522,6 +540,31 @@ class Renderer:
         self.sums = self.torch.zeros(int(n_src), 4, dtype=self.torch.int64, device=self.device)
         pbr_set_source_sums(self.ctx, self.sums, n_src)
         return self.sums
+
+    def morton_order(self, src):
+        """Permutation of the sources (int64 tensor [n_src]) sorting their positions in the field
+        box by Morton code; for set_source_order."""
+        torch = self.torch
+        src = torch.as_tensor(src, dtype=torch.float32, device=self.device).contiguous()
+        n = src.shape[0]
+        nb = pbr_source_order_morton_workspace_bytes(n)
+        if nb == 0:
+            raise PbrError(PBR_ERR_ARG, "too many sources for a Morton order")
+        ws = torch.empty(max(nb, 8) // 8, dtype=torch.int64, device=self.device)
+        order = torch.empty(n, dtype=torch.int64, device=self.device)
+        pbr_source_order_morton(self.ctx, src, n, order, ws)
+        self._order_keepalive = (src, ws)
+        return order
+
+    def set_source_order(self, order):
+        """Traces with PBR_SOURCE_ORDER take the sources in this order (int64 tensor [n_src], a
+        permutation); None clears it."""
+        if order is None:
+            pbr_set_source_order(self.ctx, None, 0)
+            self.src_order = None
+            return
+        self.src_order = self.torch.as_tensor(order, dtype=self.torch.int64, device=self.device).contiguous()
+        pbr_set_source_order(self.ctx, self.src_order, self.src_order.shape[0])
 
     def dot_displacement_map(self, with_sums, without_sums, src, grid):
         """Bilinear map of per-dot displacements (float32 tensor [ny][nx][2], pixels);

@@ -210,7 +210,7 @@ def test_call_order_and_trace_validation(lib):
         assert lib.pbr_emit_and_trace(h, FAKE, 1, 1, 0, 0.0, 0, None) == pbr.PBR_ERR_ARG
         assert lib.pbr_emit_and_trace(h, FAKE, 1, 1, 0, math.nan, 0, None) == pbr.PBR_ERR_ARG
         assert lib.pbr_emit_and_trace(h, None, 5, 1, 0, 1e-4, 0, None) == pbr.PBR_ERR_ARG
-        assert lib.pbr_emit_and_trace(h, FAKE, 1, 1, 0, 1e-4, 1 << 8, None) == pbr.PBR_ERR_ARG
+        assert lib.pbr_emit_and_trace(h, FAKE, 1, 1, 0, 1e-4, 1 << 9, None) == pbr.PBR_ERR_ARG
         # 2^32 rays could overflow one pixel of the Q32.32 sensor
         assert lib.pbr_emit_and_trace(h, FAKE, 1 << 20, 1 << 12, 0, 1e-4, 1, C.byref(st)) == pbr.PBR_ERR_OVERFLOW
         assert lib.pbr_emit_and_trace(h, FAKE, 1, 1, 0, 1e-4, 0, None) == pbr.PBR_ERR_STATE
@@ -552,3 +552,41 @@ def test_surrogate_workspace_sizes(lib):
     assert tw(0, 1, 64, 1, 1) == 0 and tw(1, 1, 100, 1, 1) == 0 and tw(1, 1, 64, 0, 1) == 0
     assert tw(1, 1, 64, 1, 1025) == 0
     assert tw((1 << 31) - 1, 1, 64, 1 << 20, 1) == 0  # more than 2^30 Adam steps
+
+
+def test_source_order_entry_points_validate_before_device_work(lib):
+    """The source order: setter arguments, the Morton order's workspace size and its state and
+    argument errors, and a trace with PBR_SOURCE_ORDER that has no matching order, all found on
+    the host."""
+    ws = lib.pbr_source_order_morton_workspace_bytes
+    assert ws(-1) == 0 and ws(1 << 31) == 0
+    assert ws(0) > 0
+    # keys in and out and the identity (8 bytes each per source) plus the sort's own scratch
+    assert ws(1 << 20) >= 3 * 8 * (1 << 20)
+    assert ws(1 << 20) < ws(1 << 21)
+    ctx = _host_ctx(lib)
+    try:
+        assert lib.pbr_set_source_order(ctx, None, -1) == pbr.PBR_ERR_ARG
+        assert lib.pbr_set_source_order(ctx, None, 5) == pbr.PBR_ERR_ARG
+        assert lib.pbr_set_source_order(ctx, FAKE + 4, 5) == pbr.PBR_ERR_ARG
+        assert lib.pbr_set_source_order(ctx, None, 0) == pbr.PBR_OK
+        order = lib.pbr_source_order_morton
+        assert order(ctx, FAKE, 10, FAKE, FAKE, ws(10)) == pbr.PBR_ERR_STATE  # no field
+        assert b"no field" in lib.pbr_last_error(ctx)
+        assert _set_field(lib, ctx) == pbr.PBR_OK
+        assert order(ctx, FAKE, -1, FAKE, FAKE, ws(10)) == pbr.PBR_ERR_ARG
+        assert order(ctx, None, 10, FAKE, FAKE, ws(10)) == pbr.PBR_ERR_ARG
+        assert order(ctx, FAKE + 8, 10, FAKE, FAKE, ws(10)) == pbr.PBR_ERR_ARG  # float4 sources
+        assert order(ctx, FAKE, 10, FAKE, FAKE, ws(10)) == pbr.PBR_ERR_STATE    # host-only context
+        o = _optics(z_front_vertex=0.5, focal_length=0.05, f_number=8.0)
+        assert lib.pbr_set_optics(ctx, C.byref(o)) == pbr.PBR_OK
+        s = _sensor(width=64, height=64, pitch=20e-6)
+        assert lib.pbr_set_sensor(ctx, C.byref(s), FAKE) == pbr.PBR_OK
+        st = pbr.pbr_stats()
+        code = lib.pbr_emit_and_trace(ctx, FAKE, 3, 1, 1, 1e-4, pbr.PBR_SOURCE_ORDER, C.byref(st))
+        assert code == pbr.PBR_ERR_STATE and b"no source order" in lib.pbr_last_error(ctx)
+        assert lib.pbr_set_source_order(ctx, FAKE, 4) == pbr.PBR_OK
+        code = lib.pbr_emit_and_trace(ctx, FAKE, 3, 1, 1, 1e-4, pbr.PBR_SOURCE_ORDER, C.byref(st))
+        assert code == pbr.PBR_ERR_ARG and b"4 sources" in lib.pbr_last_error(ctx)
+    finally:
+        lib.pbr_destroy(ctx)

@@ -145,3 +145,14 @@ def test_tomo_piv_full_image_node_layout_sampled(torch):
     assert both.sum() > 800
     assert np.quantile(d, 0.99) <= 2e-5
     assert d.max() <= 1e-4
+    # the same image with the sources taken in Morton order, as the benchmark traces them: the
+    # same bits, records and counts
+    r.set_source_order(r.morton_order(src))
+    st2 = r.emit_and_trace(src, sc.rays_per_src, sc.ray_seed, sc.ds,
+                           pbr.PBR_CLEAR_FIRST | pbr.PBR_RECORD_EXITS | pbr.PBR_SOURCE_ORDER, stats=True)
+    print(f"Morton order: {st2['rays'] / st2['trace_ms'] * 1e3:.3e} rays/s")
+    assert np.array_equal(pbr.u64_image_to_numpy(r.read_image()), q)
+    rec2 = r.read_ray_exits()
+    for f in pbr.RAY_EXIT_DTYPE.names:
+        assert np.array_equal(rec2[f], rec[f]), f
+    assert st2["status"] == st["status"] and st2["rkn_steps"] == st["rkn_steps"]
