@@ -110,20 +110,19 @@ def _cpu_model() -> str:
 
 
 def _oracle_rate(o, scene, src, threads, target_s):
-    """Rays/s of the oracle over the first sources of src on `threads` threads, about target_s of work.
-    A render has a fixed cost (per-thread images of the whole sensor, summed at the end), so the
-    per-source cost comes from two calibration renders of different sizes."""
+    """Rays/s of the oracle over the first sources of src on `threads` threads, about target_s of work:
+    renders of growing prefixes (at most 8x per step, aiming at 0.8 target_s) until one takes at least
+    half the target; the last one is the measurement."""
     def timed(n):
         t0 = time.perf_counter()
         o.render(src[:n], scene.rays_per_src, n_threads=threads, want_float=False)
         return time.perf_counter() - t0
-    n1 = max(1, threads)
-    t1 = timed(n1)
-    n2 = min(len(src), 4 * n1)
-    t2 = timed(n2)
-    per_src = max((t2 - t1) / max(n2 - n1, 1), t2 / n2 * 0.05, 1e-6)
-    n = int(min(len(src), max(n2, target_s / per_src)))
-    dt = timed(n)
+    n = min(len(src), max(1, threads))
+    while True:
+        dt = timed(n)
+        if dt >= 0.5 * target_s or n >= len(src):
+            break
+        n = min(len(src), max(n + 1, int(n * min(8.0, 0.8 * target_s / max(dt, 1e-3)))))
     rays = n * scene.rays_per_src
     return rays / dt, (f"first {n} of {len(src)} sources x {scene.rays_per_src} rays ({rays} rays, {dt:.1f} s, "
                        f"{threads} thread{'s' if threads > 1 else ''})")
