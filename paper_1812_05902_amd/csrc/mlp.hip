@@ -229,12 +229,13 @@ constexpr int kRpB5 = kRpW5 + kOut * kHidden;   // b5 [6]
 constexpr int kRpLoss = kRpB5 + kOut;           // sum of squared errors
 static_assert(kRpLoss < kTrainPartStride, "row-block record");
 
-constexpr int kTrRows = 64;  // rows per k_train_rows block; eight waves own 32 units each
+constexpr int kTrRows = kTrainBlockRows;  // rows per k_train_rows block; eight waves own 32 units each
+constexpr int kTrTiles = kTrRows / 16;     // 16-row tiles per block
 
 // Accumulators of a 64-row x 32-unit slab: [unit tile j][row tile i], lane (r, kg) holding units
 // 16 j + 4 kg + t of row 16 i + r (the transposed-product layout of k_mlp_infer).
 struct Slab {
-    floatx4 v[2][4];
+    floatx4 v[2][kTrTiles];
 };
 
 // The wave's 32 rows of a [256][256] bf16 weight matrix (output units wave * 32 .. + 31, k
@@ -270,11 +271,11 @@ __device__ __forceinline__ void slab_product(Slab &acc, const WFrag &w, const un
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) acc.v[j][i] = w.b[j];
+        for (int i = 0; i < kTrTiles; ++i) acc.v[j][i] = w.b[j];
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
+        for (int i = 0; i < kTrTiles; ++i) {
             const bf16x8 fa = *(const bf16x8 *)(act + (16 * i + r) * kActStride + 8 * kg + 32 * k);
 #pragma unroll
             for (int j = 0; j < 2; ++j)
@@ -285,8 +286,8 @@ __device__ __forceinline__ void slab_product(Slab &acc, const WFrag &w, const un
 
 // bf16 values of a slab (of g applied to it when GELU) into LDS [row][unit] and, when T is given,
 // into T [unit][ldt] (the transposed layout of the weight-gradient products).  Within each block
-// of 64 rows, T holds row 16 i + r at column 4 r + i, so that a lane's four row tiles are one
-// 8-byte store; the weight-gradient products sum over rows and read both of their operands in this
+// of kTrRows rows, T holds row 16 i + r at column kTrTiles r + i, so that a lane's row tiles are
+// one store; the weight-gradient products sum over rows and read both of their operands in this
 // same order, so the permutation only reorders the terms of their sums.
 template <bool GELU>
 __device__ __forceinline__ void slab_store(const Slab &v, unsigned short *act, unsigned short *__restrict__ T,
@@ -294,10 +295,10 @@ __device__ __forceinline__ void slab_store(const Slab &v, unsigned short *act, u
 {
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
-        unsigned short b[4][4];  // [row tile i][unit t]
+        unsigned short b[kTrTiles][4];  // [row tile i][unit t]
         const int u = wave * 32 + 16 * j + 4 * kg;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
+        for (int i = 0; i < kTrTiles; ++i) {
 #pragma unroll
             for (int t = 0; t < 4; ++t) b[i][t] = bf16_bits(GELU ? gelu(v.v[j][i][t]) : v.v[j][i][t]);
             uint2 w;
@@ -308,10 +309,17 @@ __device__ __forceinline__ void slab_store(const Slab &v, unsigned short *act, u
         if (T) {
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
-                uint2 w;
-                w.x = (unsigned)b[0][t] | ((unsigned)b[1][t] << 16);
-                w.y = (unsigned)b[2][t] | ((unsigned)b[3][t] << 16);
-                *(uint2 *)(T + (size_t)(u + t) * ldt + row0 + 4 * r) = w;
+                unsigned short *d = T + (size_t)(u + t) * ldt + row0 + kTrTiles * r;
+                if (kTrTiles == 4) {
+                    uint2 w;
+                    w.x = (unsigned)b[0][t] | ((unsigned)b[1 % kTrTiles][t] << 16);
+                    w.y = (unsigned)b[2 % kTrTiles][t] | ((unsigned)b[3 % kTrTiles][t] << 16);
+                    *(uint2 *)d = w;
+                } else if (kTrTiles == 2) {
+                    *(unsigned *)d = (unsigned)b[0][t] | ((unsigned)b[1 % kTrTiles][t] << 16);
+                } else {
+                    *d = b[0][t];
+                }
             }
         }
     }
@@ -337,7 +345,12 @@ __device__ __forceinline__ void slab_row_sums(const Slab &v, float *__restrict__
     for (int j = 0; j < 2; ++j)
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-            const float s = row16_sum((v.v[j][0][t] + v.v[j][1][t]) + (v.v[j][2][t] + v.v[j][3][t]));
+            // the block's row tiles added pairwise in a fixed tree, then the 16 rows of a tile
+            float a = v.v[j][0][t];
+            if (kTrTiles == 2) a = v.v[j][0][t] + v.v[j][1 % kTrTiles][t];
+            if (kTrTiles == 4)
+                a = (v.v[j][0][t] + v.v[j][1 % kTrTiles][t]) + (v.v[j][2 % kTrTiles][t] + v.v[j][3 % kTrTiles][t]);
+            const float s = row16_sum(a);
             if (r == 0) out[wave * 32 + 16 * j + 4 * kg + t] = s;
         }
 }
@@ -379,13 +392,13 @@ __global__ void __launch_bounds__(512, 1) k_train_rows(const float *__restrict__
 #pragma unroll
         for (int j = 0; j < 2; ++j)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) *(floatx4 *)zp(l, j, i) = v.v[j][i];
+            for (int i = 0; i < kTrTiles; ++i) *(floatx4 *)zp(l, j, i) = v.v[j][i];
     };
     auto unpark = [&](Slab &v, int l) {
 #pragma unroll
         for (int j = 0; j < 2; ++j)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) v.v[j][i] = *(const floatx4 *)zp(l, j, i);
+            for (int i = 0; i < kTrTiles; ++i) v.v[j][i] = *(const floatx4 *)zp(l, j, i);
     };
     // inputs, targets and layer 1's parameters first, then the weights of layer 2
     float xv = 0.0f, tv = 0.0f;
@@ -419,12 +432,12 @@ __global__ void __launch_bounds__(512, 1) k_train_rows(const float *__restrict__
 #pragma unroll
         for (int j = 0; j < 2; ++j)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) z.v[j][i] = b1[j];
+            for (int i = 0; i < kTrTiles; ++i) z.v[j][i] = b1[j];
 #pragma unroll
         for (int kk = 0; kk < 2; ++kk) {
             const int k = 4 * kk + kg;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
+            for (int i = 0; i < kTrTiles; ++i) {
                 const float xb = k < kIn ? xs[(16 * i + r) * kIn + k] : 0.0f;
 #pragma unroll
                 for (int j = 0; j < 2; ++j)
@@ -452,7 +465,7 @@ __global__ void __launch_bounds__(512, 1) k_train_rows(const float *__restrict__
     slab_product(dz, fw, act(0), r, kg);
     bf16x8 f5[8];
     float b5v[4];
-    if (wave < 4) {
+    if (wave < kTrTiles) {
 #pragma unroll
         for (int k = 0; k < 8; ++k) f5[k] = *(const bf16x8 *)(w5 + (size_t)r * kHidden + 8 * kg + 32 * k);
 #pragma unroll
@@ -470,7 +483,7 @@ __global__ void __launch_bounds__(512, 1) k_train_rows(const float *__restrict__
     slab_store<true>(dz, act(1), nullptr, ldt, row0, wave, r, kg);
     __syncthreads();
     // output layer (16 padded outputs x 16 rows per wave, waves 0..3), loss, dL/dy
-    if (wave < 4) {
+    if (wave < kTrTiles) {
         floatx4 acc = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
@@ -494,7 +507,12 @@ __global__ void __launch_bounds__(512, 1) k_train_rows(const float *__restrict__
         if (lane == 0) red[wave] = se;
     }
     __syncthreads();
-    if (threadIdx.x == 0) rp[kRpLoss] = (red[0] + red[1]) + (red[2] + red[3]);
+    if (threadIdx.x == 0) {
+        float l = red[0];
+        if (kTrTiles == 2) l = red[0] + red[1];
+        if (kTrTiles == 4) l = (red[0] + red[1]) + (red[2] + red[3]);
+        rp[kRpLoss] = l;
+    }
     Slab zn;  // the next backward layer's pre-activations, z3
     unpark(zn, 2);
     {   // W5 and b5 gradients, C[o][u] = sum over rows of dy[m][o] a4[m][u] (a4 as stored in bf16),
@@ -528,12 +546,12 @@ __global__ void __launch_bounds__(512, 1) k_train_rows(const float *__restrict__
 #pragma unroll
         for (int j = 0; j < 2; ++j)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) da.v[j][i] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+            for (int i = 0; i < kTrTiles; ++i) da.v[j][i] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int kk = 0; kk < 2; ++kk) {
             const int o = 4 * kk + kg;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
+            for (int i = 0; i < kTrTiles; ++i) {
                 const float yb = o < kOut ? dys[(16 * i + r) * kOut + o] : 0.0f;
 #pragma unroll
                 for (int j = 0; j < 2; ++j)
@@ -543,7 +561,7 @@ __global__ void __launch_bounds__(512, 1) k_train_rows(const float *__restrict__
 #pragma unroll
         for (int j = 0; j < 2; ++j)
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < kTrTiles; ++i)
 #pragma unroll
                 for (int t = 0; t < 4; ++t) dz.v[j][i][t] = da.v[j][i][t] * gelu_grad(dz.v[j][i][t]);
     }
@@ -564,7 +582,7 @@ __global__ void __launch_bounds__(512, 1) k_train_rows(const float *__restrict__
 #pragma unroll
         for (int j = 0; j < 2; ++j)
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < kTrTiles; ++i)
 #pragma unroll
                 for (int t = 0; t < 4; ++t) dz.v[j][i][t] *= gelu_grad(zl.v[j][i][t]);
         slab_row_sums(dz, rp + kRpB + l * kHidden, wave, r, kg);
@@ -577,7 +595,7 @@ __global__ void __launch_bounds__(512, 1) k_train_rows(const float *__restrict__
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < kTrTiles; ++i)
 #pragma unroll
             for (int t = 0; t < 4; ++t) dzf[(wave * 32 + 16 * j + 4 * kg + t) * kDz1Stride + 16 * i + r] = dz.v[j][i][t];
     __syncthreads();
@@ -602,11 +620,34 @@ __global__ void __launch_bounds__(512, 1) k_train_rows(const float *__restrict__
 
 // Weight-gradient products of the three hidden layers, rows split into slices:
 // part[l][z][n][k] = sum over rows m of slice z of dzT_l[n][m] aT_(l-1)[k][m] (both bf16,
-// [unit][ld] with the rows contiguous).  Grid (4, 4, 3 * nsplit), 64 x 64 output tiles, four waves
-// of 32 x 32.  Block (0, 0, 0) also advances the step counter when one is given.
-__global__ void __launch_bounds__(256) k_train_dw(MlpTrain tb, int64_t ldt, int64_t chunk, int nsplit,
+// [unit][ld] with the rows contiguous).  Grid (4, 4, 3 * nsplit + extra), 64 x 64 output tiles, four
+// waves of 32 x 32.  Block (0, 0, 0) also advances the step counter when one is given.  The blocks
+// of the extra z layers each add up a group of kRowGroup row-block records of k_train_rows, in
+// block order, into one group record (so that the update adds a few group records per parameter
+// instead of every row block's).
+constexpr int kRowGroup = 16;
+constexpr int kRowChunks = (kRpLoss + 256) / 256;  // 256-column chunks of a record
+
+__global__ void __launch_bounds__(256) k_train_dw(MlpTrain tb, int64_t ldt, int64_t chunk, int nsplit, int nblocks,
                                                   int *step_advance)
 {
+    if ((int)blockIdx.z >= 3 * nsplit) {
+        // block e: record columns 256 (e mod kRowChunks) .. + 255 of group e / kRowChunks; the
+        // group's loads are all issued before the sum
+        const int e = ((int)blockIdx.z - 3 * nsplit) * 16 + (int)blockIdx.y * 4 + (int)blockIdx.x;
+        const int g = e / kRowChunks, c = (e % kRowChunks) * 256 + (int)threadIdx.x;
+        const int b0 = g * kRowGroup;
+        if (b0 >= nblocks || c > kRpLoss) return;
+        float v[kRowGroup];
+#pragma unroll
+        for (int b = 0; b < kRowGroup; ++b)
+            v[b] = b0 + b < nblocks ? tb.rowpart[(size_t)(b0 + b) * kTrainPartStride + c] : 0.0f;
+        float s = v[0];
+#pragma unroll
+        for (int b = 1; b < kRowGroup; ++b) s += v[b];
+        tb.rowsum[(size_t)g * kTrainPartStride + c] = s;
+        return;
+    }
     const int l = blockIdx.z / nsplit, z = blockIdx.z % nsplit;
     if (step_advance && blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && threadIdx.x == 0) *step_advance += 1;
     const unsigned short *A = tb.dzT[l] + (size_t)z * chunk;
@@ -667,7 +708,7 @@ __global__ void __launch_bounds__(256) k_train_dw(MlpTrain tb, int64_t ldt, int6
 // step t given; mode 2: Adam with t = *step (advanced by k_train_dw) and the cosine learning rate
 // of step t - 1 of `total`; modes 1, 2 then refresh the bf16 copies.  Thread 0 writes the batch's
 // mean squared error to loss_out[0] (mode 2: loss_out[t - 1]).
-__global__ void __launch_bounds__(256) k_train_update(MlpDevice d, MlpTrain tb, int nblocks, int nsplit,
+__global__ void __launch_bounds__(256) k_train_update(MlpDevice d, MlpTrain tb, int ngroups, int nsplit,
                                                       float inv_count, int mode, float lr, int t_fixed,
                                                       const int *__restrict__ step, int total, float lr_max,
                                                       float lr_min, float *__restrict__ loss_out)
@@ -677,7 +718,7 @@ __global__ void __launch_bounds__(256) k_train_update(MlpDevice d, MlpTrain tb, 
     if (mode == 2) t = *step;
     if (blockIdx.x == 0 && threadIdx.x < 64) {  // the loss: lane-strided partial sums, then a fixed tree
         float s = 0.0f;
-        for (int b = threadIdx.x; b < nblocks; b += 64) s += tb.rowpart[(size_t)b * kTrainPartStride + kRpLoss];
+        for (int b = threadIdx.x; b < ngroups; b += 64) s += tb.rowsum[(size_t)b * kTrainPartStride + kRpLoss];
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
         if (threadIdx.x == 0) loss_out[mode == 2 ? t - 1 : 0] = s * inv_count;
@@ -702,9 +743,8 @@ __global__ void __launch_bounds__(256) k_train_update(MlpDevice d, MlpTrain tb, 
 #pragma unroll 16
         for (int z = 0; z < nsplit; ++z) g += p[(size_t)z * kHidden * kHidden];
     } else {
-        const float *p = tb.rowpart + rec;
-#pragma unroll 16
-        for (int b = 0; b < nblocks; ++b) g += p[(size_t)b * kTrainPartStride];
+        const float *p = tb.rowsum + rec;
+        for (int b = 0; b < ngroups; ++b) g += p[(size_t)b * kTrainPartStride];
     }
     d.grad[q] = g;
     if (mode == 0) return;
@@ -779,10 +819,12 @@ int mlp_train_step(const MlpDevice &d, const MlpTrain &tb, const float *x, const
     int e = (int)hipGetLastError();
     if (e) return e;
     const int ns = dw_splits(rows);
-    hipLaunchKernelGGL(k_train_dw, dim3(kHidden / 64, kHidden / 64, (unsigned)(3 * ns)), dim3(256), 0, s, tb,
-                       tb.rows_cap, (int64_t)(rows / ns), ns, mode == 2 ? step_dev : (int *)nullptr);
+    const int ngroups = (nblocks + kRowGroup - 1) / kRowGroup;
+    hipLaunchKernelGGL(k_train_dw, dim3(kHidden / 64, kHidden / 64, (unsigned)(3 * ns + (ngroups * kRowChunks + 15) / 16)),
+                       dim3(256), 0, s, tb, tb.rows_cap, (int64_t)(rows / ns), ns, nblocks,
+                       mode == 2 ? step_dev : (int *)nullptr);
     if ((e = (int)hipGetLastError())) return e;
-    hipLaunchKernelGGL(k_train_update, dim3(blocks_for(kParams)), dim3(256), 0, s, d, tb, nblocks, ns,
+    hipLaunchKernelGGL(k_train_update, dim3(blocks_for(kParams)), dim3(256), 0, s, d, tb, ngroups, ns,
                        1.0f / (float)(rows * kOut), mode, lr, step, (const int *)step_dev, total, lr_max, lr_min,
                        loss_out);
     return (int)hipGetLastError();

@@ -34,13 +34,15 @@ struct MlpDevice {
 
 // Buffers of a training step for batches of up to rows_cap rows (a multiple of 64).
 constexpr int kTrainPartStride = 4224;  // floats per 64-row block record (row sums of the small gradients)
+constexpr int kTrainBlockRows = 16;     // rows per block of the training pass's row kernel
 constexpr int kMaxDwSplits = 16;        // row slices of the weight-gradient products
 struct MlpTrain {
     int64_t rows_cap;
     unsigned short *aT[3];   // activations a1, a2, a3 (bf16) transposed: [256][rows_cap]
     unsigned short *dzT[3];  // errors dz2, dz3, dz4 (bf16) transposed: [256][rows_cap]
     float *zbuf;             // pre-activations of layers 1..4: [4][rows_cap][256] f32
-    float *rowpart;          // [rows_cap / 64][kTrainPartStride]
+    float *rowpart;          // [rows_cap / kTrainBlockRows][kTrainPartStride]
+    float *rowsum;           // [groups of 16 row blocks][kTrainPartStride]
     float *dwpart;           // [3][kMaxDwSplits][256][256]
 };
 

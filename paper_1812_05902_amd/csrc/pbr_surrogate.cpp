@@ -175,7 +175,8 @@ void layout_persistent(pbr_surrogate *s, Carve &c, int64_t R, int64_t chunk)
         s->tb.dzT[l] = c.take<unsigned short>(H * R * 2);
     }
     s->tb.zbuf = c.take<float>((size_t)4 * R * H * 4);
-    s->tb.rowpart = c.take<float>((size_t)(R / 64) * pbr::kTrainPartStride * 4);
+    s->tb.rowpart = c.take<float>((size_t)(R / pbr::kTrainBlockRows) * pbr::kTrainPartStride * 4);
+    s->tb.rowsum = c.take<float>((size_t)((R / pbr::kTrainBlockRows + 15) / 16) * pbr::kTrainPartStride * 4);
     s->tb.dwpart = c.take<float>((size_t)3 * pbr::kMaxDwSplits * H * H * 4);
     s->x = c.take<float>(R * 6 * 4);
     s->y = c.take<float>(R * 6 * 4);
