@@ -403,9 +403,15 @@ def bench_tomo(args):
         pbr.pbr_read_image(r.ctx, pbr.PBR_FMT_U16, out16, 0.0)
         return st
 
-    legs = [("fp32", rn, 0)] + ([("shock_fp64", rc, pbr.PBR_PREC_SHOCK_FP64)] if extra else [])
+    legs = [("fp32", rn, 0)] + ([("shock_fp64", rc, pbr.PBR_PREC_SHOCK_FP64),
+                                 ("shock_fp64_tight", rc, pbr.PBR_PREC_SHOCK_FP64)] if extra else [])
     res = {}
+    cal_tight = None
     for name, r, flags in legs:
+        if name == "shock_fp64_tight":
+            # a tolerance below FP32's error in the steep bricks: some bricks take FP64 steps
+            cal_tight = r.calibrate_precision(sc.ds, tol_px=1e-7)
+            print(f"calibration at 1e-7 px: {cal_tight}", file=sys.stderr, flush=True)
         for _ in range(args.warmup):
             step(r, flags, False)
         torch.cuda.synchronize()
@@ -450,6 +456,11 @@ def bench_tomo(args):
                              "field_layout": "cells", "fp64_bricks": cal["n_fp64"], "steep_bricks": cal["n_steep"],
                              "calibration_max_err_px": cal["max_err_px"],
                              "rkn_steps_fp64": res["shock_fp64"][4]["rkn_steps_fp64"]}
+        st_t = res["shock_fp64_tight"][4]
+        out["shock_fp64_tight"] = {"rays_per_s": sc.n_rays * args.steps / res["shock_fp64_tight"][0],
+                                   "field_layout": "cells", "calibration_tol_px": 1e-7,
+                                   "fp64_bricks": cal_tight["n_fp64"], "steep_bricks": cal_tight["n_steep"],
+                                   "rkn_steps_fp64": st_t["rkn_steps_fp64"], "rkn_steps": st_t["rkn_steps"]}
         out["measured_peaks"] = peaks
         out["roofline"]["frac_of_measured_fp32_fma_rate"] = achieved / peaks["fp32_fma_TFLOPs"]
         tb = bench_turbulence(args, steps=10, warmup=2, peaks=peaks)

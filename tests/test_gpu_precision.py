@@ -110,6 +110,24 @@ def test_tomo_piv_shock_full_grid_sampled(torch):
           f"{st['rays'] / st['trace_ms'] * 1e3:.3e} rays/s, fp64 steps {st['rkn_steps_fp64']}")
     assert np.quantile(d, 0.99) <= 2e-5
     assert d.max() <= 1e-4
+    # a tolerance below what FP32 reaches in the steep bricks flags some of them, so that the mixed
+    # kernel takes FP64 steps at the full grid: same rays, same bars
+    rep2 = r.calibrate_precision(sc.ds, tol_px=1e-7, steep_frac=0.1)
+    st2 = r.emit_and_trace(src, sc.rays_per_src, sc.ray_seed, sc.ds,
+                           pbr.PBR_CLEAR_FIRST | pbr.PBR_RECORD_EXITS | pbr.PBR_PREC_SHOCK_FP64, stats=True)
+    rec2 = r.read_ray_exits()
+    assert np.array_equal(rec2["ray_id"], rec["ray_id"])
+    same2 = rec2["status"] == ref["status"]
+    assert (~same2).sum() <= 1
+    both2 = same2 & (rec2["status"] == 0)
+    d2 = np.abs(rec2["sensor_px"][both2] - ref["sensor_px"][both2]).max(axis=1)
+    print(f"calibrated at 1e-7 px: {rep2['n_fp64']} of {rep2['n_steep']} steep bricks FP64, "
+          f"{st2['rkn_steps_fp64']} FP64 steps of {st2['rkn_steps']}; max {d2.max():.3e} px, "
+          f"{st2['rays'] / st2['trace_ms'] * 1e3:.3e} rays/s")
+    assert rep2["n_fp64"] > 0 and st2["rkn_steps_fp64"] > 0
+    assert abs(st2["rkn_steps"] - st["rkn_steps"]) <= 1e-6 * st["rkn_steps"]  # a few exits a step apart
+    assert np.quantile(d2, 0.99) <= 2e-5
+    assert d2.max() <= 1e-4
 
 
 def test_tomo_piv_full_image_node_layout_sampled(torch):
