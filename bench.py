@@ -368,13 +368,11 @@ def bench_tomo(args):
     sc = inputs.tomo_piv_shock()
     t0 = time.perf_counter()
     rho = inputs.density(sc)
-    # the FP32 leg takes the node layout unless told otherwise (faster on this fine grid); the
-    # precision calibration and the shock-FP64 leg need the per-cell field
+    # the node layout unless told otherwise (faster on this fine grid); the shock-FP64 legs use the
+    # same field after the precision calibration
     layout = "cells" if args.field_layout == "cells" else "nodes"
     rn = pbr.Renderer.from_scene(sc, rho=rho, nodes=layout == "nodes", rays_per_chunk=args.rays_per_chunk)
-    rc = None
-    if extra:
-        rc = rn if layout == "cells" else pbr.Renderer.from_scene(sc, rho=rho, rays_per_chunk=args.rays_per_chunk)
+    rc = rn if extra else None
     rho_cpu = rho if not args.no_cpu_baseline else None
     del rho
     src_np = inputs.sources(sc)
@@ -453,12 +451,12 @@ def bench_tomo(args):
     }
     if extra:
         out["shock_fp64"] = {"rays_per_s": sc.n_rays * args.steps / res["shock_fp64"][0],
-                             "field_layout": "cells", "fp64_bricks": cal["n_fp64"], "steep_bricks": cal["n_steep"],
+                             "field_layout": layout, "fp64_bricks": cal["n_fp64"], "steep_bricks": cal["n_steep"],
                              "calibration_max_err_px": cal["max_err_px"],
                              "rkn_steps_fp64": res["shock_fp64"][4]["rkn_steps_fp64"]}
         st_t = res["shock_fp64_tight"][4]
         out["shock_fp64_tight"] = {"rays_per_s": sc.n_rays * args.steps / res["shock_fp64_tight"][0],
-                                   "field_layout": "cells", "calibration_tol_px": 1e-7,
+                                   "field_layout": layout, "calibration_tol_px": 1e-7,
                                    "fp64_bricks": cal_tight["n_fp64"], "steep_bricks": cal_tight["n_steep"],
                                    "rkn_steps_fp64": st_t["rkn_steps_fp64"], "rkn_steps": st_t["rkn_steps"]}
         out["measured_peaks"] = peaks

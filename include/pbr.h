@@ -207,9 +207,9 @@ int pbr_set_density_field(pbr_ctx *ctx, const float *rho_dev, int nx, int ny, in
  * sample lies in directly (a dedicated kernel variant at four waves per SIMD).  Same arguments,
  * validation and results (to float32 rounding) as pbr_set_density_field; workspace
  * pbr_field_workspace_bytes_nodes: 16 bytes per node plus the brick tables, each part rounded up to
- * 256 bytes.  Lane refill (PBR_LANE_REFILL) and shock FP64 steps (PBR_PREC_SHOCK_FP64,
- * pbr_calibrate_precision) need the per-cell field and return STATE with a node-layout field;
- * batches take either layout, image by image. */
+ * 256 bytes.  Lane refill (PBR_LANE_REFILL) needs the per-cell field and returns STATE with a
+ * node-layout field; the precision calibration and shock FP64 steps take either layout, and so do
+ * batches, image by image. */
 size_t pbr_field_workspace_bytes_nodes(int nx, int ny, int nz);
 int pbr_set_density_field_nodes(pbr_ctx *ctx, const float *rho_dev, int nx, int ny, int nz,
                                 const double origin[3], const double spacing[3], double K,

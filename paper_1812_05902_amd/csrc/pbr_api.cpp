@@ -551,8 +551,8 @@ int emit_and_trace_impl(pbr_ctx *ctx, const float *src_dev, int64_t n_src, int32
                             PBR_SURROGATE | PBR_LANE_REFILL | PBR_SOURCE_SUMS | PBR_MIE | PBR_SOURCE_ORDER))
         return fail(ctx, PBR_ERR_ARG, "unknown flag bits 0x%x", flags);
     if ((flags & PBR_MIE) && !ctx->mie) return fail(ctx, PBR_ERR_STATE, "no Mie table set (pbr_set_mie)");
-    if (ctx->layout.nodes && (flags & (PBR_LANE_REFILL | PBR_PREC_SHOCK_FP64)))
-        return fail(ctx, PBR_ERR_STATE, "lane refill and shock FP64 steps need the per-cell field (pbr_set_density_field)");
+    if (ctx->layout.nodes && (flags & PBR_LANE_REFILL))
+        return fail(ctx, PBR_ERR_STATE, "lane refill needs the per-cell field (pbr_set_density_field)");
     if (flags & PBR_SOURCE_SUMS) {
         if (!ctx->src_sums) return fail(ctx, PBR_ERR_STATE, "no per-source sums set (pbr_set_source_sums)");
         if (n_src > ctx->src_sums_cap)
@@ -680,7 +680,6 @@ int pbr_calibrate_precision(pbr_ctx *ctx, double tol_px, double steep_frac, int3
     int r = derive(ctx, &d);
     if (r) return r;
     if (ctx->has_chain) return fail(ctx, PBR_ERR_STATE, "precision calibration needs the singlet (an optical chain is set)");
-    if (ctx->layout.nodes) return fail(ctx, PBR_ERR_STATE, "precision calibration needs the per-cell field");
     if (!(tol_px >= 0.0) || !std::isfinite(tol_px)) return fail(ctx, PBR_ERR_ARG, "tol_px must be finite and >= 0");
     if (!(steep_frac >= 0.0 && steep_frac <= 1.0)) return fail(ctx, PBR_ERR_ARG, "steep_frac must lie in [0, 1]");
     if (rays_per_brick < 1 || rays_per_brick > 256) return fail(ctx, PBR_ERR_ARG, "rays_per_brick must lie in [1, 256]");

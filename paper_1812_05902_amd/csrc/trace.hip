@@ -871,7 +871,7 @@ __device__ __forceinline__ bool brick_is_fp64(const TraceParams &P, const int c[
 
 // One step in FP64 from the FP32 state: T = Tr + dT is carried in double through the step, then
 // split again into a float hi/lo pair.
-template <bool FULL>
+template <bool FULL, bool NODES>
 __device__ __forceinline__ void rkn_step_fp64(const TraceParams &P, CellCache &cc, int c[3], double fd[3],
                                               float Tr[3], float dT[3], double lam)
 {
@@ -879,7 +879,7 @@ __device__ __forceinline__ void rkn_step_fp64(const TraceParams &P, CellCache &c
     const StepGeom<double> sg64 = step_geom<double>(P);
 #pragma unroll
     for (int a = 0; a < 3; ++a) T64[a] = (double)Tr[a] + (double)dT[a];
-    rkn_step<double, FULL>(P, cc, c, fd, T64, d64, sg64, lam);
+    rkn_step<double, FULL, false, NODES>(P, cc, c, fd, T64, d64, sg64, lam);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const double T = T64[a] + d64[a];
@@ -889,6 +889,7 @@ __device__ __forceinline__ void rkn_step_fp64(const TraceParams &P, CellCache &c
 }
 
 // trace_box<float> with the step precision chosen per step from the brick of the current cell.
+template <bool NODES>
 __device__ __forceinline__ int trace_box_mixed(const TraceParams &P, CellCache &cc, int c[3], double fd[3],
                                                float Tr[3], float dT[3], bool *limited, int *n64)
 {
@@ -919,8 +920,8 @@ __device__ __forceinline__ int trace_box_mixed(const TraceParams &P, CellCache &
             if (ax >= 0 && lam <= 1.0f) {
                 const bool up = (pick3<float>(Tr, ax) + pick3<float>(dT, ax)) > 0.0f;
                 if (lam > 0.0f) {
-                    if (brick_is_fp64(P, c)) { rkn_step_fp64<false>(P, cc, c, fd, Tr, dT, (double)lam); ++*n64; }
-                    else rkn_step<float, false>(P, cc, c, fd, Tr, dT, sg, lam);
+                    if (brick_is_fp64(P, c)) { rkn_step_fp64<false, NODES>(P, cc, c, fd, Tr, dT, (double)lam); ++*n64; }
+                    else rkn_step<float, false, false, NODES>(P, cc, c, fd, Tr, dT, sg, lam);
                     ++steps;
                 }
                 const float Tn[3] = {Tr[0] + dT[0], Tr[1] + dT[1], Tr[2] + dT[2]};
@@ -945,17 +946,17 @@ __device__ __forceinline__ int trace_box_mixed(const TraceParams &P, CellCache &
                 continue;
             }
         }
-        if (brick_is_fp64(P, c)) { rkn_step_fp64<true>(P, cc, c, fd, Tr, dT, 1.0); ++*n64; }
-        else rkn_step<float, true>(P, cc, c, fd, Tr, dT, sg, 1.0f);
+        if (brick_is_fp64(P, c)) { rkn_step_fp64<true, NODES>(P, cc, c, fd, Tr, dT, 1.0); ++*n64; }
+        else rkn_step<float, true, false, NODES>(P, cc, c, fd, Tr, dT, sg, 1.0f);
         if (++steps > P.max_steps) { *limited = true; return steps; }
     }
 }
 
+template <bool NODES>
 __global__ void __launch_bounds__(256) k_box_mixed(TraceParams P, RayState *__restrict__ st, int64_t n,
                                                    const int *__restrict__ list,
                                                    const unsigned long long *__restrict__ count)
 {
-    if (P.node_layout) return;  // cell records only (the host never launches it otherwise)
     __shared__ unsigned long long s64;
     if (threadIdx.x == 0) s64 = 0ull;
     __syncthreads();
@@ -969,7 +970,7 @@ __global__ void __launch_bounds__(256) k_box_mixed(TraceParams P, RayState *__re
             CellCache cc;
             cc.ix = -1;
             bool limited = false;
-            const int steps = trace_box_mixed(P, cc, r.c, r.fd, Tr, dT, &limited, &n64);
+            const int steps = trace_box_mixed<NODES>(P, cc, r.c, r.fd, Tr, dT, &limited, &n64);
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 const double T = (double)Tr[a] + (double)dT[a];
@@ -989,11 +990,11 @@ __global__ void __launch_bounds__(256) k_box_mixed(TraceParams P, RayState *__re
 // uniform point of the brick, aimed at a uniform point of the aperture, and is integrated over
 // n_steps full steps in FP32 and in FP64 from the same state.  The two results are compared where
 // they matter on the sensor: the apparent source point on the focused plane, times |M| / pitch.
+template <bool NODES>
 __global__ void __launch_bounds__(256) k_calibrate(TraceParams P, const int *__restrict__ bricks,
                                                    int n_steps, uint64_t seed, double z_focus,
                                                    double px_per_m, float *__restrict__ err)
 {
-    if (P.node_layout) return;  // cell records only (the host never launches it otherwise)
     __shared__ unsigned s_err;
     if (threadIdx.x == 0) s_err = 0u;
     __syncthreads();
@@ -1029,7 +1030,7 @@ __global__ void __launch_bounds__(256) k_calibrate(TraceParams P, const int *__r
     CellCache cc;
     cc.ix = -1;
     float G0[3];
-    const float n0 = sample_field<float>(P, cc, c, f, G0);
+    const float n0 = sample_field<float, false, false, NODES>(P, cc, c, f, G0);
     // FP32
     int c32[3] = {c[0], c[1], c[2]};
     double fd32[3] = {fd[0], fd[1], fd[2]};
@@ -1041,7 +1042,7 @@ __global__ void __launch_bounds__(256) k_calibrate(TraceParams P, const int *__r
         dT[a] = (float)(T0 - (double)Tr[a]);
     }
     const StepGeom<float> sg = step_geom<float>(P);
-    for (int k = 0; k < n_steps; ++k) rkn_step<float, true>(P, cc, c32, fd32, Tr, dT, sg, 1.0f);
+    for (int k = 0; k < n_steps; ++k) rkn_step<float, true, false, NODES>(P, cc, c32, fd32, Tr, dT, sg, 1.0f);
     // FP64
     int c64[3] = {c[0], c[1], c[2]};
     double fd64[3] = {fd[0], fd[1], fd[2]};
@@ -1050,7 +1051,7 @@ __global__ void __launch_bounds__(256) k_calibrate(TraceParams P, const int *__r
 #pragma unroll
     for (int a = 0; a < 3; ++a) T64[a] = (double)n0 * u[a];
     cc.ix = -1;
-    for (int k = 0; k < n_steps; ++k) rkn_step<double, true>(P, cc, c64, fd64, T64, d64, sg64, 1.0);
+    for (int k = 0; k < n_steps; ++k) rkn_step<double, true, false, NODES>(P, cc, c64, fd64, T64, d64, sg64, 1.0);
     double q32[2], q64[2];
     {
         double Xa[3], Xb[3], da[3], db[3];
@@ -1707,8 +1708,12 @@ int launch_calibrate(const TraceParams &p, const int *bricks, int n_bricks, int 
                      hipStream_t stream)
 {
     if (n_bricks <= 0) return 0;
-    hipLaunchKernelGGL(k_calibrate, dim3((unsigned)n_bricks), dim3((unsigned)rays_per_brick), 0, stream, p,
-                       bricks, n_steps, seed, z_focus, px_per_m, err);
+    if (p.node_layout)
+        hipLaunchKernelGGL(k_calibrate<true>, dim3((unsigned)n_bricks), dim3((unsigned)rays_per_brick), 0, stream, p,
+                           bricks, n_steps, seed, z_focus, px_per_m, err);
+    else
+        hipLaunchKernelGGL(k_calibrate<false>, dim3((unsigned)n_bricks), dim3((unsigned)rays_per_brick), 0, stream, p,
+                           bricks, n_steps, seed, z_focus, px_per_m, err);
     return (int)hipGetLastError();
 }
 
@@ -1728,8 +1733,10 @@ int launch_trace_chunk(const TraceParams &p, RayState *st, int64_t first, int64_
         if (p.node_layout) hipLaunchKernelGGL(k_box64<true>, dim3(blocks), dim3(256), 0, stream, p, st, n, tl.idx, tl.count);
         else hipLaunchKernelGGL(k_box64<false>, dim3(blocks), dim3(256), 0, stream, p, st, n, tl.idx, tl.count);
     }
-    else if (prec == PREC_MIXED)
-        hipLaunchKernelGGL(k_box_mixed, dim3(blocks), dim3(256), 0, stream, p, st, n, tl.idx, tl.count);
+    else if (prec == PREC_MIXED) {
+        if (p.node_layout) hipLaunchKernelGGL(k_box_mixed<true>, dim3(blocks), dim3(256), 0, stream, p, st, n, tl.idx, tl.count);
+        else hipLaunchKernelGGL(k_box_mixed<false>, dim3(blocks), dim3(256), 0, stream, p, st, n, tl.idx, tl.count);
+    }
     else if (refill) {
         // persistent grid: five 256-thread blocks per compute unit, fewer for small chunks
         int dev = 0, ncu = 256;

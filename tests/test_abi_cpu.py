@@ -494,12 +494,15 @@ def test_node_layout_workspace_and_limits(lib):
         assert lib.pbr_set_optics(h, C.byref(_optics())) == pbr.PBR_OK
         assert lib.pbr_set_sensor(h, C.byref(_sensor()), FAKE) == pbr.PBR_OK
         assert lib.pbr_set_trace_workspace(h, FAKE, 1 << 20) == pbr.PBR_OK
-        for flag in (pbr.PBR_LANE_REFILL, pbr.PBR_PREC_SHOCK_FP64):
-            assert lib.pbr_emit_and_trace(h, FAKE, 1, 1, 0, 1e-4, flag, None) == pbr.PBR_ERR_STATE
-            assert "per-cell" in _err(lib, h)
+        assert lib.pbr_emit_and_trace(h, FAKE, 1, 1, 0, 1e-4, pbr.PBR_LANE_REFILL, None) == pbr.PBR_ERR_STATE
+        assert "per-cell" in _err(lib, h)
+        # shock FP64 steps and their calibration take the node layout (this context is host-only)
+        assert lib.pbr_emit_and_trace(h, FAKE, 1, 1, 0, 1e-4, pbr.PBR_PREC_SHOCK_FP64, None) == pbr.PBR_ERR_STATE
+        assert "host-only" in _err(lib, h)
         rep = pbr.pbr_precision_report()
         assert lib.pbr_calibrate_precision(h, 1e-3, 0.1, 8, 1, 1e-4, C.byref(rep)) == pbr.PBR_ERR_STATE
-        # the per-cell field lifts the restriction
+        assert "host-only" in _err(lib, h)
+        # the per-cell field lifts the lane-refill restriction
         assert _set_field(lib, h) == pbr.PBR_OK
         assert lib.pbr_emit_and_trace(h, FAKE, 1, 1, 0, 1e-4, pbr.PBR_LANE_REFILL, None) == pbr.PBR_ERR_STATE
         assert "host-only" in _err(lib, h)

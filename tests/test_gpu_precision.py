@@ -32,9 +32,10 @@ def _trace(r, sc, src, flags, nrec):
     return st, r.read_ray_exits(), pbr.u64_image_to_numpy(r.read_image())
 
 
-def test_calibration_finds_the_shock_bricks(torch):
+@pytest.mark.parametrize("nodes", [False, True], ids=["cells", "nodes"])
+def test_calibration_finds_the_shock_bricks(torch, nodes):
     sc = _shock()
-    r = pbr.Renderer.from_scene(sc)
+    r = pbr.Renderer.from_scene(sc, nodes=nodes)
     rep = r.calibrate_precision(sc.ds, tol_px=1e-3, steep_frac=0.1)
     print("calibration (tol 1e-3 px):", rep)
     assert rep["n_steep"] > 0
@@ -51,10 +52,11 @@ def test_calibration_finds_the_shock_bricks(torch):
     assert rep0["max_err_px"] == rep["max_err_px"]
 
 
-def test_mixed_precision_switches_only_the_step_precision(torch):
+@pytest.mark.parametrize("nodes", [False, True], ids=["cells", "nodes"])
+def test_mixed_precision_switches_only_the_step_precision(torch, nodes):
     sc = _shock()
     src = inputs.sources(sc)
-    r = pbr.Renderer.from_scene(sc)
+    r = pbr.Renderer.from_scene(sc, nodes=nodes)
     st32, rec32, img32 = _trace(r, sc, src, 0, sc.n_rays)
     # no bricks flagged: the shock-FP64 flag changes nothing
     r.calibrate_precision(sc.ds, tol_px=1e9)
@@ -163,6 +165,20 @@ def test_tomo_piv_full_image_node_layout_sampled(torch):
     assert both.sum() > 800
     assert np.quantile(d, 0.99) <= 2e-5
     assert d.max() <= 1e-4
+    # shock FP64 steps on the node layout: calibrated below what FP32 reaches in the steep bricks,
+    # the mixed kernel takes part of the steps in FP64; the sampled rays stay within the bars
+    rep2 = r.calibrate_precision(sc.ds, tol_px=1e-7, steep_frac=0.1)
+    st3 = r.emit_and_trace(src, sc.rays_per_src, sc.ray_seed, sc.ds,
+                           pbr.PBR_CLEAR_FIRST | pbr.PBR_RECORD_EXITS | pbr.PBR_PREC_SHOCK_FP64, stats=True)
+    rec3 = r.read_ray_exits()
+    same3 = rec3["status"] == ref["status"]
+    assert (~same3).sum() <= 1
+    both3 = same3 & (rec3["status"] == 0)
+    d3 = np.abs(rec3["sensor_px"][both3] - ref["sensor_px"][both3]).max(axis=1)
+    print(f"nodes, calibrated at 1e-7 px: {rep2['n_fp64']} of {rep2['n_steep']} steep bricks FP64, "
+          f"{st3['rkn_steps_fp64']} FP64 steps; max {d3.max():.3e} px, {st3['rays'] / st3['trace_ms'] * 1e3:.3e} rays/s")
+    assert rep2["n_fp64"] > 0 and st3["rkn_steps_fp64"] > 0
+    assert np.quantile(d3, 0.99) <= 2e-5 and d3.max() <= 1e-4
     # the same image with the sources taken in Morton order, as the benchmark traces them: the
     # same bits, records and counts
     r.set_source_order(r.morton_order(src))
