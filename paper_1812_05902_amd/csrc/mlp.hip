@@ -2,7 +2,7 @@
 // the input layer in FP32 (entry positions need more than bfloat16's 8 bits), the three hidden
 // 256 x 256 layers and the output layer as bfloat16 matrix products on the gfx950 matrix cores
 // (v_mfma_f32_16x16x32_bf16, FP32 accumulation); a training step in three kernels (the forward
-// pass, the loss and the back-propagated errors of 64 rows per block; the weight-gradient
+// pass, the loss and the back-propagated errors of 16 rows per block; the weight-gradient
 // products; the fixed-order gradient sums, Adam on the FP32 master weights and the bfloat16
 // shadow copies).
 #include "mlp_internal.h"
@@ -207,7 +207,7 @@ __global__ void __launch_bounds__(64 * kFuseWaves, 2) k_mlp_infer(const float *_
 // ---------------------------------------------------------------- training step
 //
 // One step over a batch of `rows` rows (a multiple of 64) in three launches:
-//   k_train_rows   one block per 64 rows: layer 1 .. output forward with every pre-activation parked
+//   k_train_rows   one block per 16 rows: layer 1 .. output forward with every pre-activation parked
 //                  in an L2-resident buffer, the loss and dL/dy, the back-propagated errors down to
 //                  layer 1, and per block the row sums the small gradients need (biases, W1, W5, b5,
 //                  the loss), the small ones as FP32 matrix-core products;
@@ -232,7 +232,7 @@ static_assert(kRpLoss < kTrainPartStride, "row-block record");
 constexpr int kTrRows = kTrainBlockRows;  // rows per k_train_rows block; eight waves own 32 units each
 constexpr int kTrTiles = kTrRows / 16;     // 16-row tiles per block
 
-// Accumulators of a 64-row x 32-unit slab: [unit tile j][row tile i], lane (r, kg) holding units
+// Accumulators of a kTrRows-row x 32-unit slab: [unit tile j][row tile i], lane (r, kg) holding units
 // 16 j + 4 kg + t of row 16 i + r (the transposed-product layout of k_mlp_infer).
 struct Slab {
     floatx4 v[2][kTrTiles];
@@ -264,7 +264,7 @@ __device__ __forceinline__ void load_wfrag(WFrag &w, const unsigned short *__res
     }
 }
 
-// Z^T = W A^T (+ bias) over K = 256 for this wave's 32 units and the 64 rows in `act` (LDS
+// Z^T = W A^T (+ bias) over K = 256 for this wave's 32 units and the kTrRows rows in `act` (LDS
 // [row][unit] bf16), with the weights already in `w`.
 __device__ __forceinline__ void slab_product(Slab &acc, const WFrag &w, const unsigned short *act, int r, int kg)
 {
@@ -337,7 +337,7 @@ __device__ __forceinline__ float row16_sum(float s)
     return s;
 }
 
-// Sum of a slab over its 64 rows, per unit: lanes r = 0 of each kg end with the sums of units
+// Sum of a slab over its kTrRows rows, per unit: lanes r = 0 of each kg end with the sums of units
 // 16 j + 4 kg + t; written to out[wave * 32 + unit].
 __device__ __forceinline__ void slab_row_sums(const Slab &v, float *__restrict__ out, int wave, int r, int kg)
 {

@@ -33,7 +33,7 @@ struct MlpDevice {
 };
 
 // Buffers of a training step for batches of up to rows_cap rows (a multiple of 64).
-constexpr int kTrainPartStride = 4224;  // floats per 64-row block record (row sums of the small gradients)
+constexpr int kTrainPartStride = 4224;  // floats per row-block record (row sums of the small gradients)
 constexpr int kTrainBlockRows = 16;     // rows per block of the training pass's row kernel
 constexpr int kMaxDwSplits = 16;        // row slices of the weight-gradient products
 struct MlpTrain {
