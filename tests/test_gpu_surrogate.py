@@ -185,6 +185,19 @@ def test_surrogate_in_the_trace(torch, trained):
     rel = np.linalg.norm(img_s - img_t) / np.linalg.norm(img_t)
     print(f"image rel L2 surrogate vs tracer {rel:.3g}")
     assert rel < 1e-2
+    # with the sources in a random order (chunks and waves made of other rays) every ray through the
+    # network or the tracer gives the same bits: image, records and counts
+    order = np.random.default_rng(5).permutation(len(ev))
+    r.set_source_order(torch.as_tensor(order))
+    st_o = r.emit_and_trace(ev, 100, 51, sc.ds,
+                            pbr.PBR_CLEAR_FIRST | pbr.PBR_RECORD_EXITS | pbr.PBR_SURROGATE | pbr.PBR_SOURCE_ORDER,
+                            stats=True)
+    assert np.array_equal(pbr.u64_image_to_numpy(r.read_image()).astype(np.float64), img_s)
+    rec_o = r.read_ray_exits()
+    for f in pbr.RAY_EXIT_DTYPE.names:
+        assert np.array_equal(rec_o[f], rec_s[f]), f
+    assert st_o["status"] == st_s["status"] and st_o["surrogate_rays"] == st_s["surrogate_rays"]
+    r.set_source_order(None)
     r.set_exit_recording(0, 1, 0)
 
 
