@@ -45,6 +45,7 @@ extern "C" {
 #define PBR_ERR_HIP       -3  /* a HIP runtime call failed (message names it) */
 #define PBR_ERR_WORKSPACE -4  /* a caller buffer is smaller than required */
 #define PBR_ERR_OVERFLOW  -5  /* the 64-bit fixed-point sensor could overflow */
+#define PBR_ERR_BOUNDS    -6  /* checked builds only: a trace kernel met an index outside its buffer */
 
 /* ---------------------------------------------------------------- per-ray status */
 #define PBR_RAY_DEPOSITED        0  /* reached the sensor; spot deposited */
@@ -178,6 +179,15 @@ const char *pbr_last_error(const pbr_ctx *ctx);
 
 /* Changes the stream later calls enqueue on. */
 int pbr_set_stream(pbr_ctx *ctx, void *hip_stream);
+
+/* 1 if this copy of the library is the checked build, 0 for the regular one.  The checked build
+ * (libpbr_checked.so, a debugging aid: same entry points, same results) tests the index of every
+ * device access of the trace kernels against its buffer: field gathers (per cell and per node),
+ * brick flags, sources, source-order entries, the Mie table, sensor pixels and per-source sums.
+ * An access that fails its test is counted, then clamped into its buffer or skipped, and
+ * pbr_emit_and_trace, pbr_emit_and_trace_noalloc and pbr_batch_run return PBR_ERR_BOUNDS with the
+ * count in the message after the work (they synchronise the stream to read it). */
+int pbr_checked_build(void);
 
 /* ---------------------------------------------------------------- inputs */
 

@@ -15,6 +15,9 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libpbr.so")
+# the checked build: the same library with index tests on the device accesses of the trace kernels
+CHECKED_LIB = os.path.join(HERE, "libpbr_checked.so")
+CHECKED_SOURCES = ["trace.hip", "pbr_api.cpp", "pbr_batch.cpp"]
 
 SOURCES = ["field_prep.hip", "trace.hip", "readout.hip", "mlp.hip", "probe.hip", "bos_map.hip", "piv_pair.hip",
            "pbr_api.cpp", "pbr_mie.cpp", "pbr_batch.cpp", "pbr_surrogate.cpp", "pbr_noalloc.cpp", "source_order.hip"]
@@ -35,12 +38,16 @@ def _hipcc() -> str:
 
 
 def build(verbose: bool = False) -> str:
-    os.makedirs(BUILD, exist_ok=True)
+    """Builds libpbr.so and the checked build libpbr_checked.so; returns the path of the first."""
+    checked_dir = os.path.join(BUILD, "checked")
+    os.makedirs(checked_dir, exist_ok=True)
     hipcc = _hipcc()
 
-    def compile_one(src):
-        obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-        cmd = [hipcc, "-x", "hip", *HIPCC_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    def compile_one(job):
+        src, checked = job
+        obj = os.path.join(checked_dir if checked else BUILD, os.path.splitext(src)[0] + ".o")
+        cmd = [hipcc, "-x", "hip", *HIPCC_FLAGS, *(["-DPBR_CHECKED=1"] if checked else []),
+               "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         r = subprocess.run(cmd, capture_output=True, text=True)
@@ -50,14 +57,20 @@ def build(verbose: bool = False) -> str:
             print(r.stderr, file=sys.stderr)
         return obj
 
-    with ThreadPoolExecutor(max_workers=4) as ex:
-        objs = list(ex.map(compile_one, SOURCES))
-    tmp = LIB + ".tmp"
-    cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, LIB)
+    # the two trace.hip compiles take most of the time: start them first
+    jobs = [("trace.hip", False), ("trace.hip", True)]
+    jobs += [(s, False) for s in SOURCES if s != "trace.hip"] + [(s, True) for s in CHECKED_SOURCES if s != "trace.hip"]
+    with ThreadPoolExecutor(max_workers=max(2, min(8, os.cpu_count() or 1))) as ex:
+        built = dict(zip(jobs, ex.map(compile_one, jobs)))
+    regular = [built[(s, False)] for s in SOURCES]
+    checked = [built[(s, s in CHECKED_SOURCES)] for s in SOURCES]
+    for objs, lib in ((regular, LIB), (checked, CHECKED_LIB)):
+        tmp = lib + ".tmp"
+        cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
+        os.replace(tmp, lib)
     return LIB
 
 

@@ -273,6 +273,11 @@ int pbr_set_stream(pbr_ctx *ctx, void *hip_stream)
     return PBR_OK;
 }
 
+int pbr_checked_build(void)
+{
+    return PBR_CHECKED;
+}
+
 size_t pbr_field_workspace_bytes(int nx, int ny, int nz)
 {
     if (nx < 2 || ny < 2 || nz < 2) return 0;
@@ -663,6 +668,15 @@ int emit_and_trace_impl(pbr_ctx *ctx, const float *src_dev, int64_t n_src, int32
         stats->box_ms = box;
         stats->box_launches = (uint64_t)n_chunks;
     }
+#if PBR_CHECKED
+    unsigned long long bad = 0;
+    e = (int)hipMemcpyAsync(&bad, ctx->counters + pbr::CNT_BAD_ACCESS, sizeof bad, hipMemcpyDeviceToHost, ctx->stream);
+    if (!e) e = (int)hipStreamSynchronize(ctx->stream);
+    if (e) return hip_fail(ctx, e, "read the checked-access counter");
+    if (bad)
+        return fail(ctx, PBR_ERR_BOUNDS, "checked build: %llu device accesses outside their buffers (clamped or skipped)",
+                    bad);
+#endif
     return PBR_OK;
 }
 

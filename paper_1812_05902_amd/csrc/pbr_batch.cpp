@@ -460,6 +460,18 @@ int pbr_batch_run(pbr_batch *b, pbr_batch_stats *stats)
             pbr_ctx *c = b->items[i].ctx;
             c->accum_rays = ((b->items[i].flags & PBR_CLEAR_FIRST) ? 0.0 : c->accum_rays) + (double)b->params[i].n_rays;
         }
+#if PBR_CHECKED
+        if ((e = (int)hipStreamSynchronize(b->stream)))
+            return bfail(b, PBR_ERR_HIP, "batch (stream synchronise): %s", hipGetErrorString((hipError_t)e));
+        for (size_t i = 0; i < b->items.size(); ++i) {
+            unsigned long long bad = 0;
+            e = (int)hipMemcpy(&bad, b->items[i].ctx->counters + pbr::CNT_BAD_ACCESS, sizeof bad, hipMemcpyDeviceToHost);
+            if (e) return bfail(b, PBR_ERR_HIP, "read counters: %s", hipGetErrorString((hipError_t)e));
+            if (bad)
+                return bfail(b, PBR_ERR_BOUNDS, "checked build: image %zu made %llu device accesses outside their "
+                             "buffers (clamped or skipped)", i, bad);
+        }
+#endif
         if (stats) {
             std::memset(stats, 0, sizeof *stats);
             e = (int)hipStreamSynchronize(b->stream);

@@ -6,6 +6,12 @@
 
 #include "../../include/pbr.h"
 
+// Checked builds (compiled with -DPBR_CHECKED=1) test the index of every device access of the
+// trace kernels against its buffer; regular builds leave the tests out.
+#ifndef PBR_CHECKED
+#define PBR_CHECKED 0
+#endif
+
 namespace pbr {
 
 // Counter block layout (uint64 slots in the context's device block).
@@ -16,6 +22,7 @@ enum : int {
     CNT_MAXPIX = PBR_NUM_STATUS + 2,      // largest accumulator value (readout)
     CNT_STEPS64 = PBR_NUM_STATUS + 3,     // Runge-Kutta steps taken in FP64 (mixed precision)
     CNT_SURR = PBR_NUM_STATUS + 4,        // rays whose box passage the surrogate network replaced
+    CNT_BAD_ACCESS = PBR_NUM_STATUS + 5,  // checked builds: device accesses found outside their buffer
     CNT_SLOTS = 16,
     CNT_QUEUE = 32                        // ray queue of the refill integration kernel (not a statistic)
 };

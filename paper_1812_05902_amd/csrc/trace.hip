@@ -27,6 +27,22 @@ __device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t k)
     return z ^ (z >> 31);
 }
 
+// Checked builds: the access that the caller is about to make is in range if ok; a failed test
+// is counted in the CNT_BAD_ACCESS slot, and the caller then clamps the index into its buffer or
+// skips the access.  Regular builds return true and compile the test and its fix-up out.
+__device__ __forceinline__ bool access_ok(const TraceParams &P, bool ok)
+{
+#if PBR_CHECKED
+    if (!ok && P.counters)
+        __hip_atomic_fetch_add(P.counters + CNT_BAD_ACCESS, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return ok;
+#else
+    (void)P;
+    (void)ok;
+    return true;
+#endif
+}
+
 // x clamped to [0, hi] in one instruction (for a bound that is not a constant the compiler emits a
 // max and a min); hi is uniform across the wave.
 __device__ __forceinline__ int clamp_index(int x, int hi)
@@ -140,6 +156,11 @@ __device__ __forceinline__ F sample_field(const TraceParams &P, CellCache &cc, c
     }
     // compare cell coordinates (no index arithmetic unless the cell changed)
     if ((ic[0] != cc.ix) | (ic[1] != cc.iy) | (ic[2] != cc.iz)) {
+        if (PBR_CHECKED && !access_ok(P, (unsigned)ic[0] <= (unsigned)nmax[0] && (unsigned)ic[1] <= (unsigned)nmax[1] &&
+                                             (unsigned)ic[2] <= (unsigned)nmax[2])) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) ic[a] = min(max(ic[a], 0), nmax[a]);
+        }
         if (NODES) gather_nodes(P, ic, cc);
         else {
             const int key = (ic[2] * (P.ny - 1) + ic[1]) * (P.nx - 1) + ic[0];
@@ -591,8 +612,9 @@ __device__ int chain_to_sensor(const TraceParams &P, const double R[3], const do
 __device__ __forceinline__ void initial_direction(const TraceParams &P, int64_t rid, double S[3], double u[3])
 {
     #pragma clang fp contract(off)
-    const int64_t s = rid / P.rays_per_src;
+    int64_t s = rid / P.rays_per_src;
     const int32_t j = (int32_t)(rid - s * P.rays_per_src);
+    if (PBR_CHECKED && !access_ok(P, s >= 0 && s < P.n_src)) s = s < 0 ? 0 : P.n_src - 1;
     const float4 sv = P.src[s];
     S[0] = (double)sv.x;
     S[1] = (double)sv.y;
@@ -618,7 +640,8 @@ __device__ __forceinline__ double mie_weight(const TraceParams &P, const double 
     double c = u[0] * P.laser[0] + u[1] * P.laser[1] + u[2] * P.laser[2];
     c = fmin(fmax(c, -1.0), 1.0);
     const double t = acos(c) / 3.14159265358979323846 * (double)(P.mie_n - 1);
-    const int i = min((int)floor(t), P.mie_n - 2);
+    int i = min((int)floor(t), P.mie_n - 2);
+    if (PBR_CHECKED && !access_ok(P, i >= 0)) i = 0;
     const double f = t - (double)i;
     return P.mie[i] * (1.0 - f) + P.mie[i + 1] * f;
 }
@@ -631,6 +654,7 @@ __device__ __forceinline__ int64_t ray_key(const TraceParams &P, int64_t q)
 {
     if (!P.order) return q;
     const int64_t k = q / P.rays_per_src;
+    if (PBR_CHECKED && !access_ok(P, k >= 0 && k < P.n_src)) return q;
     int64_t s = P.order[k];
     s = s < 0 ? 0 : (s >= P.n_src ? P.n_src - 1 : s);
     return s * P.rays_per_src + (q - k * P.rays_per_src);
@@ -866,6 +890,7 @@ __device__ __forceinline__ bool brick_is_fp64(const TraceParams &P, const int c[
     const int bx = min(max(c[0], 0), P.nx - 2) / kBrick;
     const int by = min(max(c[1], 0), P.ny - 2) / kBrick;
     const int bz = min(max(c[2], 0), P.nz - 2) / kBrick;
+    if (PBR_CHECKED && !access_ok(P, bx < P.nbx && by < P.nby && bz < P.nbz)) return true;
     return P.brick_fp64[((size_t)bz * P.nby + by) * P.nbx + bx] != 0;
 }
 
@@ -1137,7 +1162,7 @@ __device__ __forceinline__ void add_source_sums(const TraceParams &P, bool on, i
             vy += __shfl_xor(vy, o, 64);
             c += __shfl_xor(c, o, 64);
         }
-        if ((int)__lane_id() == lead) {
+        if ((int)__lane_id() == lead && (!PBR_CHECKED || access_ok(P, s0 >= 0 && s0 < P.n_src))) {
             pbr_source_sum *d = P.src_sums + s0;
             atomic_add_u64((unsigned long long *)&d->sum_x, (unsigned long long)vx);
             atomic_add_u64((unsigned long long *)&d->sum_y, (unsigned long long)vy);
@@ -1211,7 +1236,9 @@ __device__ __forceinline__ void finish_block(const TraceParams &P, const RayStat
     const int64_t rid = valid ? ray_key(P, first + i) : first + i;
     if (P.src_sums) add_source_sums(P, valid && status == PBR_RAY_DEPOSITED, rid, xpx, ypx);
     if (valid && status == PBR_RAY_DEPOSITED) {
-        const float4 sv = P.src[rid / P.rays_per_src];
+        int64_t s = rid / P.rays_per_src;
+        if (PBR_CHECKED && !access_ok(P, s >= 0 && s < P.n_src)) s = s < 0 ? 0 : P.n_src - 1;
+        const float4 sv = P.src[s];
         double w = sv.w > 0.0f ? (sv.w < 1.0f ? (double)sv.w : 1.0) : 0.0;  // weights in [0, 1]
         if ((FEAT & FEAT_MIE) && P.mie) {  // the ray's Mie factor, from its direction at the source
             double S0[3], u0[3];
@@ -1259,6 +1286,9 @@ __device__ __forceinline__ void finish_block(const TraceParams &P, const RayStat
         const int tx0 = sh.tx0, ty0 = sh.ty0;
         for (int q = threadIdx.x; q < TILE * TILE; q += blockDim.x) {
             const unsigned long long v = sh.tile[q];
+            if (PBR_CHECKED && v &&
+                !access_ok(P, (unsigned)(ty0 + q / TILE) < (unsigned)P.H && (unsigned)(tx0 + q % TILE) < (unsigned)P.W))
+                continue;
             if (v) atomic_add_u64(P.accum + (size_t)(ty0 + q / TILE) * (size_t)P.W + (tx0 + q % TILE), v);
         }
     }

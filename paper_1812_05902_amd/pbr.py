@@ -18,8 +18,10 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpbr.so")
+CHECKED_LIB_PATH = os.path.join(_HERE, "libpbr_checked.so")  # bounds-checked trace kernels
 
 PBR_OK, PBR_ERR_ARG, PBR_ERR_STATE, PBR_ERR_HIP, PBR_ERR_WORKSPACE, PBR_ERR_OVERFLOW = 0, -1, -2, -3, -4, -5
+PBR_ERR_BOUNDS = -6
 (PBR_RAY_DEPOSITED, PBR_RAY_OFF_SENSOR, PBR_RAY_BLOCKED_APERTURE, PBR_RAY_BLOCKED_LENS,
  PBR_RAY_TIR, PBR_RAY_STEP_LIMIT, PBR_RAY_MISSED) = range(7)
 PBR_NUM_STATUS = 7
@@ -35,7 +37,7 @@ PBR_NOALLOC_MAX_CHUNK = 1 << 20
 PBR_SURR_PARAMS = 200710
 PBR_FMT_RAW_U64, PBR_FMT_F32, PBR_FMT_U16 = 0, 1, 2
 
-EXPORTED = ["pbr_create", "pbr_destroy", "pbr_last_error", "pbr_set_stream",
+EXPORTED = ["pbr_create", "pbr_destroy", "pbr_last_error", "pbr_set_stream", "pbr_checked_build",
             "pbr_field_workspace_bytes", "pbr_trace_workspace_bytes", "pbr_set_trace_workspace",
             "pbr_set_density_field", "pbr_set_optics",
             "pbr_set_sensor", "pbr_get_derived", "pbr_set_exit_recording",
@@ -173,6 +175,7 @@ def load(path: str = LIB_PATH):
         "pbr_destroy": (None, [P]),
         "pbr_last_error": (C.c_char_p, [P]),
         "pbr_set_stream": (I, [P, P]),
+        "pbr_checked_build": (I, []),
         "pbr_field_workspace_bytes": (C.c_size_t, [I, I, I]),
         "pbr_trace_workspace_bytes": (C.c_size_t, [I64]),
         "pbr_set_trace_workspace": (I, [P, P, C.c_size_t]),

@@ -595,3 +595,16 @@ def test_source_order_entry_points_validate_before_device_work(lib):
         assert code == pbr.PBR_ERR_ARG and b"4 sources" in lib.pbr_last_error(ctx)
     finally:
         lib.pbr_destroy(ctx)
+
+
+def test_checked_build_has_the_same_entry_points(lib):
+    """libpbr_checked.so (index tests on the trace kernels' device accesses) exports every declared
+    function and says that it is the checked build; the regular library says that it is not."""
+    if not os.path.exists(pbr.CHECKED_LIB_PATH):
+        from paper_1812_05902_amd import build
+        build.build()
+    chk = C.CDLL(pbr.CHECKED_LIB_PATH)
+    for n in _declared():
+        assert hasattr(chk, n), n
+    assert chk.pbr_checked_build() == 1
+    assert lib.pbr_checked_build() == 0
