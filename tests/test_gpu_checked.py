@@ -36,3 +36,58 @@ def test_gpu_suite_on_the_checked_build():
     print(tail)
     assert r.returncode == 0, tail
     assert " passed" in r.stdout and "failed" not in r.stdout
+
+
+STEEP = r"""
+import sys
+sys.path.insert(0, sys.argv[1])
+import numpy as np
+from paper_1812_05902_amd import inputs, pbr
+lib = pbr.load(pbr.CHECKED_LIB_PATH)
+assert lib.pbr_checked_build() == 1
+n = 24
+org, sp = (-0.012, -0.012, 0.113), (1e-3, 1e-3, 1e-3)
+base = inputs.tiny_bos().replace(nx=n, ny=n, nz=n, origin=org, spacing=sp, rays_per_src=32)
+rng = np.random.default_rng(7)
+# (1) node-to-node noise up to 500 kg/m^3 (n - 1 up to 0.11, |grad n| ~ 100 / m: a step of one cell
+# bends ~0.05 cells off its straight line); (2) a jump 1.2 -> 500 kg/m^3 across one cell at x = 0
+noise = (1.2 + 500.0 * rng.random((n, n, n))).astype(np.float32)
+jump = np.full((n, n, n), 1.2, np.float32)
+jump[:, :, n // 2:] = 500.0
+# particles inside the box and dots in front of it
+inside = np.zeros((3000, 4), np.float32)
+inside[:, :3] = np.asarray(org) + rng.random((3000, 3)) * (n - 1) * np.asarray(sp)
+inside[:, 3] = 1.0
+dots = inputs.sources(base.replace(n_src=3000))
+runs = 0
+for name, rho in (("noise", noise), ("jump", jump)):
+    for nodes in (False, True):
+        for ds in (1e-3, 2.5e-3, 3e-4):
+            for flags in (0, pbr.PBR_PREC_FP64_ALL, pbr.PBR_LANE_REFILL):
+                if nodes and flags == pbr.PBR_LANE_REFILL:
+                    continue
+                for src in (inside, dots):
+                    r = pbr.Renderer.from_scene(base, rho=rho, nodes=nodes)
+                    r.set_exit_recording(0, 7, 1 << 14)
+                    st = r.emit_and_trace(src, 32, 11, ds, flags | pbr.PBR_CLEAR_FIRST | pbr.PBR_RECORD_EXITS,
+                                          stats=True)   # raises on PBR_ERR_BOUNDS
+                    assert st["rays"] == len(src) * 32 and sum(st["status"]) == st["rays"]
+                    runs += 1
+    print(name, "ok", flush=True)
+print("runs", runs)
+"""
+
+
+def test_steep_fields_stay_in_bounds_on_the_checked_build():
+    """Fields far steeper than any workload (per-node noise up to 500 kg/m^3, a 1.2 -> 500 kg/m^3
+    jump across one cell) with steps of 0.3, 1 and 2.5 cells, sources inside and in front of the
+    box, both layouts, FP32, FP64 and lane refill: paths bend far more than the face margin the
+    integration assumes, and every device access must still stay inside its buffer."""
+    assert os.path.exists(pbr.CHECKED_LIB_PATH)
+    print("checked build: steep fields in a child process", flush=True)
+    r = subprocess.run([sys.executable, "-u", "-c", STEEP, ROOT], capture_output=True, text=True, timeout=600,
+                       cwd=ROOT)
+    tail = r.stdout[-3000:] + r.stderr[-3000:]
+    print(tail)
+    assert r.returncode == 0, tail
+    assert "runs 60" in r.stdout
