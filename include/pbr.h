@@ -185,8 +185,9 @@ int pbr_set_stream(pbr_ctx *ctx, void *hip_stream);
  * device access of the trace kernels against its buffer: field gathers (per cell and per node),
  * brick flags, sources, source-order entries, the Mie table, sensor pixels and per-source sums.
  * An access that fails its test is counted, then clamped into its buffer or skipped, and
- * pbr_emit_and_trace, pbr_emit_and_trace_noalloc and pbr_batch_run return PBR_ERR_BOUNDS with the
- * count in the message after the work (they synchronise the stream to read it). */
+ * pbr_emit_and_trace, pbr_emit_and_trace_noalloc, pbr_calibrate_precision and pbr_batch_run return
+ * PBR_ERR_BOUNDS with the count in the message after the work (they synchronise the stream to read
+ * it). */
 int pbr_checked_build(void);
 
 /* ---------------------------------------------------------------- inputs */

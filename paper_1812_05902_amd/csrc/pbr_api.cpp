@@ -731,12 +731,24 @@ int pbr_calibrate_precision(pbr_ctx *ctx, double tol_px, double steep_frac, int3
         if (e) return hip_fail(ctx, e, "upload brick list");
         pbr::TraceParams P;
         fill_params(ctx, d, ds, &P);
+#if PBR_CHECKED
+        if ((e = pbr::launch_clear_u64(ctx->counters + pbr::CNT_BAD_ACCESS, 1, ctx->stream)))
+            return hip_fail(ctx, e, "clear the checked-access counter");
+#endif
         e = pbr::launch_calibrate(P, dev_list, ns, rays_per_brick, n_steps, seed, ctx->optics.z_focus,
                                   std::fabs(d.M) / ctx->sensor.pitch, dev_err, ctx->stream);
         if (e) return hip_fail(ctx, e, "calibration launch");
         e = (int)hipMemcpyAsync(err.data(), dev_err, (size_t)ns * 4, hipMemcpyDeviceToHost, ctx->stream);
         if (!e) e = (int)hipStreamSynchronize(ctx->stream);
         if (e) return hip_fail(ctx, e, "calibration");
+#if PBR_CHECKED
+        unsigned long long bad = 0;
+        e = (int)hipMemcpy(&bad, ctx->counters + pbr::CNT_BAD_ACCESS, sizeof bad, hipMemcpyDeviceToHost);
+        if (e) return hip_fail(ctx, e, "read the checked-access counter");
+        if (bad)
+            return fail(ctx, PBR_ERR_BOUNDS, "checked build: calibration made %llu device accesses outside their "
+                        "buffers (clamped or skipped)", bad);
+#endif
     }
     std::vector<unsigned char> flags((size_t)nb, 0);
     int64_t nf = 0;

@@ -63,11 +63,14 @@ runs = 0
 for name, rho in (("noise", noise), ("jump", jump)):
     for nodes in (False, True):
         for ds in (1e-3, 2.5e-3, 3e-4):
-            for flags in (0, pbr.PBR_PREC_FP64_ALL, pbr.PBR_LANE_REFILL):
+            for flags in (0, pbr.PBR_PREC_FP64_ALL, pbr.PBR_PREC_SHOCK_FP64, pbr.PBR_LANE_REFILL):
                 if nodes and flags == pbr.PBR_LANE_REFILL:
                     continue
                 for src in (inside, dots):
                     r = pbr.Renderer.from_scene(base, rho=rho, nodes=nodes)
+                    if flags == pbr.PBR_PREC_SHOCK_FP64:   # calibration traces the steep bricks too
+                        rep = r.calibrate_precision(ds, tol_px=1e-6, steep_frac=0.1, rays_per_brick=64)
+                        assert rep["n_steep"] > 0
                     r.set_exit_recording(0, 7, 1 << 14)
                     st = r.emit_and_trace(src, 32, 11, ds, flags | pbr.PBR_CLEAR_FIRST | pbr.PBR_RECORD_EXITS,
                                           stats=True)   # raises on PBR_ERR_BOUNDS
@@ -81,8 +84,9 @@ print("runs", runs)
 def test_steep_fields_stay_in_bounds_on_the_checked_build():
     """Fields far steeper than any workload (per-node noise up to 500 kg/m^3, a 1.2 -> 500 kg/m^3
     jump across one cell) with steps of 0.3, 1 and 2.5 cells, sources inside and in front of the
-    box, both layouts, FP32, FP64 and lane refill: paths bend far more than the face margin the
-    integration assumes, and every device access must still stay inside its buffer."""
+    box, both layouts, FP32, FP64, calibrated mixed precision and lane refill: paths bend far more
+    than the face margin the integration assumes, and every device access must still stay inside
+    its buffer."""
     assert os.path.exists(pbr.CHECKED_LIB_PATH)
     print("checked build: steep fields in a child process", flush=True)
     r = subprocess.run([sys.executable, "-u", "-c", STEEP, ROOT], capture_output=True, text=True, timeout=600,
@@ -90,4 +94,4 @@ def test_steep_fields_stay_in_bounds_on_the_checked_build():
     tail = r.stdout[-3000:] + r.stderr[-3000:]
     print(tail)
     assert r.returncode == 0, tail
-    assert "runs 60" in r.stdout
+    assert "runs 84" in r.stdout
