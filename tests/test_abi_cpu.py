@@ -77,6 +77,26 @@ def test_binding_structs_match_c_compiler_layout(tmp_path):
         assert int(got[f"pbr_ray_exit.{f}"]) == pbr.RAY_EXIT_DTYPE.fields[f][1], f
 
 
+def test_binding_constants_match_the_header(tmp_path):
+    """Every constant include/pbr.h defines (error codes, statuses, flags, formats, limits) has the
+    value the C compiler gives it in the binding."""
+    import subprocess
+    names = [n for n in re.findall(r"^#define (PBR_\w+)\s", open(os.path.join(ROOT, "include", "pbr.h")).read(),
+                                   flags=re.M) if n != "PBR_H"]
+    assert len(names) >= 30
+    lines = ['#include <stdio.h>', '#include "pbr.h"', "int main(void) {"]
+    lines += [f'printf("{n} %lld\\n", (long long)({n}));' for n in names]
+    lines.append("return 0; }")
+    src = tmp_path / "consts.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "consts"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = dict(l.split() for l in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                   text=True).stdout.splitlines())
+    for n in names:
+        assert int(got[n]) == getattr(pbr, n), n
+
+
 def test_batch_structs_and_workspace(lib):
     assert C.sizeof(pbr.pbr_batch_item) == 48
     assert C.sizeof(pbr.pbr_batch_config) == 48
