@@ -170,6 +170,9 @@ def main():
     ap.add_argument("--no-extra", action="store_true",
                     help="tomo_piv_512: leave out the shock-FP64 leg, the 128^3 BOS workload and the peak probes "
                          "(for profiling runs; the headline value is unchanged)")
+    ap.add_argument("--mlp-forward", action="store_true",
+                    help="only the surrogate network's forward pass (k_mlp_infer) over 2^22 rows of a randomly "
+                         "initialised network, five timed passes (for counter runs)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy a 1 GiB device buffer 4 times (calibrates HBM byte counters)")
     ap.add_argument("--atomic-probe", action="store_true",
@@ -182,6 +185,9 @@ def main():
         for slots in (1 << 20, 1 << 22):  # 1024^2 and 2048^2 sensors
             out[f"u64_atomics_per_s_{slots}_slots"] = pbr.pbr_probe_u64_atomics(0, slots, 1 << 28)
         print(json.dumps(out))
+        return
+    if args.mlp_forward:
+        print(json.dumps(bench_mlp_forward()), flush=True)
         return
     if args.copy_probe:
         import torch
@@ -608,6 +614,35 @@ MLP_FLOPS_PER_ROW = 2 * (6 * 256 + 3 * 256 * 256 + 256 * 6)  # forward pass, mul
 PEAK_BF16_TFLOPS = 2500.0  # MI355X dense bfloat16 matrix cores, published
 
 
+def mlp_forward_rate(s, rows, device):
+    """Average time of five forward passes of surrogate s over `rows` uniform inputs in [-1, 1)
+    (one warm-up pass first), timed with events on torch's current stream, which the surrogate
+    uses.  Returns (ms per pass, TFLOP/s)."""
+    import torch
+    from paper_1812_05902_amd import pbr
+    x = torch.rand(rows, 6, device=device) * 2 - 1
+    y = torch.empty_like(x)
+    pbr.pbr_surrogate_forward(s.h, x, y)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        pbr.pbr_surrogate_forward(s.h, x, y)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 5
+    return ms, MLP_FLOPS_PER_ROW * rows / (ms * 1e-3) / 1e12
+
+
+def bench_mlp_forward():
+    """The surrogate network's forward pass alone (the matrix-core kernel of the surrogate path)."""
+    from paper_1812_05902_amd import pbr
+    s = pbr.Surrogate(init_seed=3, max_rows=1024, ray_chunk=0)
+    rows = 1 << 22
+    ms, achieved = mlp_forward_rate(s, rows, "cuda")
+    return {"kernel": "k_mlp_infer", "rows": rows, "ms_per_pass": ms, "achieved_TFLOPs": achieved,
+            "peak_TFLOPs": PEAK_BF16_TFLOPS, "frac": achieved / PEAK_BF16_TFLOPS, "flops_per_row": MLP_FLOPS_PER_ROW}
+
+
 def bench_surrogate(args):
     """Surrogate workload: train on 1e7 tracer rays (1e6 validation rays fix the fallback tiles),
     then render the same 1e9 evaluation rays with the plain tracer and with the surrogate, and
@@ -657,18 +692,9 @@ def bench_surrogate(args):
     surr = (rec_s["entered"] == 1) & (rec_s["n_steps"] == 0) & (rec_t["n_steps"] > 0)
     both = surr & (rec_s["status"] == 0) & (rec_t["status"] == 0)
     e = np.hypot(*(rec_s["sensor_px"][both] - rec_t["sensor_px"][both]).T) if both.any() else np.zeros(1)
-    # matrix-core rate of the network alone: one forward pass over 2^22 rows
-    x = torch.rand(1 << 22, 6, device=r.device) * 2 - 1
-    y = torch.empty_like(x)
-    pbr.pbr_surrogate_forward(s.h, x, y)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(5):
-        pbr.pbr_surrogate_forward(s.h, x, y)
-    e1.record()
-    torch.cuda.synchronize()
-    fwd_ms = e0.elapsed_time(e1) / 5
-    achieved = MLP_FLOPS_PER_ROW * x.shape[0] / (fwd_ms * 1e-3) / 1e12
+    # matrix-core rate of the network alone: forward passes over 2^22 rows
+    fwd_rows = 1 << 22
+    fwd_ms, achieved = mlp_forward_rate(s, fwd_rows, r.device)
     wall_t, st_t = res["tracer"]
     wall_s, st_s = res["surrogate"]
     out = {
@@ -690,7 +716,7 @@ def bench_surrogate(args):
                          us_per_adam_step=rep["train_ms"] / max(rep["steps"], 1) * 1e3, batch=4096),
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_BF16_TFLOPS, "traffic": None,
-                     "kernel": "surrogate forward (all layers)", "rows": int(x.shape[0]),
+                     "kernel": "surrogate forward (all layers)", "rows": fwd_rows,
                      "ms_per_pass": fwd_ms, "flops_per_row": MLP_FLOPS_PER_ROW},
     }
     print(json.dumps(out), flush=True)
