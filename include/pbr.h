@@ -418,7 +418,8 @@ typedef struct pbr_source_sum {
  * records, sums and counters are the same bit for bit; only the order in which rays meet the
  * field, and so the cache reuse between rays in flight together, changes.  An entry outside
  * [0, n_src) is clamped into range (a non-permutation then traces some sources twice and others
- * not at all).  NULL with n_src = 0 clears the order.
+ * not at all); the checked build counts such entries and the trace returns PBR_ERR_BOUNDS.  NULL
+ * with n_src = 0 clears the order.
  * Errors: ARG (n_src < 0, null with n_src > 0, misaligned). */
 int pbr_set_source_order(pbr_ctx *ctx, const int64_t *order_dev, int64_t n_src);
 

@@ -708,6 +708,7 @@ __device__ __forceinline__ int64_t ray_key(const TraceParams &P, int64_t q)
     const int64_t k = q / P.rays_per_src;
     if (PBR_CHECKED && !access_ok(P, k >= 0 && k < P.n_src)) return q;
     int64_t s = P.order[k];
+    if (PBR_CHECKED) access_ok(P, s >= 0 && s < P.n_src);  // an entry that is no source index is counted
     s = s < 0 ? 0 : (s >= P.n_src ? P.n_src - 1 : s);
     return s * P.rays_per_src + (q - k * P.rays_per_src);
 }

@@ -95,3 +95,57 @@ def test_steep_fields_stay_in_bounds_on_the_checked_build():
     print(tail)
     assert r.returncode == 0, tail
     assert "runs 84" in r.stdout
+
+
+BAD_ORDER = r"""
+import sys
+sys.path.insert(0, sys.argv[1])
+import numpy as np
+import torch
+from paper_1812_05902_amd import inputs, pbr
+lib = pbr.load(pbr.CHECKED_LIB_PATH)
+assert lib.pbr_checked_build() == 1
+sc = inputs.tiny_bos().replace(n_src=40, rays_per_src=16)
+r = pbr.Renderer.from_scene(sc)
+src = inputs.sources(sc)
+flags = pbr.PBR_CLEAR_FIRST | pbr.PBR_SOURCE_ORDER
+good = torch.arange(sc.n_src - 1, -1, -1, dtype=torch.int64, device=r.device)
+pbr.pbr_set_source_order(r.ctx, good, sc.n_src)
+r.emit_and_trace(src, sc.rays_per_src, 5, sc.ds, flags)
+img = pbr.u64_image_to_numpy(r.read_image())
+assert img.sum() > 0
+bad = good.clone()
+bad[3] = sc.n_src + 7   # no source index: clamped on every build, counted on this one
+bad[9] = -2
+pbr.pbr_set_source_order(r.ctx, bad, sc.n_src)
+try:
+    r.emit_and_trace(src, sc.rays_per_src, 5, sc.ds, flags)
+except pbr.PbrError as e:
+    assert e.code == pbr.PBR_ERR_BOUNDS, e
+    assert "outside their buffers" in str(e), e
+    # the rays of the two bad entries, counted where emission and the finish look up their keys
+    n = int(str(e).split("checked build: ")[1].split()[0])
+    assert n > 0 and n % (2 * sc.rays_per_src) == 0, n
+    print("reported:", e, flush=True)
+else:
+    raise SystemExit("no PBR_ERR_BOUNDS for an order entry outside [0, n_src)")
+# the context stays usable: a valid order traces cleanly again, to the same image
+pbr.pbr_set_source_order(r.ctx, good, sc.n_src)
+r.emit_and_trace(src, sc.rays_per_src, 5, sc.ds, flags)
+assert np.array_equal(pbr.u64_image_to_numpy(r.read_image()), img)
+print("bad order ok", flush=True)
+"""
+
+
+def test_checked_build_reports_an_order_entry_outside_the_sources():
+    """The checked build's report path end to end: a source order with two entries that are no
+    source index (the kernels clamp them on every build) makes the trace return PBR_ERR_BOUNDS
+    with the count in the message; the same context then traces a valid order cleanly."""
+    assert os.path.exists(pbr.CHECKED_LIB_PATH)
+    print("checked build: invalid order entries in a child process", flush=True)
+    r = subprocess.run([sys.executable, "-u", "-c", BAD_ORDER, ROOT], capture_output=True, text=True, timeout=300,
+                       cwd=ROOT)
+    tail = r.stdout[-3000:] + r.stderr[-3000:]
+    print(tail)
+    assert r.returncode == 0, tail
+    assert "bad order ok" in r.stdout
