@@ -149,3 +149,37 @@ def test_checked_build_reports_an_order_entry_outside_the_sources():
     print(tail)
     assert r.returncode == 0, tail
     assert "bad order ok" in r.stdout
+
+
+SAME_BITS = r"""
+import sys
+sys.path.insert(0, sys.argv[1])
+import numpy as np
+from paper_1812_05902_amd import inputs, pbr
+lib = pbr.load(pbr.CHECKED_LIB_PATH)
+assert lib.pbr_checked_build() == 1
+out = {}
+for nodes in (False, True):
+    sc = inputs.tiny_bos()
+    r, st, _ = pbr.trace_scene(sc, nodes=nodes)
+    out[f"img{int(nodes)}"] = pbr.u64_image_to_numpy(r.read_image())
+np.savez(sys.argv[2], **out)
+print("checked images written", flush=True)
+"""
+
+
+def test_checked_build_renders_the_same_bits(tmp_path):
+    """The checked build only adds tests: the tiny BOS image in both field layouts is the same bit
+    for bit from both libraries (the regular one in this process, the checked one in a child)."""
+    import numpy as np
+    from paper_1812_05902_amd import inputs
+    path = tmp_path / "checked.npz"
+    r = subprocess.run([sys.executable, "-u", "-c", SAME_BITS, ROOT, str(path)], capture_output=True, text=True,
+                       timeout=300, cwd=ROOT)
+    assert r.returncode == 0, r.stdout[-3000:] + r.stderr[-3000:]
+    got = np.load(path)
+    for nodes in (False, True):
+        rr, _, _ = pbr.trace_scene(inputs.tiny_bos(), nodes=nodes)
+        mine = pbr.u64_image_to_numpy(rr.read_image())
+        assert mine.sum() > 0
+        assert np.array_equal(got[f"img{int(nodes)}"], mine), nodes
